@@ -1,0 +1,218 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench.
+
+This module holds problem set-up only: mesh node coordinates, boundary
+specifications, initial macroscopic fields, velocity-grid extents and seeded
+random perturbations.  It contains none of the scheme's arithmetic (no
+quadrature weights, equilibria, moments or corrections); each side computes
+those from these inputs with its own code.
+
+Boundary kinds (integers shared by both sides):
+  WALL     isothermal diffuse wall at (T, u, v)
+  FARFIELD incoming Maxwellian at (rho, u, v, T); also used for inflow slots
+  OUTFLOW  zero-gradient extrapolation
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+WALL, FARFIELD, OUTFLOW = 1, 2, 3
+
+
+@dataclasses.dataclass
+class BC:
+    kind: int
+    rho: float = 1.0
+    u: float = 0.0
+    v: float = 0.0
+    T: float = 1.0
+
+
+@dataclasses.dataclass
+class Problem:
+    """A structured-mesh problem: nodes, boundaries, initial state, physics."""
+
+    name: str
+    dim: int
+    X: np.ndarray            # node x, shape (nj+1, ni+1)
+    Y: np.ndarray            # node y, shape (nj+1, ni+1)
+    periodic_i: bool
+    periodic_j: bool
+    bcs: List[BC]            # boundary table; ids below index into it
+    bc_imin: np.ndarray      # (nj,) bc id of the face at i = 0
+    bc_imax: np.ndarray      # (nj,) bc id of the face at i = ni
+    bc_jmin: np.ndarray      # (ni,) bc id of the face at j = 0
+    bc_jmax: np.ndarray      # (ni,) bc id of the face at j = nj
+    rho0: np.ndarray         # (nj, ni) initial density
+    u0: np.ndarray           # (nj, ni)
+    v0: np.ndarray           # (nj, ni)
+    T0: np.ndarray           # (nj, ni)
+    R: float
+    Pr: float
+    K: int
+    omega: float
+    T_ref: float
+    rho_ref: float
+    L_ref: float
+    Kn: float
+    cfl: float
+    vel_kind: str            # 'nc' (Newton-Cotes) or 'gh' (Gauss-Hermite)
+    nv: int                  # velocity points per axis
+    vmax: float              # half-width of a Newton-Cotes grid
+    gh_scale_T: float = 1.0  # temperature whose sqrt(2RT) scales a GH grid
+
+    @property
+    def ni(self) -> int:
+        return self.X.shape[1] - 1
+
+    @property
+    def nj(self) -> int:
+        return self.X.shape[0] - 1
+
+    @property
+    def n_cells(self) -> int:
+        return self.ni * self.nj
+
+
+def _nodes_rect(x0, x1, y0, y1, ni, nj):
+    xs = np.linspace(x0, x1, ni + 1)
+    ys = np.linspace(y0, y1, nj + 1)
+    X, Y = np.meshgrid(xs, ys)
+    return X.copy(), Y.copy()
+
+
+def sod_1d(n_cells: int = 200, Kn: float = 1e-3, nv: int = 101, vmax: float = 10.0) -> Problem:
+    """1-D Sod tube on [0, 1]: left (1, 0, 1), right (0.125, 0, 0.8), R = 1, BGK."""
+    X, Y = _nodes_rect(0.0, 1.0, 0.0, 1.0, n_cells, 1)
+    xc = 0.5 * (X[0, :-1] + X[0, 1:])
+    left = xc < 0.5
+    rho = np.where(left, 1.0, 0.125)[None, :]
+    T = np.where(left, 1.0, 0.8)[None, :]
+    z = np.zeros_like(rho)
+    ids1 = np.zeros(1, np.int32)
+    return Problem("sod1d", 1, X, Y, False, False, [BC(OUTFLOW)], ids1, ids1.copy(),
+                   np.zeros(n_cells, np.int32), np.zeros(n_cells, np.int32),
+                   rho, z, z.copy(), T, R=1.0, Pr=1.0, K=0, omega=0.81, T_ref=1.0,
+                   rho_ref=1.0, L_ref=1.0, Kn=Kn, cfl=0.5, vel_kind="nc", nv=nv, vmax=vmax)
+
+
+def cavity(n: int = 64, Kn: float = 0.075, nv: int = 28, vel_kind: str = "gh",
+           vmax: float = 4.0, lid_mach: float = 0.16) -> Problem:
+    """Lid-driven cavity on [0,1]^2, R = 0.5, T0 = Tw = 1, Shakhov Pr = 2/3."""
+    R = 0.5
+    X, Y = _nodes_rect(0.0, 1.0, 0.0, 1.0, n, n)
+    uw = lid_mach * math.sqrt(5.0 / 3.0 * R * 1.0)
+    bcs = [BC(WALL, T=1.0), BC(WALL, u=uw, T=1.0)]
+    ones = np.ones((n, n))
+    zi = np.zeros(n, np.int32)
+    return Problem("cavity", 2, X, Y, False, False, bcs, zi, zi.copy(), zi.copy(),
+                   np.ones(n, np.int32), ones.copy(), 0 * ones, 0 * ones, ones.copy(),
+                   R=R, Pr=2.0 / 3.0, K=0, omega=0.81, T_ref=1.0, rho_ref=1.0, L_ref=1.0,
+                   Kn=Kn, cfl=0.5, vel_kind=vel_kind, nv=nv, vmax=vmax, gh_scale_T=1.0)
+
+
+def cylinder(ntheta: int = 256, nr: int = 128, Kn: float = 0.1, mach: float = 3.0,
+             nv: int = 101, vmax: float = 10.0, r_out: float = 11.0, dr1: float = 0.02) -> Problem:
+    """O-grid around a unit cylinder, geometric radial spacing, R = 0.5, T_inf = 1.
+
+    Node (i, j) sits at angle -2*pi*i/ntheta and radius r_j so that cells are
+    counter-clockwise; i is periodic, j = 0 is the wall, j = nr the far field.
+    """
+    R = 0.5
+    # geometric ratio q with dr1 * (q^nr - 1)/(q - 1) = r_out - 1
+    total = r_out - 1.0
+    lo, hi = 1.0 + 1e-12, 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        s = dr1 * (mid ** nr - 1.0) / (mid - 1.0)
+        lo, hi = (mid, hi) if s < total else (lo, mid)
+    q = 0.5 * (lo + hi)
+    r = 1.0 + dr1 * (q ** np.arange(nr + 1) - 1.0) / (q - 1.0)
+    r[-1] = r_out
+    th = -2.0 * math.pi * np.arange(ntheta + 1) / ntheta
+    X = r[:, None] * np.cos(th)[None, :]
+    Y = r[:, None] * np.sin(th)[None, :]
+    X[:, -1] = X[:, 0]
+    Y[:, -1] = Y[:, 0]
+    U = mach * math.sqrt(5.0 / 3.0 * R * 1.0)
+    bcs = [BC(WALL, T=1.0), BC(FARFIELD, rho=1.0, u=U, v=0.0, T=1.0)]
+    shape = (nr, ntheta)
+    z = np.zeros(ntheta, np.int32)
+    return Problem("cylinder", 2, X, Y, True, False, bcs, np.zeros(nr, np.int32),
+                   np.zeros(nr, np.int32), z, np.ones(ntheta, np.int32),
+                   np.ones(shape), np.full(shape, U), np.zeros(shape), np.ones(shape),
+                   R=R, Pr=2.0 / 3.0, K=0, omega=0.81, T_ref=1.0, rho_ref=1.0, L_ref=1.0,
+                   Kn=Kn, cfl=0.5, vel_kind="nc", nv=nv, vmax=vmax)
+
+
+def jet(ni: int = 512, nj: int = 256, Kn_jet: float = 1e-3, nv: int = 161, vmax: float = 7.0,
+        rho_b: float = 0.01) -> Problem:
+    """Slot jet into near vacuum on [0,32]x[-8,8]; sonic inflow at |y| <= 0.5, x = 0."""
+    R = 0.5
+    X, Y = _nodes_rect(0.0, 32.0, -8.0, 8.0, ni, nj)
+    uj = math.sqrt(5.0 / 3.0 * R * 1.0)
+    bcs = [BC(WALL, T=1.0), BC(FARFIELD, rho=1.0, u=uj, T=1.0),
+           BC(FARFIELD, rho=rho_b, T=1.0)]
+    yc = 0.5 * (Y[:-1, 0] + Y[1:, 0])
+    imin = np.where(np.abs(yc) <= 0.5, 1, 0).astype(np.int32)
+    shape = (nj, ni)
+    return Problem("jet", 2, X, Y, False, False, bcs, imin, np.full(nj, 2, np.int32),
+                   np.full(ni, 2, np.int32), np.full(ni, 2, np.int32),
+                   np.full(shape, rho_b), np.zeros(shape), np.zeros(shape), np.ones(shape),
+                   R=R, Pr=2.0 / 3.0, K=0, omega=0.81, T_ref=1.0, rho_ref=1.0, L_ref=1.0,
+                   Kn=Kn_jet, cfl=0.5, vel_kind="nc", nv=nv, vmax=vmax)
+
+
+def periodic_box(ni: int, nj: int, Lx: float = 1.0, Ly: float = 0.1, Kn: float = 0.1,
+                 nv: int = 17, vmax: float = 4.0, kind: str = "uniform", amp: float = 0.2,
+                 Pr: float = 2.0 / 3.0) -> Problem:
+    """Periodic box: uniform flow (u = 0.1) or a sine density wave (U0 = 0.1, p0 = 0.5)."""
+    R = 0.5
+    X, Y = _nodes_rect(0.0, Lx, 0.0, Ly, ni, nj)
+    xc = 0.5 * (X[:-1, :-1] + X[:-1, 1:])
+    shape = (nj, ni)
+    if kind == "uniform":
+        rho = np.ones(shape)
+        T = np.ones(shape)
+    else:
+        rho = 1.0 + amp * np.sin(2 * math.pi * xc / Lx)
+        T = 0.5 / (rho * R)
+    z = np.zeros(ni, np.int32)
+    return Problem(kind, 2, X, Y, True, True, [BC(OUTFLOW)], np.zeros(nj, np.int32),
+                   np.zeros(nj, np.int32), z, z.copy(), rho, np.full(shape, 0.1),
+                   np.zeros(shape), T, R=R, Pr=Pr, K=0, omega=0.81, T_ref=1.0, rho_ref=1.0,
+                   L_ref=1.0, Kn=Kn, cfl=0.5, vel_kind="nc", nv=nv, vmax=vmax)
+
+
+def perturb(problem: Problem, seed: int, amp: float = 0.05) -> Problem:
+    """Return a copy with seeded smooth-ish random perturbations of rho, u, v, T."""
+    rng = np.random.default_rng(seed)
+    p = dataclasses.replace(problem)
+    shape = problem.rho0.shape
+    p.rho0 = problem.rho0 * (1.0 + amp * rng.uniform(-1, 1, shape))
+    p.u0 = problem.u0 + amp * rng.uniform(-1, 1, shape)
+    p.v0 = problem.v0 + (amp * rng.uniform(-1, 1, shape) if problem.dim == 2 else 0.0)
+    p.T0 = problem.T0 * (1.0 + amp * rng.uniform(-1, 1, shape))
+    return p
+
+
+def random_positive_rows(seed: int, n_rows: int, n_cols: int, lo: float = 0.2,
+                         hi: float = 1.0) -> np.ndarray:
+    """Seeded random positive values, shape (n_rows, n_cols)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(n_rows, n_cols))
+
+
+def random_states(seed: int, n: int, dim: int = 2):
+    """Seeded random macroscopic states (rho, u, v, T, qx, qy) for micro tests."""
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.5, 2.0, n)
+    u = rng.uniform(-0.5, 0.5, n)
+    v = rng.uniform(-0.5, 0.5, n) if dim == 2 else np.zeros(n)
+    T = rng.uniform(0.6, 1.6, n)
+    qx = rng.uniform(-0.05, 0.05, n)
+    qy = rng.uniform(-0.05, 0.05, n) if dim == 2 else np.zeros(n)
+    return rho, u, v, T, qx, qy
