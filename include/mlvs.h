@@ -1,0 +1,211 @@
+/*
+ * mlvs.h -- C ABI of the MI355X (gfx950) multi-level adaptive velocity-space
+ * DUGKS library (libmlvs.so).
+ *
+ * The library advances the reduced BGK-Shakhov distributions g~, h~ of a
+ * structured 2-D (or 1-D) finite-volume mesh with the discrete unified
+ * gas-kinetic scheme (Sec. 2.2 of the paper, Eqs. phi_update .. recover_phi),
+ * on one uniform velocity space or on a few representative velocity levels
+ * built from per-cell requirements (Sec. 3.2) with conservative inter-level
+ * coupling (Secs. 3.3-3.4).  Every hot-path step runs in HIP kernels on the
+ * device; the host only builds geometry and level tables.
+ *
+ * Conventions
+ *  - Every call returns mlvs_status (0 = MLVS_OK, negative = error).  No C++
+ *    exception crosses the ABI.  mlvs_last_error() returns a thread-local,
+ *    NUL-terminated message describing the last failure on that thread; it
+ *    stays valid until the next call on that thread.
+ *  - Arguments are checked before any device work; a failed check returns
+ *    MLVS_E_ARG (bad argument) or MLVS_E_STATE (call not valid now) and leaves
+ *    the context unchanged.  HIP runtime failures return MLVS_E_HIP.
+ *  - Host arrays passed in are read during the call and copied; the caller
+ *    keeps ownership.  Output arrays are caller-owned host buffers of the
+ *    stated size.  Device memory is obtained only through the allocator in
+ *    mlvs_device (or hipMalloc when none is given) and is owned by the context
+ *    until mlvs_destroy.
+ *  - All device work is ordered on the stream given in mlvs_device (the null
+ *    stream when NULL).  mlvs_step is asynchronous; calls that return data to
+ *    the host synchronise that stream.
+ *  - Cells are numbered c = i + ni * j.  Velocity points of the base grid are
+ *    numbered b = ix + nx * iy.  Points of a level follow the ascending order
+ *    of their first (smallest) base index.
+ */
+#ifndef MLVS_H
+#define MLVS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mlvs_ctx_s* mlvs_ctx;
+typedef int mlvs_status;
+
+enum {
+    MLVS_OK = 0,
+    MLVS_E_ARG = -1,      /* invalid argument                              */
+    MLVS_E_HIP = -2,      /* HIP runtime or kernel launch failure          */
+    MLVS_E_OOM = -3,      /* device allocation failed                      */
+    MLVS_E_STATE = -4,    /* call not valid in the current context state   */
+    MLVS_E_NUMERIC = -5   /* non-finite or non-physical state (strict mode) */
+};
+
+/* Boundary kinds (Sec. 4 workloads; the wall is the isothermal diffuse wall). */
+enum { MLVS_BC_WALL = 1, MLVS_BC_FARFIELD = 2, MLVS_BC_OUTFLOW = 3 };
+
+typedef struct {
+    int kind;          /* MLVS_BC_*                                                */
+    double rho, u, v;  /* FARFIELD: incoming Maxwellian state; WALL: wall velocity */
+    double T;          /* WALL: wall temperature; FARFIELD: temperature            */
+} mlvs_bc;
+
+/* Physical and numerical parameters.
+ *  dim        1 or 2 (D of the paper); K internal degrees of freedom (0).
+ *  R, Pr      gas constant and Prandtl number (Pr = 1 gives BGK).
+ *  mu = mu_ref (T / T_ref)^omega  (power-law viscosity, Sec. 4 opening).
+ *  dt > 0     fixed time step; dt <= 0: dt = cfl * hmin / max|xi| with hmin
+ *             twice the smallest centre-to-face distance.
+ *  precision  64 (g~, h~ stored in double) or 32 (stored in float; moment
+ *             sums, corrections and totals in double).
+ *  compat     0 or 4: four-moment compatibility correction of the Shakhov
+ *             target (Sec. 3.3.1, Eq. eq_four_moment_constraint).
+ *  face_compat 1: also correct the face target used in Eq. recover_phi.
+ *  map_moments 0 or 4: four-moment linear mapping correction for level
+ *             switches, neighbour mapping and cross-level fluxes (Sec. 3.3.2). */
+typedef struct {
+    int dim, K;
+    double R, Pr, omega, mu_ref, T_ref;
+    double dt, cfl;
+    int precision, compat, face_compat, map_moments;
+} mlvs_physics;
+
+/* Structured mesh: node coordinates row-major by j, (nj+1) x (ni+1) values
+ * each; cells must be counter-clockwise.  1-D: nj = 1 and only x-faces are
+ * used.  bc_* hold ids into bcs for the faces on each side (ignored on a
+ * periodic side): bc_imin/bc_imax have nj entries, bc_jmin/bc_jmax ni. */
+typedef struct {
+    int ni, nj;
+    const double *node_x, *node_y;
+    int periodic_i, periodic_j;
+    const int32_t *bc_imin, *bc_imax, *bc_jmin, *bc_jmax;
+    int n_bc;
+    const mlvs_bc* bcs;
+} mlvs_mesh;
+
+/* Tensor base velocity grid V_base: xi_b = (x[ix], y[iy]), w_b = wx[ix] * wy[iy].
+ * 1-D: ny = 1, y = {0}, wy = {1}. */
+typedef struct {
+    int nx, ny;
+    const double *x, *wx, *y, *wy;
+} mlvs_vgrid;
+
+/* Adaptation parameters (Sec. 3.2, Eqs. block-hysteresis-rule and
+ * combined-merge-condition; tau_clust of the clustering).  interval > 0:
+ * mlvs_step adapts at step 0 and every interval steps, before the step. */
+typedef struct {
+    double C_split, C_merge, eps_merge, tau_clust;
+    int flux_test, interval;
+} mlvs_adapt_params;
+
+/* Device allocator hooks.  alloc returns device memory of at least `bytes`
+ * (256-byte aligned) or NULL; free releases it.  NULL hooks use hipMalloc. */
+typedef struct {
+    void* stream;
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+} mlvs_device;
+
+typedef struct {
+    int n_levels;          /* levels after the adaptation                   */
+    int64_t n_unique;      /* distinct per-cell masks                       */
+    int64_t n_changed;     /* cells whose velocity space changed (remapped) */
+    int64_t n_cross;       /* cross-level faces                             */
+    double nbar;           /* cell-weighted mean number of velocity points  */
+    int64_t neg_count;     /* corrections that produced negative g          */
+} mlvs_adapt_report;
+
+/* Quadrature helpers (Sec. 2.3).  Newton-Cotes on [-a, a]: composite Boole
+ * when (n-1) % 4 == 0, composite Simpson when (n-1) is even, composite
+ * midpoint (cell-centred nodes) when n is even.  Gauss-Hermite: nodes
+ * sqrt(2 R T0) x_k, weights sqrt(2 R T0) w_k exp(x_k^2).  x, w: n doubles. */
+mlvs_status mlvs_vgrid_newton_cotes(int n, double a, double* x, double* w);
+mlvs_status mlvs_vgrid_gauss_hermite(int n, double R, double T0, double* x, double* w);
+
+/* mu_ref from a Knudsen number with the VHS relation
+ * mu = 15 sqrt(pi) / (2 (5 - 2 omega)(7 - 2 omega)) Kn rho sqrt(2 R T) L. */
+mlvs_status mlvs_mu_ref_from_kn(double Kn, double rho, double T, double R, double L,
+                                double omega, double* mu_out);
+
+/* Create a context on the current HIP device.  adapt may be NULL (uniform
+ * velocity space).  Multi-level mode needs dim == 2. */
+mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const mlvs_vgrid* vgrid,
+                        const mlvs_adapt_params* adapt, const mlvs_device* dev, mlvs_ctx* out);
+
+/* Initial state: g~ = g_eq, h~ = h_eq at (rho, u, v, T) per cell, with the
+ * compatibility correction when enabled.  rho_u_v_T: [n_cells][4] host. */
+mlvs_status mlvs_init_equilibrium(mlvs_ctx ctx, const double* rho_u_v_T);
+
+/* Install a level catalogue: kappa [n_levels][N_b] coarsening indices on the
+ * 2x2 blocks of V_base (Sec. 3.2), cell_level [n_cells].  Cells whose space
+ * changes are remapped (projection + mapping correction, Eq.
+ * level_switch_conservation). */
+mlvs_status mlvs_set_levels(mlvs_ctx ctx, int n_levels, const uint8_t* kappa, const int32_t* cell_level);
+
+/* Advance n_steps time steps (stream-ordered, asynchronous). */
+mlvs_status mlvs_step(mlvs_ctx ctx, int n_steps);
+
+/* Criterion + grouping + remap now (Secs. 3.2, 3.4).  report may be NULL. */
+mlvs_status mlvs_adapt(mlvs_ctx ctx, mlvs_adapt_report* report);
+
+/* Per-cell coarsening masks of the criterion on the current state, without
+ * changing levels: out [n_cells][N_b] host bytes.  Synchronises. */
+mlvs_status mlvs_criterion(mlvs_ctx ctx, uint8_t* out);
+
+/* Per-cell (rho, u, v, T, qx, qy) from g~, h~ (q as in Eq. discrete_q):
+ * out [n_cells][6] host.  Synchronises. */
+mlvs_status mlvs_moments(mlvs_ctx ctx, double* out);
+
+/* sum_cells |V| (rho, rho u, rho v, rho E), FP64, fixed-order tree sum. */
+mlvs_status mlvs_totals(mlvs_ctx ctx, double out[4]);
+
+/* Levels: n_levels; npts [n_levels]; ncells [n_levels]; n_cross.  Arrays may
+ * be NULL; when given they must hold at least *n_levels entries (call once
+ * with NULL arrays to size them). */
+mlvs_status mlvs_level_info(mlvs_ctx ctx, int* n_levels, int32_t* npts, int32_t* ncells, int64_t* n_cross);
+
+/* kappa of a level: out [N_b]. */
+mlvs_status mlvs_level_kappa(mlvs_ctx ctx, int level, uint8_t* out);
+
+/* Cell -> level map: out [n_cells]. */
+mlvs_status mlvs_cell_levels(mlvs_ctx ctx, int32_t* out);
+
+/* Read / write one cell's g~, h~ on its level (FP64 host values, npts of the
+ * cell's level; g, h may be NULL to query npts).  Synchronises. */
+mlvs_status mlvs_get_f(mlvs_ctx ctx, int64_t cell, double* g, double* h, int32_t* npts);
+mlvs_status mlvs_set_f(mlvs_ctx ctx, int64_t cell, const double* g, const double* h);
+
+/* Bulk read / write of every cell's g~, h~ in cell order, each cell's
+ * values on its level: g, h hold sum over cells of npts(level(cell)). */
+mlvs_status mlvs_get_state(mlvs_ctx ctx, double* g, double* h);
+mlvs_status mlvs_set_state(mlvs_ctx ctx, const double* g, const double* h);
+
+/* Time step in use, mesh hmin, and counts: n_cells, N_b (2x2 blocks). */
+mlvs_status mlvs_info(mlvs_ctx ctx, double* dt, int64_t* n_cells, int32_t* n_blocks, int32_t* n_base);
+
+/* Device bytes held by the context. */
+mlvs_status mlvs_memory(mlvs_ctx ctx, size_t* device_bytes);
+
+/* Number of corrections since creation whose result had a negative g where
+ * the provisional distribution had none (positivity check; values kept). */
+mlvs_status mlvs_neg_count(mlvs_ctx ctx, int64_t* count);
+
+void mlvs_destroy(mlvs_ctx ctx);
+const char* mlvs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLVS_H */

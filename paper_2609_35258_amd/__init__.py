@@ -1,0 +1,338 @@
+"""MI355X (gfx950) multi-level adaptive velocity-space DUGKS.
+
+Thin Python binding of libmlvs.so (include/mlvs.h): argument marshalling only.
+Every step of the scheme runs in the library's HIP kernels; PyTorch provides
+device memory (through the library's allocator hooks) and the stream.  There
+is no CPU fallback: if the library is not built, or no GPU is present, calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmlvs.so")
+
+MLVS_BC_WALL, MLVS_BC_FARFIELD, MLVS_BC_OUTFLOW = 1, 2, 3
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_int32_p = ctypes.POINTER(ctypes.c_int32)
+_c_uint8_p = ctypes.POINTER(ctypes.c_uint8)
+
+
+class mlvs_bc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("rho", ctypes.c_double), ("u", ctypes.c_double),
+                ("v", ctypes.c_double), ("T", ctypes.c_double)]
+
+
+class mlvs_physics(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("K", ctypes.c_int), ("R", ctypes.c_double), ("Pr", ctypes.c_double),
+                ("omega", ctypes.c_double), ("mu_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
+                ("dt", ctypes.c_double), ("cfl", ctypes.c_double), ("precision", ctypes.c_int),
+                ("compat", ctypes.c_int), ("face_compat", ctypes.c_int), ("map_moments", ctypes.c_int)]
+
+
+class mlvs_mesh(ctypes.Structure):
+    _fields_ = [("ni", ctypes.c_int), ("nj", ctypes.c_int), ("node_x", _c_double_p), ("node_y", _c_double_p),
+                ("periodic_i", ctypes.c_int), ("periodic_j", ctypes.c_int), ("bc_imin", _c_int32_p),
+                ("bc_imax", _c_int32_p), ("bc_jmin", _c_int32_p), ("bc_jmax", _c_int32_p),
+                ("n_bc", ctypes.c_int), ("bcs", ctypes.POINTER(mlvs_bc))]
+
+
+class mlvs_vgrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("x", _c_double_p), ("wx", _c_double_p),
+                ("y", _c_double_p), ("wy", _c_double_p)]
+
+
+class mlvs_adapt_params(ctypes.Structure):
+    _fields_ = [("C_split", ctypes.c_double), ("C_merge", ctypes.c_double), ("eps_merge", ctypes.c_double),
+                ("tau_clust", ctypes.c_double), ("flux_test", ctypes.c_int), ("interval", ctypes.c_int)]
+
+
+_ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class mlvs_device(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p), ("alloc", _ALLOC), ("free", _FREE), ("user", ctypes.c_void_p)]
+
+
+class mlvs_adapt_report(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int), ("n_unique", ctypes.c_int64), ("n_changed", ctypes.c_int64),
+                ("n_cross", ctypes.c_int64), ("nbar", ctypes.c_double), ("neg_count", ctypes.c_int64)]
+
+
+# name -> (restype, argtypes)
+_PROTOS = {
+    "mlvs_vgrid_newton_cotes": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, _c_double_p, _c_double_p]),
+    "mlvs_vgrid_gauss_hermite": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, _c_double_p,
+                                                _c_double_p]),
+    "mlvs_mu_ref_from_kn": (ctypes.c_int, [ctypes.c_double] * 6 + [_c_double_p]),
+    "mlvs_create": (ctypes.c_int, [ctypes.POINTER(mlvs_physics), ctypes.POINTER(mlvs_mesh),
+                                   ctypes.POINTER(mlvs_vgrid), ctypes.POINTER(mlvs_adapt_params),
+                                   ctypes.POINTER(mlvs_device), ctypes.POINTER(ctypes.c_void_p)]),
+    "mlvs_init_equilibrium": (ctypes.c_int, [ctypes.c_void_p, _c_double_p]),
+    "mlvs_set_levels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_uint8_p, _c_int32_p]),
+    "mlvs_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "mlvs_adapt": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(mlvs_adapt_report)]),
+    "mlvs_criterion": (ctypes.c_int, [ctypes.c_void_p, _c_uint8_p]),
+    "mlvs_moments": (ctypes.c_int, [ctypes.c_void_p, _c_double_p]),
+    "mlvs_totals": (ctypes.c_int, [ctypes.c_void_p, _c_double_p]),
+    "mlvs_level_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), _c_int32_p, _c_int32_p,
+                                       ctypes.POINTER(ctypes.c_int64)]),
+    "mlvs_level_kappa": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_uint8_p]),
+    "mlvs_cell_levels": (ctypes.c_int, [ctypes.c_void_p, _c_int32_p]),
+    "mlvs_get_f": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _c_double_p, _c_double_p, _c_int32_p]),
+    "mlvs_set_f": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _c_double_p, _c_double_p]),
+    "mlvs_get_state": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p]),
+    "mlvs_set_state": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, _c_double_p]),
+    "mlvs_info": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, ctypes.POINTER(ctypes.c_int64), _c_int32_p,
+                                 _c_int32_p]),
+    "mlvs_memory": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "mlvs_neg_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "mlvs_destroy": (None, [ctypes.c_void_p]),
+    "mlvs_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmlvs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmlvs.so is not built (run paper_2609_35258_amd.build.build())")
+        # Load torch first so that the library binds to the same HIP runtime
+        # (libamdhip64.so.7) as torch: streams and memory are torch's.
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _PROTOS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class MLVSError(RuntimeError):
+    pass
+
+
+def _check(status):
+    if status != 0:
+        msg = lib().mlvs_last_error().decode(errors="replace")
+        raise MLVSError("mlvs error %d: %s" % (status, msg))
+
+
+def _dp(a):
+    return a.ctypes.data_as(_c_double_p)
+
+
+def newton_cotes(n: int, a: float):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    _check(lib().mlvs_vgrid_newton_cotes(n, a, _dp(x), _dp(w)))
+    return x, w
+
+
+def gauss_hermite(n: int, R: float, T0: float):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    _check(lib().mlvs_vgrid_gauss_hermite(n, R, T0, _dp(x), _dp(w)))
+    return x, w
+
+
+def mu_ref_from_kn(Kn, rho, T, R, L, omega):
+    out = ctypes.c_double()
+    _check(lib().mlvs_mu_ref_from_kn(Kn, rho, T, R, L, omega, ctypes.byref(out)))
+    return out.value
+
+
+class Solver:
+    """One MLVS-DUGKS context on the current torch CUDA (HIP) device and stream."""
+
+    def __init__(self, *, dim: int, node_x, node_y, periodic_i: bool, periodic_j: bool, bcs: Sequence,
+                 bc_imin, bc_imax, bc_jmin, bc_jmax, vx, vwx, vy, vwy, R: float, Pr: float, K: int,
+                 omega: float, mu_ref: float, T_ref: float, cfl: float, dt: float = 0.0,
+                 precision: int = 64, compat: int = 4, face_compat: bool = True, map_moments: int = 4,
+                 adapt: Optional[dict] = None, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the MLVS library runs on the device only")
+        L = lib()
+        self.torch = torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._keep = {}
+
+        def _alloc(n, user):
+            t = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+            p = t.data_ptr()
+            self._keep[p] = t
+            return p
+
+        def _free(p, user):
+            self._keep.pop(p, None)
+
+        self._alloc_cb = _ALLOC(_alloc)
+        self._free_cb = _FREE(_free)
+        self.stream = torch.cuda.current_stream(self.device)
+        dev = mlvs_device(ctypes.c_void_p(self.stream.cuda_stream), self._alloc_cb, self._free_cb, None)
+        node_x = np.ascontiguousarray(node_x, dtype=np.float64)
+        node_y = np.ascontiguousarray(node_y, dtype=np.float64)
+        nj, ni = node_x.shape[0] - 1, node_x.shape[1] - 1
+        self._arrays = []
+
+        def keep(a, dt_=np.float64):
+            a = np.ascontiguousarray(a, dtype=dt_)
+            self._arrays.append(a)
+            return a
+
+        bc_arr = (mlvs_bc * max(len(bcs), 1))()
+        for k, b in enumerate(bcs):
+            bc_arr[k] = mlvs_bc(int(b.kind), float(b.rho), float(b.u), float(b.v), float(b.T))
+        self._bc_arr = bc_arr
+        i32 = lambda a: keep(a, np.int32).ctypes.data_as(_c_int32_p)
+        mesh = mlvs_mesh(ni, nj, _dp(keep(node_x)), _dp(keep(node_y)), int(periodic_i), int(periodic_j),
+                         i32(bc_imin), i32(bc_imax), i32(bc_jmin), i32(bc_jmax), len(bcs), bc_arr)
+        vg = mlvs_vgrid(len(vx), len(vy), _dp(keep(vx)), _dp(keep(vwx)), _dp(keep(vy)), _dp(keep(vwy)))
+        phys = mlvs_physics(dim, K, R, Pr, omega, mu_ref, T_ref, dt, cfl, precision, compat, int(face_compat),
+                            map_moments)
+        ap = None
+        if adapt is not None:
+            ap = mlvs_adapt_params(adapt["C_split"], adapt["C_merge"], adapt.get("eps_merge", 0.0),
+                                   adapt["tau_clust"], int(adapt.get("flux_test", False)),
+                                   int(adapt.get("interval", 0)))
+        h = ctypes.c_void_p()
+        _check(L.mlvs_create(ctypes.byref(phys), ctypes.byref(mesh), ctypes.byref(vg),
+                             ctypes.byref(ap) if ap is not None else None, ctypes.byref(dev), ctypes.byref(h)))
+        self.h = h
+        self.n_cells = ni * nj
+        self.dim = dim
+        dt_ = ctypes.c_double()
+        nc = ctypes.c_int64()
+        nb = ctypes.c_int32()
+        nbase = ctypes.c_int32()
+        _check(L.mlvs_info(self.h, ctypes.byref(dt_), ctypes.byref(nc), ctypes.byref(nb), ctypes.byref(nbase)))
+        self.dt = dt_.value
+        self.n_blocks = nb.value
+        self.n_base = nbase.value
+
+    @classmethod
+    def from_problem(cls, p, precision: int = 64, compat: int = 4, face_compat: bool = True,
+                     map_moments: int = 4, adapt: Optional[dict] = None, dt: float = 0.0):
+        """Build from a problem description (attributes as in the workload generators)."""
+        if p.vel_kind == "gh":
+            x, w = gauss_hermite(p.nv, p.R, p.gh_scale_T)
+        else:
+            x, w = newton_cotes(p.nv, p.vmax)
+        if p.dim == 1:
+            y, wy = np.zeros(1), np.ones(1)
+        else:
+            y, wy = x, w
+        mu = mu_ref_from_kn(p.Kn, p.rho_ref, p.T_ref, p.R, p.L_ref, p.omega)
+        s = cls(dim=p.dim, node_x=p.X, node_y=p.Y, periodic_i=p.periodic_i, periodic_j=p.periodic_j,
+                bcs=p.bcs, bc_imin=p.bc_imin, bc_imax=p.bc_imax, bc_jmin=p.bc_jmin, bc_jmax=p.bc_jmax,
+                vx=x, vwx=w, vy=y, vwy=wy, R=p.R, Pr=p.Pr, K=p.K, omega=p.omega, mu_ref=mu, T_ref=p.T_ref,
+                cfl=p.cfl, dt=dt, precision=precision, compat=compat, face_compat=face_compat,
+                map_moments=map_moments, adapt=adapt)
+        s.init_equilibrium(np.stack([p.rho0.ravel(), p.u0.ravel(), p.v0.ravel(), p.T0.ravel()], axis=1))
+        return s
+
+    # -- calls -------------------------------------------------------------------
+    def init_equilibrium(self, rho_u_v_T):
+        a = np.ascontiguousarray(rho_u_v_T, dtype=np.float64)
+        _check(lib().mlvs_init_equilibrium(self.h, _dp(a)))
+
+    def step(self, n: int = 1):
+        _check(lib().mlvs_step(self.h, int(n)))
+
+    def moments(self):
+        out = np.zeros((self.n_cells, 6))
+        _check(lib().mlvs_moments(self.h, _dp(out)))
+        return out
+
+    def totals(self):
+        out = np.zeros(4)
+        _check(lib().mlvs_totals(self.h, _dp(out)))
+        return out
+
+    def level_info(self):
+        n = ctypes.c_int()
+        _check(lib().mlvs_level_info(self.h, ctypes.byref(n), None, None, None))
+        npts = np.zeros(n.value, np.int32)
+        ncell = np.zeros(n.value, np.int32)
+        ncross = ctypes.c_int64()
+        _check(lib().mlvs_level_info(self.h, ctypes.byref(n), npts.ctypes.data_as(_c_int32_p),
+                                     ncell.ctypes.data_as(_c_int32_p), ctypes.byref(ncross)))
+        return npts, ncell, ncross.value
+
+    def level_kappa(self, level: int):
+        out = np.zeros(self.n_blocks, np.uint8)
+        _check(lib().mlvs_level_kappa(self.h, level, out.ctypes.data_as(_c_uint8_p)))
+        return out
+
+    def cell_levels(self):
+        out = np.zeros(self.n_cells, np.int32)
+        _check(lib().mlvs_cell_levels(self.h, out.ctypes.data_as(_c_int32_p)))
+        return out
+
+    def npts_per_cell(self):
+        npts, _, _ = self.level_info()
+        return npts[self.cell_levels()]
+
+    def get_state(self):
+        """List of (g, h) per cell, FP64 on the host."""
+        n = self.npts_per_cell()
+        tot = int(n.sum())
+        g = np.zeros(tot)
+        h = np.zeros(tot)
+        _check(lib().mlvs_get_state(self.h, _dp(g), _dp(h)))
+        off = np.concatenate([[0], np.cumsum(n)])
+        return [(g[off[c]:off[c + 1]], h[off[c]:off[c + 1]]) for c in range(self.n_cells)]
+
+    def set_state(self, gs, hs):
+        g = np.ascontiguousarray(np.concatenate(gs), dtype=np.float64)
+        h = np.ascontiguousarray(np.concatenate(hs), dtype=np.float64)
+        _check(lib().mlvs_set_state(self.h, _dp(g), _dp(h)))
+
+    def set_levels(self, kappas, cell_level):
+        k = np.ascontiguousarray(np.asarray(kappas, np.uint8).reshape(-1))
+        cl = np.ascontiguousarray(cell_level, np.int32)
+        n = len(k) // max(self.n_blocks, 1)
+        _check(lib().mlvs_set_levels(self.h, n, k.ctypes.data_as(_c_uint8_p), cl.ctypes.data_as(_c_int32_p)))
+
+    def adapt(self):
+        rep = mlvs_adapt_report()
+        _check(lib().mlvs_adapt(self.h, ctypes.byref(rep)))
+        return {k: getattr(rep, k) for k, _ in mlvs_adapt_report._fields_}
+
+    def criterion(self):
+        out = np.zeros((self.n_cells, self.n_blocks), np.uint8)
+        _check(lib().mlvs_criterion(self.h, out.ctypes.data_as(_c_uint8_p)))
+        return out
+
+    def memory(self):
+        v = ctypes.c_size_t()
+        _check(lib().mlvs_memory(self.h, ctypes.byref(v)))
+        return v.value
+
+    def neg_count(self):
+        v = ctypes.c_int64()
+        _check(lib().mlvs_neg_count(self.h, ctypes.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mlvs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,1226 @@
+// Host side of libmlvs: the C ABI, mesh geometry, velocity levels, projection
+// tables, clustering and the per-step launch sequence.  All per-velocity work
+// runs in the kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/mlvs.h"
+#include "mlvs_impl.h"
+
+using namespace mlvs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Fail {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw Fail{code, buf};
+}
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) fail(MLVS_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <typename F>
+mlvs_status guarded(F&& f) {
+    try {
+        f();
+        return MLVS_OK;
+    } catch (const Fail& e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return MLVS_E_OOM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return MLVS_E_STATE;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// quadrature (Sec. 2.3)
+// ---------------------------------------------------------------------------
+void newton_cotes(int n, double a, double* x, double* w) {
+    if (n < 2) fail(MLVS_E_ARG, "need at least two velocity nodes");
+    if (n % 2 == 0) {
+        const double hh = 2.0 * a / n;
+        for (int k = 0; k < n; ++k) { x[k] = -a + hh * (k + 0.5); w[k] = hh; }
+        return;
+    }
+    const double hh = 2.0 * a / (n - 1);
+    for (int k = 0; k < n; ++k) { x[k] = a * (2.0 * k - (n - 1)) / (n - 1); w[k] = 0.0; }
+    if ((n - 1) % 4 == 0) {
+        const double c[5] = {7, 32, 12, 32, 7};
+        for (int p = 0; p < n - 1; p += 4)
+            for (int k = 0; k < 5; ++k) w[p + k] += c[k] * (2.0 * hh / 45.0);
+    } else {
+        const double c[3] = {1, 4, 1};
+        for (int p = 0; p < n - 1; p += 2)
+            for (int k = 0; k < 3; ++k) w[p + k] += c[k] * (hh / 3.0);
+    }
+}
+
+// Gauss-Hermite nodes/weights for weight exp(-x^2) by Newton on the
+// orthonormal Hermite recurrence; scaled to integrate f itself.
+void gauss_hermite(int n, double R, double T0, double* x, double* w) {
+    if (n < 1 || n > 400) fail(MLVS_E_ARG, "Gauss-Hermite order out of range");
+    std::vector<double> xs(n), ws(n);
+    const double pim4 = 0.7511255444649425;   // pi^(-1/4)
+    double z = 0.0;
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        if (i == 0) z = std::sqrt(2.0 * n + 1.0) - 1.85575 * std::pow(2.0 * n + 1.0, -0.16667);
+        else if (i == 1) z -= 1.14 * std::pow((double)n, 0.426) / z;
+        else if (i == 2) z = 1.86 * z - 0.86 * xs[0];
+        else if (i == 3) z = 1.91 * z - 0.91 * xs[1];
+        else z = 2.0 * z - xs[i - 2];
+        double pp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p1 = pim4, p2 = 0.0;
+            for (int j = 0; j < n; ++j) {
+                const double p3 = p2;
+                p2 = p1;
+                p1 = z * std::sqrt(2.0 / (j + 1)) * p2 - std::sqrt((double)j / (j + 1)) * p3;
+            }
+            pp = std::sqrt(2.0 * n) * p2;
+            const double z1 = z;
+            z = z1 - p1 / pp;
+            if (std::fabs(z - z1) <= 1e-15 * std::max(1.0, std::fabs(z))) break;
+        }
+        xs[i] = z;
+        xs[n - 1 - i] = -z;
+        ws[i] = 2.0 / (pp * pp);
+        ws[n - 1 - i] = ws[i];
+    }
+    const double c = std::sqrt(2.0 * R * T0);
+    for (int i = 0; i < n; ++i) {
+        const double xi = xs[n - 1 - i];   // ascending
+        x[i] = c * xi;
+        w[i] = c * ws[n - 1 - i] * std::exp(xi * xi);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// small dense helpers
+// ---------------------------------------------------------------------------
+bool invert4(const double* A, double* inv) {
+    double M[4][8];
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 8; ++c) M[r][c] = c < 4 ? A[r * 4 + c] : (c - 4 == r ? 1.0 : 0.0);
+    for (int k = 0; k < 4; ++k) {
+        int p = k;
+        for (int i = k + 1; i < 4; ++i)
+            if (std::fabs(M[i][k]) > std::fabs(M[p][k])) p = i;
+        if (M[p][k] == 0.0) return false;
+        if (p != k)
+            for (int c = 0; c < 8; ++c) std::swap(M[k][c], M[p][c]);
+        const double d = M[k][k];
+        for (int c = 0; c < 8; ++c) M[k][c] /= d;
+        for (int i = 0; i < 4; ++i) {
+            if (i == k) continue;
+            const double f = M[i][k];
+            for (int c = 0; c < 8; ++c) M[i][c] -= f * M[k][c];
+        }
+    }
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) inv[r * 4 + c] = M[r][c + 4];
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+struct DevMem {
+    mlvs_device dev{};
+    size_t bytes = 0;
+    std::unordered_map<void*, size_t> live;
+
+    void* alloc(size_t n) {
+        if (n == 0) n = 8;
+        n = (n + 255) & ~size_t(255);
+        void* p = nullptr;
+        if (dev.alloc) {
+            p = dev.alloc(n, dev.user);
+            if (!p) fail(MLVS_E_OOM, "device allocation of %zu bytes failed", n);
+        } else {
+            if (hipMalloc(&p, n) != hipSuccess) fail(MLVS_E_OOM, "hipMalloc of %zu bytes failed", n);
+        }
+        live[p] = n;
+        bytes += n;
+        return p;
+    }
+    void release(void* p) {
+        if (!p) return;
+        auto it = live.find(p);
+        if (it == live.end()) return;
+        bytes -= it->second;
+        live.erase(it);
+        if (dev.free) dev.free(p, dev.user);
+        else (void)hipFree(p);
+    }
+    void release_all() {
+        std::vector<void*> ps;
+        for (auto& kv : live) ps.push_back(kv.first);
+        for (void* p : ps) release(p);
+    }
+};
+
+template <typename T>
+T* upload(DevMem& dm, const std::vector<T>& v, hipStream_t st) {
+    T* d = static_cast<T*>(dm.alloc(sizeof(T) * std::max<size_t>(v.size(), 1)));
+    if (!v.empty()) hip_check(hipMemcpyAsync(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st), "upload");
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// velocity levels (Sec. 3.2)
+// ---------------------------------------------------------------------------
+struct Base {
+    int nx = 0, ny = 0, N = 0, nbx = 0, nby = 0, Nb = 0;
+    std::vector<double> x, y, w;     // per base point
+};
+
+struct Level {
+    std::vector<uint8_t> kappa;
+    int N = 0;
+    std::vector<double> xi_x, xi_y, w;
+    std::vector<int> pt_of_base;
+    std::vector<int> mem_off, mem_idx;     // base members per point (ascending)
+    double Minv[16];
+    bool is_iface = false;
+    // device
+    double *d_x = nullptr, *d_y = nullptr, *d_w = nullptr;
+    int* d_pt_of_base = nullptr;
+    int stride = 0;
+    int n_cells = 0, n_rows = 0, n_ghost = 0;
+    void *g = nullptr, *h = nullptr, *fg = nullptr, *fh = nullptr;
+    void *Fg = nullptr, *Fh = nullptr, *Gg = nullptr, *Gh = nullptr;
+    size_t rows_alloc = 0, ghost_alloc = 0;
+};
+
+void check_kappa(const Base& B, const uint8_t* k) {
+    for (int b = 0; b < B.Nb; ++b)
+        if (k[b] > 3) fail(MLVS_E_ARG, "kappa value out of range");
+    const int n8x = B.nbx / 4, n8y = B.nby / 4, n4x = B.nbx / 2, n4y = B.nby / 2;
+    for (int by = 0; by < B.nby; ++by)
+        for (int bx = 0; bx < B.nbx; ++bx) {
+            const int v = k[bx + B.nbx * by];
+            if (v == 3 && !(bx < 4 * n8x && by < 4 * n8y)) fail(MLVS_E_ARG, "8x8 merge outside an eligible block");
+            if (v == 2 && !(bx < 2 * n4x && by < 2 * n4y)) fail(MLVS_E_ARG, "4x4 merge outside an eligible block");
+        }
+    for (int oy = 0; oy < n8y; ++oy)
+        for (int ox = 0; ox < n8x; ++ox) {
+            int c3 = 0;
+            for (int j = 0; j < 4; ++j)
+                for (int i = 0; i < 4; ++i) c3 += k[4 * ox + i + B.nbx * (4 * oy + j)] == 3;
+            if (c3 != 0 && c3 != 16) fail(MLVS_E_ARG, "inconsistent 8x8 block in kappa");
+        }
+    for (int qy = 0; qy < n4y; ++qy)
+        for (int qx = 0; qx < n4x; ++qx) {
+            int c2 = 0, cge = 0;
+            for (int j = 0; j < 2; ++j)
+                for (int i = 0; i < 2; ++i) {
+                    const int v = k[2 * qx + i + B.nbx * (2 * qy + j)];
+                    c2 += v == 2;
+                    cge += v >= 2;
+                }
+            if (c2 != 0 && cge != 4) fail(MLVS_E_ARG, "inconsistent 4x4 block in kappa");
+        }
+}
+
+std::unique_ptr<Level> build_level(const Base& B, const std::vector<uint8_t>& kappa) {
+    auto L = std::make_unique<Level>();
+    L->kappa = kappa;
+    std::vector<std::vector<int>> groups;
+    std::vector<char> covered(B.N, 0);
+    auto block = [&](int s, int bx, int by) {
+        const int size = 1 << s;
+        std::vector<int> g;
+        for (int iy = by * size; iy < by * size + size; ++iy)
+            for (int ix = bx * size; ix < bx * size + size; ++ix) g.push_back(ix + B.nx * iy);
+        return g;
+    };
+    auto kap = [&](int bx, int by) { return (int)kappa[bx + B.nbx * by]; };
+    if (B.Nb > 0) {
+        for (int oy = 0; oy < B.nby / 4; ++oy)
+            for (int ox = 0; ox < B.nbx / 4; ++ox)
+                if (kap(4 * ox, 4 * oy) == 3) groups.push_back(block(3, ox, oy));
+        for (int qy = 0; qy < B.nby / 2; ++qy)
+            for (int qx = 0; qx < B.nbx / 2; ++qx)
+                if (kap(2 * qx, 2 * qy) == 2) groups.push_back(block(2, qx, qy));
+        for (int by = 0; by < B.nby; ++by)
+            for (int bx = 0; bx < B.nbx; ++bx)
+                if (kap(bx, by) == 1) groups.push_back(block(1, bx, by));
+    }
+    for (auto& g : groups)
+        for (int b : g) covered[b] = 1;
+    for (int b = 0; b < B.N; ++b)
+        if (!covered[b]) groups.push_back({b});
+    for (auto& g : groups) std::sort(g.begin(), g.end());
+    std::sort(groups.begin(), groups.end(), [](const std::vector<int>& a, const std::vector<int>& b) { return a[0] < b[0]; });
+    L->N = (int)groups.size();
+    L->pt_of_base.assign(B.N, -1);
+    L->mem_off.assign(L->N + 1, 0);
+    L->xi_x.resize(L->N);
+    L->xi_y.resize(L->N);
+    L->w.resize(L->N);
+    for (int p = 0; p < L->N; ++p) {
+        double ws = 0.0, sx = 0.0, sy = 0.0;
+        for (int b : groups[p]) {
+            L->pt_of_base[b] = p;
+            L->mem_idx.push_back(b);
+            ws += B.w[b];
+        }
+        for (int b : groups[p]) { sx += B.w[b] * B.x[b]; sy += B.w[b] * B.y[b]; }
+        L->w[p] = ws;
+        L->xi_x[p] = sx / ws;
+        L->xi_y[p] = sy / ws;
+        L->mem_off[p + 1] = (int)L->mem_idx.size();
+    }
+    // state-independent four-moment mapping matrix (Eqs. raw_four_g_basis, raw_four_gh_coupling)
+    double A[16] = {0};
+    for (int p = 0; p < L->N; ++p) {
+        const double x = L->xi_x[p], y = L->xi_y[p], w = L->w[p], x2 = x * x + y * y;
+        const double psi[4] = {1.0, x, y, 0.5 * x2}, phi[4] = {1.0, x, y, x2};
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) A[r * 4 + c] += w * psi[r] * phi[c];
+    }
+    if (!invert4(A, L->Minv)) std::fill(L->Minv, L->Minv + 16, 0.0);
+    return L;
+}
+
+// dst <- src projection table (CSR over dst points).
+struct HostTable {
+    std::vector<int> off, idx;
+    std::vector<double> frac;
+};
+
+HostTable make_table(const Level& dst, const Level& src) {
+    HostTable t;
+    t.off.push_back(0);
+    for (int P = 0; P < dst.N; ++P) {
+        const int b0 = dst.mem_idx[dst.mem_off[P]];
+        const int a0 = src.pt_of_base[b0];
+        bool single = true;
+        for (int e = dst.mem_off[P]; e < dst.mem_off[P + 1]; ++e)
+            if (src.pt_of_base[dst.mem_idx[e]] != a0) { single = false; break; }
+        if (single) {
+            t.idx.push_back(a0);
+            t.frac.push_back(1.0);
+        } else {
+            int last = -1;
+            for (int e = dst.mem_off[P]; e < dst.mem_off[P + 1]; ++e) {
+                const int a = src.pt_of_base[dst.mem_idx[e]];
+                if (a == last) continue;
+                bool seen = false;
+                for (int q = t.off.back(); q < (int)t.idx.size(); ++q)
+                    if (t.idx[q] == a) { seen = true; break; }
+                if (!seen) {
+                    t.idx.push_back(a);
+                    t.frac.push_back(src.w[a] / dst.w[P]);
+                }
+                last = a;
+            }
+        }
+        t.off.push_back((int)t.idx.size());
+    }
+    return t;
+}
+
+struct DevTable {
+    int* off = nullptr;
+    int* idx = nullptr;
+    double* frac = nullptr;
+    PairTable view() const { return PairTable{off, idx, frac}; }
+};
+
+// ---------------------------------------------------------------------------
+// mesh geometry
+// ---------------------------------------------------------------------------
+struct FaceH {
+    int L, R;                    // R < 0: boundary, L is the interior cell
+    int bc;
+    double nx, ny, area, cx, cy, dLx, dLy, dRx, dRy;
+};
+
+struct MeshH {
+    int ni = 0, nj = 0, dim = 2, n_cells = 0;
+    bool per_i = false, per_j = false;
+    std::vector<double> vol, xc, yc;
+    std::vector<FaceH> faces;          // interior faces
+    std::vector<FaceH> bfaces;         // boundary faces (outward normal)
+    std::vector<int> face_of_cell;     // [c][4]: interior face id or -1 (W, E, S, N)
+    std::vector<int> bface_of_cell;    // [c][4]: boundary face id or -1
+    std::vector<int> nbr;              // [c][4]
+    std::vector<CellGeom> geom;
+    double hmin = 1e300;
+};
+
+void build_mesh(MeshH& M, const mlvs_mesh& in, int dim) {
+    const int ni = in.ni, nj = in.nj;
+    M.ni = ni; M.nj = nj; M.dim = dim; M.n_cells = ni * nj;
+    M.per_i = in.periodic_i != 0; M.per_j = in.periodic_j != 0;
+    auto X = [&](int i, int j) { return in.node_x[(size_t)j * (ni + 1) + i]; };
+    auto Y = [&](int i, int j) { return in.node_y[(size_t)j * (ni + 1) + i]; };
+    const int n = M.n_cells;
+    M.vol.resize(n); M.xc.resize(n); M.yc.resize(n);
+    for (int j = 0; j < nj; ++j)
+        for (int i = 0; i < ni; ++i) {
+            const double px[4] = {X(i, j), X(i + 1, j), X(i + 1, j + 1), X(i, j + 1)};
+            const double py[4] = {Y(i, j), Y(i + 1, j), Y(i + 1, j + 1), Y(i, j + 1)};
+            double a = 0, cx = 0, cy = 0;
+            for (int k = 0; k < 4; ++k) {
+                const double x0 = px[k], y0 = py[k], x1 = px[(k + 1) % 4], y1 = py[(k + 1) % 4];
+                const double cr = x0 * y1 - x1 * y0;
+                a += cr; cx += (x0 + x1) * cr; cy += (y0 + y1) * cr;
+            }
+            a *= 0.5;
+            if (!(a > 0)) fail(MLVS_E_ARG, "cell (%d, %d) is not counter-clockwise", i, j);
+            const int c = i + ni * j;
+            M.vol[c] = a; M.xc[c] = cx / (6.0 * a); M.yc[c] = cy / (6.0 * a);
+        }
+    double Tix = 0, Tiy = 0, Tjx = 0, Tjy = 0;
+    if (M.per_i) { Tix = X(ni, 0) - X(0, 0); Tiy = Y(ni, 0) - Y(0, 0); }
+    if (M.per_j) { Tjx = X(0, nj) - X(0, 0); Tjy = Y(0, nj) - Y(0, 0); }
+    M.face_of_cell.assign(4 * n, -1);
+    M.bface_of_cell.assign(4 * n, -1);
+    auto geomf = [](double x0, double y0, double x1, double y1, bool plus_i, FaceH& f) {
+        const double tx = x1 - x0, ty = y1 - y0;
+        f.area = std::hypot(tx, ty);
+        if (plus_i) { f.nx = ty / f.area; f.ny = -tx / f.area; }
+        else { f.nx = -ty / f.area; f.ny = tx / f.area; }
+        f.cx = 0.5 * (x0 + x1); f.cy = 0.5 * (y0 + y1);
+    };
+    for (int j = 0; j < nj; ++j)
+        for (int i = 0; i < ni + (M.per_i ? 0 : 1); ++i) {
+            FaceH f{};
+            geomf(X(i, j), Y(i, j), X(i, j + 1), Y(i, j + 1), true, f);
+            if ((i > 0 && i < ni) || M.per_i) {
+                f.L = (i - 1 + ni) % ni + ni * j;
+                f.R = i + ni * j;
+                const bool wrap = M.per_i && i == 0;
+                f.dLx = f.cx - (M.xc[f.L] - (wrap ? Tix : 0.0));
+                f.dLy = f.cy - (M.yc[f.L] - (wrap ? Tiy : 0.0));
+                f.dRx = f.cx - M.xc[f.R];
+                f.dRy = f.cy - M.yc[f.R];
+                f.bc = -1;
+                M.faces.push_back(f);
+                M.face_of_cell[4 * f.L + 1] = (int)M.faces.size() - 1;
+                M.face_of_cell[4 * f.R + 0] = (int)M.faces.size() - 1;
+            } else {
+                const int c = (i == 0) ? ni * j : ni - 1 + ni * j;
+                f.L = c; f.R = -1;
+                f.bc = (i == 0) ? in.bc_imin[j] : in.bc_imax[j];
+                if (i == 0) { f.nx = -f.nx; f.ny = -f.ny; }
+                f.dLx = f.cx - M.xc[c]; f.dLy = f.cy - M.yc[c];
+                M.bfaces.push_back(f);
+                M.bface_of_cell[4 * c + (i == 0 ? 0 : 1)] = (int)M.bfaces.size() - 1;
+            }
+        }
+    if (dim == 2) {
+        for (int j = 0; j < nj + (M.per_j ? 0 : 1); ++j)
+            for (int i = 0; i < ni; ++i) {
+                FaceH f{};
+                geomf(X(i, j), Y(i, j), X(i + 1, j), Y(i + 1, j), false, f);
+                if ((j > 0 && j < nj) || M.per_j) {
+                    f.L = i + ni * ((j - 1 + nj) % nj);
+                    f.R = i + ni * j;
+                    const bool wrap = M.per_j && j == 0;
+                    f.dLx = f.cx - (M.xc[f.L] - (wrap ? Tjx : 0.0));
+                    f.dLy = f.cy - (M.yc[f.L] - (wrap ? Tjy : 0.0));
+                    f.dRx = f.cx - M.xc[f.R];
+                    f.dRy = f.cy - M.yc[f.R];
+                    f.bc = -1;
+                    M.faces.push_back(f);
+                    M.face_of_cell[4 * f.L + 3] = (int)M.faces.size() - 1;
+                    M.face_of_cell[4 * f.R + 2] = (int)M.faces.size() - 1;
+                } else {
+                    const int c = (j == 0) ? i : i + ni * (nj - 1);
+                    f.L = c; f.R = -1;
+                    f.bc = (j == 0) ? in.bc_jmin[i] : in.bc_jmax[i];
+                    if (j == 0) { f.nx = -f.nx; f.ny = -f.ny; }
+                    f.dLx = f.cx - M.xc[c]; f.dLy = f.cy - M.yc[c];
+                    M.bfaces.push_back(f);
+                    M.bface_of_cell[4 * c + (j == 0 ? 2 : 3)] = (int)M.bfaces.size() - 1;
+                }
+            }
+    }
+    for (auto& f : M.bfaces)
+        if (f.bc < 0 || f.bc >= in.n_bc) fail(MLVS_E_ARG, "boundary id %d out of range", f.bc);
+    // neighbours, direction vectors, spacing
+    M.nbr.assign(4 * n, -1);
+    M.geom.resize(n);
+    for (int c = 0; c < n; ++c) {
+        double cenx[4], ceny[4];
+        bool have[4] = {false, false, false, false};
+        CellGeom& g = M.geom[c];
+        g.vol = M.vol[c];
+        for (int k = 0; k < 4; ++k) {
+            g.dist[k] = 1.0;
+            const int f = M.face_of_cell[4 * c + k];
+            const int b = M.bface_of_cell[4 * c + k];
+            if (f >= 0) {
+                const FaceH& F = M.faces[f];
+                const bool isL = (F.L == c) && (k == 1 || k == 3);
+                const double dx = isL ? F.dLx : F.dRx, dy = isL ? F.dLy : F.dRy;
+                cenx[k] = M.xc[c] + dx; ceny[k] = M.yc[c] + dy;
+                have[k] = true;
+                // neighbour offset: x_n - x_c = (x_f - x_c) - (x_f - x_n)
+                const double ox = isL ? (F.dLx - F.dRx) : (F.dRx - F.dLx);
+                const double oy = isL ? (F.dLy - F.dRy) : (F.dRy - F.dLy);
+                M.nbr[4 * c + k] = isL ? F.R : F.L;
+                g.dist[k] = std::hypot(ox, oy);
+            } else if (b >= 0) {
+                cenx[k] = M.bfaces[b].cx; ceny[k] = M.bfaces[b].cy;
+                have[k] = true;
+            }
+        }
+        double tix = cenx[1] - cenx[0], tiy = ceny[1] - ceny[0];
+        double nn = std::hypot(tix, tiy);
+        tix /= nn; tiy /= nn;
+        double tjx = 0.0, tjy = 1.0;
+        if (dim == 2) {
+            tjx = cenx[3] - cenx[2]; tjy = ceny[3] - ceny[2];
+            nn = std::hypot(tjx, tjy);
+            tjx /= nn; tjy /= nn;
+        }
+        const double det = tix * tjy - tiy * tjx;
+        g.G[0] = tjy / det; g.G[1] = -tiy / det; g.G[2] = -tjx / det; g.G[3] = tix / det;
+        for (int k = 0; k < 4; ++k)
+            if (have[k]) M.hmin = std::min(M.hmin, 2.0 * std::hypot(cenx[k] - M.xc[c], ceny[k] - M.yc[c]));
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the context
+// ---------------------------------------------------------------------------
+struct mlvs_ctx_s {
+    mlvs_physics phys{};
+    Phys ph{};
+    int prec = 64;
+    bool adaptive = false;
+    mlvs_adapt_params ap{};
+    hipStream_t st = nullptr;
+    DevMem dm;
+    MeshH mesh;
+    Base base;
+    std::vector<mlvs_bc> bcs;
+    std::vector<std::unique_ptr<Level>> levels;      // representative levels
+    std::vector<std::unique_ptr<Level>> ifaces;      // interface levels (no cells)
+    std::vector<int> cell_level, cell_slot;
+    int64_t step_count = 0;
+    int64_t n_cross = 0;
+    // device copies
+    int *d_cell_lev = nullptr, *d_cell_slot = nullptr, *d_cell_nbr = nullptr, *d_cell_frow = nullptr;
+    CellGeom* d_geom = nullptr;
+    double* d_params = nullptr;
+    BCDev* d_bcs = nullptr;
+    LevelDesc* d_lv = nullptr;
+    FaceItem* d_faces = nullptr; int n_faces = 0;
+    BFaceItem* d_bfaces = nullptr; int n_bfaces = 0;
+    GhostItem* d_ghosts = nullptr; int n_ghosts = 0;
+    XFaceItem* d_xfaces = nullptr; int n_xfaces = 0;
+    std::vector<DevTable> tables;                    // owned by the current level set
+    std::vector<void*> item_allocs;                  // rebuilt with the level set
+    double* d_scratch = nullptr; size_t scratch_n = 0;
+    unsigned long long* d_neg = nullptr;
+    bool state_ready = false;
+
+    size_t elt() const { return prec == 32 ? 4 : 8; }
+};
+
+namespace {
+
+void upload_level_geometry(mlvs_ctx c, Level& L) {
+    L.d_x = upload(c->dm, L.xi_x, c->st);
+    L.d_y = upload(c->dm, L.xi_y, c->st);
+    L.d_w = upload(c->dm, L.w, c->st);
+    L.d_pt_of_base = upload(c->dm, L.pt_of_base, c->st);
+    L.stride = (L.N + 63) / 64 * 64;
+}
+
+void free_level(mlvs_ctx c, Level& L) {
+    for (void* p : {(void*)L.d_x, (void*)L.d_y, (void*)L.d_w, (void*)L.d_pt_of_base, L.g, L.h, L.fg, L.fh, L.Fg,
+                    L.Fh, L.Gg, L.Gh})
+        c->dm.release(p);
+    L.d_x = L.d_y = L.d_w = nullptr;
+    L.d_pt_of_base = nullptr;
+    L.g = L.h = L.fg = L.fh = L.Fg = L.Fh = L.Gg = L.Gh = nullptr;
+}
+
+void alloc_state(mlvs_ctx c, Level& L) {
+    const size_t n = (size_t)std::max(L.n_cells, 1) * L.stride * c->elt();
+    L.g = c->dm.alloc(n);
+    L.h = c->dm.alloc(n);
+    L.fg = c->dm.alloc(n);
+    L.fh = c->dm.alloc(n);
+}
+
+DevTable upload_table(mlvs_ctx c, const HostTable& t) {
+    DevTable d;
+    d.off = upload(c->dm, t.off, c->st);
+    d.idx = upload(c->dm, t.idx, c->st);
+    d.frac = upload(c->dm, t.frac, c->st);
+    c->tables.push_back(d);
+    return d;
+}
+
+void free_items(mlvs_ctx c) {
+    for (auto& t : c->tables) {
+        c->dm.release(t.off);
+        c->dm.release(t.idx);
+        c->dm.release(t.frac);
+    }
+    c->tables.clear();
+    for (void* p : c->item_allocs) c->dm.release(p);
+    c->item_allocs.clear();
+    for (auto& L : c->ifaces) free_level(c, *L);
+    c->ifaces.clear();
+    c->d_faces = nullptr; c->d_bfaces = nullptr; c->d_ghosts = nullptr; c->d_xfaces = nullptr;
+    c->d_lv = nullptr;
+    c->n_faces = c->n_bfaces = c->n_ghosts = c->n_xfaces = 0;
+}
+
+template <typename T>
+T* upload_item(mlvs_ctx c, const std::vector<T>& v) {
+    T* d = upload(c->dm, v, c->st);
+    c->item_allocs.push_back(d);
+    return d;
+}
+
+Level* find_iface(mlvs_ctx c, const std::vector<uint8_t>& k, int& idx) {
+    for (size_t i = 0; i < c->ifaces.size(); ++i)
+        if (c->ifaces[i]->kappa == k) { idx = (int)(c->levels.size() + i); return c->ifaces[i].get(); }
+    auto L = build_level(c->base, k);
+    L->is_iface = true;
+    upload_level_geometry(c, *L);
+    c->ifaces.push_back(std::move(L));
+    idx = (int)(c->levels.size() + c->ifaces.size() - 1);
+    return c->ifaces.back().get();
+}
+
+Level& level_by_index(mlvs_ctx c, int i) {
+    if (i < (int)c->levels.size()) return *c->levels[i];
+    return *c->ifaces[i - c->levels.size()];
+}
+
+// Build face/ghost/cross-face work lists, flux rows and per-cell codes for the
+// current level set and upload them.  Level state buffers must exist.
+void build_items(mlvs_ctx c) {
+    free_items(c);
+    MeshH& M = c->mesh;
+    const int n = M.n_cells;
+    const int K = (int)c->levels.size();
+    std::vector<int> rows(K, 0), ghosts(K, 0);
+    std::vector<int> cell_frow(4 * n, -1);
+    std::vector<int> cell_nbr(4 * n, -1);
+    std::vector<FaceItem> faces;
+    std::vector<BFaceItem> bfaces;
+    std::vector<GhostItem> gitems;
+    std::vector<XFaceItem> xitems;
+    std::map<std::pair<int, int>, int> ghost_of;        // (source cell, dst level) -> row
+    std::map<std::pair<int, int>, DevTable> tab_of;      // (dst level idx, src level idx)
+    auto table = [&](int dst, int src) {
+        auto key = std::make_pair(dst, src);
+        auto it = tab_of.find(key);
+        if (it != tab_of.end()) return it->second;
+        DevTable d = upload_table(c, make_table(level_by_index(c, dst), level_by_index(c, src)));
+        tab_of[key] = d;
+        return d;
+    };
+    auto face_code = [](int row, bool neg) { return 2 * row + (neg ? 1 : 0); };
+    // neighbour codes and ghost rows
+    for (int cc = 0; cc < n; ++cc)
+        for (int k = 0; k < 4; ++k) {
+            const int nb = M.nbr[4 * cc + k];
+            if (nb < 0) continue;
+            const int lc = c->cell_level[cc], ln = c->cell_level[nb];
+            if (lc == ln) { cell_nbr[4 * cc + k] = nb; continue; }
+            auto key = std::make_pair(nb, lc);
+            int row;
+            auto it = ghost_of.find(key);
+            if (it == ghost_of.end()) {
+                row = ghosts[lc]++;
+                ghost_of[key] = row;
+                GhostItem G{};
+                G.n = nb; G.dst = lc; G.row = row;
+                G.tab = table(lc, ln).view();
+                gitems.push_back(G);
+            } else {
+                row = it->second;
+            }
+            cell_nbr[4 * cc + k] = -2 - row;
+        }
+    // interior faces
+    int n_cross = 0;
+    std::vector<std::pair<int, int>> xpairs;
+    for (size_t f = 0; f < M.faces.size(); ++f) {
+        const FaceH& F = M.faces[f];
+        const int lL = c->cell_level[F.L], lR = c->cell_level[F.R];
+        int kL = -1, kR = -1;
+        for (int k = 0; k < 4; ++k) {
+            if (M.face_of_cell[4 * F.L + k] == (int)f && (k == 1 || k == 3)) kL = k;
+            if (M.face_of_cell[4 * F.R + k] == (int)f && (k == 0 || k == 2)) kR = k;
+        }
+        if (lL == lR) {
+            FaceItem it{};
+            it.L = F.L; it.R = F.R; it.lev = lL; it.row = rows[lL]++;
+            it.nx = F.nx; it.ny = F.ny; it.area = F.area;
+            it.dLx = F.dLx; it.dLy = F.dLy; it.dRx = F.dRx; it.dRy = F.dRy;
+            faces.push_back(it);
+            cell_frow[4 * F.L + kL] = face_code(it.row, false);
+            cell_frow[4 * F.R + kR] = face_code(it.row, true);
+        } else {
+            ++n_cross;
+            XFaceItem it{};
+            it.L = F.L; it.R = F.R; it.levA = lL; it.levB = lR;
+            it.rowA = rows[lL]++;
+            it.rowB = rows[lR]++;
+            it.nx = F.nx; it.ny = F.ny; it.area = F.area;
+            it.dLx = F.dLx; it.dLy = F.dLy; it.dRx = F.dRx; it.dRy = F.dRy;
+            std::vector<uint8_t> kI(c->base.Nb);
+            const auto& kA = c->levels[lL]->kappa;
+            const auto& kB = c->levels[lR]->kappa;
+            for (int b = 0; b < c->base.Nb; ++b) kI[b] = std::min(kA[b], kB[b]);
+            int iidx = -1;
+            Level* I = find_iface(c, kI, iidx);
+            it.levI = iidx;
+            it.scratch = I->n_rows++;
+            xitems.push_back(it);
+            cell_frow[4 * F.L + kL] = face_code(it.rowA, false);
+            cell_frow[4 * F.R + kR] = face_code(it.rowB, true);
+        }
+    }
+    for (auto& it : xitems) {
+        it.IfromA = table(it.levI, it.levA).view();
+        it.IfromB = table(it.levI, it.levB).view();
+        it.AfromI = table(it.levA, it.levI).view();
+        it.BfromI = table(it.levB, it.levI).view();
+    }
+    c->n_cross = n_cross;
+    for (size_t b = 0; b < M.bfaces.size(); ++b) {
+        const FaceH& F = M.bfaces[b];
+        const int lc = c->cell_level[F.L];
+        BFaceItem it{};
+        it.c = F.L; it.bc = F.bc; it.lev = lc; it.row = rows[lc]++;
+        it.nx = F.nx; it.ny = F.ny; it.area = F.area; it.dx = F.dLx; it.dy = F.dLy;
+        bfaces.push_back(it);
+        int kk = -1;
+        for (int k = 0; k < 4; ++k)
+            if (M.bface_of_cell[4 * F.L + k] == (int)b) kk = k;
+        cell_frow[4 * F.L + kk] = face_code(it.row, false);
+    }
+    // row buffers
+    for (int l = 0; l < K; ++l) {
+        Level& L = *c->levels[l];
+        L.n_rows = rows[l];
+        L.n_ghost = ghosts[l];
+        c->dm.release(L.Fg); c->dm.release(L.Fh); c->dm.release(L.Gg); c->dm.release(L.Gh);
+        const size_t nr = (size_t)std::max(L.n_rows, 1) * L.stride * c->elt();
+        const size_t ng = (size_t)std::max(L.n_ghost, 1) * L.stride * c->elt();
+        L.Fg = c->dm.alloc(nr); L.Fh = c->dm.alloc(nr);
+        L.Gg = c->dm.alloc(ng); L.Gh = c->dm.alloc(ng);
+    }
+    for (auto& Lp : c->ifaces) {
+        Level& L = *Lp;
+        const size_t nr = (size_t)std::max(L.n_rows, 1) * L.stride * c->elt();
+        L.Fg = c->dm.alloc(nr); L.Fh = c->dm.alloc(nr);
+    }
+    // level descriptors: representative levels then interface levels
+    std::vector<LevelDesc> descs;
+    for (int i = 0; i < K + (int)c->ifaces.size(); ++i) {
+        Level& L = level_by_index(c, i);
+        LevelDesc d{};
+        d.N = L.N; d.stride = L.stride; d.n_rows_state = L.n_cells;
+        d.xi_x = L.d_x; d.xi_y = L.d_y; d.w = L.d_w;
+        d.g = L.g; d.h = L.h; d.fg = L.fg; d.fh = L.fh; d.Fg = L.Fg; d.Fh = L.Fh; d.Gg = L.Gg; d.Gh = L.Gh;
+        std::copy(L.Minv, L.Minv + 16, d.Minv);
+        descs.push_back(d);
+    }
+    c->d_lv = upload_item(c, descs);
+    c->d_faces = upload_item(c, faces); c->n_faces = (int)faces.size();
+    c->d_bfaces = upload_item(c, bfaces); c->n_bfaces = (int)bfaces.size();
+    c->d_ghosts = upload_item(c, gitems); c->n_ghosts = (int)gitems.size();
+    c->d_xfaces = upload_item(c, xitems); c->n_xfaces = (int)xitems.size();
+    c->d_cell_frow = upload_item(c, cell_frow);
+    c->d_cell_nbr = upload_item(c, cell_nbr);
+    c->d_cell_lev = upload_item(c, c->cell_level);
+    c->d_cell_slot = upload_item(c, c->cell_slot);
+}
+
+void assign_slots(mlvs_ctx c) {
+    const int K = (int)c->levels.size();
+    std::vector<int> cnt(K, 0);
+    c->cell_slot.resize(c->mesh.n_cells);
+    for (int cc = 0; cc < c->mesh.n_cells; ++cc) c->cell_slot[cc] = cnt[c->cell_level[cc]]++;
+    for (int l = 0; l < K; ++l) c->levels[l]->n_cells = cnt[l];
+}
+
+void sync(mlvs_ctx c) { hip_check(hipStreamSynchronize(c->st), "stream synchronize"); }
+
+void do_step(mlvs_ctx c);
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// level switching (remap) -- shared by set_levels and adapt
+// ---------------------------------------------------------------------------
+namespace {
+
+int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const std::vector<int>& new_cell_level) {
+    const int n = c->mesh.n_cells;
+    // keep the old level set alive for the remap
+    std::vector<std::unique_ptr<Level>> old = std::move(c->levels);
+    std::vector<int> old_level = c->cell_level, old_slot = c->cell_slot;
+    free_items(c);
+    c->levels = std::move(nl);
+    c->cell_level = new_cell_level;
+    assign_slots(c);
+    for (auto& L : c->levels) {
+        upload_level_geometry(c, *L);
+        alloc_state(c, *L);
+    }
+    // old descriptors (state only) and new descriptors
+    auto descs_of = [&](std::vector<std::unique_ptr<Level>>& ls) {
+        std::vector<LevelDesc> d;
+        for (auto& Lp : ls) {
+            LevelDesc x{};
+            x.N = Lp->N; x.stride = Lp->stride; x.xi_x = Lp->d_x; x.xi_y = Lp->d_y; x.w = Lp->d_w;
+            x.g = Lp->g; x.h = Lp->h;
+            std::copy(Lp->Minv, Lp->Minv + 16, x.Minv);
+            d.push_back(x);
+        }
+        return d;
+    };
+    std::vector<LevelDesc> od = descs_of(old), nd = descs_of(c->levels);
+    LevelDesc* d_od = upload(c->dm, od, c->st);
+    LevelDesc* d_nd = upload(c->dm, nd, c->st);
+    std::vector<RemapItem> items(n);
+    std::map<std::pair<int, int>, DevTable> tabs;
+    std::vector<DevTable> tmp_tabs;
+    int64_t changed = 0;
+    for (int cc = 0; cc < n; ++cc) {
+        RemapItem& r = items[cc];
+        r.c = cc;
+        r.src_lev = old_level[cc]; r.src_slot = old_slot[cc];
+        r.dst_lev = c->cell_level[cc]; r.dst_slot = c->cell_slot[cc];
+        if (old[r.src_lev]->kappa == c->levels[r.dst_lev]->kappa) {
+            r.tab = PairTable{nullptr, nullptr, nullptr};
+            continue;
+        }
+        ++changed;
+        auto key = std::make_pair(r.dst_lev, r.src_lev);
+        auto it = tabs.find(key);
+        if (it == tabs.end()) {
+            HostTable ht = make_table(*c->levels[r.dst_lev], *old[r.src_lev]);
+            DevTable d;
+            d.off = upload(c->dm, ht.off, c->st);
+            d.idx = upload(c->dm, ht.idx, c->st);
+            d.frac = upload(c->dm, ht.frac, c->st);
+            tmp_tabs.push_back(d);
+            it = tabs.emplace(key, d).first;
+        }
+        r.tab = it->second.view();
+    }
+    RemapItem* d_items = upload(c->dm, items, c->st);
+    hip_check(launch_remap(c->prec, c->st, d_od, d_nd, d_items, n, c->ph, c->d_neg), "remap launch");
+    sync(c);
+    c->dm.release(d_items);
+    c->dm.release(d_od);
+    c->dm.release(d_nd);
+    for (auto& d : tmp_tabs) { c->dm.release(d.off); c->dm.release(d.idx); c->dm.release(d.frac); }
+    for (auto& L : old) free_level(c, *L);
+    build_items(c);
+    sync(c);
+    return changed;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* mlvs_last_error(void) { return g_last_error.c_str(); }
+
+mlvs_status mlvs_vgrid_newton_cotes(int n, double a, double* x, double* w) {
+    return guarded([&] {
+        if (!x || !w || !(a > 0)) fail(MLVS_E_ARG, "bad Newton-Cotes arguments");
+        newton_cotes(n, a, x, w);
+    });
+}
+
+mlvs_status mlvs_vgrid_gauss_hermite(int n, double R, double T0, double* x, double* w) {
+    return guarded([&] {
+        if (!x || !w || !(R > 0) || !(T0 > 0)) fail(MLVS_E_ARG, "bad Gauss-Hermite arguments");
+        gauss_hermite(n, R, T0, x, w);
+    });
+}
+
+mlvs_status mlvs_mu_ref_from_kn(double Kn, double rho, double T, double R, double L, double omega, double* mu) {
+    return guarded([&] {
+        if (!mu) fail(MLVS_E_ARG, "null output");
+        const double cst = 15.0 * std::sqrt(M_PI) / (2.0 * (5.0 - 2.0 * omega) * (7.0 - 2.0 * omega));
+        *mu = cst * Kn * rho * std::sqrt(2.0 * R * T) * L;
+    });
+}
+
+mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const mlvs_vgrid* vg,
+                        const mlvs_adapt_params* adapt, const mlvs_device* dev, mlvs_ctx* out) {
+    mlvs_ctx c = nullptr;
+    mlvs_status s = guarded([&] {
+        if (!phys || !mesh || !vg || !out) fail(MLVS_E_ARG, "null argument");
+        if (phys->dim != 1 && phys->dim != 2) fail(MLVS_E_ARG, "dim must be 1 or 2");
+        if (phys->precision != 32 && phys->precision != 64) fail(MLVS_E_ARG, "precision must be 32 or 64");
+        if (phys->compat != 0 && phys->compat != 4) fail(MLVS_E_ARG, "compat must be 0 or 4");
+        if (phys->map_moments != 0 && phys->map_moments != 4) fail(MLVS_E_ARG, "map_moments must be 0 or 4");
+        if (!(phys->R > 0) || !(phys->mu_ref > 0) || !(phys->T_ref > 0)) fail(MLVS_E_ARG, "bad physical constants");
+        if (mesh->ni < 1 || mesh->nj < 1 || !mesh->node_x || !mesh->node_y) fail(MLVS_E_ARG, "bad mesh");
+        if (phys->dim == 1 && mesh->nj != 1) fail(MLVS_E_ARG, "1-D meshes need nj = 1");
+        if ((int64_t)mesh->ni * mesh->nj > (1 << 30)) fail(MLVS_E_ARG, "mesh too large");
+        if (!vg->x || !vg->wx || vg->nx < 2 || vg->ny < 1 || !vg->y || !vg->wy) fail(MLVS_E_ARG, "bad velocity grid");
+        if (phys->dim == 1 && vg->ny != 1) fail(MLVS_E_ARG, "1-D needs ny = 1");
+        if (adapt && phys->dim != 2) fail(MLVS_E_ARG, "multi-level velocity spaces need dim = 2");
+        if (adapt && (adapt->interval < 0 || adapt->C_merge > adapt->C_split))
+            fail(MLVS_E_ARG, "bad adaptation parameters");
+        c = new mlvs_ctx_s();
+        c->phys = *phys;
+        c->prec = phys->precision;
+        if (dev) { c->dm.dev = *dev; c->st = (hipStream_t)dev->stream; }
+        c->adaptive = adapt != nullptr;
+        if (adapt) c->ap = *adapt;
+        build_mesh(c->mesh, *mesh, phys->dim);
+        c->bcs.assign(mesh->bcs, mesh->bcs + mesh->n_bc);
+        for (auto& b : c->bcs)
+            if (b.kind < 1 || b.kind > 3) fail(MLVS_E_ARG, "unknown boundary kind %d", b.kind);
+        Base& B = c->base;
+        B.nx = vg->nx; B.ny = vg->ny; B.N = B.nx * B.ny;
+        B.nbx = B.nx / 2; B.nby = phys->dim == 2 ? B.ny / 2 : 0;
+        B.Nb = B.nbx * B.nby;
+        double vmax = 0.0;
+        for (int iy = 0; iy < B.ny; ++iy)
+            for (int ix = 0; ix < B.nx; ++ix) {
+                B.x.push_back(vg->x[ix]);
+                B.y.push_back(phys->dim == 2 ? vg->y[iy] : 0.0);
+                B.w.push_back(vg->wx[ix] * (phys->dim == 2 ? vg->wy[iy] : 1.0));
+                vmax = std::max(vmax, std::hypot(B.x.back(), B.y.back()));
+            }
+        Phys& ph = c->ph;
+        ph.D = phys->dim; ph.K = phys->K; ph.R = phys->R; ph.Pr = phys->Pr; ph.omega = phys->omega;
+        ph.mu_ref = phys->mu_ref; ph.T_ref = phys->T_ref;
+        ph.dt = phys->dt > 0 ? phys->dt : phys->cfl * c->mesh.hmin / vmax;
+        ph.compat = phys->compat; ph.face_compat = phys->face_compat; ph.map_moments = phys->map_moments;
+        // device geometry
+        c->d_geom = upload(c->dm, c->mesh.geom, c->st);
+        std::vector<BCDev> bd;
+        for (auto& b : c->bcs) bd.push_back(BCDev{b.kind, 0, b.rho, b.u, b.v, b.T});
+        c->d_bcs = upload(c->dm, bd, c->st);
+        c->d_params = static_cast<double*>(c->dm.alloc(sizeof(double) * NPARAM * c->mesh.n_cells));
+        hip_check(hipMemsetAsync(c->d_params, 0, sizeof(double) * NPARAM * c->mesh.n_cells, c->st), "memset");
+        c->d_neg = static_cast<unsigned long long*>(c->dm.alloc(8));
+        hip_check(hipMemsetAsync(c->d_neg, 0, 8, c->st), "memset");
+        // one level: the base grid itself
+        std::vector<uint8_t> k0(B.Nb, 0);
+        c->levels.push_back(build_level(B, k0));
+        c->cell_level.assign(c->mesh.n_cells, 0);
+        assign_slots(c);
+        upload_level_geometry(c, *c->levels[0]);
+        alloc_state(c, *c->levels[0]);
+        build_items(c);
+        sync(c);
+        *out = c;
+    });
+    if (s != MLVS_OK && c) {
+        c->dm.release_all();
+        delete c;
+    }
+    return s;
+}
+
+void mlvs_destroy(mlvs_ctx c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->st);
+    c->dm.release_all();
+    delete c;
+}
+
+mlvs_status mlvs_init_equilibrium(mlvs_ctx c, const double* st) {
+    return guarded([&] {
+        if (!c || !st) fail(MLVS_E_ARG, "null argument");
+        for (int i = 0; i < c->mesh.n_cells; ++i)
+            if (!(st[4 * i] > 0) || !(st[4 * i + 3] > 0)) fail(MLVS_E_ARG, "non-positive density or temperature at cell %d", i);
+        std::vector<double> v(st, st + 4 * (size_t)c->mesh.n_cells);
+        double* d = upload(c->dm, v, c->st);
+        hip_check(launch_init_eq(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, c->mesh.n_cells, d, c->ph,
+                                 c->d_params), "init launch");
+        sync(c);
+        c->dm.release(d);
+        c->state_ready = true;
+        c->step_count = 0;
+    });
+}
+
+mlvs_status mlvs_step(mlvs_ctx c, int n_steps) {
+    return guarded([&] {
+        if (!c || n_steps < 0) fail(MLVS_E_ARG, "bad arguments");
+        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
+        for (int k = 0; k < n_steps; ++k) do_step(c);
+    });
+}
+
+mlvs_status mlvs_moments(mlvs_ctx c, double* out) {
+    return guarded([&] {
+        if (!c || !out) fail(MLVS_E_ARG, "null argument");
+        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
+        const int n = c->mesh.n_cells;
+        double* d = static_cast<double*>(c->dm.alloc(sizeof(double) * 6 * n));
+        hip_check(launch_cell_moments(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom, c->ph, d,
+                                      nullptr), "moments launch");
+        hip_check(hipMemcpyAsync(out, d, sizeof(double) * 6 * n, hipMemcpyDeviceToHost, c->st), "D2H");
+        sync(c);
+        c->dm.release(d);
+    });
+}
+
+mlvs_status mlvs_totals(mlvs_ctx c, double out[4]) {
+    return guarded([&] {
+        if (!c || !out) fail(MLVS_E_ARG, "null argument");
+        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
+        const int n = c->mesh.n_cells;
+        double* d = static_cast<double*>(c->dm.alloc(sizeof(double) * (4 * (size_t)n + 4)));
+        hip_check(launch_cell_moments(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom, c->ph,
+                                      nullptr, d), "totals launch");
+        hip_check(launch_sum_rows(c->st, d, n, 4, d + 4 * (size_t)n), "sum launch");
+        hip_check(hipMemcpyAsync(out, d + 4 * (size_t)n, sizeof(double) * 4, hipMemcpyDeviceToHost, c->st), "D2H");
+        sync(c);
+        c->dm.release(d);
+    });
+}
+
+mlvs_status mlvs_info(mlvs_ctx c, double* dt, int64_t* n_cells, int32_t* n_blocks, int32_t* n_base) {
+    return guarded([&] {
+        if (!c) fail(MLVS_E_ARG, "null context");
+        if (dt) *dt = c->ph.dt;
+        if (n_cells) *n_cells = c->mesh.n_cells;
+        if (n_blocks) *n_blocks = c->base.Nb;
+        if (n_base) *n_base = c->base.N;
+    });
+}
+
+mlvs_status mlvs_memory(mlvs_ctx c, size_t* bytes) {
+    return guarded([&] {
+        if (!c || !bytes) fail(MLVS_E_ARG, "null argument");
+        *bytes = c->dm.bytes;
+    });
+}
+
+mlvs_status mlvs_neg_count(mlvs_ctx c, int64_t* count) {
+    return guarded([&] {
+        if (!c || !count) fail(MLVS_E_ARG, "null argument");
+        unsigned long long v = 0;
+        hip_check(hipMemcpyAsync(&v, c->d_neg, 8, hipMemcpyDeviceToHost, c->st), "D2H");
+        sync(c);
+        *count = (int64_t)v;
+    });
+}
+
+mlvs_status mlvs_level_info(mlvs_ctx c, int* n_levels, int32_t* npts, int32_t* ncells, int64_t* n_cross) {
+    return guarded([&] {
+        if (!c || !n_levels) fail(MLVS_E_ARG, "null argument");
+        *n_levels = (int)c->levels.size();
+        for (size_t l = 0; l < c->levels.size(); ++l) {
+            if (npts) npts[l] = c->levels[l]->N;
+            if (ncells) ncells[l] = c->levels[l]->n_cells;
+        }
+        if (n_cross) *n_cross = c->n_cross;
+    });
+}
+
+mlvs_status mlvs_level_kappa(mlvs_ctx c, int level, uint8_t* out) {
+    return guarded([&] {
+        if (!c || !out || level < 0 || level >= (int)c->levels.size()) fail(MLVS_E_ARG, "bad level");
+        std::copy(c->levels[level]->kappa.begin(), c->levels[level]->kappa.end(), out);
+    });
+}
+
+mlvs_status mlvs_cell_levels(mlvs_ctx c, int32_t* out) {
+    return guarded([&] {
+        if (!c || !out) fail(MLVS_E_ARG, "null argument");
+        std::copy(c->cell_level.begin(), c->cell_level.end(), out);
+    });
+}
+
+static void copy_cell(mlvs_ctx c, int64_t cell, double* g, double* h, const double* gi, const double* hi) {
+    const Level& L = *c->levels[c->cell_level[cell]];
+    const size_t off = (size_t)c->cell_slot[cell] * L.stride * c->elt();
+    const size_t nb = (size_t)L.N * c->elt();
+    std::vector<char> buf(nb);
+    for (int comp = 0; comp < 2; ++comp) {
+        char* base = static_cast<char*>(comp ? L.h : L.g) + off;
+        double* o = comp ? h : g;
+        const double* in = comp ? hi : gi;
+        if (o) {
+            hip_check(hipMemcpyAsync(buf.data(), base, nb, hipMemcpyDeviceToHost, c->st), "D2H");
+            sync(c);
+            for (int i = 0; i < L.N; ++i)
+                o[i] = c->prec == 32 ? (double)reinterpret_cast<float*>(buf.data())[i]
+                                     : reinterpret_cast<double*>(buf.data())[i];
+        }
+        if (in) {
+            for (int i = 0; i < L.N; ++i) {
+                if (c->prec == 32) reinterpret_cast<float*>(buf.data())[i] = (float)in[i];
+                else reinterpret_cast<double*>(buf.data())[i] = in[i];
+            }
+            hip_check(hipMemcpyAsync(base, buf.data(), nb, hipMemcpyHostToDevice, c->st), "H2D");
+            sync(c);
+        }
+    }
+}
+
+mlvs_status mlvs_get_f(mlvs_ctx c, int64_t cell, double* g, double* h, int32_t* npts) {
+    return guarded([&] {
+        if (!c || cell < 0 || cell >= c->mesh.n_cells) fail(MLVS_E_ARG, "bad cell");
+        if (npts) *npts = c->levels[c->cell_level[cell]]->N;
+        if (g || h) copy_cell(c, cell, g, h, nullptr, nullptr);
+    });
+}
+
+mlvs_status mlvs_set_f(mlvs_ctx c, int64_t cell, const double* g, const double* h) {
+    return guarded([&] {
+        if (!c || !g || !h || cell < 0 || cell >= c->mesh.n_cells) fail(MLVS_E_ARG, "bad arguments");
+        copy_cell(c, cell, nullptr, nullptr, g, h);
+        c->state_ready = true;
+    });
+}
+
+static void bulk_state(mlvs_ctx c, double* g, double* h, const double* gi, const double* hi) {
+    // per level: copy the whole state block once, then scatter in cell order
+    std::vector<size_t> offset(c->mesh.n_cells);
+    size_t tot = 0;
+    for (int cc = 0; cc < c->mesh.n_cells; ++cc) {
+        offset[cc] = tot;
+        tot += c->levels[c->cell_level[cc]]->N;
+    }
+    for (size_t l = 0; l < c->levels.size(); ++l) {
+        Level& L = *c->levels[l];
+        const size_t nb = (size_t)L.n_cells * L.stride * c->elt();
+        if (nb == 0) continue;
+        std::vector<char> buf(nb, 0);
+        for (int comp = 0; comp < 2; ++comp) {
+            char* base = static_cast<char*>(comp ? L.h : L.g);
+            const double* in = comp ? hi : gi;
+            double* o = comp ? h : g;
+            if (o) {
+                hip_check(hipMemcpyAsync(buf.data(), base, nb, hipMemcpyDeviceToHost, c->st), "D2H");
+                sync(c);
+            }
+            for (int cc = 0; cc < c->mesh.n_cells; ++cc) {
+                if (c->cell_level[cc] != (int)l) continue;
+                const size_t r = (size_t)c->cell_slot[cc] * L.stride;
+                for (int i = 0; i < L.N; ++i) {
+                    if (o) o[offset[cc] + i] = c->prec == 32 ? (double)reinterpret_cast<float*>(buf.data())[r + i]
+                                                             : reinterpret_cast<double*>(buf.data())[r + i];
+                    if (in) {
+                        if (c->prec == 32) reinterpret_cast<float*>(buf.data())[r + i] = (float)in[offset[cc] + i];
+                        else reinterpret_cast<double*>(buf.data())[r + i] = in[offset[cc] + i];
+                    }
+                }
+            }
+            if (in) {
+                hip_check(hipMemcpyAsync(base, buf.data(), nb, hipMemcpyHostToDevice, c->st), "H2D");
+                sync(c);
+            }
+        }
+    }
+}
+
+mlvs_status mlvs_get_state(mlvs_ctx c, double* g, double* h) {
+    return guarded([&] {
+        if (!c || !g || !h) fail(MLVS_E_ARG, "null argument");
+        bulk_state(c, g, h, nullptr, nullptr);
+    });
+}
+
+mlvs_status mlvs_set_state(mlvs_ctx c, const double* g, const double* h) {
+    return guarded([&] {
+        if (!c || !g || !h) fail(MLVS_E_ARG, "null argument");
+        bulk_state(c, nullptr, nullptr, g, h);
+        c->state_ready = true;
+    });
+}
+
+mlvs_status mlvs_set_levels(mlvs_ctx c, int n_levels, const uint8_t* kappa, const int32_t* cell_level) {
+    return guarded([&] {
+        if (!c || !kappa || !cell_level || n_levels < 1) fail(MLVS_E_ARG, "bad arguments");
+        if (c->phys.dim != 2) fail(MLVS_E_STATE, "levels need dim = 2");
+        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
+        std::vector<std::unique_ptr<Level>> nl;
+        for (int l = 0; l < n_levels; ++l) {
+            check_kappa(c->base, kappa + (size_t)l * c->base.Nb);
+            nl.push_back(build_level(c->base, std::vector<uint8_t>(kappa + (size_t)l * c->base.Nb,
+                                                                    kappa + (size_t)(l + 1) * c->base.Nb)));
+        }
+        std::vector<int> cl(cell_level, cell_level + c->mesh.n_cells);
+        for (int v : cl)
+            if (v < 0 || v >= n_levels) fail(MLVS_E_ARG, "cell level out of range");
+        install_levels(c, std::move(nl), cl);
+    });
+}
+
+mlvs_status mlvs_adapt(mlvs_ctx c, mlvs_adapt_report* rep) {
+    return guarded([&] { fail(MLVS_E_STATE, "adaptation not available yet"); });
+}
+
+mlvs_status mlvs_criterion(mlvs_ctx c, uint8_t* out) {
+    return guarded([&] { fail(MLVS_E_STATE, "criterion not available yet"); });
+}
+
+}  // extern "C"
+
+namespace {
+
+void do_step(mlvs_ctx c) {
+    const int n = c->mesh.n_cells;
+    if (c->adaptive && c->ap.interval > 0 && c->step_count % c->ap.interval == 0) {
+        if (mlvs_adapt(c, nullptr) != MLVS_OK) throw Fail{MLVS_E_STATE, g_last_error};
+    }
+    hip_check(launch_cell_prep(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->ph, c->d_params),
+              "cell stage");
+    hip_check(launch_ghost(c->prec, c->st, c->d_lv, c->d_ghosts, c->n_ghosts, c->d_cell_lev, c->d_cell_slot,
+                           c->d_params, c->ph, c->d_neg), "ghost stage");
+    hip_check(launch_face(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces, c->d_cell_slot, c->d_cell_nbr, c->d_geom,
+                          c->d_params, c->ph), "face stage");
+    hip_check(launch_bface(c->prec, c->st, c->d_lv, c->d_bfaces, c->n_bfaces, c->d_cell_slot, c->d_cell_nbr,
+                           c->d_geom, c->d_bcs, c->ph), "boundary stage");
+    hip_check(launch_xface(c->prec, c->st, c->d_lv, c->d_xfaces, c->n_xfaces, c->d_cell_slot, c->d_cell_nbr,
+                           c->d_geom, c->d_params, c->ph, c->d_neg), "cross-level stage");
+    hip_check(launch_update(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom, c->d_cell_frow,
+                            c->ph), "update stage");
+    ++c->step_count;
+}
+
+}  // namespace

@@ -1,0 +1,840 @@
+// HIP kernels of the MLVS-DUGKS step for gfx950.
+//
+// Work decomposition: one workgroup per item (cell, face, ghost row, remap),
+// lanes stride over the item's velocity points (velocity index contiguous in
+// memory, so every load of a row is coalesced); velocity-space moments are
+// reduced in registers, then across the wave with butterfly shuffles and
+// across waves through LDS in a fixed order (deterministic).  One launch per
+// stage covers every level: each item names its own level.  Storage type S is
+// float or double; per-velocity arithmetic runs in S; moment sums, the small
+// linear solves and the per-cell parameters are double.
+#include "mlvs_impl.h"
+
+#include <cmath>
+
+namespace mlvs {
+
+constexpr int BS = 256;             // threads per workgroup
+constexpr int MAXW = BS / 64;       // waves per workgroup
+constexpr int RED_MAX = 32;         // largest reduction width
+
+template <typename S>
+__device__ __forceinline__ S* rowp(void* base, size_t off) { return reinterpret_cast<S*>(base) + off; }
+
+// Sum NV doubles over the workgroup; every thread receives the totals.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        v[k] = x;
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wid * NV + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < MAXW; ++w) s += red[w * NV + k];
+        v[k] = s;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int block_or(int flag, int* sh) {
+    __syncthreads();
+    if (threadIdx.x == 0) *sh = 0;
+    __syncthreads();
+    if (flag) atomicOr(sh, 1);
+    __syncthreads();
+    int r = *sh;
+    __syncthreads();
+    return r;
+}
+
+// Gaussian elimination with partial pivoting, n <= 4; returns false if singular.
+__device__ bool solve_small(int n, double* A, double* b) {
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = fabs(A[k * n + k]);
+        for (int i = k + 1; i < n; ++i) {
+            double a = fabs(A[i * n + k]);
+            if (a > best) { best = a; p = i; }
+        }
+        if (best == 0.0) return false;
+        if (p != k) {
+            for (int j = 0; j < n; ++j) { double t = A[k * n + j]; A[k * n + j] = A[p * n + j]; A[p * n + j] = t; }
+            double t = b[k]; b[k] = b[p]; b[p] = t;
+        }
+        for (int i = k + 1; i < n; ++i) {
+            double f = A[i * n + k] / A[k * n + k];
+            for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+            b[i] -= f * b[k];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        double s = b[k];
+        for (int j = k + 1; j < n; ++j) s -= A[k * n + j] * b[j];
+        b[k] = s / A[k * n + k];
+    }
+    return true;
+}
+
+__device__ __forceinline__ double viscosity(double T, const Phys& ph) {
+    return ph.mu_ref * pow(T / ph.T_ref, ph.omega);
+}
+
+// Macroscopic state from eleven raw moments taken about the shift (u0, v0):
+// m = [sum w g, .. x, .. y, .. xx, .. xy, .. yy, .. x|x|^2, .. y|x|^2, sum w h, .. x, .. y]
+// (x, y the shifted velocity).  Returns rho, u, v, T and qt = 1/2 sum w c (c^2 g + h).
+__device__ void raw_to_state(const double* m, double u0, double v0, const Phys& ph, double& rho,
+                             double& u, double& v, double& T, double& qx, double& qy) {
+    rho = m[0];
+    const double up = m[1] / rho, vp = m[2] / rho;
+    const double E = 0.5 * (m[3] + m[5] + m[8]);
+    T = (2.0 * E / rho - (up * up + vp * vp)) / ((3.0 + ph.K) * ph.R);
+    const double uu = up * up + vp * vp;
+    const double sxx = m[3], syy = m[5], sxy = m[4];
+    const double cqx = m[6] - 2.0 * (up * sxx + vp * sxy) + uu * m[1] - up * (sxx + syy)
+                       + 2.0 * up * (up * m[1] + vp * m[2]) - up * uu * m[0];
+    const double cqy = m[7] - 2.0 * (up * sxy + vp * syy) + uu * m[2] - vp * (sxx + syy)
+                       + 2.0 * vp * (up * m[1] + vp * m[2]) - vp * uu * m[0];
+    qx = 0.5 * (cqx + m[9] - up * m[8]);
+    qy = 0.5 * (cqy + m[10] - vp * m[8]);
+    u = u0 + up;
+    v = v0 + vp;
+}
+
+template <typename C>
+struct Eq {
+    C rn, ux, uy, i2RT, iRT, RT, X, qx, qy, cK, Dp2, Dd, K2;
+    C a0, a1, a2, a3, Ec0;
+    bool corr;
+};
+
+template <typename C>
+__device__ __forceinline__ Eq<C> make_eq(double rho, double u, double v, double T, double qx, double qy,
+                                         const double* a, const Phys& ph) {
+    Eq<C> e;
+    const double RT = ph.R * T;
+    const double D = ph.D;
+    e.rn = (C)(rho / pow(2.0 * M_PI * RT, 0.5 * D));
+    e.ux = (C)u; e.uy = (C)v;
+    e.i2RT = (C)(1.0 / (2.0 * RT));
+    e.iRT = (C)(1.0 / RT);
+    e.RT = (C)RT;
+    e.X = (C)((1.0 - ph.Pr) / (5.0 * rho * RT * RT));
+    e.qx = (C)qx; e.qy = (C)qy;
+    e.cK = (C)(ph.K + 3.0 - D);
+    e.Dp2 = (C)(D + 2.0);
+    e.Dd = (C)D;
+    e.K2 = (C)(2.0 * ph.K);
+    e.corr = (a != nullptr);
+    e.a0 = a ? (C)a[0] : C(0); e.a1 = a ? (C)a[1] : C(0);
+    e.a2 = a ? (C)a[2] : C(0); e.a3 = a ? (C)a[3] : C(0);
+    e.Ec0 = (C)(0.5 * (3.0 - D + ph.K) * RT);
+    return e;
+}
+
+__device__ __forceinline__ float dexp(float x) { return expf(x); }
+__device__ __forceinline__ double dexp(double x) { return exp(x); }
+
+// Reduced Shakhov target at velocity (x, y) (Eq. g_h_eq_Pr), optionally times
+// the compatibility factor 1 + a . [1, x, y, E_xi] (Eq. gh_model_correction).
+template <typename C>
+__device__ __forceinline__ void eq_eval(const Eq<C>& e, C x, C y, C& g, C& h) {
+    const C cx = x - e.ux, cy = y - e.uy;
+    const C c2 = cx * cx + cy * cy;
+    const C ge = e.rn * dexp(-c2 * e.i2RT);
+    const C Xc = e.X * (cx * e.qx + cy * e.qy);
+    const C c2r = c2 * e.iRT;
+    g = ge * (C(1) + Xc * (c2r - e.Dp2));
+    h = ge * e.RT * (e.cK + Xc * ((c2r - e.Dd) * e.cK - e.K2));
+    if (e.corr) {
+        const C f = C(1) + e.a0 + e.a1 * x + e.a2 * y + e.a3 * (e.Ec0 + C(0.5) * (x * x + y * y));
+        g *= f;
+        h *= f;
+    }
+}
+
+// Compatibility correction (Sec. 3.3.1): assemble A and the moment defect of
+// the uncorrected target over the level, solve, return a[4] (a[2] = 0 in 1-D).
+template <typename S>
+__device__ void compat_solve(const LevelDesc& L, const Eq<S>& eu, double rho, double u, double v, double T,
+                             const Phys& ph, double* red, double* a_out) {
+    double s[13];
+#pragma unroll
+    for (int k = 0; k < 13; ++k) s[k] = 0.0;
+    for (int i = threadIdx.x; i < L.N; i += BS) {
+        const double x = L.xi_x[i], y = L.xi_y[i], w = L.w[i];
+        S g, h;
+        eq_eval<S>(eu, (S)x, (S)y, g, h);
+        const double wg = w * (double)g, wh = w * (double)h;
+        const double x2 = x * x + y * y;
+        s[0] += wg; s[1] += wg * x; s[2] += wg * y; s[3] += wg * x * x; s[4] += wg * x * y;
+        s[5] += wg * y * y; s[6] += wg * x * x2; s[7] += wg * y * x2; s[8] += wg * x2 * x2;
+        s[9] += wh; s[10] += wh * x; s[11] += wh * y; s[12] += wh * x2;
+    }
+    block_sum<13>(s, red);
+    const double E0 = 0.5 * (3.0 - ph.D + ph.K) * ph.R * T;
+    const double sx2 = s[3] + s[5];
+    double A4[16] = {
+        s[0], s[1], s[2], E0 * s[0] + 0.5 * sx2,
+        s[1], s[3], s[4], E0 * s[1] + 0.5 * s[6],
+        s[2], s[4], s[5], E0 * s[2] + 0.5 * s[7],
+        0.5 * (sx2 + s[9]), 0.5 * (s[6] + s[10]), 0.5 * (s[7] + s[11]),
+        E0 * 0.5 * (sx2 + s[9]) + 0.5 * (0.5 * s[8] + 0.5 * s[12])};
+    const double rhoE = 0.5 * rho * (u * u + v * v) + 0.5 * (3.0 + ph.K) * rho * ph.R * T;
+    double b4[4] = {rho - s[0], rho * u - s[1], rho * v - s[2], rhoE - 0.5 * (sx2 + s[9])};
+    if (ph.D == 2) {
+        if (!solve_small(4, A4, b4)) { b4[0] = b4[1] = b4[2] = b4[3] = 0.0; }
+        for (int k = 0; k < 4; ++k) a_out[k] = b4[k];
+    } else {
+        const int id[3] = {0, 1, 3};
+        double A3[9], b3[3];
+        for (int r = 0; r < 3; ++r) {
+            b3[r] = b4[id[r]];
+            for (int c = 0; c < 3; ++c) A3[r * 3 + c] = A4[id[r] * 4 + id[c]];
+        }
+        if (!solve_small(3, A3, b3)) { b3[0] = b3[1] = b3[2] = 0.0; }
+        a_out[0] = b3[0]; a_out[1] = b3[1]; a_out[2] = 0.0; a_out[3] = b3[2];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// cell stage: W, q, tau, compatibility coefficients, phi_bar+ rows
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(BS) void k_cell_prep(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
+                                                  const int* __restrict__ cell_slot, int n_cells, Phys ph,
+                                                  double* __restrict__ params) {
+    __shared__ double red[MAXW * RED_MAX];
+    for (int c = blockIdx.x; c < n_cells; c += gridDim.x) {
+        const LevelDesc& L = lvs[cell_lev[c]];
+        const size_t row = (size_t)cell_slot[c] * L.stride;
+        const S* g = rowp<S>(L.g, row);
+        const S* h = rowp<S>(L.h, row);
+        double* pr = params + (size_t)c * NPARAM;
+        const double u0 = pr[P_U], v0 = pr[P_V];
+        double m[11];
+#pragma unroll
+        for (int k = 0; k < 11; ++k) m[k] = 0.0;
+        for (int i = threadIdx.x; i < L.N; i += BS) {
+            const double w = L.w[i], x = L.xi_x[i] - u0, y = L.xi_y[i] - v0;
+            const double wg = w * (double)g[i], wh = w * (double)h[i];
+            const double x2 = x * x + y * y;
+            m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += wg * x * x; m[4] += wg * x * y;
+            m[5] += wg * y * y; m[6] += wg * x * x2; m[7] += wg * y * x2;
+            m[8] += wh; m[9] += wh * x; m[10] += wh * y;
+        }
+        block_sum<11>(m, red);
+        double rho, u, v, T, qx, qy;
+        raw_to_state(m, u0, v0, ph, rho, u, v, T, qx, qy);
+        const double p = rho * ph.R * T;
+        const double tau = viscosity(T, ph) / p;
+        const double dt = ph.dt, s = 0.5 * dt;
+        qx = 2.0 * tau * qx / (2.0 * tau + dt * ph.Pr);
+        qy = 2.0 * tau * qy / (2.0 * tau + dt * ph.Pr);
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        if (ph.compat) {
+            Eq<S> eu = make_eq<S>(rho, u, v, T, qx, qy, nullptr, ph);
+            compat_solve<S>(L, eu, rho, u, v, T, ph, red, a);
+        }
+        const double alpha = (2.0 * tau - s) / (2.0 * tau + dt);
+        const double beta = 3.0 * s / (2.0 * tau + dt);
+        Eq<S> e = make_eq<S>(rho, u, v, T, qx, qy, ph.compat ? a : nullptr, ph);
+        S* fg = rowp<S>(L.fg, row);
+        S* fh = rowp<S>(L.fh, row);
+        const S al = (S)alpha, be = (S)beta;
+        for (int i = threadIdx.x; i < L.N; i += BS) {
+            S gs, hs;
+            eq_eval<S>(e, (S)L.xi_x[i], (S)L.xi_y[i], gs, hs);
+            fg[i] = al * g[i] + be * gs;
+            fh[i] = al * h[i] + be * hs;
+        }
+        if (threadIdx.x == 0) {
+            pr[P_RHO] = rho; pr[P_U] = u; pr[P_V] = v; pr[P_T] = T; pr[P_QX] = qx; pr[P_QY] = qy;
+            pr[P_TAU] = tau; pr[P_A0] = a[0]; pr[P_A1] = a[1]; pr[P_A2] = a[2]; pr[P_A3] = a[3];
+            pr[P_ALPHA] = alpha; pr[P_BETA] = beta;
+        }
+        __syncthreads();
+    }
+}
+
+// Equilibrium start: g~ = g_eq*, h~ = h_eq* at (rho, u, v, T), q = 0.
+template <typename S>
+__global__ __launch_bounds__(BS) void k_init_eq(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
+                                                const int* __restrict__ cell_slot, int n_cells,
+                                                const double* __restrict__ st, Phys ph, double* __restrict__ params) {
+    __shared__ double red[MAXW * RED_MAX];
+    for (int c = blockIdx.x; c < n_cells; c += gridDim.x) {
+        const LevelDesc& L = lvs[cell_lev[c]];
+        const double rho = st[4 * c], u = st[4 * c + 1], v = ph.D == 2 ? st[4 * c + 2] : 0.0, T = st[4 * c + 3];
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        if (ph.compat) {
+            Eq<S> eu = make_eq<S>(rho, u, v, T, 0.0, 0.0, nullptr, ph);
+            compat_solve<S>(L, eu, rho, u, v, T, ph, red, a);
+        }
+        Eq<S> e = make_eq<S>(rho, u, v, T, 0.0, 0.0, ph.compat ? a : nullptr, ph);
+        const size_t row = (size_t)cell_slot[c] * L.stride;
+        S* g = rowp<S>(L.g, row);
+        S* h = rowp<S>(L.h, row);
+        for (int i = threadIdx.x; i < L.N; i += BS) {
+            S gs, hs;
+            eq_eval<S>(e, (S)L.xi_x[i], (S)L.xi_y[i], gs, hs);
+            g[i] = gs;
+            h[i] = hs;
+        }
+        if (threadIdx.x == 0) {
+            double* pr = params + (size_t)c * NPARAM;
+            for (int k = 0; k < NPARAM; ++k) pr[k] = 0.0;
+            pr[P_RHO] = rho; pr[P_U] = u; pr[P_V] = v; pr[P_T] = T;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// neighbours on other levels: projection + four-moment mapping correction
+// ---------------------------------------------------------------------------
+template <typename S>
+__device__ void map_correct_apply(const LevelDesc& D, S* gdst, S* hdst, const double* dM, double Ttar,
+                                  const Phys& ph, int& negflag, const S* gprov_check) {
+    const double cK = 3.0 - ph.D + ph.K;
+    double rhs[4] = {dM[0], dM[1], dM[2], dM[3] - 0.5 * cK * ph.R * Ttar * dM[0]};
+    double a[4];
+    for (int r = 0; r < 4; ++r) {
+        double s = 0.0;
+        for (int c = 0; c < 4; ++c) s += D.Minv[r * 4 + c] * rhs[c];
+        a[r] = s;
+    }
+    const double kh = cK * ph.R * Ttar;
+    for (int i = threadIdx.x; i < D.N; i += BS) {
+        const double x = D.xi_x[i], y = D.xi_y[i];
+        const double dg = a[0] + a[1] * x + a[2] * y + a[3] * (x * x + y * y);
+        const S gp = gdst[i];
+        const S gn = (S)((double)gp + dg);
+        if (gn < S(0) && gp >= S(0)) negflag = 1;
+        gdst[i] = gn;
+        hdst[i] = (S)((double)hdst[i] + kh * dg);
+    }
+    (void)gprov_check;
+}
+
+template <typename S>
+__global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs, const GhostItem* __restrict__ items,
+                                              int n, const int* __restrict__ cell_lev,
+                                              const int* __restrict__ cell_slot, const double* __restrict__ params,
+                                              Phys ph, unsigned long long* neg) {
+    __shared__ double red[MAXW * RED_MAX];
+    __shared__ int shflag;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const GhostItem G = items[it];
+        const LevelDesc& Ls = lvs[cell_lev[G.n]];
+        const LevelDesc& Ld = lvs[G.dst];
+        const size_t srow = (size_t)cell_slot[G.n] * Ls.stride;
+        const S* sg = rowp<S>(Ls.fg, srow);
+        const S* sh = rowp<S>(Ls.fh, srow);
+        S* dg = rowp<S>(Ld.Gg, (size_t)G.row * Ld.stride);
+        S* dh = rowp<S>(Ld.Gh, (size_t)G.row * Ld.stride);
+        double m[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) m[k] = 0.0;
+        for (int i = threadIdx.x; i < Ls.N; i += BS) {       // target: moments on the source level
+            const double x = Ls.xi_x[i], y = Ls.xi_y[i], w = Ls.w[i];
+            const double wg = w * (double)sg[i];
+            m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += 0.5 * (wg * (x * x + y * y) + w * (double)sh[i]);
+        }
+        for (int P = threadIdx.x; P < Ld.N; P += BS) {       // provisional projection
+            double gP = 0.0, HP = 0.0;
+            for (int e = G.tab.off[P]; e < G.tab.off[P + 1]; ++e) {
+                const int a = G.tab.idx[e];
+                const double fr = G.tab.frac[e];
+                const double ga = (double)sg[a];
+                const double xa = Ls.xi_x[a], ya = Ls.xi_y[a];
+                gP += fr * ga;
+                HP += fr * ((double)sh[a] + (xa * xa + ya * ya) * ga);
+            }
+            const double x = Ld.xi_x[P], y = Ld.xi_y[P], w = Ld.w[P];
+            const double hP = HP - (x * x + y * y) * gP;
+            const S gs = (S)gP, hs = (S)hP;
+            dg[P] = gs;
+            dh[P] = hs;
+            const double wg = w * (double)gs;
+            m[4] += wg; m[5] += wg * x; m[6] += wg * y; m[7] += 0.5 * (wg * (x * x + y * y) + w * (double)hs);
+        }
+        block_sum<8>(m, red);
+        int nf = 0;
+        if (ph.map_moments) {
+            const double dM[4] = {m[0] - m[4], m[1] - m[5], m[2] - m[6], m[3] - m[7]};
+            map_correct_apply<S>(Ld, dg, dh, dM, params[(size_t)G.n * NPARAM + P_T], ph, nf, nullptr);
+        }
+        nf = block_or(nf, &shflag);
+        if (threadIdx.x == 0 && nf) atomicAdd(neg, 1ull);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// same-level faces
+// ---------------------------------------------------------------------------
+template <typename C>
+__device__ __forceinline__ C van_leer(C a, C b) {
+    const C p = a * b;
+    return p > C(0) ? C(2) * p / (a + b) : C(0);
+}
+
+template <typename S>
+struct Side {                       // one cell's reconstruction stencil
+    const S* own[2];                // phi_bar+ row (g, h)
+    const S* nb[4][2];              // neighbour rows on the same level (nullptr: none)
+    double G[4], dist[4];
+    double dx, dy;                  // x_f - x_cell
+};
+
+template <typename S>
+__device__ __forceinline__ const S* nb_row(const LevelDesc& L, int code, const int* cell_slot, int comp) {
+    if (code == -1) return nullptr;
+    if (code >= 0) return rowp<S>(comp ? L.fh : L.fg, (size_t)cell_slot[code] * L.stride);
+    return rowp<S>(comp ? L.Gh : L.Gg, (size_t)(-2 - code) * L.stride);
+}
+
+template <typename S>
+__device__ __forceinline__ void load_side(Side<S>& sd, const LevelDesc& L, int cell, const int* cell_slot,
+                                          const int* cell_nbr, const CellGeom* geom, double dx, double dy) {
+    const size_t row = (size_t)cell_slot[cell] * L.stride;
+    sd.own[0] = rowp<S>(L.fg, row);
+    sd.own[1] = rowp<S>(L.fh, row);
+    for (int k = 0; k < 4; ++k) {
+        const int code = cell_nbr[4 * cell + k];
+        sd.nb[k][0] = nb_row<S>(L, code, cell_slot, 0);
+        sd.nb[k][1] = nb_row<S>(L, code, cell_slot, 1);
+    }
+    const CellGeom gm = geom[cell];
+    for (int k = 0; k < 4; ++k) { sd.G[k] = gm.G[k]; sd.dist[k] = gm.dist[k]; }
+    sd.dx = dx; sd.dy = dy;
+}
+
+// phi_bar+ of the side's cell extrapolated to the face at velocity index i:
+// phi_bar+ + (x_f - x_c - xi s) . sigma, sigma from limited one-sided slopes.
+template <typename S>
+__device__ __forceinline__ void side_ext(const Side<S>& sd, int i, S x, S y, S s, S& eg, S& eh) {
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        const S f = sd.own[comp][i];
+        S sl[2];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const S* lo = sd.nb[2 * d][comp];
+            const S* hi = sd.nb[2 * d + 1][comp];
+            const S a = lo ? (f - lo[i]) / (S)sd.dist[2 * d] : S(0);
+            const S b = hi ? (hi[i] - f) / (S)sd.dist[2 * d + 1] : S(0);
+            sl[d] = van_leer<S>(a, b);
+        }
+        const S sx = (S)sd.G[0] * sl[0] + (S)sd.G[1] * sl[1];
+        const S sy = (S)sd.G[2] * sl[0] + (S)sd.G[3] * sl[1];
+        const S e = f + ((S)sd.dx - x * s) * sx + ((S)sd.dy - y * s) * sy;
+        if (comp == 0) eg = e; else eh = e;
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ void acc_raw(double* m, double w, double x, double y, S g, S h) {
+    const double wg = w * (double)g, wh = w * (double)h;
+    const double x2 = x * x + y * y;
+    m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += wg * x * x; m[4] += wg * x * y;
+    m[5] += wg * y * y; m[6] += wg * x * x2; m[7] += wg * y * x2;
+    m[8] += wh; m[9] += wh * x; m[10] += wh * y;
+}
+
+// Face state from the reduced raw moments of phi_bar_f (Eq. W_from_bar) and the
+// compatibility coefficients of the face target; returns the recovery weights.
+template <typename S>
+__device__ void face_target(const LevelDesc& L, double* m, double u0, double v0, const Phys& ph, double* red,
+                            bool compat, Eq<S>& e, double& c1, double& c2) {
+    double rho, u, v, T, qx, qy;
+    raw_to_state(m, u0, v0, ph, rho, u, v, T, qx, qy);
+    const double s = 0.5 * ph.dt;
+    const double tau = viscosity(T, ph) / (rho * ph.R * T);
+    qx = 2.0 * tau * qx / (2.0 * tau + s * ph.Pr);
+    qy = 2.0 * tau * qy / (2.0 * tau + s * ph.Pr);
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    if (compat) {
+        Eq<S> eu = make_eq<S>(rho, u, v, T, qx, qy, nullptr, ph);
+        compat_solve<S>(L, eu, rho, u, v, T, ph, red, a);
+    }
+    e = make_eq<S>(rho, u, v, T, qx, qy, compat ? a : nullptr, ph);
+    c1 = 2.0 * tau / (2.0 * tau + s);
+    c2 = s / (2.0 * tau + s);
+}
+
+template <typename S>
+__global__ __launch_bounds__(BS) void k_face(const LevelDesc* __restrict__ lvs, const FaceItem* __restrict__ items,
+                                             int n, const int* __restrict__ cell_slot,
+                                             const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
+                                             const double* __restrict__ params, Phys ph) {
+    __shared__ double red[MAXW * RED_MAX];
+    const S s = (S)(0.5 * ph.dt);
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const FaceItem F = items[it];
+        const LevelDesc& L = lvs[F.lev];
+        Side<S> sL, sR;
+        load_side<S>(sL, L, F.L, cell_slot, cell_nbr, geom, F.dLx, F.dLy);
+        load_side<S>(sR, L, F.R, cell_slot, cell_nbr, geom, F.dRx, F.dRy);
+        const double u0 = 0.5 * (params[(size_t)F.L * NPARAM + P_U] + params[(size_t)F.R * NPARAM + P_U]);
+        const double v0 = 0.5 * (params[(size_t)F.L * NPARAM + P_V] + params[(size_t)F.R * NPARAM + P_V]);
+        S* rg = rowp<S>(L.Fg, (size_t)F.row * L.stride);
+        S* rh = rowp<S>(L.Fh, (size_t)F.row * L.stride);
+        double m[11];
+#pragma unroll
+        for (int k = 0; k < 11; ++k) m[k] = 0.0;
+        for (int i = threadIdx.x; i < L.N; i += BS) {
+            const double xd = L.xi_x[i], yd = L.xi_y[i];
+            const S x = (S)xd, y = (S)yd;
+            const double dn = xd * F.nx + yd * F.ny;
+            S eg, eh;
+            if (dn > 0) {
+                side_ext<S>(sL, i, x, y, s, eg, eh);
+            } else if (dn < 0) {
+                side_ext<S>(sR, i, x, y, s, eg, eh);
+            } else {
+                S ag, ah, bg, bh;
+                side_ext<S>(sL, i, x, y, s, ag, ah);
+                side_ext<S>(sR, i, x, y, s, bg, bh);
+                eg = S(0.5) * (ag + bg);
+                eh = S(0.5) * (ah + bh);
+            }
+            rg[i] = eg;
+            rh[i] = eh;
+            acc_raw<S>(m, L.w[i], xd - u0, yd - v0, eg, eh);
+        }
+        block_sum<11>(m, red);
+        Eq<S> e;
+        double c1, c2;
+        face_target<S>(L, m, u0, v0, ph, red, ph.compat && ph.face_compat, e, c1, c2);
+        const S a1 = (S)c1, a2 = (S)c2, ar = (S)F.area;
+        for (int i = threadIdx.x; i < L.N; i += BS) {
+            const double xd = L.xi_x[i], yd = L.xi_y[i];
+            const S x = (S)xd, y = (S)yd;
+            S gs, hs;
+            eq_eval<S>(e, x, y, gs, hs);
+            const S dn = (S)(xd * F.nx + yd * F.ny);
+            rg[i] = ar * dn * (a1 * rg[i] + a2 * gs);
+            rh[i] = ar * dn * (a1 * rh[i] + a2 * hs);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// boundary faces (Sec. 4 workloads): outgoing from the interior reconstruction
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(BS) void k_bface(const LevelDesc* __restrict__ lvs, const BFaceItem* __restrict__ items,
+                                              int n, const int* __restrict__ cell_slot,
+                                              const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
+                                              const BCDev* __restrict__ bcs, Phys ph, const int* __restrict__ cell_lev) {
+    __shared__ double red[MAXW * RED_MAX];
+    const S s = (S)(0.5 * ph.dt);
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const BFaceItem F = items[it];
+        const LevelDesc& L = lvs[F.lev];
+        const BCDev bc = bcs[F.bc];
+        Side<S> sd;
+        load_side<S>(sd, L, F.c, cell_slot, cell_nbr, geom, F.dx, F.dy);
+        S* rg = rowp<S>(L.Fg, (size_t)F.row * L.stride);
+        S* rh = rowp<S>(L.Fh, (size_t)F.row * L.stride);
+        Eq<S> e;
+        S rho_w = S(1);
+        if (bc.kind == 1) {
+            e = make_eq<S>(1.0, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
+            double m[2] = {0.0, 0.0};
+            for (int i = threadIdx.x; i < L.N; i += BS) {
+                const double xd = L.xi_x[i], yd = L.xi_y[i], w = L.w[i];
+                const double dn = xd * F.nx + yd * F.ny;
+                if (dn > 0) {
+                    S eg, eh;
+                    side_ext<S>(sd, i, (S)xd, (S)yd, s, eg, eh);
+                    m[0] += w * dn * (double)eg;
+                } else if (dn < 0) {
+                    S gs, hs;
+                    eq_eval<S>(e, (S)xd, (S)yd, gs, hs);
+                    m[1] += w * dn * (double)gs;
+                }
+            }
+            block_sum<2>(m, red);
+            rho_w = (S)(-m[0] / m[1]);
+        } else if (bc.kind == 2) {
+            e = make_eq<S>(bc.rho, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
+        }
+        const S ar = (S)F.area;
+        for (int i = threadIdx.x; i < L.N; i += BS) {
+            const double xd = L.xi_x[i], yd = L.xi_y[i];
+            const S x = (S)xd, y = (S)yd;
+            const double dnd = xd * F.nx + yd * F.ny;
+            const S dn = (S)dnd;
+            S gf, hf;
+            if (dnd > 0) {
+                side_ext<S>(sd, i, x, y, s, gf, hf);
+            } else if (bc.kind == 3) {
+                gf = sd.own[0][i];
+                hf = sd.own[1][i];
+            } else {
+                eq_eval<S>(e, x, y, gf, hf);
+                if (bc.kind == 1) { gf *= rho_w; hf *= rho_w; }
+            }
+            rg[i] = ar * dn * gf;
+            rh[i] = ar * dn * hf;
+        }
+        __syncthreads();
+    }
+    (void)cell_lev;
+}
+
+// ---------------------------------------------------------------------------
+// cell update: phi~^{n+1} = 4/3 phi_bar+ - 1/3 phi~ - dt/|V| sum(+-F)
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(BS) void k_update(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
+                                               const int* __restrict__ cell_slot, int n_cells,
+                                               const CellGeom* __restrict__ geom, const int* __restrict__ cell_frow,
+                                               Phys ph) {
+    for (int c = blockIdx.x; c < n_cells; c += gridDim.x) {
+        const LevelDesc& L = lvs[cell_lev[c]];
+        const size_t row = (size_t)cell_slot[c] * L.stride;
+        S* g = rowp<S>(L.g, row);
+        S* h = rowp<S>(L.h, row);
+        const S* fg = rowp<S>(L.fg, row);
+        const S* fh = rowp<S>(L.fh, row);
+        const S* Fg[4];
+        const S* Fh[4];
+        S sg[4];
+        int nf = 0;
+        for (int k = 0; k < 4; ++k) {
+            const int code = cell_frow[4 * c + k];
+            if (code < 0) continue;
+            const size_t r = (size_t)(code >> 1) * L.stride;
+            Fg[nf] = rowp<S>(L.Fg, r);
+            Fh[nf] = rowp<S>(L.Fh, r);
+            sg[nf] = (code & 1) ? S(-1) : S(1);
+            ++nf;
+        }
+        const S k = (S)(ph.dt / geom[c].vol);
+        const S c43 = (S)(4.0 / 3.0), c13 = (S)(1.0 / 3.0);
+        for (int i = threadIdx.x; i < L.N; i += BS) {
+            S ag = S(0), ah = S(0);
+            for (int j = 0; j < nf; ++j) {
+                ag += sg[j] * Fg[j][i];
+                ah += sg[j] * Fh[j][i];
+            }
+            g[i] = c43 * fg[i] - c13 * g[i] - k * ag;
+            h[i] = c43 * fh[i] - c13 * h[i] - k * ah;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics: per-cell fields and volume-weighted conserved totals
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(BS) void k_cell_moments(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
+                                                     const int* __restrict__ cell_slot, int n_cells,
+                                                     const CellGeom* __restrict__ geom, Phys ph,
+                                                     double* __restrict__ out6, double* __restrict__ tot4) {
+    __shared__ double red[MAXW * RED_MAX];
+    for (int c = blockIdx.x; c < n_cells; c += gridDim.x) {
+        const LevelDesc& L = lvs[cell_lev[c]];
+        const size_t row = (size_t)cell_slot[c] * L.stride;
+        const S* g = rowp<S>(L.g, row);
+        const S* h = rowp<S>(L.h, row);
+        double m[11];
+#pragma unroll
+        for (int k = 0; k < 11; ++k) m[k] = 0.0;
+        for (int i = threadIdx.x; i < L.N; i += BS) acc_raw<S>(m, L.w[i], L.xi_x[i], L.xi_y[i], g[i], h[i]);
+        block_sum<11>(m, red);
+        if (threadIdx.x == 0) {
+            double rho, u, v, T, qx, qy;
+            raw_to_state(m, 0.0, 0.0, ph, rho, u, v, T, qx, qy);
+            const double tau = viscosity(T, ph) / (rho * ph.R * T);
+            const double f = 2.0 * tau / (2.0 * tau + ph.dt * ph.Pr);
+            if (out6) {
+                double* o = out6 + 6 * (size_t)c;
+                o[0] = rho; o[1] = u; o[2] = v; o[3] = T; o[4] = f * qx; o[5] = f * qy;
+            }
+            if (tot4) {
+                const double V = geom[c].vol;
+                double* o = tot4 + 4 * (size_t)c;
+                o[0] = V * m[0]; o[1] = V * m[1]; o[2] = V * m[2]; o[3] = V * 0.5 * (m[3] + m[5] + m[8]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Fixed-order sum of n rows of `width` doubles (one workgroup).
+__global__ __launch_bounds__(BS) void k_sum_rows(const double* __restrict__ in, int n, int width,
+                                                 double* __restrict__ out) {
+    __shared__ double red[MAXW * RED_MAX];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = threadIdx.x; r < n; r += BS)
+        for (int k = 0; k < width; ++k) v[k] += in[(size_t)r * width + k];
+    block_sum<4>(v, red);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < width; ++k) out[k] = v[k];
+}
+
+// ---------------------------------------------------------------------------
+// level switch: projection + four-moment mapping correction (Eq.
+// level_switch_conservation), T_tar the cell temperature
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv, const LevelDesc* __restrict__ nlv,
+                                              const RemapItem* __restrict__ items, int n, Phys ph,
+                                              unsigned long long* neg) {
+    __shared__ double red[MAXW * RED_MAX];
+    __shared__ int shflag;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const RemapItem R = items[it];
+        const LevelDesc& Ls = olv[R.src_lev];
+        const LevelDesc& Ld = nlv[R.dst_lev];
+        const S* sg = rowp<S>(Ls.g, (size_t)R.src_slot * Ls.stride);
+        const S* sh = rowp<S>(Ls.h, (size_t)R.src_slot * Ls.stride);
+        S* dg = rowp<S>(Ld.g, (size_t)R.dst_slot * Ld.stride);
+        S* dh = rowp<S>(Ld.h, (size_t)R.dst_slot * Ld.stride);
+        if (R.tab.off == nullptr) {
+            for (int i = threadIdx.x; i < Ld.N; i += BS) { dg[i] = sg[i]; dh[i] = sh[i]; }
+            continue;
+        }
+        double m[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) m[k] = 0.0;
+        for (int i = threadIdx.x; i < Ls.N; i += BS) {
+            const double x = Ls.xi_x[i], y = Ls.xi_y[i], w = Ls.w[i];
+            const double wg = w * (double)sg[i];
+            m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += 0.5 * (wg * (x * x + y * y) + w * (double)sh[i]);
+        }
+        for (int P = threadIdx.x; P < Ld.N; P += BS) {
+            double gP = 0.0, HP = 0.0;
+            for (int e = R.tab.off[P]; e < R.tab.off[P + 1]; ++e) {
+                const int a = R.tab.idx[e];
+                const double fr = R.tab.frac[e];
+                const double ga = (double)sg[a];
+                const double xa = Ls.xi_x[a], ya = Ls.xi_y[a];
+                gP += fr * ga;
+                HP += fr * ((double)sh[a] + (xa * xa + ya * ya) * ga);
+            }
+            const double x = Ld.xi_x[P], y = Ld.xi_y[P], w = Ld.w[P];
+            const S gs = (S)gP, hs = (S)(HP - (x * x + y * y) * gP);
+            dg[P] = gs;
+            dh[P] = hs;
+            const double wg = w * (double)gs;
+            m[4] += wg; m[5] += wg * x; m[6] += wg * y; m[7] += 0.5 * (wg * (x * x + y * y) + w * (double)hs);
+        }
+        block_sum<8>(m, red);
+        int nf = 0;
+        if (ph.map_moments) {
+            const double rho = m[0], u = m[1] / rho, v = m[2] / rho;
+            const double T = (2.0 * m[3] / rho - (u * u + v * v)) / ((3.0 + ph.K) * ph.R);
+            const double dM[4] = {m[0] - m[4], m[1] - m[5], m[2] - m[6], m[3] - m[7]};
+            map_correct_apply<S>(Ld, dg, dh, dM, T, ph, nf, nullptr);
+        }
+        nf = block_or(nf, &shflag);
+        if (threadIdx.x == 0 && nf) atomicAdd(neg, 1ull);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+static inline int grid_for(int n) { return n < 1 ? 1 : (n > 1048576 ? 1048576 : n); }
+
+#define MLVS_DISPATCH(prec, KERNEL, ...)                                                        \
+    do {                                                                                        \
+        if ((prec) == 32) hipLaunchKernelGGL(KERNEL<float>, __VA_ARGS__);                        \
+        else hipLaunchKernelGGL(KERNEL<double>, __VA_ARGS__);                                    \
+    } while (0)
+
+hipError_t launch_cell_prep(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
+                            int n_cells, Phys ph, double* params) {
+    if (n_cells <= 0) return hipSuccess;
+    MLVS_DISPATCH(prec, k_cell_prep, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells, ph,
+                  params);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_eq(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
+                          int n_cells, const double* rho_u_v_T, Phys ph, double* params) {
+    if (n_cells <= 0) return hipSuccess;
+    MLVS_DISPATCH(prec, k_init_eq, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
+                  rho_u_v_T, ph, params);
+    return hipGetLastError();
+}
+
+hipError_t launch_ghost(int prec, hipStream_t st, const LevelDesc* lv, const GhostItem* items, int n,
+                        const int* cell_lev, const int* cell_slot, const double* params, Phys ph,
+                        unsigned long long* neg) {
+    if (n <= 0) return hipSuccess;
+    MLVS_DISPATCH(prec, k_ghost, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_lev, cell_slot, params, ph,
+                  neg);
+    return hipGetLastError();
+}
+
+hipError_t launch_face(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
+                       const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
+                       Phys ph) {
+    if (n <= 0) return hipSuccess;
+    MLVS_DISPATCH(prec, k_face, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr, geom, params,
+                  ph);
+    return hipGetLastError();
+}
+
+hipError_t launch_bface(int prec, hipStream_t st, const LevelDesc* lv, const BFaceItem* items, int n,
+                        const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const BCDev* bcs, Phys ph) {
+    if (n <= 0) return hipSuccess;
+    MLVS_DISPATCH(prec, k_bface, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr, geom, bcs,
+                  ph, (const int*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
+                         int n_cells, const CellGeom* geom, const int* cell_frow, Phys ph) {
+    if (n_cells <= 0) return hipSuccess;
+    MLVS_DISPATCH(prec, k_update, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells, geom,
+                  cell_frow, ph);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_moments(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
+                               const int* cell_slot, int n_cells, const CellGeom* geom, Phys ph, double* out6,
+                               double* tot4) {
+    if (n_cells <= 0) return hipSuccess;
+    MLVS_DISPATCH(prec, k_cell_moments, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
+                  geom, ph, out6, tot4);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_rows(hipStream_t st, const double* in, int n, int width, double* out) {
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(BS), 0, st, in, n, width, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_remap(int prec, hipStream_t st, const LevelDesc* old_lv, const LevelDesc* new_lv,
+                        const RemapItem* items, int n, Phys ph, unsigned long long* neg) {
+    if (n <= 0) return hipSuccess;
+    MLVS_DISPATCH(prec, k_remap, dim3(grid_for(n)), dim3(BS), 0, st, old_lv, new_lv, items, n, ph, neg);
+    return hipGetLastError();
+}
+
+hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFaceItem* items, int n,
+                        const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
+                        Phys ph, unsigned long long* neg) {
+    if (n <= 0) return hipSuccess;
+    return hipErrorNotSupported;
+}
+
+}  // namespace mlvs

@@ -1,0 +1,129 @@
+// Internal declarations shared by the host code and the HIP kernels of libmlvs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mlvs {
+
+// Per-cell parameter block (double).  Written by the cell stage of each step.
+enum {
+    P_RHO = 0, P_U, P_V, P_T, P_QX, P_QY, P_TAU,
+    P_A0, P_A1, P_A2, P_A3,          // compatibility-correction coefficients
+    P_ALPHA, P_BETA,                 // phi_bar+ = alpha phi~ + beta phi_S
+    P_NEG,                           // 1 if the corrected target had g < 0
+    NPARAM = 16
+};
+
+// Per-face parameter block for the face target (double).
+enum { F_RHO = 0, F_U, F_V, F_T, F_QX, F_QY, F_TAU, F_A0, F_A1, F_A2, F_A3, NFPARAM = 12 };
+
+// One velocity space (a representative level or an interface level).
+struct LevelDesc {
+    int N;             // points
+    int stride;        // row stride in elements (multiple of 64)
+    int n_rows_state;  // cells on this level
+    int pad;
+    const double* xi_x;
+    const double* xi_y;
+    const double* w;
+    void* g;   void* h;     // state g~, h~           [cells][stride]
+    void* fg;  void* fh;    // phi_bar+ of the step    [cells][stride]
+    void* Fg;  void* Fh;    // face rows (flux)        [rows][stride]
+    void* Gg;  void* Gh;    // ghost rows (neighbours of other levels mapped here)
+    double Minv[16];        // inverse of the state-independent 4x4 mapping matrix
+};
+
+struct Phys {
+    int D, K;
+    double R, Pr, omega, mu_ref, T_ref, dt;
+    int compat, face_compat, map_moments;
+};
+
+// Encoded neighbour: >= 0 same-level cell id; -1 none (boundary);
+// <= -2: ghost row (-2 - v) in the cell's level.
+struct CellGeom {
+    double vol;
+    double G[4];       // inverse of [t_i; t_j] (row-major)
+    double dist[4];    // |x_n - x_c| for W, E, S, N (1 when absent)
+};
+
+struct FaceItem {      // same-level interior face
+    int L, R, lev, row;
+    double nx, ny, area, dLx, dLy, dRx, dRy;
+};
+
+struct BFaceItem {     // boundary face of one cell
+    int c, bc, lev, row;
+    double nx, ny, area, dx, dy;     // outward normal; x_f - x_c
+};
+
+struct BCDev {
+    int kind, pad;
+    double rho, u, v, T;
+};
+
+// CSR projection table dst <- src: for each dst point, entries (src index, fraction).
+struct PairTable {
+    const int* off;
+    const int* idx;
+    const double* frac;
+};
+
+struct XFaceItem {     // cross-level interior face
+    int L, R, levA, levB, levI, rowA, rowB, scratch;   // scratch: row in levI's face rows
+    PairTable IfromA, IfromB, AfromI, BfromI;
+    double nx, ny, area, dLx, dLy, dRx, dRy;
+};
+
+struct GhostItem {     // neighbour n (on level src) mapped onto level dst
+    int n, dst, row, pad;
+    PairTable tab;     // dst <- src
+};
+
+struct RemapItem {     // cell moved from an old level to a new one
+    int c, src_lev, src_slot, dst_lev, dst_slot, pad;
+    PairTable tab;     // dst <- src (null off => identical spaces: copy)
+};
+
+// Launch wrappers (kernels.hip).  `S` selects float (32) or double (64) storage.
+hipError_t launch_cell_prep(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
+                            const int* cell_slot, int n_cells, Phys ph, double* params);
+hipError_t launch_ghost(int prec, hipStream_t st, const LevelDesc* lv, const GhostItem* items, int n,
+                        const int* cell_lev, const int* cell_slot, const double* params, Phys ph,
+                        unsigned long long* neg);
+hipError_t launch_face(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
+                       const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
+                       const double* params, Phys ph);
+hipError_t launch_bface(int prec, hipStream_t st, const LevelDesc* lv, const BFaceItem* items, int n,
+                        const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
+                        const BCDev* bcs, Phys ph);
+hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFaceItem* items, int n,
+                        const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
+                        const double* params, Phys ph, unsigned long long* neg);
+hipError_t launch_update(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
+                         const int* cell_slot, int n_cells, const CellGeom* geom,
+                         const int* cell_frow, Phys ph);
+hipError_t launch_init_eq(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
+                          const int* cell_slot, int n_cells, const double* rho_u_v_T, Phys ph,
+                          double* params);
+hipError_t launch_cell_moments(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
+                               const int* cell_slot, int n_cells, const CellGeom* geom, Phys ph,
+                               double* out6, double* out_tot4);
+hipError_t launch_sum_rows(hipStream_t st, const double* in, int n, int width, double* out);
+hipError_t launch_remap(int prec, hipStream_t st, const LevelDesc* old_lv, const LevelDesc* new_lv,
+                        const RemapItem* items, int n, Phys ph, unsigned long long* neg);
+hipError_t launch_criterion(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
+                            const int* cell_slot, int n_cells, const int* pt_of_base_all,
+                            const int* pt_off, const uint8_t* kappa_all, const double* bxi_x,
+                            const double* bxi_y, const double* bw, int nx, int ny,
+                            double C_split, double C_merge, double eps_merge, int flux_test,
+                            uint8_t* kappa_out, unsigned long long* hash_out);
+hipError_t launch_gather_rows_u8(hipStream_t st, const uint8_t* src, int width, const int* rows, int n,
+                                 uint8_t* dst);
+hipError_t launch_compare_rows_u8(hipStream_t st, const uint8_t* all, int width, const int* rep_of_cell,
+                                  const uint8_t* reps, int n, unsigned long long* mismatch);
+
+}  // namespace mlvs

@@ -1,0 +1,63 @@
+"""The C-ABI library loads and exports every symbol its header declares (no GPU needed).
+
+Also checks the library's host-only helpers (quadrature, VHS viscosity) against
+the oracle's, which were pinned separately.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2609_35258_amd as m
+from oracle import kinetic as kin
+from oracle.quadrature import gauss_hermite_1d, newton_cotes_1d
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "mlvs.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mlvs_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported():
+    L = m.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_binding_covers_header():
+    assert set(_declared()) == set(m._PROTOS)
+
+
+@pytest.mark.parametrize("n,a", [(101, 10.0), (89, 4.0), (31, 3.0), (28, 4.0), (161, 7.0)])
+def test_newton_cotes_matches_oracle(n, a):
+    x, w = m.newton_cotes(n, a)
+    xo, wo = newton_cotes_1d(n, a)
+    assert np.array_equal(x, xo)
+    assert np.allclose(w, wo, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("n", [6, 12, 28, 40])
+def test_gauss_hermite_matches_oracle(n):
+    x, w = m.gauss_hermite(n, 0.5, 1.0)
+    xo, wo = gauss_hermite_1d(n, 0.5, 1.0)
+    assert np.allclose(x, xo, rtol=1e-13, atol=1e-14)
+    assert np.allclose(w, wo, rtol=1e-12, atol=0)
+
+
+def test_mu_ref_matches_oracle():
+    assert abs(m.mu_ref_from_kn(0.075, 1.0, 1.0, 0.5, 1.0, 0.81)
+               - kin.mu_ref_from_kn(0.075, 1.0, 1.0, 0.5, 1.0, 0.81)) < 1e-16
+
+
+def test_errors_are_reported_not_raised():
+    L = m.lib()
+    st = L.mlvs_vgrid_newton_cotes(1, 1.0, None, None)
+    assert st == -1
+    assert b"Newton" in L.mlvs_last_error() or len(L.mlvs_last_error()) > 0
