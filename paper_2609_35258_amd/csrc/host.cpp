@@ -548,6 +548,13 @@ struct mlvs_ctx_s {
     double* d_scratch = nullptr; size_t scratch_n = 0;
     unsigned long long* d_neg = nullptr;
     bool state_ready = false;
+    // criterion inputs: base grid and per-level maps / masks
+    double *d_bx = nullptr, *d_by = nullptr, *d_bw = nullptr;
+    int *d_ptb_all = nullptr, *d_ptb_off = nullptr;
+    uint8_t* d_kappa_all = nullptr;
+    uint8_t* d_kcell = nullptr;
+    unsigned long long* d_hash = nullptr;
+    int64_t last_unique = 0;
 
     size_t elt() const { return prec == 32 ? 4 : 8; }
 };
@@ -769,6 +776,18 @@ void build_items(mlvs_ctx c) {
     c->d_cell_nbr = upload_item(c, cell_nbr);
     c->d_cell_lev = upload_item(c, c->cell_level);
     c->d_cell_slot = upload_item(c, c->cell_slot);
+    if (c->base.Nb > 0) {
+        std::vector<int> ptb, off;
+        std::vector<uint8_t> kap;
+        for (int l = 0; l < K; ++l) {
+            off.push_back((int)ptb.size());
+            ptb.insert(ptb.end(), c->levels[l]->pt_of_base.begin(), c->levels[l]->pt_of_base.end());
+            kap.insert(kap.end(), c->levels[l]->kappa.begin(), c->levels[l]->kappa.end());
+        }
+        c->d_ptb_all = upload_item(c, ptb);
+        c->d_ptb_off = upload_item(c, off);
+        c->d_kappa_all = upload_item(c, kap);
+    }
 }
 
 void assign_slots(mlvs_ctx c) {
@@ -861,6 +880,163 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// adaptation: device criterion, host grouping (Sec. 3.2), remap
+// ---------------------------------------------------------------------------
+namespace {
+
+void run_criterion(mlvs_ctx c) {
+    const int n = c->mesh.n_cells;
+    const int Nb = c->base.Nb;
+    if (!c->d_kcell) c->d_kcell = static_cast<uint8_t*>(c->dm.alloc((size_t)n * Nb));
+    if (!c->d_hash) c->d_hash = static_cast<unsigned long long*>(c->dm.alloc(sizeof(unsigned long long) * n));
+    hip_check(launch_criterion(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_ptb_all, c->d_ptb_off,
+                               c->d_kappa_all, c->d_bx, c->d_by, c->d_bw, c->base.nx, c->base.ny, c->ap.C_split,
+                               c->ap.C_merge, c->ap.eps_merge, c->ap.flux_test, c->d_kcell, c->d_hash),
+              "criterion launch");
+}
+
+// Deduplicate the per-cell masks: returns unique masks (row-major), their first
+// cell and count, and the unique index of every cell.
+void dedupe(mlvs_ctx c, std::vector<uint8_t>& uniq, std::vector<int>& first, std::vector<int64_t>& count,
+            std::vector<int>& uidx) {
+    const int n = c->mesh.n_cells, Nb = c->base.Nb;
+    std::vector<unsigned long long> hs(n);
+    hip_check(hipMemcpyAsync(hs.data(), c->d_hash, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, c->st), "D2H");
+    sync(c);
+    std::unordered_map<unsigned long long, int> of;
+    uidx.assign(n, -1);
+    first.clear();
+    count.clear();
+    for (int i = 0; i < n; ++i) {
+        auto it = of.find(hs[i]);
+        if (it == of.end()) {
+            of.emplace(hs[i], (int)first.size());
+            uidx[i] = (int)first.size();
+            first.push_back(i);
+            count.push_back(1);
+        } else {
+            uidx[i] = it->second;
+            ++count[it->second];
+        }
+    }
+    const int U = (int)first.size();
+    int* d_rows = upload(c->dm, first, c->st);
+    int* d_rep = upload(c->dm, uidx, c->st);
+    uint8_t* d_u = static_cast<uint8_t*>(c->dm.alloc((size_t)U * Nb));
+    unsigned long long* d_mis = static_cast<unsigned long long*>(c->dm.alloc(8));
+    hip_check(hipMemsetAsync(d_mis, 0, 8, c->st), "memset");
+    hip_check(launch_gather_rows_u8(c->st, c->d_kcell, Nb, d_rows, U, d_u), "gather");
+    hip_check(launch_compare_rows_u8(c->st, c->d_kcell, Nb, d_rep, d_u, n, d_mis), "compare");
+    unsigned long long mis = 0;
+    uniq.resize((size_t)U * Nb);
+    hip_check(hipMemcpyAsync(&mis, d_mis, 8, hipMemcpyDeviceToHost, c->st), "D2H");
+    hip_check(hipMemcpyAsync(uniq.data(), d_u, (size_t)U * Nb, hipMemcpyDeviceToHost, c->st), "D2H");
+    sync(c);
+    c->dm.release(d_rows); c->dm.release(d_rep); c->dm.release(d_u); c->dm.release(d_mis);
+    if (mis != 0) {
+        // hash collision: exact deduplication on the host
+        std::vector<uint8_t> all((size_t)n * Nb);
+        hip_check(hipMemcpyAsync(all.data(), c->d_kcell, all.size(), hipMemcpyDeviceToHost, c->st), "D2H");
+        sync(c);
+        std::map<std::vector<uint8_t>, int> ex;
+        uniq.clear(); first.clear(); count.clear();
+        for (int i = 0; i < n; ++i) {
+            std::vector<uint8_t> row(all.begin() + (size_t)i * Nb, all.begin() + (size_t)(i + 1) * Nb);
+            auto it = ex.find(row);
+            if (it == ex.end()) {
+                ex.emplace(row, (int)first.size());
+                uidx[i] = (int)first.size();
+                first.push_back(i);
+                count.push_back(1);
+                uniq.insert(uniq.end(), row.begin(), row.end());
+            } else {
+                uidx[i] = it->second;
+                ++count[it->second];
+            }
+        }
+    }
+}
+
+// Leader clustering of the unique masks (descending frequency, ties by first
+// cell), integer graded distance, enclosing mask = elementwise min, identical
+// enclosing masks merged.
+void cluster(int Nb, double tau, const std::vector<uint8_t>& uniq, const std::vector<int>& first,
+             const std::vector<int64_t>& count, std::vector<std::vector<uint8_t>>& reps, std::vector<int>& level_of_u) {
+    const int U = (int)first.size();
+    std::vector<int> order(U);
+    for (int u = 0; u < U; ++u) order[u] = u;
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+        if (count[a] != count[b]) return count[a] > count[b];
+        return first[a] < first[b];
+    });
+    const long thr = (long)std::floor(tau * 3.0 * Nb + 1e-9);
+    std::vector<int> centres;
+    std::vector<int> cl_of_u(U, -1);
+    std::vector<std::vector<uint8_t>> kmin;
+    for (int u : order) {
+        const uint8_t* ku = &uniq[(size_t)u * Nb];
+        int best = -1;
+        long bestd = 0;
+        for (size_t cid = 0; cid < centres.size(); ++cid) {
+            const uint8_t* kc = &uniq[(size_t)centres[cid] * Nb];
+            long d = 0;
+            for (int b = 0; b < Nb; ++b) d += std::abs((int)ku[b] - (int)kc[b]);
+            if (best < 0 || d < bestd) { best = (int)cid; bestd = d; }
+        }
+        if (best >= 0 && bestd <= thr) {
+            cl_of_u[u] = best;
+            for (int b = 0; b < Nb; ++b) kmin[best][b] = std::min(kmin[best][b], ku[b]);
+        } else {
+            centres.push_back(u);
+            cl_of_u[u] = (int)centres.size() - 1;
+            kmin.emplace_back(ku, ku + Nb);
+        }
+    }
+    std::vector<int> level_of_cl(kmin.size());
+    reps.clear();
+    for (size_t k = 0; k < kmin.size(); ++k) {
+        int found = -1;
+        for (size_t l = 0; l < reps.size(); ++l)
+            if (reps[l] == kmin[k]) { found = (int)l; break; }
+        if (found < 0) { reps.push_back(kmin[k]); found = (int)reps.size() - 1; }
+        level_of_cl[k] = found;
+    }
+    level_of_u.resize(U);
+    for (int u = 0; u < U; ++u) level_of_u[u] = level_of_cl[cl_of_u[u]];
+}
+
+void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
+    run_criterion(c);
+    std::vector<uint8_t> uniq;
+    std::vector<int> first, uidx, level_of_u;
+    std::vector<int64_t> count;
+    dedupe(c, uniq, first, count, uidx);
+    std::vector<std::vector<uint8_t>> reps;
+    cluster(c->base.Nb, c->ap.tau_clust, uniq, first, count, reps, level_of_u);
+    std::vector<std::unique_ptr<Level>> nl;
+    for (auto& k : reps) nl.push_back(build_level(c->base, k));
+    std::vector<int> cl(c->mesh.n_cells);
+    for (int i = 0; i < c->mesh.n_cells; ++i) cl[i] = level_of_u[uidx[i]];
+    const int64_t changed = install_levels(c, std::move(nl), cl);
+    c->last_unique = (int64_t)first.size();
+    if (rep) {
+        rep->n_levels = (int)c->levels.size();
+        rep->n_unique = c->last_unique;
+        rep->n_changed = changed;
+        rep->n_cross = c->n_cross;
+        double tot = 0.0;
+        for (auto& L : c->levels) tot += (double)L->N * L->n_cells;
+        rep->nbar = tot / c->mesh.n_cells;
+        unsigned long long v = 0;
+        hip_check(hipMemcpyAsync(&v, c->d_neg, 8, hipMemcpyDeviceToHost, c->st), "D2H");
+        sync(c);
+        rep->neg_count = (int64_t)v;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -936,6 +1112,9 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         ph.compat = phys->compat; ph.face_compat = phys->face_compat; ph.map_moments = phys->map_moments;
         // device geometry
         c->d_geom = upload(c->dm, c->mesh.geom, c->st);
+        c->d_bx = upload(c->dm, B.x, c->st);
+        c->d_by = upload(c->dm, B.y, c->st);
+        c->d_bw = upload(c->dm, B.w, c->st);
         std::vector<BCDev> bd;
         for (auto& b : c->bcs) bd.push_back(BCDev{b.kind, 0, b.rho, b.u, b.v, b.T});
         c->d_bcs = upload(c->dm, bd, c->st);
@@ -1192,11 +1371,24 @@ mlvs_status mlvs_set_levels(mlvs_ctx c, int n_levels, const uint8_t* kappa, cons
 }
 
 mlvs_status mlvs_adapt(mlvs_ctx c, mlvs_adapt_report* rep) {
-    return guarded([&] { fail(MLVS_E_STATE, "adaptation not available yet"); });
+    return guarded([&] {
+        if (!c) fail(MLVS_E_ARG, "null context");
+        if (!c->adaptive) fail(MLVS_E_STATE, "context was created without adaptation parameters");
+        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
+        adapt_now(c, rep);
+    });
 }
 
 mlvs_status mlvs_criterion(mlvs_ctx c, uint8_t* out) {
-    return guarded([&] { fail(MLVS_E_STATE, "criterion not available yet"); });
+    return guarded([&] {
+        if (!c || !out) fail(MLVS_E_ARG, "null argument");
+        if (!c->adaptive) fail(MLVS_E_STATE, "context was created without adaptation parameters");
+        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
+        run_criterion(c);
+        hip_check(hipMemcpyAsync(out, c->d_kcell, (size_t)c->mesh.n_cells * c->base.Nb, hipMemcpyDeviceToHost, c->st),
+                  "D2H");
+        sync(c);
+    });
 }
 
 }  // extern "C"

@@ -456,7 +456,7 @@ __device__ __forceinline__ void acc_raw(double* m, double w, double x, double y,
 // compatibility coefficients of the face target; returns the recovery weights.
 template <typename S>
 __device__ void face_target(const LevelDesc& L, double* m, double u0, double v0, const Phys& ph, double* red,
-                            bool compat, Eq<S>& e, double& c1, double& c2) {
+                            bool compat, Eq<S>& e, double& c1, double& c2, double* Tout = nullptr) {
     double rho, u, v, T, qx, qy;
     raw_to_state(m, u0, v0, ph, rho, u, v, T, qx, qy);
     const double s = 0.5 * ph.dt;
@@ -471,6 +471,7 @@ __device__ void face_target(const LevelDesc& L, double* m, double u0, double v0,
     e = make_eq<S>(rho, u, v, T, qx, qy, compat ? a : nullptr, ph);
     c1 = 2.0 * tau / (2.0 * tau + s);
     c2 = s / (2.0 * tau + s);
+    if (Tout) *Tout = T;
 }
 
 template <typename S>
@@ -830,11 +831,459 @@ hipError_t launch_remap(int prec, hipStream_t st, const LevelDesc* old_lv, const
     return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// cross-level faces (Sec. 3.4): states refined to V_int = min(kappa_L, kappa_R)
+// and corrected to their own native moments (Eq. interface_state_moment_matching),
+// slopes refined by inheritance, DUGKS face evaluation on V_int, the interface
+// microflux (Eq. interface_reduced_fluxes) coarsened to each native level and
+// corrected to the common target F_int (Eq. native_flux_moment_matching).
+// ---------------------------------------------------------------------------
+template <typename S>
+__device__ __forceinline__ void side_slope(const Side<S>& sd, int i, S (&f)[2], S (&sx)[2], S (&sy)[2]) {
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        const S fv = sd.own[comp][i];
+        S sl[2];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const S* lo = sd.nb[2 * d][comp];
+            const S* hi = sd.nb[2 * d + 1][comp];
+            const S a = lo ? (fv - lo[i]) / (S)sd.dist[2 * d] : S(0);
+            const S b = hi ? (hi[i] - fv) / (S)sd.dist[2 * d + 1] : S(0);
+            sl[d] = van_leer<S>(a, b);
+        }
+        f[comp] = fv;
+        sx[comp] = (S)sd.G[0] * sl[0] + (S)sd.G[1] * sl[1];
+        sy[comp] = (S)sd.G[2] * sl[0] + (S)sd.G[3] * sl[1];
+    }
+}
+
+// phi_bar+ and slope of one side at interface point P (parent a on the native level).
+template <typename S>
+__device__ __forceinline__ void side_refined(const Side<S>& sd, const LevelDesc& Ln, const LevelDesc& LI, int a,
+                                             int P, S (&f)[2], S (&sx)[2], S (&sy)[2]) {
+    side_slope<S>(sd, a, f, sx, sy);
+    const double xa = Ln.xi_x[a], ya = Ln.xi_y[a], xP = LI.xi_x[P], yP = LI.xi_y[P];
+    const S dq = (S)((xa * xa + ya * ya) - (xP * xP + yP * yP));
+    f[1] = f[1] + dq * f[0];
+    sx[1] = sx[1] + dq * sx[0];
+    sy[1] = sy[1] + dq * sy[0];
+}
+
+template <typename S>
+__global__ __launch_bounds__(BS) void k_xface(const LevelDesc* __restrict__ lvs, const XFaceItem* __restrict__ items,
+                                              int n, const int* __restrict__ cell_slot,
+                                              const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
+                                              const double* __restrict__ params, Phys ph, unsigned long long* neg) {
+    __shared__ double red[MAXW * RED_MAX];
+    __shared__ int shflag;
+    const S s = (S)(0.5 * ph.dt);
+    const double cK = 3.0 - ph.D + ph.K;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const XFaceItem F = items[it];
+        const LevelDesc& LA = lvs[F.levA];
+        const LevelDesc& LB = lvs[F.levB];
+        const LevelDesc& LI = lvs[F.levI];
+        Side<S> sL, sR;
+        load_side<S>(sL, LA, F.L, cell_slot, cell_nbr, geom, F.dLx, F.dLy);
+        load_side<S>(sR, LB, F.R, cell_slot, cell_nbr, geom, F.dRx, F.dRy);
+        const double TL = params[(size_t)F.L * NPARAM + P_T], TR = params[(size_t)F.R * NPARAM + P_T];
+        // pass 1: provisional refined states and native target moments
+        double m[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) m[k] = 0.0;
+        for (int P = threadIdx.x; P < LI.N; P += BS) {
+            const double x = LI.xi_x[P], y = LI.xi_y[P], w = LI.w[P];
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const Side<S>& sd = side ? sR : sL;
+                const LevelDesc& Ln = side ? LB : LA;
+                const PairTable& tb = side ? F.IfromB : F.IfromA;
+                const int a = tb.idx[tb.off[P]];
+                S f[2], sx[2], sy[2];
+                side_slope<S>(sd, a, f, sx, sy);
+                const double xa = Ln.xi_x[a], ya = Ln.xi_y[a];
+                const double ga = (double)f[0], ha = (double)f[1];
+                const double hP = ha + ((xa * xa + ya * ya) - (x * x + y * y)) * ga;
+                double* mm = m + 8 * side;
+                mm[0] += w * ga; mm[1] += w * x * ga; mm[2] += w * y * ga;
+                mm[3] += 0.5 * w * ((x * x + y * y) * ga + hP);
+                mm[4] += w * ga; mm[5] += w * xa * ga; mm[6] += w * ya * ga;
+                mm[7] += 0.5 * w * ((xa * xa + ya * ya) * ga + ha);
+            }
+        }
+        block_sum<16>(m, red);
+        double aL[4] = {0, 0, 0, 0}, aR[4] = {0, 0, 0, 0};
+        if (ph.map_moments) {
+            for (int side = 0; side < 2; ++side) {
+                const double* mm = m + 8 * side;
+                const double T = side ? TR : TL;
+                const double dM[4] = {mm[4] - mm[0], mm[5] - mm[1], mm[6] - mm[2], mm[7] - mm[3]};
+                const double rhs[4] = {dM[0], dM[1], dM[2], dM[3] - 0.5 * cK * ph.R * T * dM[0]};
+                double* aa = side ? aR : aL;
+                for (int r = 0; r < 4; ++r) {
+                    double acc = 0.0;
+                    for (int c = 0; c < 4; ++c) acc += LI.Minv[r * 4 + c] * rhs[c];
+                    aa[r] = acc;
+                }
+            }
+        }
+        const double khL = cK * ph.R * TL, khR = cK * ph.R * TR;
+        const double u0 = 0.5 * (params[(size_t)F.L * NPARAM + P_U] + params[(size_t)F.R * NPARAM + P_U]);
+        const double v0 = 0.5 * (params[(size_t)F.L * NPARAM + P_V] + params[(size_t)F.R * NPARAM + P_V]);
+        S* rg = rowp<S>(LI.Fg, (size_t)F.scratch * LI.stride);
+        S* rh = rowp<S>(LI.Fh, (size_t)F.scratch * LI.stride);
+        // pass 2: corrected states, upwind reconstruction on V_int, face moments
+        double fm[11];
+#pragma unroll
+        for (int k = 0; k < 11; ++k) fm[k] = 0.0;
+        int nf = 0;
+        for (int P = threadIdx.x; P < LI.N; P += BS) {
+            const double xd = LI.xi_x[P], yd = LI.xi_y[P];
+            const S x = (S)xd, y = (S)yd;
+            S e[2][2];
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const Side<S>& sd = side ? sR : sL;
+                const LevelDesc& Ln = side ? LB : LA;
+                const PairTable& tb = side ? F.IfromB : F.IfromA;
+                const int a = tb.idx[tb.off[P]];
+                S f[2], sx[2], sy[2];
+                side_refined<S>(sd, Ln, LI, a, P, f, sx, sy);
+                const double* aa = side ? aR : aL;
+                const double dg = aa[0] + aa[1] * xd + aa[2] * yd + aa[3] * (xd * xd + yd * yd);
+                const S gp = f[0];
+                f[0] = (S)((double)f[0] + dg);
+                f[1] = (S)((double)f[1] + (side ? khR : khL) * dg);
+                if (f[0] < S(0) && gp >= S(0)) nf = 1;
+                e[side][0] = f[0] + ((S)sd.dx - x * s) * sx[0] + ((S)sd.dy - y * s) * sy[0];
+                e[side][1] = f[1] + ((S)sd.dx - x * s) * sx[1] + ((S)sd.dy - y * s) * sy[1];
+            }
+            const double dn = xd * F.nx + yd * F.ny;
+            S eg, eh;
+            if (dn > 0) { eg = e[0][0]; eh = e[0][1]; }
+            else if (dn < 0) { eg = e[1][0]; eh = e[1][1]; }
+            else { eg = S(0.5) * (e[0][0] + e[1][0]); eh = S(0.5) * (e[0][1] + e[1][1]); }
+            rg[P] = eg;
+            rh[P] = eh;
+            acc_raw<S>(fm, LI.w[P], xd - u0, yd - v0, eg, eh);
+        }
+        block_sum<11>(fm, red);
+        Eq<S> eq;
+        double c1, c2;
+        double Tf = 1.0;
+        face_target<S>(LI, fm, u0, v0, ph, red, ph.compat && ph.face_compat, eq, c1, c2, &Tf);
+        // pass 3: interface microflux per unit area and its moments F_int
+        double Fm[4] = {0, 0, 0, 0};
+        const S k1 = (S)c1, k2 = (S)c2;
+        for (int P = threadIdx.x; P < LI.N; P += BS) {
+            const double xd = LI.xi_x[P], yd = LI.xi_y[P], w = LI.w[P];
+            S gs, hs;
+            eq_eval<S>(eq, (S)xd, (S)yd, gs, hs);
+            const S dn = (S)(xd * F.nx + yd * F.ny);
+            const S fg = dn * (k1 * rg[P] + k2 * gs);
+            const S fh = dn * (k1 * rh[P] + k2 * hs);
+            rg[P] = fg;
+            rh[P] = fh;
+            const double wg = w * (double)fg;
+            Fm[0] += wg; Fm[1] += wg * xd; Fm[2] += wg * yd;
+            Fm[3] += 0.5 * (wg * (xd * xd + yd * yd) + w * (double)fh);
+        }
+        block_sum<4>(Fm, red);
+        // pass 4: coarsen to both native levels (provisional) and their moments
+        double pm[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pm[k] = 0.0;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const LevelDesc& Ln = side ? LB : LA;
+            const PairTable& tb = side ? F.BfromI : F.AfromI;
+            S* og = rowp<S>(Ln.Fg, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
+            S* oh = rowp<S>(Ln.Fh, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
+            for (int a = threadIdx.x; a < Ln.N; a += BS) {
+                double gA = 0.0, HA = 0.0;
+                for (int e = tb.off[a]; e < tb.off[a + 1]; ++e) {
+                    const int P = tb.idx[e];
+                    const double fr = tb.frac[e];
+                    const double xP = LI.xi_x[P], yP = LI.xi_y[P];
+                    const double gP = (double)rg[P];
+                    gA += fr * gP;
+                    HA += fr * ((double)rh[P] + (xP * xP + yP * yP) * gP);
+                }
+                const double x = Ln.xi_x[a], y = Ln.xi_y[a], w = Ln.w[a];
+                const S gs = (S)gA, hs = (S)(HA - (x * x + y * y) * gA);
+                og[a] = gs;
+                oh[a] = hs;
+                const double wg = w * (double)gs;
+                double* mm = pm + 4 * side;
+                mm[0] += wg; mm[1] += wg * x; mm[2] += wg * y; mm[3] += 0.5 * (wg * (x * x + y * y) + w * (double)hs);
+            }
+        }
+        block_sum<8>(pm, red);
+        // pass 5: four-moment flux correction to F_int (T_tar = face T), times area
+        const S ar = (S)F.area;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const LevelDesc& Ln = side ? LB : LA;
+            S* og = rowp<S>(Ln.Fg, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
+            S* oh = rowp<S>(Ln.Fh, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
+            double aa[4] = {0, 0, 0, 0};
+            if (ph.map_moments) {
+                const double* mm = pm + 4 * side;
+                const double dM[4] = {Fm[0] - mm[0], Fm[1] - mm[1], Fm[2] - mm[2], Fm[3] - mm[3]};
+                const double rhs[4] = {dM[0], dM[1], dM[2], dM[3] - 0.5 * cK * ph.R * Tf * dM[0]};
+                for (int r = 0; r < 4; ++r) {
+                    double acc = 0.0;
+                    for (int c = 0; c < 4; ++c) acc += Ln.Minv[r * 4 + c] * rhs[c];
+                    aa[r] = acc;
+                }
+            }
+            const double kh = cK * ph.R * Tf;
+            for (int a = threadIdx.x; a < Ln.N; a += BS) {
+                const double x = Ln.xi_x[a], y = Ln.xi_y[a];
+                const double dg = aa[0] + aa[1] * x + aa[2] * y + aa[3] * (x * x + y * y);
+                og[a] = ar * (S)((double)og[a] + dg);
+                oh[a] = ar * (S)((double)oh[a] + kh * dg);
+            }
+        }
+        nf = block_or(nf, &shflag);
+        if (threadIdx.x == 0 && nf) atomicAdd(neg, 1ull);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// criterion (Sec. 3.2): per cell, on the stored distribution refined to V_base
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+struct CritCtx {
+    const int* ptb;           // base -> level point of the cell's level
+    const uint8_t* prev;      // kappa of the cell's current level
+    const double *bx, *by, *bw;
+    int nx, nbx;
+    double rho_tot, E_tot, S[4];
+    double C_split, C_merge, eps_merge;
+    int flux_test;
+};
+
+template <typename S>
+__device__ bool crit_merges(const CritCtx& cc, const LevelDesc& L, const S* g, const S* h, int s, int bx, int by) {
+    const int size = 1 << s;
+    double m1 = 0.0, m2 = 0.0;
+    double Wb = 0.0, Wx = 0.0, Wy = 0.0, Wg = 0.0, WH = 0.0;
+    double Ff[4][2][2];
+    for (int r = 0; r < 4; ++r)
+        for (int d = 0; d < 2; ++d) { Ff[r][d][0] = 0.0; Ff[r][d][1] = 0.0; }
+    for (int iy = by * size; iy < by * size + size; ++iy)
+        for (int ix = bx * size; ix < bx * size + size; ++ix) {
+            const int b = ix + cc.nx * iy;
+            const int p = cc.ptb[b];
+            const double gp = (double)g[p];
+            const double xp = L.xi_x[p], yp = L.xi_y[p];
+            const double Hb = (double)h[p] + (xp * xp + yp * yp) * gp;
+            const double w = cc.bw[b], x = cc.bx[b], y = cc.by[b];
+            m1 += w * gp;
+            m2 += 0.5 * w * Hb;
+            if (cc.flux_test) {
+                Wb += w; Wx += w * x; Wy += w * y; Wg += w * gp; WH += w * Hb;
+                const double mr[4] = {gp, x * gp, y * gp, 0.5 * Hb};
+                const double xd[2] = {x, y};
+                for (int d = 0; d < 2; ++d)
+                    for (int r = 0; r < 4; ++r) {
+                        const double t = w * xd[d] * mr[r];
+                        if (xd[d] >= 0) Ff[r][d][0] += t;
+                        if (-xd[d] >= 0) Ff[r][d][1] += t;
+                    }
+            }
+        }
+    const double I = fmax(m1 / cc.rho_tot, m2 / cc.E_tot);
+    bool prev_merged = true;
+    const int csz = size >> 1;
+    for (int cy = by * csz; cy < by * csz + csz; ++cy)
+        for (int cx = bx * csz; cx < bx * csz + csz; ++cx)
+            if (cc.prev[cx + cc.nbx * cy] < s) prev_merged = false;
+    bool cand = (I < cc.C_merge) || (cc.C_merge <= I && I <= cc.C_split && prev_merged);
+    if (cand && cc.flux_test) {
+        const double xB = Wx / Wb, yB = Wy / Wb, gB = Wg / Wb, HB = WH / Wb;
+        const double mB[4] = {gB, xB * gB, yB * gB, 0.5 * HB};
+        const double xdB[2] = {xB, yB};
+        double err = 0.0;
+        for (int d = 0; d < 2; ++d)
+            for (int sg = 0; sg < 2; ++sg) {
+                const bool on = (sg == 0) ? (xdB[d] >= 0) : (-xdB[d] >= 0);
+                for (int r = 0; r < 4; ++r) {
+                    const double Fm = on ? Wb * xdB[d] * mB[r] : 0.0;
+                    err = fmax(err, fabs(Ff[r][d][sg] - Fm) / cc.S[r]);
+                }
+            }
+        cand = err <= cc.eps_merge;
+    }
+    return cand;
+}
+
+template <typename S>
+__global__ __launch_bounds__(BS) void k_criterion(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
+                                                  const int* __restrict__ cell_slot, int n_cells,
+                                                  const int* __restrict__ ptb_all, const int* __restrict__ ptb_off,
+                                                  const uint8_t* __restrict__ kappa_all, const double* __restrict__ bx,
+                                                  const double* __restrict__ by, const double* __restrict__ bw,
+                                                  int nx, int ny, double C_split, double C_merge, double eps_merge,
+                                                  int flux_test, uint8_t* __restrict__ kout,
+                                                  unsigned long long* __restrict__ hout) {
+    __shared__ double red[MAXW * RED_MAX];
+    __shared__ unsigned long long hred[MAXW];
+    const int nbx = nx / 2, nby = ny / 2, Nb = nbx * nby, Nbase = nx * ny;
+    const int n8x = nbx / 4, n8y = nby / 4, n4x = nbx / 2, n4y = nby / 2;
+    for (int c = blockIdx.x; c < n_cells; c += gridDim.x) {
+        const int lev = cell_lev[c];
+        const LevelDesc& L = lvs[lev];
+        const size_t row = (size_t)cell_slot[c] * L.stride;
+        const S* g = rowp<S>(L.g, row);
+        const S* h = rowp<S>(L.h, row);
+        CritCtx cc;
+        cc.ptb = ptb_all + (size_t)ptb_off[lev];
+        cc.prev = kappa_all + (size_t)lev * Nb;
+        cc.bx = bx; cc.by = by; cc.bw = bw; cc.nx = nx; cc.nbx = nbx;
+        cc.C_split = C_split; cc.C_merge = C_merge; cc.eps_merge = eps_merge; cc.flux_test = flux_test;
+        double t[10];
+#pragma unroll
+        for (int k = 0; k < 10; ++k) t[k] = 0.0;
+        for (int b = threadIdx.x; b < Nbase; b += BS) {
+            const int p = cc.ptb[b];
+            const double gp = (double)g[p];
+            const double xp = L.xi_x[p], yp = L.xi_y[p];
+            const double Hb = (double)h[p] + (xp * xp + yp * yp) * gp;
+            const double w = bw[b], x = bx[b], y = by[b];
+            t[0] += w * gp;
+            t[1] += 0.5 * w * Hb;
+            const double mr[4] = {fabs(gp), fabs(x * gp), fabs(y * gp), fabs(0.5 * Hb)};
+            for (int r = 0; r < 4; ++r) {
+                t[2 + r] += w * fabs(x) * mr[r];
+                t[6 + r] += w * fabs(y) * mr[r];
+            }
+        }
+        block_sum<10>(t, red);
+        cc.rho_tot = t[0];
+        cc.E_tot = t[1];
+        for (int r = 0; r < 4; ++r) cc.S[r] = fmax(t[2 + r], t[6 + r]);
+        uint8_t* ko = kout + (size_t)c * Nb;
+        // top-level candidates: eligible 8x8 blocks, then 4x4 and 2x2 blocks outside them
+        const int n8 = n8x * n8y;
+        const int n4rest = n4x * n4y - (2 * n8x) * (2 * n8y);
+        const int n2rest = nbx * nby - (2 * n4x) * (2 * n4y);
+        const int ntop = n8 + n4rest + n2rest;
+        for (int tb = threadIdx.x; tb < ntop; tb += BS) {
+            int s0, X0, Y0;
+            if (tb < n8) { s0 = 3; X0 = tb % n8x; Y0 = tb / n8x; }
+            else if (tb < n8 + n4rest) {
+                int k = tb - n8, cnt = 0;
+                s0 = 2; X0 = Y0 = 0;
+                for (int qy = 0; qy < n4y; ++qy)
+                    for (int qx = 0; qx < n4x; ++qx) {
+                        if (qx < 2 * n8x && qy < 2 * n8y) continue;
+                        if (cnt++ == k) { X0 = qx; Y0 = qy; qy = n4y; break; }
+                    }
+            } else {
+                int k = tb - n8 - n4rest, cnt = 0;
+                s0 = 1; X0 = Y0 = 0;
+                for (int yy = 0; yy < nby; ++yy)
+                    for (int xx = 0; xx < nbx; ++xx) {
+                        if (xx < 2 * n4x && yy < 2 * n4y) continue;
+                        if (cnt++ == k) { X0 = xx; Y0 = yy; yy = nby; break; }
+                    }
+            }
+            // explicit coarse-to-fine descent (at most 1 + 4 + 16 candidates)
+            int stk_s[24], stk_x[24], stk_y[24], sp = 0;
+            stk_s[sp] = s0; stk_x[sp] = X0; stk_y[sp] = Y0; ++sp;
+            while (sp > 0) {
+                --sp;
+                const int s = stk_s[sp], X = stk_x[sp], Y = stk_y[sp];
+                const bool mg = crit_merges<S>(cc, L, g, h, s, X, Y);
+                const int csz = 1 << (s - 1);
+                if (mg || s == 1) {
+                    const uint8_t v = mg ? (uint8_t)s : (uint8_t)0;
+                    for (int cy = Y * csz; cy < Y * csz + csz; ++cy)
+                        for (int cx = X * csz; cx < X * csz + csz; ++cx) ko[cx + nbx * cy] = v;
+                } else {
+                    for (int k = 3; k >= 0; --k) {
+                        stk_s[sp] = s - 1; stk_x[sp] = 2 * X + (k & 1); stk_y[sp] = 2 * Y + (k >> 1); ++sp;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        unsigned long long hs = 0ull;
+        for (int b = threadIdx.x; b < Nb; b += BS) hs += mix64(((unsigned long long)b << 2) | ko[b]);
+        for (int off = 32; off > 0; off >>= 1) hs += __shfl_xor(hs, off, 64);
+        if ((threadIdx.x & 63) == 0) hred[threadIdx.x >> 6] = hs;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tot = 0ull;
+            for (int w = 0; w < MAXW; ++w) tot += hred[w];
+            hout[c] = tot;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_gather_rows_u8(const uint8_t* __restrict__ src, int width, const int* __restrict__ rows, int n,
+                                 uint8_t* __restrict__ dst) {
+    for (int r = blockIdx.x; r < n; r += gridDim.x)
+        for (int k = threadIdx.x; k < width; k += blockDim.x) dst[(size_t)r * width + k] = src[(size_t)rows[r] * width + k];
+}
+
+__global__ void k_compare_rows_u8(const uint8_t* __restrict__ all, int width, const int* __restrict__ rep_of_cell,
+                                  const uint8_t* __restrict__ reps, int n, unsigned long long* mismatch) {
+    for (int c = blockIdx.x; c < n; c += gridDim.x) {
+        int bad = 0;
+        const uint8_t* a = all + (size_t)c * width;
+        const uint8_t* r = reps + (size_t)rep_of_cell[c] * width;
+        for (int k = threadIdx.x; k < width; k += blockDim.x) bad |= (a[k] != r[k]);
+        if (bad) atomicAdd(mismatch, 1ull);
+    }
+}
+
 hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFaceItem* items, int n,
                         const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
                         Phys ph, unsigned long long* neg) {
     if (n <= 0) return hipSuccess;
-    return hipErrorNotSupported;
+    MLVS_DISPATCH(prec, k_xface, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr, geom, params,
+                  ph, neg);
+    return hipGetLastError();
+}
+
+hipError_t launch_criterion(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
+                            int n_cells, const int* pt_of_base_all, const int* pt_off, const uint8_t* kappa_all,
+                            const double* bxi_x, const double* bxi_y, const double* bw, int nx, int ny,
+                            double C_split, double C_merge, double eps_merge, int flux_test, uint8_t* kappa_out,
+                            unsigned long long* hash_out) {
+    if (n_cells <= 0) return hipSuccess;
+    MLVS_DISPATCH(prec, k_criterion, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
+                  pt_of_base_all, pt_off, kappa_all, bxi_x, bxi_y, bw, nx, ny, C_split, C_merge, eps_merge, flux_test,
+                  kappa_out, hash_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows_u8(hipStream_t st, const uint8_t* src, int width, const int* rows, int n,
+                                 uint8_t* dst) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_rows_u8, dim3(grid_for(n)), dim3(BS), 0, st, src, width, rows, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_compare_rows_u8(hipStream_t st, const uint8_t* all, int width, const int* rep_of_cell,
+                                  const uint8_t* reps, int n, unsigned long long* mismatch) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compare_rows_u8, dim3(grid_for(n)), dim3(BS), 0, st, all, width, rep_of_cell, reps, n,
+                       mismatch);
+    return hipGetLastError();
 }
 
 }  // namespace mlvs

@@ -1,0 +1,140 @@
+"""GPU parity of the multi-level path (FP64) against the oracle.
+
+Covers: the level switch (projection + four-moment mapping correction), the
+step with neighbours on other levels and cross-level faces on V_int, the
+criterion masks, the grouping into levels, and conservation to round-off.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import levels as lv
+from oracle.solver import AdaptParams
+from oracle.solver import Solver as Oracle
+from tests.parity import state_error
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _gpu(p, **kw):
+    import paper_2609_35258_amd as m
+    return m.Solver.from_problem(p, **kw)
+
+
+def _sine(ni=10, nj=4, nv=24, seed=2):
+    return W.perturb(W.periodic_box(ni, nj, Lx=1.0, Ly=0.4, Kn=0.05, nv=nv, vmax=5.0, kind="sine", amp=0.5),
+                     seed=seed)
+
+
+def _catalog(nv, n_levels, seed):
+    nb = nv // 2
+    ks = [np.zeros(nb * nb, np.uint8)] + [W.random_kappa(nb, nb, seed + k) for k in range(n_levels - 1)]
+    return np.stack(ks)
+
+
+@pytest.mark.parametrize("n_levels,axis,seed", [(2, 0, 1), (3, 1, 7), (4, 0, 12)])
+def test_fixed_catalog_remap_and_steps(n_levels, axis, seed):
+    p = _sine()
+    print("case fixed catalog", n_levels, axis, seed, flush=True)
+    kap = _catalog(p.nv, n_levels, seed)
+    cl = W.striped_levels(p.ni, p.nj, n_levels, axis)
+    o = Oracle(p, compat=4)
+    g = _gpu(p, compat=4)
+    o.set_levels(list(kap), cl)
+    g.set_levels(kap, cl)
+    assert np.array_equal(g.cell_levels(), cl)
+    e = state_error(g.get_state(), o.g, o.h)
+    assert max(e) < TOL, ("remap", e)
+    t0 = g.totals()
+    _, _, ncross = g.level_info()
+    assert ncross > 0
+    for k in range(4):
+        o.step()
+        g.step(1)
+        e = state_error(g.get_state(), o.g, o.h)
+        assert max(e) < TOL, (k, e)
+    assert np.max(np.abs(g.totals() - t0)) < 1e-13
+    g.close()
+
+
+def test_criterion_catalog_cylinder_walls_and_far_field():
+    # catalogue from the oracle's criterion + grouping on a perturbed Ma-3 start
+    p = W.perturb(W.cylinder(16, 8, Kn=0.1, nv=32, vmax=10.0), seed=3, amp=0.1)
+    print("case cylinder catalog", flush=True)
+    o1 = Oracle(p, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 1e-3, 0.02, True, 100))
+    kap, cl = lv.cluster_masks(o1.criterion_masks(), 0.02)
+    assert len(kap) >= 2
+    o = Oracle(p, compat=4)
+    g = _gpu(p, compat=4)
+    o.set_levels(kap, cl)
+    g.set_levels(np.stack(kap), cl)
+    e = state_error(g.get_state(), o.g, o.h)
+    assert max(e) < TOL, ("remap", e)
+    for k in range(3):
+        o.step()
+        g.step(1)
+        e = state_error(g.get_state(), o.g, o.h)
+        assert max(e) < TOL, (k, e)
+    g.close()
+
+
+def _near_threshold(o, C_split, C_merge, rel=1e-9):
+    """Blocks whose indicator lies within rel of a threshold, per cell (oracle side)."""
+    out = []
+    base = o.base
+    for c in range(o.mesh.n_cells):
+        L = o.levels[o.cell_level[c]]
+        gb, hb = lv.refine_to_base(L, o.g[c], o.h[c])
+        w, xi = base.w, base.xi
+        x2 = np.sum(xi * xi, 1)
+        M1 = w * gb / np.sum(w * gb)
+        M2 = 0.5 * w * (hb + x2 * gb) / np.sum(0.5 * w * (hb + x2 * gb))
+        amb = np.zeros(base.Nb, bool)
+        for s in (1, 2, 3):
+            n = 1 << (s - 1)
+            for by in range(base.nby // n):
+                for bx in range(base.nbx // n):
+                    pts = base.block_points(s, bx, by)
+                    I = max(M1[pts].sum(), M2[pts].sum())
+                    for C in (C_split, C_merge):
+                        if abs(I - C) <= rel * C:
+                            amb[base.block_children2(s, bx, by)] = True
+        out.append(amb)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("flux_test", [False, True])
+def test_criterion_masks_match(flux_test):
+    p = _sine(nv=32, seed=4)
+    ap = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=1e-3, tau_clust=0.05, flux_test=flux_test, interval=0)
+    o = Oracle(p, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 1e-3, 0.05, flux_test, 1))
+    g = _gpu(p, compat=4, adapt=ap)
+    ko = o.criterion_masks()
+    kg = g.criterion()
+    amb = _near_threshold(o, 5e-3, 2.5e-3)
+    diff = (ko != kg) & ~amb
+    assert not diff.any(), int(diff.sum())
+    assert kg.max() >= 2
+    g.close()
+
+
+def test_adaptive_run_matches_oracle():
+    p = _sine(nv=24, seed=9)
+    ap = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=1e-3, tau_clust=0.02, flux_test=True, interval=2)
+    o = Oracle(p, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 1e-3, 0.02, True, 2))
+    g = _gpu(p, compat=4, adapt=ap)
+    t0 = g.totals()
+    for k in range(5):
+        o.step()
+        g.step(1)
+        npts, ncells, ncross = g.level_info()
+        assert len(npts) == len(o.levels), k
+        for l in range(len(npts)):
+            assert np.array_equal(g.level_kappa(l), o.levels[l].kappa), (k, l)
+        assert np.array_equal(g.cell_levels(), o.cell_level), k
+        e = state_error(g.get_state(), o.g, o.h)
+        assert max(e) < TOL, (k, e)
+    assert len(o.levels) >= 2
+    assert np.max(np.abs(g.totals() - t0)) < 1e-13
+    g.close()

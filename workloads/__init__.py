@@ -216,3 +216,32 @@ def random_states(seed: int, n: int, dim: int = 2):
     qx = rng.uniform(-0.05, 0.05, n)
     qy = rng.uniform(-0.05, 0.05, n) if dim == 2 else np.zeros(n)
     return rho, u, v, T, qx, qy
+
+
+def random_kappa(nbx: int, nby: int, seed: int, p8: float = 0.25, p4: float = 0.33,
+                 p2: float = 0.5) -> np.ndarray:
+    """A seeded random coarsening-index array on nbx x nby 2x2 blocks that is
+    parent-child consistent (whole 8x8 / 4x4 merges only where those blocks fit)."""
+    rng = np.random.default_rng(seed)
+    k = np.zeros((nby, nbx), np.uint8)
+    for by in range(nby):
+        for bx in range(nbx):
+            k[by, bx] = 1 if rng.random() < p2 else 0
+    for qy in range(nby // 2):
+        for qx in range(nbx // 2):
+            if rng.random() < p4:
+                k[2 * qy:2 * qy + 2, 2 * qx:2 * qx + 2] = 2
+    for oy in range(nby // 4):
+        for ox in range(nbx // 4):
+            if rng.random() < p8:
+                k[4 * oy:4 * oy + 4, 4 * ox:4 * ox + 4] = 3
+    return k.ravel()
+
+
+def striped_levels(ni: int, nj: int, n_levels: int, axis: int = 0) -> np.ndarray:
+    """Cell -> level index in stripes along one mesh axis (cell c = i + ni*j)."""
+    i = np.arange(ni)[None, :].repeat(nj, 0)
+    j = np.arange(nj)[:, None].repeat(ni, 1)
+    idx = i if axis == 0 else j
+    n = ni if axis == 0 else nj
+    return (idx * n_levels // n).ravel().astype(np.int32)
