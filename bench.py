@@ -1,0 +1,163 @@
+"""Benchmark: MLVS-DUGKS cell-velocity updates/s on one MI355X, MLVS vs UVS.
+
+Workload (synthetic, deterministic): 2-D lid-driven cavity, 64 x 64 uniform
+cells on [0,1]^2, lid Mach 0.16, Kn 0.075, Shakhov Pr 2/3, 28 x 28
+Gauss-Hermite base velocity grid, FP64.  MLVS: criterion C_split 5e-3,
+C_merge 2.5e-3, transport-error test eps 5e-5, tau_clust 0.05, adaptation
+every 100 steps (levels built from the distributions); UVS: the same run on
+the fixed base grid.  A step is one pass of the whole hot path (adaptation at
+its interval, cell stage, neighbour mapping, same-level / boundary /
+cross-level faces, update).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+ADAPT = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=5e-5, tau_clust=0.05, flux_test=True, interval=100)
+
+
+def workload(args):
+    return W.cavity(args.n, Kn=0.075, nv=args.nv)
+
+
+def run_gpu(p, steps, warmup, precision, adapt):
+    import torch
+    import paper_2609_35258_amd as m
+    s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=adapt)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    c0 = s.counters()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c1 = s.counters()
+    return s, t1 - t0, c1["cell_updates"] - c0["cell_updates"], c1["iface_points"] - c0["iface_points"]
+
+
+def stage_profile(s, reps=20):
+    """Mean ms per launch of each stage (HIP events on the context stream)."""
+    out = {}
+    for st in ("cell", "ghost", "face", "bface", "xface"):
+        items, pts = s.stage_size(st)
+        if items == 0:
+            continue
+        out[st] = {"ms": s.time_stage(st, reps), "items": items, "points": pts}
+    return out
+
+
+# algorithmic bytes per velocity point of each stage (FP64 values, 8 B; FP32, 4 B):
+#   cell:  read g~,h~ + write phi_bar+ g,h                   -> 4 values
+#   face:  read phi_bar+ g,h of the upwind cell + write F g,h -> 4 values
+#   bface: same as face                                        -> 4 values
+#   xface: per V_int point, read both sides' phi_bar+ (2x2) + write one native flux row (2) -> 6 values
+#   ghost: read source phi_bar+ + write mapped row            -> 4 values
+ALG_VALUES = {"cell": 4, "face": 4, "bface": 4, "xface": 6, "ghost": 4}
+
+
+def cpu_baseline(p, sample_steps=2, sample_cells=256):
+    """The oracle as it stands on the same workload: full-size steps from the
+    initial state plus the criterion on a sample of cells (scaled to the whole
+    mesh), the adaptation amortised over its interval."""
+    from oracle import levels as lv
+    from oracle.solver import Solver as Oracle
+    o = Oracle(p, compat=4)
+    t0 = time.perf_counter()
+    for c in range(min(sample_cells, o.mesh.n_cells)):
+        lv.criterion(o.levels[0], o.g[c], o.h[c], ADAPT["C_split"], ADAPT["C_merge"], ADAPT["eps_merge"],
+                     ADAPT["flux_test"])
+    t_crit = (time.perf_counter() - t0) * o.mesh.n_cells / min(sample_cells, o.mesh.n_cells)
+    t0 = time.perf_counter()
+    for _ in range(sample_steps):
+        o.step()
+    t_step = (time.perf_counter() - t0) / sample_steps
+    pts = float(o.mesh.n_cells * o.levels[0].N)
+    rate = pts / (t_step + t_crit / ADAPT["interval"])
+    return {"value": rate, "unit": "cell-velocity updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%dx%d cavity, %d-point base grid: %d oracle steps (%.2f s/step) + criterion on %d cells "
+                      "(scaled to %d cells: %.1f s), adaptation amortised over %d steps"
+                      % (p.ni, p.nj, o.levels[0].N, sample_steps, t_step, sample_cells, o.mesh.n_cells,
+                         t_crit, ADAPT["interval"])}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--nv", type=int, default=28)
+    ap.add_argument("--precision", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-uvs", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    p = workload(args)
+    s, t_mlvs, upd, ipts = run_gpu(p, args.steps, args.warmup, args.precision, ADAPT)
+    value = upd / t_mlvs
+    npts, ncells, ncross = s.level_info()
+    nbar = float(np.sum(npts * ncells) / np.sum(ncells))
+    prof = stage_profile(s)
+    evsz = 8 if args.precision == 64 else 4
+    # dominant kernel: largest time per step among the stages
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    alg_bytes = d["points"] * ALG_VALUES[dom] * evsz
+    achieved = alg_bytes / (d["ms"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "stage_ms": {k: round(v["ms"], 5) for k, v in prof.items()}}
+    fields_m = s.moments()
+    mem_m = s.memory()
+    out = {"metric": "DUGKS cell-velocity updates/s (MLVS-DUGKS hot path, adaptation included)",
+           "value": value, "unit": "cell-velocity updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * t_mlvs / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == 64 else "f32",
+           "data": "synthetic",
+           "config": {"workload": "lid-driven cavity %dx%d, Kn 0.075, lid Ma 0.16, Shakhov Pr 2/3, %dx%d "
+                                  "Gauss-Hermite base grid, MLVS (criterion levels, interval 100)"
+                                  % (args.n, args.n, args.nv, args.nv),
+                      "n_cells": p.n_cells, "base_points": args.nv * args.nv, "levels": len(npts),
+                      "level_points": [int(x) for x in npts], "level_cells": [int(x) for x in ncells],
+                      "nbar": nbar, "n_cross": int(ncross), "iface_points_per_s": ipts / t_mlvs},
+           "roofline": roof}
+    s.close()
+    if not args.no_uvs:
+        u, t_uvs, upd_u, _ = run_gpu(p, args.steps, args.warmup, args.precision, None)
+        fields_u = u.moments()
+        mem_u = u.memory()
+        vol = np.ones(p.n_cells)
+        err = {}
+        for k, name in ((0, "rho"), (1, "u"), (3, "T")):
+            a, b = fields_m[:, k], fields_u[:, k]
+            err[name] = float(np.sqrt(np.sum(vol * (a - b) ** 2) / np.sum(vol * b ** 2)))
+        out["uvs"] = {"value": upd_u / t_uvs, "ms_per_step": 1e3 * t_uvs / args.steps,
+                      "time_to_solution_ratio": t_uvs / t_mlvs, "memory_ratio": mem_u / mem_m,
+                      "mlvs_vs_uvs_rel_l2": err}
+        u.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -195,6 +195,23 @@ mlvs_status mlvs_set_state(mlvs_ctx ctx, const double* g, const double* h);
 /* Time step in use, mesh hmin, and counts: n_cells, N_b (2x2 blocks). */
 mlvs_status mlvs_info(mlvs_ctx ctx, double* dt, int64_t* n_cells, int32_t* n_blocks, int32_t* n_base);
 
+/* Work counters since creation: steps taken, cell-velocity updates on the
+ * cells' own levels (sum over steps of sum over cells of the level size),
+ * interface-space points processed on cross-level faces, adaptations. */
+mlvs_status mlvs_counters(mlvs_ctx ctx, int64_t* steps, double* cell_updates, double* iface_points,
+                          int64_t* adaptations);
+
+/* Profiling: launch one stage of the step `reps` times on the context stream,
+ * bracketed by two HIP events recorded on that stream, and return the mean
+ * duration per launch in milliseconds.  stage: 0 cell, 1 neighbour mapping,
+ * 2 same-level faces, 3 boundary faces, 4 cross-level faces, 5 update
+ * (advances g~, h~ once per repetition), 6 criterion.  Synchronises. */
+mlvs_status mlvs_time_stage(mlvs_ctx ctx, int stage, int reps, double* ms_per_launch);
+
+/* Item counts of a stage's launch (cells, ghost rows, faces, ...) and the
+ * total number of velocity points the launch processes. */
+mlvs_status mlvs_stage_size(mlvs_ctx ctx, int stage, int64_t* items, double* points);
+
 /* Device bytes held by the context. */
 mlvs_status mlvs_memory(mlvs_ctx ctx, size_t* device_bytes);
 

@@ -93,6 +93,11 @@ _PROTOS = {
     "mlvs_info": (ctypes.c_int, [ctypes.c_void_p, _c_double_p, ctypes.POINTER(ctypes.c_int64), _c_int32_p,
                                  _c_int32_p]),
     "mlvs_memory": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "mlvs_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), _c_double_p, _c_double_p,
+                                     ctypes.POINTER(ctypes.c_int64)]),
+    "mlvs_time_stage": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_double_p]),
+    "mlvs_stage_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                       _c_double_p]),
     "mlvs_neg_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "mlvs_destroy": (None, [ctypes.c_void_p]),
     "mlvs_last_error": (ctypes.c_char_p, []),
@@ -320,6 +325,26 @@ class Solver:
         v = ctypes.c_size_t()
         _check(lib().mlvs_memory(self.h, ctypes.byref(v)))
         return v.value
+
+    def counters(self):
+        st, ad = ctypes.c_int64(), ctypes.c_int64()
+        up, ip = ctypes.c_double(), ctypes.c_double()
+        _check(lib().mlvs_counters(self.h, ctypes.byref(st), ctypes.byref(up), ctypes.byref(ip), ctypes.byref(ad)))
+        return {"steps": st.value, "cell_updates": up.value, "iface_points": ip.value, "adaptations": ad.value}
+
+    STAGES = {"cell": 0, "ghost": 1, "face": 2, "bface": 3, "xface": 4, "update": 5, "criterion": 6}
+
+    def time_stage(self, stage, reps: int = 10):
+        """Mean ms per launch of one stage, timed with HIP events on the context stream."""
+        ms = ctypes.c_double()
+        _check(lib().mlvs_time_stage(self.h, self.STAGES.get(stage, stage), int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    def stage_size(self, stage):
+        it = ctypes.c_int64()
+        pts = ctypes.c_double()
+        _check(lib().mlvs_stage_size(self.h, self.STAGES.get(stage, stage), ctypes.byref(it), ctypes.byref(pts)))
+        return it.value, pts.value
 
     def neg_count(self):
         v = ctypes.c_int64()

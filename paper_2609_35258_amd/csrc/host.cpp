@@ -555,6 +555,10 @@ struct mlvs_ctx_s {
     uint8_t* d_kcell = nullptr;
     unsigned long long* d_hash = nullptr;
     int64_t last_unique = 0;
+    // counters
+    double cnt_updates = 0.0, cnt_iface = 0.0;
+    int64_t cnt_adapt = 0;
+    double step_points = 0.0, step_iface_points = 0.0;   // per step, current level set
 
     size_t elt() const { return prec == 32 ? 4 : 8; }
 };
@@ -728,6 +732,10 @@ void build_items(mlvs_ctx c) {
         it.BfromI = table(it.levB, it.levI).view();
     }
     c->n_cross = n_cross;
+    c->step_points = 0.0;
+    for (int cc = 0; cc < n; ++cc) c->step_points += c->levels[c->cell_level[cc]]->N;
+    c->step_iface_points = 0.0;
+    for (auto& it : xitems) c->step_iface_points += level_by_index(c, it.levI).N;
     for (size_t b = 0; b < M.bfaces.size(); ++b) {
         const FaceH& F = M.bfaces[b];
         const int lc = c->cell_level[F.L];
@@ -801,6 +809,7 @@ void assign_slots(mlvs_ctx c) {
 void sync(mlvs_ctx c) { hip_check(hipStreamSynchronize(c->st), "stream synchronize"); }
 
 void do_step(mlvs_ctx c);
+hipError_t launch_stage(mlvs_ctx c, int stage);
 
 }  // namespace
 
@@ -1019,6 +1028,7 @@ void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
     for (int i = 0; i < c->mesh.n_cells; ++i) cl[i] = level_of_u[uidx[i]];
     const int64_t changed = install_levels(c, std::move(nl), cl);
     c->last_unique = (int64_t)first.size();
+    ++c->cnt_adapt;
     if (rep) {
         rep->n_levels = (int)c->levels.size();
         rep->n_unique = c->last_unique;
@@ -1207,6 +1217,69 @@ mlvs_status mlvs_info(mlvs_ctx c, double* dt, int64_t* n_cells, int32_t* n_block
         if (n_cells) *n_cells = c->mesh.n_cells;
         if (n_blocks) *n_blocks = c->base.Nb;
         if (n_base) *n_base = c->base.N;
+    });
+}
+
+mlvs_status mlvs_counters(mlvs_ctx c, int64_t* steps, double* cell_updates, double* iface_points,
+                          int64_t* adaptations) {
+    return guarded([&] {
+        if (!c) fail(MLVS_E_ARG, "null context");
+        if (steps) *steps = c->step_count;
+        if (cell_updates) *cell_updates = c->cnt_updates;
+        if (iface_points) *iface_points = c->cnt_iface;
+        if (adaptations) *adaptations = c->cnt_adapt;
+    });
+}
+
+mlvs_status mlvs_time_stage(mlvs_ctx c, int stage, int reps, double* ms) {
+    return guarded([&] {
+        if (!c || !ms || reps < 1 || stage < 0 || stage > 6) fail(MLVS_E_ARG, "bad arguments");
+        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
+        if (stage == 6 && !c->adaptive) fail(MLVS_E_STATE, "criterion needs adaptation parameters");
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "event");
+        hip_check(hipEventCreate(&e1), "event");
+        hip_check(hipEventRecord(e0, c->st), "event record");
+        for (int r = 0; r < reps; ++r) {
+            if (stage == 6) run_criterion(c);
+            else hip_check(launch_stage(c, stage), "stage launch");
+        }
+        hip_check(hipEventRecord(e1, c->st), "event record");
+        hip_check(hipEventSynchronize(e1), "event sync");
+        float t = 0.f;
+        hip_check(hipEventElapsedTime(&t, e0, e1), "elapsed");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *ms = (double)t / reps;
+    });
+}
+
+mlvs_status mlvs_stage_size(mlvs_ctx c, int stage, int64_t* items, double* points) {
+    return guarded([&] {
+        if (!c || stage < 0 || stage > 6) fail(MLVS_E_ARG, "bad arguments");
+        int64_t ni = 0;
+        double np = 0.0;
+        switch (stage) {
+        case 0: case 5: case 6:
+            ni = c->mesh.n_cells;
+            np = stage == 6 ? (double)c->mesh.n_cells * c->base.N : c->step_points;
+            break;
+        case 1: ni = c->n_ghosts; for (auto& L : c->levels) np += (double)L->n_ghost * L->N; break;
+        case 2: {
+            ni = c->n_faces;
+            std::vector<double> per(c->levels.size(), 0.0);
+            // same-level faces: each carries its level's points
+            for (auto& f : c->mesh.faces) {
+                const int a = c->cell_level[f.L];
+                if (a == c->cell_level[f.R]) np += c->levels[a]->N;
+            }
+            break;
+        }
+        case 3: ni = c->n_bfaces; for (auto& f : c->mesh.bfaces) np += c->levels[c->cell_level[f.L]]->N; break;
+        case 4: ni = c->n_xfaces; np = c->step_iface_points; break;
+        }
+        if (items) *items = ni;
+        if (points) *points = np;
     });
 }
 
@@ -1413,6 +1486,26 @@ void do_step(mlvs_ctx c) {
     hip_check(launch_update(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom, c->d_cell_frow,
                             c->ph), "update stage");
     ++c->step_count;
+    c->cnt_updates += c->step_points;
+    c->cnt_iface += c->step_iface_points;
+}
+
+hipError_t launch_stage(mlvs_ctx c, int stage) {
+    const int n = c->mesh.n_cells;
+    switch (stage) {
+    case 0: return launch_cell_prep(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->ph, c->d_params);
+    case 1: return launch_ghost(c->prec, c->st, c->d_lv, c->d_ghosts, c->n_ghosts, c->d_cell_lev, c->d_cell_slot,
+                                c->d_params, c->ph, c->d_neg);
+    case 2: return launch_face(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces, c->d_cell_slot, c->d_cell_nbr,
+                               c->d_geom, c->d_params, c->ph);
+    case 3: return launch_bface(c->prec, c->st, c->d_lv, c->d_bfaces, c->n_bfaces, c->d_cell_slot, c->d_cell_nbr,
+                                c->d_geom, c->d_bcs, c->ph);
+    case 4: return launch_xface(c->prec, c->st, c->d_lv, c->d_xfaces, c->n_xfaces, c->d_cell_slot, c->d_cell_nbr,
+                                c->d_geom, c->d_params, c->ph, c->d_neg);
+    case 5: return launch_update(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom,
+                                 c->d_cell_frow, c->ph);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace

@@ -1,10 +1,11 @@
 // HIP kernels of the MLVS-DUGKS step for gfx950.
 //
-// Work decomposition: one workgroup per item (cell, face, ghost row, remap),
-// lanes stride over the item's velocity points (velocity index contiguous in
-// memory, so every load of a row is coalesced); velocity-space moments are
-// reduced in registers, then across the wave with butterfly shuffles and
-// across waves through LDS in a fixed order (deterministic).  One launch per
+// Work decomposition: one 64-lane wavefront per item (cell, face, ghost row,
+// remap); a 256-thread workgroup carries four independent items.  Lanes
+// stride over the item's velocity points (velocity index contiguous in
+// memory, so every row access is coalesced); velocity-space moments are
+// reduced in registers, then across the wave with a fixed butterfly of
+// shuffles (deterministic, no LDS and no barriers).  One launch per
 // stage covers every level: each item names its own level.  Storage type S is
 // float or double; per-velocity arithmetic runs in S; moment sums, the small
 // linear solves and the per-cell parameters are double.
@@ -15,75 +16,64 @@
 namespace mlvs {
 
 constexpr int BS = 256;             // threads per workgroup
-constexpr int MAXW = BS / 64;       // waves per workgroup
+constexpr int WL = 64;              // lanes per wavefront
+constexpr int MAXW = BS / WL;       // waves (items) per workgroup
 constexpr int RED_MAX = 32;         // largest reduction width
 
-template <typename S>
-__device__ __forceinline__ S* rowp(void* base, size_t off) { return reinterpret_cast<S*>(base) + off; }
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WL - 1); }
+__device__ __forceinline__ int item0() { return blockIdx.x * MAXW + (threadIdx.x >> 6); }
+__device__ __forceinline__ int istride() { return gridDim.x * MAXW; }
 
-// Sum NV doubles over the workgroup; every thread receives the totals.
+// Sum NV doubles over the wavefront; every lane receives the totals.
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* red) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+__device__ __forceinline__ void wave_sum(double (&v)[NV]) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double x = v[k];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, WL);
         v[k] = x;
     }
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) red[wid * NV + k] = v[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double s = 0.0;
-        for (int w = 0; w < MAXW; ++w) s += red[w * NV + k];
-        v[k] = s;
-    }
-    __syncthreads();
 }
 
-__device__ __forceinline__ int block_or(int flag, int* sh) {
-    __syncthreads();
-    if (threadIdx.x == 0) *sh = 0;
-    __syncthreads();
-    if (flag) atomicOr(sh, 1);
-    __syncthreads();
-    int r = *sh;
-    __syncthreads();
-    return r;
-}
+template <typename S>
+__device__ __forceinline__ S* rowp(void* base, size_t off) { return reinterpret_cast<S*>(base) + off; }
 
-// Gaussian elimination with partial pivoting, n <= 4; returns false if singular.
-__device__ bool solve_small(int n, double* A, double* b) {
-    for (int k = 0; k < n; ++k) {
-        int p = k;
-        double best = fabs(A[k * n + k]);
-        for (int i = k + 1; i < n; ++i) {
-            double a = fabs(A[i * n + k]);
-            if (a > best) { best = a; p = i; }
+// Gaussian elimination with partial pivoting on a register-resident N x N
+// system (all indices compile-time: no scratch).  The pivot search keeps the
+// first largest entry, as LAPACK does.  A singular system yields a = 0.
+template <int N>
+__device__ __forceinline__ void solve_fixed(double (&A)[N][N], double (&b)[N]) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) {
+            const bool sw = fabs(A[i][k]) > fabs(A[k][k]);
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const double t = A[k][j];
+                A[k][j] = sw ? A[i][j] : t;
+                A[i][j] = sw ? t : A[i][j];
+            }
+            const double t = b[k];
+            b[k] = sw ? b[i] : t;
+            b[i] = sw ? t : b[i];
         }
-        if (best == 0.0) return false;
-        if (p != k) {
-            for (int j = 0; j < n; ++j) { double t = A[k * n + j]; A[k * n + j] = A[p * n + j]; A[p * n + j] = t; }
-            double t = b[k]; b[k] = b[p]; b[p] = t;
-        }
-        for (int i = k + 1; i < n; ++i) {
-            double f = A[i * n + k] / A[k * n + k];
-            for (int j = k; j < n; ++j) A[i * n + j] -= f * A[k * n + j];
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) {
+            const double f = A[k][k] != 0.0 ? A[i][k] / A[k][k] : 0.0;
+#pragma unroll
+            for (int j = k; j < N; ++j) A[i][j] -= f * A[k][j];
             b[i] -= f * b[k];
         }
     }
-    for (int k = n - 1; k >= 0; --k) {
-        double s = b[k];
-        for (int j = k + 1; j < n; ++j) s -= A[k * n + j] * b[j];
-        b[k] = s / A[k * n + k];
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+        double acc = b[k];
+#pragma unroll
+        for (int j = k + 1; j < N; ++j) acc -= A[k][j] * b[j];
+        b[k] = A[k][k] != 0.0 ? acc / A[k][k] : 0.0;
     }
-    return true;
 }
 
 __device__ __forceinline__ double viscosity(double T, const Phys& ph) {
@@ -124,7 +114,7 @@ __device__ __forceinline__ Eq<C> make_eq(double rho, double u, double v, double 
     Eq<C> e;
     const double RT = ph.R * T;
     const double D = ph.D;
-    e.rn = (C)(rho / pow(2.0 * M_PI * RT, 0.5 * D));
+    e.rn = (C)(ph.D == 2 ? rho / (2.0 * M_PI * RT) : rho / sqrt(2.0 * M_PI * RT));
     e.ux = (C)u; e.uy = (C)v;
     e.i2RT = (C)(1.0 / (2.0 * RT));
     e.iRT = (C)(1.0 / RT);
@@ -167,11 +157,11 @@ __device__ __forceinline__ void eq_eval(const Eq<C>& e, C x, C y, C& g, C& h) {
 // the uncorrected target over the level, solve, return a[4] (a[2] = 0 in 1-D).
 template <typename S>
 __device__ void compat_solve(const LevelDesc& L, const Eq<S>& eu, double rho, double u, double v, double T,
-                             const Phys& ph, double* red, double* a_out) {
+                             const Phys& ph, double* a_out) {
     double s[13];
 #pragma unroll
     for (int k = 0; k < 13; ++k) s[k] = 0.0;
-    for (int i = threadIdx.x; i < L.N; i += BS) {
+    for (int i = lane_id(); i < L.N; i += WL) {
         const double x = L.xi_x[i], y = L.xi_y[i], w = L.w[i];
         S g, h;
         eq_eval<S>(eu, (S)x, (S)y, g, h);
@@ -181,29 +171,27 @@ __device__ void compat_solve(const LevelDesc& L, const Eq<S>& eu, double rho, do
         s[5] += wg * y * y; s[6] += wg * x * x2; s[7] += wg * y * x2; s[8] += wg * x2 * x2;
         s[9] += wh; s[10] += wh * x; s[11] += wh * y; s[12] += wh * x2;
     }
-    block_sum<13>(s, red);
+    wave_sum<13>(s);
     const double E0 = 0.5 * (3.0 - ph.D + ph.K) * ph.R * T;
     const double sx2 = s[3] + s[5];
-    double A4[16] = {
-        s[0], s[1], s[2], E0 * s[0] + 0.5 * sx2,
-        s[1], s[3], s[4], E0 * s[1] + 0.5 * s[6],
-        s[2], s[4], s[5], E0 * s[2] + 0.5 * s[7],
-        0.5 * (sx2 + s[9]), 0.5 * (s[6] + s[10]), 0.5 * (s[7] + s[11]),
-        E0 * 0.5 * (sx2 + s[9]) + 0.5 * (0.5 * s[8] + 0.5 * s[12])};
     const double rhoE = 0.5 * rho * (u * u + v * v) + 0.5 * (3.0 + ph.K) * rho * ph.R * T;
-    double b4[4] = {rho - s[0], rho * u - s[1], rho * v - s[2], rhoE - 0.5 * (sx2 + s[9])};
     if (ph.D == 2) {
-        if (!solve_small(4, A4, b4)) { b4[0] = b4[1] = b4[2] = b4[3] = 0.0; }
-        for (int k = 0; k < 4; ++k) a_out[k] = b4[k];
+        double A[4][4] = {{s[0], s[1], s[2], E0 * s[0] + 0.5 * sx2},
+                          {s[1], s[3], s[4], E0 * s[1] + 0.5 * s[6]},
+                          {s[2], s[4], s[5], E0 * s[2] + 0.5 * s[7]},
+                          {0.5 * (sx2 + s[9]), 0.5 * (s[6] + s[10]), 0.5 * (s[7] + s[11]),
+                           E0 * 0.5 * (sx2 + s[9]) + 0.5 * (0.5 * s[8] + 0.5 * s[12])}};
+        double b[4] = {rho - s[0], rho * u - s[1], rho * v - s[2], rhoE - 0.5 * (sx2 + s[9])};
+        solve_fixed<4>(A, b);
+        a_out[0] = b[0]; a_out[1] = b[1]; a_out[2] = b[2]; a_out[3] = b[3];
     } else {
-        const int id[3] = {0, 1, 3};
-        double A3[9], b3[3];
-        for (int r = 0; r < 3; ++r) {
-            b3[r] = b4[id[r]];
-            for (int c = 0; c < 3; ++c) A3[r * 3 + c] = A4[id[r] * 4 + id[c]];
-        }
-        if (!solve_small(3, A3, b3)) { b3[0] = b3[1] = b3[2] = 0.0; }
-        a_out[0] = b3[0]; a_out[1] = b3[1]; a_out[2] = 0.0; a_out[3] = b3[2];
+        double A[3][3] = {{s[0], s[1], E0 * s[0] + 0.5 * sx2},
+                          {s[1], s[3], E0 * s[1] + 0.5 * s[6]},
+                          {0.5 * (sx2 + s[9]), 0.5 * (s[6] + s[10]),
+                           E0 * 0.5 * (sx2 + s[9]) + 0.5 * (0.5 * s[8] + 0.5 * s[12])}};
+        double b[3] = {rho - s[0], rho * u - s[1], rhoE - 0.5 * (sx2 + s[9])};
+        solve_fixed<3>(A, b);
+        a_out[0] = b[0]; a_out[1] = b[1]; a_out[2] = 0.0; a_out[3] = b[2];
     }
 }
 
@@ -214,8 +202,7 @@ template <typename S>
 __global__ __launch_bounds__(BS) void k_cell_prep(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
                                                   const int* __restrict__ cell_slot, int n_cells, Phys ph,
                                                   double* __restrict__ params) {
-    __shared__ double red[MAXW * RED_MAX];
-    for (int c = blockIdx.x; c < n_cells; c += gridDim.x) {
+    for (int c = item0(); c < n_cells; c += istride()) {
         const LevelDesc& L = lvs[cell_lev[c]];
         const size_t row = (size_t)cell_slot[c] * L.stride;
         const S* g = rowp<S>(L.g, row);
@@ -225,7 +212,7 @@ __global__ __launch_bounds__(BS) void k_cell_prep(const LevelDesc* __restrict__ 
         double m[11];
 #pragma unroll
         for (int k = 0; k < 11; ++k) m[k] = 0.0;
-        for (int i = threadIdx.x; i < L.N; i += BS) {
+        for (int i = lane_id(); i < L.N; i += WL) {
             const double w = L.w[i], x = L.xi_x[i] - u0, y = L.xi_y[i] - v0;
             const double wg = w * (double)g[i], wh = w * (double)h[i];
             const double x2 = x * x + y * y;
@@ -233,7 +220,7 @@ __global__ __launch_bounds__(BS) void k_cell_prep(const LevelDesc* __restrict__ 
             m[5] += wg * y * y; m[6] += wg * x * x2; m[7] += wg * y * x2;
             m[8] += wh; m[9] += wh * x; m[10] += wh * y;
         }
-        block_sum<11>(m, red);
+        wave_sum<11>(m);
         double rho, u, v, T, qx, qy;
         raw_to_state(m, u0, v0, ph, rho, u, v, T, qx, qy);
         const double p = rho * ph.R * T;
@@ -244,7 +231,7 @@ __global__ __launch_bounds__(BS) void k_cell_prep(const LevelDesc* __restrict__ 
         double a[4] = {0.0, 0.0, 0.0, 0.0};
         if (ph.compat) {
             Eq<S> eu = make_eq<S>(rho, u, v, T, qx, qy, nullptr, ph);
-            compat_solve<S>(L, eu, rho, u, v, T, ph, red, a);
+            compat_solve<S>(L, eu, rho, u, v, T, ph, a);
         }
         const double alpha = (2.0 * tau - s) / (2.0 * tau + dt);
         const double beta = 3.0 * s / (2.0 * tau + dt);
@@ -252,18 +239,17 @@ __global__ __launch_bounds__(BS) void k_cell_prep(const LevelDesc* __restrict__ 
         S* fg = rowp<S>(L.fg, row);
         S* fh = rowp<S>(L.fh, row);
         const S al = (S)alpha, be = (S)beta;
-        for (int i = threadIdx.x; i < L.N; i += BS) {
+        for (int i = lane_id(); i < L.N; i += WL) {
             S gs, hs;
             eq_eval<S>(e, (S)L.xi_x[i], (S)L.xi_y[i], gs, hs);
             fg[i] = al * g[i] + be * gs;
             fh[i] = al * h[i] + be * hs;
         }
-        if (threadIdx.x == 0) {
+        if (lane_id() == 0) {
             pr[P_RHO] = rho; pr[P_U] = u; pr[P_V] = v; pr[P_T] = T; pr[P_QX] = qx; pr[P_QY] = qy;
             pr[P_TAU] = tau; pr[P_A0] = a[0]; pr[P_A1] = a[1]; pr[P_A2] = a[2]; pr[P_A3] = a[3];
             pr[P_ALPHA] = alpha; pr[P_BETA] = beta;
         }
-        __syncthreads();
     }
 }
 
@@ -272,31 +258,29 @@ template <typename S>
 __global__ __launch_bounds__(BS) void k_init_eq(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
                                                 const int* __restrict__ cell_slot, int n_cells,
                                                 const double* __restrict__ st, Phys ph, double* __restrict__ params) {
-    __shared__ double red[MAXW * RED_MAX];
-    for (int c = blockIdx.x; c < n_cells; c += gridDim.x) {
+    for (int c = item0(); c < n_cells; c += istride()) {
         const LevelDesc& L = lvs[cell_lev[c]];
         const double rho = st[4 * c], u = st[4 * c + 1], v = ph.D == 2 ? st[4 * c + 2] : 0.0, T = st[4 * c + 3];
         double a[4] = {0.0, 0.0, 0.0, 0.0};
         if (ph.compat) {
             Eq<S> eu = make_eq<S>(rho, u, v, T, 0.0, 0.0, nullptr, ph);
-            compat_solve<S>(L, eu, rho, u, v, T, ph, red, a);
+            compat_solve<S>(L, eu, rho, u, v, T, ph, a);
         }
         Eq<S> e = make_eq<S>(rho, u, v, T, 0.0, 0.0, ph.compat ? a : nullptr, ph);
         const size_t row = (size_t)cell_slot[c] * L.stride;
         S* g = rowp<S>(L.g, row);
         S* h = rowp<S>(L.h, row);
-        for (int i = threadIdx.x; i < L.N; i += BS) {
+        for (int i = lane_id(); i < L.N; i += WL) {
             S gs, hs;
             eq_eval<S>(e, (S)L.xi_x[i], (S)L.xi_y[i], gs, hs);
             g[i] = gs;
             h[i] = hs;
         }
-        if (threadIdx.x == 0) {
+        if (lane_id() == 0) {
             double* pr = params + (size_t)c * NPARAM;
             for (int k = 0; k < NPARAM; ++k) pr[k] = 0.0;
             pr[P_RHO] = rho; pr[P_U] = u; pr[P_V] = v; pr[P_T] = T;
         }
-        __syncthreads();
     }
 }
 
@@ -315,7 +299,7 @@ __device__ void map_correct_apply(const LevelDesc& D, S* gdst, S* hdst, const do
         a[r] = s;
     }
     const double kh = cK * ph.R * Ttar;
-    for (int i = threadIdx.x; i < D.N; i += BS) {
+    for (int i = lane_id(); i < D.N; i += WL) {
         const double x = D.xi_x[i], y = D.xi_y[i];
         const double dg = a[0] + a[1] * x + a[2] * y + a[3] * (x * x + y * y);
         const S gp = gdst[i];
@@ -332,9 +316,7 @@ __global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs,
                                               int n, const int* __restrict__ cell_lev,
                                               const int* __restrict__ cell_slot, const double* __restrict__ params,
                                               Phys ph, unsigned long long* neg) {
-    __shared__ double red[MAXW * RED_MAX];
-    __shared__ int shflag;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    for (int it = item0(); it < n; it += istride()) {
         const GhostItem G = items[it];
         const LevelDesc& Ls = lvs[cell_lev[G.n]];
         const LevelDesc& Ld = lvs[G.dst];
@@ -346,12 +328,12 @@ __global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs,
         double m[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) m[k] = 0.0;
-        for (int i = threadIdx.x; i < Ls.N; i += BS) {       // target: moments on the source level
+        for (int i = lane_id(); i < Ls.N; i += WL) {       // target: moments on the source level
             const double x = Ls.xi_x[i], y = Ls.xi_y[i], w = Ls.w[i];
             const double wg = w * (double)sg[i];
             m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += 0.5 * (wg * (x * x + y * y) + w * (double)sh[i]);
         }
-        for (int P = threadIdx.x; P < Ld.N; P += BS) {       // provisional projection
+        for (int P = lane_id(); P < Ld.N; P += WL) {       // provisional projection
             double gP = 0.0, HP = 0.0;
             for (int e = G.tab.off[P]; e < G.tab.off[P + 1]; ++e) {
                 const int a = G.tab.idx[e];
@@ -369,14 +351,14 @@ __global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs,
             const double wg = w * (double)gs;
             m[4] += wg; m[5] += wg * x; m[6] += wg * y; m[7] += 0.5 * (wg * (x * x + y * y) + w * (double)hs);
         }
-        block_sum<8>(m, red);
+        wave_sum<8>(m);
         int nf = 0;
         if (ph.map_moments) {
             const double dM[4] = {m[0] - m[4], m[1] - m[5], m[2] - m[6], m[3] - m[7]};
             map_correct_apply<S>(Ld, dg, dh, dM, params[(size_t)G.n * NPARAM + P_T], ph, nf, nullptr);
         }
-        nf = block_or(nf, &shflag);
-        if (threadIdx.x == 0 && nf) atomicAdd(neg, 1ull);
+        nf = __any(nf);
+        if (lane_id() == 0 && nf) atomicAdd(neg, 1ull);
     }
 }
 
@@ -392,14 +374,15 @@ __device__ __forceinline__ C van_leer(C a, C b) {
 template <typename S>
 struct Side {                       // one cell's reconstruction stencil
     const S* own[2];                // phi_bar+ row (g, h)
-    const S* nb[4][2];              // neighbour rows on the same level (nullptr: none)
-    double G[4], dist[4];
-    double dx, dy;                  // x_f - x_cell
+    const S* nb[4][2];              // neighbour rows on the cell's level (own row when absent)
+    S G[4], id[4];                  // [t_i; t_j]^-1 and 1/|x_n - x_c|
+    S dx, dy;                       // x_f - x_cell
 };
 
 template <typename S>
-__device__ __forceinline__ const S* nb_row(const LevelDesc& L, int code, const int* cell_slot, int comp) {
-    if (code == -1) return nullptr;
+__device__ __forceinline__ const S* nb_row(const LevelDesc& L, int code, const int* cell_slot, int comp,
+                                           const S* own) {
+    if (code == -1) return own;      // zero-gradient ghost: one-sided difference 0
     if (code >= 0) return rowp<S>(comp ? L.fh : L.fg, (size_t)cell_slot[code] * L.stride);
     return rowp<S>(comp ? L.Gh : L.Gg, (size_t)(-2 - code) * L.stride);
 }
@@ -410,37 +393,62 @@ __device__ __forceinline__ void load_side(Side<S>& sd, const LevelDesc& L, int c
     const size_t row = (size_t)cell_slot[cell] * L.stride;
     sd.own[0] = rowp<S>(L.fg, row);
     sd.own[1] = rowp<S>(L.fh, row);
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int code = cell_nbr[4 * cell + k];
-        sd.nb[k][0] = nb_row<S>(L, code, cell_slot, 0);
-        sd.nb[k][1] = nb_row<S>(L, code, cell_slot, 1);
+        sd.nb[k][0] = nb_row<S>(L, code, cell_slot, 0, sd.own[0]);
+        sd.nb[k][1] = nb_row<S>(L, code, cell_slot, 1, sd.own[1]);
     }
-    const CellGeom gm = geom[cell];
-    for (int k = 0; k < 4; ++k) { sd.G[k] = gm.G[k]; sd.dist[k] = gm.dist[k]; }
-    sd.dx = dx; sd.dy = dy;
+    const CellGeom& gm = geom[cell];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { sd.G[k] = (S)gm.G[k]; sd.id[k] = (S)(1.0 / gm.dist[k]); }
+    sd.dx = (S)dx; sd.dy = (S)dy;
 }
 
-// phi_bar+ of the side's cell extrapolated to the face at velocity index i:
-// phi_bar+ + (x_f - x_c - xi s) . sigma, sigma from limited one-sided slopes.
+// Per-lane choice between two stencils (branch-free upwind selection).
 template <typename S>
-__device__ __forceinline__ void side_ext(const Side<S>& sd, int i, S x, S y, S s, S& eg, S& eh) {
+__device__ __forceinline__ void select_side(Side<S>& o, const Side<S>& a, const Side<S>& b, bool useA) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        o.own[c] = useA ? a.own[c] : b.own[c];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o.nb[k][c] = useA ? a.nb[k][c] : b.nb[k][c];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { o.G[k] = useA ? a.G[k] : b.G[k]; o.id[k] = useA ? a.id[k] : b.id[k]; }
+    o.dx = useA ? a.dx : b.dx;
+    o.dy = useA ? a.dy : b.dy;
+}
+
+// Limited gradient of phi_bar+ at velocity index i: per index direction a van
+// Leer limited pair of one-sided slopes, mapped through [t_i; t_j]^-1.
+template <typename S>
+__device__ __forceinline__ void side_slope(const Side<S>& sd, int i, S (&f)[2], S (&sx)[2], S (&sy)[2]) {
 #pragma unroll
     for (int comp = 0; comp < 2; ++comp) {
-        const S f = sd.own[comp][i];
+        const S fv = sd.own[comp][i];
         S sl[2];
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
-            const S* lo = sd.nb[2 * d][comp];
-            const S* hi = sd.nb[2 * d + 1][comp];
-            const S a = lo ? (f - lo[i]) / (S)sd.dist[2 * d] : S(0);
-            const S b = hi ? (hi[i] - f) / (S)sd.dist[2 * d + 1] : S(0);
+            const S a = (fv - sd.nb[2 * d][comp][i]) * sd.id[2 * d];
+            const S b = (sd.nb[2 * d + 1][comp][i] - fv) * sd.id[2 * d + 1];
             sl[d] = van_leer<S>(a, b);
         }
-        const S sx = (S)sd.G[0] * sl[0] + (S)sd.G[1] * sl[1];
-        const S sy = (S)sd.G[2] * sl[0] + (S)sd.G[3] * sl[1];
-        const S e = f + ((S)sd.dx - x * s) * sx + ((S)sd.dy - y * s) * sy;
-        if (comp == 0) eg = e; else eh = e;
+        f[comp] = fv;
+        sx[comp] = sd.G[0] * sl[0] + sd.G[1] * sl[1];
+        sy[comp] = sd.G[2] * sl[0] + sd.G[3] * sl[1];
     }
+}
+
+// phi_bar+ of the side's cell extrapolated to the face at velocity index i:
+// phi_bar+ + (x_f - x_c - xi s) . sigma.
+template <typename S>
+__device__ __forceinline__ void side_ext(const Side<S>& sd, int i, S x, S y, S s, S& eg, S& eh) {
+    S f[2], sx[2], sy[2];
+    side_slope<S>(sd, i, f, sx, sy);
+    const S ax = sd.dx - x * s, ay = sd.dy - y * s;
+    eg = f[0] + ax * sx[0] + ay * sy[0];
+    eh = f[1] + ax * sx[1] + ay * sy[1];
 }
 
 template <typename S>
@@ -455,7 +463,7 @@ __device__ __forceinline__ void acc_raw(double* m, double w, double x, double y,
 // Face state from the reduced raw moments of phi_bar_f (Eq. W_from_bar) and the
 // compatibility coefficients of the face target; returns the recovery weights.
 template <typename S>
-__device__ void face_target(const LevelDesc& L, double* m, double u0, double v0, const Phys& ph, double* red,
+__device__ void face_target(const LevelDesc& L, double* m, double u0, double v0, const Phys& ph,
                             bool compat, Eq<S>& e, double& c1, double& c2, double* Tout = nullptr) {
     double rho, u, v, T, qx, qy;
     raw_to_state(m, u0, v0, ph, rho, u, v, T, qx, qy);
@@ -466,7 +474,7 @@ __device__ void face_target(const LevelDesc& L, double* m, double u0, double v0,
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     if (compat) {
         Eq<S> eu = make_eq<S>(rho, u, v, T, qx, qy, nullptr, ph);
-        compat_solve<S>(L, eu, rho, u, v, T, ph, red, a);
+        compat_solve<S>(L, eu, rho, u, v, T, ph, a);
     }
     e = make_eq<S>(rho, u, v, T, qx, qy, compat ? a : nullptr, ph);
     c1 = 2.0 * tau / (2.0 * tau + s);
@@ -479,9 +487,8 @@ __global__ __launch_bounds__(BS) void k_face(const LevelDesc* __restrict__ lvs, 
                                              int n, const int* __restrict__ cell_slot,
                                              const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
                                              const double* __restrict__ params, Phys ph) {
-    __shared__ double red[MAXW * RED_MAX];
     const S s = (S)(0.5 * ph.dt);
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    for (int it = item0(); it < n; it += istride()) {
         const FaceItem F = items[it];
         const LevelDesc& L = lvs[F.lev];
         Side<S> sL, sR;
@@ -494,32 +501,30 @@ __global__ __launch_bounds__(BS) void k_face(const LevelDesc* __restrict__ lvs, 
         double m[11];
 #pragma unroll
         for (int k = 0; k < 11; ++k) m[k] = 0.0;
-        for (int i = threadIdx.x; i < L.N; i += BS) {
+        for (int i = lane_id(); i < L.N; i += WL) {
             const double xd = L.xi_x[i], yd = L.xi_y[i];
             const S x = (S)xd, y = (S)yd;
             const double dn = xd * F.nx + yd * F.ny;
             S eg, eh;
-            if (dn > 0) {
-                side_ext<S>(sL, i, x, y, s, eg, eh);
-            } else if (dn < 0) {
-                side_ext<S>(sR, i, x, y, s, eg, eh);
-            } else {
-                S ag, ah, bg, bh;
-                side_ext<S>(sL, i, x, y, s, ag, ah);
+            Side<S> sd;
+            select_side<S>(sd, sL, sR, dn >= 0);
+            side_ext<S>(sd, i, x, y, s, eg, eh);
+            if (dn == 0) {                          // both sides, averaged
+                S bg, bh;
                 side_ext<S>(sR, i, x, y, s, bg, bh);
-                eg = S(0.5) * (ag + bg);
-                eh = S(0.5) * (ah + bh);
+                eg = S(0.5) * (eg + bg);
+                eh = S(0.5) * (eh + bh);
             }
             rg[i] = eg;
             rh[i] = eh;
             acc_raw<S>(m, L.w[i], xd - u0, yd - v0, eg, eh);
         }
-        block_sum<11>(m, red);
+        wave_sum<11>(m);
         Eq<S> e;
         double c1, c2;
-        face_target<S>(L, m, u0, v0, ph, red, ph.compat && ph.face_compat, e, c1, c2);
+        face_target<S>(L, m, u0, v0, ph, ph.compat && ph.face_compat, e, c1, c2);
         const S a1 = (S)c1, a2 = (S)c2, ar = (S)F.area;
-        for (int i = threadIdx.x; i < L.N; i += BS) {
+        for (int i = lane_id(); i < L.N; i += WL) {
             const double xd = L.xi_x[i], yd = L.xi_y[i];
             const S x = (S)xd, y = (S)yd;
             S gs, hs;
@@ -528,7 +533,6 @@ __global__ __launch_bounds__(BS) void k_face(const LevelDesc* __restrict__ lvs, 
             rg[i] = ar * dn * (a1 * rg[i] + a2 * gs);
             rh[i] = ar * dn * (a1 * rh[i] + a2 * hs);
         }
-        __syncthreads();
     }
 }
 
@@ -540,9 +544,8 @@ __global__ __launch_bounds__(BS) void k_bface(const LevelDesc* __restrict__ lvs,
                                               int n, const int* __restrict__ cell_slot,
                                               const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
                                               const BCDev* __restrict__ bcs, Phys ph, const int* __restrict__ cell_lev) {
-    __shared__ double red[MAXW * RED_MAX];
     const S s = (S)(0.5 * ph.dt);
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    for (int it = item0(); it < n; it += istride()) {
         const BFaceItem F = items[it];
         const LevelDesc& L = lvs[F.lev];
         const BCDev bc = bcs[F.bc];
@@ -555,7 +558,7 @@ __global__ __launch_bounds__(BS) void k_bface(const LevelDesc* __restrict__ lvs,
         if (bc.kind == 1) {
             e = make_eq<S>(1.0, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
             double m[2] = {0.0, 0.0};
-            for (int i = threadIdx.x; i < L.N; i += BS) {
+            for (int i = lane_id(); i < L.N; i += WL) {
                 const double xd = L.xi_x[i], yd = L.xi_y[i], w = L.w[i];
                 const double dn = xd * F.nx + yd * F.ny;
                 if (dn > 0) {
@@ -568,13 +571,13 @@ __global__ __launch_bounds__(BS) void k_bface(const LevelDesc* __restrict__ lvs,
                     m[1] += w * dn * (double)gs;
                 }
             }
-            block_sum<2>(m, red);
+            wave_sum<2>(m);
             rho_w = (S)(-m[0] / m[1]);
         } else if (bc.kind == 2) {
             e = make_eq<S>(bc.rho, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
         }
         const S ar = (S)F.area;
-        for (int i = threadIdx.x; i < L.N; i += BS) {
+        for (int i = lane_id(); i < L.N; i += WL) {
             const double xd = L.xi_x[i], yd = L.xi_y[i];
             const S x = (S)xd, y = (S)yd;
             const double dnd = xd * F.nx + yd * F.ny;
@@ -592,7 +595,6 @@ __global__ __launch_bounds__(BS) void k_bface(const LevelDesc* __restrict__ lvs,
             rg[i] = ar * dn * gf;
             rh[i] = ar * dn * hf;
         }
-        __syncthreads();
     }
     (void)cell_lev;
 }
@@ -605,7 +607,7 @@ __global__ __launch_bounds__(BS) void k_update(const LevelDesc* __restrict__ lvs
                                                const int* __restrict__ cell_slot, int n_cells,
                                                const CellGeom* __restrict__ geom, const int* __restrict__ cell_frow,
                                                Phys ph) {
-    for (int c = blockIdx.x; c < n_cells; c += gridDim.x) {
+    for (int c = item0(); c < n_cells; c += istride()) {
         const LevelDesc& L = lvs[cell_lev[c]];
         const size_t row = (size_t)cell_slot[c] * L.stride;
         S* g = rowp<S>(L.g, row);
@@ -627,7 +629,7 @@ __global__ __launch_bounds__(BS) void k_update(const LevelDesc* __restrict__ lvs
         }
         const S k = (S)(ph.dt / geom[c].vol);
         const S c43 = (S)(4.0 / 3.0), c13 = (S)(1.0 / 3.0);
-        for (int i = threadIdx.x; i < L.N; i += BS) {
+        for (int i = lane_id(); i < L.N; i += WL) {
             S ag = S(0), ah = S(0);
             for (int j = 0; j < nf; ++j) {
                 ag += sg[j] * Fg[j][i];
@@ -647,8 +649,7 @@ __global__ __launch_bounds__(BS) void k_cell_moments(const LevelDesc* __restrict
                                                      const int* __restrict__ cell_slot, int n_cells,
                                                      const CellGeom* __restrict__ geom, Phys ph,
                                                      double* __restrict__ out6, double* __restrict__ tot4) {
-    __shared__ double red[MAXW * RED_MAX];
-    for (int c = blockIdx.x; c < n_cells; c += gridDim.x) {
+    for (int c = item0(); c < n_cells; c += istride()) {
         const LevelDesc& L = lvs[cell_lev[c]];
         const size_t row = (size_t)cell_slot[c] * L.stride;
         const S* g = rowp<S>(L.g, row);
@@ -656,9 +657,9 @@ __global__ __launch_bounds__(BS) void k_cell_moments(const LevelDesc* __restrict
         double m[11];
 #pragma unroll
         for (int k = 0; k < 11; ++k) m[k] = 0.0;
-        for (int i = threadIdx.x; i < L.N; i += BS) acc_raw<S>(m, L.w[i], L.xi_x[i], L.xi_y[i], g[i], h[i]);
-        block_sum<11>(m, red);
-        if (threadIdx.x == 0) {
+        for (int i = lane_id(); i < L.N; i += WL) acc_raw<S>(m, L.w[i], L.xi_x[i], L.xi_y[i], g[i], h[i]);
+        wave_sum<11>(m);
+        if (lane_id() == 0) {
             double rho, u, v, T, qx, qy;
             raw_to_state(m, 0.0, 0.0, ph, rho, u, v, T, qx, qy);
             const double tau = viscosity(T, ph) / (rho * ph.R * T);
@@ -673,19 +674,17 @@ __global__ __launch_bounds__(BS) void k_cell_moments(const LevelDesc* __restrict
                 o[0] = V * m[0]; o[1] = V * m[1]; o[2] = V * m[2]; o[3] = V * 0.5 * (m[3] + m[5] + m[8]);
             }
         }
-        __syncthreads();
     }
 }
 
 // Fixed-order sum of n rows of `width` doubles (one workgroup).
-__global__ __launch_bounds__(BS) void k_sum_rows(const double* __restrict__ in, int n, int width,
-                                                 double* __restrict__ out) {
-    __shared__ double red[MAXW * RED_MAX];
+// Fixed-order sum of n rows of `width` (<= 4) doubles by one wavefront.
+__global__ void k_sum_rows(const double* __restrict__ in, int n, int width, double* __restrict__ out) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int r = threadIdx.x; r < n; r += BS)
+    for (int r = lane_id(); r < n; r += WL)
         for (int k = 0; k < width; ++k) v[k] += in[(size_t)r * width + k];
-    block_sum<4>(v, red);
-    if (threadIdx.x == 0)
+    wave_sum<4>(v);
+    if (lane_id() == 0)
         for (int k = 0; k < width; ++k) out[k] = v[k];
 }
 
@@ -697,9 +696,7 @@ template <typename S>
 __global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv, const LevelDesc* __restrict__ nlv,
                                               const RemapItem* __restrict__ items, int n, Phys ph,
                                               unsigned long long* neg) {
-    __shared__ double red[MAXW * RED_MAX];
-    __shared__ int shflag;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    for (int it = item0(); it < n; it += istride()) {
         const RemapItem R = items[it];
         const LevelDesc& Ls = olv[R.src_lev];
         const LevelDesc& Ld = nlv[R.dst_lev];
@@ -708,18 +705,18 @@ __global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv,
         S* dg = rowp<S>(Ld.g, (size_t)R.dst_slot * Ld.stride);
         S* dh = rowp<S>(Ld.h, (size_t)R.dst_slot * Ld.stride);
         if (R.tab.off == nullptr) {
-            for (int i = threadIdx.x; i < Ld.N; i += BS) { dg[i] = sg[i]; dh[i] = sh[i]; }
+            for (int i = lane_id(); i < Ld.N; i += WL) { dg[i] = sg[i]; dh[i] = sh[i]; }
             continue;
         }
         double m[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) m[k] = 0.0;
-        for (int i = threadIdx.x; i < Ls.N; i += BS) {
+        for (int i = lane_id(); i < Ls.N; i += WL) {
             const double x = Ls.xi_x[i], y = Ls.xi_y[i], w = Ls.w[i];
             const double wg = w * (double)sg[i];
             m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += 0.5 * (wg * (x * x + y * y) + w * (double)sh[i]);
         }
-        for (int P = threadIdx.x; P < Ld.N; P += BS) {
+        for (int P = lane_id(); P < Ld.N; P += WL) {
             double gP = 0.0, HP = 0.0;
             for (int e = R.tab.off[P]; e < R.tab.off[P + 1]; ++e) {
                 const int a = R.tab.idx[e];
@@ -736,7 +733,7 @@ __global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv,
             const double wg = w * (double)gs;
             m[4] += wg; m[5] += wg * x; m[6] += wg * y; m[7] += 0.5 * (wg * (x * x + y * y) + w * (double)hs);
         }
-        block_sum<8>(m, red);
+        wave_sum<8>(m);
         int nf = 0;
         if (ph.map_moments) {
             const double rho = m[0], u = m[1] / rho, v = m[2] / rho;
@@ -744,15 +741,18 @@ __global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv,
             const double dM[4] = {m[0] - m[4], m[1] - m[5], m[2] - m[6], m[3] - m[7]};
             map_correct_apply<S>(Ld, dg, dh, dM, T, ph, nf, nullptr);
         }
-        nf = block_or(nf, &shflag);
-        if (threadIdx.x == 0 && nf) atomicAdd(neg, 1ull);
+        nf = __any(nf);
+        if (lane_id() == 0 && nf) atomicAdd(neg, 1ull);
     }
 }
 
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
-static inline int grid_for(int n) { return n < 1 ? 1 : (n > 1048576 ? 1048576 : n); }
+static inline int grid_for(int n) {
+    const int b = (n + MAXW - 1) / MAXW;
+    return b < 1 ? 1 : (b > 1048576 ? 1048576 : b);
+}
 
 #define MLVS_DISPATCH(prec, KERNEL, ...)                                                        \
     do {                                                                                        \
@@ -820,7 +820,7 @@ hipError_t launch_cell_moments(int prec, hipStream_t st, const LevelDesc* lv, co
 }
 
 hipError_t launch_sum_rows(hipStream_t st, const double* in, int n, int width, double* out) {
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(BS), 0, st, in, n, width, out);
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(WL), 0, st, in, n, width, out);
     return hipGetLastError();
 }
 
@@ -839,25 +839,6 @@ hipError_t launch_remap(int prec, hipStream_t st, const LevelDesc* old_lv, const
 // microflux (Eq. interface_reduced_fluxes) coarsened to each native level and
 // corrected to the common target F_int (Eq. native_flux_moment_matching).
 // ---------------------------------------------------------------------------
-template <typename S>
-__device__ __forceinline__ void side_slope(const Side<S>& sd, int i, S (&f)[2], S (&sx)[2], S (&sy)[2]) {
-#pragma unroll
-    for (int comp = 0; comp < 2; ++comp) {
-        const S fv = sd.own[comp][i];
-        S sl[2];
-#pragma unroll
-        for (int d = 0; d < 2; ++d) {
-            const S* lo = sd.nb[2 * d][comp];
-            const S* hi = sd.nb[2 * d + 1][comp];
-            const S a = lo ? (fv - lo[i]) / (S)sd.dist[2 * d] : S(0);
-            const S b = hi ? (hi[i] - fv) / (S)sd.dist[2 * d + 1] : S(0);
-            sl[d] = van_leer<S>(a, b);
-        }
-        f[comp] = fv;
-        sx[comp] = (S)sd.G[0] * sl[0] + (S)sd.G[1] * sl[1];
-        sy[comp] = (S)sd.G[2] * sl[0] + (S)sd.G[3] * sl[1];
-    }
-}
 
 // phi_bar+ and slope of one side at interface point P (parent a on the native level).
 template <typename S>
@@ -876,11 +857,9 @@ __global__ __launch_bounds__(BS) void k_xface(const LevelDesc* __restrict__ lvs,
                                               int n, const int* __restrict__ cell_slot,
                                               const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
                                               const double* __restrict__ params, Phys ph, unsigned long long* neg) {
-    __shared__ double red[MAXW * RED_MAX];
-    __shared__ int shflag;
     const S s = (S)(0.5 * ph.dt);
     const double cK = 3.0 - ph.D + ph.K;
-    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    for (int it = item0(); it < n; it += istride()) {
         const XFaceItem F = items[it];
         const LevelDesc& LA = lvs[F.levA];
         const LevelDesc& LB = lvs[F.levB];
@@ -893,7 +872,7 @@ __global__ __launch_bounds__(BS) void k_xface(const LevelDesc* __restrict__ lvs,
         double m[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) m[k] = 0.0;
-        for (int P = threadIdx.x; P < LI.N; P += BS) {
+        for (int P = lane_id(); P < LI.N; P += WL) {
             const double x = LI.xi_x[P], y = LI.xi_y[P], w = LI.w[P];
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
@@ -913,7 +892,7 @@ __global__ __launch_bounds__(BS) void k_xface(const LevelDesc* __restrict__ lvs,
                 mm[7] += 0.5 * w * ((xa * xa + ya * ya) * ga + ha);
             }
         }
-        block_sum<16>(m, red);
+        wave_sum<16>(m);
         double aL[4] = {0, 0, 0, 0}, aR[4] = {0, 0, 0, 0};
         if (ph.map_moments) {
             for (int side = 0; side < 2; ++side) {
@@ -939,7 +918,7 @@ __global__ __launch_bounds__(BS) void k_xface(const LevelDesc* __restrict__ lvs,
 #pragma unroll
         for (int k = 0; k < 11; ++k) fm[k] = 0.0;
         int nf = 0;
-        for (int P = threadIdx.x; P < LI.N; P += BS) {
+        for (int P = lane_id(); P < LI.N; P += WL) {
             const double xd = LI.xi_x[P], yd = LI.xi_y[P];
             const S x = (S)xd, y = (S)yd;
             S e[2][2];
@@ -969,15 +948,15 @@ __global__ __launch_bounds__(BS) void k_xface(const LevelDesc* __restrict__ lvs,
             rh[P] = eh;
             acc_raw<S>(fm, LI.w[P], xd - u0, yd - v0, eg, eh);
         }
-        block_sum<11>(fm, red);
+        wave_sum<11>(fm);
         Eq<S> eq;
         double c1, c2;
         double Tf = 1.0;
-        face_target<S>(LI, fm, u0, v0, ph, red, ph.compat && ph.face_compat, eq, c1, c2, &Tf);
+        face_target<S>(LI, fm, u0, v0, ph, ph.compat && ph.face_compat, eq, c1, c2, &Tf);
         // pass 3: interface microflux per unit area and its moments F_int
         double Fm[4] = {0, 0, 0, 0};
         const S k1 = (S)c1, k2 = (S)c2;
-        for (int P = threadIdx.x; P < LI.N; P += BS) {
+        for (int P = lane_id(); P < LI.N; P += WL) {
             const double xd = LI.xi_x[P], yd = LI.xi_y[P], w = LI.w[P];
             S gs, hs;
             eq_eval<S>(eq, (S)xd, (S)yd, gs, hs);
@@ -990,7 +969,8 @@ __global__ __launch_bounds__(BS) void k_xface(const LevelDesc* __restrict__ lvs,
             Fm[0] += wg; Fm[1] += wg * xd; Fm[2] += wg * yd;
             Fm[3] += 0.5 * (wg * (xd * xd + yd * yd) + w * (double)fh);
         }
-        block_sum<4>(Fm, red);
+        wave_sum<4>(Fm);
+        __threadfence_block();   // pass 4 reads interface rows written by other lanes
         // pass 4: coarsen to both native levels (provisional) and their moments
         double pm[8];
 #pragma unroll
@@ -1001,7 +981,7 @@ __global__ __launch_bounds__(BS) void k_xface(const LevelDesc* __restrict__ lvs,
             const PairTable& tb = side ? F.BfromI : F.AfromI;
             S* og = rowp<S>(Ln.Fg, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
             S* oh = rowp<S>(Ln.Fh, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
-            for (int a = threadIdx.x; a < Ln.N; a += BS) {
+            for (int a = lane_id(); a < Ln.N; a += WL) {
                 double gA = 0.0, HA = 0.0;
                 for (int e = tb.off[a]; e < tb.off[a + 1]; ++e) {
                     const int P = tb.idx[e];
@@ -1020,7 +1000,7 @@ __global__ __launch_bounds__(BS) void k_xface(const LevelDesc* __restrict__ lvs,
                 mm[0] += wg; mm[1] += wg * x; mm[2] += wg * y; mm[3] += 0.5 * (wg * (x * x + y * y) + w * (double)hs);
             }
         }
-        block_sum<8>(pm, red);
+        wave_sum<8>(pm);
         // pass 5: four-moment flux correction to F_int (T_tar = face T), times area
         const S ar = (S)F.area;
 #pragma unroll
@@ -1040,16 +1020,15 @@ __global__ __launch_bounds__(BS) void k_xface(const LevelDesc* __restrict__ lvs,
                 }
             }
             const double kh = cK * ph.R * Tf;
-            for (int a = threadIdx.x; a < Ln.N; a += BS) {
+            for (int a = lane_id(); a < Ln.N; a += WL) {
                 const double x = Ln.xi_x[a], y = Ln.xi_y[a];
                 const double dg = aa[0] + aa[1] * x + aa[2] * y + aa[3] * (x * x + y * y);
                 og[a] = ar * (S)((double)og[a] + dg);
                 oh[a] = ar * (S)((double)oh[a] + kh * dg);
             }
         }
-        nf = block_or(nf, &shflag);
-        if (threadIdx.x == 0 && nf) atomicAdd(neg, 1ull);
-        __syncthreads();
+        nf = __any(nf);
+        if (lane_id() == 0 && nf) atomicAdd(neg, 1ull);
     }
 }
 
@@ -1137,11 +1116,9 @@ __global__ __launch_bounds__(BS) void k_criterion(const LevelDesc* __restrict__ 
                                                   int nx, int ny, double C_split, double C_merge, double eps_merge,
                                                   int flux_test, uint8_t* __restrict__ kout,
                                                   unsigned long long* __restrict__ hout) {
-    __shared__ double red[MAXW * RED_MAX];
-    __shared__ unsigned long long hred[MAXW];
     const int nbx = nx / 2, nby = ny / 2, Nb = nbx * nby, Nbase = nx * ny;
     const int n8x = nbx / 4, n8y = nby / 4, n4x = nbx / 2, n4y = nby / 2;
-    for (int c = blockIdx.x; c < n_cells; c += gridDim.x) {
+    for (int c = item0(); c < n_cells; c += istride()) {
         const int lev = cell_lev[c];
         const LevelDesc& L = lvs[lev];
         const size_t row = (size_t)cell_slot[c] * L.stride;
@@ -1155,7 +1132,7 @@ __global__ __launch_bounds__(BS) void k_criterion(const LevelDesc* __restrict__ 
         double t[10];
 #pragma unroll
         for (int k = 0; k < 10; ++k) t[k] = 0.0;
-        for (int b = threadIdx.x; b < Nbase; b += BS) {
+        for (int b = lane_id(); b < Nbase; b += WL) {
             const int p = cc.ptb[b];
             const double gp = (double)g[p];
             const double xp = L.xi_x[p], yp = L.xi_y[p];
@@ -1169,7 +1146,7 @@ __global__ __launch_bounds__(BS) void k_criterion(const LevelDesc* __restrict__ 
                 t[6 + r] += w * fabs(y) * mr[r];
             }
         }
-        block_sum<10>(t, red);
+        wave_sum<10>(t);
         cc.rho_tot = t[0];
         cc.E_tot = t[1];
         for (int r = 0; r < 4; ++r) cc.S[r] = fmax(t[2 + r], t[6 + r]);
@@ -1179,7 +1156,7 @@ __global__ __launch_bounds__(BS) void k_criterion(const LevelDesc* __restrict__ 
         const int n4rest = n4x * n4y - (2 * n8x) * (2 * n8y);
         const int n2rest = nbx * nby - (2 * n4x) * (2 * n4y);
         const int ntop = n8 + n4rest + n2rest;
-        for (int tb = threadIdx.x; tb < ntop; tb += BS) {
+        for (int tb = lane_id(); tb < ntop; tb += WL) {
             int s0, X0, Y0;
             if (tb < n8) { s0 = 3; X0 = tb % n8x; Y0 = tb / n8x; }
             else if (tb < n8 + n4rest) {
@@ -1218,35 +1195,28 @@ __global__ __launch_bounds__(BS) void k_criterion(const LevelDesc* __restrict__ 
                 }
             }
         }
-        __syncthreads();
+        __threadfence_block();
         unsigned long long hs = 0ull;
-        for (int b = threadIdx.x; b < Nb; b += BS) hs += mix64(((unsigned long long)b << 2) | ko[b]);
-        for (int off = 32; off > 0; off >>= 1) hs += __shfl_xor(hs, off, 64);
-        if ((threadIdx.x & 63) == 0) hred[threadIdx.x >> 6] = hs;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long tot = 0ull;
-            for (int w = 0; w < MAXW; ++w) tot += hred[w];
-            hout[c] = tot;
-        }
-        __syncthreads();
+        for (int b = lane_id(); b < Nb; b += WL) hs += mix64(((unsigned long long)b << 2) | ko[b]);
+        for (int off = 32; off > 0; off >>= 1) hs += __shfl_xor(hs, off, WL);
+        if (lane_id() == 0) hout[c] = hs;
     }
 }
 
 __global__ void k_gather_rows_u8(const uint8_t* __restrict__ src, int width, const int* __restrict__ rows, int n,
                                  uint8_t* __restrict__ dst) {
-    for (int r = blockIdx.x; r < n; r += gridDim.x)
-        for (int k = threadIdx.x; k < width; k += blockDim.x) dst[(size_t)r * width + k] = src[(size_t)rows[r] * width + k];
+    for (int r = item0(); r < n; r += istride())
+        for (int k = lane_id(); k < width; k += WL) dst[(size_t)r * width + k] = src[(size_t)rows[r] * width + k];
 }
 
 __global__ void k_compare_rows_u8(const uint8_t* __restrict__ all, int width, const int* __restrict__ rep_of_cell,
                                   const uint8_t* __restrict__ reps, int n, unsigned long long* mismatch) {
-    for (int c = blockIdx.x; c < n; c += gridDim.x) {
+    for (int c = item0(); c < n; c += istride()) {
         int bad = 0;
         const uint8_t* a = all + (size_t)c * width;
         const uint8_t* r = reps + (size_t)rep_of_cell[c] * width;
-        for (int k = threadIdx.x; k < width; k += blockDim.x) bad |= (a[k] != r[k]);
-        if (bad) atomicAdd(mismatch, 1ull);
+        for (int k = lane_id(); k < width; k += WL) bad |= (a[k] != r[k]);
+        if (__any(bad) && lane_id() == 0) atomicAdd(mismatch, 1ull);
     }
 }
 
