@@ -215,7 +215,7 @@ struct Level {
     int stride = 0;
     int n_cells = 0, n_rows = 0, n_ghost = 0;
     void *g = nullptr, *h = nullptr, *fg = nullptr, *fh = nullptr;
-    void *Fg = nullptr, *Fh = nullptr, *Gg = nullptr, *Gh = nullptr;
+    void *Fg = nullptr, *Fh = nullptr;
     size_t rows_alloc = 0, ghost_alloc = 0;
 };
 
@@ -575,19 +575,17 @@ void upload_level_geometry(mlvs_ctx c, Level& L) {
 
 void free_level(mlvs_ctx c, Level& L) {
     for (void* p : {(void*)L.d_x, (void*)L.d_y, (void*)L.d_w, (void*)L.d_pt_of_base, L.g, L.h, L.fg, L.fh, L.Fg,
-                    L.Fh, L.Gg, L.Gh})
+                    L.Fh})
         c->dm.release(p);
     L.d_x = L.d_y = L.d_w = nullptr;
     L.d_pt_of_base = nullptr;
-    L.g = L.h = L.fg = L.fh = L.Fg = L.Fh = L.Gg = L.Gh = nullptr;
+    L.g = L.h = L.fg = L.fh = L.Fg = L.Fh = nullptr;
 }
 
 void alloc_state(mlvs_ctx c, Level& L) {
     const size_t n = (size_t)std::max(L.n_cells, 1) * L.stride * c->elt();
     L.g = c->dm.alloc(n);
     L.h = c->dm.alloc(n);
-    L.fg = c->dm.alloc(n);
-    L.fh = c->dm.alloc(n);
 }
 
 DevTable upload_table(mlvs_ctx c, const HostTable& t) {
@@ -753,11 +751,11 @@ void build_items(mlvs_ctx c) {
         Level& L = *c->levels[l];
         L.n_rows = rows[l];
         L.n_ghost = ghosts[l];
-        c->dm.release(L.Fg); c->dm.release(L.Fh); c->dm.release(L.Gg); c->dm.release(L.Gh);
+        c->dm.release(L.Fg); c->dm.release(L.Fh); c->dm.release(L.fg); c->dm.release(L.fh);
         const size_t nr = (size_t)std::max(L.n_rows, 1) * L.stride * c->elt();
-        const size_t ng = (size_t)std::max(L.n_ghost, 1) * L.stride * c->elt();
+        const size_t nf = (size_t)std::max(L.n_cells + L.n_ghost, 1) * L.stride * c->elt();
         L.Fg = c->dm.alloc(nr); L.Fh = c->dm.alloc(nr);
-        L.Gg = c->dm.alloc(ng); L.Gh = c->dm.alloc(ng);
+        L.fg = c->dm.alloc(nf); L.fh = c->dm.alloc(nf);
     }
     for (auto& Lp : c->ifaces) {
         Level& L = *Lp;
@@ -771,7 +769,7 @@ void build_items(mlvs_ctx c) {
         LevelDesc d{};
         d.N = L.N; d.stride = L.stride; d.n_rows_state = L.n_cells;
         d.xi_x = L.d_x; d.xi_y = L.d_y; d.w = L.d_w;
-        d.g = L.g; d.h = L.h; d.fg = L.fg; d.fh = L.fh; d.Fg = L.Fg; d.Fh = L.Fh; d.Gg = L.Gg; d.Gh = L.Gh;
+        d.g = L.g; d.h = L.h; d.fg = L.fg; d.fh = L.fh; d.Fg = L.Fg; d.Fh = L.Fh;
         std::copy(L.Minv, L.Minv + 16, d.Minv);
         descs.push_back(d);
     }

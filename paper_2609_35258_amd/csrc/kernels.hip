@@ -21,7 +21,11 @@ constexpr int MAXW = BS / WL;       // waves (items) per workgroup
 constexpr int RED_MAX = 32;         // largest reduction width
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WL - 1); }
-__device__ __forceinline__ int item0() { return blockIdx.x * MAXW + (threadIdx.x >> 6); }
+// The wave index is uniform within a wavefront; readfirstlane tells the
+// compiler so, and every per-item quantity then lives in scalar registers.
+__device__ __forceinline__ int item0() {
+    return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * MAXW + (threadIdx.x >> 6)));
+}
 __device__ __forceinline__ int istride() { return gridDim.x * MAXW; }
 
 // Sum NV doubles over the wavefront; every lane receives the totals.
@@ -83,7 +87,7 @@ __device__ __forceinline__ double viscosity(double T, const Phys& ph) {
 // Macroscopic state from eleven raw moments taken about the shift (u0, v0):
 // m = [sum w g, .. x, .. y, .. xx, .. xy, .. yy, .. x|x|^2, .. y|x|^2, sum w h, .. x, .. y]
 // (x, y the shifted velocity).  Returns rho, u, v, T and qt = 1/2 sum w c (c^2 g + h).
-__device__ void raw_to_state(const double* m, double u0, double v0, const Phys& ph, double& rho,
+__device__ __forceinline__ void raw_to_state(const double* m, double u0, double v0, const Phys& ph, double& rho,
                              double& u, double& v, double& T, double& qx, double& qy) {
     rho = m[0];
     const double up = m[1] / rho, vp = m[2] / rho;
@@ -156,7 +160,7 @@ __device__ __forceinline__ void eq_eval(const Eq<C>& e, C x, C y, C& g, C& h) {
 // Compatibility correction (Sec. 3.3.1): assemble A and the moment defect of
 // the uncorrected target over the level, solve, return a[4] (a[2] = 0 in 1-D).
 template <typename S>
-__device__ void compat_solve(const LevelDesc& L, const Eq<S>& eu, double rho, double u, double v, double T,
+__device__ __forceinline__ void compat_solve(const LevelDesc& L, const Eq<S>& eu, double rho, double u, double v, double T,
                              const Phys& ph, double* a_out) {
     double s[13];
 #pragma unroll
@@ -199,7 +203,7 @@ __device__ void compat_solve(const LevelDesc& L, const Eq<S>& eu, double rho, do
 // cell stage: W, q, tau, compatibility coefficients, phi_bar+ rows
 // ---------------------------------------------------------------------------
 template <typename S>
-__global__ __launch_bounds__(BS) void k_cell_prep(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
+__global__ __launch_bounds__(BS, 4) void k_cell_prep(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
                                                   const int* __restrict__ cell_slot, int n_cells, Phys ph,
                                                   double* __restrict__ params) {
     for (int c = item0(); c < n_cells; c += istride()) {
@@ -288,7 +292,7 @@ __global__ __launch_bounds__(BS) void k_init_eq(const LevelDesc* __restrict__ lv
 // neighbours on other levels: projection + four-moment mapping correction
 // ---------------------------------------------------------------------------
 template <typename S>
-__device__ void map_correct_apply(const LevelDesc& D, S* gdst, S* hdst, const double* dM, double Ttar,
+__device__ __forceinline__ void map_correct_apply(const LevelDesc& D, S* gdst, S* hdst, const double* dM, double Ttar,
                                   const Phys& ph, int& negflag, const S* gprov_check) {
     const double cK = 3.0 - ph.D + ph.K;
     double rhs[4] = {dM[0], dM[1], dM[2], dM[3] - 0.5 * cK * ph.R * Ttar * dM[0]};
@@ -323,8 +327,8 @@ __global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs,
         const size_t srow = (size_t)cell_slot[G.n] * Ls.stride;
         const S* sg = rowp<S>(Ls.fg, srow);
         const S* sh = rowp<S>(Ls.fh, srow);
-        S* dg = rowp<S>(Ld.Gg, (size_t)G.row * Ld.stride);
-        S* dh = rowp<S>(Ld.Gh, (size_t)G.row * Ld.stride);
+        S* dg = rowp<S>(Ld.fg, (size_t)(Ld.n_rows_state + G.row) * Ld.stride);
+        S* dh = rowp<S>(Ld.fh, (size_t)(Ld.n_rows_state + G.row) * Ld.stride);
         double m[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) m[k] = 0.0;
@@ -372,48 +376,43 @@ __device__ __forceinline__ C van_leer(C a, C b) {
 }
 
 template <typename S>
-struct Side {                       // one cell's reconstruction stencil
-    const S* own[2];                // phi_bar+ row (g, h)
-    const S* nb[4][2];              // neighbour rows on the cell's level (own row when absent)
+struct Side {                       // one cell's reconstruction stencil on its level
+    const S* base[2];               // the level's phi_bar+ buffers (g, h)
+    size_t off[5];                  // element offsets of the rows: own, W, E, S, N
     S G[4], id[4];                  // [t_i; t_j]^-1 and 1/|x_n - x_c|
     S dx, dy;                       // x_f - x_cell
 };
 
-template <typename S>
-__device__ __forceinline__ const S* nb_row(const LevelDesc& L, int code, const int* cell_slot, int comp,
-                                           const S* own) {
-    if (code == -1) return own;      // zero-gradient ghost: one-sided difference 0
-    if (code >= 0) return rowp<S>(comp ? L.fh : L.fg, (size_t)cell_slot[code] * L.stride);
-    return rowp<S>(comp ? L.Gh : L.Gg, (size_t)(-2 - code) * L.stride);
+// Row of a neighbour code: same-level cell, ghost row after the level's cells,
+// or the cell's own row when there is no neighbour (zero one-sided difference).
+__device__ __forceinline__ size_t nb_off(const LevelDesc& L, int code, const int* cell_slot, size_t own) {
+    if (code == -1) return own;
+    if (code >= 0) return (size_t)cell_slot[code] * L.stride;
+    return (size_t)(L.n_rows_state + (-2 - code)) * L.stride;
 }
 
 template <typename S>
 __device__ __forceinline__ void load_side(Side<S>& sd, const LevelDesc& L, int cell, const int* cell_slot,
                                           const int* cell_nbr, const CellGeom* geom, double dx, double dy) {
-    const size_t row = (size_t)cell_slot[cell] * L.stride;
-    sd.own[0] = rowp<S>(L.fg, row);
-    sd.own[1] = rowp<S>(L.fh, row);
+    sd.base[0] = reinterpret_cast<const S*>(L.fg);
+    sd.base[1] = reinterpret_cast<const S*>(L.fh);
+    const size_t own = (size_t)cell_slot[cell] * L.stride;
+    sd.off[0] = own;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int code = cell_nbr[4 * cell + k];
-        sd.nb[k][0] = nb_row<S>(L, code, cell_slot, 0, sd.own[0]);
-        sd.nb[k][1] = nb_row<S>(L, code, cell_slot, 1, sd.own[1]);
-    }
+    for (int k = 0; k < 4; ++k) sd.off[k + 1] = nb_off(L, cell_nbr[4 * cell + k], cell_slot, own);
     const CellGeom& gm = geom[cell];
 #pragma unroll
     for (int k = 0; k < 4; ++k) { sd.G[k] = (S)gm.G[k]; sd.id[k] = (S)(1.0 / gm.dist[k]); }
     sd.dx = (S)dx; sd.dy = (S)dy;
 }
 
-// Per-lane choice between two stencils (branch-free upwind selection).
+// Per-lane choice between two stencils of the same level (branch-free upwind selection).
 template <typename S>
 __device__ __forceinline__ void select_side(Side<S>& o, const Side<S>& a, const Side<S>& b, bool useA) {
+    o.base[0] = a.base[0];
+    o.base[1] = a.base[1];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        o.own[c] = useA ? a.own[c] : b.own[c];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) o.nb[k][c] = useA ? a.nb[k][c] : b.nb[k][c];
-    }
+    for (int k = 0; k < 5; ++k) o.off[k] = useA ? a.off[k] : b.off[k];
 #pragma unroll
     for (int k = 0; k < 4; ++k) { o.G[k] = useA ? a.G[k] : b.G[k]; o.id[k] = useA ? a.id[k] : b.id[k]; }
     o.dx = useA ? a.dx : b.dx;
@@ -426,12 +425,13 @@ template <typename S>
 __device__ __forceinline__ void side_slope(const Side<S>& sd, int i, S (&f)[2], S (&sx)[2], S (&sy)[2]) {
 #pragma unroll
     for (int comp = 0; comp < 2; ++comp) {
-        const S fv = sd.own[comp][i];
+        const S* B = sd.base[comp] + i;
+        const S fv = B[sd.off[0]];
         S sl[2];
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
-            const S a = (fv - sd.nb[2 * d][comp][i]) * sd.id[2 * d];
-            const S b = (sd.nb[2 * d + 1][comp][i] - fv) * sd.id[2 * d + 1];
+            const S a = (fv - B[sd.off[1 + 2 * d]]) * sd.id[2 * d];
+            const S b = (B[sd.off[2 + 2 * d]] - fv) * sd.id[2 * d + 1];
             sl[d] = van_leer<S>(a, b);
         }
         f[comp] = fv;
@@ -463,7 +463,7 @@ __device__ __forceinline__ void acc_raw(double* m, double w, double x, double y,
 // Face state from the reduced raw moments of phi_bar_f (Eq. W_from_bar) and the
 // compatibility coefficients of the face target; returns the recovery weights.
 template <typename S>
-__device__ void face_target(const LevelDesc& L, double* m, double u0, double v0, const Phys& ph,
+__device__ __forceinline__ void face_target(const LevelDesc& L, double* m, double u0, double v0, const Phys& ph,
                             bool compat, Eq<S>& e, double& c1, double& c2, double* Tout = nullptr) {
     double rho, u, v, T, qx, qy;
     raw_to_state(m, u0, v0, ph, rho, u, v, T, qx, qy);
@@ -483,7 +483,7 @@ __device__ void face_target(const LevelDesc& L, double* m, double u0, double v0,
 }
 
 template <typename S>
-__global__ __launch_bounds__(BS) void k_face(const LevelDesc* __restrict__ lvs, const FaceItem* __restrict__ items,
+__global__ __launch_bounds__(BS, 4) void k_face(const LevelDesc* __restrict__ lvs, const FaceItem* __restrict__ items,
                                              int n, const int* __restrict__ cell_slot,
                                              const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
                                              const double* __restrict__ params, Phys ph) {
@@ -586,8 +586,8 @@ __global__ __launch_bounds__(BS) void k_bface(const LevelDesc* __restrict__ lvs,
             if (dnd > 0) {
                 side_ext<S>(sd, i, x, y, s, gf, hf);
             } else if (bc.kind == 3) {
-                gf = sd.own[0][i];
-                hf = sd.own[1][i];
+                gf = sd.base[0][sd.off[0] + i];
+                hf = sd.base[1][sd.off[0] + i];
             } else {
                 eq_eval<S>(e, x, y, gf, hf);
                 if (bc.kind == 1) { gf *= rho_w; hf *= rho_w; }
@@ -853,7 +853,7 @@ __device__ __forceinline__ void side_refined(const Side<S>& sd, const LevelDesc&
 }
 
 template <typename S>
-__global__ __launch_bounds__(BS) void k_xface(const LevelDesc* __restrict__ lvs, const XFaceItem* __restrict__ items,
+__global__ __launch_bounds__(BS, 4) void k_xface(const LevelDesc* __restrict__ lvs, const XFaceItem* __restrict__ items,
                                               int n, const int* __restrict__ cell_slot,
                                               const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
                                               const double* __restrict__ params, Phys ph, unsigned long long* neg) {
@@ -1053,7 +1053,7 @@ struct CritCtx {
 };
 
 template <typename S>
-__device__ bool crit_merges(const CritCtx& cc, const LevelDesc& L, const S* g, const S* h, int s, int bx, int by) {
+__device__ __forceinline__ bool crit_merges(const CritCtx& cc, const LevelDesc& L, const S* g, const S* h, int s, int bx, int by) {
     const int size = 1 << s;
     double m1 = 0.0, m2 = 0.0;
     double Wb = 0.0, Wx = 0.0, Wy = 0.0, Wg = 0.0, WH = 0.0;
@@ -1108,7 +1108,7 @@ __device__ bool crit_merges(const CritCtx& cc, const LevelDesc& L, const S* g, c
 }
 
 template <typename S>
-__global__ __launch_bounds__(BS) void k_criterion(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
+__global__ __launch_bounds__(BS, 4) void k_criterion(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
                                                   const int* __restrict__ cell_slot, int n_cells,
                                                   const int* __restrict__ ptb_all, const int* __restrict__ ptb_off,
                                                   const uint8_t* __restrict__ kappa_all, const double* __restrict__ bx,

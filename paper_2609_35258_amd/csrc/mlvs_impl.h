@@ -30,9 +30,9 @@ struct LevelDesc {
     const double* xi_y;
     const double* w;
     void* g;   void* h;     // state g~, h~           [cells][stride]
-    void* fg;  void* fh;    // phi_bar+ of the step    [cells][stride]
+    void* fg;  void* fh;    // phi_bar+ of the step: [cells][stride] followed by the ghost
+                            // rows (neighbours on other levels mapped onto this level)
     void* Fg;  void* Fh;    // face rows (flux)        [rows][stride]
-    void* Gg;  void* Gh;    // ghost rows (neighbours of other levels mapped here)
     double Minv[16];        // inverse of the state-independent 4x4 mapping matrix
 };
 
