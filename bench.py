@@ -53,7 +53,7 @@ def run_gpu(p, steps, warmup, precision, adapt):
 def stage_profile(s, reps=20):
     """Mean ms per launch of each stage (HIP events on the context stream)."""
     out = {}
-    for st in ("cell", "ghost", "face", "bface", "xface"):
+    for st in ("cell", "ghost", "face_rec", "face_flux", "xface"):
         items, pts = s.stage_size(st)
         if items == 0:
             continue
@@ -62,12 +62,12 @@ def stage_profile(s, reps=20):
 
 
 # algorithmic bytes per velocity point of each stage (FP64 values, 8 B; FP32, 4 B):
-#   cell:  read g~,h~ + write phi_bar+ g,h                   -> 4 values
-#   face:  read phi_bar+ g,h of the upwind cell + write F g,h -> 4 values
-#   bface: same as face                                        -> 4 values
-#   xface: per V_int point, read both sides' phi_bar+ (2x2) + write one native flux row (2) -> 6 values
-#   ghost: read source phi_bar+ + write mapped row            -> 4 values
-ALG_VALUES = {"cell": 4, "face": 4, "bface": 4, "xface": 6, "ghost": 4}
+#   cell:      read g~,h~ + write phi_bar+ g,h                         -> 4 values
+#   face_rec:  read phi_bar+ g,h of the upwind cell + write phi_bar_f  -> 4 values
+#   face_flux: read phi_bar_f g,h + write F g,h                        -> 4 values
+#   xface:     per V_int point, read both sides' phi_bar+ (2x2) + write one native row (2) -> 6 values
+#   ghost:     read source phi_bar+ + write mapped row                 -> 4 values
+ALG_VALUES = {"cell": 4, "face_rec": 4, "face_flux": 4, "xface": 6, "ghost": 4}
 
 
 def cpu_baseline(p, sample_steps=2, sample_cells=256):

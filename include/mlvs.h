@@ -204,8 +204,9 @@ mlvs_status mlvs_counters(mlvs_ctx ctx, int64_t* steps, double* cell_updates, do
 /* Profiling: launch one stage of the step `reps` times on the context stream,
  * bracketed by two HIP events recorded on that stream, and return the mean
  * duration per launch in milliseconds.  stage: 0 cell, 1 neighbour mapping,
- * 2 same-level faces, 3 boundary faces, 4 cross-level faces, 5 update
- * (advances g~, h~ once per repetition), 6 criterion.  Synchronises. */
+ * 2 face reconstruction (same-level and boundary faces), 3 face flux (same
+ * faces), 4 cross-level faces, 5 update (advances g~, h~ once per
+ * repetition), 6 criterion.  Synchronises. */
 mlvs_status mlvs_time_stage(mlvs_ctx ctx, int stage, int reps, double* ms_per_launch);
 
 /* Item counts of a stage's launch (cells, ghost rows, faces, ...) and the

@@ -482,121 +482,163 @@ __device__ __forceinline__ void face_target(const LevelDesc& L, double* m, doubl
     if (Tout) *Tout = T;
 }
 
+// Face stage, part 1 (reconstruction): for every same-level interior face and
+// every boundary face, the interface value phi_bar_f = phi_bar+_up + (x_f -
+// x_up - xi s) . sigma_up (Eqs. bar_phi_transport, reconstruction; both sides
+// averaged where xi . n = 0) is written to the face row.  Interior faces also
+// reduce the eleven raw moments of phi_bar_f (about the mean of the two cell
+// velocities); wall faces reduce the outgoing mass flux.  Per-face results go
+// to fmom[item][12].
 template <typename S>
-__global__ __launch_bounds__(BS, 4) void k_face(const LevelDesc* __restrict__ lvs, const FaceItem* __restrict__ items,
-                                             int n, const int* __restrict__ cell_slot,
-                                             const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
-                                             const double* __restrict__ params, Phys ph) {
+__global__ __launch_bounds__(BS, 4) void k_face_rec(const LevelDesc* __restrict__ lvs,
+                                                    const FaceItem* __restrict__ items, int n,
+                                                    const int* __restrict__ cell_slot,
+                                                    const int* __restrict__ cell_nbr,
+                                                    const CellGeom* __restrict__ geom,
+                                                    const double* __restrict__ params, Phys ph,
+                                                    double* __restrict__ fmom) {
     const S s = (S)(0.5 * ph.dt);
     for (int it = item0(); it < n; it += istride()) {
         const FaceItem F = items[it];
         const LevelDesc& L = lvs[F.lev];
-        Side<S> sL, sR;
-        load_side<S>(sL, L, F.L, cell_slot, cell_nbr, geom, F.dLx, F.dLy);
-        load_side<S>(sR, L, F.R, cell_slot, cell_nbr, geom, F.dRx, F.dRy);
-        const double u0 = 0.5 * (params[(size_t)F.L * NPARAM + P_U] + params[(size_t)F.R * NPARAM + P_U]);
-        const double v0 = 0.5 * (params[(size_t)F.L * NPARAM + P_V] + params[(size_t)F.R * NPARAM + P_V]);
         S* rg = rowp<S>(L.Fg, (size_t)F.row * L.stride);
         S* rh = rowp<S>(L.Fh, (size_t)F.row * L.stride);
-        double m[11];
+        Side<S> sL;
+        load_side<S>(sL, L, F.L, cell_slot, cell_nbr, geom, F.dLx, F.dLy);
+        double* out = fmom + (size_t)it * 12;
+        if (F.R >= 0) {
+            Side<S> sR;
+            load_side<S>(sR, L, F.R, cell_slot, cell_nbr, geom, F.dRx, F.dRy);
+            const double u0 = 0.5 * (params[(size_t)F.L * NPARAM + P_U] + params[(size_t)F.R * NPARAM + P_U]);
+            const double v0 = 0.5 * (params[(size_t)F.L * NPARAM + P_V] + params[(size_t)F.R * NPARAM + P_V]);
+            double m[11];
 #pragma unroll
-        for (int k = 0; k < 11; ++k) m[k] = 0.0;
-        for (int i = lane_id(); i < L.N; i += WL) {
-            const double xd = L.xi_x[i], yd = L.xi_y[i];
-            const S x = (S)xd, y = (S)yd;
-            const double dn = xd * F.nx + yd * F.ny;
-            S eg, eh;
-            Side<S> sd;
-            select_side<S>(sd, sL, sR, dn >= 0);
-            side_ext<S>(sd, i, x, y, s, eg, eh);
-            if (dn == 0) {                          // both sides, averaged
-                S bg, bh;
-                side_ext<S>(sR, i, x, y, s, bg, bh);
-                eg = S(0.5) * (eg + bg);
-                eh = S(0.5) * (eh + bh);
+            for (int k = 0; k < 11; ++k) m[k] = 0.0;
+            for (int i = lane_id(); i < L.N; i += WL) {
+                const double xd = L.xi_x[i], yd = L.xi_y[i];
+                const S x = (S)xd, y = (S)yd;
+                const double dn = xd * F.nx + yd * F.ny;
+                S eg, eh;
+                Side<S> sd;
+                select_side<S>(sd, sL, sR, dn >= 0);
+                side_ext<S>(sd, i, x, y, s, eg, eh);
+                if (dn == 0) {                          // both sides, averaged
+                    S bg, bh;
+                    side_ext<S>(sR, i, x, y, s, bg, bh);
+                    eg = S(0.5) * (eg + bg);
+                    eh = S(0.5) * (eh + bh);
+                }
+                rg[i] = eg;
+                rh[i] = eh;
+                acc_raw<S>(m, L.w[i], xd - u0, yd - v0, eg, eh);
             }
-            rg[i] = eg;
-            rh[i] = eh;
-            acc_raw<S>(m, L.w[i], xd - u0, yd - v0, eg, eh);
-        }
-        wave_sum<11>(m);
-        Eq<S> e;
-        double c1, c2;
-        face_target<S>(L, m, u0, v0, ph, ph.compat && ph.face_compat, e, c1, c2);
-        const S a1 = (S)c1, a2 = (S)c2, ar = (S)F.area;
-        for (int i = lane_id(); i < L.N; i += WL) {
-            const double xd = L.xi_x[i], yd = L.xi_y[i];
-            const S x = (S)xd, y = (S)yd;
-            S gs, hs;
-            eq_eval<S>(e, x, y, gs, hs);
-            const S dn = (S)(xd * F.nx + yd * F.ny);
-            rg[i] = ar * dn * (a1 * rg[i] + a2 * gs);
-            rh[i] = ar * dn * (a1 * rh[i] + a2 * hs);
+            wave_sum<11>(m);
+            if (lane_id() < 11) {
+#pragma unroll
+                for (int k = 0; k < 11; ++k)
+                    if (lane_id() == k) out[k] = m[k];
+            }
+        } else {
+            double m[1] = {0.0};
+            for (int i = lane_id(); i < L.N; i += WL) {
+                const double xd = L.xi_x[i], yd = L.xi_y[i], w = L.w[i];
+                const double dn = xd * F.nx + yd * F.ny;
+                S eg, eh;
+                side_ext<S>(sL, i, (S)xd, (S)yd, s, eg, eh);
+                rg[i] = eg;
+                rh[i] = eh;
+                if (dn > 0) m[0] += w * dn * (double)eg;
+            }
+            wave_sum<1>(m);
+            if (lane_id() == 0) out[0] = m[0];
         }
     }
 }
 
-// ---------------------------------------------------------------------------
-// boundary faces (Sec. 4 workloads): outgoing from the interior reconstruction
-// ---------------------------------------------------------------------------
+// Face stage, part 2 (flux).  Interior faces: face state from the reduced
+// moments (Eq. W_from_bar, q_f = 2 tau_f q_bar / (2 tau_f + s Pr)), the
+// corrected face target, phi_f (Eq. recover_phi) and F = A_f (xi . n) phi_f.
+// Boundary faces (outward normal): outgoing velocities carry the interior
+// reconstruction, incoming ones the boundary state -- diffuse wall rho_w
+// g_eq(u_w, T_w) with rho_w from zero net mass flux, far-field Maxwellian, or
+// the cell's phi_bar+ (zero-gradient outflow).
 template <typename S>
-__global__ __launch_bounds__(BS) void k_bface(const LevelDesc* __restrict__ lvs, const BFaceItem* __restrict__ items,
-                                              int n, const int* __restrict__ cell_slot,
-                                              const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
-                                              const BCDev* __restrict__ bcs, Phys ph, const int* __restrict__ cell_lev) {
-    const S s = (S)(0.5 * ph.dt);
+__global__ __launch_bounds__(BS, 4) void k_face_flux(const LevelDesc* __restrict__ lvs,
+                                                     const FaceItem* __restrict__ items, int n,
+                                                     const int* __restrict__ cell_slot,
+                                                     const double* __restrict__ params,
+                                                     const BCDev* __restrict__ bcs, Phys ph,
+                                                     const double* __restrict__ fmom) {
     for (int it = item0(); it < n; it += istride()) {
-        const BFaceItem F = items[it];
+        const FaceItem F = items[it];
         const LevelDesc& L = lvs[F.lev];
-        const BCDev bc = bcs[F.bc];
-        Side<S> sd;
-        load_side<S>(sd, L, F.c, cell_slot, cell_nbr, geom, F.dx, F.dy);
         S* rg = rowp<S>(L.Fg, (size_t)F.row * L.stride);
         S* rh = rowp<S>(L.Fh, (size_t)F.row * L.stride);
-        Eq<S> e;
-        S rho_w = S(1);
-        if (bc.kind == 1) {
-            e = make_eq<S>(1.0, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
-            double m[2] = {0.0, 0.0};
-            for (int i = lane_id(); i < L.N; i += WL) {
-                const double xd = L.xi_x[i], yd = L.xi_y[i], w = L.w[i];
-                const double dn = xd * F.nx + yd * F.ny;
-                if (dn > 0) {
-                    S eg, eh;
-                    side_ext<S>(sd, i, (S)xd, (S)yd, s, eg, eh);
-                    m[0] += w * dn * (double)eg;
-                } else if (dn < 0) {
-                    S gs, hs;
-                    eq_eval<S>(e, (S)xd, (S)yd, gs, hs);
-                    m[1] += w * dn * (double)gs;
-                }
-            }
-            wave_sum<2>(m);
-            rho_w = (S)(-m[0] / m[1]);
-        } else if (bc.kind == 2) {
-            e = make_eq<S>(bc.rho, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
-        }
+        const double* mm = fmom + (size_t)it * 12;
         const S ar = (S)F.area;
-        for (int i = lane_id(); i < L.N; i += WL) {
-            const double xd = L.xi_x[i], yd = L.xi_y[i];
-            const S x = (S)xd, y = (S)yd;
-            const double dnd = xd * F.nx + yd * F.ny;
-            const S dn = (S)dnd;
-            S gf, hf;
-            if (dnd > 0) {
-                side_ext<S>(sd, i, x, y, s, gf, hf);
-            } else if (bc.kind == 3) {
-                gf = sd.base[0][sd.off[0] + i];
-                hf = sd.base[1][sd.off[0] + i];
-            } else {
-                eq_eval<S>(e, x, y, gf, hf);
-                if (bc.kind == 1) { gf *= rho_w; hf *= rho_w; }
+        if (F.R >= 0) {
+            double m[11];
+#pragma unroll
+            for (int k = 0; k < 11; ++k) m[k] = mm[k];
+            const double u0 = 0.5 * (params[(size_t)F.L * NPARAM + P_U] + params[(size_t)F.R * NPARAM + P_U]);
+            const double v0 = 0.5 * (params[(size_t)F.L * NPARAM + P_V] + params[(size_t)F.R * NPARAM + P_V]);
+            Eq<S> e;
+            double c1, c2;
+            face_target<S>(L, m, u0, v0, ph, ph.compat && ph.face_compat, e, c1, c2);
+            const S a1 = (S)c1, a2 = (S)c2;
+            for (int i = lane_id(); i < L.N; i += WL) {
+                const double xd = L.xi_x[i], yd = L.xi_y[i];
+                S gs, hs;
+                eq_eval<S>(e, (S)xd, (S)yd, gs, hs);
+                const S dn = (S)(xd * F.nx + yd * F.ny);
+                rg[i] = ar * dn * (a1 * rg[i] + a2 * gs);
+                rh[i] = ar * dn * (a1 * rh[i] + a2 * hs);
             }
-            rg[i] = ar * dn * gf;
-            rh[i] = ar * dn * hf;
+        } else {
+            const BCDev bc = bcs[-1 - F.R];
+            Eq<S> e;
+            S rho_w = S(1);
+            if (bc.kind == 1) {
+                e = make_eq<S>(1.0, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
+                double m[1] = {0.0};
+                for (int i = lane_id(); i < L.N; i += WL) {
+                    const double xd = L.xi_x[i], yd = L.xi_y[i], w = L.w[i];
+                    const double dn = xd * F.nx + yd * F.ny;
+                    if (dn < 0) {
+                        S gs, hs;
+                        eq_eval<S>(e, (S)xd, (S)yd, gs, hs);
+                        m[0] += w * dn * (double)gs;
+                    }
+                }
+                wave_sum<1>(m);
+                rho_w = (S)(-mm[0] / m[0]);
+            } else if (bc.kind == 2) {
+                e = make_eq<S>(bc.rho, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
+            }
+            const size_t own = (size_t)cell_slot[F.L] * L.stride;
+            const S* og = rowp<S>(L.fg, own);
+            const S* oh = rowp<S>(L.fh, own);
+            for (int i = lane_id(); i < L.N; i += WL) {
+                const double xd = L.xi_x[i], yd = L.xi_y[i];
+                const double dnd = xd * F.nx + yd * F.ny;
+                const S dn = (S)dnd;
+                S gf, hf;
+                if (dnd > 0) {
+                    gf = rg[i];
+                    hf = rh[i];
+                } else if (bc.kind == 3) {
+                    gf = og[i];
+                    hf = oh[i];
+                } else {
+                    eq_eval<S>(e, (S)xd, (S)yd, gf, hf);
+                    gf *= rho_w;
+                    hf *= rho_w;
+                }
+                rg[i] = ar * dn * gf;
+                rh[i] = ar * dn * hf;
+            }
         }
     }
-    (void)cell_lev;
 }
 
 // ---------------------------------------------------------------------------
@@ -785,20 +827,21 @@ hipError_t launch_ghost(int prec, hipStream_t st, const LevelDesc* lv, const Gho
     return hipGetLastError();
 }
 
-hipError_t launch_face(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
-                       const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
-                       Phys ph) {
+hipError_t launch_face_rec(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
+                           const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
+                           Phys ph, double* fmom) {
     if (n <= 0) return hipSuccess;
-    MLVS_DISPATCH(prec, k_face, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr, geom, params,
-                  ph);
+    MLVS_DISPATCH(prec, k_face_rec, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr, geom,
+                  params, ph, fmom);
     return hipGetLastError();
 }
 
-hipError_t launch_bface(int prec, hipStream_t st, const LevelDesc* lv, const BFaceItem* items, int n,
-                        const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const BCDev* bcs, Phys ph) {
+hipError_t launch_face_flux(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
+                            const int* cell_slot, const double* params, const BCDev* bcs, Phys ph,
+                            const double* fmom) {
     if (n <= 0) return hipSuccess;
-    MLVS_DISPATCH(prec, k_bface, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr, geom, bcs,
-                  ph, (const int*)nullptr);
+    MLVS_DISPATCH(prec, k_face_flux, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, params, bcs, ph,
+                  fmom);
     return hipGetLastError();
 }
 

@@ -50,14 +50,9 @@ struct CellGeom {
     double dist[4];    // |x_n - x_c| for W, E, S, N (1 when absent)
 };
 
-struct FaceItem {      // same-level interior face
-    int L, R, lev, row;
+struct FaceItem {      // same-level interior face (R >= 0) or boundary face (R = -1 - bc id)
+    int L, R, lev, row;  // boundary: L is the interior cell, normal points out of the domain
     double nx, ny, area, dLx, dLy, dRx, dRy;
-};
-
-struct BFaceItem {     // boundary face of one cell
-    int c, bc, lev, row;
-    double nx, ny, area, dx, dy;     // outward normal; x_f - x_c
 };
 
 struct BCDev {
@@ -94,12 +89,12 @@ hipError_t launch_cell_prep(int prec, hipStream_t st, const LevelDesc* lv, const
 hipError_t launch_ghost(int prec, hipStream_t st, const LevelDesc* lv, const GhostItem* items, int n,
                         const int* cell_lev, const int* cell_slot, const double* params, Phys ph,
                         unsigned long long* neg);
-hipError_t launch_face(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
-                       const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
-                       const double* params, Phys ph);
-hipError_t launch_bface(int prec, hipStream_t st, const LevelDesc* lv, const BFaceItem* items, int n,
-                        const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
-                        const BCDev* bcs, Phys ph);
+hipError_t launch_face_rec(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
+                           const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
+                           const double* params, Phys ph, double* fmom);
+hipError_t launch_face_flux(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
+                            const int* cell_slot, const double* params, const BCDev* bcs, Phys ph,
+                            const double* fmom);
 hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFaceItem* items, int n,
                         const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
                         const double* params, Phys ph, unsigned long long* neg);
