@@ -35,11 +35,14 @@ def workload(args):
     return W.cavity(args.n, Kn=0.075, nv=args.nv)
 
 
-def run_gpu(p, steps, warmup, precision, adapt):
+def run_gpu(p, steps, warmup, precision, adapt, graph=True, tune=True):
     import torch
     import paper_2609_35258_amd as m
-    s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=adapt)
+    from paper_2609_35258_amd import autotune
+    s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=adapt, graph=graph)
     s.step(warmup)
+    if tune:
+        s.tuned = autotune.autotune(s, precision)
     torch.cuda.synchronize()
     c0 = s.counters()
     t0 = time.perf_counter()
@@ -105,6 +108,8 @@ def main():
     ap.add_argument("--precision", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uvs", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -123,7 +128,8 @@ def main():
         sys.exit(2)
     import torch
     p = workload(args)
-    s, t_mlvs, upd, ipts = run_gpu(p, args.steps, args.warmup, args.precision, ADAPT)
+    s, t_mlvs, upd, ipts = run_gpu(p, args.steps, args.warmup, args.precision, ADAPT, not args.no_graph,
+                                   not args.no_tune)
     value = upd / t_mlvs
     npts, ncells, ncross = s.level_info()
     nbar = float(np.sum(npts * ncells) / np.sum(ncells))
@@ -149,11 +155,14 @@ def main():
                                   % (args.n, args.n, args.nv, args.nv),
                       "n_cells": p.n_cells, "base_points": args.nv * args.nv, "levels": len(npts),
                       "level_points": [int(x) for x in npts], "level_cells": [int(x) for x in ncells],
-                      "nbar": nbar, "n_cross": int(ncross), "iface_points_per_s": ipts / t_mlvs},
+                      "nbar": nbar, "n_cross": int(ncross), "iface_points_per_s": ipts / t_mlvs,
+                      "graph": not args.no_graph,
+                      "variants": {k: v["variant"] for k, v in getattr(s, "tuned", {}).items()}},
            "roofline": roof}
     s.close()
     if not args.no_uvs:
-        u, t_uvs, upd_u, _ = run_gpu(p, args.steps, args.warmup, args.precision, None)
+        u, t_uvs, upd_u, _ = run_gpu(p, args.steps, args.warmup, args.precision, None, not args.no_graph,
+                                     not args.no_tune)
         fields_u = u.moments()
         mem_u = u.memory()
         vol = np.ones(p.n_cells)

@@ -195,6 +195,19 @@ mlvs_status mlvs_set_state(mlvs_ctx ctx, const double* g, const double* h);
 /* Time step in use, mesh hmin, and counts: n_cells, N_b (2x2 blocks). */
 mlvs_status mlvs_info(mlvs_ctx ctx, double* dt, int64_t* n_cells, int32_t* n_blocks, int32_t* n_base);
 
+/* Launch variants of a stage (kernels instantiated for several minimum
+ * occupancies): *count variants exist for `stage` (numbering as in
+ * mlvs_time_stage); mlvs_set_variant selects one for subsequent launches.
+ * Used by the autotuner; results do not depend on the variant. */
+mlvs_status mlvs_variants(int stage, int* count);
+mlvs_status mlvs_set_variant(mlvs_ctx ctx, int stage, int variant);
+
+/* Replay each step as a HIP graph (on = 1): the launches of one step are
+ * captured once per level set (again after every adaptation or level
+ * change) and replayed with hipGraphLaunch.  Needs a non-default stream
+ * (MLVS_E_STATE otherwise).  Results are identical to direct launches. */
+mlvs_status mlvs_set_graph(mlvs_ctx ctx, int on);
+
 /* Work counters since creation: steps taken, cell-velocity updates on the
  * cells' own levels (sum over steps of sum over cells of the level size),
  * interface-space points processed on cross-level faces, adaptations. */

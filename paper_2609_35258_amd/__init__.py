@@ -95,6 +95,9 @@ _PROTOS = {
     "mlvs_memory": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
     "mlvs_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), _c_double_p, _c_double_p,
                                      ctypes.POINTER(ctypes.c_int64)]),
+    "mlvs_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "mlvs_variants": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "mlvs_set_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "mlvs_time_stage": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_double_p]),
     "mlvs_stage_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                                        _c_double_p]),
@@ -165,7 +168,7 @@ class Solver:
                  bc_imin, bc_imax, bc_jmin, bc_jmax, vx, vwx, vy, vwy, R: float, Pr: float, K: int,
                  omega: float, mu_ref: float, T_ref: float, cfl: float, dt: float = 0.0,
                  precision: int = 64, compat: int = 4, face_compat: bool = True, map_moments: int = 4,
-                 adapt: Optional[dict] = None, device=None):
+                 adapt: Optional[dict] = None, device=None, graph: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the MLVS library runs on the device only")
@@ -173,9 +176,14 @@ class Solver:
         self.torch = torch
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self._keep = {}
+        self.stream = torch.cuda.current_stream(self.device)
+        if graph and self.stream.cuda_stream == 0:
+            # graph capture needs a stream of its own (default priority)
+            self.stream = torch.cuda.Stream(self.device)
 
         def _alloc(n, user):
-            t = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+            with torch.cuda.stream(self.stream):
+                t = torch.empty(int(n), dtype=torch.uint8, device=self.device)
             p = t.data_ptr()
             self._keep[p] = t
             return p
@@ -185,7 +193,6 @@ class Solver:
 
         self._alloc_cb = _ALLOC(_alloc)
         self._free_cb = _FREE(_free)
-        self.stream = torch.cuda.current_stream(self.device)
         dev = mlvs_device(ctypes.c_void_p(self.stream.cuda_stream), self._alloc_cb, self._free_cb, None)
         node_x = np.ascontiguousarray(node_x, dtype=np.float64)
         node_y = np.ascontiguousarray(node_y, dtype=np.float64)
@@ -216,6 +223,8 @@ class Solver:
         _check(L.mlvs_create(ctypes.byref(phys), ctypes.byref(mesh), ctypes.byref(vg),
                              ctypes.byref(ap) if ap is not None else None, ctypes.byref(dev), ctypes.byref(h)))
         self.h = h
+        if graph:
+            _check(L.mlvs_set_graph(self.h, 1))
         self.n_cells = ni * nj
         self.dim = dim
         dt_ = ctypes.c_double()
@@ -229,7 +238,7 @@ class Solver:
 
     @classmethod
     def from_problem(cls, p, precision: int = 64, compat: int = 4, face_compat: bool = True,
-                     map_moments: int = 4, adapt: Optional[dict] = None, dt: float = 0.0):
+                     map_moments: int = 4, adapt: Optional[dict] = None, dt: float = 0.0, graph: bool = False):
         """Build from a problem description (attributes as in the workload generators)."""
         if p.vel_kind == "gh":
             x, w = gauss_hermite(p.nv, p.R, p.gh_scale_T)
@@ -244,7 +253,7 @@ class Solver:
                 bcs=p.bcs, bc_imin=p.bc_imin, bc_imax=p.bc_imax, bc_jmin=p.bc_jmin, bc_jmax=p.bc_jmax,
                 vx=x, vwx=w, vy=y, vwy=wy, R=p.R, Pr=p.Pr, K=p.K, omega=p.omega, mu_ref=mu, T_ref=p.T_ref,
                 cfl=p.cfl, dt=dt, precision=precision, compat=compat, face_compat=face_compat,
-                map_moments=map_moments, adapt=adapt)
+                map_moments=map_moments, adapt=adapt, graph=graph)
         s.init_equilibrium(np.stack([p.rho0.ravel(), p.u0.ravel(), p.v0.ravel(), p.T0.ravel()], axis=1))
         return s
 
@@ -339,6 +348,14 @@ class Solver:
         ms = ctypes.c_double()
         _check(lib().mlvs_time_stage(self.h, self.STAGES.get(stage, stage), int(reps), ctypes.byref(ms)))
         return ms.value
+
+    def variants(self, stage):
+        n = ctypes.c_int()
+        _check(lib().mlvs_variants(self.STAGES.get(stage, stage), ctypes.byref(n)))
+        return n.value
+
+    def set_variant(self, stage, v: int):
+        _check(lib().mlvs_set_variant(self.h, self.STAGES.get(stage, stage), int(v)))
 
     def stage_size(self, stage):
         it = ctypes.c_int64()

@@ -1,0 +1,77 @@
+"""Autotuner for the launch variants of the step's kernels.
+
+For each tunable stage the library holds several instantiations of the kernel
+(minimum-occupancy targets of 2, 4, 6 and 8 waves per SIMD, i.e. a register
+budget per lane).  The tuner times every variant on the solver's current
+state with HIP events (``Solver.time_stage``), keeps the fastest, and caches
+the choice in a JSON file keyed by GPU architecture, storage precision and the
+stage's work shape (items, mean velocity points per item), so later runs of
+the same shape skip the sweep.  Variants only change scheduling, never the
+results.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Iterable, Optional
+
+TUNABLE = ("cell", "face_rec", "face_flux", "xface")
+
+
+def default_cache() -> str:
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(base, "mlvs", "tuned.json")
+
+
+def _arch() -> str:
+    import torch
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return getattr(props, "gcnArchName", props.name).split(":")[0]
+
+
+def shape_key(solver, stage: str, precision: int) -> Optional[str]:
+    items, pts = solver.stage_size(stage)
+    if items == 0:
+        return None
+    per = int(round(pts / items))
+    # bucket the size so nearby shapes share an entry
+    bucket = 1 << max(per - 1, 1).bit_length()
+    return "%s|fp%d|%s|items~%d|pts<=%d" % (_arch(), precision, stage, 1 << max(items - 1, 1).bit_length(), bucket)
+
+
+def autotune(solver, precision: int, stages: Iterable[str] = TUNABLE, reps: int = 5,
+             cache: Optional[str] = None, force: bool = False) -> Dict[str, dict]:
+    """Choose the fastest variant per stage; returns {stage: {variant, ms, key, from_cache}}."""
+    path = cache or default_cache()
+    table = {}
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                table = json.load(f)
+        except (OSError, ValueError):
+            table = {}
+    out = {}
+    for st in stages:
+        key = shape_key(solver, st, precision)
+        if key is None:
+            continue
+        if key in table and not force:
+            solver.set_variant(st, table[key]["variant"])
+            out[st] = dict(table[key], key=key, from_cache=True)
+            continue
+        times = []
+        for v in range(solver.variants(st)):
+            solver.set_variant(st, v)
+            solver.time_stage(st, 1)                      # warm the variant
+            times.append(solver.time_stage(st, reps))
+        best = min(range(len(times)), key=lambda k: times[k])
+        solver.set_variant(st, best)
+        table[key] = {"variant": best, "ms": times[best], "all_ms": times}
+        out[st] = dict(table[key], key=key, from_cache=False)
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+    except OSError:
+        pass
+    return out

@@ -556,6 +556,11 @@ struct mlvs_ctx_s {
     uint8_t* d_kcell = nullptr;
     unsigned long long* d_hash = nullptr;
     int64_t last_unique = 0;
+    // step graph: the launches of one step captured once per level set
+    bool use_graph = false;
+    int variant[8] = {1, 1, 1, 1, 1, 1, 1, 1};   // per stage launch variant (autotuned)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     // counters
     double cnt_updates = 0.0, cnt_iface = 0.0;
     int64_t cnt_adapt = 0;
@@ -598,7 +603,15 @@ DevTable upload_table(mlvs_ctx c, const HostTable& t) {
     return d;
 }
 
+void drop_graph(mlvs_ctx c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+}
+
 void free_items(mlvs_ctx c) {
+    drop_graph(c);
     for (auto& t : c->tables) {
         c->dm.release(t.off);
         c->dm.release(t.idx);
@@ -813,6 +826,7 @@ void sync(mlvs_ctx c) { hip_check(hipStreamSynchronize(c->st), "stream synchroni
 
 void do_step(mlvs_ctx c);
 hipError_t launch_stage(mlvs_ctx c, int stage);
+hipError_t launch_step_kernels(mlvs_ctx c);
 
 }  // namespace
 
@@ -1156,6 +1170,7 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
 void mlvs_destroy(mlvs_ctx c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
+    drop_graph(c);
     c->dm.release_all();
     delete c;
 }
@@ -1220,6 +1235,33 @@ mlvs_status mlvs_info(mlvs_ctx c, double* dt, int64_t* n_cells, int32_t* n_block
         if (n_cells) *n_cells = c->mesh.n_cells;
         if (n_blocks) *n_blocks = c->base.Nb;
         if (n_base) *n_base = c->base.N;
+    });
+}
+
+mlvs_status mlvs_variants(int stage, int* count) {
+    return guarded([&] {
+        if (!count || stage < 0 || stage > 6) fail(MLVS_E_ARG, "bad arguments");
+        *count = (stage == 0 || stage == 2 || stage == 3 || stage == 4) ? variant_count() : 1;
+    });
+}
+
+mlvs_status mlvs_set_variant(mlvs_ctx c, int stage, int v) {
+    return guarded([&] {
+        int cnt = 0;
+        if (!c || mlvs_variants(stage, &cnt) != MLVS_OK || v < 0 || v >= cnt) fail(MLVS_E_ARG, "bad variant");
+        sync(c);
+        drop_graph(c);
+        c->variant[stage] = v;
+    });
+}
+
+mlvs_status mlvs_set_graph(mlvs_ctx c, int on) {
+    return guarded([&] {
+        if (!c) fail(MLVS_E_ARG, "null context");
+        if (on && c->st == nullptr) fail(MLVS_E_STATE, "graph capture needs a non-default stream");
+        sync(c);
+        drop_graph(c);
+        c->use_graph = on != 0;
     });
 }
 
@@ -1480,35 +1522,61 @@ void do_step(mlvs_ctx c) {
     if (c->adaptive && c->ap.interval > 0 && c->step_count % c->ap.interval == 0) {
         if (mlvs_adapt(c, nullptr) != MLVS_OK) throw Fail{MLVS_E_STATE, g_last_error};
     }
-    hip_check(launch_cell_prep(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->ph, c->d_params),
-              "cell stage");
-    hip_check(launch_ghost(c->prec, c->st, c->d_lv, c->d_ghosts, c->n_ghosts, c->d_cell_lev, c->d_cell_slot,
-                           c->d_params, c->ph, c->d_neg), "ghost stage");
-    hip_check(launch_face_rec(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces + c->n_bfaces, c->d_cell_slot,
-                              c->d_cell_nbr, c->d_geom, c->d_params, c->ph, c->d_fmom), "face reconstruction");
-    hip_check(launch_face_flux(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces + c->n_bfaces, c->d_cell_slot,
-                               c->d_params, c->d_bcs, c->ph, c->d_fmom), "face flux");
-    hip_check(launch_xface(c->prec, c->st, c->d_lv, c->d_xfaces, c->n_xfaces, c->d_cell_slot, c->d_cell_nbr,
-                           c->d_geom, c->d_params, c->ph, c->d_neg), "cross-level stage");
-    hip_check(launch_update(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom, c->d_cell_frow,
-                            c->ph), "update stage");
+    if (c->use_graph) {
+        if (!c->gexec) {
+            hip_check(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal), "begin capture");
+            hipError_t e = launch_step_kernels(c);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(c->st, &g);
+            hip_check(e, "captured launch");
+            hip_check(e2, "end capture");
+            c->graph = g;
+            hip_check(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0), "graph instantiate");
+        }
+        hip_check(hipGraphLaunch(c->gexec, c->st), "graph launch");
+    } else {
+        hip_check(launch_step_kernels(c), "step launch");
+    }
     ++c->step_count;
     c->cnt_updates += c->step_points;
     c->cnt_iface += c->step_iface_points;
 }
 
+hipError_t launch_step_kernels(mlvs_ctx c) {
+    const int n = c->mesh.n_cells;
+    hipError_t e;
+    if ((e = launch_cell_prep(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->ph, c->d_params,
+                                 c->variant[0])))
+        return e;
+    if ((e = launch_ghost(c->prec, c->st, c->d_lv, c->d_ghosts, c->n_ghosts, c->d_cell_lev, c->d_cell_slot,
+                          c->d_params, c->ph, c->d_neg)))
+        return e;
+    if ((e = launch_face_rec(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces + c->n_bfaces, c->d_cell_slot,
+                             c->d_cell_nbr, c->d_geom, c->d_params, c->ph, c->d_fmom, c->variant[2])))
+        return e;
+    if ((e = launch_face_flux(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces + c->n_bfaces, c->d_cell_slot,
+                              c->d_params, c->d_bcs, c->ph, c->d_fmom, c->variant[3])))
+        return e;
+    if ((e = launch_xface(c->prec, c->st, c->d_lv, c->d_xfaces, c->n_xfaces, c->d_cell_slot, c->d_cell_nbr,
+                          c->d_geom, c->d_params, c->ph, c->d_neg, c->variant[4])))
+        return e;
+    return launch_update(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom, c->d_cell_frow,
+                         c->ph);
+}
+
 hipError_t launch_stage(mlvs_ctx c, int stage) {
     const int n = c->mesh.n_cells;
     switch (stage) {
-    case 0: return launch_cell_prep(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->ph, c->d_params);
+    case 0: return launch_cell_prep(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->ph, c->d_params,
+                                 c->variant[0]);
     case 1: return launch_ghost(c->prec, c->st, c->d_lv, c->d_ghosts, c->n_ghosts, c->d_cell_lev, c->d_cell_slot,
                                 c->d_params, c->ph, c->d_neg);
     case 2: return launch_face_rec(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces + c->n_bfaces, c->d_cell_slot,
-                                   c->d_cell_nbr, c->d_geom, c->d_params, c->ph, c->d_fmom);
+                                   c->d_cell_nbr, c->d_geom, c->d_params, c->ph, c->d_fmom, c->variant[2]);
     case 3: return launch_face_flux(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces + c->n_bfaces, c->d_cell_slot,
-                                    c->d_params, c->d_bcs, c->ph, c->d_fmom);
+                                    c->d_params, c->d_bcs, c->ph, c->d_fmom, c->variant[3]);
     case 4: return launch_xface(c->prec, c->st, c->d_lv, c->d_xfaces, c->n_xfaces, c->d_cell_slot, c->d_cell_nbr,
-                                c->d_geom, c->d_params, c->ph, c->d_neg);
+                                c->d_geom, c->d_params, c->ph, c->d_neg, c->variant[4]);
     case 5: return launch_update(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom,
                                  c->d_cell_frow, c->ph);
     default: return hipErrorInvalidValue;

@@ -202,8 +202,8 @@ __device__ __forceinline__ void compat_solve(const LevelDesc& L, const Eq<S>& eu
 // ---------------------------------------------------------------------------
 // cell stage: W, q, tau, compatibility coefficients, phi_bar+ rows
 // ---------------------------------------------------------------------------
-template <typename S>
-__global__ __launch_bounds__(BS, 4) void k_cell_prep(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
+template <typename S, int MINW>
+__global__ __launch_bounds__(BS, MINW) void k_cell_prep(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
                                                   const int* __restrict__ cell_slot, int n_cells, Phys ph,
                                                   double* __restrict__ params) {
     for (int c = item0(); c < n_cells; c += istride()) {
@@ -489,8 +489,8 @@ __device__ __forceinline__ void face_target(const LevelDesc& L, double* m, doubl
 // reduce the eleven raw moments of phi_bar_f (about the mean of the two cell
 // velocities); wall faces reduce the outgoing mass flux.  Per-face results go
 // to fmom[item][12].
-template <typename S>
-__global__ __launch_bounds__(BS, 4) void k_face_rec(const LevelDesc* __restrict__ lvs,
+template <typename S, int MINW>
+__global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restrict__ lvs,
                                                     const FaceItem* __restrict__ items, int n,
                                                     const int* __restrict__ cell_slot,
                                                     const int* __restrict__ cell_nbr,
@@ -562,8 +562,8 @@ __global__ __launch_bounds__(BS, 4) void k_face_rec(const LevelDesc* __restrict_
 // reconstruction, incoming ones the boundary state -- diffuse wall rho_w
 // g_eq(u_w, T_w) with rho_w from zero net mass flux, far-field Maxwellian, or
 // the cell's phi_bar+ (zero-gradient outflow).
-template <typename S>
-__global__ __launch_bounds__(BS, 4) void k_face_flux(const LevelDesc* __restrict__ lvs,
+template <typename S, int MINW>
+__global__ __launch_bounds__(BS, MINW) void k_face_flux(const LevelDesc* __restrict__ lvs,
                                                      const FaceItem* __restrict__ items, int n,
                                                      const int* __restrict__ cell_slot,
                                                      const double* __restrict__ params,
@@ -796,6 +796,25 @@ static inline int grid_for(int n) {
     return b < 1 ? 1 : (b > 1048576 ? 1048576 : b);
 }
 
+// Tunable kernels are instantiated for several minimum-occupancy targets
+// (waves per SIMD); the variant index selects one at launch.
+constexpr int N_VARIANTS = 4;
+#define MLVS_DISPATCH_V(prec, var, KERNEL, ...)                                                  \
+    do {                                                                                        \
+        switch (var) {                                                                          \
+        case 0: if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, 2>), __VA_ARGS__);            \
+                else hipLaunchKernelGGL((KERNEL<double, 2>), __VA_ARGS__); break;                 \
+        case 2: if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, 6>), __VA_ARGS__);            \
+                else hipLaunchKernelGGL((KERNEL<double, 6>), __VA_ARGS__); break;                 \
+        case 3: if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, 8>), __VA_ARGS__);            \
+                else hipLaunchKernelGGL((KERNEL<double, 8>), __VA_ARGS__); break;                 \
+        default: if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, 4>), __VA_ARGS__);           \
+                 else hipLaunchKernelGGL((KERNEL<double, 4>), __VA_ARGS__); break;                \
+        }                                                                                       \
+    } while (0)
+
+int variant_count() { return N_VARIANTS; }
+
 #define MLVS_DISPATCH(prec, KERNEL, ...)                                                        \
     do {                                                                                        \
         if ((prec) == 32) hipLaunchKernelGGL(KERNEL<float>, __VA_ARGS__);                        \
@@ -803,9 +822,9 @@ static inline int grid_for(int n) {
     } while (0)
 
 hipError_t launch_cell_prep(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
-                            int n_cells, Phys ph, double* params) {
+                            int n_cells, Phys ph, double* params, int var) {
     if (n_cells <= 0) return hipSuccess;
-    MLVS_DISPATCH(prec, k_cell_prep, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells, ph,
+    MLVS_DISPATCH_V(prec, var, k_cell_prep, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells, ph,
                   params);
     return hipGetLastError();
 }
@@ -829,18 +848,18 @@ hipError_t launch_ghost(int prec, hipStream_t st, const LevelDesc* lv, const Gho
 
 hipError_t launch_face_rec(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
                            const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
-                           Phys ph, double* fmom) {
+                           Phys ph, double* fmom, int var) {
     if (n <= 0) return hipSuccess;
-    MLVS_DISPATCH(prec, k_face_rec, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr, geom,
+    MLVS_DISPATCH_V(prec, var, k_face_rec, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr, geom,
                   params, ph, fmom);
     return hipGetLastError();
 }
 
 hipError_t launch_face_flux(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
                             const int* cell_slot, const double* params, const BCDev* bcs, Phys ph,
-                            const double* fmom) {
+                            const double* fmom, int var) {
     if (n <= 0) return hipSuccess;
-    MLVS_DISPATCH(prec, k_face_flux, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, params, bcs, ph,
+    MLVS_DISPATCH_V(prec, var, k_face_flux, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, params, bcs, ph,
                   fmom);
     return hipGetLastError();
 }
@@ -895,8 +914,8 @@ __device__ __forceinline__ void side_refined(const Side<S>& sd, const LevelDesc&
     sy[1] = sy[1] + dq * sy[0];
 }
 
-template <typename S>
-__global__ __launch_bounds__(BS, 4) void k_xface(const LevelDesc* __restrict__ lvs, const XFaceItem* __restrict__ items,
+template <typename S, int MINW>
+__global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict__ lvs, const XFaceItem* __restrict__ items,
                                               int n, const int* __restrict__ cell_slot,
                                               const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
                                               const double* __restrict__ params, Phys ph, unsigned long long* neg) {
@@ -1265,9 +1284,9 @@ __global__ void k_compare_rows_u8(const uint8_t* __restrict__ all, int width, co
 
 hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFaceItem* items, int n,
                         const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
-                        Phys ph, unsigned long long* neg) {
+                        Phys ph, unsigned long long* neg, int var) {
     if (n <= 0) return hipSuccess;
-    MLVS_DISPATCH(prec, k_xface, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr, geom, params,
+    MLVS_DISPATCH_V(prec, var, k_xface, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr, geom, params,
                   ph, neg);
     return hipGetLastError();
 }

@@ -84,20 +84,21 @@ struct RemapItem {     // cell moved from an old level to a new one
 };
 
 // Launch wrappers (kernels.hip).  `S` selects float (32) or double (64) storage.
+int variant_count();
 hipError_t launch_cell_prep(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
-                            const int* cell_slot, int n_cells, Phys ph, double* params);
+                            const int* cell_slot, int n_cells, Phys ph, double* params, int var = 1);
 hipError_t launch_ghost(int prec, hipStream_t st, const LevelDesc* lv, const GhostItem* items, int n,
                         const int* cell_lev, const int* cell_slot, const double* params, Phys ph,
                         unsigned long long* neg);
 hipError_t launch_face_rec(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
                            const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
-                           const double* params, Phys ph, double* fmom);
+                           const double* params, Phys ph, double* fmom, int var = 1);
 hipError_t launch_face_flux(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
                             const int* cell_slot, const double* params, const BCDev* bcs, Phys ph,
-                            const double* fmom);
+                            const double* fmom, int var = 1);
 hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFaceItem* items, int n,
                         const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
-                        const double* params, Phys ph, unsigned long long* neg);
+                        const double* params, Phys ph, unsigned long long* neg, int var = 1);
 hipError_t launch_update(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
                          const int* cell_slot, int n_cells, const CellGeom* geom,
                          const int* cell_frow, Phys ph);

@@ -1,0 +1,57 @@
+"""Graph replay of the step: every replay equals the directly launched step, bit
+for bit, including re-capture after adaptations and host work between replays."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(p, **kw):
+    import paper_2609_35258_amd as m
+    return m.Solver.from_problem(p, **kw)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_graph_replay_matches_eager_with_adaptation(precision):
+    import torch
+    p = W.perturb(W.periodic_box(12, 6, Lx=1.0, Ly=0.5, Kn=0.05, nv=24, vmax=5.0, kind="sine", amp=0.5), seed=4)
+    ap = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=1e-3, tau_clust=0.02, flux_test=True, interval=3)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        a = _gpu(p, precision=precision, adapt=ap)
+    b = _gpu(p, precision=precision, adapt=ap, graph=True)
+    for k in range(8):
+        a.step(1)
+        b.step(1)
+        sa, sb = a.get_state(), b.get_state()      # host work and syncs between replays
+        assert all(np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1]) for x, y in zip(sa, sb)), k
+    assert b.counters()["adaptations"] >= 2
+    a.close()
+    b.close()
+
+
+def test_variants_give_identical_results_and_autotune_runs(tmp_path):
+    import paper_2609_35258_amd.autotune as at
+    p = W.cylinder(16, 8, Kn=0.1, nv=21, vmax=10.0)
+    ref = None
+    for v in range(4):
+        s = _gpu(p, precision=32)
+        for st in at.TUNABLE:
+            if s.variants(st) > 1:
+                s.set_variant(st, v)
+        s.step(3)
+        st_ = s.get_state()
+        if ref is None:
+            ref = st_
+        else:
+            assert all(np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1]) for x, y in zip(st_, ref)), v
+        s.close()
+    s = _gpu(p, precision=32)
+    res = at.autotune(s, 32, cache=str(tmp_path / "t.json"))
+    assert "face_rec" in res and "cell" in res
+    res2 = at.autotune(s, 32, cache=str(tmp_path / "t.json"))
+    assert all(r["from_cache"] for r in res2.values())
+    s.step(2)
+    s.close()
