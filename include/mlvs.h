@@ -125,6 +125,7 @@ typedef struct {
     int64_t n_cross;       /* cross-level faces                             */
     double nbar;           /* cell-weighted mean number of velocity points  */
     int64_t neg_count;     /* corrections that produced negative g          */
+    int64_t n_fallback;    /* learned adaptation: cells sent to the criterion */
 } mlvs_adapt_report;
 
 /* Quadrature helpers (Sec. 2.3).  Newton-Cotes on [-a, a]: composite Boole
@@ -233,7 +234,68 @@ mlvs_status mlvs_memory(mlvs_ctx ctx, size_t* device_bytes);
  * the provisional distribution had none (positivity check; values kept). */
 mlvs_status mlvs_neg_count(mlvs_ctx ctx, int64_t* count);
 
-void mlvs_destroy(mlvs_ctx ctx);
+/* ---- learned level selector ------------------------------------------------
+ * Network 10 -> 64 -> 64 -> K (ReLU, softmax), parameters as float in the
+ * layout W1 [64][10], b1 [64], W2 [64][64], b2 [64], W3 [K][64], b3 [K],
+ * mean [10], std [10] (inputs are standardised by mean/std); 2 <= K <= 16.
+ * Features per cell: log rho, u/sqrt(R T_ref), v/sqrt(R T_ref), log(T/T_ref),
+ * q_x/(p sqrt(RT)), q_y/(p sqrt(RT)), sigma_xx/p, sigma_xy/p,
+ * log(1 + dx |grad rho|/rho), log10(lambda/dx) with lambda = (mu/p)
+ * sqrt(pi R T/2), dx = sqrt(|V|).  Labels: the fewest-point level of the
+ * current catalogue whose enclosing mask is no coarser than the cell's own
+ * criterion mask anywhere (the criterion is the judge), -1 if none. */
+typedef struct {
+    int epochs, batch;
+    double lr, beta1, beta2, eps;
+    double val_frac;       /* last fraction of the samples (in given order) held out */
+    uint64_t seed;         /* shuffling */
+} mlvs_train_cfg;
+
+typedef struct {
+    double loss_first, loss_last;   /* mean training loss of the first / last epoch */
+    double train_acc, val_acc;      /* FP32 inference accuracy                     */
+    int64_t n_train, n_val, steps;
+    double ms;                      /* device time of the training loop            */
+} mlvs_train_report;
+
+/* Number of float parameters for K classes. */
+mlvs_status mlvs_mlp_nparams(int K, int64_t* n);
+
+/* Features of every cell from the current state: out [n_cells][10] floats. */
+mlvs_status mlvs_features(mlvs_ctx ctx, float* out);
+
+/* Criterion-judged catalogue labels of every cell: out [n_cells] (needs
+ * adaptation parameters; the catalogue is the current level set). */
+mlvs_status mlvs_labels(mlvs_ctx ctx, int32_t* out);
+
+/* Train on the device (FP32 forward/backward/Adam kernels).  params: in the
+ * initial values, out the trained ones (the mean/std block is set from the
+ * training samples).  X [n][10], y [n] host arrays.  Uses hipMalloc and the
+ * null stream; synchronous. */
+mlvs_status mlvs_mlp_train(float* params, int K, const float* X, const int32_t* y, int64_t n,
+                           const mlvs_train_cfg* cfg, mlvs_train_report* report);
+
+/* One forward/backward pass on the device (no update): probs [B][K], grad
+ * [n_params] (zero on the mean/std block), *loss the mean cross-entropy.
+ * Host arrays; synchronous. */
+mlvs_status mlvs_mlp_eval(const float* params, int K, const float* X, const int32_t* y, int B,
+                          float* probs, float* grad, double* loss);
+
+/* Inference: classes [B] (argmax) and optional probs [B][K]; bf16 = 1 rounds
+ * weights and activations to bfloat16 (FP32 accumulation). */
+mlvs_status mlvs_mlp_predict(const float* params, int K, const float* X, int B, int bf16,
+                             int32_t* classes, float* probs);
+
+/* Install a trained selector for the current catalogue (K == number of
+ * levels).  Afterwards adaptations (mlvs_adapt, and those mlvs_step runs at
+ * its interval) keep this catalogue frozen: each cell's level is predicted
+ * from its features (BF16 inference); a prediction is rejected when a block
+ * the predicted level merges has I_B > C_split on the cell's distribution
+ * (tail-mass check); rejected cells take the criterion's label.  params NULL
+ * removes the selector. */
+mlvs_status mlvs_selector_set(mlvs_ctx ctx, const float* params, int K);
+
+void        mlvs_destroy(mlvs_ctx ctx);
 const char* mlvs_last_error(void);
 
 #ifdef __cplusplus

@@ -63,7 +63,23 @@ class mlvs_device(ctypes.Structure):
 
 class mlvs_adapt_report(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int), ("n_unique", ctypes.c_int64), ("n_changed", ctypes.c_int64),
-                ("n_cross", ctypes.c_int64), ("nbar", ctypes.c_double), ("neg_count", ctypes.c_int64)]
+                ("n_cross", ctypes.c_int64), ("nbar", ctypes.c_double), ("neg_count", ctypes.c_int64),
+                ("n_fallback", ctypes.c_int64)]
+
+
+class mlvs_train_cfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("val_frac", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class mlvs_train_report(ctypes.Structure):
+    _fields_ = [("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double), ("train_acc", ctypes.c_double),
+                ("val_acc", ctypes.c_double), ("n_train", ctypes.c_int64), ("n_val", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("ms", ctypes.c_double)]
+
+
+_c_float_p = ctypes.POINTER(ctypes.c_float)
 
 
 # name -> (restype, argtypes)
@@ -102,6 +118,16 @@ _PROTOS = {
     "mlvs_stage_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                                        _c_double_p]),
     "mlvs_neg_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "mlvs_mlp_nparams": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
+    "mlvs_features": (ctypes.c_int, [ctypes.c_void_p, _c_float_p]),
+    "mlvs_labels": (ctypes.c_int, [ctypes.c_void_p, _c_int32_p]),
+    "mlvs_mlp_train": (ctypes.c_int, [_c_float_p, ctypes.c_int, _c_float_p, _c_int32_p, ctypes.c_int64,
+                                      ctypes.POINTER(mlvs_train_cfg), ctypes.POINTER(mlvs_train_report)]),
+    "mlvs_mlp_eval": (ctypes.c_int, [_c_float_p, ctypes.c_int, _c_float_p, _c_int32_p, ctypes.c_int, _c_float_p,
+                                     _c_float_p, _c_double_p]),
+    "mlvs_mlp_predict": (ctypes.c_int, [_c_float_p, ctypes.c_int, _c_float_p, ctypes.c_int, ctypes.c_int,
+                                        _c_int32_p, _c_float_p]),
+    "mlvs_selector_set": (ctypes.c_int, [ctypes.c_void_p, _c_float_p, ctypes.c_int]),
     "mlvs_destroy": (None, [ctypes.c_void_p]),
     "mlvs_last_error": (ctypes.c_char_p, []),
 }
@@ -159,6 +185,52 @@ def mu_ref_from_kn(Kn, rho, T, R, L, omega):
     out = ctypes.c_double()
     _check(lib().mlvs_mu_ref_from_kn(Kn, rho, T, R, L, omega, ctypes.byref(out)))
     return out.value
+
+
+def _fp(a):
+    return a.ctypes.data_as(_c_float_p)
+
+
+def mlp_nparams(K: int) -> int:
+    n = ctypes.c_int64()
+    _check(lib().mlvs_mlp_nparams(K, ctypes.byref(n)))
+    return n.value
+
+
+def mlp_eval(params, K, X, y):
+    """One device forward/backward pass: (probs [B][K], grad [n_params], mean loss)."""
+    P = np.ascontiguousarray(params, np.float32)
+    Xf = np.ascontiguousarray(X, np.float32)
+    yy = np.ascontiguousarray(y, np.int32)
+    B = len(yy)
+    probs = np.zeros((B, K), np.float32)
+    grad = np.zeros(len(P), np.float32)
+    loss = ctypes.c_double()
+    _check(lib().mlvs_mlp_eval(_fp(P), K, _fp(Xf), yy.ctypes.data_as(_c_int32_p), B, _fp(probs), _fp(grad),
+                               ctypes.byref(loss)))
+    return probs, grad, loss.value
+
+
+def mlp_predict(params, K, X, bf16=True):
+    P = np.ascontiguousarray(params, np.float32)
+    Xf = np.ascontiguousarray(X, np.float32)
+    B = len(Xf)
+    cls = np.zeros(B, np.int32)
+    probs = np.zeros((B, K), np.float32)
+    _check(lib().mlvs_mlp_predict(_fp(P), K, _fp(Xf), B, int(bf16), cls.ctypes.data_as(_c_int32_p), _fp(probs)))
+    return cls, probs
+
+
+def mlp_train(params, K, X, y, epochs=10, batch=4096, lr=1e-3, val_frac=0.2, seed=0):
+    """Train on the device; returns (trained params, report dict)."""
+    P = np.array(params, np.float32)
+    Xf = np.ascontiguousarray(X, np.float32)
+    yy = np.ascontiguousarray(y, np.int32)
+    cfg = mlvs_train_cfg(int(epochs), int(batch), float(lr), 0.9, 0.999, 1e-8, float(val_frac), int(seed))
+    rep = mlvs_train_report()
+    _check(lib().mlvs_mlp_train(_fp(P), K, _fp(Xf), yy.ctypes.data_as(_c_int32_p), len(yy), ctypes.byref(cfg),
+                                ctypes.byref(rep)))
+    return P, {k: getattr(rep, k) for k, _ in mlvs_train_report._fields_}
 
 
 class Solver:
@@ -329,6 +401,23 @@ class Solver:
         out = np.zeros((self.n_cells, self.n_blocks), np.uint8)
         _check(lib().mlvs_criterion(self.h, out.ctypes.data_as(_c_uint8_p)))
         return out
+
+    def features(self):
+        out = np.zeros((self.n_cells, 10), np.float32)
+        _check(lib().mlvs_features(self.h, _fp(out)))
+        return out
+
+    def labels(self):
+        out = np.zeros(self.n_cells, np.int32)
+        _check(lib().mlvs_labels(self.h, out.ctypes.data_as(_c_int32_p)))
+        return out
+
+    def selector_set(self, params, K):
+        if params is None:
+            _check(lib().mlvs_selector_set(self.h, None, 0))
+            return
+        self._sel = np.ascontiguousarray(params, np.float32)
+        _check(lib().mlvs_selector_set(self.h, _fp(self._sel), int(K)))
 
     def memory(self):
         v = ctypes.c_size_t()

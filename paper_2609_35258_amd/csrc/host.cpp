@@ -556,6 +556,11 @@ struct mlvs_ctx_s {
     uint8_t* d_kcell = nullptr;
     unsigned long long* d_hash = nullptr;
     int64_t last_unique = 0;
+    // learned selector
+    int* d_nbr_cell = nullptr;
+    float* d_sel = nullptr;
+    int sel_K = 0;
+    int64_t last_fallback = 0;
     // step graph: the launches of one step captured once per level set
     bool use_graph = false;
     int variant[8] = {1, 1, 1, 1, 1, 1, 1, 1};   // per stage launch variant (autotuned)
@@ -1031,6 +1036,8 @@ void cluster(int Nb, double tau, const std::vector<uint8_t>& uniq, const std::ve
     for (int u = 0; u < U; ++u) level_of_u[u] = level_of_cl[cl_of_u[u]];
 }
 
+void adapt_learned(mlvs_ctx c, mlvs_adapt_report* rep);
+
 void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
     run_criterion(c);
     std::vector<uint8_t> uniq;
@@ -1058,7 +1065,106 @@ void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
         hip_check(hipMemcpyAsync(&v, c->d_neg, 8, hipMemcpyDeviceToHost, c->st), "D2H");
         sync(c);
         rep->neg_count = (int64_t)v;
+        rep->n_fallback = 0;
     }
+}
+
+void compute_features(mlvs_ctx c, float* d_out) {
+    const int n = c->mesh.n_cells;
+    double* d8 = static_cast<double*>(c->dm.alloc(sizeof(double) * 8 * (size_t)n));
+    hip_check(launch_cell_moments(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom, c->ph,
+                                  nullptr, nullptr, d8), "moments launch");
+    hip_check(launch_features(c->st, d8, c->d_nbr_cell, c->d_geom, n, c->ph.R, c->ph.T_ref, c->ph.mu_ref,
+                              c->ph.omega, d_out), "features launch");
+    sync(c);
+    c->dm.release(d8);
+}
+
+std::vector<int> level_order(mlvs_ctx c) {
+    std::vector<int> order(c->levels.size());
+    for (size_t l = 0; l < order.size(); ++l) order[l] = (int)l;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->levels[a]->N < c->levels[b]->N; });
+    return order;
+}
+
+// Frozen catalogue: predicted level per cell, tail-mass check, criterion labels
+// for the rejected cells, remap of the cells whose level changes.
+void adapt_learned(mlvs_ctx c, mlvs_adapt_report* rep) {
+    const int n = c->mesh.n_cells, K = (int)c->levels.size(), Nb = c->base.Nb;
+    if (K != c->sel_K) fail(MLVS_E_STATE, "selector trained for %d levels, catalogue has %d", c->sel_K, K);
+    float* d_feat = static_cast<float*>(c->dm.alloc(sizeof(float) * 10 * (size_t)n));
+    int* d_pred = static_cast<int*>(c->dm.alloc(sizeof(int) * (size_t)n));
+    int* d_acc = static_cast<int*>(c->dm.alloc(sizeof(int) * (size_t)n));
+    compute_features(c, d_feat);
+    hip_check(launch_mlp_predict(c->st, c->d_sel, K, d_feat, n, 1, d_pred, nullptr), "predict launch");
+    hip_check(launch_tail_check(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_ptb_all,
+                                c->d_ptb_off, c->d_kappa_all, d_pred, c->d_bw, c->base.nx, c->base.ny,
+                                c->ap.C_split, d_acc), "tail check launch");
+    std::vector<int> pred(n), acc(n);
+    hip_check(hipMemcpyAsync(pred.data(), d_pred, sizeof(int) * n, hipMemcpyDeviceToHost, c->st), "D2H");
+    hip_check(hipMemcpyAsync(acc.data(), d_acc, sizeof(int) * n, hipMemcpyDeviceToHost, c->st), "D2H");
+    sync(c);
+    std::vector<int> rej;
+    for (int i = 0; i < n; ++i)
+        if (!acc[i]) rej.push_back(i);
+    std::vector<int> cl = pred;
+    if (!rej.empty()) {
+        if (!c->d_kcell) c->d_kcell = static_cast<uint8_t*>(c->dm.alloc((size_t)n * Nb));
+        if (!c->d_hash) c->d_hash = static_cast<unsigned long long*>(c->dm.alloc(sizeof(unsigned long long) * n));
+        int* d_list = upload(c->dm, rej, c->st);
+        hip_check(launch_criterion(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, (int)rej.size(),
+                                   c->d_ptb_all, c->d_ptb_off, c->d_kappa_all, c->d_bx, c->d_by, c->d_bw, c->base.nx,
+                                   c->base.ny, c->ap.C_split, c->ap.C_merge, c->ap.eps_merge, c->ap.flux_test,
+                                   c->d_kcell, c->d_hash, d_list), "criterion launch");
+        std::vector<int> order = level_order(c);
+        int* d_order = upload(c->dm, order, c->st);
+        hip_check(launch_labels(c->st, c->d_kcell, n, Nb, c->d_kappa_all, d_order, K, d_pred), "labels launch");
+        std::vector<int> lab(n);
+        hip_check(hipMemcpyAsync(lab.data(), d_pred, sizeof(int) * n, hipMemcpyDeviceToHost, c->st), "D2H");
+        sync(c);
+        const int finest = order.back();
+        for (int i : rej) cl[i] = lab[i] >= 0 ? lab[i] : finest;
+        c->dm.release(d_list);
+        c->dm.release(d_order);
+    }
+    c->dm.release(d_feat);
+    c->dm.release(d_pred);
+    c->dm.release(d_acc);
+    std::vector<std::unique_ptr<Level>> nl;
+    for (auto& L : c->levels) nl.push_back(build_level(c->base, L->kappa));
+    const int64_t changed = install_levels(c, std::move(nl), cl);
+    c->last_fallback = (int64_t)rej.size();
+    ++c->cnt_adapt;
+    if (rep) {
+        rep->n_levels = K;
+        rep->n_unique = -1;
+        rep->n_changed = changed;
+        rep->n_cross = c->n_cross;
+        double tot = 0.0;
+        for (auto& L : c->levels) tot += (double)L->N * L->n_cells;
+        rep->nbar = tot / n;
+        unsigned long long v = 0;
+        hip_check(hipMemcpyAsync(&v, c->d_neg, 8, hipMemcpyDeviceToHost, c->st), "D2H");
+        sync(c);
+        rep->neg_count = (int64_t)v;
+        rep->n_fallback = c->last_fallback;
+    }
+}
+
+// Context-free device buffers for the network routines (hipMalloc, null stream).
+struct DevBuf {
+    void* p = nullptr;
+    explicit DevBuf(size_t n) {
+        if (hipMalloc(&p, n == 0 ? 8 : n) != hipSuccess) fail(MLVS_E_OOM, "hipMalloc of %zu bytes failed", n);
+    }
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    template <typename T> T* as() { return static_cast<T*>(p); }
+};
+
+void check_mlp_args(int K) {
+    if (K < 2 || K > 16) fail(MLVS_E_ARG, "number of classes must be in [2, 16]");
 }
 
 }  // namespace
@@ -1067,6 +1173,222 @@ void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
 // ABI
 // ---------------------------------------------------------------------------
 extern "C" {
+
+mlvs_status mlvs_mlp_nparams(int K, int64_t* n) {
+    return guarded([&] {
+        check_mlp_args(K);
+        if (!n) fail(MLVS_E_ARG, "null output");
+        *n = mlp_nparams(K);
+    });
+}
+
+mlvs_status mlvs_features(mlvs_ctx c, float* out) {
+    return guarded([&] {
+        if (!c || !out) fail(MLVS_E_ARG, "null argument");
+        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
+        if (c->phys.dim != 2) fail(MLVS_E_STATE, "features need dim = 2");
+        const int n = c->mesh.n_cells;
+        float* d = static_cast<float*>(c->dm.alloc(sizeof(float) * 10 * (size_t)n));
+        compute_features(c, d);
+        hip_check(hipMemcpyAsync(out, d, sizeof(float) * 10 * (size_t)n, hipMemcpyDeviceToHost, c->st), "D2H");
+        sync(c);
+        c->dm.release(d);
+    });
+}
+
+mlvs_status mlvs_labels(mlvs_ctx c, int32_t* out) {
+    return guarded([&] {
+        if (!c || !out) fail(MLVS_E_ARG, "null argument");
+        if (!c->adaptive) fail(MLVS_E_STATE, "context was created without adaptation parameters");
+        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
+        run_criterion(c);
+        const int n = c->mesh.n_cells;
+        std::vector<int> order = level_order(c);
+        int* d_order = upload(c->dm, order, c->st);
+        int* d_lab = static_cast<int*>(c->dm.alloc(sizeof(int) * (size_t)n));
+        hip_check(launch_labels(c->st, c->d_kcell, n, c->base.Nb, c->d_kappa_all, d_order, (int)order.size(), d_lab),
+                  "labels launch");
+        hip_check(hipMemcpyAsync(out, d_lab, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost, c->st), "D2H");
+        sync(c);
+        c->dm.release(d_order);
+        c->dm.release(d_lab);
+    });
+}
+
+mlvs_status mlvs_mlp_eval(const float* params, int K, const float* X, const int32_t* y, int B, float* probs,
+                          float* grad, double* loss) {
+    return guarded([&] {
+        check_mlp_args(K);
+        if (!params || !X || !y || B < 1) fail(MLVS_E_ARG, "bad arguments");
+        for (int b = 0; b < B; ++b)
+            if (y[b] < 0 || y[b] >= K) fail(MLVS_E_ARG, "label out of range");
+        const size_t np = mlp_nparams(K), Bs = (size_t)B;
+        DevBuf P(4 * np), G(4 * np), Xd(40 * Bs), Yd(4 * Bs), XN(40 * Bs), A1(256 * Bs), A2(256 * Bs),
+            D1(256 * Bs), D2(256 * Bs), D3(4 * K * Bs), PR(4 * K * Bs), LV(4 * Bs), LS(8);
+        hip_check(hipMemcpy(P.p, params, 4 * np, hipMemcpyHostToDevice), "H2D");
+        hip_check(hipMemcpy(Xd.p, X, 40 * Bs, hipMemcpyHostToDevice), "H2D");
+        hip_check(hipMemcpy(Yd.p, y, 4 * Bs, hipMemcpyHostToDevice), "H2D");
+        hip_check(hipMemset(G.p, 0, 4 * np), "memset");
+        hip_check(launch_mlp_fwd_bwd(nullptr, P.as<float>(), K, Xd.as<float>(), Yd.as<int>(), nullptr, B,
+                                     XN.as<float>(), A1.as<float>(), A2.as<float>(), D1.as<float>(), D2.as<float>(),
+                                     D3.as<float>(), PR.as<float>(), LV.as<float>(), LS.as<double>()), "fwd/bwd");
+        hip_check(launch_mlp_grad(nullptr, K, B, XN.as<float>(), A1.as<float>(), A2.as<float>(), D1.as<float>(),
+                                  D2.as<float>(), D3.as<float>(), G.as<float>()), "grad");
+        hip_check(hipDeviceSynchronize(), "sync");
+        if (probs) hip_check(hipMemcpy(probs, PR.p, 4 * K * Bs, hipMemcpyDeviceToHost), "D2H");
+        if (grad) hip_check(hipMemcpy(grad, G.p, 4 * np, hipMemcpyDeviceToHost), "D2H");
+        if (loss) {
+            double sum = 0.0;
+            hip_check(hipMemcpy(&sum, LS.p, 8, hipMemcpyDeviceToHost), "D2H");
+            *loss = sum / B;
+        }
+    });
+}
+
+mlvs_status mlvs_mlp_predict(const float* params, int K, const float* X, int B, int bf16, int32_t* classes,
+                             float* probs) {
+    return guarded([&] {
+        check_mlp_args(K);
+        if (!params || !X || !classes || B < 1) fail(MLVS_E_ARG, "bad arguments");
+        const size_t np = mlp_nparams(K), Bs = (size_t)B;
+        DevBuf P(4 * np), Xd(40 * Bs), C(4 * Bs), PR(4 * K * Bs);
+        hip_check(hipMemcpy(P.p, params, 4 * np, hipMemcpyHostToDevice), "H2D");
+        hip_check(hipMemcpy(Xd.p, X, 40 * Bs, hipMemcpyHostToDevice), "H2D");
+        hip_check(launch_mlp_predict(nullptr, P.as<float>(), K, Xd.as<float>(), B, bf16, C.as<int>(),
+                                     probs ? PR.as<float>() : nullptr), "predict");
+        hip_check(hipDeviceSynchronize(), "sync");
+        hip_check(hipMemcpy(classes, C.p, 4 * Bs, hipMemcpyDeviceToHost), "D2H");
+        if (probs) hip_check(hipMemcpy(probs, PR.p, 4 * K * Bs, hipMemcpyDeviceToHost), "D2H");
+    });
+}
+
+mlvs_status mlvs_mlp_train(float* params, int K, const float* X, const int32_t* y, int64_t n,
+                           const mlvs_train_cfg* cfg, mlvs_train_report* rep) {
+    return guarded([&] {
+        check_mlp_args(K);
+        if (!params || !X || !y || !cfg || n < 2 || n > (int64_t)1 << 30) fail(MLVS_E_ARG, "bad arguments");
+        if (cfg->epochs < 1 || cfg->batch < 1 || !(cfg->val_frac >= 0.0 && cfg->val_frac < 1.0))
+            fail(MLVS_E_ARG, "bad training configuration");
+        for (int64_t i = 0; i < n; ++i)
+            if (y[i] < 0 || y[i] >= K) fail(MLVS_E_ARG, "label out of range at %lld", (long long)i);
+        const int64_t n_val = (int64_t)std::floor(cfg->val_frac * n);
+        const int64_t n_tr = n - n_val;
+        if (n_tr < 1) fail(MLVS_E_ARG, "no training samples");
+        const int np = mlp_nparams(K);
+        std::vector<float> P(params, params + np);
+        for (int k = 0; k < 10; ++k) {   // input standardisation from the training samples
+            double m = 0.0, v = 0.0;
+            for (int64_t i = 0; i < n_tr; ++i) m += X[i * 10 + k];
+            m /= n_tr;
+            for (int64_t i = 0; i < n_tr; ++i) v += (X[i * 10 + k] - m) * (X[i * 10 + k] - m);
+            v = std::sqrt(v / n_tr);
+            P[np - 20 + k] = (float)m;
+            P[np - 10 + k] = (float)(v > 1e-12 ? v : 1.0);
+        }
+        const int B = (int)std::min<int64_t>(cfg->batch, n_tr);
+        const size_t Bs = (size_t)B, ns = (size_t)n;
+        const int ntr = np - 20;
+        DevBuf Pd(4 * (size_t)np), G(4 * (size_t)np), M(4 * (size_t)np), V(4 * (size_t)np), Xd(40 * ns),
+            Yd(4 * ns), IDX(4 * (size_t)n_tr), XN(40 * Bs), A1(256 * Bs), A2(256 * Bs), D1(256 * Bs),
+            D2(256 * Bs), D3(4 * K * Bs), LV(4 * Bs);
+        const int64_t steps_per_epoch = n_tr / B;
+        const int64_t total_steps = steps_per_epoch * cfg->epochs;
+        DevBuf LS(8 * (size_t)std::max<int64_t>(total_steps, 1));
+        hip_check(hipMemcpy(Pd.p, P.data(), 4 * (size_t)np, hipMemcpyHostToDevice), "H2D");
+        hip_check(hipMemcpy(Xd.p, X, 40 * ns, hipMemcpyHostToDevice), "H2D");
+        hip_check(hipMemcpy(Yd.p, y, 4 * ns, hipMemcpyHostToDevice), "H2D");
+        hip_check(hipMemset(M.p, 0, 4 * (size_t)np), "memset");
+        hip_check(hipMemset(V.p, 0, 4 * (size_t)np), "memset");
+        hip_check(hipMemset(G.p, 0, 4 * (size_t)np), "memset");
+        std::vector<int> perm(n_tr);
+        uint64_t state = cfg->seed ? cfg->seed : 0x2545f4914f6cdd1dull;
+        auto next = [&]() {   // splitmix64
+            uint64_t z = (state += 0x9e3779b97f4a7c15ull);
+            z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+            z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+            return z ^ (z >> 31);
+        };
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "event");
+        hip_check(hipEventCreate(&e1), "event");
+        hip_check(hipEventRecord(e0, nullptr), "event");
+        int64_t t = 0;
+        for (int ep = 0; ep < cfg->epochs; ++ep) {
+            for (int64_t i = 0; i < n_tr; ++i) perm[i] = (int)i;
+            for (int64_t i = n_tr - 1; i > 0; --i) std::swap(perm[i], perm[next() % (uint64_t)(i + 1)]);
+            hip_check(hipMemcpy(IDX.p, perm.data(), 4 * (size_t)n_tr, hipMemcpyHostToDevice), "H2D");
+            for (int64_t sidx = 0; sidx < steps_per_epoch; ++sidx, ++t) {
+                hip_check(launch_mlp_fwd_bwd(nullptr, Pd.as<float>(), K, Xd.as<float>(), Yd.as<int>(),
+                                             IDX.as<int>() + sidx * B, B, XN.as<float>(), A1.as<float>(),
+                                             A2.as<float>(), D1.as<float>(), D2.as<float>(), D3.as<float>(), nullptr,
+                                             LV.as<float>(), LS.as<double>() + t), "fwd/bwd");
+                hip_check(launch_mlp_grad(nullptr, K, B, XN.as<float>(), A1.as<float>(), A2.as<float>(),
+                                          D1.as<float>(), D2.as<float>(), D3.as<float>(), G.as<float>()), "grad");
+                hip_check(launch_adam(nullptr, Pd.as<float>(), G.as<float>(), M.as<float>(), V.as<float>(), ntr,
+                                      (float)cfg->lr, (float)cfg->beta1, (float)cfg->beta2, (float)cfg->eps,
+                                      (int)(t + 1)), "adam");
+            }
+        }
+        hip_check(hipEventRecord(e1, nullptr), "event");
+        hip_check(hipEventSynchronize(e1), "event");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        std::vector<double> ls(std::max<int64_t>(total_steps, 1), 0.0);
+        if (total_steps > 0) hip_check(hipMemcpy(ls.data(), LS.p, 8 * total_steps, hipMemcpyDeviceToHost), "D2H");
+        hip_check(hipMemcpy(P.data(), Pd.p, 4 * (size_t)np, hipMemcpyDeviceToHost), "D2H");
+        std::copy(P.begin(), P.end(), params);
+        std::vector<int> cls(n);
+        DevBuf C(4 * ns);
+        hip_check(launch_mlp_predict(nullptr, Pd.as<float>(), K, Xd.as<float>(), (int)n, 0, C.as<int>(), nullptr),
+                  "predict");
+        hip_check(hipMemcpy(cls.data(), C.p, 4 * ns, hipMemcpyDeviceToHost), "D2H");
+        if (rep) {
+            int64_t ok_tr = 0, ok_va = 0;
+            for (int64_t i = 0; i < n; ++i) {
+                if (i < n_tr) ok_tr += cls[i] == y[i];
+                else ok_va += cls[i] == y[i];
+            }
+            auto mean_epoch = [&](int ep) {
+                double sum = 0.0;
+                for (int64_t k = 0; k < steps_per_epoch; ++k) sum += ls[ep * steps_per_epoch + k] / B;
+                return steps_per_epoch ? sum / steps_per_epoch : 0.0;
+            };
+            rep->loss_first = mean_epoch(0);
+            rep->loss_last = mean_epoch(cfg->epochs - 1);
+            rep->train_acc = (double)ok_tr / n_tr;
+            rep->val_acc = n_val ? (double)ok_va / n_val : 0.0;
+            rep->n_train = n_tr;
+            rep->n_val = n_val;
+            rep->steps = total_steps;
+            rep->ms = ms;
+        }
+    });
+}
+
+mlvs_status mlvs_selector_set(mlvs_ctx c, const float* params, int K) {
+    return guarded([&] {
+        if (!c) fail(MLVS_E_ARG, "null context");
+        if (!params) {
+            c->dm.release(c->d_sel);
+            c->d_sel = nullptr;
+            c->sel_K = 0;
+            return;
+        }
+        check_mlp_args(K);
+        if (!c->adaptive) fail(MLVS_E_STATE, "context was created without adaptation parameters");
+        if (K != (int)c->levels.size())
+            fail(MLVS_E_ARG, "K = %d but the catalogue has %d levels", K, (int)c->levels.size());
+        const int np = mlp_nparams(K);
+        c->dm.release(c->d_sel);
+        c->d_sel = static_cast<float*>(c->dm.alloc(4 * (size_t)np));
+        hip_check(hipMemcpyAsync(c->d_sel, params, 4 * (size_t)np, hipMemcpyHostToDevice, c->st), "H2D");
+        sync(c);
+        c->sel_K = K;
+    });
+}
+
 
 const char* mlvs_last_error(void) { return g_last_error.c_str(); }
 
@@ -1139,6 +1461,7 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         ph.compat = phys->compat; ph.face_compat = phys->face_compat; ph.map_moments = phys->map_moments;
         // device geometry
         c->d_geom = upload(c->dm, c->mesh.geom, c->st);
+        c->d_nbr_cell = upload(c->dm, c->mesh.nbr, c->st);
         c->d_bx = upload(c->dm, B.x, c->st);
         c->d_by = upload(c->dm, B.y, c->st);
         c->d_bw = upload(c->dm, B.w, c->st);
@@ -1497,7 +1820,8 @@ mlvs_status mlvs_adapt(mlvs_ctx c, mlvs_adapt_report* rep) {
         if (!c) fail(MLVS_E_ARG, "null context");
         if (!c->adaptive) fail(MLVS_E_STATE, "context was created without adaptation parameters");
         if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
-        adapt_now(c, rep);
+        if (c->sel_K > 0) adapt_learned(c, rep);
+        else adapt_now(c, rep);
     });
 }
 

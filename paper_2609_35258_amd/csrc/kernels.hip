@@ -690,7 +690,8 @@ template <typename S>
 __global__ __launch_bounds__(BS) void k_cell_moments(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
                                                      const int* __restrict__ cell_slot, int n_cells,
                                                      const CellGeom* __restrict__ geom, Phys ph,
-                                                     double* __restrict__ out6, double* __restrict__ tot4) {
+                                                     double* __restrict__ out6, double* __restrict__ tot4,
+                                                     double* __restrict__ out8) {
     for (int c = item0(); c < n_cells; c += istride()) {
         const LevelDesc& L = lvs[cell_lev[c]];
         const size_t row = (size_t)cell_slot[c] * L.stride;
@@ -709,6 +710,14 @@ __global__ __launch_bounds__(BS) void k_cell_moments(const LevelDesc* __restrict
             if (out6) {
                 double* o = out6 + 6 * (size_t)c;
                 o[0] = rho; o[1] = u; o[2] = v; o[3] = T; o[4] = f * qx; o[5] = f * qy;
+            }
+            if (out8) {
+                // (rho, u, v, T, qx, qy, sigma_xx, sigma_xy): deviatoric stress from
+                // P_ab = sum w c_a c_b g, sigma_xx = P_xx - p
+                double* o = out8 + 8 * (size_t)c;
+                o[0] = rho; o[1] = u; o[2] = v; o[3] = T; o[4] = f * qx; o[5] = f * qy;
+                o[6] = (m[3] - rho * u * u) - rho * ph.R * T;
+                o[7] = m[4] - rho * u * v;
             }
             if (tot4) {
                 const double V = geom[c].vol;
@@ -874,10 +883,10 @@ hipError_t launch_update(int prec, hipStream_t st, const LevelDesc* lv, const in
 
 hipError_t launch_cell_moments(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
                                const int* cell_slot, int n_cells, const CellGeom* geom, Phys ph, double* out6,
-                               double* tot4) {
+                               double* tot4, double* out8) {
     if (n_cells <= 0) return hipSuccess;
     MLVS_DISPATCH(prec, k_cell_moments, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
-                  geom, ph, out6, tot4);
+                  geom, ph, out6, tot4, out8);
     return hipGetLastError();
 }
 
@@ -1177,10 +1186,12 @@ __global__ __launch_bounds__(BS, 4) void k_criterion(const LevelDesc* __restrict
                                                   const double* __restrict__ by, const double* __restrict__ bw,
                                                   int nx, int ny, double C_split, double C_merge, double eps_merge,
                                                   int flux_test, uint8_t* __restrict__ kout,
-                                                  unsigned long long* __restrict__ hout) {
+                                                  unsigned long long* __restrict__ hout,
+                                                  const int* __restrict__ cell_list) {
     const int nbx = nx / 2, nby = ny / 2, Nb = nbx * nby, Nbase = nx * ny;
     const int n8x = nbx / 4, n8y = nby / 4, n4x = nbx / 2, n4y = nby / 2;
-    for (int c = item0(); c < n_cells; c += istride()) {
+    for (int ci = item0(); ci < n_cells; ci += istride()) {
+        const int c = cell_list ? cell_list[ci] : ci;
         const int lev = cell_lev[c];
         const LevelDesc& L = lvs[lev];
         const size_t row = (size_t)cell_slot[c] * L.stride;
@@ -1295,11 +1306,11 @@ hipError_t launch_criterion(int prec, hipStream_t st, const LevelDesc* lv, const
                             int n_cells, const int* pt_of_base_all, const int* pt_off, const uint8_t* kappa_all,
                             const double* bxi_x, const double* bxi_y, const double* bw, int nx, int ny,
                             double C_split, double C_merge, double eps_merge, int flux_test, uint8_t* kappa_out,
-                            unsigned long long* hash_out) {
+                            unsigned long long* hash_out, const int* cell_list) {
     if (n_cells <= 0) return hipSuccess;
     MLVS_DISPATCH(prec, k_criterion, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
                   pt_of_base_all, pt_off, kappa_all, bxi_x, bxi_y, bw, nx, ny, C_split, C_merge, eps_merge, flux_test,
-                  kappa_out, hash_out);
+                  kappa_out, hash_out, cell_list);
     return hipGetLastError();
 }
 

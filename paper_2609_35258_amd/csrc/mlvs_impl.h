@@ -107,7 +107,7 @@ hipError_t launch_init_eq(int prec, hipStream_t st, const LevelDesc* lv, const i
                           double* params);
 hipError_t launch_cell_moments(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
                                const int* cell_slot, int n_cells, const CellGeom* geom, Phys ph,
-                               double* out6, double* out_tot4);
+                               double* out6, double* out_tot4, double* out8 = nullptr);
 hipError_t launch_sum_rows(hipStream_t st, const double* in, int n, int width, double* out);
 hipError_t launch_remap(int prec, hipStream_t st, const LevelDesc* old_lv, const LevelDesc* new_lv,
                         const RemapItem* items, int n, Phys ph, unsigned long long* neg);
@@ -116,10 +116,29 @@ hipError_t launch_criterion(int prec, hipStream_t st, const LevelDesc* lv, const
                             const int* pt_off, const uint8_t* kappa_all, const double* bxi_x,
                             const double* bxi_y, const double* bw, int nx, int ny,
                             double C_split, double C_merge, double eps_merge, int flux_test,
-                            uint8_t* kappa_out, unsigned long long* hash_out);
+                            uint8_t* kappa_out, unsigned long long* hash_out, const int* cell_list = nullptr);
 hipError_t launch_gather_rows_u8(hipStream_t st, const uint8_t* src, int width, const int* rows, int n,
                                  uint8_t* dst);
 hipError_t launch_compare_rows_u8(hipStream_t st, const uint8_t* all, int width, const int* rep_of_cell,
                                   const uint8_t* reps, int n, unsigned long long* mismatch);
+
+// learned selector (selector.hip)
+int mlp_nparams(int K);
+hipError_t launch_features(hipStream_t st, const double* f8, const int* nbr_cell, const CellGeom* geom, int n,
+                           double R, double T_ref, double mu_ref, double omega, float* out);
+hipError_t launch_mlp_fwd_bwd(hipStream_t st, const float* P, int K, const float* X, const int* y, const int* idx,
+                              int B, float* XN, float* A1, float* A2, float* D1, float* D2, float* D3, float* prob,
+                              float* lossv, double* loss_sum);
+hipError_t launch_mlp_grad(hipStream_t st, int K, int B, const float* XN, const float* A1, const float* A2,
+                           const float* D1, const float* D2, const float* D3, float* G);
+hipError_t launch_adam(hipStream_t st, float* P, const float* G, float* M, float* V, int n, float lr, float b1,
+                       float b2, float eps, int t);
+hipError_t launch_mlp_predict(hipStream_t st, const float* P, int K, const float* X, int B, int bf16, int* cls,
+                              float* prob);
+hipError_t launch_tail_check(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
+                             int n, const int* ptb_all, const int* ptb_off, const uint8_t* kappa_all, const int* pred,
+                             const double* bw, int nx, int ny, double C_split, int* accept);
+hipError_t launch_labels(hipStream_t st, const uint8_t* kcell, int n, int Nb, const uint8_t* kappa_all,
+                         const int* order, int K, int* out);
 
 }  // namespace mlvs

@@ -1,0 +1,129 @@
+"""Learned level selector on the GPU: network forward/backward against the FP64
+oracle, BF16 inference, features and criterion-judged labels against the
+oracle, and a learned adaptation run (trained on solver snapshots, judged by the
+criterion, conservation kept)."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import levels as lv
+from oracle import mlp
+from oracle.solver import AdaptParams
+from oracle.solver import Solver as Oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _m():
+    import paper_2609_35258_amd as m
+    return m
+
+
+def _net(K=4, B=257, seed=3):
+    th = W.mlp_init_params(K, seed)
+    rng = np.random.default_rng(seed + 1)
+    X = rng.normal(size=(B, 10))
+    y = rng.integers(0, K, size=B)
+    th[-20:-10] = rng.normal(size=10) * 0.1
+    th[-10:] = rng.uniform(0.5, 2.0, size=10)
+    return th, X, y
+
+
+def test_network_forward_backward_matches_oracle():
+    K = 4
+    th, X, y = _net(K)
+    th32 = th.astype(np.float32)
+    probs, grad, loss = _m().mlp_eval(th32, K, X.astype(np.float32), y)
+    lo, go, po = mlp.loss_and_grad(th32.astype(np.float64), X.astype(np.float32).astype(np.float64), y, K)
+    assert np.allclose(probs, po, rtol=1e-4, atol=1e-6)
+    assert abs(loss - lo) <= 1e-5 * abs(lo)
+    assert np.max(np.abs(grad - go)) <= 1e-4 * np.max(np.abs(go))
+
+
+def test_bf16_inference_agrees_with_fp32():
+    K = 5
+    th, X, y = _net(K, B=2000, seed=9)
+    c32, p32 = _m().mlp_predict(th, K, X, bf16=False)
+    c16, p16 = _m().mlp_predict(th, K, X, bf16=True)
+    _, po, _ = mlp.forward(th.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64), K)
+    top2 = np.sort(po, axis=1)[:, -2:]
+    clear = (top2[:, 1] - top2[:, 0]) > 1e-4
+    assert np.all(c32[clear] == np.argmax(po, axis=1)[clear])
+    assert np.mean(c16 == c32) > 0.97
+    assert np.max(np.abs(p16 - p32)) < 0.05
+
+
+def test_features_match_oracle():
+    p = W.perturb(W.cylinder(16, 8, Kn=0.1, nv=24, vmax=10.0), seed=5, amp=0.1)
+    o = Oracle(p, compat=4)
+    g = _m().Solver.from_problem(p, compat=4)
+    o.step(); g.step(1)
+    f = o.fields()
+    xi, w = o.vset(0)
+    sig = np.array([mlp.cell_stress(xi, w, o.g[c], f[c, 0], f[c, 1:3], f[c, 3], p.R) for c in range(p.n_cells)])
+    grad = mlp.cell_gradient(o.mesh, f[:, 0])
+    ref = mlp.features(f[:, 0], f[:, 1], f[:, 2], f[:, 3], f[:, 4], f[:, 5], sig[:, 0], sig[:, 1], grad,
+                       o.mesh.vol, p.R, p.T_ref, o.mu(f[:, 3]))
+    got = g.features()
+    assert np.allclose(got, ref, rtol=2e-5, atol=2e-6)
+    g.close()
+
+
+def _catalogue_problem(seed=4):
+    p = W.perturb(W.periodic_box(12, 6, Lx=1.0, Ly=0.5, Kn=0.05, nv=32, vmax=5.0, kind="sine", amp=0.5), seed=seed)
+    o1 = Oracle(p, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 1e-3, 0.03, True, 100))
+    kap, cl = lv.cluster_masks(o1.criterion_masks(), 0.03)
+    return p, kap, cl
+
+
+def test_labels_match_oracle():
+    p, kap, cl = _catalogue_problem()
+    o = Oracle(p, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 1e-3, 0.03, True, 100))
+    o.set_levels(kap, cl)
+    g = _m().Solver.from_problem(p, compat=4, adapt=dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=1e-3,
+                                                         tau_clust=0.03, flux_test=True, interval=0))
+    g.set_levels(np.stack(kap), cl)
+    ko = o.criterion_masks()
+    lab_o = mlp.label_from_masks(ko, np.stack(kap), [L.N for L in o.levels])
+    lab_g = g.labels()
+    assert np.mean(lab_g == lab_o) > 0.98, (lab_g, lab_o)
+    g.close()
+
+
+def test_learned_adaptation_run():
+    m = _m()
+    p = W.perturb(W.periodic_box(24, 8, Lx=1.0, Ly=1.0 / 3, Kn=0.05, nv=32, vmax=5.0, kind="sine", amp=0.5), seed=8)
+    # adaptation only when called: one full adaptation builds the catalogue, which
+    # then stays frozen while snapshots are collected and during learned adaptation
+    ap = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=1e-3, tau_clust=0.05, flux_test=True, interval=0)
+    g = m.Solver.from_problem(p, compat=4, adapt=ap)
+    g.step(2)
+    g.adapt()
+    K = len(g.level_info()[0])
+    assert K >= 2
+    X, Y = [], []
+    for snap in range(12):                      # snapshots in time order
+        g.step(5)
+        X.append(g.features())
+        Y.append(g.labels())
+    X = np.concatenate(X)
+    Y = np.concatenate(Y)
+    ok = Y >= 0
+    params, rep = m.mlp_train(W.mlp_init_params(K, 0), K, X[ok], Y[ok], epochs=40, batch=256, lr=3e-3,
+                              val_frac=0.2, seed=1)
+    print("training", rep, flush=True)
+    assert rep["loss_last"] < rep["loss_first"]
+    assert rep["val_acc"] > 0.6
+    t0 = g.totals()
+    g.selector_set(params, K)
+    reps = []
+    for _ in range(3):
+        t = time.perf_counter()
+        reps.append(g.adapt())
+        g.step(5)
+    print("learned adaptations", reps, flush=True)
+    assert np.max(np.abs(g.totals() - t0)) < 1e-12
+    assert all(r["n_fallback"] < g.n_cells for r in reps)
+    g.close()

@@ -245,3 +245,15 @@ def striped_levels(ni: int, nj: int, n_levels: int, axis: int = 0) -> np.ndarray
     idx = i if axis == 0 else j
     n = ni if axis == 0 else nj
     return (idx * n_levels // n).ravel().astype(np.int32)
+
+
+def mlp_init_params(K: int, seed: int, H: int = 64, NF: int = 10) -> np.ndarray:
+    """Seeded He-normal initial weights of the 10 -> H -> H -> K selector, zero
+    biases, identity normalisation (mean 0, std 1); flat layout
+    W1 [H][NF], b1, W2 [H][H], b2, W3 [K][H], b3, mean [NF], std [NF]."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.normal(size=(H, NF)) * math.sqrt(2.0 / NF)
+    W2 = rng.normal(size=(H, H)) * math.sqrt(2.0 / H)
+    W3 = rng.normal(size=(K, H)) * math.sqrt(2.0 / H)
+    return np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), W3.ravel(), np.zeros(K),
+                           np.zeros(NF), np.ones(NF)])
