@@ -98,6 +98,86 @@ def cpu_baseline(p, sample_steps=2, sample_cells=256):
                          t_crit, ADAPT["interval"])}
 
 
+LEARNED_ADAPT = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, flux_test=True, interval=0)
+
+
+def learned_vs_criterion(precision=32, n_theta=64, n_r=32, nv=41, warm=200, snaps=16, every=10, rounds=6):
+    """Learned vs criterion adaptation on the same GPU.
+
+    Supersonic cylinder (Ma 3, Kn 0.1, Shakhov) reduced to n_theta x n_r cells
+    and an nv^2 Newton-Cotes base grid.  A criterion run builds the catalogue
+    (one full adaptation after `warm` steps) and collects (features, criterion
+    label) snapshots every `every` steps; the network is trained on the GPU on
+    the earlier 80% of the snapshots.  A second solver starts from the same
+    state and levels with the selector on.  Both then run `rounds` rounds of
+    `every` steps plus one adaptation: full criterion adaptation (the paper's
+    method, catalogue rebuilt) vs learned adaptation (frozen catalogue, tail-mass
+    check, criterion on rejected cells only)."""
+    import torch
+    import paper_2609_35258_amd as m
+    p = W.cylinder(n_theta, n_r, Kn=0.1, nv=nv, vmax=10.0)
+    crit = m.Solver.from_problem(p, precision=precision, compat=4, adapt=LEARNED_ADAPT)
+    crit.step(warm)
+    crit.adapt()
+    K = len(crit.level_info()[0])
+    X, Y = [], []
+    for _ in range(snaps):
+        crit.step(every)
+        X.append(crit.features())
+        Y.append(crit.labels())
+    X = np.concatenate(X)
+    Y = np.concatenate(Y)
+    ok = Y >= 0
+    params, trep = m.mlp_train(W.mlp_init_params(K, 0), K, X[ok], Y[ok], epochs=30, batch=1024, lr=3e-3,
+                               val_frac=0.2, seed=0)
+    lrn = m.Solver.from_problem(p, precision=precision, compat=4, adapt=LEARNED_ADAPT)
+    lrn.set_levels(np.stack([crit.level_kappa(k) for k in range(K)]), crit.cell_levels())
+    st = crit.get_state()
+    lrn.set_state([g for g, _ in st], [h for _, h in st])
+    lrn.selector_set(params, K)
+    n = p.n_cells
+    out = {"workload": "cylinder %dx%d, Ma 3, Kn 0.1, %dx%d Newton-Cotes on [-10,10]^2, fp%d, C_split 0.01, "
+                       "C_merge 0.005, eps_merge 2e-5, tau_clust 0.05" % (n_theta, n_r, nv, nv, precision),
+           "K": K, "samples": int(ok.sum()), "train": {k: trep[k] for k in ("loss_first", "loss_last", "train_acc",
+                                                                           "val_acc", "ms")}}
+    mis, fb, t_c, t_l, run_c, run_l = [], [], [], [], 0.0, 0.0
+    for _ in range(rounds):
+        feats, lab = lrn.features(), lrn.labels()
+        pred, _ = m.mlp_predict(params, K, feats, bf16=True)
+        v = lab >= 0
+        mis.append(float(np.mean(pred[v] != lab[v])))
+        for s, acc, tl in ((crit, t_c, "c"), (lrn, t_l, "l")):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = s.adapt()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s.step(every)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            acc.append(1e3 * (t1 - t0))
+            if tl == "c":
+                run_c += t2 - t0
+            else:
+                run_l += t2 - t0
+                fb.append(rep["n_fallback"] / n)
+    fc, fl = crit.moments(), lrn.moments()
+    err = {}
+    for k, name in ((0, "rho"), (1, "u"), (3, "T")):
+        err[name] = float(np.sqrt(np.sum((fl[:, k] - fc[:, k]) ** 2) / np.sum(fc[:, k] ** 2)))
+    npc, ncc, _ = crit.level_info()
+    npl, ncl, _ = lrn.level_info()
+    out.update({"misclassification": float(np.mean(mis)), "fallback_rate": float(np.mean(fb)),
+                "criterion_adapt_ms": float(np.median(t_c)), "learned_adapt_ms": float(np.median(t_l)),
+                "adapt_speedup": float(np.median(t_c) / np.median(t_l)),
+                "end_to_end_s": {"criterion": run_c, "learned": run_l},
+                "nbar": {"criterion": float(np.sum(npc * ncc) / n), "learned": float(np.sum(npl * ncl) / n)},
+                "learned_vs_criterion_rel_l2": err})
+    crit.close()
+    lrn.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +189,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uvs", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
@@ -174,6 +255,8 @@ def main():
                       "time_to_solution_ratio": t_uvs / t_mlvs, "memory_ratio": mem_u / mem_m,
                       "mlvs_vs_uvs_rel_l2": err}
         u.close()
+    if not args.no_learned:
+        out["learned"] = learned_vs_criterion()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)

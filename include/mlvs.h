@@ -196,10 +196,11 @@ mlvs_status mlvs_set_state(mlvs_ctx ctx, const double* g, const double* h);
 /* Time step in use, mesh hmin, and counts: n_cells, N_b (2x2 blocks). */
 mlvs_status mlvs_info(mlvs_ctx ctx, double* dt, int64_t* n_cells, int32_t* n_blocks, int32_t* n_base);
 
-/* Launch variants of a stage (kernels instantiated for several minimum
- * occupancies): *count variants exist for `stage` (numbering as in
- * mlvs_time_stage); mlvs_set_variant selects one for subsequent launches.
- * Used by the autotuner; results do not depend on the variant. */
+/* Launch variants of a stage (kernels instantiated for several pairs of
+ * velocity points per lane per load batch and minimum occupancy): *count
+ * variants exist for `stage` (numbering as in mlvs_time_stage);
+ * mlvs_set_variant selects one for subsequent launches.  Used by the
+ * autotuner; results do not depend on the variant. */
 mlvs_status mlvs_variants(int stage, int* count);
 mlvs_status mlvs_set_variant(mlvs_ctx ctx, int stage, int variant);
 
@@ -218,9 +219,11 @@ mlvs_status mlvs_counters(mlvs_ctx ctx, int64_t* steps, double* cell_updates, do
 /* Profiling: launch one stage of the step `reps` times on the context stream,
  * bracketed by two HIP events recorded on that stream, and return the mean
  * duration per launch in milliseconds.  stage: 0 cell, 1 neighbour mapping,
- * 2 face reconstruction (same-level and boundary faces), 3 face flux (same
- * faces), 4 cross-level faces, 5 update (advances g~, h~ once per
- * repetition), 6 criterion.  Synchronises. */
+ * 2 face reconstruction (same-level and boundary faces), 3 face target (same
+ * faces: face state, corrected target, recovery weights), 4 cross-level
+ * faces, 5 update (fluxes and new state; the state is saved before and put
+ * back after the timed launches), 6 criterion.  Needs a step taken since the
+ * last level change for meaningful inputs.  Synchronises. */
 mlvs_status mlvs_time_stage(mlvs_ctx ctx, int stage, int reps, double* ms_per_launch);
 
 /* Item counts of a stage's launch (cells, ghost rows, faces, ...) and the

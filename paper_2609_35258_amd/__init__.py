@@ -430,7 +430,7 @@ class Solver:
         _check(lib().mlvs_counters(self.h, ctypes.byref(st), ctypes.byref(up), ctypes.byref(ip), ctypes.byref(ad)))
         return {"steps": st.value, "cell_updates": up.value, "iface_points": ip.value, "adaptations": ad.value}
 
-    STAGES = {"cell": 0, "ghost": 1, "face_rec": 2, "face_flux": 3, "xface": 4, "update": 5, "criterion": 6}
+    STAGES = {"cell": 0, "ghost": 1, "face_rec": 2, "face_target": 3, "xface": 4, "update": 5, "criterion": 6}
 
     def time_stage(self, stage, reps: int = 10):
         """Mean ms per launch of one stage, timed with HIP events on the context stream."""

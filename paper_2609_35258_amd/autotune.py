@@ -15,7 +15,7 @@ import json
 import os
 from typing import Dict, Iterable, Optional
 
-TUNABLE = ("cell", "face_rec", "face_flux", "xface")
+TUNABLE = ("cell", "face_rec", "face_target", "xface", "update")
 
 
 def default_cache() -> str:

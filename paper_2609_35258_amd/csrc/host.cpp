@@ -537,6 +537,9 @@ struct mlvs_ctx_s {
     int *d_cell_lev = nullptr, *d_cell_slot = nullptr, *d_cell_nbr = nullptr, *d_cell_frow = nullptr;
     CellGeom* d_geom = nullptr;
     double* d_params = nullptr;
+    double* d_cmom = nullptr;          // [n_cells][NMOM] raw moments of the stored state
+    double* d_fpar = nullptr;          // [faces + boundary faces][NFP] face records
+    bool mom_valid = false;            // d_cmom matches the stored state
     BCDev* d_bcs = nullptr;
     LevelDesc* d_lv = nullptr;
     FaceItem* d_faces = nullptr; int n_faces = 0;    // interior same-level faces, then boundary faces
@@ -627,7 +630,7 @@ void free_items(mlvs_ctx c) {
     c->item_allocs.clear();
     for (auto& L : c->ifaces) free_level(c, *L);
     c->ifaces.clear();
-    c->d_faces = nullptr; c->d_fmom = nullptr; c->d_ghosts = nullptr; c->d_xfaces = nullptr;
+    c->d_faces = nullptr; c->d_fmom = nullptr; c->d_fpar = nullptr; c->d_ghosts = nullptr; c->d_xfaces = nullptr;
     c->d_lv = nullptr;
     c->n_faces = c->n_bfaces = c->n_ghosts = c->n_xfaces = 0;
 }
@@ -679,7 +682,9 @@ void build_items(mlvs_ctx c) {
         tab_of[key] = d;
         return d;
     };
-    auto face_code = [](int row, bool neg) { return 2 * row + (neg ? 1 : 0); };
+    // face codes read by the update: 4 x + 2 final + neg, x = face item (final = 0)
+    // or the level row of a final cross-level flux (final = 1)
+    auto face_code = [](int x, bool final_flux, bool neg) { return 4 * x + (final_flux ? 2 : 0) + (neg ? 1 : 0); };
     // neighbour codes and ghost rows
     for (int cc = 0; cc < n; ++cc)
         for (int k = 0; k < 4; ++k) {
@@ -718,9 +723,9 @@ void build_items(mlvs_ctx c) {
             it.L = F.L; it.R = F.R; it.lev = lL; it.row = rows[lL]++;
             it.nx = F.nx; it.ny = F.ny; it.area = F.area;
             it.dLx = F.dLx; it.dLy = F.dLy; it.dRx = F.dRx; it.dRy = F.dRy;
+            cell_frow[4 * F.L + kL] = face_code((int)faces.size(), false, false);
+            cell_frow[4 * F.R + kR] = face_code((int)faces.size(), false, true);
             faces.push_back(it);
-            cell_frow[4 * F.L + kL] = face_code(it.row, false);
-            cell_frow[4 * F.R + kR] = face_code(it.row, true);
         } else {
             ++n_cross;
             XFaceItem it{};
@@ -738,8 +743,8 @@ void build_items(mlvs_ctx c) {
             it.levI = iidx;
             it.scratch = I->n_rows++;
             xitems.push_back(it);
-            cell_frow[4 * F.L + kL] = face_code(it.rowA, false);
-            cell_frow[4 * F.R + kR] = face_code(it.rowB, true);
+            cell_frow[4 * F.L + kL] = face_code(it.rowA, true, false);
+            cell_frow[4 * F.R + kR] = face_code(it.rowB, true, true);
         }
     }
     for (auto& it : xitems) {
@@ -759,11 +764,11 @@ void build_items(mlvs_ctx c) {
         FaceItem it{};
         it.L = F.L; it.R = -1 - F.bc; it.lev = lc; it.row = rows[lc]++;
         it.nx = F.nx; it.ny = F.ny; it.area = F.area; it.dLx = F.dLx; it.dLy = F.dLy;
-        bfaces.push_back(it);
         int kk = -1;
         for (int k = 0; k < 4; ++k)
             if (M.bface_of_cell[4 * F.L + k] == (int)b) kk = k;
-        cell_frow[4 * F.L + kk] = face_code(it.row, false);
+        cell_frow[4 * F.L + kk] = face_code((int)(faces.size() + bfaces.size()), false, false);
+        bfaces.push_back(it);
     }
     // row buffers
     for (int l = 0; l < K; ++l) {
@@ -799,6 +804,8 @@ void build_items(mlvs_ctx c) {
     c->d_faces = upload_item(c, faces);
     c->d_fmom = static_cast<double*>(c->dm.alloc(sizeof(double) * 12 * std::max<size_t>(faces.size(), 1)));
     c->item_allocs.push_back(c->d_fmom);
+    c->d_fpar = static_cast<double*>(c->dm.alloc(sizeof(double) * NFP * std::max<size_t>(faces.size(), 1)));
+    c->item_allocs.push_back(c->d_fpar);
     c->d_ghosts = upload_item(c, gitems); c->n_ghosts = (int)gitems.size();
     c->d_xfaces = upload_item(c, xitems); c->n_xfaces = (int)xitems.size();
     c->d_cell_frow = upload_item(c, cell_frow);
@@ -830,6 +837,15 @@ void assign_slots(mlvs_ctx c) {
 void sync(mlvs_ctx c) { hip_check(hipStreamSynchronize(c->st), "stream synchronize"); }
 
 void do_step(mlvs_ctx c);
+// The cell stage reads the raw moments of the stored state from d_cmom; the
+// update keeps them current.  After any other write of the state they are
+// recomputed once, outside the step (and outside a captured step graph).
+void ensure_moments(mlvs_ctx c) {
+    if (c->mom_valid) return;
+    hip_check(launch_raw_moments(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, c->mesh.n_cells,
+                                 c->d_params, c->d_cmom), "moments launch");
+    c->mom_valid = true;
+}
 hipError_t launch_stage(mlvs_ctx c, int stage);
 hipError_t launch_step_kernels(mlvs_ctx c);
 
@@ -905,6 +921,7 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
     for (auto& L : old) free_level(c, *L);
     build_items(c);
     sync(c);
+    c->mom_valid = false;
     return changed;
 }
 
@@ -1470,6 +1487,7 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         c->d_bcs = upload(c->dm, bd, c->st);
         c->d_params = static_cast<double*>(c->dm.alloc(sizeof(double) * NPARAM * c->mesh.n_cells));
         hip_check(hipMemsetAsync(c->d_params, 0, sizeof(double) * NPARAM * c->mesh.n_cells, c->st), "memset");
+        c->d_cmom = static_cast<double*>(c->dm.alloc(sizeof(double) * NMOM * c->mesh.n_cells));
         c->d_neg = static_cast<unsigned long long*>(c->dm.alloc(8));
         hip_check(hipMemsetAsync(c->d_neg, 0, 8, c->st), "memset");
         // one level: the base grid itself
@@ -1510,6 +1528,7 @@ mlvs_status mlvs_init_equilibrium(mlvs_ctx c, const double* st) {
         sync(c);
         c->dm.release(d);
         c->state_ready = true;
+        c->mom_valid = false;
         c->step_count = 0;
     });
 }
@@ -1564,7 +1583,7 @@ mlvs_status mlvs_info(mlvs_ctx c, double* dt, int64_t* n_cells, int32_t* n_block
 mlvs_status mlvs_variants(int stage, int* count) {
     return guarded([&] {
         if (!count || stage < 0 || stage > 6) fail(MLVS_E_ARG, "bad arguments");
-        *count = (stage == 0 || stage == 2 || stage == 3 || stage == 4) ? variant_count() : 1;
+        *count = (stage == 0 || stage == 2 || stage == 3 || stage == 4 || stage == 5) ? variant_count() : 1;
     });
 }
 
@@ -1604,14 +1623,31 @@ mlvs_status mlvs_time_stage(mlvs_ctx c, int stage, int reps, double* ms) {
         if (!c || !ms || reps < 1 || stage < 0 || stage > 6) fail(MLVS_E_ARG, "bad arguments");
         if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
         if (stage == 6 && !c->adaptive) fail(MLVS_E_STATE, "criterion needs adaptation parameters");
-        // the face-flux stage overwrites the rows the reconstruction stage fills:
-        // rebuild them before each timed launch, outside the timed window
+        ensure_moments(c);
+        // every stage but the update only rewrites its own outputs; the update
+        // advances the state, which is saved here and put back afterwards
+        std::vector<std::pair<void*, void*>> saved;    // (live buffer, copy)
+        std::vector<size_t> saved_bytes;
+        if (stage == 5) {
+            auto keep = [&](void* p, size_t nb) {
+                if (!p || nb == 0) return;
+                void* q = c->dm.alloc(nb);
+                hip_check(hipMemcpyAsync(q, p, nb, hipMemcpyDeviceToDevice, c->st), "D2D");
+                saved.emplace_back(p, q);
+                saved_bytes.push_back(nb);
+            };
+            for (auto& L : c->levels) {
+                const size_t nb = (size_t)L->n_cells * L->stride * c->elt();
+                keep(L->g, nb);
+                keep(L->h, nb);
+            }
+            keep(c->d_cmom, sizeof(double) * NMOM * (size_t)c->mesh.n_cells);
+        }
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "event");
         hip_check(hipEventCreate(&e1), "event");
         double tot = 0.0;
         for (int r = 0; r < reps; ++r) {
-            if (stage == 3) hip_check(launch_stage(c, 2), "stage launch");
             hip_check(hipEventRecord(e0, c->st), "event record");
             if (stage == 6) run_criterion(c);
             else hip_check(launch_stage(c, stage), "stage launch");
@@ -1623,6 +1659,12 @@ mlvs_status mlvs_time_stage(mlvs_ctx c, int stage, int reps, double* ms) {
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        for (size_t k = 0; k < saved.size(); ++k) {
+            hip_check(hipMemcpyAsync(saved[k].first, saved[k].second, saved_bytes[k], hipMemcpyDeviceToDevice, c->st),
+                      "D2D");
+        }
+        sync(c);
+        for (auto& pr : saved) c->dm.release(pr.second);
         *ms = tot / reps;
     });
 }
@@ -1738,6 +1780,7 @@ mlvs_status mlvs_set_f(mlvs_ctx c, int64_t cell, const double* g, const double* 
         if (!c || !g || !h || cell < 0 || cell >= c->mesh.n_cells) fail(MLVS_E_ARG, "bad arguments");
         copy_cell(c, cell, nullptr, nullptr, g, h);
         c->state_ready = true;
+        c->mom_valid = false;
     });
 }
 
@@ -1794,6 +1837,7 @@ mlvs_status mlvs_set_state(mlvs_ctx c, const double* g, const double* h) {
         if (!c || !g || !h) fail(MLVS_E_ARG, "null argument");
         bulk_state(c, nullptr, nullptr, g, h);
         c->state_ready = true;
+        c->mom_valid = false;
     });
 }
 
@@ -1846,6 +1890,7 @@ void do_step(mlvs_ctx c) {
     if (c->adaptive && c->ap.interval > 0 && c->step_count % c->ap.interval == 0) {
         if (mlvs_adapt(c, nullptr) != MLVS_OK) throw Fail{MLVS_E_STATE, g_last_error};
     }
+    ensure_moments(c);
     if (c->use_graph) {
         if (!c->gexec) {
             hip_check(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -1867,42 +1912,29 @@ void do_step(mlvs_ctx c) {
 }
 
 hipError_t launch_step_kernels(mlvs_ctx c) {
-    const int n = c->mesh.n_cells;
-    hipError_t e;
-    if ((e = launch_cell_prep(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->ph, c->d_params,
-                                 c->variant[0])))
-        return e;
-    if ((e = launch_ghost(c->prec, c->st, c->d_lv, c->d_ghosts, c->n_ghosts, c->d_cell_lev, c->d_cell_slot,
-                          c->d_params, c->ph, c->d_neg)))
-        return e;
-    if ((e = launch_face_rec(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces + c->n_bfaces, c->d_cell_slot,
-                             c->d_cell_nbr, c->d_geom, c->d_params, c->ph, c->d_fmom, c->variant[2])))
-        return e;
-    if ((e = launch_face_flux(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces + c->n_bfaces, c->d_cell_slot,
-                              c->d_params, c->d_bcs, c->ph, c->d_fmom, c->variant[3])))
-        return e;
-    if ((e = launch_xface(c->prec, c->st, c->d_lv, c->d_xfaces, c->n_xfaces, c->d_cell_slot, c->d_cell_nbr,
-                          c->d_geom, c->d_params, c->ph, c->d_neg, c->variant[4])))
-        return e;
-    return launch_update(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom, c->d_cell_frow,
-                         c->ph);
+    for (int stage = 0; stage <= 5; ++stage) {
+        const hipError_t e = launch_stage(c, stage);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_stage(mlvs_ctx c, int stage) {
     const int n = c->mesh.n_cells;
     switch (stage) {
     case 0: return launch_cell_prep(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->ph, c->d_params,
-                                 c->variant[0]);
+                                    c->d_cmom, c->variant[0]);
     case 1: return launch_ghost(c->prec, c->st, c->d_lv, c->d_ghosts, c->n_ghosts, c->d_cell_lev, c->d_cell_slot,
                                 c->d_params, c->ph, c->d_neg);
     case 2: return launch_face_rec(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces + c->n_bfaces, c->d_cell_slot,
                                    c->d_cell_nbr, c->d_geom, c->d_params, c->ph, c->d_fmom, c->variant[2]);
-    case 3: return launch_face_flux(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces + c->n_bfaces, c->d_cell_slot,
-                                    c->d_params, c->d_bcs, c->ph, c->d_fmom, c->variant[3]);
+    case 3: return launch_face_target(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces + c->n_bfaces, c->d_params,
+                                      c->d_bcs, c->ph, c->d_fmom, c->d_fpar, c->variant[3]);
     case 4: return launch_xface(c->prec, c->st, c->d_lv, c->d_xfaces, c->n_xfaces, c->d_cell_slot, c->d_cell_nbr,
                                 c->d_geom, c->d_params, c->ph, c->d_neg, c->variant[4]);
     case 5: return launch_update(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom,
-                                 c->d_cell_frow, c->ph);
+                                 c->d_cell_frow, c->d_faces, c->d_fpar, c->d_params, c->ph, c->d_cmom,
+                                 c->variant[5]);
     default: return hipErrorInvalidValue;
     }
 }

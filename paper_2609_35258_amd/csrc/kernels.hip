@@ -20,13 +20,34 @@ constexpr int WL = 64;              // lanes per wavefront
 constexpr int MAXW = BS / WL;       // waves (items) per workgroup
 constexpr int RED_MAX = 32;         // largest reduction width
 
+constexpr int NXCD = 8;             // accelerator complex dies (each with its own L2)
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WL - 1); }
+// Workgroups are dealt to the XCDs round-robin.  Renumber them so that each
+// XCD works through one contiguous range of items: neighbouring faces and
+// cells share stencil rows, which then meet in the same L2.  Grids are
+// launched as multiples of NXCD, so the renumbering is a bijection.
+__device__ __forceinline__ int wg_index() {
+    const int per = gridDim.x / NXCD;
+    return (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+}
 // The wave index is uniform within a wavefront; readfirstlane tells the
 // compiler so, and every per-item quantity then lives in scalar registers.
 __device__ __forceinline__ int item0() {
-    return __builtin_amdgcn_readfirstlane((int)(blockIdx.x * MAXW + (threadIdx.x >> 6)));
+    return __builtin_amdgcn_readfirstlane((int)(wg_index() * MAXW + (threadIdx.x >> 6)));
 }
 __device__ __forceinline__ int istride() { return gridDim.x * MAXW; }
+
+// A value equal on every lane, moved to scalar registers.
+__device__ __forceinline__ double uni(double x) {
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ float uni(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
 
 // Sum NV doubles over the wavefront; every lane receives the totals.
 template <int NV>
@@ -105,75 +126,109 @@ __device__ __forceinline__ void raw_to_state(const double* m, double u0, double 
     v = v0 + vp;
 }
 
+// Reduced Shakhov target (Eq. g_h_eq_Pr) in evaluation form.  With
+// c = xi - u:  g = rn e^{-c^2/2RT} (1 + X.c (c^2/RT - D - 2)),
+// h = RT rn e^{-c^2/2RT} (cK + X.c ((c^2/RT - D) cK - 2K)), X = (1-Pr) q/(5 p RT),
+// cK = K + 3 - D; the compatibility factor 1 + a . [1, xi_x, xi_y, E_xi]
+// (Eq. gh_model_correction) is folded into b0 + b1 xi_x + b2 xi_y + b3 |xi|^2.
 template <typename C>
 struct Eq {
-    C rn, ux, uy, i2RT, iRT, RT, X, qx, qy, cK, Dp2, Dd, K2;
-    C a0, a1, a2, a3, Ec0;
+    C rn, ux, uy, i2RT, iRT, RT, Xqx, Xqy;
+    C b0, b1, b2, b3;
+    C cK, Dp2, Dd, K2;
     bool corr;
 };
 
-template <typename C>
-__device__ __forceinline__ Eq<C> make_eq(double rho, double u, double v, double T, double qx, double qy,
-                                         const double* a, const Phys& ph) {
-    Eq<C> e;
+__device__ __forceinline__ Eq<double> make_eq(double rho, double u, double v, double T, double qx, double qy,
+                                              const double* a, const Phys& ph) {
+    Eq<double> e;
     const double RT = ph.R * T;
     const double D = ph.D;
-    e.rn = (C)(ph.D == 2 ? rho / (2.0 * M_PI * RT) : rho / sqrt(2.0 * M_PI * RT));
-    e.ux = (C)u; e.uy = (C)v;
-    e.i2RT = (C)(1.0 / (2.0 * RT));
-    e.iRT = (C)(1.0 / RT);
-    e.RT = (C)RT;
-    e.X = (C)((1.0 - ph.Pr) / (5.0 * rho * RT * RT));
-    e.qx = (C)qx; e.qy = (C)qy;
-    e.cK = (C)(ph.K + 3.0 - D);
-    e.Dp2 = (C)(D + 2.0);
-    e.Dd = (C)D;
-    e.K2 = (C)(2.0 * ph.K);
+    e.rn = ph.D == 2 ? rho / (2.0 * M_PI * RT) : rho / sqrt(2.0 * M_PI * RT);
+    e.ux = u; e.uy = v;
+    e.i2RT = 1.0 / (2.0 * RT);
+    e.iRT = 1.0 / RT;
+    e.RT = RT;
+    const double X = (1.0 - ph.Pr) / (5.0 * rho * RT * RT);
+    e.Xqx = X * qx; e.Xqy = X * qy;
+    e.cK = ph.K + 3.0 - D;
+    e.Dp2 = D + 2.0;
+    e.Dd = D;
+    e.K2 = 2.0 * ph.K;
     e.corr = (a != nullptr);
-    e.a0 = a ? (C)a[0] : C(0); e.a1 = a ? (C)a[1] : C(0);
-    e.a2 = a ? (C)a[2] : C(0); e.a3 = a ? (C)a[3] : C(0);
-    e.Ec0 = (C)(0.5 * (3.0 - D + ph.K) * RT);
+    const double Ec0 = 0.5 * (3.0 - D + ph.K) * RT;
+    e.b0 = a ? 1.0 + a[0] + a[3] * Ec0 : 1.0;
+    e.b1 = a ? a[1] : 0.0;
+    e.b2 = a ? a[2] : 0.0;
+    e.b3 = a ? 0.5 * a[3] : 0.0;
+    return e;
+}
+
+// Storage-precision copy held in scalar registers (the values are per item).
+template <typename C>
+__device__ __forceinline__ Eq<C> eq_cast(const Eq<double>& d) {
+    Eq<C> e;
+    e.rn = uni((C)d.rn); e.ux = uni((C)d.ux); e.uy = uni((C)d.uy); e.i2RT = uni((C)d.i2RT);
+    e.iRT = uni((C)d.iRT); e.RT = uni((C)d.RT); e.Xqx = uni((C)d.Xqx); e.Xqy = uni((C)d.Xqy);
+    e.b0 = uni((C)d.b0); e.b1 = uni((C)d.b1); e.b2 = uni((C)d.b2); e.b3 = uni((C)d.b3);
+    e.cK = (C)d.cK; e.Dp2 = (C)d.Dp2; e.Dd = (C)d.Dd; e.K2 = (C)d.K2;
+    e.corr = d.corr;
     return e;
 }
 
 __device__ __forceinline__ float dexp(float x) { return expf(x); }
 __device__ __forceinline__ double dexp(double x) { return exp(x); }
 
-// Reduced Shakhov target at velocity (x, y) (Eq. g_h_eq_Pr), optionally times
-// the compatibility factor 1 + a . [1, x, y, E_xi] (Eq. gh_model_correction).
 template <typename C>
 __device__ __forceinline__ void eq_eval(const Eq<C>& e, C x, C y, C& g, C& h) {
     const C cx = x - e.ux, cy = y - e.uy;
     const C c2 = cx * cx + cy * cy;
     const C ge = e.rn * dexp(-c2 * e.i2RT);
-    const C Xc = e.X * (cx * e.qx + cy * e.qy);
+    const C Xc = cx * e.Xqx + cy * e.Xqy;
     const C c2r = c2 * e.iRT;
     g = ge * (C(1) + Xc * (c2r - e.Dp2));
     h = ge * e.RT * (e.cK + Xc * ((c2r - e.Dd) * e.cK - e.K2));
     if (e.corr) {
-        const C f = C(1) + e.a0 + e.a1 * x + e.a2 * y + e.a3 * (e.Ec0 + C(0.5) * (x * x + y * y));
+        const C f = e.b0 + e.b1 * x + e.b2 * y + e.b3 * (x * x + y * y);
         g *= f;
         h *= f;
     }
 }
 
+// Velocity points of one item are visited in chunks of U points per lane:
+// every load of a chunk is issued before any of its arithmetic, so U loads
+// per lane are in flight.  Indices past the end are clamped to the last point
+// (a valid address) and their weight is zero.
+__device__ __forceinline__ int clampi(int i, int N) { return i < N ? i : N - 1; }
+
 // Compatibility correction (Sec. 3.3.1): assemble A and the moment defect of
 // the uncorrected target over the level, solve, return a[4] (a[2] = 0 in 1-D).
-template <typename S>
-__device__ __forceinline__ void compat_solve(const LevelDesc& L, const Eq<S>& eu, double rho, double u, double v, double T,
-                             const Phys& ph, double* a_out) {
+template <typename S, int U>
+__device__ __forceinline__ void compat_solve(const LevelDesc& L, const Eq<S>& eu, double rho, double u, double v,
+                                             double T, const Phys& ph, double* a_out) {
     double s[13];
 #pragma unroll
     for (int k = 0; k < 13; ++k) s[k] = 0.0;
-    for (int i = lane_id(); i < L.N; i += WL) {
-        const double x = L.xi_x[i], y = L.xi_y[i], w = L.w[i];
-        S g, h;
-        eq_eval<S>(eu, (S)x, (S)y, g, h);
-        const double wg = w * (double)g, wh = w * (double)h;
-        const double x2 = x * x + y * y;
-        s[0] += wg; s[1] += wg * x; s[2] += wg * y; s[3] += wg * x * x; s[4] += wg * x * y;
-        s[5] += wg * y * y; s[6] += wg * x * x2; s[7] += wg * y * x2; s[8] += wg * x2 * x2;
-        s[9] += wh; s[10] += wh * x; s[11] += wh * y; s[12] += wh * x2;
+    const int N = L.N;
+    for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
+        double xv[U], yv[U], wv[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int i = i0 + q * WL, ic = clampi(i, N);
+            xv[q] = L.xi_x[ic]; yv[q] = L.xi_y[ic];
+            wv[q] = i < N ? L.w[ic] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const double x = xv[q], y = yv[q];
+            S g, h;
+            eq_eval<S>(eu, (S)x, (S)y, g, h);
+            const double wg = wv[q] * (double)g, wh = wv[q] * (double)h;
+            const double x2 = x * x + y * y;
+            s[0] += wg; s[1] += wg * x; s[2] += wg * y; s[3] += wg * x * x; s[4] += wg * x * y;
+            s[5] += wg * y * y; s[6] += wg * x * x2; s[7] += wg * y * x2; s[8] += wg * x2 * x2;
+            s[9] += wh; s[10] += wh * x; s[11] += wh * y; s[12] += wh * x2;
+        }
     }
     wave_sum<13>(s);
     const double E0 = 0.5 * (3.0 - ph.D + ph.K) * ph.R * T;
@@ -187,7 +242,7 @@ __device__ __forceinline__ void compat_solve(const LevelDesc& L, const Eq<S>& eu
                            E0 * 0.5 * (sx2 + s[9]) + 0.5 * (0.5 * s[8] + 0.5 * s[12])}};
         double b[4] = {rho - s[0], rho * u - s[1], rho * v - s[2], rhoE - 0.5 * (sx2 + s[9])};
         solve_fixed<4>(A, b);
-        a_out[0] = b[0]; a_out[1] = b[1]; a_out[2] = b[2]; a_out[3] = b[3];
+        a_out[0] = uni(b[0]); a_out[1] = uni(b[1]); a_out[2] = uni(b[2]); a_out[3] = uni(b[3]);
     } else {
         double A[3][3] = {{s[0], s[1], E0 * s[0] + 0.5 * sx2},
                           {s[1], s[3], E0 * s[1] + 0.5 * s[6]},
@@ -195,38 +250,44 @@ __device__ __forceinline__ void compat_solve(const LevelDesc& L, const Eq<S>& eu
                            E0 * 0.5 * (sx2 + s[9]) + 0.5 * (0.5 * s[8] + 0.5 * s[12])}};
         double b[3] = {rho - s[0], rho * u - s[1], rhoE - 0.5 * (sx2 + s[9])};
         solve_fixed<3>(A, b);
-        a_out[0] = b[0]; a_out[1] = b[1]; a_out[2] = 0.0; a_out[3] = b[2];
+        a_out[0] = uni(b[0]); a_out[1] = uni(b[1]); a_out[2] = 0.0; a_out[3] = uni(b[2]);
     }
 }
 
+// Eleven raw moments of (g, h) at velocity (x, y) taken about a shift (the
+// layout raw_to_state reads), accumulated in double.
+template <typename S>
+__device__ __forceinline__ void acc_raw(double* m, double w, double x, double y, S g, S h) {
+    const double wg = w * (double)g, wh = w * (double)h;
+    const double x2 = x * x + y * y;
+    m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += wg * x * x; m[4] += wg * x * y;
+    m[5] += wg * y * y; m[6] += wg * x * x2; m[7] += wg * y * x2;
+    m[8] += wh; m[9] += wh * x; m[10] += wh * y;
+}
+
 // ---------------------------------------------------------------------------
-// cell stage: W, q, tau, compatibility coefficients, phi_bar+ rows
+// cell stage: W, q, tau, compatibility coefficients, phi_bar+ rows.  The raw
+// moments of g~, h~ come from cmom (written by the previous update, or by
+// k_raw_moments after the state was set from outside).
 // ---------------------------------------------------------------------------
-template <typename S, int MINW>
-__global__ __launch_bounds__(BS, MINW) void k_cell_prep(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
-                                                  const int* __restrict__ cell_slot, int n_cells, Phys ph,
-                                                  double* __restrict__ params) {
+template <typename S, int U, int MINW>
+__global__ __launch_bounds__(BS, MINW) void k_cell_prep(const LevelDesc* __restrict__ lvs,
+                                                        const int* __restrict__ cell_lev,
+                                                        const int* __restrict__ cell_slot, int n_cells, Phys ph,
+                                                        double* __restrict__ params,
+                                                        const double* __restrict__ cmom) {
     for (int c = item0(); c < n_cells; c += istride()) {
         const LevelDesc& L = lvs[cell_lev[c]];
+        const int N = L.N;
         const size_t row = (size_t)cell_slot[c] * L.stride;
         const S* g = rowp<S>(L.g, row);
         const S* h = rowp<S>(L.h, row);
-        double* pr = params + (size_t)c * NPARAM;
-        const double u0 = pr[P_U], v0 = pr[P_V];
+        const double* cm = cmom + (size_t)c * NMOM;
         double m[11];
 #pragma unroll
-        for (int k = 0; k < 11; ++k) m[k] = 0.0;
-        for (int i = lane_id(); i < L.N; i += WL) {
-            const double w = L.w[i], x = L.xi_x[i] - u0, y = L.xi_y[i] - v0;
-            const double wg = w * (double)g[i], wh = w * (double)h[i];
-            const double x2 = x * x + y * y;
-            m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += wg * x * x; m[4] += wg * x * y;
-            m[5] += wg * y * y; m[6] += wg * x * x2; m[7] += wg * y * x2;
-            m[8] += wh; m[9] += wh * x; m[10] += wh * y;
-        }
-        wave_sum<11>(m);
+        for (int k = 0; k < 11; ++k) m[k] = cm[k];
         double rho, u, v, T, qx, qy;
-        raw_to_state(m, u0, v0, ph, rho, u, v, T, qx, qy);
+        raw_to_state(m, cm[M_U0], cm[M_V0], ph, rho, u, v, T, qx, qy);
         const double p = rho * ph.R * T;
         const double tau = viscosity(T, ph) / p;
         const double dt = ph.dt, s = 0.5 * dt;
@@ -234,25 +295,81 @@ __global__ __launch_bounds__(BS, MINW) void k_cell_prep(const LevelDesc* __restr
         qy = 2.0 * tau * qy / (2.0 * tau + dt * ph.Pr);
         double a[4] = {0.0, 0.0, 0.0, 0.0};
         if (ph.compat) {
-            Eq<S> eu = make_eq<S>(rho, u, v, T, qx, qy, nullptr, ph);
-            compat_solve<S>(L, eu, rho, u, v, T, ph, a);
+            const Eq<S> eu = eq_cast<S>(make_eq(rho, u, v, T, qx, qy, nullptr, ph));
+            compat_solve<S, U>(L, eu, rho, u, v, T, ph, a);
         }
         const double alpha = (2.0 * tau - s) / (2.0 * tau + dt);
         const double beta = 3.0 * s / (2.0 * tau + dt);
-        Eq<S> e = make_eq<S>(rho, u, v, T, qx, qy, ph.compat ? a : nullptr, ph);
+        const Eq<S> e = eq_cast<S>(make_eq(rho, u, v, T, qx, qy, ph.compat ? a : nullptr, ph));
         S* fg = rowp<S>(L.fg, row);
         S* fh = rowp<S>(L.fh, row);
-        const S al = (S)alpha, be = (S)beta;
-        for (int i = lane_id(); i < L.N; i += WL) {
-            S gs, hs;
-            eq_eval<S>(e, (S)L.xi_x[i], (S)L.xi_y[i], gs, hs);
-            fg[i] = al * g[i] + be * gs;
-            fh[i] = al * h[i] + be * hs;
+        const S al = uni((S)alpha), be = uni((S)beta);
+        for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
+            S gv[U], hv[U], xv[U], yv[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int ic = clampi(i0 + q * WL, N);
+                gv[q] = g[ic]; hv[q] = h[ic];
+                xv[q] = (S)L.xi_x[ic]; yv[q] = (S)L.xi_y[ic];
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                S gs, hs;
+                eq_eval<S>(e, xv[q], yv[q], gs, hs);
+                gv[q] = al * gv[q] + be * gs;
+                hv[q] = al * hv[q] + be * hs;
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int i = i0 + q * WL;
+                if (i < N) { fg[i] = gv[q]; fh[i] = hv[q]; }
+            }
         }
         if (lane_id() == 0) {
+            double* pr = params + (size_t)c * NPARAM;
             pr[P_RHO] = rho; pr[P_U] = u; pr[P_V] = v; pr[P_T] = T; pr[P_QX] = qx; pr[P_QY] = qy;
             pr[P_TAU] = tau; pr[P_A0] = a[0]; pr[P_A1] = a[1]; pr[P_A2] = a[2]; pr[P_A3] = a[3];
             pr[P_ALPHA] = alpha; pr[P_BETA] = beta;
+        }
+    }
+}
+
+// Raw moments of the stored g~, h~ about the cell velocity held in params (used
+// when the state was written by anything other than the update).
+template <typename S>
+__global__ __launch_bounds__(BS) void k_raw_moments(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
+                                                    const int* __restrict__ cell_slot, int n_cells,
+                                                    const double* __restrict__ params, double* __restrict__ cmom) {
+    constexpr int U = 4;
+    for (int c = item0(); c < n_cells; c += istride()) {
+        const LevelDesc& L = lvs[cell_lev[c]];
+        const int N = L.N;
+        const size_t row = (size_t)cell_slot[c] * L.stride;
+        const S* g = rowp<S>(L.g, row);
+        const S* h = rowp<S>(L.h, row);
+        const double u0 = params[(size_t)c * NPARAM + P_U], v0 = params[(size_t)c * NPARAM + P_V];
+        double m[11];
+#pragma unroll
+        for (int k = 0; k < 11; ++k) m[k] = 0.0;
+        for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
+            S gv[U], hv[U];
+            double xv[U], yv[U], wv[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int i = i0 + q * WL, ic = clampi(i, N);
+                gv[q] = g[ic]; hv[q] = h[ic];
+                xv[q] = L.xi_x[ic]; yv[q] = L.xi_y[ic];
+                wv[q] = i < N ? L.w[ic] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q) acc_raw<S>(m, wv[q], xv[q] - u0, yv[q] - v0, gv[q], hv[q]);
+        }
+        wave_sum<11>(m);
+        if (lane_id() == 0) {
+            double* o = cmom + (size_t)c * NMOM;
+            for (int k = 0; k < 11; ++k) o[k] = m[k];
+            o[M_U0] = u0;
+            o[M_V0] = v0;
         }
     }
 }
@@ -267,10 +384,10 @@ __global__ __launch_bounds__(BS) void k_init_eq(const LevelDesc* __restrict__ lv
         const double rho = st[4 * c], u = st[4 * c + 1], v = ph.D == 2 ? st[4 * c + 2] : 0.0, T = st[4 * c + 3];
         double a[4] = {0.0, 0.0, 0.0, 0.0};
         if (ph.compat) {
-            Eq<S> eu = make_eq<S>(rho, u, v, T, 0.0, 0.0, nullptr, ph);
-            compat_solve<S>(L, eu, rho, u, v, T, ph, a);
+            const Eq<S> eu = eq_cast<S>(make_eq(rho, u, v, T, 0.0, 0.0, nullptr, ph));
+            compat_solve<S, 4>(L, eu, rho, u, v, T, ph, a);
         }
-        Eq<S> e = make_eq<S>(rho, u, v, T, 0.0, 0.0, ph.compat ? a : nullptr, ph);
+        const Eq<S> e = eq_cast<S>(make_eq(rho, u, v, T, 0.0, 0.0, ph.compat ? a : nullptr, ph));
         const size_t row = (size_t)cell_slot[c] * L.stride;
         S* g = rowp<S>(L.g, row);
         S* h = rowp<S>(L.h, row);
@@ -451,20 +568,14 @@ __device__ __forceinline__ void side_ext(const Side<S>& sd, int i, S x, S y, S s
     eh = f[1] + ax * sx[1] + ay * sy[1];
 }
 
-template <typename S>
-__device__ __forceinline__ void acc_raw(double* m, double w, double x, double y, S g, S h) {
-    const double wg = w * (double)g, wh = w * (double)h;
-    const double x2 = x * x + y * y;
-    m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += wg * x * x; m[4] += wg * x * y;
-    m[5] += wg * y * y; m[6] += wg * x * x2; m[7] += wg * y * x2;
-    m[8] += wh; m[9] += wh * x; m[10] += wh * y;
-}
-
-// Face state from the reduced raw moments of phi_bar_f (Eq. W_from_bar) and the
-// compatibility coefficients of the face target; returns the recovery weights.
-template <typename S>
-__device__ __forceinline__ void face_target(const LevelDesc& L, double* m, double u0, double v0, const Phys& ph,
-                            bool compat, Eq<S>& e, double& c1, double& c2, double* Tout = nullptr) {
+// Face state from the reduced raw moments of phi_bar_f (Eq. W_from_bar,
+// q_f = 2 tau_f q_bar / (2 tau_f + s Pr)), the compatibility coefficients of
+// the face target, and the recovery weights c1 = 2 tau_f/(2 tau_f + s),
+// c2 = s/(2 tau_f + s) of Eq. recover_phi.  Returns the target in double.
+template <typename S, int U>
+__device__ __forceinline__ Eq<double> face_target(const LevelDesc& L, double* m, double u0, double v0,
+                                                  const Phys& ph, bool compat, double& c1, double& c2,
+                                                  double* Tout = nullptr) {
     double rho, u, v, T, qx, qy;
     raw_to_state(m, u0, v0, ph, rho, u, v, T, qx, qy);
     const double s = 0.5 * ph.dt;
@@ -473,212 +584,354 @@ __device__ __forceinline__ void face_target(const LevelDesc& L, double* m, doubl
     qy = 2.0 * tau * qy / (2.0 * tau + s * ph.Pr);
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     if (compat) {
-        Eq<S> eu = make_eq<S>(rho, u, v, T, qx, qy, nullptr, ph);
-        compat_solve<S>(L, eu, rho, u, v, T, ph, a);
+        const Eq<S> eu = eq_cast<S>(make_eq(rho, u, v, T, qx, qy, nullptr, ph));
+        compat_solve<S, U>(L, eu, rho, u, v, T, ph, a);
     }
-    e = make_eq<S>(rho, u, v, T, qx, qy, compat ? a : nullptr, ph);
     c1 = 2.0 * tau / (2.0 * tau + s);
     c2 = s / (2.0 * tau + s);
     if (Tout) *Tout = T;
+    return make_eq(rho, u, v, T, qx, qy, compat ? a : nullptr, ph);
+}
+
+// The five stencil values (own, W, E, S, N) of g and h at one velocity index,
+// from side a or b chosen per lane.
+template <typename S>
+struct Stencil { S v[2][5]; };
+
+template <typename S>
+__device__ __forceinline__ void load_stencil(const Side<S>& a, const Side<S>& b, bool useA, int i, Stencil<S>& st) {
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        const S* B = a.base[comp] + i;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) st.v[comp][k] = B[useA ? a.off[k] : b.off[k]];
+    }
+}
+
+// phi_bar+ + (x_f - x_c - xi s) . sigma from a loaded stencil (Eqs.
+// bar_phi_transport, reconstruction): per index direction a van Leer limited
+// pair of one-sided slopes, mapped through [t_i; t_j]^-1.
+template <typename S>
+__device__ __forceinline__ void stencil_ext(const Side<S>& a, const Side<S>& b, bool useA, const Stencil<S>& st,
+                                            S x, S y, S s, S& eg, S& eh) {
+    S G[4], id[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { G[k] = useA ? a.G[k] : b.G[k]; id[k] = useA ? a.id[k] : b.id[k]; }
+    const S ax = (useA ? a.dx : b.dx) - x * s, ay = (useA ? a.dy : b.dy) - y * s;
+    S e[2];
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        const S fv = st.v[comp][0];
+        const S s0 = van_leer<S>((fv - st.v[comp][1]) * id[0], (st.v[comp][2] - fv) * id[1]);
+        const S s1 = van_leer<S>((fv - st.v[comp][3]) * id[2], (st.v[comp][4] - fv) * id[3]);
+        e[comp] = fv + ax * (G[0] * s0 + G[1] * s1) + ay * (G[2] * s0 + G[3] * s1);
+    }
+    eg = e[0];
+    eh = e[1];
 }
 
 // Face stage, part 1 (reconstruction): for every same-level interior face and
 // every boundary face, the interface value phi_bar_f = phi_bar+_up + (x_f -
-// x_up - xi s) . sigma_up (Eqs. bar_phi_transport, reconstruction; both sides
-// averaged where xi . n = 0) is written to the face row.  Interior faces also
-// reduce the eleven raw moments of phi_bar_f (about the mean of the two cell
-// velocities); wall faces reduce the outgoing mass flux.  Per-face results go
-// to fmom[item][12].
-template <typename S, int MINW>
+// x_up - xi s) . sigma_up (both sides averaged where xi . n = 0) is written to
+// the face row.  Interior faces also reduce the eleven raw moments of phi_bar_f
+// (about the mean of the two cell velocities); boundary faces reduce the
+// outgoing mass flux.  Per-face results go to fmom[item][12].
+template <typename S, int U, int MINW>
 __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restrict__ lvs,
-                                                    const FaceItem* __restrict__ items, int n,
-                                                    const int* __restrict__ cell_slot,
-                                                    const int* __restrict__ cell_nbr,
-                                                    const CellGeom* __restrict__ geom,
-                                                    const double* __restrict__ params, Phys ph,
-                                                    double* __restrict__ fmom) {
+                                                       const FaceItem* __restrict__ items, int n,
+                                                       const int* __restrict__ cell_slot,
+                                                       const int* __restrict__ cell_nbr,
+                                                       const CellGeom* __restrict__ geom,
+                                                       const double* __restrict__ params, Phys ph,
+                                                       double* __restrict__ fmom) {
     const S s = (S)(0.5 * ph.dt);
     for (int it = item0(); it < n; it += istride()) {
         const FaceItem F = items[it];
         const LevelDesc& L = lvs[F.lev];
+        const int N = L.N;
         S* rg = rowp<S>(L.Fg, (size_t)F.row * L.stride);
         S* rh = rowp<S>(L.Fh, (size_t)F.row * L.stride);
         Side<S> sL;
         load_side<S>(sL, L, F.L, cell_slot, cell_nbr, geom, F.dLx, F.dLy);
         double* out = fmom + (size_t)it * 12;
-        if (F.R >= 0) {
-            Side<S> sR;
+        const bool interior = F.R >= 0;
+        Side<S> sR = sL;
+        double u0 = 0.0, v0 = 0.0;
+        if (interior) {
             load_side<S>(sR, L, F.R, cell_slot, cell_nbr, geom, F.dRx, F.dRy);
-            const double u0 = 0.5 * (params[(size_t)F.L * NPARAM + P_U] + params[(size_t)F.R * NPARAM + P_U]);
-            const double v0 = 0.5 * (params[(size_t)F.L * NPARAM + P_V] + params[(size_t)F.R * NPARAM + P_V]);
-            double m[11];
+            u0 = 0.5 * (params[(size_t)F.L * NPARAM + P_U] + params[(size_t)F.R * NPARAM + P_U]);
+            v0 = 0.5 * (params[(size_t)F.L * NPARAM + P_V] + params[(size_t)F.R * NPARAM + P_V]);
+        }
+        double m[11];
 #pragma unroll
-            for (int k = 0; k < 11; ++k) m[k] = 0.0;
-            for (int i = lane_id(); i < L.N; i += WL) {
-                const double xd = L.xi_x[i], yd = L.xi_y[i];
-                const S x = (S)xd, y = (S)yd;
-                const double dn = xd * F.nx + yd * F.ny;
-                S eg, eh;
-                Side<S> sd;
-                select_side<S>(sd, sL, sR, dn >= 0);
-                side_ext<S>(sd, i, x, y, s, eg, eh);
-                if (dn == 0) {                          // both sides, averaged
+        for (int k = 0; k < 11; ++k) m[k] = 0.0;
+        for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
+            double xv[U], yv[U], wv[U];
+            Stencil<S> st[U];
+            bool up[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int i = i0 + q * WL, ic = clampi(i, N);
+                xv[q] = L.xi_x[ic]; yv[q] = L.xi_y[ic];
+                wv[q] = i < N ? L.w[ic] : 0.0;
+                up[q] = xv[q] * F.nx + yv[q] * F.ny >= 0.0;
+                load_stencil<S>(sL, sR, up[q], ic, st[q]);
+            }
+            S eg[U], eh[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int ic = clampi(i0 + q * WL, N);
+                const S x = (S)xv[q], y = (S)yv[q];
+                stencil_ext<S>(sL, sR, up[q], st[q], x, y, s, eg[q], eh[q]);
+                const double dn = xv[q] * F.nx + yv[q] * F.ny;
+                if (interior && dn == 0.0) {            // both sides, averaged
+                    Stencil<S> sb;
+                    load_stencil<S>(sL, sR, false, ic, sb);
                     S bg, bh;
-                    side_ext<S>(sR, i, x, y, s, bg, bh);
-                    eg = S(0.5) * (eg + bg);
-                    eh = S(0.5) * (eh + bh);
+                    stencil_ext<S>(sL, sR, false, sb, x, y, s, bg, bh);
+                    eg[q] = S(0.5) * (eg[q] + bg);
+                    eh[q] = S(0.5) * (eh[q] + bh);
                 }
-                rg[i] = eg;
-                rh[i] = eh;
-                acc_raw<S>(m, L.w[i], xd - u0, yd - v0, eg, eh);
             }
-            wave_sum<11>(m);
-            if (lane_id() < 11) {
 #pragma unroll
-                for (int k = 0; k < 11; ++k)
-                    if (lane_id() == k) out[k] = m[k];
+            for (int q = 0; q < U; ++q) {
+                const int i = i0 + q * WL;
+                if (i < N) { rg[i] = eg[q]; rh[i] = eh[q]; }
+                if (interior) {
+                    acc_raw<S>(m, wv[q], xv[q] - u0, yv[q] - v0, eg[q], eh[q]);
+                } else {
+                    const double dn = xv[q] * F.nx + yv[q] * F.ny;
+                    if (dn > 0) m[0] += wv[q] * dn * (double)eg[q];
+                }
             }
-        } else {
-            double m[1] = {0.0};
-            for (int i = lane_id(); i < L.N; i += WL) {
-                const double xd = L.xi_x[i], yd = L.xi_y[i], w = L.w[i];
-                const double dn = xd * F.nx + yd * F.ny;
-                S eg, eh;
-                side_ext<S>(sL, i, (S)xd, (S)yd, s, eg, eh);
-                rg[i] = eg;
-                rh[i] = eh;
-                if (dn > 0) m[0] += w * dn * (double)eg;
-            }
-            wave_sum<1>(m);
-            if (lane_id() == 0) out[0] = m[0];
+        }
+        wave_sum<11>(m);
+        if (lane_id() < 11) {
+#pragma unroll
+            for (int k = 0; k < 11; ++k)
+                if (lane_id() == k) out[k] = m[k];
         }
     }
 }
 
-// Face stage, part 2 (flux).  Interior faces: face state from the reduced
-// moments (Eq. W_from_bar, q_f = 2 tau_f q_bar / (2 tau_f + s Pr)), the
-// corrected face target, phi_f (Eq. recover_phi) and F = A_f (xi . n) phi_f.
-// Boundary faces (outward normal): outgoing velocities carry the interior
-// reconstruction, incoming ones the boundary state -- diffuse wall rho_w
-// g_eq(u_w, T_w) with rho_w from zero net mass flux, far-field Maxwellian, or
-// the cell's phi_bar+ (zero-gradient outflow).
-template <typename S, int MINW>
-__global__ __launch_bounds__(BS, MINW) void k_face_flux(const LevelDesc* __restrict__ lvs,
-                                                     const FaceItem* __restrict__ items, int n,
-                                                     const int* __restrict__ cell_slot,
-                                                     const double* __restrict__ params,
-                                                     const BCDev* __restrict__ bcs, Phys ph,
-                                                     const double* __restrict__ fmom) {
+// Face stage, part 2 (target): per face, the parameters the update needs to
+// finish the flux F = A_f (xi . n) phi_f at every velocity.  Interior faces:
+// the face state from the reduced moments, the corrected face target and the
+// recovery weights (Eq. recover_phi).  Boundary faces (outward normal):
+// outgoing velocities carry the interior reconstruction, incoming ones the
+// boundary state -- diffuse wall rho_w g_eq(u_w, T_w) with rho_w from zero net
+// mass flux, far-field Maxwellian, or the cell's phi_bar+ (zero-gradient
+// outflow).  Record layout: FP_* (mlvs_impl.h).
+template <typename S, int U, int MINW>
+__global__ __launch_bounds__(BS, MINW) void k_face_target(const LevelDesc* __restrict__ lvs,
+                                                          const FaceItem* __restrict__ items, int n,
+                                                          const double* __restrict__ params,
+                                                          const BCDev* __restrict__ bcs, Phys ph,
+                                                          const double* __restrict__ fmom,
+                                                          double* __restrict__ fpar) {
     for (int it = item0(); it < n; it += istride()) {
         const FaceItem F = items[it];
         const LevelDesc& L = lvs[F.lev];
-        S* rg = rowp<S>(L.Fg, (size_t)F.row * L.stride);
-        S* rh = rowp<S>(L.Fh, (size_t)F.row * L.stride);
         const double* mm = fmom + (size_t)it * 12;
-        const S ar = (S)F.area;
+        Eq<double> e = make_eq(1.0, 0.0, 0.0, 1.0, 0.0, 0.0, nullptr, ph);
+        double kind = 0.0, c1 = 0.0, c2 = 0.0;
         if (F.R >= 0) {
             double m[11];
 #pragma unroll
             for (int k = 0; k < 11; ++k) m[k] = mm[k];
             const double u0 = 0.5 * (params[(size_t)F.L * NPARAM + P_U] + params[(size_t)F.R * NPARAM + P_U]);
             const double v0 = 0.5 * (params[(size_t)F.L * NPARAM + P_V] + params[(size_t)F.R * NPARAM + P_V]);
-            Eq<S> e;
-            double c1, c2;
-            face_target<S>(L, m, u0, v0, ph, ph.compat && ph.face_compat, e, c1, c2);
-            const S a1 = (S)c1, a2 = (S)c2;
-            for (int i = lane_id(); i < L.N; i += WL) {
-                const double xd = L.xi_x[i], yd = L.xi_y[i];
-                S gs, hs;
-                eq_eval<S>(e, (S)xd, (S)yd, gs, hs);
-                const S dn = (S)(xd * F.nx + yd * F.ny);
-                rg[i] = ar * dn * (a1 * rg[i] + a2 * gs);
-                rh[i] = ar * dn * (a1 * rh[i] + a2 * hs);
-            }
+            e = face_target<S, U>(L, m, u0, v0, ph, ph.compat && ph.face_compat, c1, c2);
+            c1 *= F.area;
+            c2 *= F.area;
         } else {
             const BCDev bc = bcs[-1 - F.R];
-            Eq<S> e;
-            S rho_w = S(1);
+            kind = (double)bc.kind;
+            c1 = F.area;
+            c2 = F.area;
             if (bc.kind == 1) {
-                e = make_eq<S>(1.0, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
+                e = make_eq(1.0, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
+                const Eq<S> es = eq_cast<S>(e);
+                const int N = L.N;
                 double m[1] = {0.0};
-                for (int i = lane_id(); i < L.N; i += WL) {
-                    const double xd = L.xi_x[i], yd = L.xi_y[i], w = L.w[i];
-                    const double dn = xd * F.nx + yd * F.ny;
-                    if (dn < 0) {
-                        S gs, hs;
-                        eq_eval<S>(e, (S)xd, (S)yd, gs, hs);
-                        m[0] += w * dn * (double)gs;
+                for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
+                    double xv[U], yv[U], wv[U];
+#pragma unroll
+                    for (int q = 0; q < U; ++q) {
+                        const int i = i0 + q * WL, ic = clampi(i, N);
+                        xv[q] = L.xi_x[ic]; yv[q] = L.xi_y[ic];
+                        wv[q] = i < N ? L.w[ic] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < U; ++q) {
+                        const double dn = xv[q] * F.nx + yv[q] * F.ny;
+                        if (dn < 0) {
+                            S gs, hs;
+                            eq_eval<S>(es, (S)xv[q], (S)yv[q], gs, hs);
+                            m[0] += wv[q] * dn * (double)gs;
+                        }
                     }
                 }
                 wave_sum<1>(m);
-                rho_w = (S)(-mm[0] / m[0]);
+                c2 = F.area * (-mm[0] / m[0]);
             } else if (bc.kind == 2) {
-                e = make_eq<S>(bc.rho, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
+                e = make_eq(bc.rho, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
             }
-            const size_t own = (size_t)cell_slot[F.L] * L.stride;
-            const S* og = rowp<S>(L.fg, own);
-            const S* oh = rowp<S>(L.fh, own);
-            for (int i = lane_id(); i < L.N; i += WL) {
-                const double xd = L.xi_x[i], yd = L.xi_y[i];
-                const double dnd = xd * F.nx + yd * F.ny;
-                const S dn = (S)dnd;
-                S gf, hf;
-                if (dnd > 0) {
-                    gf = rg[i];
-                    hf = rh[i];
-                } else if (bc.kind == 3) {
-                    gf = og[i];
-                    hf = oh[i];
-                } else {
-                    eq_eval<S>(e, (S)xd, (S)yd, gf, hf);
-                    gf *= rho_w;
-                    hf *= rho_w;
-                }
-                rg[i] = ar * dn * gf;
-                rh[i] = ar * dn * hf;
-            }
+        }
+        if (lane_id() == 0) {
+            double* o = fpar + (size_t)it * NFP;
+            o[FP_KIND] = kind; o[FP_ROW] = (double)F.row; o[FP_NX] = F.nx; o[FP_NY] = F.ny;
+            o[FP_C1] = c1; o[FP_C2] = c2;
+            o[FP_RN] = e.rn; o[FP_UX] = e.ux; o[FP_UY] = e.uy; o[FP_I2RT] = e.i2RT; o[FP_RT] = e.RT;
+            o[FP_IRT] = e.iRT; o[FP_XQX] = e.Xqx; o[FP_XQY] = e.Xqy;
+            o[FP_B0] = e.b0; o[FP_B1] = e.b1; o[FP_B2] = e.b2; o[FP_B3] = e.b3;
+            o[FP_CORR] = e.corr ? 1.0 : 0.0;
         }
     }
 }
 
+template <typename S>
+__device__ __forceinline__ Eq<S> load_face_eq(const double* fp, const Phys& ph) {
+    Eq<double> d;
+    d.rn = fp[FP_RN]; d.ux = fp[FP_UX]; d.uy = fp[FP_UY]; d.i2RT = fp[FP_I2RT]; d.RT = fp[FP_RT];
+    d.iRT = fp[FP_IRT]; d.Xqx = fp[FP_XQX]; d.Xqy = fp[FP_XQY];
+    d.b0 = fp[FP_B0]; d.b1 = fp[FP_B1]; d.b2 = fp[FP_B2]; d.b3 = fp[FP_B3];
+    d.cK = ph.K + 3.0 - ph.D; d.Dp2 = ph.D + 2.0; d.Dd = ph.D; d.K2 = 2.0 * ph.K;
+    d.corr = fp[FP_CORR] != 0.0;
+    return eq_cast<S>(d);
+}
+
 // ---------------------------------------------------------------------------
 // cell update: phi~^{n+1} = 4/3 phi_bar+ - 1/3 phi~ - dt/|V| sum(+-F)
+// (Eq. explicit_update).  Same-level and boundary faces are finished here from
+// the face row phi_bar_f and the face record; cross-level faces arrive as final
+// flux rows.  Both cells of a face evaluate the same expression on the same
+// data, so the two contributions cancel exactly in the totals.  The raw moments
+// of the new state (about this step's cell velocity) go to cmom for the next
+// cell stage.
+// Face codes (cell_frow): -1 none; else 4 x + 2 final + neg, x the face item
+// (final = 0) or the level row of a final flux (final = 1).
 // ---------------------------------------------------------------------------
-template <typename S>
-__global__ __launch_bounds__(BS) void k_update(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
-                                               const int* __restrict__ cell_slot, int n_cells,
-                                               const CellGeom* __restrict__ geom, const int* __restrict__ cell_frow,
-                                               Phys ph) {
+template <typename S, int U, int MINW>
+__global__ __launch_bounds__(BS, MINW) void k_update(const LevelDesc* __restrict__ lvs,
+                                                     const int* __restrict__ cell_lev,
+                                                     const int* __restrict__ cell_slot, int n_cells,
+                                                     const CellGeom* __restrict__ geom,
+                                                     const int* __restrict__ cell_frow,
+                                                     const FaceItem* __restrict__ items,
+                                                     const double* __restrict__ fpar,
+                                                     const double* __restrict__ params, Phys ph,
+                                                     double* __restrict__ cmom) {
+    const S c43 = (S)(4.0 / 3.0), c13 = (S)(1.0 / 3.0);
     for (int c = item0(); c < n_cells; c += istride()) {
         const LevelDesc& L = lvs[cell_lev[c]];
+        const int N = L.N;
         const size_t row = (size_t)cell_slot[c] * L.stride;
         S* g = rowp<S>(L.g, row);
         S* h = rowp<S>(L.h, row);
         const S* fg = rowp<S>(L.fg, row);
         const S* fh = rowp<S>(L.fh, row);
-        const S* Fg[4];
-        const S* Fh[4];
-        S sg[4];
-        int nf = 0;
-        for (int k = 0; k < 4; ++k) {
-            const int code = cell_frow[4 * c + k];
-            if (code < 0) continue;
-            const size_t r = (size_t)(code >> 1) * L.stride;
-            Fg[nf] = rowp<S>(L.Fg, r);
-            Fh[nf] = rowp<S>(L.Fh, r);
-            sg[nf] = (code & 1) ? S(-1) : S(1);
-            ++nf;
-        }
-        const S k = (S)(ph.dt / geom[c].vol);
-        const S c43 = (S)(4.0 / 3.0), c13 = (S)(1.0 / 3.0);
-        for (int i = lane_id(); i < L.N; i += WL) {
-            S ag = S(0), ah = S(0);
-            for (int j = 0; j < nf; ++j) {
-                ag += sg[j] * Fg[j][i];
-                ah += sg[j] * Fh[j][i];
+        int code[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) code[k] = cell_frow[4 * c + k];
+        const S kv = uni((S)(ph.dt / geom[c].vol));
+        const double u0 = params[(size_t)c * NPARAM + P_U], v0 = params[(size_t)c * NPARAM + P_V];
+        double m[11];
+#pragma unroll
+        for (int k = 0; k < 11; ++k) m[k] = 0.0;
+        for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
+            double xv[U], yv[U], wv[U];
+            S bg[U], bh[U], go[U], ho[U], ag[U], ah[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int i = i0 + q * WL, ic = clampi(i, N);
+                xv[q] = L.xi_x[ic]; yv[q] = L.xi_y[ic];
+                wv[q] = i < N ? L.w[ic] : 0.0;
+                bg[q] = fg[ic]; bh[q] = fh[ic];
+                go[q] = g[ic]; ho[q] = h[ic];
+                ag[q] = S(0); ah[q] = S(0);
             }
-            g[i] = c43 * fg[i] - c13 * g[i] - k * ag;
-            h[i] = c43 * fh[i] - c13 * h[i] - k * ah;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int cd = code[f];
+                if (cd < 0) continue;
+                const S sgn = (cd & 1) ? S(-1) : S(1);
+                if (cd & 2) {
+                    const size_t r = (size_t)(cd >> 2) * L.stride;
+                    const S* Fg = rowp<S>(L.Fg, r);
+                    const S* Fh = rowp<S>(L.Fh, r);
+                    S vg[U], vh[U];
+#pragma unroll
+                    for (int q = 0; q < U; ++q) {
+                        const int ic = clampi(i0 + q * WL, N);
+                        vg[q] = Fg[ic]; vh[q] = Fh[ic];
+                    }
+#pragma unroll
+                    for (int q = 0; q < U; ++q) { ag[q] += sgn * vg[q]; ah[q] += sgn * vh[q]; }
+                    continue;
+                }
+                const double* fp = fpar + (size_t)(cd >> 2) * NFP;
+                const int kind = __builtin_amdgcn_readfirstlane((int)fp[FP_KIND]);
+                const size_t r = (size_t)items[cd >> 2].row * L.stride;
+                const S* Fg = rowp<S>(L.Fg, r);
+                const S* Fh = rowp<S>(L.Fh, r);
+                const double nx = fp[FP_NX], ny = fp[FP_NY];
+                const S k1 = uni((S)fp[FP_C1]), k2 = uni((S)fp[FP_C2]);
+                S vg[U], vh[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const int ic = clampi(i0 + q * WL, N);
+                    vg[q] = Fg[ic]; vh[q] = Fh[ic];
+                }
+                if (kind == 3) {            // outflow: incoming = the cell's phi_bar+
+#pragma unroll
+                    for (int q = 0; q < U; ++q) {
+                        const double dnd = xv[q] * nx + yv[q] * ny;
+                        const S dn = (S)dnd;
+                        const S pg = dnd > 0 ? vg[q] : bg[q], ph_ = dnd > 0 ? vh[q] : bh[q];
+                        ag[q] += sgn * (k1 * dn * pg);
+                        ah[q] += sgn * (k1 * dn * ph_);
+                    }
+                    continue;
+                }
+                const Eq<S> e = load_face_eq<S>(fp, ph);
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const double dnd = xv[q] * nx + yv[q] * ny;
+                    const S dn = (S)dnd;
+                    S gs, hs;
+                    eq_eval<S>(e, (S)xv[q], (S)yv[q], gs, hs);
+                    S pg, ph_;
+                    if (kind == 0) {
+                        pg = k1 * vg[q] + k2 * gs;
+                        ph_ = k1 * vh[q] + k2 * hs;
+                    } else {
+                        pg = dnd > 0 ? k1 * vg[q] : k2 * gs;
+                        ph_ = dnd > 0 ? k1 * vh[q] : k2 * hs;
+                    }
+                    ag[q] += sgn * (dn * pg);
+                    ah[q] += sgn * (dn * ph_);
+                }
+            }
+            S gn[U], hn[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                gn[q] = c43 * bg[q] - c13 * go[q] - kv * ag[q];
+                hn[q] = c43 * bh[q] - c13 * ho[q] - kv * ah[q];
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int i = i0 + q * WL;
+                if (i < N) { g[i] = gn[q]; h[i] = hn[q]; }
+                acc_raw<S>(m, wv[q], xv[q] - u0, yv[q] - v0, gn[q], hn[q]);
+            }
+        }
+        wave_sum<11>(m);
+        if (lane_id() == 0) {
+            double* o = cmom + (size_t)c * NMOM;
+            for (int k = 0; k < 11; ++k) o[k] = m[k];
+            o[M_U0] = u0;
+            o[M_V0] = v0;
         }
     }
 }
@@ -801,24 +1054,26 @@ __global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv,
 // launch wrappers
 // ---------------------------------------------------------------------------
 static inline int grid_for(int n) {
-    const int b = (n + MAXW - 1) / MAXW;
-    return b < 1 ? 1 : (b > 1048576 ? 1048576 : b);
+    int b = (n + MAXW - 1) / MAXW;
+    b = (b + NXCD - 1) / NXCD * NXCD;          // whole rounds over the XCDs (see wg_index)
+    return b < NXCD ? NXCD : (b > 1048576 ? 1048576 : b);
 }
 
-// Tunable kernels are instantiated for several minimum-occupancy targets
-// (waves per SIMD); the variant index selects one at launch.
+// Tunable kernels are instantiated for several (points per lane per chunk U,
+// minimum waves per SIMD) pairs; the variant index selects one at launch.
 constexpr int N_VARIANTS = 4;
+#define MLVS_LAUNCH_UW(prec, KERNEL, U_, W_, ...)                                                \
+    do {                                                                                        \
+        if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, U_, W_>), __VA_ARGS__);              \
+        else hipLaunchKernelGGL((KERNEL<double, U_, W_>), __VA_ARGS__);                          \
+    } while (0)
 #define MLVS_DISPATCH_V(prec, var, KERNEL, ...)                                                  \
     do {                                                                                        \
         switch (var) {                                                                          \
-        case 0: if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, 2>), __VA_ARGS__);            \
-                else hipLaunchKernelGGL((KERNEL<double, 2>), __VA_ARGS__); break;                 \
-        case 2: if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, 6>), __VA_ARGS__);            \
-                else hipLaunchKernelGGL((KERNEL<double, 6>), __VA_ARGS__); break;                 \
-        case 3: if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, 8>), __VA_ARGS__);            \
-                else hipLaunchKernelGGL((KERNEL<double, 8>), __VA_ARGS__); break;                 \
-        default: if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, 4>), __VA_ARGS__);           \
-                 else hipLaunchKernelGGL((KERNEL<double, 4>), __VA_ARGS__); break;                \
+        case 0: MLVS_LAUNCH_UW(prec, KERNEL, 1, 4, __VA_ARGS__); break;                          \
+        case 2: MLVS_LAUNCH_UW(prec, KERNEL, 4, 2, __VA_ARGS__); break;                          \
+        case 3: MLVS_LAUNCH_UW(prec, KERNEL, 4, 4, __VA_ARGS__); break;                          \
+        default: MLVS_LAUNCH_UW(prec, KERNEL, 2, 4, __VA_ARGS__); break;                         \
         }                                                                                       \
     } while (0)
 
@@ -831,10 +1086,18 @@ int variant_count() { return N_VARIANTS; }
     } while (0)
 
 hipError_t launch_cell_prep(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
-                            int n_cells, Phys ph, double* params, int var) {
+                            int n_cells, Phys ph, double* params, const double* cmom, int var) {
     if (n_cells <= 0) return hipSuccess;
-    MLVS_DISPATCH_V(prec, var, k_cell_prep, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells, ph,
-                  params);
+    MLVS_DISPATCH_V(prec, var, k_cell_prep, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot,
+                    n_cells, ph, params, cmom);
+    return hipGetLastError();
+}
+
+hipError_t launch_raw_moments(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
+                              const int* cell_slot, int n_cells, const double* params, double* cmom) {
+    if (n_cells <= 0) return hipSuccess;
+    MLVS_DISPATCH(prec, k_raw_moments, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
+                  params, cmom);
     return hipGetLastError();
 }
 
@@ -859,25 +1122,26 @@ hipError_t launch_face_rec(int prec, hipStream_t st, const LevelDesc* lv, const 
                            const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
                            Phys ph, double* fmom, int var) {
     if (n <= 0) return hipSuccess;
-    MLVS_DISPATCH_V(prec, var, k_face_rec, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr, geom,
-                  params, ph, fmom);
+    MLVS_DISPATCH_V(prec, var, k_face_rec, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr,
+                    geom, params, ph, fmom);
     return hipGetLastError();
 }
 
-hipError_t launch_face_flux(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
-                            const int* cell_slot, const double* params, const BCDev* bcs, Phys ph,
-                            const double* fmom, int var) {
+hipError_t launch_face_target(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
+                              const double* params, const BCDev* bcs, Phys ph, const double* fmom, double* fpar,
+                              int var) {
     if (n <= 0) return hipSuccess;
-    MLVS_DISPATCH_V(prec, var, k_face_flux, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, params, bcs, ph,
-                  fmom);
+    MLVS_DISPATCH_V(prec, var, k_face_target, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, params, bcs, ph,
+                    fmom, fpar);
     return hipGetLastError();
 }
 
 hipError_t launch_update(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
-                         int n_cells, const CellGeom* geom, const int* cell_frow, Phys ph) {
+                         int n_cells, const CellGeom* geom, const int* cell_frow, const FaceItem* items,
+                         const double* fpar, const double* params, Phys ph, double* cmom, int var) {
     if (n_cells <= 0) return hipSuccess;
-    MLVS_DISPATCH(prec, k_update, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells, geom,
-                  cell_frow, ph);
+    MLVS_DISPATCH_V(prec, var, k_update, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
+                    geom, cell_frow, items, fpar, params, ph, cmom);
     return hipGetLastError();
 }
 
@@ -923,7 +1187,7 @@ __device__ __forceinline__ void side_refined(const Side<S>& sd, const LevelDesc&
     sy[1] = sy[1] + dq * sy[0];
 }
 
-template <typename S, int MINW>
+template <typename S, int U, int MINW>
 __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict__ lvs, const XFaceItem* __restrict__ items,
                                               int n, const int* __restrict__ cell_slot,
                                               const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
@@ -1020,10 +1284,9 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
             acc_raw<S>(fm, LI.w[P], xd - u0, yd - v0, eg, eh);
         }
         wave_sum<11>(fm);
-        Eq<S> eq;
         double c1, c2;
         double Tf = 1.0;
-        face_target<S>(LI, fm, u0, v0, ph, ph.compat && ph.face_compat, eq, c1, c2, &Tf);
+        const Eq<S> eq = eq_cast<S>(face_target<S, 1>(LI, fm, u0, v0, ph, ph.compat && ph.face_compat, c1, c2, &Tf));
         // pass 3: interface microflux per unit area and its moments F_int
         double Fm[4] = {0, 0, 0, 0};
         const S k1 = (S)c1, k2 = (S)c2;

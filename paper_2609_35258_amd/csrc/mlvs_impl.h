@@ -17,8 +17,20 @@ enum {
     NPARAM = 16
 };
 
-// Per-face parameter block for the face target (double).
-enum { F_RHO = 0, F_U, F_V, F_T, F_QX, F_QY, F_TAU, F_A0, F_A1, F_A2, F_A3, NFPARAM = 12 };
+// Per-cell raw moments of the stored g~, h~ (double): the eleven sums read by
+// the cell stage, taken about the velocity shift (M_U0, M_V0).
+enum { M_U0 = 11, M_V0 = 12, NMOM = 16 };
+
+// Per-face record written by the face-target stage and read by the update
+// (double).  KIND: 0 interior, else the boundary kind; C1, C2: the weights of
+// phi_bar_f and of the target (area included); RN..B3: the target in the
+// evaluation form of the kernels; CORR: 1 if the compatibility factor applies.
+enum {
+    FP_KIND = 0, FP_ROW, FP_NX, FP_NY, FP_C1, FP_C2,
+    FP_RN, FP_UX, FP_UY, FP_I2RT, FP_RT, FP_IRT, FP_XQX, FP_XQY,
+    FP_B0, FP_B1, FP_B2, FP_B3, FP_CORR,
+    NFP = 20
+};
 
 // One velocity space (a representative level or an interface level).
 struct LevelDesc {
@@ -86,22 +98,26 @@ struct RemapItem {     // cell moved from an old level to a new one
 // Launch wrappers (kernels.hip).  `S` selects float (32) or double (64) storage.
 int variant_count();
 hipError_t launch_cell_prep(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
-                            const int* cell_slot, int n_cells, Phys ph, double* params, int var = 1);
+                            const int* cell_slot, int n_cells, Phys ph, double* params, const double* cmom,
+                            int var = 1);
+hipError_t launch_raw_moments(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
+                              const int* cell_slot, int n_cells, const double* params, double* cmom);
 hipError_t launch_ghost(int prec, hipStream_t st, const LevelDesc* lv, const GhostItem* items, int n,
                         const int* cell_lev, const int* cell_slot, const double* params, Phys ph,
                         unsigned long long* neg);
 hipError_t launch_face_rec(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
                            const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
                            const double* params, Phys ph, double* fmom, int var = 1);
-hipError_t launch_face_flux(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
-                            const int* cell_slot, const double* params, const BCDev* bcs, Phys ph,
-                            const double* fmom, int var = 1);
+hipError_t launch_face_target(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
+                              const double* params, const BCDev* bcs, Phys ph, const double* fmom, double* fpar,
+                              int var = 1);
 hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFaceItem* items, int n,
                         const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
                         const double* params, Phys ph, unsigned long long* neg, int var = 1);
 hipError_t launch_update(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
-                         const int* cell_slot, int n_cells, const CellGeom* geom,
-                         const int* cell_frow, Phys ph);
+                         const int* cell_slot, int n_cells, const CellGeom* geom, const int* cell_frow,
+                         const FaceItem* items, const double* fpar, const double* params, Phys ph, double* cmom,
+                         int var = 1);
 hipError_t launch_init_eq(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
                           const int* cell_slot, int n_cells, const double* rho_u_v_T, Phys ph,
                           double* params);
