@@ -61,8 +61,15 @@ __device__ __forceinline__ void wave_sum(double (&v)[NV]) {
     }
 }
 
+// Device buffers reached through the level descriptors are global memory; the
+// address-space cast lets the compiler use global (not flat) loads and stores.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gp(T* p) { return (gptr<T>)p; }
+
 template <typename S>
-__device__ __forceinline__ S* rowp(void* base, size_t off) { return reinterpret_cast<S*>(base) + off; }
+__device__ __forceinline__ gptr<S> rowp(void* base, size_t off) { return gp(reinterpret_cast<S*>(base)) + off; }
 
 // Gaussian elimination with partial pivoting on a register-resident N x N
 // system (all indices compile-time: no scratch).  The pivot search keeps the
@@ -215,8 +222,8 @@ __device__ __forceinline__ void compat_solve(const LevelDesc& L, const Eq<S>& eu
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const int i = i0 + q * WL, ic = clampi(i, N);
-            xv[q] = L.xi_x[ic]; yv[q] = L.xi_y[ic];
-            wv[q] = i < N ? L.w[ic] : 0.0;
+            xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
+            wv[q] = i < N ? gp(L.w)[ic] : 0.0;
         }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
@@ -280,8 +287,8 @@ __global__ __launch_bounds__(BS, MINW) void k_cell_prep(const LevelDesc* __restr
         const LevelDesc& L = lvs[cell_lev[c]];
         const int N = L.N;
         const size_t row = (size_t)cell_slot[c] * L.stride;
-        const S* g = rowp<S>(L.g, row);
-        const S* h = rowp<S>(L.h, row);
+        auto g = rowp<S>(L.g, row);
+        auto h = rowp<S>(L.h, row);
         const double* cm = cmom + (size_t)c * NMOM;
         double m[11];
 #pragma unroll
@@ -301,8 +308,8 @@ __global__ __launch_bounds__(BS, MINW) void k_cell_prep(const LevelDesc* __restr
         const double alpha = (2.0 * tau - s) / (2.0 * tau + dt);
         const double beta = 3.0 * s / (2.0 * tau + dt);
         const Eq<S> e = eq_cast<S>(make_eq(rho, u, v, T, qx, qy, ph.compat ? a : nullptr, ph));
-        S* fg = rowp<S>(L.fg, row);
-        S* fh = rowp<S>(L.fh, row);
+        auto fg = rowp<S>(L.fg, row);
+        auto fh = rowp<S>(L.fh, row);
         const S al = uni((S)alpha), be = uni((S)beta);
         for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
             S gv[U], hv[U], xv[U], yv[U];
@@ -310,7 +317,7 @@ __global__ __launch_bounds__(BS, MINW) void k_cell_prep(const LevelDesc* __restr
             for (int q = 0; q < U; ++q) {
                 const int ic = clampi(i0 + q * WL, N);
                 gv[q] = g[ic]; hv[q] = h[ic];
-                xv[q] = (S)L.xi_x[ic]; yv[q] = (S)L.xi_y[ic];
+                xv[q] = (S)gp(L.xi_x)[ic]; yv[q] = (S)gp(L.xi_y)[ic];
             }
 #pragma unroll
             for (int q = 0; q < U; ++q) {
@@ -345,8 +352,8 @@ __global__ __launch_bounds__(BS) void k_raw_moments(const LevelDesc* __restrict_
         const LevelDesc& L = lvs[cell_lev[c]];
         const int N = L.N;
         const size_t row = (size_t)cell_slot[c] * L.stride;
-        const S* g = rowp<S>(L.g, row);
-        const S* h = rowp<S>(L.h, row);
+        auto g = rowp<S>(L.g, row);
+        auto h = rowp<S>(L.h, row);
         const double u0 = params[(size_t)c * NPARAM + P_U], v0 = params[(size_t)c * NPARAM + P_V];
         double m[11];
 #pragma unroll
@@ -358,8 +365,8 @@ __global__ __launch_bounds__(BS) void k_raw_moments(const LevelDesc* __restrict_
             for (int q = 0; q < U; ++q) {
                 const int i = i0 + q * WL, ic = clampi(i, N);
                 gv[q] = g[ic]; hv[q] = h[ic];
-                xv[q] = L.xi_x[ic]; yv[q] = L.xi_y[ic];
-                wv[q] = i < N ? L.w[ic] : 0.0;
+                xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
+                wv[q] = i < N ? gp(L.w)[ic] : 0.0;
             }
 #pragma unroll
             for (int q = 0; q < U; ++q) acc_raw<S>(m, wv[q], xv[q] - u0, yv[q] - v0, gv[q], hv[q]);
@@ -389,11 +396,11 @@ __global__ __launch_bounds__(BS) void k_init_eq(const LevelDesc* __restrict__ lv
         }
         const Eq<S> e = eq_cast<S>(make_eq(rho, u, v, T, 0.0, 0.0, ph.compat ? a : nullptr, ph));
         const size_t row = (size_t)cell_slot[c] * L.stride;
-        S* g = rowp<S>(L.g, row);
-        S* h = rowp<S>(L.h, row);
+        auto g = rowp<S>(L.g, row);
+        auto h = rowp<S>(L.h, row);
         for (int i = lane_id(); i < L.N; i += WL) {
             S gs, hs;
-            eq_eval<S>(e, (S)L.xi_x[i], (S)L.xi_y[i], gs, hs);
+            eq_eval<S>(e, (S)gp(L.xi_x)[i], (S)gp(L.xi_y)[i], gs, hs);
             g[i] = gs;
             h[i] = hs;
         }
@@ -409,8 +416,8 @@ __global__ __launch_bounds__(BS) void k_init_eq(const LevelDesc* __restrict__ lv
 // neighbours on other levels: projection + four-moment mapping correction
 // ---------------------------------------------------------------------------
 template <typename S>
-__device__ __forceinline__ void map_correct_apply(const LevelDesc& D, S* gdst, S* hdst, const double* dM, double Ttar,
-                                  const Phys& ph, int& negflag, const S* gprov_check) {
+__device__ __forceinline__ void map_correct_apply(const LevelDesc& D, gptr<S> gdst, gptr<S> hdst, const double* dM,
+                                                  double Ttar, const Phys& ph, int& negflag) {
     const double cK = 3.0 - ph.D + ph.K;
     double rhs[4] = {dM[0], dM[1], dM[2], dM[3] - 0.5 * cK * ph.R * Ttar * dM[0]};
     double a[4];
@@ -421,7 +428,7 @@ __device__ __forceinline__ void map_correct_apply(const LevelDesc& D, S* gdst, S
     }
     const double kh = cK * ph.R * Ttar;
     for (int i = lane_id(); i < D.N; i += WL) {
-        const double x = D.xi_x[i], y = D.xi_y[i];
+        const double x = gp(D.xi_x)[i], y = gp(D.xi_y)[i];
         const double dg = a[0] + a[1] * x + a[2] * y + a[3] * (x * x + y * y);
         const S gp = gdst[i];
         const S gn = (S)((double)gp + dg);
@@ -429,7 +436,6 @@ __device__ __forceinline__ void map_correct_apply(const LevelDesc& D, S* gdst, S
         gdst[i] = gn;
         hdst[i] = (S)((double)hdst[i] + kh * dg);
     }
-    (void)gprov_check;
 }
 
 template <typename S>
@@ -442,29 +448,29 @@ __global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs,
         const LevelDesc& Ls = lvs[cell_lev[G.n]];
         const LevelDesc& Ld = lvs[G.dst];
         const size_t srow = (size_t)cell_slot[G.n] * Ls.stride;
-        const S* sg = rowp<S>(Ls.fg, srow);
-        const S* sh = rowp<S>(Ls.fh, srow);
-        S* dg = rowp<S>(Ld.fg, (size_t)(Ld.n_rows_state + G.row) * Ld.stride);
-        S* dh = rowp<S>(Ld.fh, (size_t)(Ld.n_rows_state + G.row) * Ld.stride);
+        auto sg = rowp<S>(Ls.fg, srow);
+        auto sh = rowp<S>(Ls.fh, srow);
+        auto dg = rowp<S>(Ld.fg, (size_t)(Ld.n_rows_state + G.row) * Ld.stride);
+        auto dh = rowp<S>(Ld.fh, (size_t)(Ld.n_rows_state + G.row) * Ld.stride);
         double m[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) m[k] = 0.0;
         for (int i = lane_id(); i < Ls.N; i += WL) {       // target: moments on the source level
-            const double x = Ls.xi_x[i], y = Ls.xi_y[i], w = Ls.w[i];
+            const double x = gp(Ls.xi_x)[i], y = gp(Ls.xi_y)[i], w = gp(Ls.w)[i];
             const double wg = w * (double)sg[i];
             m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += 0.5 * (wg * (x * x + y * y) + w * (double)sh[i]);
         }
         for (int P = lane_id(); P < Ld.N; P += WL) {       // provisional projection
             double gP = 0.0, HP = 0.0;
-            for (int e = G.tab.off[P]; e < G.tab.off[P + 1]; ++e) {
-                const int a = G.tab.idx[e];
-                const double fr = G.tab.frac[e];
+            for (int e = gp(G.tab.off)[P]; e < gp(G.tab.off)[P + 1]; ++e) {
+                const int a = gp(G.tab.idx)[e];
+                const double fr = gp(G.tab.frac)[e];
                 const double ga = (double)sg[a];
-                const double xa = Ls.xi_x[a], ya = Ls.xi_y[a];
+                const double xa = gp(Ls.xi_x)[a], ya = gp(Ls.xi_y)[a];
                 gP += fr * ga;
                 HP += fr * ((double)sh[a] + (xa * xa + ya * ya) * ga);
             }
-            const double x = Ld.xi_x[P], y = Ld.xi_y[P], w = Ld.w[P];
+            const double x = gp(Ld.xi_x)[P], y = gp(Ld.xi_y)[P], w = gp(Ld.w)[P];
             const double hP = HP - (x * x + y * y) * gP;
             const S gs = (S)gP, hs = (S)hP;
             dg[P] = gs;
@@ -476,7 +482,7 @@ __global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs,
         int nf = 0;
         if (ph.map_moments) {
             const double dM[4] = {m[0] - m[4], m[1] - m[5], m[2] - m[6], m[3] - m[7]};
-            map_correct_apply<S>(Ld, dg, dh, dM, params[(size_t)G.n * NPARAM + P_T], ph, nf, nullptr);
+            map_correct_apply<S>(Ld, dg, dh, dM, params[(size_t)G.n * NPARAM + P_T], ph, nf);
         }
         nf = __any(nf);
         if (lane_id() == 0 && nf) atomicAdd(neg, 1ull);
@@ -486,15 +492,22 @@ __global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs,
 // ---------------------------------------------------------------------------
 // same-level faces
 // ---------------------------------------------------------------------------
+// van Leer's limited slope from two one-sided slopes: 2ab/(a+b) where they
+// agree in sign, else 0.  Written without a branch (the division runs on every
+// lane with a safe denominator) so the stencil loads around it stay batched.
+__device__ __forceinline__ double vl_div(double n, double d) { return n / d; }
+__device__ __forceinline__ float vl_div(float n, float d) { return n * __builtin_amdgcn_rcpf(d); }
 template <typename C>
 __device__ __forceinline__ C van_leer(C a, C b) {
     const C p = a * b;
-    return p > C(0) ? C(2) * p / (a + b) : C(0);
+    const bool pos = p > C(0);
+    const C q = vl_div(C(2) * p, pos ? a + b : C(1));
+    return pos ? q : C(0);
 }
 
 template <typename S>
 struct Side {                       // one cell's reconstruction stencil on its level
-    const S* base[2];               // the level's phi_bar+ buffers (g, h)
+    gptr<const S> base[2];          // the level's phi_bar+ buffers (g, h)
     size_t off[5];                  // element offsets of the rows: own, W, E, S, N
     S G[4], id[4];                  // [t_i; t_j]^-1 and 1/|x_n - x_c|
     S dx, dy;                       // x_f - x_cell
@@ -511,8 +524,8 @@ __device__ __forceinline__ size_t nb_off(const LevelDesc& L, int code, const int
 template <typename S>
 __device__ __forceinline__ void load_side(Side<S>& sd, const LevelDesc& L, int cell, const int* cell_slot,
                                           const int* cell_nbr, const CellGeom* geom, double dx, double dy) {
-    sd.base[0] = reinterpret_cast<const S*>(L.fg);
-    sd.base[1] = reinterpret_cast<const S*>(L.fh);
+    sd.base[0] = gp(reinterpret_cast<const S*>(L.fg));
+    sd.base[1] = gp(reinterpret_cast<const S*>(L.fh));
     const size_t own = (size_t)cell_slot[cell] * L.stride;
     sd.off[0] = own;
 #pragma unroll
@@ -542,7 +555,7 @@ template <typename S>
 __device__ __forceinline__ void side_slope(const Side<S>& sd, int i, S (&f)[2], S (&sx)[2], S (&sy)[2]) {
 #pragma unroll
     for (int comp = 0; comp < 2; ++comp) {
-        const S* B = sd.base[comp] + i;
+        const auto B = sd.base[comp] + i;
         const S fv = B[sd.off[0]];
         S sl[2];
 #pragma unroll
@@ -602,7 +615,7 @@ template <typename S>
 __device__ __forceinline__ void load_stencil(const Side<S>& a, const Side<S>& b, bool useA, int i, Stencil<S>& st) {
 #pragma unroll
     for (int comp = 0; comp < 2; ++comp) {
-        const S* B = a.base[comp] + i;
+        const auto B = a.base[comp] + i;
 #pragma unroll
         for (int k = 0; k < 5; ++k) st.v[comp][k] = B[useA ? a.off[k] : b.off[k]];
     }
@@ -649,8 +662,8 @@ __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restri
         const FaceItem F = items[it];
         const LevelDesc& L = lvs[F.lev];
         const int N = L.N;
-        S* rg = rowp<S>(L.Fg, (size_t)F.row * L.stride);
-        S* rh = rowp<S>(L.Fh, (size_t)F.row * L.stride);
+        auto rg = rowp<S>(L.Fg, (size_t)F.row * L.stride);
+        auto rh = rowp<S>(L.Fh, (size_t)F.row * L.stride);
         Side<S> sL;
         load_side<S>(sL, L, F.L, cell_slot, cell_nbr, geom, F.dLx, F.dLy);
         double* out = fmom + (size_t)it * 12;
@@ -672,8 +685,8 @@ __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restri
 #pragma unroll
             for (int q = 0; q < U; ++q) {
                 const int i = i0 + q * WL, ic = clampi(i, N);
-                xv[q] = L.xi_x[ic]; yv[q] = L.xi_y[ic];
-                wv[q] = i < N ? L.w[ic] : 0.0;
+                xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
+                wv[q] = i < N ? gp(L.w)[ic] : 0.0;
                 up[q] = xv[q] * F.nx + yv[q] * F.ny >= 0.0;
                 load_stencil<S>(sL, sR, up[q], ic, st[q]);
             }
@@ -759,8 +772,8 @@ __global__ __launch_bounds__(BS, MINW) void k_face_target(const LevelDesc* __res
 #pragma unroll
                     for (int q = 0; q < U; ++q) {
                         const int i = i0 + q * WL, ic = clampi(i, N);
-                        xv[q] = L.xi_x[ic]; yv[q] = L.xi_y[ic];
-                        wv[q] = i < N ? L.w[ic] : 0.0;
+                        xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
+                        wv[q] = i < N ? gp(L.w)[ic] : 0.0;
                     }
 #pragma unroll
                     for (int q = 0; q < U; ++q) {
@@ -827,10 +840,10 @@ __global__ __launch_bounds__(BS, MINW) void k_update(const LevelDesc* __restrict
         const LevelDesc& L = lvs[cell_lev[c]];
         const int N = L.N;
         const size_t row = (size_t)cell_slot[c] * L.stride;
-        S* g = rowp<S>(L.g, row);
-        S* h = rowp<S>(L.h, row);
-        const S* fg = rowp<S>(L.fg, row);
-        const S* fh = rowp<S>(L.fh, row);
+        auto g = rowp<S>(L.g, row);
+        auto h = rowp<S>(L.h, row);
+        auto fg = rowp<S>(L.fg, row);
+        auto fh = rowp<S>(L.fh, row);
         int code[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) code[k] = cell_frow[4 * c + k];
@@ -845,8 +858,8 @@ __global__ __launch_bounds__(BS, MINW) void k_update(const LevelDesc* __restrict
 #pragma unroll
             for (int q = 0; q < U; ++q) {
                 const int i = i0 + q * WL, ic = clampi(i, N);
-                xv[q] = L.xi_x[ic]; yv[q] = L.xi_y[ic];
-                wv[q] = i < N ? L.w[ic] : 0.0;
+                xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
+                wv[q] = i < N ? gp(L.w)[ic] : 0.0;
                 bg[q] = fg[ic]; bh[q] = fh[ic];
                 go[q] = g[ic]; ho[q] = h[ic];
                 ag[q] = S(0); ah[q] = S(0);
@@ -858,8 +871,8 @@ __global__ __launch_bounds__(BS, MINW) void k_update(const LevelDesc* __restrict
                 const S sgn = (cd & 1) ? S(-1) : S(1);
                 if (cd & 2) {
                     const size_t r = (size_t)(cd >> 2) * L.stride;
-                    const S* Fg = rowp<S>(L.Fg, r);
-                    const S* Fh = rowp<S>(L.Fh, r);
+                    auto Fg = rowp<S>(L.Fg, r);
+                    auto Fh = rowp<S>(L.Fh, r);
                     S vg[U], vh[U];
 #pragma unroll
                     for (int q = 0; q < U; ++q) {
@@ -873,8 +886,8 @@ __global__ __launch_bounds__(BS, MINW) void k_update(const LevelDesc* __restrict
                 const double* fp = fpar + (size_t)(cd >> 2) * NFP;
                 const int kind = __builtin_amdgcn_readfirstlane((int)fp[FP_KIND]);
                 const size_t r = (size_t)items[cd >> 2].row * L.stride;
-                const S* Fg = rowp<S>(L.Fg, r);
-                const S* Fh = rowp<S>(L.Fh, r);
+                auto Fg = rowp<S>(L.Fg, r);
+                auto Fh = rowp<S>(L.Fh, r);
                 const double nx = fp[FP_NX], ny = fp[FP_NY];
                 const S k1 = uni((S)fp[FP_C1]), k2 = uni((S)fp[FP_C2]);
                 S vg[U], vh[U];
@@ -948,12 +961,12 @@ __global__ __launch_bounds__(BS) void k_cell_moments(const LevelDesc* __restrict
     for (int c = item0(); c < n_cells; c += istride()) {
         const LevelDesc& L = lvs[cell_lev[c]];
         const size_t row = (size_t)cell_slot[c] * L.stride;
-        const S* g = rowp<S>(L.g, row);
-        const S* h = rowp<S>(L.h, row);
+        auto g = rowp<S>(L.g, row);
+        auto h = rowp<S>(L.h, row);
         double m[11];
 #pragma unroll
         for (int k = 0; k < 11; ++k) m[k] = 0.0;
-        for (int i = lane_id(); i < L.N; i += WL) acc_raw<S>(m, L.w[i], L.xi_x[i], L.xi_y[i], g[i], h[i]);
+        for (int i = lane_id(); i < L.N; i += WL) acc_raw<S>(m, gp(L.w)[i], gp(L.xi_x)[i], gp(L.xi_y)[i], g[i], h[i]);
         wave_sum<11>(m);
         if (lane_id() == 0) {
             double rho, u, v, T, qx, qy;
@@ -1004,10 +1017,10 @@ __global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv,
         const RemapItem R = items[it];
         const LevelDesc& Ls = olv[R.src_lev];
         const LevelDesc& Ld = nlv[R.dst_lev];
-        const S* sg = rowp<S>(Ls.g, (size_t)R.src_slot * Ls.stride);
-        const S* sh = rowp<S>(Ls.h, (size_t)R.src_slot * Ls.stride);
-        S* dg = rowp<S>(Ld.g, (size_t)R.dst_slot * Ld.stride);
-        S* dh = rowp<S>(Ld.h, (size_t)R.dst_slot * Ld.stride);
+        auto sg = rowp<S>(Ls.g, (size_t)R.src_slot * Ls.stride);
+        auto sh = rowp<S>(Ls.h, (size_t)R.src_slot * Ls.stride);
+        auto dg = rowp<S>(Ld.g, (size_t)R.dst_slot * Ld.stride);
+        auto dh = rowp<S>(Ld.h, (size_t)R.dst_slot * Ld.stride);
         if (R.tab.off == nullptr) {
             for (int i = lane_id(); i < Ld.N; i += WL) { dg[i] = sg[i]; dh[i] = sh[i]; }
             continue;
@@ -1016,21 +1029,21 @@ __global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv,
 #pragma unroll
         for (int k = 0; k < 8; ++k) m[k] = 0.0;
         for (int i = lane_id(); i < Ls.N; i += WL) {
-            const double x = Ls.xi_x[i], y = Ls.xi_y[i], w = Ls.w[i];
+            const double x = gp(Ls.xi_x)[i], y = gp(Ls.xi_y)[i], w = gp(Ls.w)[i];
             const double wg = w * (double)sg[i];
             m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += 0.5 * (wg * (x * x + y * y) + w * (double)sh[i]);
         }
         for (int P = lane_id(); P < Ld.N; P += WL) {
             double gP = 0.0, HP = 0.0;
-            for (int e = R.tab.off[P]; e < R.tab.off[P + 1]; ++e) {
-                const int a = R.tab.idx[e];
-                const double fr = R.tab.frac[e];
+            for (int e = gp(R.tab.off)[P]; e < gp(R.tab.off)[P + 1]; ++e) {
+                const int a = gp(R.tab.idx)[e];
+                const double fr = gp(R.tab.frac)[e];
                 const double ga = (double)sg[a];
-                const double xa = Ls.xi_x[a], ya = Ls.xi_y[a];
+                const double xa = gp(Ls.xi_x)[a], ya = gp(Ls.xi_y)[a];
                 gP += fr * ga;
                 HP += fr * ((double)sh[a] + (xa * xa + ya * ya) * ga);
             }
-            const double x = Ld.xi_x[P], y = Ld.xi_y[P], w = Ld.w[P];
+            const double x = gp(Ld.xi_x)[P], y = gp(Ld.xi_y)[P], w = gp(Ld.w)[P];
             const S gs = (S)gP, hs = (S)(HP - (x * x + y * y) * gP);
             dg[P] = gs;
             dh[P] = hs;
@@ -1043,7 +1056,7 @@ __global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv,
             const double rho = m[0], u = m[1] / rho, v = m[2] / rho;
             const double T = (2.0 * m[3] / rho - (u * u + v * v)) / ((3.0 + ph.K) * ph.R);
             const double dM[4] = {m[0] - m[4], m[1] - m[5], m[2] - m[6], m[3] - m[7]};
-            map_correct_apply<S>(Ld, dg, dh, dM, T, ph, nf, nullptr);
+            map_correct_apply<S>(Ld, dg, dh, dM, T, ph, nf);
         }
         nf = __any(nf);
         if (lane_id() == 0 && nf) atomicAdd(neg, 1ull);
@@ -1180,7 +1193,7 @@ template <typename S>
 __device__ __forceinline__ void side_refined(const Side<S>& sd, const LevelDesc& Ln, const LevelDesc& LI, int a,
                                              int P, S (&f)[2], S (&sx)[2], S (&sy)[2]) {
     side_slope<S>(sd, a, f, sx, sy);
-    const double xa = Ln.xi_x[a], ya = Ln.xi_y[a], xP = LI.xi_x[P], yP = LI.xi_y[P];
+    const double xa = gp(Ln.xi_x)[a], ya = gp(Ln.xi_y)[a], xP = gp(LI.xi_x)[P], yP = gp(LI.xi_y)[P];
     const S dq = (S)((xa * xa + ya * ya) - (xP * xP + yP * yP));
     f[1] = f[1] + dq * f[0];
     sx[1] = sx[1] + dq * sx[0];
@@ -1208,16 +1221,16 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
 #pragma unroll
         for (int k = 0; k < 16; ++k) m[k] = 0.0;
         for (int P = lane_id(); P < LI.N; P += WL) {
-            const double x = LI.xi_x[P], y = LI.xi_y[P], w = LI.w[P];
+            const double x = gp(LI.xi_x)[P], y = gp(LI.xi_y)[P], w = gp(LI.w)[P];
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
                 const Side<S>& sd = side ? sR : sL;
                 const LevelDesc& Ln = side ? LB : LA;
                 const PairTable& tb = side ? F.IfromB : F.IfromA;
-                const int a = tb.idx[tb.off[P]];
+                const int a = gp(tb.idx)[gp(tb.off)[P]];
                 S f[2], sx[2], sy[2];
                 side_slope<S>(sd, a, f, sx, sy);
-                const double xa = Ln.xi_x[a], ya = Ln.xi_y[a];
+                const double xa = gp(Ln.xi_x)[a], ya = gp(Ln.xi_y)[a];
                 const double ga = (double)f[0], ha = (double)f[1];
                 const double hP = ha + ((xa * xa + ya * ya) - (x * x + y * y)) * ga;
                 double* mm = m + 8 * side;
@@ -1246,15 +1259,15 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
         const double khL = cK * ph.R * TL, khR = cK * ph.R * TR;
         const double u0 = 0.5 * (params[(size_t)F.L * NPARAM + P_U] + params[(size_t)F.R * NPARAM + P_U]);
         const double v0 = 0.5 * (params[(size_t)F.L * NPARAM + P_V] + params[(size_t)F.R * NPARAM + P_V]);
-        S* rg = rowp<S>(LI.Fg, (size_t)F.scratch * LI.stride);
-        S* rh = rowp<S>(LI.Fh, (size_t)F.scratch * LI.stride);
+        auto rg = rowp<S>(LI.Fg, (size_t)F.scratch * LI.stride);
+        auto rh = rowp<S>(LI.Fh, (size_t)F.scratch * LI.stride);
         // pass 2: corrected states, upwind reconstruction on V_int, face moments
         double fm[11];
 #pragma unroll
         for (int k = 0; k < 11; ++k) fm[k] = 0.0;
         int nf = 0;
         for (int P = lane_id(); P < LI.N; P += WL) {
-            const double xd = LI.xi_x[P], yd = LI.xi_y[P];
+            const double xd = gp(LI.xi_x)[P], yd = gp(LI.xi_y)[P];
             const S x = (S)xd, y = (S)yd;
             S e[2][2];
 #pragma unroll
@@ -1262,7 +1275,7 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
                 const Side<S>& sd = side ? sR : sL;
                 const LevelDesc& Ln = side ? LB : LA;
                 const PairTable& tb = side ? F.IfromB : F.IfromA;
-                const int a = tb.idx[tb.off[P]];
+                const int a = gp(tb.idx)[gp(tb.off)[P]];
                 S f[2], sx[2], sy[2];
                 side_refined<S>(sd, Ln, LI, a, P, f, sx, sy);
                 const double* aa = side ? aR : aL;
@@ -1281,7 +1294,7 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
             else { eg = S(0.5) * (e[0][0] + e[1][0]); eh = S(0.5) * (e[0][1] + e[1][1]); }
             rg[P] = eg;
             rh[P] = eh;
-            acc_raw<S>(fm, LI.w[P], xd - u0, yd - v0, eg, eh);
+            acc_raw<S>(fm, gp(LI.w)[P], xd - u0, yd - v0, eg, eh);
         }
         wave_sum<11>(fm);
         double c1, c2;
@@ -1291,7 +1304,7 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
         double Fm[4] = {0, 0, 0, 0};
         const S k1 = (S)c1, k2 = (S)c2;
         for (int P = lane_id(); P < LI.N; P += WL) {
-            const double xd = LI.xi_x[P], yd = LI.xi_y[P], w = LI.w[P];
+            const double xd = gp(LI.xi_x)[P], yd = gp(LI.xi_y)[P], w = gp(LI.w)[P];
             S gs, hs;
             eq_eval<S>(eq, (S)xd, (S)yd, gs, hs);
             const S dn = (S)(xd * F.nx + yd * F.ny);
@@ -1313,19 +1326,19 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
         for (int side = 0; side < 2; ++side) {
             const LevelDesc& Ln = side ? LB : LA;
             const PairTable& tb = side ? F.BfromI : F.AfromI;
-            S* og = rowp<S>(Ln.Fg, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
-            S* oh = rowp<S>(Ln.Fh, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
+            auto og = rowp<S>(Ln.Fg, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
+            auto oh = rowp<S>(Ln.Fh, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
             for (int a = lane_id(); a < Ln.N; a += WL) {
                 double gA = 0.0, HA = 0.0;
-                for (int e = tb.off[a]; e < tb.off[a + 1]; ++e) {
-                    const int P = tb.idx[e];
-                    const double fr = tb.frac[e];
-                    const double xP = LI.xi_x[P], yP = LI.xi_y[P];
+                for (int e = gp(tb.off)[a]; e < gp(tb.off)[a + 1]; ++e) {
+                    const int P = gp(tb.idx)[e];
+                    const double fr = gp(tb.frac)[e];
+                    const double xP = gp(LI.xi_x)[P], yP = gp(LI.xi_y)[P];
                     const double gP = (double)rg[P];
                     gA += fr * gP;
                     HA += fr * ((double)rh[P] + (xP * xP + yP * yP) * gP);
                 }
-                const double x = Ln.xi_x[a], y = Ln.xi_y[a], w = Ln.w[a];
+                const double x = gp(Ln.xi_x)[a], y = gp(Ln.xi_y)[a], w = gp(Ln.w)[a];
                 const S gs = (S)gA, hs = (S)(HA - (x * x + y * y) * gA);
                 og[a] = gs;
                 oh[a] = hs;
@@ -1340,8 +1353,8 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const LevelDesc& Ln = side ? LB : LA;
-            S* og = rowp<S>(Ln.Fg, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
-            S* oh = rowp<S>(Ln.Fh, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
+            auto og = rowp<S>(Ln.Fg, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
+            auto oh = rowp<S>(Ln.Fh, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
             double aa[4] = {0, 0, 0, 0};
             if (ph.map_moments) {
                 const double* mm = pm + 4 * side;
@@ -1355,7 +1368,7 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
             }
             const double kh = cK * ph.R * Tf;
             for (int a = lane_id(); a < Ln.N; a += WL) {
-                const double x = Ln.xi_x[a], y = Ln.xi_y[a];
+                const double x = gp(Ln.xi_x)[a], y = gp(Ln.xi_y)[a];
                 const double dg = aa[0] + aa[1] * x + aa[2] * y + aa[3] * (x * x + y * y);
                 og[a] = ar * (S)((double)og[a] + dg);
                 oh[a] = ar * (S)((double)oh[a] + kh * dg);
@@ -1387,7 +1400,8 @@ struct CritCtx {
 };
 
 template <typename S>
-__device__ __forceinline__ bool crit_merges(const CritCtx& cc, const LevelDesc& L, const S* g, const S* h, int s, int bx, int by) {
+__device__ __forceinline__ bool crit_merges(const CritCtx& cc, const LevelDesc& L, gptr<S> g, gptr<S> h, int s, int bx,
+                                            int by) {
     const int size = 1 << s;
     double m1 = 0.0, m2 = 0.0;
     double Wb = 0.0, Wx = 0.0, Wy = 0.0, Wg = 0.0, WH = 0.0;
@@ -1398,15 +1412,15 @@ __device__ __forceinline__ bool crit_merges(const CritCtx& cc, const LevelDesc& 
         for (int ix = bx * size; ix < bx * size + size; ++ix) {
             const int b = ix + cc.nx * iy;
             const int p = cc.ptb[b];
-            const double gp = (double)g[p];
-            const double xp = L.xi_x[p], yp = L.xi_y[p];
-            const double Hb = (double)h[p] + (xp * xp + yp * yp) * gp;
+            const double gpv = (double)g[p];
+            const double xp = gp(L.xi_x)[p], yp = gp(L.xi_y)[p];
+            const double Hb = (double)h[p] + (xp * xp + yp * yp) * gpv;
             const double w = cc.bw[b], x = cc.bx[b], y = cc.by[b];
-            m1 += w * gp;
+            m1 += w * gpv;
             m2 += 0.5 * w * Hb;
             if (cc.flux_test) {
-                Wb += w; Wx += w * x; Wy += w * y; Wg += w * gp; WH += w * Hb;
-                const double mr[4] = {gp, x * gp, y * gp, 0.5 * Hb};
+                Wb += w; Wx += w * x; Wy += w * y; Wg += w * gpv; WH += w * Hb;
+                const double mr[4] = {gpv, x * gpv, y * gpv, 0.5 * Hb};
                 const double xd[2] = {x, y};
                 for (int d = 0; d < 2; ++d)
                     for (int r = 0; r < 4; ++r) {
@@ -1458,8 +1472,8 @@ __global__ __launch_bounds__(BS, 4) void k_criterion(const LevelDesc* __restrict
         const int lev = cell_lev[c];
         const LevelDesc& L = lvs[lev];
         const size_t row = (size_t)cell_slot[c] * L.stride;
-        const S* g = rowp<S>(L.g, row);
-        const S* h = rowp<S>(L.h, row);
+        auto g = rowp<S>(L.g, row);
+        auto h = rowp<S>(L.h, row);
         CritCtx cc;
         cc.ptb = ptb_all + (size_t)ptb_off[lev];
         cc.prev = kappa_all + (size_t)lev * Nb;
@@ -1470,13 +1484,13 @@ __global__ __launch_bounds__(BS, 4) void k_criterion(const LevelDesc* __restrict
         for (int k = 0; k < 10; ++k) t[k] = 0.0;
         for (int b = lane_id(); b < Nbase; b += WL) {
             const int p = cc.ptb[b];
-            const double gp = (double)g[p];
-            const double xp = L.xi_x[p], yp = L.xi_y[p];
-            const double Hb = (double)h[p] + (xp * xp + yp * yp) * gp;
+            const double gpv = (double)g[p];
+            const double xp = gp(L.xi_x)[p], yp = gp(L.xi_y)[p];
+            const double Hb = (double)h[p] + (xp * xp + yp * yp) * gpv;
             const double w = bw[b], x = bx[b], y = by[b];
-            t[0] += w * gp;
+            t[0] += w * gpv;
             t[1] += 0.5 * w * Hb;
-            const double mr[4] = {fabs(gp), fabs(x * gp), fabs(y * gp), fabs(0.5 * Hb)};
+            const double mr[4] = {fabs(gpv), fabs(x * gpv), fabs(y * gpv), fabs(0.5 * Hb)};
             for (int r = 0; r < 4; ++r) {
                 t[2 + r] += w * fabs(x) * mr[r];
                 t[6 + r] += w * fabs(y) * mr[r];
