@@ -537,14 +537,14 @@ struct mlvs_ctx_s {
     int *d_cell_lev = nullptr, *d_cell_slot = nullptr, *d_cell_nbr = nullptr, *d_cell_frow = nullptr;
     CellGeom* d_geom = nullptr;
     double* d_params = nullptr;
-    double* d_cmom = nullptr;          // [n_cells][NMOM] raw moments of the stored state
+    double* d_cmom = nullptr;
+    double* d_fmom = nullptr;          // [faces + boundary faces][NFMOM] face moments          // [n_cells][NMOM] raw moments of the stored state
     double* d_fpar = nullptr;          // [faces + boundary faces][NFP] face records
     bool mom_valid = false;            // d_cmom matches the stored state
     BCDev* d_bcs = nullptr;
     LevelDesc* d_lv = nullptr;
     FaceItem* d_faces = nullptr; int n_faces = 0;    // interior same-level faces, then boundary faces
     int n_bfaces = 0;
-    double* d_fmom = nullptr;
     GhostItem* d_ghosts = nullptr; int n_ghosts = 0;
     XFaceItem* d_xfaces = nullptr; int n_xfaces = 0;
     std::vector<DevTable> tables;                    // owned by the current level set
@@ -802,7 +802,7 @@ void build_items(mlvs_ctx c) {
     c->n_bfaces = (int)bfaces.size();
     faces.insert(faces.end(), bfaces.begin(), bfaces.end());
     c->d_faces = upload_item(c, faces);
-    c->d_fmom = static_cast<double*>(c->dm.alloc(sizeof(double) * 12 * std::max<size_t>(faces.size(), 1)));
+    c->d_fmom = static_cast<double*>(c->dm.alloc(sizeof(double) * NFMOM * std::max<size_t>(faces.size(), 1)));
     c->item_allocs.push_back(c->d_fmom);
     c->d_fpar = static_cast<double*>(c->dm.alloc(sizeof(double) * NFP * std::max<size_t>(faces.size(), 1)));
     c->item_allocs.push_back(c->d_fpar);
@@ -1919,17 +1919,21 @@ hipError_t launch_step_kernels(mlvs_ctx c) {
     return hipSuccess;
 }
 
+// Stages of the step: 0 cell, 1 neighbour mapping (ghost rows), 2 face
+// reconstruction and 3 face target (same-level and boundary faces), 4
+// cross-level faces, 5 update.  6 (criterion) is timed apart.
 hipError_t launch_stage(mlvs_ctx c, int stage) {
     const int n = c->mesh.n_cells;
+    const int nf = c->n_faces + c->n_bfaces;
     switch (stage) {
     case 0: return launch_cell_prep(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->ph, c->d_params,
                                     c->d_cmom, c->variant[0]);
     case 1: return launch_ghost(c->prec, c->st, c->d_lv, c->d_ghosts, c->n_ghosts, c->d_cell_lev, c->d_cell_slot,
                                 c->d_params, c->ph, c->d_neg);
-    case 2: return launch_face_rec(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces + c->n_bfaces, c->d_cell_slot,
-                                   c->d_cell_nbr, c->d_geom, c->d_params, c->ph, c->d_fmom, c->variant[2]);
-    case 3: return launch_face_target(c->prec, c->st, c->d_lv, c->d_faces, c->n_faces + c->n_bfaces, c->d_params,
-                                      c->d_bcs, c->ph, c->d_fmom, c->d_fpar, c->variant[3]);
+    case 2: return launch_face_rec(c->prec, c->st, c->d_lv, c->d_faces, nf, c->d_cell_slot, c->d_cell_nbr, c->d_geom,
+                                   c->d_params, c->ph, c->d_fmom, c->variant[2]);
+    case 3: return launch_face_target(c->prec, c->st, c->d_lv, c->d_faces, nf, c->d_bcs, c->ph, c->d_fmom,
+                                      c->d_fpar, c->variant[3]);
     case 4: return launch_xface(c->prec, c->st, c->d_lv, c->d_xfaces, c->n_xfaces, c->d_cell_slot, c->d_cell_nbr,
                                 c->d_geom, c->d_params, c->ph, c->d_neg, c->variant[4]);
     case 5: return launch_update(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom,

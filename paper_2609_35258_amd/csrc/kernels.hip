@@ -49,15 +49,36 @@ __device__ __forceinline__ float uni(float x) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
-// Sum NV doubles over the wavefront; every lane receives the totals.
+// A double moved across lanes by a DPP pattern (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double read_lane(double x, int lane) {
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum NV doubles over the wavefront (all lanes active); every lane receives
+// the totals.  Within each row of 16 lanes: DPP exchanges with lane^1, lane^2,
+// the mirrored lane of the half row and of the row (each lane then holds its
+// row's sum; every step adds two equal-order operands, so all lanes of a row
+// agree bit for bit); the four row sums are then combined in a fixed order.
 template <int NV>
 __device__ __forceinline__ void wave_sum(double (&v)[NV]) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double x = v[k];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, WL);
-        v[k] = x;
+        x += dpp_mov<0xB1>(x);     // quad_perm [1,0,3,2]
+        x += dpp_mov<0x4E>(x);     // quad_perm [2,3,0,1]
+        x += dpp_mov<0x141>(x);    // row_half_mirror
+        x += dpp_mov<0x140>(x);    // row_mirror
+        v[k] = (read_lane(x, 0) + read_lane(x, 16)) + (read_lane(x, 32) + read_lane(x, 48));
     }
 }
 
@@ -208,12 +229,11 @@ __device__ __forceinline__ void eq_eval(const Eq<C>& e, C x, C y, C& g, C& h) {
 // (a valid address) and their weight is zero.
 __device__ __forceinline__ int clampi(int i, int N) { return i < N ? i : N - 1; }
 
-// Compatibility correction (Sec. 3.3.1): assemble A and the moment defect of
-// the uncorrected target over the level, solve, return a[4] (a[2] = 0 in 1-D).
+// Compatibility correction (Sec. 3.3.1), part 1: the thirteen velocity sums of
+// the uncorrected target over the level that the 4x4 system needs (wave per
+// item; every lane receives the totals).
 template <typename S, int U>
-__device__ __forceinline__ void compat_solve(const LevelDesc& L, const Eq<S>& eu, double rho, double u, double v,
-                                             double T, const Phys& ph, double* a_out) {
-    double s[13];
+__device__ __forceinline__ void compat_sums(const LevelDesc& L, const Eq<S>& eu, double (&s)[13]) {
 #pragma unroll
     for (int k = 0; k < 13; ++k) s[k] = 0.0;
     const int N = L.N;
@@ -238,6 +258,12 @@ __device__ __forceinline__ void compat_solve(const LevelDesc& L, const Eq<S>& eu
         }
     }
     wave_sum<13>(s);
+}
+
+// Part 2 (one lane per item): assemble A and the moment defect from the sums,
+// solve, return a[4] (a[2] = 0 in 1-D).
+__device__ __forceinline__ void compat_from_sums(const double* s, double rho, double u, double v, double T,
+                                                 const Phys& ph, double* a_out) {
     const double E0 = 0.5 * (3.0 - ph.D + ph.K) * ph.R * T;
     const double sx2 = s[3] + s[5];
     const double rhoE = 0.5 * rho * (u * u + v * v) + 0.5 * (3.0 + ph.K) * rho * ph.R * T;
@@ -249,7 +275,7 @@ __device__ __forceinline__ void compat_solve(const LevelDesc& L, const Eq<S>& eu
                            E0 * 0.5 * (sx2 + s[9]) + 0.5 * (0.5 * s[8] + 0.5 * s[12])}};
         double b[4] = {rho - s[0], rho * u - s[1], rho * v - s[2], rhoE - 0.5 * (sx2 + s[9])};
         solve_fixed<4>(A, b);
-        a_out[0] = uni(b[0]); a_out[1] = uni(b[1]); a_out[2] = uni(b[2]); a_out[3] = uni(b[3]);
+        a_out[0] = b[0]; a_out[1] = b[1]; a_out[2] = b[2]; a_out[3] = b[3];
     } else {
         double A[3][3] = {{s[0], s[1], E0 * s[0] + 0.5 * sx2},
                           {s[1], s[3], E0 * s[1] + 0.5 * s[6]},
@@ -257,8 +283,19 @@ __device__ __forceinline__ void compat_solve(const LevelDesc& L, const Eq<S>& eu
                            E0 * 0.5 * (sx2 + s[9]) + 0.5 * (0.5 * s[8] + 0.5 * s[12])}};
         double b[3] = {rho - s[0], rho * u - s[1], rhoE - 0.5 * (sx2 + s[9])};
         solve_fixed<3>(A, b);
-        a_out[0] = uni(b[0]); a_out[1] = uni(b[1]); a_out[2] = 0.0; a_out[3] = uni(b[2]);
+        a_out[0] = b[0]; a_out[1] = b[1]; a_out[2] = 0.0; a_out[3] = b[2];
     }
+}
+
+// Both parts in one wave (every lane solves the same system).
+template <typename S, int U>
+__device__ __forceinline__ void compat_solve(const LevelDesc& L, const Eq<S>& eu, double rho, double u, double v,
+                                             double T, const Phys& ph, double* a_out) {
+    double s[13];
+    compat_sums<S, U>(L, eu, s);
+    compat_from_sums(s, rho, u, v, T, ph, a_out);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a_out[k] = uni(a_out[k]);
 }
 
 // Eleven raw moments of (g, h) at velocity (x, y) taken about a shift (the
@@ -273,71 +310,120 @@ __device__ __forceinline__ void acc_raw(double* m, double w, double x, double y,
 }
 
 // ---------------------------------------------------------------------------
-// cell stage: W, q, tau, compatibility coefficients, phi_bar+ rows.  The raw
-// moments of g~, h~ come from cmom (written by the previous update, or by
-// k_raw_moments after the state was set from outside).
+// Staged kernels.  A workgroup of GW waves takes GW items.  Velocity passes run
+// with one wave per item (lanes over the item's points); the per-item scalar
+// steps (state, relaxation time, the small solves) run once per item on one
+// lane of wave 0, and the two kinds of step hand their results over through
+// LDS.  The scalar work is not repeated on 64 lanes.
 // ---------------------------------------------------------------------------
+constexpr int GW = 8;
+constexpr int GBS = GW * WL;
+
+// Cell state from the raw moments (Eqs. W_from_tilde, discrete_q): W, tau,
+// q = 2 tau q~/(2 tau + dt Pr), and the update weights
+// alpha = (2 tau - s)/(2 tau + dt), beta = 3 s/(2 tau + dt), s = dt/2.
+struct CellState { double rho, u, v, T, qx, qy, tau, alpha, beta; };
+
+__device__ __forceinline__ CellState cell_state(const double* cm, const Phys& ph) {
+    double m[11];
+#pragma unroll
+    for (int k = 0; k < 11; ++k) m[k] = cm[k];
+    CellState c;
+    raw_to_state(m, cm[M_U0], cm[M_V0], ph, c.rho, c.u, c.v, c.T, c.qx, c.qy);
+    const double p = c.rho * ph.R * c.T;
+    c.tau = viscosity(c.T, ph) / p;
+    const double dt = ph.dt, s = 0.5 * dt;
+    c.qx = 2.0 * c.tau * c.qx / (2.0 * c.tau + dt * ph.Pr);
+    c.qy = 2.0 * c.tau * c.qy / (2.0 * c.tau + dt * ph.Pr);
+    c.alpha = (2.0 * c.tau - s) / (2.0 * c.tau + dt);
+    c.beta = 3.0 * s / (2.0 * c.tau + dt);
+    return c;
+}
+
+// Cell stage: W, q, tau, compatibility coefficients (written to params) and
+// the rows phi_bar+ = alpha phi~ + beta phi_S* (Eq. g_h_eq_Pr with the
+// correction of Sec. 3.3.1).  The raw moments of g~, h~ come from cmom (the
+// previous update, or k_raw_moments after the state was set from outside).
 template <typename S, int U, int MINW>
-__global__ __launch_bounds__(BS, MINW) void k_cell_prep(const LevelDesc* __restrict__ lvs,
-                                                        const int* __restrict__ cell_lev,
-                                                        const int* __restrict__ cell_slot, int n_cells, Phys ph,
-                                                        double* __restrict__ params,
-                                                        const double* __restrict__ cmom) {
-    for (int c = item0(); c < n_cells; c += istride()) {
-        const LevelDesc& L = lvs[cell_lev[c]];
-        const int N = L.N;
-        const size_t row = (size_t)cell_slot[c] * L.stride;
-        auto g = rowp<S>(L.g, row);
-        auto h = rowp<S>(L.h, row);
-        const double* cm = cmom + (size_t)c * NMOM;
-        double m[11];
-#pragma unroll
-        for (int k = 0; k < 11; ++k) m[k] = cm[k];
-        double rho, u, v, T, qx, qy;
-        raw_to_state(m, cm[M_U0], cm[M_V0], ph, rho, u, v, T, qx, qy);
-        const double p = rho * ph.R * T;
-        const double tau = viscosity(T, ph) / p;
-        const double dt = ph.dt, s = 0.5 * dt;
-        qx = 2.0 * tau * qx / (2.0 * tau + dt * ph.Pr);
-        qy = 2.0 * tau * qy / (2.0 * tau + dt * ph.Pr);
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
-        if (ph.compat) {
-            const Eq<S> eu = eq_cast<S>(make_eq(rho, u, v, T, qx, qy, nullptr, ph));
-            compat_solve<S, U>(L, eu, rho, u, v, T, ph, a);
+__global__ __launch_bounds__(GBS, MINW) void k_cell_prep(const LevelDesc* __restrict__ lvs,
+                                                         const int* __restrict__ cell_lev,
+                                                         const int* __restrict__ cell_slot, int n_cells, Phys ph,
+                                                         double* __restrict__ params,
+                                                         const double* __restrict__ cmom) {
+    __shared__ CellState sh_c[GW];
+    __shared__ Eq<double> sh_e[GW];
+    __shared__ double sh_s[GW][13];
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave index (uniform)
+    const int t = threadIdx.x;
+    for (int g0 = wg_index() * GW; g0 < n_cells; g0 += gridDim.x * GW) {
+        // scalar: state and the uncorrected target, one lane per cell
+        if (t < GW && g0 + t < n_cells) {
+            const CellState cs = cell_state(cmom + (size_t)(g0 + t) * NMOM, ph);
+            sh_c[t] = cs;
+            sh_e[t] = make_eq(cs.rho, cs.u, cs.v, cs.T, cs.qx, cs.qy, nullptr, ph);
         }
-        const double alpha = (2.0 * tau - s) / (2.0 * tau + dt);
-        const double beta = 3.0 * s / (2.0 * tau + dt);
-        const Eq<S> e = eq_cast<S>(make_eq(rho, u, v, T, qx, qy, ph.compat ? a : nullptr, ph));
-        auto fg = rowp<S>(L.fg, row);
-        auto fh = rowp<S>(L.fh, row);
-        const S al = uni((S)alpha), be = uni((S)beta);
-        for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
-            S gv[U], hv[U], xv[U], yv[U];
+        __syncthreads();
+        const int c = g0 + w;
+        // velocity pass: the compatibility sums, one wave per cell
+        if (ph.compat && c < n_cells) {
+            const LevelDesc& L = lvs[cell_lev[c]];
+            double sm[13];
+            compat_sums<S, U>(L, eq_cast<S>(sh_e[w]), sm);
+            if (lane_id() < 13) {
 #pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const int ic = clampi(i0 + q * WL, N);
-                gv[q] = g[ic]; hv[q] = h[ic];
-                xv[q] = (S)gp(L.xi_x)[ic]; yv[q] = (S)gp(L.xi_y)[ic];
-            }
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                S gs, hs;
-                eq_eval<S>(e, xv[q], yv[q], gs, hs);
-                gv[q] = al * gv[q] + be * gs;
-                hv[q] = al * hv[q] + be * hs;
-            }
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const int i = i0 + q * WL;
-                if (i < N) { fg[i] = gv[q]; fh[i] = hv[q]; }
+                for (int k = 0; k < 13; ++k)
+                    if (lane_id() == k) sh_s[w][k] = sm[k];
             }
         }
-        if (lane_id() == 0) {
-            double* pr = params + (size_t)c * NPARAM;
-            pr[P_RHO] = rho; pr[P_U] = u; pr[P_V] = v; pr[P_T] = T; pr[P_QX] = qx; pr[P_QY] = qy;
-            pr[P_TAU] = tau; pr[P_A0] = a[0]; pr[P_A1] = a[1]; pr[P_A2] = a[2]; pr[P_A3] = a[3];
-            pr[P_ALPHA] = alpha; pr[P_BETA] = beta;
+        __syncthreads();
+        // scalar: solve, corrected target, parameters
+        if (t < GW && g0 + t < n_cells) {
+            const CellState cs = sh_c[t];
+            double a[4] = {0.0, 0.0, 0.0, 0.0};
+            if (ph.compat) {
+                compat_from_sums(sh_s[t], cs.rho, cs.u, cs.v, cs.T, ph, a);
+                sh_e[t] = make_eq(cs.rho, cs.u, cs.v, cs.T, cs.qx, cs.qy, a, ph);
+            }
+            double* pr = params + (size_t)(g0 + t) * NPARAM;
+            pr[P_RHO] = cs.rho; pr[P_U] = cs.u; pr[P_V] = cs.v; pr[P_T] = cs.T; pr[P_QX] = cs.qx;
+            pr[P_QY] = cs.qy; pr[P_TAU] = cs.tau; pr[P_A0] = a[0]; pr[P_A1] = a[1]; pr[P_A2] = a[2];
+            pr[P_A3] = a[3]; pr[P_ALPHA] = cs.alpha; pr[P_BETA] = cs.beta;
         }
+        __syncthreads();
+        // velocity pass: the phi_bar+ rows
+        if (c < n_cells) {
+            const LevelDesc& L = lvs[cell_lev[c]];
+            const int N = L.N;
+            const size_t row = (size_t)cell_slot[c] * L.stride;
+            auto g = rowp<S>(L.g, row);
+            auto h = rowp<S>(L.h, row);
+            auto fg = rowp<S>(L.fg, row);
+            auto fh = rowp<S>(L.fh, row);
+            const Eq<S> e = eq_cast<S>(sh_e[w]);
+            const S al = uni((S)sh_c[w].alpha), be = uni((S)sh_c[w].beta);
+            for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
+                S gv[U], hv[U], xv[U], yv[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const int ic = clampi(i0 + q * WL, N);
+                    gv[q] = g[ic]; hv[q] = h[ic];
+                    xv[q] = (S)gp(L.xi_x)[ic]; yv[q] = (S)gp(L.xi_y)[ic];
+                }
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    S gs, hs;
+                    eq_eval<S>(e, xv[q], yv[q], gs, hs);
+                    gv[q] = al * gv[q] + be * gs;
+                    hv[q] = al * hv[q] + be * hs;
+                }
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const int i = i0 + q * WL;
+                    if (i < N) { fg[i] = gv[q]; fh[i] = hv[q]; }
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -643,12 +729,33 @@ __device__ __forceinline__ void stencil_ext(const Side<S>& a, const Side<S>& b, 
     eh = e[1];
 }
 
+// Face state from the raw moments of phi_bar_f (Eq. W_from_bar): W_f, tau_f,
+// q_f = 2 tau_f q_bar/(2 tau_f + s Pr) and the recovery weights c1 = 2 tau_f /
+// (2 tau_f + s), c2 = s/(2 tau_f + s) of Eq. recover_phi (one lane per face).
+struct FaceState { double rho, u, v, T, qx, qy, c1, c2; };
+
+__device__ __forceinline__ FaceState face_state(const double* mm, double u0, double v0, const Phys& ph) {
+    double m[11];
+#pragma unroll
+    for (int k = 0; k < 11; ++k) m[k] = mm[k];
+    FaceState f;
+    raw_to_state(m, u0, v0, ph, f.rho, f.u, f.v, f.T, f.qx, f.qy);
+    const double s = 0.5 * ph.dt;
+    const double tau = viscosity(f.T, ph) / (f.rho * ph.R * f.T);
+    f.qx = 2.0 * tau * f.qx / (2.0 * tau + s * ph.Pr);
+    f.qy = 2.0 * tau * f.qy / (2.0 * tau + s * ph.Pr);
+    f.c1 = 2.0 * tau / (2.0 * tau + s);
+    f.c2 = s / (2.0 * tau + s);
+    return f;
+}
+
 // Face stage, part 1 (reconstruction): for every same-level interior face and
 // every boundary face, the interface value phi_bar_f = phi_bar+_up + (x_f -
 // x_up - xi s) . sigma_up (both sides averaged where xi . n = 0) is written to
 // the face row.  Interior faces also reduce the eleven raw moments of phi_bar_f
 // (about the mean of the two cell velocities); boundary faces reduce the
-// outgoing mass flux.  Per-face results go to fmom[item][12].
+// outgoing mass flux.  Per-face results go to fmom[item][NFMOM] (the moments,
+// then the velocity shift they are taken about).
 template <typename S, int U, int MINW>
 __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restrict__ lvs,
                                                        const FaceItem* __restrict__ items, int n,
@@ -666,7 +773,7 @@ __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restri
         auto rh = rowp<S>(L.Fh, (size_t)F.row * L.stride);
         Side<S> sL;
         load_side<S>(sL, L, F.L, cell_slot, cell_nbr, geom, F.dLx, F.dLy);
-        double* out = fmom + (size_t)it * 12;
+        double* out = fmom + (size_t)it * NFMOM;
         const bool interior = F.R >= 0;
         Side<S> sR = sL;
         double u0 = 0.0, v0 = 0.0;
@@ -724,49 +831,72 @@ __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restri
             for (int k = 0; k < 11; ++k)
                 if (lane_id() == k) out[k] = m[k];
         }
+        if (lane_id() == 0) { out[11] = u0; out[12] = v0; }
     }
 }
 
-// Face stage, part 2 (target): per face, the parameters the update needs to
-// finish the flux F = A_f (xi . n) phi_f at every velocity.  Interior faces:
-// the face state from the reduced moments, the corrected face target and the
-// recovery weights (Eq. recover_phi).  Boundary faces (outward normal):
-// outgoing velocities carry the interior reconstruction, incoming ones the
-// boundary state -- diffuse wall rho_w g_eq(u_w, T_w) with rho_w from zero net
-// mass flux, far-field Maxwellian, or the cell's phi_bar+ (zero-gradient
-// outflow).  Record layout: FP_* (mlvs_impl.h).
+// Face stage, part 2 (target), staged as the cell stage, for the same faces:
+//  (lane per face) the face state and the uncorrected target;
+//  (wave per face) the compatibility sums of the target; for a diffuse wall
+//     the incoming mass flux of the wall Maxwellian;
+//  (lane per face) the record the update needs to finish F = A_f (xi . n)
+//     phi_f at every velocity (layout FP_*).  Interior faces: corrected target
+//     and recovery weights (Eq. recover_phi).  Boundary faces (outward normal):
+//     outgoing velocities carry the reconstruction, incoming ones the boundary
+//     state -- diffuse wall rho_w g_eq(u_w, T_w) with rho_w from zero net mass
+//     flux, far-field Maxwellian, or the cell's phi_bar+ (zero-gradient
+//     outflow).
 template <typename S, int U, int MINW>
-__global__ __launch_bounds__(BS, MINW) void k_face_target(const LevelDesc* __restrict__ lvs,
-                                                          const FaceItem* __restrict__ items, int n,
-                                                          const double* __restrict__ params,
-                                                          const BCDev* __restrict__ bcs, Phys ph,
-                                                          const double* __restrict__ fmom,
-                                                          double* __restrict__ fpar) {
-    for (int it = item0(); it < n; it += istride()) {
-        const FaceItem F = items[it];
-        const LevelDesc& L = lvs[F.lev];
-        const double* mm = fmom + (size_t)it * 12;
-        Eq<double> e = make_eq(1.0, 0.0, 0.0, 1.0, 0.0, 0.0, nullptr, ph);
-        double kind = 0.0, c1 = 0.0, c2 = 0.0;
-        if (F.R >= 0) {
-            double m[11];
+__global__ __launch_bounds__(GBS, MINW) void k_face_target(const LevelDesc* __restrict__ lvs,
+                                                           const FaceItem* __restrict__ items, int n,
+                                                           const BCDev* __restrict__ bcs, Phys ph,
+                                                           const double* __restrict__ fmom,
+                                                           double* __restrict__ fpar) {
+    __shared__ double sh_m[GW][13];
+    __shared__ FaceState sh_f[GW];
+    __shared__ Eq<double> sh_e[GW];
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave index (uniform)
+    const int t = threadIdx.x;
+    for (int g0 = wg_index() * GW; g0 < n; g0 += gridDim.x * GW) {
+        const int it = g0 + w;
+        // face state and uncorrected target
+        if (t < GW && g0 + t < n) {
+            const FaceItem F = items[g0 + t];
+            const double* mm = fmom + (size_t)(g0 + t) * NFMOM;
+            sh_m[t][0] = mm[0];                       // boundary: the outgoing mass flux
+            if (F.R >= 0) {
+                const FaceState fs = face_state(mm, mm[11], mm[12], ph);
+                sh_f[t] = fs;
+                sh_e[t] = make_eq(fs.rho, fs.u, fs.v, fs.T, fs.qx, fs.qy, nullptr, ph);
+            } else {
+                const BCDev bc = bcs[-1 - F.R];
+                FaceState fs{};
+                fs.c1 = F.area;
+                fs.c2 = F.area;
+                sh_f[t] = fs;
+                sh_e[t] = bc.kind == 2 ? make_eq(bc.rho, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph)
+                                       : make_eq(1.0, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
+            }
+        }
+        __syncthreads();
+        // compatibility sums (interior) or the wall's incoming mass flux
+        if (it < n) {
+            const FaceItem F = items[it];
+            const LevelDesc& L = lvs[F.lev];
+            if (F.R >= 0) {
+                if (ph.compat && ph.face_compat) {
+                    double sm[13];
+                    compat_sums<S, U>(L, eq_cast<S>(sh_e[w]), sm);
+                    if (lane_id() < 13) {
 #pragma unroll
-            for (int k = 0; k < 11; ++k) m[k] = mm[k];
-            const double u0 = 0.5 * (params[(size_t)F.L * NPARAM + P_U] + params[(size_t)F.R * NPARAM + P_U]);
-            const double v0 = 0.5 * (params[(size_t)F.L * NPARAM + P_V] + params[(size_t)F.R * NPARAM + P_V]);
-            e = face_target<S, U>(L, m, u0, v0, ph, ph.compat && ph.face_compat, c1, c2);
-            c1 *= F.area;
-            c2 *= F.area;
-        } else {
-            const BCDev bc = bcs[-1 - F.R];
-            kind = (double)bc.kind;
-            c1 = F.area;
-            c2 = F.area;
-            if (bc.kind == 1) {
-                e = make_eq(1.0, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
-                const Eq<S> es = eq_cast<S>(e);
+                        for (int k = 0; k < 13; ++k)
+                            if (lane_id() == k) sh_m[w][k] = sm[k];
+                    }
+                }
+            } else if (bcs[-1 - F.R].kind == 1) {
+                const Eq<S> es = eq_cast<S>(sh_e[w]);
                 const int N = L.N;
-                double m[1] = {0.0};
+                double m1[1] = {0.0};
                 for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
                     double xv[U], yv[U], wv[U];
 #pragma unroll
@@ -781,18 +911,35 @@ __global__ __launch_bounds__(BS, MINW) void k_face_target(const LevelDesc* __res
                         if (dn < 0) {
                             S gs, hs;
                             eq_eval<S>(es, (S)xv[q], (S)yv[q], gs, hs);
-                            m[0] += wv[q] * dn * (double)gs;
+                            m1[0] += wv[q] * dn * (double)gs;
                         }
                     }
                 }
-                wave_sum<1>(m);
-                c2 = F.area * (-mm[0] / m[0]);
-            } else if (bc.kind == 2) {
-                e = make_eq(bc.rho, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
+                wave_sum<1>(m1);
+                if (lane_id() == 0) sh_m[w][1] = m1[0];   // [0] keeps the outgoing flux
             }
         }
-        if (lane_id() == 0) {
-            double* o = fpar + (size_t)it * NFP;
+        __syncthreads();
+        // face record
+        if (t < GW && g0 + t < n) {
+            const FaceItem F = items[g0 + t];
+            FaceState fs = sh_f[t];
+            Eq<double> e = sh_e[t];
+            double kind = 0.0, c1 = fs.c1, c2 = fs.c2;
+            if (F.R >= 0) {
+                if (ph.compat && ph.face_compat) {
+                    double a[4];
+                    compat_from_sums(sh_m[t], fs.rho, fs.u, fs.v, fs.T, ph, a);
+                    e = make_eq(fs.rho, fs.u, fs.v, fs.T, fs.qx, fs.qy, a, ph);
+                }
+                c1 *= F.area;
+                c2 *= F.area;
+            } else {
+                const BCDev bc = bcs[-1 - F.R];
+                kind = (double)bc.kind;
+                if (bc.kind == 1) c2 = F.area * (-sh_m[t][0] / sh_m[t][1]);
+            }
+            double* o = fpar + (size_t)(g0 + t) * NFP;
             o[FP_KIND] = kind; o[FP_ROW] = (double)F.row; o[FP_NX] = F.nx; o[FP_NY] = F.ny;
             o[FP_C1] = c1; o[FP_C2] = c2;
             o[FP_RN] = e.rn; o[FP_UX] = e.ux; o[FP_UY] = e.uy; o[FP_I2RT] = e.i2RT; o[FP_RT] = e.RT;
@@ -800,6 +947,7 @@ __global__ __launch_bounds__(BS, MINW) void k_face_target(const LevelDesc* __res
             o[FP_B0] = e.b0; o[FP_B1] = e.b1; o[FP_B2] = e.b2; o[FP_B3] = e.b3;
             o[FP_CORR] = e.corr ? 1.0 : 0.0;
         }
+        __syncthreads();
     }
 }
 
@@ -1066,9 +1214,11 @@ __global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv,
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
-static inline int grid_for(int n) {
-    int b = (n + MAXW - 1) / MAXW;
-    b = (b + NXCD - 1) / NXCD * NXCD;          // whole rounds over the XCDs (see wg_index)
+// Workgroups for n items at `per` items each, in whole rounds over the XCDs
+// (see wg_index).
+static inline int grid_for(int n, int per = MAXW) {
+    int b = (n + per - 1) / per;
+    b = (b + NXCD - 1) / NXCD * NXCD;
     return b < NXCD ? NXCD : (b > 1048576 ? 1048576 : b);
 }
 
@@ -1101,7 +1251,7 @@ int variant_count() { return N_VARIANTS; }
 hipError_t launch_cell_prep(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
                             int n_cells, Phys ph, double* params, const double* cmom, int var) {
     if (n_cells <= 0) return hipSuccess;
-    MLVS_DISPATCH_V(prec, var, k_cell_prep, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot,
+    MLVS_DISPATCH_V(prec, var, k_cell_prep, dim3(grid_for(n_cells, GW)), dim3(GBS), 0, st, lv, cell_lev, cell_slot,
                     n_cells, ph, params, cmom);
     return hipGetLastError();
 }
@@ -1141,11 +1291,10 @@ hipError_t launch_face_rec(int prec, hipStream_t st, const LevelDesc* lv, const 
 }
 
 hipError_t launch_face_target(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
-                              const double* params, const BCDev* bcs, Phys ph, const double* fmom, double* fpar,
-                              int var) {
+                              const BCDev* bcs, Phys ph, const double* fmom, double* fpar, int var) {
     if (n <= 0) return hipSuccess;
-    MLVS_DISPATCH_V(prec, var, k_face_target, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, params, bcs, ph,
-                    fmom, fpar);
+    MLVS_DISPATCH_V(prec, var, k_face_target, dim3(grid_for(n, GW)), dim3(GBS), 0, st, lv, items, n, bcs, ph, fmom,
+                    fpar);
     return hipGetLastError();
 }
 

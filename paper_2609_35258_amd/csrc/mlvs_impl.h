@@ -21,6 +21,11 @@ enum {
 // the cell stage, taken about the velocity shift (M_U0, M_V0).
 enum { M_U0 = 11, M_V0 = 12, NMOM = 16 };
 
+// Per-face raw moments of phi_bar_f written by the reconstruction stage: the
+// eleven sums (interior faces; boundary faces: [0] the outgoing mass flux),
+// then the velocity shift (u0, v0) they are taken about.
+enum { NFMOM = 16 };
+
 // Per-face record written by the face-target stage and read by the update
 // (double).  KIND: 0 interior, else the boundary kind; C1, C2: the weights of
 // phi_bar_f and of the target (area included); RN..B3: the target in the
@@ -109,8 +114,7 @@ hipError_t launch_face_rec(int prec, hipStream_t st, const LevelDesc* lv, const 
                            const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
                            const double* params, Phys ph, double* fmom, int var = 1);
 hipError_t launch_face_target(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
-                              const double* params, const BCDev* bcs, Phys ph, const double* fmom, double* fpar,
-                              int var = 1);
+                              const BCDev* bcs, Phys ph, const double* fmom, double* fpar, int var = 1);
 hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFaceItem* items, int n,
                         const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
                         const double* params, Phys ph, unsigned long long* neg, int var = 1);

@@ -37,7 +37,9 @@ def _run_parity(p, steps, compat=4, face_compat=True):
         worst = max(worst, *e)
         assert max(e) < TOL, (k, e)
     t_o, t_g = o.totals(), g.totals()
-    assert np.allclose(t_g, t_o, rtol=1e-12, atol=1e-13)
+    # totals near zero (a symmetric momentum component) carry only rounding of
+    # the order of the largest total times machine epsilon
+    assert np.allclose(t_g, t_o, rtol=1e-12, atol=1e-14 * np.max(np.abs(t_o)))
     f_o, f_g = o.fields(), g.moments()
     assert np.allclose(f_g, f_o, rtol=1e-10, atol=1e-12)
     g.close()
