@@ -180,6 +180,71 @@ def learned_vs_criterion(precision=32, n_theta=64, n_r=32, nv=41, warm=200, snap
     return out
 
 
+CYL_ADAPT = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, flux_test=True, interval=0)
+CYL_INTERVAL = 100
+
+
+def roofline(prof, precision):
+    """Roofline entry for the dominant stage: algorithmic bytes / mean launch time."""
+    evsz = 8 if precision == 64 else 4
+    dom = max((k for k in prof if ALG_VALUES[k] > 0), key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    achieved = d["points"] * ALG_VALUES[dom] * evsz / (d["ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "stage_ms": {k: round(v["ms"], 5) for k, v in prof.items()}}
+
+
+def cylinder_case(steps=200, warmup=100, precision=32):
+    """Supersonic cylinder at full size (256 x 128 O-grid, Ma 3, Kn 0.1, 101^2
+    Newton-Cotes base grid, FP32 storage), MLVS against UVS.  Both start from
+    the freestream and take `warmup` untimed steps on the base grid (an
+    impulsive Ma 3 start is not resolved by levels built from the uniform
+    freestream); then the MLVS run adapts (criterion levels) at the start of
+    every block of 100 steps, adaptation time included in the timed steps."""
+    import torch
+    import paper_2609_35258_amd as m
+    from paper_2609_35258_amd import autotune
+    p = W.cylinder(256, 128, Kn=0.1, nv=101, vmax=10.0)
+    s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=CYL_ADAPT, graph=True)
+    s.step(warmup)
+    s.adapt()
+    s.step(2)
+    autotune.autotune(s, precision)
+    torch.cuda.synchronize()
+    c0 = s.counters()
+    t0 = time.perf_counter()
+    for _ in range(steps // CYL_INTERVAL):
+        s.adapt()
+        s.step(CYL_INTERVAL)
+    torch.cuda.synchronize()
+    t_m = time.perf_counter() - t0
+    upd = s.counters()["cell_updates"] - c0["cell_updates"]
+    npts, ncells, ncross = s.level_info()
+    f_m = s.moments()
+    mem_m = s.memory()
+    prof = stage_profile(s, reps=5)
+    s.close()
+    u, t_u, upd_u, _ = run_gpu(p, steps, warmup + 2, precision, None)
+    f_u = u.moments()
+    mem_u = u.memory()
+    prof_u = stage_profile(u, reps=5)
+    u.close()
+    err = {name: float(np.sqrt(np.sum((f_m[:, k] - f_u[:, k]) ** 2) / np.sum(f_u[:, k] ** 2)))
+           for k, name in ((0, "rho"), (1, "u"), (3, "T"))}
+    return {"workload": "cylinder O-grid 256x128, Ma 3, Kn 0.1, Shakhov Pr 2/3, 101x101 Newton-Cotes on "
+                        "[-10,10]^2, fp%d; %d base-grid steps from a freestream start, then %d timed steps; MLVS "
+                        "C_split 0.01 C_merge 0.005 eps 2e-5 tau 0.05, adaptation every %d steps"
+                        % (precision, warmup, steps, CYL_INTERVAL),
+            "value": upd / t_m, "ms_per_step": 1e3 * t_m / steps, "levels": len(npts),
+            "level_points": [int(x) for x in npts], "level_cells": [int(x) for x in ncells],
+            "nbar": float(np.sum(npts * ncells) / np.sum(ncells)), "n_cross": int(ncross),
+            "roofline": roofline(prof, precision),
+            "uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps, "roofline": roofline(prof_u, precision),
+                    "time_to_solution_ratio": t_u / t_m, "memory_ratio": mem_u / mem_m,
+                    "mlvs_vs_uvs_rel_l2": err}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +257,7 @@ def main():
     ap.add_argument("--no-uvs", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-cylinder", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
@@ -219,15 +285,7 @@ def main():
     fields_m = s.moments()
     mem_m = s.memory()
     prof = stage_profile(s)
-    evsz = 8 if args.precision == 64 else 4
-    # dominant kernel: largest time per step among the stages that move rows
-    dom = max((k for k in prof if ALG_VALUES[k] > 0), key=lambda k: prof[k]["ms"])
-    d = prof[dom]
-    alg_bytes = d["points"] * ALG_VALUES[dom] * evsz
-    achieved = alg_bytes / (d["ms"] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "stage_ms": {k: round(v["ms"], 5) for k, v in prof.items()}}
+    roof = roofline(prof, args.precision)
     out = {"metric": "DUGKS cell-velocity updates/s (MLVS-DUGKS hot path, adaptation included)",
            "value": value, "unit": "cell-velocity updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * t_mlvs / args.steps, "higher_is_better": True,
@@ -257,6 +315,8 @@ def main():
                       "time_to_solution_ratio": t_uvs / t_mlvs, "memory_ratio": mem_u / mem_m,
                       "mlvs_vs_uvs_rel_l2": err}
         u.close()
+    if not args.no_cylinder:
+        out["cylinder"] = cylinder_case()
     if not args.no_learned:
         out["learned"] = learned_vs_criterion()
     if not args.no_cpu_baseline:

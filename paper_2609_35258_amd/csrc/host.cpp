@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -207,6 +208,7 @@ struct Level {
     std::vector<double> xi_x, xi_y, w;
     std::vector<int> pt_of_base;
     std::vector<int> mem_off, mem_idx;     // base members per point (ascending)
+    std::vector<int> canon_of;             // device point -> canonical point (I/O order)
     double Minv[16];
     bool is_iface = false;
     // device
@@ -278,7 +280,35 @@ std::unique_ptr<Level> build_level(const Base& B, const std::vector<uint8_t>& ka
     for (int b = 0; b < B.N; ++b)
         if (!covered[b]) groups.push_back({b});
     for (auto& g : groups) std::sort(g.begin(), g.end());
+    // canonical order (the interface order of every per-point array): ascending
+    // smallest base index of each point
     std::sort(groups.begin(), groups.end(), [](const std::vector<int>& a, const std::vector<int>& b) { return a[0] < b[0]; });
+    // device order: by polar angle of the point's velocity, then speed, then
+    // canonical index.  For any face normal n the points with xi . n > 0 then
+    // form one arc of consecutive indices (two pieces if it wraps), so almost
+    // every 64-point chunk of a face has a single upwind side.
+    {
+        const int n = (int)groups.size();
+        std::vector<double> ang(n), r2(n);
+        for (int p = 0; p < n; ++p) {
+            double ws = 0.0, sx = 0.0, sy = 0.0;
+            for (int b : groups[p]) { ws += B.w[b]; sx += B.w[b] * B.x[b]; sy += B.w[b] * B.y[b]; }
+            const double x = sx / ws + 0.0, y = sy / ws + 0.0;   // + 0.0: no negative zeros
+            ang[p] = std::atan2(y, x);
+            r2[p] = x * x + y * y;
+        }
+        std::vector<int> ord(n);
+        for (int p = 0; p < n; ++p) ord[p] = p;
+        std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+            if (ang[a] != ang[b]) return ang[a] < ang[b];
+            if (r2[a] != r2[b]) return r2[a] < r2[b];
+            return a < b;
+        });
+        std::vector<std::vector<int>> dev(n);
+        L->canon_of.resize(n);
+        for (int d = 0; d < n; ++d) { dev[d] = std::move(groups[ord[d]]); L->canon_of[d] = ord[d]; }
+        groups = std::move(dev);
+    }
     L->N = (int)groups.size();
     L->pt_of_base.assign(B.N, -1);
     L->mem_off.assign(L->N + 1, 0);
@@ -496,6 +526,7 @@ void build_mesh(MeshH& M, const mlvs_mesh& in, int dim) {
                 have[k] = true;
             }
         }
+        for (int k = 0; k < 4; ++k) g.inv_dist[k] = 1.0 / g.dist[k];
         double tix = cenx[1] - cenx[0], tiy = ceny[1] - ceny[0];
         double nn = std::hypot(tix, tiy);
         tix /= nn; tiy /= nn;
@@ -537,8 +568,10 @@ struct mlvs_ctx_s {
     int *d_cell_lev = nullptr, *d_cell_slot = nullptr, *d_cell_nbr = nullptr, *d_cell_frow = nullptr;
     CellGeom* d_geom = nullptr;
     double* d_params = nullptr;
-    double* d_cmom = nullptr;
-    double* d_fmom = nullptr;          // [faces + boundary faces][NFMOM] face moments          // [n_cells][NMOM] raw moments of the stored state
+    double* d_cmom = nullptr;          // [chunks][n_cells][NMOM] raw moments of the stored state
+    double* d_fmom = nullptr;          // [chunks][faces + boundary faces][NFMOM] face moments
+    int chunk = 1024;                  // velocity points per chunk (multiple of 64)
+    int nch = 1;                       // chunks of the largest level
     double* d_fpar = nullptr;          // [faces + boundary faces][NFP] face records
     bool mom_valid = false;            // d_cmom matches the stored state
     BCDev* d_bcs = nullptr;
@@ -630,7 +663,7 @@ void free_items(mlvs_ctx c) {
     c->item_allocs.clear();
     for (auto& L : c->ifaces) free_level(c, *L);
     c->ifaces.clear();
-    c->d_faces = nullptr; c->d_fmom = nullptr; c->d_fpar = nullptr; c->d_ghosts = nullptr; c->d_xfaces = nullptr;
+    c->d_faces = nullptr; c->d_fmom = nullptr; c->d_fpar = nullptr; c->d_cmom = nullptr; c->d_ghosts = nullptr; c->d_xfaces = nullptr;
     c->d_lv = nullptr;
     c->n_faces = c->n_bfaces = c->n_ghosts = c->n_xfaces = 0;
 }
@@ -802,8 +835,15 @@ void build_items(mlvs_ctx c) {
     c->n_bfaces = (int)bfaces.size();
     faces.insert(faces.end(), bfaces.begin(), bfaces.end());
     c->d_faces = upload_item(c, faces);
-    c->d_fmom = static_cast<double*>(c->dm.alloc(sizeof(double) * NFMOM * std::max<size_t>(faces.size(), 1)));
+    int nmax = 1;
+    for (int l = 0; l < K; ++l) nmax = std::max(nmax, c->levels[l]->N);
+    c->nch = (nmax + c->chunk - 1) / c->chunk;
+    c->d_fmom = static_cast<double*>(
+        c->dm.alloc(sizeof(double) * NFMOM * c->nch * std::max<size_t>(faces.size(), 1)));
     c->item_allocs.push_back(c->d_fmom);
+    c->d_cmom = static_cast<double*>(c->dm.alloc(sizeof(double) * NMOM * c->nch * (size_t)std::max(n, 1)));
+    c->item_allocs.push_back(c->d_cmom);
+    c->mom_valid = false;
     c->d_fpar = static_cast<double*>(c->dm.alloc(sizeof(double) * NFP * std::max<size_t>(faces.size(), 1)));
     c->item_allocs.push_back(c->d_fpar);
     c->d_ghosts = upload_item(c, gitems); c->n_ghosts = (int)gitems.size();
@@ -843,7 +883,7 @@ void do_step(mlvs_ctx c);
 void ensure_moments(mlvs_ctx c) {
     if (c->mom_valid) return;
     hip_check(launch_raw_moments(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, c->mesh.n_cells,
-                                 c->d_params, c->d_cmom), "moments launch");
+                                 c->d_params, c->d_cmom, c->chunk, c->nch), "moments launch");
     c->mom_valid = true;
 }
 hipError_t launch_stage(mlvs_ctx c, int stage);
@@ -1487,9 +1527,14 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         c->d_bcs = upload(c->dm, bd, c->st);
         c->d_params = static_cast<double*>(c->dm.alloc(sizeof(double) * NPARAM * c->mesh.n_cells));
         hip_check(hipMemsetAsync(c->d_params, 0, sizeof(double) * NPARAM * c->mesh.n_cells, c->st), "memset");
-        c->d_cmom = static_cast<double*>(c->dm.alloc(sizeof(double) * NMOM * c->mesh.n_cells));
         c->d_neg = static_cast<unsigned long long*>(c->dm.alloc(8));
         hip_check(hipMemsetAsync(c->d_neg, 0, 8, c->st), "memset");
+        // velocity chunk of the streaming stages (MLVS_CHUNK overrides; multiple of 64)
+        if (const char* e = std::getenv("MLVS_CHUNK")) {
+            const int v = std::atoi(e);
+            if (v < 64 || v % 64 != 0) fail(MLVS_E_ARG, "MLVS_CHUNK must be a positive multiple of 64");
+            c->chunk = v;
+        }
         // one level: the base grid itself
         std::vector<uint8_t> k0(B.Nb, 0);
         c->levels.push_back(build_level(B, k0));
@@ -1641,7 +1686,7 @@ mlvs_status mlvs_time_stage(mlvs_ctx c, int stage, int reps, double* ms) {
                 keep(L->g, nb);
                 keep(L->h, nb);
             }
-            keep(c->d_cmom, sizeof(double) * NMOM * (size_t)c->mesh.n_cells);
+            keep(c->d_cmom, sizeof(double) * NMOM * c->nch * (size_t)c->mesh.n_cells);
         }
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "event");
@@ -1753,13 +1798,13 @@ static void copy_cell(mlvs_ctx c, int64_t cell, double* g, double* h, const doub
             hip_check(hipMemcpyAsync(buf.data(), base, nb, hipMemcpyDeviceToHost, c->st), "D2H");
             sync(c);
             for (int i = 0; i < L.N; ++i)
-                o[i] = c->prec == 32 ? (double)reinterpret_cast<float*>(buf.data())[i]
-                                     : reinterpret_cast<double*>(buf.data())[i];
+                o[L.canon_of[i]] = c->prec == 32 ? (double)reinterpret_cast<float*>(buf.data())[i]
+                                                 : reinterpret_cast<double*>(buf.data())[i];
         }
         if (in) {
             for (int i = 0; i < L.N; ++i) {
-                if (c->prec == 32) reinterpret_cast<float*>(buf.data())[i] = (float)in[i];
-                else reinterpret_cast<double*>(buf.data())[i] = in[i];
+                if (c->prec == 32) reinterpret_cast<float*>(buf.data())[i] = (float)in[L.canon_of[i]];
+                else reinterpret_cast<double*>(buf.data())[i] = in[L.canon_of[i]];
             }
             hip_check(hipMemcpyAsync(base, buf.data(), nb, hipMemcpyHostToDevice, c->st), "H2D");
             sync(c);
@@ -1809,11 +1854,12 @@ static void bulk_state(mlvs_ctx c, double* g, double* h, const double* gi, const
                 if (c->cell_level[cc] != (int)l) continue;
                 const size_t r = (size_t)c->cell_slot[cc] * L.stride;
                 for (int i = 0; i < L.N; ++i) {
-                    if (o) o[offset[cc] + i] = c->prec == 32 ? (double)reinterpret_cast<float*>(buf.data())[r + i]
-                                                             : reinterpret_cast<double*>(buf.data())[r + i];
+                    const size_t ci = offset[cc] + L.canon_of[i];
+                    if (o) o[ci] = c->prec == 32 ? (double)reinterpret_cast<float*>(buf.data())[r + i]
+                                                 : reinterpret_cast<double*>(buf.data())[r + i];
                     if (in) {
-                        if (c->prec == 32) reinterpret_cast<float*>(buf.data())[r + i] = (float)in[offset[cc] + i];
-                        else reinterpret_cast<double*>(buf.data())[r + i] = in[offset[cc] + i];
+                        if (c->prec == 32) reinterpret_cast<float*>(buf.data())[r + i] = (float)in[ci];
+                        else reinterpret_cast<double*>(buf.data())[r + i] = in[ci];
                     }
                 }
             }
@@ -1927,18 +1973,18 @@ hipError_t launch_stage(mlvs_ctx c, int stage) {
     const int nf = c->n_faces + c->n_bfaces;
     switch (stage) {
     case 0: return launch_cell_prep(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->ph, c->d_params,
-                                    c->d_cmom, c->variant[0]);
+                                    c->d_cmom, c->chunk, c->variant[0]);
     case 1: return launch_ghost(c->prec, c->st, c->d_lv, c->d_ghosts, c->n_ghosts, c->d_cell_lev, c->d_cell_slot,
                                 c->d_params, c->ph, c->d_neg);
     case 2: return launch_face_rec(c->prec, c->st, c->d_lv, c->d_faces, nf, c->d_cell_slot, c->d_cell_nbr, c->d_geom,
-                                   c->d_params, c->ph, c->d_fmom, c->variant[2]);
+                                   c->d_params, c->ph, c->d_fmom, c->chunk, c->nch, c->variant[2]);
     case 3: return launch_face_target(c->prec, c->st, c->d_lv, c->d_faces, nf, c->d_bcs, c->ph, c->d_fmom,
-                                      c->d_fpar, c->variant[3]);
+                                      c->d_fpar, c->chunk, c->variant[3]);
     case 4: return launch_xface(c->prec, c->st, c->d_lv, c->d_xfaces, c->n_xfaces, c->d_cell_slot, c->d_cell_nbr,
                                 c->d_geom, c->d_params, c->ph, c->d_neg, c->variant[4]);
     case 5: return launch_update(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom,
-                                 c->d_cell_frow, c->d_faces, c->d_fpar, c->d_params, c->ph, c->d_cmom,
-                                 c->variant[5]);
+                                 c->d_cell_frow, c->d_faces, c->d_fpar, c->d_params, c->ph, c->d_cmom, c->chunk,
+                                 c->nch, c->variant[5]);
     default: return hipErrorInvalidValue;
     }
 }

@@ -319,6 +319,23 @@ __device__ __forceinline__ void acc_raw(double* m, double w, double x, double y,
 constexpr int GW = 8;
 constexpr int GBS = GW * WL;
 
+// Velocity chunks.  Streaming stages that reuse neighbours' rows (face
+// reconstruction, update) split each item's points into chunks of CH points
+// and take (chunk, item) pairs chunk-major, so the waves resident on an XCD
+// work on the same velocity range of neighbouring items and their rows meet in
+// that XCD's L2.  Each pair writes partial sums; the next stage adds the
+// chunks of an item in chunk order (fixed order: deterministic).
+__device__ __forceinline__ void sum_chunks(const double* part, int item, int n_items, int N, int CH, double* out) {
+    const int nch = (N + CH - 1) / CH;
+    for (int j = 0; j < 11; ++j) out[j] = 0.0;
+    for (int k = 0; k < nch; ++k) {
+        const double* q = part + ((size_t)k * n_items + item) * NMOM;
+        for (int j = 0; j < 11; ++j) out[j] += q[j];
+    }
+    out[M_U0] = part[(size_t)item * NMOM + M_U0];
+    out[M_V0] = part[(size_t)item * NMOM + M_V0];
+}
+
 // Cell state from the raw moments (Eqs. W_from_tilde, discrete_q): W, tau,
 // q = 2 tau q~/(2 tau + dt Pr), and the update weights
 // alpha = (2 tau - s)/(2 tau + dt), beta = 3 s/(2 tau + dt), s = dt/2.
@@ -349,7 +366,7 @@ __global__ __launch_bounds__(GBS, MINW) void k_cell_prep(const LevelDesc* __rest
                                                          const int* __restrict__ cell_lev,
                                                          const int* __restrict__ cell_slot, int n_cells, Phys ph,
                                                          double* __restrict__ params,
-                                                         const double* __restrict__ cmom) {
+                                                         const double* __restrict__ cmom, int CH) {
     __shared__ CellState sh_c[GW];
     __shared__ Eq<double> sh_e[GW];
     __shared__ double sh_s[GW][13];
@@ -358,7 +375,10 @@ __global__ __launch_bounds__(GBS, MINW) void k_cell_prep(const LevelDesc* __rest
     for (int g0 = wg_index() * GW; g0 < n_cells; g0 += gridDim.x * GW) {
         // scalar: state and the uncorrected target, one lane per cell
         if (t < GW && g0 + t < n_cells) {
-            const CellState cs = cell_state(cmom + (size_t)(g0 + t) * NMOM, ph);
+            const int ci = g0 + t;
+            double cm[NMOM];
+            sum_chunks(cmom, ci, n_cells, lvs[cell_lev[ci]].N, CH, cm);
+            const CellState cs = cell_state(cm, ph);
             sh_c[t] = cs;
             sh_e[t] = make_eq(cs.rho, cs.u, cs.v, cs.T, cs.qx, cs.qy, nullptr, ph);
         }
@@ -428,39 +448,45 @@ __global__ __launch_bounds__(GBS, MINW) void k_cell_prep(const LevelDesc* __rest
 }
 
 // Raw moments of the stored g~, h~ about the cell velocity held in params (used
-// when the state was written by anything other than the update).
+// when the state was written by anything other than the update), per (chunk,
+// cell) pair in the layout the update writes.
 template <typename S>
 __global__ __launch_bounds__(BS) void k_raw_moments(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
                                                     const int* __restrict__ cell_slot, int n_cells,
-                                                    const double* __restrict__ params, double* __restrict__ cmom) {
+                                                    const double* __restrict__ params, double* __restrict__ cmom,
+                                                    int CH, int nch) {
     constexpr int U = 4;
-    for (int c = item0(); c < n_cells; c += istride()) {
+    const int n = n_cells * nch;
+    for (int it = item0(); it < n; it += istride()) {
+        const int k = it / n_cells, c = it - k * n_cells;
         const LevelDesc& L = lvs[cell_lev[c]];
-        const int N = L.N;
+        const int beg = k * CH;
+        if (beg >= L.N) continue;
+        const int end = min(L.N, beg + CH);
         const size_t row = (size_t)cell_slot[c] * L.stride;
         auto g = rowp<S>(L.g, row);
         auto h = rowp<S>(L.h, row);
         const double u0 = params[(size_t)c * NPARAM + P_U], v0 = params[(size_t)c * NPARAM + P_V];
         double m[11];
 #pragma unroll
-        for (int k = 0; k < 11; ++k) m[k] = 0.0;
-        for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
+        for (int j = 0; j < 11; ++j) m[j] = 0.0;
+        for (int i0 = beg + lane_id(); i0 < end; i0 += WL * U) {
             S gv[U], hv[U];
             double xv[U], yv[U], wv[U];
 #pragma unroll
             for (int q = 0; q < U; ++q) {
-                const int i = i0 + q * WL, ic = clampi(i, N);
+                const int i = i0 + q * WL, ic = clampi(i, end);
                 gv[q] = g[ic]; hv[q] = h[ic];
                 xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
-                wv[q] = i < N ? gp(L.w)[ic] : 0.0;
+                wv[q] = i < end ? gp(L.w)[ic] : 0.0;
             }
 #pragma unroll
             for (int q = 0; q < U; ++q) acc_raw<S>(m, wv[q], xv[q] - u0, yv[q] - v0, gv[q], hv[q]);
         }
         wave_sum<11>(m);
         if (lane_id() == 0) {
-            double* o = cmom + (size_t)c * NMOM;
-            for (int k = 0; k < 11; ++k) o[k] = m[k];
+            double* o = cmom + (size_t)it * NMOM;
+            for (int j = 0; j < 11; ++j) o[j] = m[j];
             o[M_U0] = u0;
             o[M_V0] = v0;
         }
@@ -618,7 +644,7 @@ __device__ __forceinline__ void load_side(Side<S>& sd, const LevelDesc& L, int c
     for (int k = 0; k < 4; ++k) sd.off[k + 1] = nb_off(L, cell_nbr[4 * cell + k], cell_slot, own);
     const CellGeom& gm = geom[cell];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) { sd.G[k] = (S)gm.G[k]; sd.id[k] = (S)(1.0 / gm.dist[k]); }
+    for (int k = 0; k < 4; ++k) { sd.G[k] = (S)gm.G[k]; sd.id[k] = (S)gm.inv_dist[k]; }
     sd.dx = (S)dx; sd.dy = (S)dy;
 }
 
@@ -749,6 +775,32 @@ __device__ __forceinline__ FaceState face_state(const double* mm, double u0, dou
     return f;
 }
 
+// The same with one side for the whole wavefront (no per-lane choice).
+template <typename S>
+__device__ __forceinline__ void load_stencil1(const Side<S>& a, int i, Stencil<S>& st) {
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        const auto B = a.base[comp] + i;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) st.v[comp][k] = B[a.off[k]];
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ void stencil_ext1(const Side<S>& a, const Stencil<S>& st, S x, S y, S s, S& eg, S& eh) {
+    const S ax = a.dx - x * s, ay = a.dy - y * s;
+    S e[2];
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        const S fv = st.v[comp][0];
+        const S s0 = van_leer<S>((fv - st.v[comp][1]) * a.id[0], (st.v[comp][2] - fv) * a.id[1]);
+        const S s1 = van_leer<S>((fv - st.v[comp][3]) * a.id[2], (st.v[comp][4] - fv) * a.id[3]);
+        e[comp] = fv + ax * (a.G[0] * s0 + a.G[1] * s1) + ay * (a.G[2] * s0 + a.G[3] * s1);
+    }
+    eg = e[0];
+    eh = e[1];
+}
+
 // Face stage, part 1 (reconstruction): for every same-level interior face and
 // every boundary face, the interface value phi_bar_f = phi_bar+_up + (x_f -
 // x_up - xi s) . sigma_up (both sides averaged where xi . n = 0) is written to
@@ -758,17 +810,21 @@ __device__ __forceinline__ FaceState face_state(const double* mm, double u0, dou
 // then the velocity shift they are taken about).
 template <typename S, int U, int MINW>
 __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restrict__ lvs,
-                                                       const FaceItem* __restrict__ items, int n,
+                                                       const FaceItem* __restrict__ items, int nF,
                                                        const int* __restrict__ cell_slot,
                                                        const int* __restrict__ cell_nbr,
                                                        const CellGeom* __restrict__ geom,
                                                        const double* __restrict__ params, Phys ph,
-                                                       double* __restrict__ fmom) {
+                                                       double* __restrict__ fmom, int CH, int nch) {
     const S s = (S)(0.5 * ph.dt);
+    const int n = nF * nch;
     for (int it = item0(); it < n; it += istride()) {
-        const FaceItem F = items[it];
+        const int kc = it / nF, f = it - kc * nF;
+        const FaceItem F = items[f];
         const LevelDesc& L = lvs[F.lev];
-        const int N = L.N;
+        const int beg = kc * CH;
+        if (beg >= L.N) continue;
+        const int N = min(L.N, beg + CH);      // end of this chunk
         auto rg = rowp<S>(L.Fg, (size_t)F.row * L.stride);
         auto rh = rowp<S>(L.Fh, (size_t)F.row * L.stride);
         Side<S> sL;
@@ -785,32 +841,50 @@ __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restri
         double m[11];
 #pragma unroll
         for (int k = 0; k < 11; ++k) m[k] = 0.0;
-        for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
+        for (int i0 = beg + lane_id(); i0 < N; i0 += WL * U) {
             double xv[U], yv[U], wv[U];
-            Stencil<S> st[U];
             bool up[U];
+            // points are stored by velocity angle, so a chunk almost always has
+            // one upwind side for the whole wavefront: then that side's stencil
+            // is used with scalar offsets and coefficients
+            bool allL = true, allR = true;
 #pragma unroll
             for (int q = 0; q < U; ++q) {
                 const int i = i0 + q * WL, ic = clampi(i, N);
                 xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
                 wv[q] = i < N ? gp(L.w)[ic] : 0.0;
-                up[q] = xv[q] * F.nx + yv[q] * F.ny >= 0.0;
-                load_stencil<S>(sL, sR, up[q], ic, st[q]);
-            }
-            S eg[U], eh[U];
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const int ic = clampi(i0 + q * WL, N);
-                const S x = (S)xv[q], y = (S)yv[q];
-                stencil_ext<S>(sL, sR, up[q], st[q], x, y, s, eg[q], eh[q]);
                 const double dn = xv[q] * F.nx + yv[q] * F.ny;
-                if (interior && dn == 0.0) {            // both sides, averaged
-                    Stencil<S> sb;
-                    load_stencil<S>(sL, sR, false, ic, sb);
-                    S bg, bh;
-                    stencil_ext<S>(sL, sR, false, sb, x, y, s, bg, bh);
-                    eg[q] = S(0.5) * (eg[q] + bg);
-                    eh[q] = S(0.5) * (eh[q] + bh);
+                up[q] = dn >= 0.0;
+                allL = allL && (i >= N || dn > 0.0);
+                allR = allR && (i >= N || dn < 0.0);
+            }
+            const int side = !interior ? 0 : (__all(allL) ? 0 : (__all(allR) ? 1 : 2));
+            S eg[U], eh[U];
+            if (side < 2) {
+                const Side<S>& sd = side == 0 ? sL : sR;
+                Stencil<S> st[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) load_stencil1<S>(sd, clampi(i0 + q * WL, N), st[q]);
+#pragma unroll
+                for (int q = 0; q < U; ++q) stencil_ext1<S>(sd, st[q], (S)xv[q], (S)yv[q], s, eg[q], eh[q]);
+            } else {
+                Stencil<S> st[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) load_stencil<S>(sL, sR, up[q], clampi(i0 + q * WL, N), st[q]);
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const int ic = clampi(i0 + q * WL, N);
+                    const S x = (S)xv[q], y = (S)yv[q];
+                    stencil_ext<S>(sL, sR, up[q], st[q], x, y, s, eg[q], eh[q]);
+                    const double dn = xv[q] * F.nx + yv[q] * F.ny;
+                    if (dn == 0.0) {                    // both sides, averaged
+                        Stencil<S> sb;
+                        load_stencil<S>(sL, sR, false, ic, sb);
+                        S bg, bh;
+                        stencil_ext<S>(sL, sR, false, sb, x, y, s, bg, bh);
+                        eg[q] = S(0.5) * (eg[q] + bg);
+                        eh[q] = S(0.5) * (eh[q] + bh);
+                    }
                 }
             }
 #pragma unroll
@@ -851,7 +925,7 @@ __global__ __launch_bounds__(GBS, MINW) void k_face_target(const LevelDesc* __re
                                                            const FaceItem* __restrict__ items, int n,
                                                            const BCDev* __restrict__ bcs, Phys ph,
                                                            const double* __restrict__ fmom,
-                                                           double* __restrict__ fpar) {
+                                                           double* __restrict__ fpar, int CH) {
     __shared__ double sh_m[GW][13];
     __shared__ FaceState sh_f[GW];
     __shared__ Eq<double> sh_e[GW];
@@ -862,7 +936,8 @@ __global__ __launch_bounds__(GBS, MINW) void k_face_target(const LevelDesc* __re
         // face state and uncorrected target
         if (t < GW && g0 + t < n) {
             const FaceItem F = items[g0 + t];
-            const double* mm = fmom + (size_t)(g0 + t) * NFMOM;
+            double mm[NFMOM];
+            sum_chunks(fmom, g0 + t, n, lvs[F.lev].N, CH, mm);
             sh_m[t][0] = mm[0];                       // boundary: the outgoing mass flux
             if (F.R >= 0) {
                 const FaceState fs = face_state(mm, mm[11], mm[12], ph);
@@ -982,11 +1057,15 @@ __global__ __launch_bounds__(BS, MINW) void k_update(const LevelDesc* __restrict
                                                      const FaceItem* __restrict__ items,
                                                      const double* __restrict__ fpar,
                                                      const double* __restrict__ params, Phys ph,
-                                                     double* __restrict__ cmom) {
+                                                     double* __restrict__ cmom, int CH, int nch) {
     const S c43 = (S)(4.0 / 3.0), c13 = (S)(1.0 / 3.0);
-    for (int c = item0(); c < n_cells; c += istride()) {
+    const int n = n_cells * nch;
+    for (int it = item0(); it < n; it += istride()) {
+        const int kc = it / n_cells, c = it - kc * n_cells;
         const LevelDesc& L = lvs[cell_lev[c]];
-        const int N = L.N;
+        const int beg = kc * CH;
+        if (beg >= L.N) continue;
+        const int N = min(L.N, beg + CH);      // end of this chunk
         const size_t row = (size_t)cell_slot[c] * L.stride;
         auto g = rowp<S>(L.g, row);
         auto h = rowp<S>(L.h, row);
@@ -1000,7 +1079,7 @@ __global__ __launch_bounds__(BS, MINW) void k_update(const LevelDesc* __restrict
         double m[11];
 #pragma unroll
         for (int k = 0; k < 11; ++k) m[k] = 0.0;
-        for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
+        for (int i0 = beg + lane_id(); i0 < N; i0 += WL * U) {
             double xv[U], yv[U], wv[U];
             S bg[U], bh[U], go[U], ho[U], ag[U], ah[U];
 #pragma unroll
@@ -1089,7 +1168,7 @@ __global__ __launch_bounds__(BS, MINW) void k_update(const LevelDesc* __restrict
         }
         wave_sum<11>(m);
         if (lane_id() == 0) {
-            double* o = cmom + (size_t)c * NMOM;
+            double* o = cmom + (size_t)it * NMOM;
             for (int k = 0; k < 11; ++k) o[k] = m[k];
             o[M_U0] = u0;
             o[M_V0] = v0;
@@ -1249,18 +1328,19 @@ int variant_count() { return N_VARIANTS; }
     } while (0)
 
 hipError_t launch_cell_prep(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
-                            int n_cells, Phys ph, double* params, const double* cmom, int var) {
+                            int n_cells, Phys ph, double* params, const double* cmom, int CH, int var) {
     if (n_cells <= 0) return hipSuccess;
     MLVS_DISPATCH_V(prec, var, k_cell_prep, dim3(grid_for(n_cells, GW)), dim3(GBS), 0, st, lv, cell_lev, cell_slot,
-                    n_cells, ph, params, cmom);
+                    n_cells, ph, params, cmom, CH);
     return hipGetLastError();
 }
 
 hipError_t launch_raw_moments(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
-                              const int* cell_slot, int n_cells, const double* params, double* cmom) {
+                              const int* cell_slot, int n_cells, const double* params, double* cmom, int CH,
+                              int nch) {
     if (n_cells <= 0) return hipSuccess;
-    MLVS_DISPATCH(prec, k_raw_moments, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
-                  params, cmom);
+    MLVS_DISPATCH(prec, k_raw_moments, dim3(grid_for(n_cells * nch)), dim3(BS), 0, st, lv, cell_lev, cell_slot,
+                  n_cells, params, cmom, CH, nch);
     return hipGetLastError();
 }
 
@@ -1283,27 +1363,27 @@ hipError_t launch_ghost(int prec, hipStream_t st, const LevelDesc* lv, const Gho
 
 hipError_t launch_face_rec(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
                            const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
-                           Phys ph, double* fmom, int var) {
+                           Phys ph, double* fmom, int CH, int nch, int var) {
     if (n <= 0) return hipSuccess;
-    MLVS_DISPATCH_V(prec, var, k_face_rec, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr,
-                    geom, params, ph, fmom);
+    MLVS_DISPATCH_V(prec, var, k_face_rec, dim3(grid_for(n * nch)), dim3(BS), 0, st, lv, items, n, cell_slot,
+                    cell_nbr, geom, params, ph, fmom, CH, nch);
     return hipGetLastError();
 }
 
 hipError_t launch_face_target(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
-                              const BCDev* bcs, Phys ph, const double* fmom, double* fpar, int var) {
+                              const BCDev* bcs, Phys ph, const double* fmom, double* fpar, int CH, int var) {
     if (n <= 0) return hipSuccess;
     MLVS_DISPATCH_V(prec, var, k_face_target, dim3(grid_for(n, GW)), dim3(GBS), 0, st, lv, items, n, bcs, ph, fmom,
-                    fpar);
+                    fpar, CH);
     return hipGetLastError();
 }
 
 hipError_t launch_update(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
                          int n_cells, const CellGeom* geom, const int* cell_frow, const FaceItem* items,
-                         const double* fpar, const double* params, Phys ph, double* cmom, int var) {
+                         const double* fpar, const double* params, Phys ph, double* cmom, int CH, int nch, int var) {
     if (n_cells <= 0) return hipSuccess;
-    MLVS_DISPATCH_V(prec, var, k_update, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
-                    geom, cell_frow, items, fpar, params, ph, cmom);
+    MLVS_DISPATCH_V(prec, var, k_update, dim3(grid_for(n_cells * nch)), dim3(BS), 0, st, lv, cell_lev, cell_slot,
+                    n_cells, geom, cell_frow, items, fpar, params, ph, cmom, CH, nch);
     return hipGetLastError();
 }
 

@@ -21,10 +21,11 @@ enum {
 // the cell stage, taken about the velocity shift (M_U0, M_V0).
 enum { M_U0 = 11, M_V0 = 12, NMOM = 16 };
 
-// Per-face raw moments of phi_bar_f written by the reconstruction stage: the
-// eleven sums (interior faces; boundary faces: [0] the outgoing mass flux),
-// then the velocity shift (u0, v0) they are taken about.
-enum { NFMOM = 16 };
+// Per-face raw moments of phi_bar_f written by the reconstruction stage, per
+// (velocity chunk, face): the eleven sums (interior faces; boundary faces: [0]
+// the outgoing mass flux), then the velocity shift (u0, v0) they are taken
+// about -- the layout of the cell moments, so NFMOM = NMOM.
+enum { NFMOM = NMOM };
 
 // Per-face record written by the face-target stage and read by the update
 // (double).  KIND: 0 interior, else the boundary kind; C1, C2: the weights of
@@ -65,6 +66,7 @@ struct CellGeom {
     double vol;
     double G[4];       // inverse of [t_i; t_j] (row-major)
     double dist[4];    // |x_n - x_c| for W, E, S, N (1 when absent)
+    double inv_dist[4];  // 1 / dist
 };
 
 struct FaceItem {      // same-level interior face (R >= 0) or boundary face (R = -1 - bc id)
@@ -104,24 +106,25 @@ struct RemapItem {     // cell moved from an old level to a new one
 int variant_count();
 hipError_t launch_cell_prep(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
                             const int* cell_slot, int n_cells, Phys ph, double* params, const double* cmom,
-                            int var = 1);
+                            int CH, int var = 1);
 hipError_t launch_raw_moments(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
-                              const int* cell_slot, int n_cells, const double* params, double* cmom);
+                              const int* cell_slot, int n_cells, const double* params, double* cmom, int CH,
+                              int nch);
 hipError_t launch_ghost(int prec, hipStream_t st, const LevelDesc* lv, const GhostItem* items, int n,
                         const int* cell_lev, const int* cell_slot, const double* params, Phys ph,
                         unsigned long long* neg);
 hipError_t launch_face_rec(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
                            const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
-                           const double* params, Phys ph, double* fmom, int var = 1);
+                           const double* params, Phys ph, double* fmom, int CH, int nch, int var = 1);
 hipError_t launch_face_target(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
-                              const BCDev* bcs, Phys ph, const double* fmom, double* fpar, int var = 1);
+                              const BCDev* bcs, Phys ph, const double* fmom, double* fpar, int CH, int var = 1);
 hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFaceItem* items, int n,
                         const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
                         const double* params, Phys ph, unsigned long long* neg, int var = 1);
 hipError_t launch_update(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
                          const int* cell_slot, int n_cells, const CellGeom* geom, const int* cell_frow,
                          const FaceItem* items, const double* fpar, const double* params, Phys ph, double* cmom,
-                         int var = 1);
+                         int CH, int nch, int var = 1);
 hipError_t launch_init_eq(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
                           const int* cell_slot, int n_cells, const double* rho_u_v_T, Phys ph,
                           double* params);

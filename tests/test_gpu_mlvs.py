@@ -119,7 +119,12 @@ def test_criterion_masks_match(flux_test):
     g.close()
 
 
-def test_adaptive_run_matches_oracle():
+@pytest.mark.parametrize("chunk", [None, "64"])
+def test_adaptive_run_matches_oracle(chunk, monkeypatch):
+    # chunk "64": levels of different sizes split into different numbers of
+    # velocity chunks in the reconstruction and update launches
+    if chunk:
+        monkeypatch.setenv("MLVS_CHUNK", chunk)
     p = _sine(nv=24, seed=9)
     ap = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=1e-3, tau_clust=0.02, flux_test=True, interval=2)
     o = Oracle(p, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 1e-3, 0.02, True, 2))

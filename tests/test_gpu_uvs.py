@@ -68,6 +68,13 @@ def test_cylinder_ogrid():
     _run_parity(W.cylinder(24, 10, Kn=0.1, nv=21, vmax=10.0), 4)
 
 
+def test_cylinder_velocity_chunks(monkeypatch):
+    # 441 points in chunks of 64: the reconstruction and update split every
+    # row into 7 chunks whose partial moments are added in chunk order
+    monkeypatch.setenv("MLVS_CHUNK", "64")
+    _run_parity(W.cylinder(24, 10, Kn=0.1, nv=21, vmax=10.0), 3)
+
+
 def test_jet_slot():
     _run_parity(W.jet(20, 12, Kn_jet=0.01, nv=21, vmax=7.0), 3)
 
