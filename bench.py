@@ -12,6 +12,7 @@ cross-level faces, update).  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -184,18 +185,44 @@ CYL_ADAPT = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, fl
 CYL_INTERVAL = 100
 
 
-def roofline(prof, precision):
+# launch variant index -> (velocity points per lane per load batch, minimum waves per SIMD)
+VARIANTS = {0: (1, 4), 1: (2, 4), 2: (4, 2), 3: (4, 4)}
+STAGE_KERNEL = {"cell": "k_cell_prep", "face_rec": "k_face_rec", "face_target": "k_face_target",
+                "update": "k_update", "xface": "k_xface"}
+
+
+def measured_traffic(workload, stage, precision, variant):
+    """HBM-side bytes per dispatch of the stage's kernel from profiles/traffic.txt
+    (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when absent or
+    when the kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    src = os.path.join(ROOT, "paper_2609_35258_amd", "csrc", "kernels.hip")
+    if stage not in STAGE_KERNEL or variant is None or not os.path.exists(path):
+        return None
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    u, w = VARIANTS[variant]
+    name = "mlvs::%s<%s,%d,%d>" % (STAGE_KERNEL[stage], "double" if precision == 64 else "float", u, w)
+    for line in open(path):
+        f = line.split()
+        if len(f) == 4 and not line.startswith("#") and f[0] == h and f[1] == workload and f[2] == name:
+            return float(f[3])
+    return None
+
+
+def roofline(prof, precision, variants=None, workload=None):
     """Roofline entry for the dominant stage: algorithmic bytes / mean launch time."""
     evsz = 8 if precision == 64 else 4
     dom = max((k for k in prof if ALG_VALUES[k] > 0), key=lambda k: prof[k]["ms"])
     d = prof[dom]
     achieved = d["points"] * ALG_VALUES[dom] * evsz / (d["ms"] * 1e-3) / 1e9
+    t = measured_traffic(workload, dom, precision, (variants or {}).get(dom)) if workload else None
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": t,
+            "algorithmic_bytes": d["points"] * ALG_VALUES[dom] * evsz,
             "stage_ms": {k: round(v["ms"], 5) for k, v in prof.items()}}
 
 
-def cylinder_case(steps=200, warmup=100, precision=32):
+def cylinder_case(steps=200, warmup=100, precision=32, mode="both"):
     """Supersonic cylinder at full size (256 x 128 O-grid, Ma 3, Kn 0.1, 101^2
     Newton-Cotes base grid, FP32 storage), MLVS against UVS.  Both start from
     the freestream and take `warmup` untimed steps on the base grid (an
@@ -206,6 +233,12 @@ def cylinder_case(steps=200, warmup=100, precision=32):
     import paper_2609_35258_amd as m
     from paper_2609_35258_amd import autotune
     p = W.cylinder(256, 128, Kn=0.1, nv=101, vmax=10.0)
+    if mode == "uvs":
+        u, t_u, upd_u, _ = run_gpu(p, steps, warmup + 2, precision, None)
+        prof_u = stage_profile(u, reps=5)
+        u.close()
+        return {"uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps,
+                        "roofline": roofline(prof_u, precision)}}
     s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=CYL_ADAPT, graph=True)
     s.step(warmup)
     s.adapt()
@@ -225,6 +258,9 @@ def cylinder_case(steps=200, warmup=100, precision=32):
     mem_m = s.memory()
     prof = stage_profile(s, reps=5)
     s.close()
+    if mode == "mlvs":
+        return {"value": upd / t_m, "ms_per_step": 1e3 * t_m / steps, "nbar": float(np.sum(npts * ncells) / np.sum(ncells)),
+                "roofline": roofline(prof, precision)}
     u, t_u, upd_u, _ = run_gpu(p, steps, warmup + 2, precision, None)
     f_u = u.moments()
     mem_u = u.memory()
@@ -258,6 +294,10 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-cylinder", action="store_true")
+    ap.add_argument("--cylinder-only", action="store_true",
+                    help="only the full-size cylinder comparison (profiling runs)")
+    ap.add_argument("--cylinder-steps", type=int, default=200)
+    ap.add_argument("--cylinder-mode", choices=("both", "mlvs", "uvs"), default="both")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
@@ -270,6 +310,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": args.copy_probe}))
+        return
+    if args.cylinder_only:
+        print(json.dumps({"cylinder": cylinder_case(steps=args.cylinder_steps, mode=args.cylinder_mode)}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
@@ -285,7 +328,9 @@ def main():
     fields_m = s.moments()
     mem_m = s.memory()
     prof = stage_profile(s)
-    roof = roofline(prof, args.precision)
+    variants = {k: v["variant"] for k, v in getattr(s, "tuned", {}).items()}
+    roof = roofline(prof, args.precision, variants,
+                    "cavity64-gh28-fp64-mlvs" if (args.n, args.nv, args.precision) == (64, 28, 64) else None)
     out = {"metric": "DUGKS cell-velocity updates/s (MLVS-DUGKS hot path, adaptation included)",
            "value": value, "unit": "cell-velocity updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * t_mlvs / args.steps, "higher_is_better": True,
@@ -316,7 +361,7 @@ def main():
                       "mlvs_vs_uvs_rel_l2": err}
         u.close()
     if not args.no_cylinder:
-        out["cylinder"] = cylinder_case()
+        out["cylinder"] = cylinder_case(steps=args.cylinder_steps)
     if not args.no_learned:
         out["learned"] = learned_vs_criterion()
     if not args.no_cpu_baseline:

@@ -1,8 +1,9 @@
 """Autotuner for the launch variants of the step's kernels.
 
 For each tunable stage the library holds several instantiations of the kernel
-(minimum-occupancy targets of 2, 4, 6 and 8 waves per SIMD, i.e. a register
-budget per lane).  The tuner times every variant on the solver's current
+(pairs of velocity points per lane per load batch and minimum waves per SIMD,
+i.e. memory-level parallelism against a register budget per lane).  The tuner
+times every variant on the solver's current
 state with HIP events (``Solver.time_stage``), keeps the fastest, and caches
 the choice in a JSON file keyed by GPU architecture, storage precision and the
 stage's work shape (items, mean velocity points per item), so later runs of

@@ -127,3 +127,54 @@ def test_learned_adaptation_run():
     assert np.max(np.abs(g.totals() - t0)) < 1e-12
     assert all(r["n_fallback"] < g.n_cells for r in reps)
     g.close()
+
+
+def test_learned_gain_over_criterion():
+    """What the network gains: from the same state and catalogue, a learned
+    adaptation runs the criterion only on the cells the tail-mass check rejects
+    (the criterion adaptation runs it on every cell), with few misclassified
+    cells, and the run stays close to the criterion-adapted run."""
+    m = _m()
+    p = W.perturb(W.periodic_box(24, 8, Lx=1.0, Ly=1.0 / 3, Kn=0.05, nv=32, vmax=5.0, kind="sine", amp=0.5), seed=8)
+    ap = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=1e-3, tau_clust=0.05, flux_test=True, interval=0)
+    crit = m.Solver.from_problem(p, compat=4, adapt=ap)
+    crit.step(2)
+    crit.adapt()
+    K = len(crit.level_info()[0])
+    X, Y = [], []
+    for _ in range(12):
+        crit.step(5)
+        X.append(crit.features())
+        Y.append(crit.labels())
+    X, Y = np.concatenate(X), np.concatenate(Y)
+    ok = Y >= 0
+    params, rep = m.mlp_train(W.mlp_init_params(K, 0), K, X[ok], Y[ok], epochs=40, batch=256, lr=3e-3,
+                              val_frac=0.2, seed=1)
+    lrn = m.Solver.from_problem(p, compat=4, adapt=ap)
+    lrn.set_levels(np.stack([crit.level_kappa(k) for k in range(K)]), crit.cell_levels())
+    st = crit.get_state()
+    lrn.set_state([g for g, _ in st], [h for _, h in st])
+    lrn.selector_set(params, K)
+    n = p.n_cells
+    fb, mis = [], []
+    for _ in range(3):
+        lab = lrn.labels()
+        pred, _ = m.mlp_predict(params, K, lrn.features(), bf16=True)
+        mis.append(np.mean(pred[lab >= 0] != lab[lab >= 0]))
+        t0 = time.perf_counter()
+        crit.adapt()
+        t1 = time.perf_counter()
+        r = lrn.adapt()
+        t2 = time.perf_counter()
+        fb.append(r["n_fallback"] / n)
+        crit.step(5)
+        lrn.step(5)
+        print("adapt ms criterion %.2f learned %.2f, criterion cells %d of %d, misclassified %.3f"
+              % (1e3 * (t1 - t0), 1e3 * (t2 - t1), r["n_fallback"], n, mis[-1]), flush=True)
+    assert max(fb) < 0.2, fb
+    assert np.mean(mis) < 0.15, mis
+    fc, fl = crit.moments(), lrn.moments()
+    for k in (0, 3):
+        assert np.sqrt(np.sum((fl[:, k] - fc[:, k]) ** 2) / np.sum(fc[:, k] ** 2)) < 1e-3
+    crit.close()
+    lrn.close()
