@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -211,6 +212,7 @@ struct Level {
     std::vector<int> canon_of;             // device point -> canonical point (I/O order)
     double Minv[16];
     bool is_iface = false;
+    bool geo_in_arena = false;             // device geometry lives in a build's staging block
     // device
     double *d_x = nullptr, *d_y = nullptr, *d_w = nullptr;
     int* d_pt_of_base = nullptr;
@@ -383,6 +385,36 @@ struct DevTable {
     int* idx = nullptr;
     double* frac = nullptr;
     PairTable view() const { return PairTable{off, idx, frac}; }
+};
+
+// Host image of the many small arrays a level set needs on the device (work
+// lists, projection tables, descriptors): one device block and one copy per
+// build instead of one allocation and copy per array.  Pieces are 256-byte
+// aligned; the block starts with a 256-byte pad so no piece shares the block's
+// address.
+struct Stage {
+    std::vector<char> buf;
+    Stage() { buf.assign(256, 0); }
+    size_t put(const void* p, size_t n) {
+        const size_t off = (buf.size() + 255) & ~size_t(255);
+        buf.resize(off + std::max<size_t>(n, 1), 0);
+        if (p && n) std::memcpy(buf.data() + off, p, n);
+        return off;
+    }
+    template <typename T>
+    size_t put(const std::vector<T>& v) { return put(v.data(), sizeof(T) * v.size()); }
+    template <typename T>
+    void fill(size_t off, const std::vector<T>& v) {
+        if (!v.empty()) std::memcpy(buf.data() + off, v.data(), sizeof(T) * v.size());
+    }
+};
+
+struct TabOff {
+    size_t off = 0, idx = 0, frac = 0;
+    PairTable at(char* base) const {
+        return PairTable{reinterpret_cast<const int*>(base + off), reinterpret_cast<const int*>(base + idx),
+                         reinterpret_cast<const double*>(base + frac)};
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -569,6 +601,8 @@ struct mlvs_ctx_s {
     CellGeom* d_geom = nullptr;
     double* d_params = nullptr;
     double* d_cmom = nullptr;          // [chunks][n_cells][NMOM] raw moments of the stored state
+    std::vector<char> stage_keep;      // host image of the last staged upload
+    void* levels_block = nullptr;      // device block with the current levels' geometry
     double* d_fmom = nullptr;          // [chunks][faces + boundary faces][NFMOM] face moments
     int chunk = 1024;                  // velocity points per chunk (multiple of 64)
     int nch = 1;                       // chunks of the largest level
@@ -621,9 +655,9 @@ void upload_level_geometry(mlvs_ctx c, Level& L) {
 }
 
 void free_level(mlvs_ctx c, Level& L) {
-    for (void* p : {(void*)L.d_x, (void*)L.d_y, (void*)L.d_w, (void*)L.d_pt_of_base, L.g, L.h, L.fg, L.fh, L.Fg,
-                    L.Fh})
-        c->dm.release(p);
+    if (!L.geo_in_arena)
+        for (void* p : {(void*)L.d_x, (void*)L.d_y, (void*)L.d_w, (void*)L.d_pt_of_base}) c->dm.release(p);
+    for (void* p : {L.g, L.h, L.fg, L.fh, L.Fg, L.Fh}) c->dm.release(p);
     L.d_x = L.d_y = L.d_w = nullptr;
     L.d_pt_of_base = nullptr;
     L.g = L.h = L.fg = L.fh = L.Fg = L.Fh = nullptr;
@@ -635,14 +669,6 @@ void alloc_state(mlvs_ctx c, Level& L) {
     L.h = c->dm.alloc(n);
 }
 
-DevTable upload_table(mlvs_ctx c, const HostTable& t) {
-    DevTable d;
-    d.off = upload(c->dm, t.off, c->st);
-    d.idx = upload(c->dm, t.idx, c->st);
-    d.frac = upload(c->dm, t.frac, c->st);
-    c->tables.push_back(d);
-    return d;
-}
 
 void drop_graph(mlvs_ctx c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -668,19 +694,15 @@ void free_items(mlvs_ctx c) {
     c->n_faces = c->n_bfaces = c->n_ghosts = c->n_xfaces = 0;
 }
 
-template <typename T>
-T* upload_item(mlvs_ctx c, const std::vector<T>& v) {
-    T* d = upload(c->dm, v, c->st);
-    c->item_allocs.push_back(d);
-    return d;
-}
 
+// Interface level min(kA, kB): host tables only; build_items stages its
+// device geometry.
 Level* find_iface(mlvs_ctx c, const std::vector<uint8_t>& k, int& idx) {
     for (size_t i = 0; i < c->ifaces.size(); ++i)
         if (c->ifaces[i]->kappa == k) { idx = (int)(c->levels.size() + i); return c->ifaces[i].get(); }
     auto L = build_level(c->base, k);
     L->is_iface = true;
-    upload_level_geometry(c, *L);
+    L->stride = (L->N + 63) / 64 * 64;
     c->ifaces.push_back(std::move(L));
     idx = (int)(c->levels.size() + c->ifaces.size() - 1);
     return c->ifaces.back().get();
@@ -692,28 +714,35 @@ Level& level_by_index(mlvs_ctx c, int i) {
 }
 
 // Build face/ghost/cross-face work lists, flux rows and per-cell codes for the
-// current level set and upload them.  Level state buffers must exist.
+// current level set and upload them (one staged block).  Level state buffers
+// must exist.
 void build_items(mlvs_ctx c) {
     free_items(c);
     MeshH& M = c->mesh;
     const int n = M.n_cells;
     const int K = (int)c->levels.size();
+    Stage stg;
     std::vector<int> rows(K, 0), ghosts(K, 0);
     std::vector<int> cell_frow(4 * n, -1);
     std::vector<int> cell_nbr(4 * n, -1);
     std::vector<FaceItem> faces;
     std::vector<FaceItem> bfaces;
     std::vector<GhostItem> gitems;
+    std::vector<TabOff> gtab;
     std::vector<XFaceItem> xitems;
     std::map<std::pair<int, int>, int> ghost_of;        // (source cell, dst level) -> row
-    std::map<std::pair<int, int>, DevTable> tab_of;      // (dst level idx, src level idx)
+    std::map<std::pair<int, int>, TabOff> tab_of;       // (dst level idx, src level idx)
     auto table = [&](int dst, int src) {
         auto key = std::make_pair(dst, src);
         auto it = tab_of.find(key);
         if (it != tab_of.end()) return it->second;
-        DevTable d = upload_table(c, make_table(level_by_index(c, dst), level_by_index(c, src)));
-        tab_of[key] = d;
-        return d;
+        const HostTable ht = make_table(level_by_index(c, dst), level_by_index(c, src));
+        TabOff t;
+        t.off = stg.put(ht.off);
+        t.idx = stg.put(ht.idx);
+        t.frac = stg.put(ht.frac);
+        tab_of[key] = t;
+        return t;
     };
     // face codes read by the update: 4 x + 2 final + neg, x = face item (final = 0)
     // or the level row of a final cross-level flux (final = 1)
@@ -733,8 +762,8 @@ void build_items(mlvs_ctx c) {
                 ghost_of[key] = row;
                 GhostItem G{};
                 G.n = nb; G.dst = lc; G.row = row;
-                G.tab = table(lc, ln).view();
                 gitems.push_back(G);
+                gtab.push_back(table(lc, ln));
             } else {
                 row = it->second;
             }
@@ -742,7 +771,6 @@ void build_items(mlvs_ctx c) {
         }
     // interior faces
     int n_cross = 0;
-    std::vector<std::pair<int, int>> xpairs;
     for (size_t f = 0; f < M.faces.size(); ++f) {
         const FaceH& F = M.faces[f];
         const int lL = c->cell_level[F.L], lR = c->cell_level[F.R];
@@ -780,12 +808,10 @@ void build_items(mlvs_ctx c) {
             cell_frow[4 * F.R + kR] = face_code(it.rowB, true, true);
         }
     }
-    for (auto& it : xitems) {
-        it.IfromA = table(it.levI, it.levA).view();
-        it.IfromB = table(it.levI, it.levB).view();
-        it.AfromI = table(it.levA, it.levI).view();
-        it.BfromI = table(it.levB, it.levI).view();
-    }
+    std::vector<std::array<TabOff, 4>> xtab;
+    for (auto& it : xitems)
+        xtab.push_back({table(it.levI, it.levA), table(it.levI, it.levB), table(it.levA, it.levI),
+                        table(it.levB, it.levI)});
     c->n_cross = n_cross;
     c->step_points = 0.0;
     for (int cc = 0; cc < n; ++cc) c->step_points += c->levels[c->cell_level[cc]]->N;
@@ -814,10 +840,52 @@ void build_items(mlvs_ctx c) {
         L.Fg = c->dm.alloc(nr); L.Fh = c->dm.alloc(nr);
         L.fg = c->dm.alloc(nf); L.fh = c->dm.alloc(nf);
     }
+    struct GeoOff { size_t x, y, w, ptb; };
+    std::vector<GeoOff> igeo;
     for (auto& Lp : c->ifaces) {
         Level& L = *Lp;
         const size_t nr = (size_t)std::max(L.n_rows, 1) * L.stride * c->elt();
         L.Fg = c->dm.alloc(nr); L.Fh = c->dm.alloc(nr);
+        igeo.push_back({stg.put(L.xi_x), stg.put(L.xi_y), stg.put(L.w), stg.put(L.pt_of_base)});
+    }
+    c->n_faces = (int)faces.size();
+    c->n_bfaces = (int)bfaces.size();
+    faces.insert(faces.end(), bfaces.begin(), bfaces.end());
+    std::vector<int> ptb, poff;
+    std::vector<uint8_t> kap;
+    if (c->base.Nb > 0) {
+        for (int l = 0; l < K; ++l) {
+            poff.push_back((int)ptb.size());
+            ptb.insert(ptb.end(), c->levels[l]->pt_of_base.begin(), c->levels[l]->pt_of_base.end());
+            kap.insert(kap.end(), c->levels[l]->kappa.begin(), c->levels[l]->kappa.end());
+        }
+    }
+    // places of the arrays that hold device pointers (filled once the block exists)
+    const size_t o_lv = stg.put(nullptr, sizeof(LevelDesc) * (K + c->ifaces.size()));
+    const size_t o_gh = stg.put(nullptr, sizeof(GhostItem) * gitems.size());
+    const size_t o_xf = stg.put(nullptr, sizeof(XFaceItem) * xitems.size());
+    const size_t o_faces = stg.put(faces);
+    const size_t o_frow = stg.put(cell_frow);
+    const size_t o_nbr = stg.put(cell_nbr);
+    const size_t o_lev = stg.put(c->cell_level);
+    const size_t o_slot = stg.put(c->cell_slot);
+    const size_t o_ptb = stg.put(ptb), o_poff = stg.put(poff), o_kap = stg.put(kap);
+    char* base = static_cast<char*>(c->dm.alloc(stg.buf.size()));
+    c->item_allocs.push_back(base);
+    for (size_t i = 0; i < c->ifaces.size(); ++i) {
+        Level& L = *c->ifaces[i];
+        L.d_x = reinterpret_cast<double*>(base + igeo[i].x);
+        L.d_y = reinterpret_cast<double*>(base + igeo[i].y);
+        L.d_w = reinterpret_cast<double*>(base + igeo[i].w);
+        L.d_pt_of_base = reinterpret_cast<int*>(base + igeo[i].ptb);
+        L.geo_in_arena = true;
+    }
+    for (size_t i = 0; i < gitems.size(); ++i) gitems[i].tab = gtab[i].at(base);
+    for (size_t i = 0; i < xitems.size(); ++i) {
+        xitems[i].IfromA = xtab[i][0].at(base);
+        xitems[i].IfromB = xtab[i][1].at(base);
+        xitems[i].AfromI = xtab[i][2].at(base);
+        xitems[i].BfromI = xtab[i][3].at(base);
     }
     // level descriptors: representative levels then interface levels
     std::vector<LevelDesc> descs;
@@ -830,11 +898,24 @@ void build_items(mlvs_ctx c) {
         std::copy(L.Minv, L.Minv + 16, d.Minv);
         descs.push_back(d);
     }
-    c->d_lv = upload_item(c, descs);
-    c->n_faces = (int)faces.size();
-    c->n_bfaces = (int)bfaces.size();
-    faces.insert(faces.end(), bfaces.begin(), bfaces.end());
-    c->d_faces = upload_item(c, faces);
+    stg.fill(o_lv, descs);
+    stg.fill(o_gh, gitems);
+    stg.fill(o_xf, xitems);
+    hip_check(hipMemcpyAsync(base, stg.buf.data(), stg.buf.size(), hipMemcpyHostToDevice, c->st), "upload");
+    c->stage_keep = std::move(stg.buf);        // the host image stays alive until the next build
+    c->d_lv = reinterpret_cast<LevelDesc*>(base + o_lv);
+    c->d_faces = reinterpret_cast<FaceItem*>(base + o_faces);
+    c->d_ghosts = reinterpret_cast<GhostItem*>(base + o_gh); c->n_ghosts = (int)gitems.size();
+    c->d_xfaces = reinterpret_cast<XFaceItem*>(base + o_xf); c->n_xfaces = (int)xitems.size();
+    c->d_cell_frow = reinterpret_cast<int*>(base + o_frow);
+    c->d_cell_nbr = reinterpret_cast<int*>(base + o_nbr);
+    c->d_cell_lev = reinterpret_cast<int*>(base + o_lev);
+    c->d_cell_slot = reinterpret_cast<int*>(base + o_slot);
+    if (c->base.Nb > 0) {
+        c->d_ptb_all = reinterpret_cast<int*>(base + o_ptb);
+        c->d_ptb_off = reinterpret_cast<int*>(base + o_poff);
+        c->d_kappa_all = reinterpret_cast<uint8_t*>(base + o_kap);
+    }
     int nmax = 1;
     for (int l = 0; l < K; ++l) nmax = std::max(nmax, c->levels[l]->N);
     c->nch = (nmax + c->chunk - 1) / c->chunk;
@@ -846,24 +927,6 @@ void build_items(mlvs_ctx c) {
     c->mom_valid = false;
     c->d_fpar = static_cast<double*>(c->dm.alloc(sizeof(double) * NFP * std::max<size_t>(faces.size(), 1)));
     c->item_allocs.push_back(c->d_fpar);
-    c->d_ghosts = upload_item(c, gitems); c->n_ghosts = (int)gitems.size();
-    c->d_xfaces = upload_item(c, xitems); c->n_xfaces = (int)xitems.size();
-    c->d_cell_frow = upload_item(c, cell_frow);
-    c->d_cell_nbr = upload_item(c, cell_nbr);
-    c->d_cell_lev = upload_item(c, c->cell_level);
-    c->d_cell_slot = upload_item(c, c->cell_slot);
-    if (c->base.Nb > 0) {
-        std::vector<int> ptb, off;
-        std::vector<uint8_t> kap;
-        for (int l = 0; l < K; ++l) {
-            off.push_back((int)ptb.size());
-            ptb.insert(ptb.end(), c->levels[l]->pt_of_base.begin(), c->levels[l]->pt_of_base.end());
-            kap.insert(kap.end(), c->levels[l]->kappa.begin(), c->levels[l]->kappa.end());
-        }
-        c->d_ptb_all = upload_item(c, ptb);
-        c->d_ptb_off = upload_item(c, off);
-        c->d_kappa_all = upload_item(c, kap);
-    }
 }
 
 void assign_slots(mlvs_ctx c) {
@@ -905,10 +968,56 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
     c->levels = std::move(nl);
     c->cell_level = new_cell_level;
     assign_slots(c);
+    // one staged block: the new levels' geometry (kept with the level set) and
+    // the remap's descriptors, tables and work list
+    Stage stg;
+    struct GeoOff { size_t x, y, w, ptb; };
+    std::vector<GeoOff> geo;
     for (auto& L : c->levels) {
-        upload_level_geometry(c, *L);
+        L->stride = (L->N + 63) / 64 * 64;
+        geo.push_back({stg.put(L->xi_x), stg.put(L->xi_y), stg.put(L->w), stg.put(L->pt_of_base)});
         alloc_state(c, *L);
     }
+    std::vector<RemapItem> items(n);
+    std::map<std::pair<int, int>, TabOff> tabs;
+    std::vector<TabOff> item_tab(n);
+    std::vector<char> has_tab(n, 0);
+    int64_t changed = 0;
+    for (int cc = 0; cc < n; ++cc) {
+        RemapItem& r = items[cc];
+        r.c = cc;
+        r.src_lev = old_level[cc]; r.src_slot = old_slot[cc];
+        r.dst_lev = c->cell_level[cc]; r.dst_slot = c->cell_slot[cc];
+        r.tab = PairTable{nullptr, nullptr, nullptr};
+        if (old[r.src_lev]->kappa == c->levels[r.dst_lev]->kappa) continue;
+        ++changed;
+        auto key = std::make_pair(r.dst_lev, r.src_lev);
+        auto it = tabs.find(key);
+        if (it == tabs.end()) {
+            const HostTable ht = make_table(*c->levels[r.dst_lev], *old[r.src_lev]);
+            TabOff t;
+            t.off = stg.put(ht.off);
+            t.idx = stg.put(ht.idx);
+            t.frac = stg.put(ht.frac);
+            it = tabs.emplace(key, t).first;
+        }
+        item_tab[cc] = it->second;
+        has_tab[cc] = 1;
+    }
+    const size_t o_od = stg.put(nullptr, sizeof(LevelDesc) * old.size());
+    const size_t o_nd = stg.put(nullptr, sizeof(LevelDesc) * c->levels.size());
+    const size_t o_items = stg.put(nullptr, sizeof(RemapItem) * n);
+    char* base = static_cast<char*>(c->dm.alloc(stg.buf.size()));
+    for (size_t l = 0; l < c->levels.size(); ++l) {
+        Level& L = *c->levels[l];
+        L.d_x = reinterpret_cast<double*>(base + geo[l].x);
+        L.d_y = reinterpret_cast<double*>(base + geo[l].y);
+        L.d_w = reinterpret_cast<double*>(base + geo[l].w);
+        L.d_pt_of_base = reinterpret_cast<int*>(base + geo[l].ptb);
+        L.geo_in_arena = true;
+    }
+    for (int cc = 0; cc < n; ++cc)
+        if (has_tab[cc]) items[cc].tab = item_tab[cc].at(base);
     // old descriptors (state only) and new descriptors
     auto descs_of = [&](std::vector<std::unique_ptr<Level>>& ls) {
         std::vector<LevelDesc> d;
@@ -921,44 +1030,17 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
         }
         return d;
     };
-    std::vector<LevelDesc> od = descs_of(old), nd = descs_of(c->levels);
-    LevelDesc* d_od = upload(c->dm, od, c->st);
-    LevelDesc* d_nd = upload(c->dm, nd, c->st);
-    std::vector<RemapItem> items(n);
-    std::map<std::pair<int, int>, DevTable> tabs;
-    std::vector<DevTable> tmp_tabs;
-    int64_t changed = 0;
-    for (int cc = 0; cc < n; ++cc) {
-        RemapItem& r = items[cc];
-        r.c = cc;
-        r.src_lev = old_level[cc]; r.src_slot = old_slot[cc];
-        r.dst_lev = c->cell_level[cc]; r.dst_slot = c->cell_slot[cc];
-        if (old[r.src_lev]->kappa == c->levels[r.dst_lev]->kappa) {
-            r.tab = PairTable{nullptr, nullptr, nullptr};
-            continue;
-        }
-        ++changed;
-        auto key = std::make_pair(r.dst_lev, r.src_lev);
-        auto it = tabs.find(key);
-        if (it == tabs.end()) {
-            HostTable ht = make_table(*c->levels[r.dst_lev], *old[r.src_lev]);
-            DevTable d;
-            d.off = upload(c->dm, ht.off, c->st);
-            d.idx = upload(c->dm, ht.idx, c->st);
-            d.frac = upload(c->dm, ht.frac, c->st);
-            tmp_tabs.push_back(d);
-            it = tabs.emplace(key, d).first;
-        }
-        r.tab = it->second.view();
-    }
-    RemapItem* d_items = upload(c->dm, items, c->st);
-    hip_check(launch_remap(c->prec, c->st, d_od, d_nd, d_items, n, c->ph, c->d_neg), "remap launch");
+    stg.fill(o_od, descs_of(old));
+    stg.fill(o_nd, descs_of(c->levels));
+    stg.fill(o_items, items);
+    hip_check(hipMemcpyAsync(base, stg.buf.data(), stg.buf.size(), hipMemcpyHostToDevice, c->st), "upload");
+    hip_check(launch_remap(c->prec, c->st, reinterpret_cast<LevelDesc*>(base + o_od),
+                           reinterpret_cast<LevelDesc*>(base + o_nd), reinterpret_cast<RemapItem*>(base + o_items), n,
+                           c->ph, c->d_neg), "remap launch");
     sync(c);
-    c->dm.release(d_items);
-    c->dm.release(d_od);
-    c->dm.release(d_nd);
-    for (auto& d : tmp_tabs) { c->dm.release(d.off); c->dm.release(d.idx); c->dm.release(d.frac); }
     for (auto& L : old) free_level(c, *L);
+    c->dm.release(c->levels_block);            // the old level set's geometry block
+    c->levels_block = base;
     build_items(c);
     sync(c);
     c->mom_valid = false;
