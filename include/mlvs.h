@@ -72,8 +72,12 @@ typedef struct {
  *  compat     0 or 4: four-moment compatibility correction of the Shakhov
  *             target (Sec. 3.3.1, Eq. eq_four_moment_constraint).
  *  face_compat 1: also correct the face target used in Eq. recover_phi.
- *  map_moments 0 or 4: four-moment linear mapping correction for level
- *             switches, neighbour mapping and cross-level fluxes (Sec. 3.3.2). */
+ *  map_moments 0, 4 or 9: linear mapping correction for level switches,
+ *             neighbour mapping and cross-level states and fluxes (Sec. 3.3.2):
+ *             four moments (mass, momentum, energy; Eqs. raw_four_g_basis,
+ *             raw_four_gh_coupling) or nine (also the second g moments and the
+ *             energy flux; Eqs. raw_six_g_basis, raw_three_h_basis,
+ *             mapping_h_residual_correction).  9 needs dim = 2. */
 typedef struct {
     int dim, K;
     double R, Pr, omega, mu_ref, T_ref;

@@ -126,29 +126,33 @@ void gauss_hermite(int n, double R, double T0, double* x, double* w) {
 // ---------------------------------------------------------------------------
 // small dense helpers
 // ---------------------------------------------------------------------------
-bool invert4(const double* A, double* inv) {
-    double M[4][8];
-    for (int r = 0; r < 4; ++r)
-        for (int c = 0; c < 8; ++c) M[r][c] = c < 4 ? A[r * 4 + c] : (c - 4 == r ? 1.0 : 0.0);
-    for (int k = 0; k < 4; ++k) {
+// Inverse of a row-major n x n matrix (n <= 8) by Gauss-Jordan elimination with
+// partial pivoting; false if singular.
+bool invert_n(const double* A, int n, double* inv) {
+    double M[8][16];
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < 2 * n; ++c) M[r][c] = c < n ? A[r * n + c] : (c - n == r ? 1.0 : 0.0);
+    for (int k = 0; k < n; ++k) {
         int p = k;
-        for (int i = k + 1; i < 4; ++i)
+        for (int i = k + 1; i < n; ++i)
             if (std::fabs(M[i][k]) > std::fabs(M[p][k])) p = i;
         if (M[p][k] == 0.0) return false;
         if (p != k)
-            for (int c = 0; c < 8; ++c) std::swap(M[k][c], M[p][c]);
+            for (int c = 0; c < 2 * n; ++c) std::swap(M[k][c], M[p][c]);
         const double d = M[k][k];
-        for (int c = 0; c < 8; ++c) M[k][c] /= d;
-        for (int i = 0; i < 4; ++i) {
+        for (int c = 0; c < 2 * n; ++c) M[k][c] /= d;
+        for (int i = 0; i < n; ++i) {
             if (i == k) continue;
             const double f = M[i][k];
-            for (int c = 0; c < 8; ++c) M[i][c] -= f * M[k][c];
+            for (int c = 0; c < 2 * n; ++c) M[i][c] -= f * M[k][c];
         }
     }
-    for (int r = 0; r < 4; ++r)
-        for (int c = 0; c < 4; ++c) inv[r * 4 + c] = M[r][c + 4];
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) inv[r * n + c] = M[r][c + n];
     return true;
 }
+
+bool invert4(const double* A, double* inv) { return invert_n(A, 4, inv); }
 
 // ---------------------------------------------------------------------------
 // device memory
@@ -211,6 +215,7 @@ struct Level {
     std::vector<int> mem_off, mem_idx;     // base members per point (ascending)
     std::vector<int> canon_of;             // device point -> canonical point (I/O order)
     double Minv[16];
+    double G6inv[36], B36[18], H3inv[9];   // nine-moment mapping (see build_level)
     bool is_iface = false;
     bool geo_in_arena = false;             // device geometry lives in a build's staging block
     // device
@@ -339,6 +344,25 @@ std::unique_ptr<Level> build_level(const Base& B, const std::vector<uint8_t>& ka
             for (int c = 0; c < 4; ++c) A[r * 4 + c] += w * psi[r] * phi[c];
     }
     if (!invert4(A, L->Minv)) std::fill(L->Minv, L->Minv + 16, 0.0);
+    // state-independent matrices of the nine-moment mapping (Eqs. raw_six_g_basis,
+    // raw_three_h_basis, mapping_h_residual_correction): g basis [1, x, y, x^2,
+    // y^2, xy] against the same six g moments; h basis [1, x, y] against the
+    // energy and energy-flux moments (1/2 weight); B couples the g correction
+    // into those three through 1/2 |xi|^2 dg.
+    double Ag[36] = {0}, Ah[9] = {0};
+    std::fill(L->B36, L->B36 + 18, 0.0);
+    for (int p = 0; p < L->N; ++p) {
+        const double x = L->xi_x[p], y = L->xi_y[p], w = L->w[p], x2 = x * x + y * y;
+        const double pg[6] = {1.0, x, y, x * x, y * y, x * y}, ph3[3] = {1.0, x, y};
+        for (int r = 0; r < 6; ++r)
+            for (int c = 0; c < 6; ++c) Ag[r * 6 + c] += w * pg[r] * pg[c];
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) Ah[r * 3 + c] += 0.5 * w * ph3[r] * ph3[c];
+            for (int c = 0; c < 6; ++c) L->B36[r * 6 + c] += w * x2 * ph3[r] * pg[c];
+        }
+    }
+    if (!invert_n(Ag, 6, L->G6inv)) std::fill(L->G6inv, L->G6inv + 36, 0.0);
+    if (!invert_n(Ah, 3, L->H3inv)) std::fill(L->H3inv, L->H3inv + 9, 0.0);
     return L;
 }
 
@@ -896,6 +920,9 @@ void build_items(mlvs_ctx c) {
         d.xi_x = L.d_x; d.xi_y = L.d_y; d.w = L.d_w;
         d.g = L.g; d.h = L.h; d.fg = L.fg; d.fh = L.fh; d.Fg = L.Fg; d.Fh = L.Fh;
         std::copy(L.Minv, L.Minv + 16, d.Minv);
+        std::copy(L.G6inv, L.G6inv + 36, d.G6inv);
+        std::copy(L.B36, L.B36 + 18, d.B36);
+        std::copy(L.H3inv, L.H3inv + 9, d.H3inv);
         descs.push_back(d);
     }
     stg.fill(o_lv, descs);
@@ -1026,6 +1053,9 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
             x.N = Lp->N; x.stride = Lp->stride; x.xi_x = Lp->d_x; x.xi_y = Lp->d_y; x.w = Lp->d_w;
             x.g = Lp->g; x.h = Lp->h;
             std::copy(Lp->Minv, Lp->Minv + 16, x.Minv);
+            std::copy(Lp->G6inv, Lp->G6inv + 36, x.G6inv);
+            std::copy(Lp->B36, Lp->B36 + 18, x.B36);
+            std::copy(Lp->H3inv, Lp->H3inv + 9, x.H3inv);
             d.push_back(x);
         }
         return d;
@@ -1561,7 +1591,9 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         if (phys->dim != 1 && phys->dim != 2) fail(MLVS_E_ARG, "dim must be 1 or 2");
         if (phys->precision != 32 && phys->precision != 64) fail(MLVS_E_ARG, "precision must be 32 or 64");
         if (phys->compat != 0 && phys->compat != 4) fail(MLVS_E_ARG, "compat must be 0 or 4");
-        if (phys->map_moments != 0 && phys->map_moments != 4) fail(MLVS_E_ARG, "map_moments must be 0 or 4");
+        if (phys->map_moments != 0 && phys->map_moments != 4 && phys->map_moments != 9)
+            fail(MLVS_E_ARG, "map_moments must be 0, 4 or 9");
+        if (phys->map_moments == 9 && phys->dim != 2) fail(MLVS_E_ARG, "map_moments 9 needs dim = 2");
         if (!(phys->R > 0) || !(phys->mu_ref > 0) || !(phys->T_ref > 0)) fail(MLVS_E_ARG, "bad physical constants");
         if (mesh->ni < 1 || mesh->nj < 1 || !mesh->node_x || !mesh->node_y) fail(MLVS_E_ARG, "bad mesh");
         if (phys->dim == 1 && mesh->nj != 1) fail(MLVS_E_ARG, "1-D meshes need nj = 1");

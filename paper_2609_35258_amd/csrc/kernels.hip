@@ -525,28 +525,86 @@ __global__ __launch_bounds__(BS) void k_init_eq(const LevelDesc* __restrict__ lv
 }
 
 // ---------------------------------------------------------------------------
-// neighbours on other levels: projection + four-moment mapping correction
+// neighbours on other levels: projection + linear mapping correction
 // ---------------------------------------------------------------------------
+// The nine mapped moments (Eq. mapping_nine_targets): [rho, rho u, rho v,
+// rho E, G_xx, G_yy, G_xy, J_x, J_y] with E = (|xi|^2 g + h)/2, G the second g
+// moments and J = sum w xi E.  The first four are the four-moment set.
+__device__ __forceinline__ void acc_m9(double* m, double w, double x, double y, double g, double h) {
+    const double wg = w * g, E = 0.5 * w * ((x * x + y * y) * g + h);
+    m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += E;
+    m[4] += wg * x * x; m[5] += wg * y * y; m[6] += wg * x * y; m[7] += E * x; m[8] += E * y;
+}
+
+// Coefficients of the linear correction on level D for the moment defect dM:
+// four moments (Eqs. raw_four_g_basis, raw_four_gh_coupling): dg = a . [1, x,
+// y, |xi|^2], dh = (3 - D + K) R T_tar dg; nine moments (Eqs. raw_six_g_basis,
+// raw_three_h_basis, mapping_h_residual_correction): dg = a . [1, x, y, x^2,
+// y^2, xy] against the six g moments, then dh = b . [1, x, y] against the
+// energy and energy-flux residuals left by dg.
+struct MapCoef { double a[6], b[3]; bool nine; };
+
+__device__ __forceinline__ MapCoef map_coeffs(const LevelDesc& D, const double* dM, double Ttar, const Phys& ph) {
+    MapCoef m{};
+    m.nine = ph.map_moments == 9;
+    if (m.nine) {
+        const double d6[6] = {dM[0], dM[1], dM[2], dM[4], dM[5], dM[6]};
+        for (int r = 0; r < 6; ++r) {
+            double s = 0.0;
+            for (int c = 0; c < 6; ++c) s += D.G6inv[r * 6 + c] * d6[c];
+            m.a[r] = s;
+        }
+        double r3[3];
+        for (int r = 0; r < 3; ++r) {
+            double s = 0.0;
+            for (int c = 0; c < 6; ++c) s += D.B36[r * 6 + c] * m.a[c];
+            r3[r] = (r == 0 ? dM[3] : dM[6 + r]) - 0.5 * s;
+        }
+        for (int r = 0; r < 3; ++r) {
+            double s = 0.0;
+            for (int c = 0; c < 3; ++c) s += D.H3inv[r * 3 + c] * r3[c];
+            m.b[r] = s;
+        }
+    } else {
+        const double cK = 3.0 - ph.D + ph.K;
+        const double rhs[4] = {dM[0], dM[1], dM[2], dM[3] - 0.5 * cK * ph.R * Ttar * dM[0]};
+        for (int r = 0; r < 4; ++r) {
+            double s = 0.0;
+            for (int c = 0; c < 4; ++c) s += D.Minv[r * 4 + c] * rhs[c];
+            m.a[r] = s;
+        }
+        m.b[0] = cK * ph.R * Ttar;         // dh = b0 dg
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) m.a[k] = uni(m.a[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) m.b[k] = uni(m.b[k]);
+    return m;
+}
+
+__device__ __forceinline__ void map_delta(const MapCoef& m, double x, double y, double& dg, double& dh) {
+    if (m.nine) {
+        dg = m.a[0] + m.a[1] * x + m.a[2] * y + m.a[3] * x * x + m.a[4] * y * y + m.a[5] * x * y;
+        dh = m.b[0] + m.b[1] * x + m.b[2] * y;
+    } else {
+        dg = m.a[0] + m.a[1] * x + m.a[2] * y + m.a[3] * (x * x + y * y);
+        dh = m.b[0] * dg;
+    }
+}
+
 template <typename S>
 __device__ __forceinline__ void map_correct_apply(const LevelDesc& D, gptr<S> gdst, gptr<S> hdst, const double* dM,
                                                   double Ttar, const Phys& ph, int& negflag) {
-    const double cK = 3.0 - ph.D + ph.K;
-    double rhs[4] = {dM[0], dM[1], dM[2], dM[3] - 0.5 * cK * ph.R * Ttar * dM[0]};
-    double a[4];
-    for (int r = 0; r < 4; ++r) {
-        double s = 0.0;
-        for (int c = 0; c < 4; ++c) s += D.Minv[r * 4 + c] * rhs[c];
-        a[r] = s;
-    }
-    const double kh = cK * ph.R * Ttar;
+    const MapCoef mc = map_coeffs(D, dM, Ttar, ph);
     for (int i = lane_id(); i < D.N; i += WL) {
         const double x = gp(D.xi_x)[i], y = gp(D.xi_y)[i];
-        const double dg = a[0] + a[1] * x + a[2] * y + a[3] * (x * x + y * y);
-        const S gp = gdst[i];
-        const S gn = (S)((double)gp + dg);
-        if (gn < S(0) && gp >= S(0)) negflag = 1;
+        double dg, dh;
+        map_delta(mc, x, y, dg, dh);
+        const S gprov = gdst[i];
+        const S gn = (S)((double)gprov + dg);
+        if (gn < S(0) && gprov >= S(0)) negflag = 1;
         gdst[i] = gn;
-        hdst[i] = (S)((double)hdst[i] + kh * dg);
+        hdst[i] = (S)((double)hdst[i] + dh);
     }
 }
 
@@ -564,14 +622,11 @@ __global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs,
         auto sh = rowp<S>(Ls.fh, srow);
         auto dg = rowp<S>(Ld.fg, (size_t)(Ld.n_rows_state + G.row) * Ld.stride);
         auto dh = rowp<S>(Ld.fh, (size_t)(Ld.n_rows_state + G.row) * Ld.stride);
-        double m[8];
+        double m[18];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) m[k] = 0.0;
-        for (int i = lane_id(); i < Ls.N; i += WL) {       // target: moments on the source level
-            const double x = gp(Ls.xi_x)[i], y = gp(Ls.xi_y)[i], w = gp(Ls.w)[i];
-            const double wg = w * (double)sg[i];
-            m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += 0.5 * (wg * (x * x + y * y) + w * (double)sh[i]);
-        }
+        for (int k = 0; k < 18; ++k) m[k] = 0.0;
+        for (int i = lane_id(); i < Ls.N; i += WL)         // target: moments on the source level
+            acc_m9(m, gp(Ls.w)[i], gp(Ls.xi_x)[i], gp(Ls.xi_y)[i], (double)sg[i], (double)sh[i]);
         for (int P = lane_id(); P < Ld.N; P += WL) {       // provisional projection
             double gP = 0.0, HP = 0.0;
             for (int e = gp(G.tab.off)[P]; e < gp(G.tab.off)[P + 1]; ++e) {
@@ -587,13 +642,13 @@ __global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs,
             const S gs = (S)gP, hs = (S)hP;
             dg[P] = gs;
             dh[P] = hs;
-            const double wg = w * (double)gs;
-            m[4] += wg; m[5] += wg * x; m[6] += wg * y; m[7] += 0.5 * (wg * (x * x + y * y) + w * (double)hs);
+            acc_m9(m + 9, w, x, y, (double)gs, (double)hs);
         }
-        wave_sum<8>(m);
+        wave_sum<18>(m);
         int nf = 0;
         if (ph.map_moments) {
-            const double dM[4] = {m[0] - m[4], m[1] - m[5], m[2] - m[6], m[3] - m[7]};
+            double dM[9];
+            for (int k = 0; k < 9; ++k) dM[k] = m[k] - m[9 + k];
             map_correct_apply<S>(Ld, dg, dh, dM, params[(size_t)G.n * NPARAM + P_T], ph, nf);
         }
         nf = __any(nf);
@@ -1252,14 +1307,11 @@ __global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv,
             for (int i = lane_id(); i < Ld.N; i += WL) { dg[i] = sg[i]; dh[i] = sh[i]; }
             continue;
         }
-        double m[8];
+        double m[18];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) m[k] = 0.0;
-        for (int i = lane_id(); i < Ls.N; i += WL) {
-            const double x = gp(Ls.xi_x)[i], y = gp(Ls.xi_y)[i], w = gp(Ls.w)[i];
-            const double wg = w * (double)sg[i];
-            m[0] += wg; m[1] += wg * x; m[2] += wg * y; m[3] += 0.5 * (wg * (x * x + y * y) + w * (double)sh[i]);
-        }
+        for (int k = 0; k < 18; ++k) m[k] = 0.0;
+        for (int i = lane_id(); i < Ls.N; i += WL)
+            acc_m9(m, gp(Ls.w)[i], gp(Ls.xi_x)[i], gp(Ls.xi_y)[i], (double)sg[i], (double)sh[i]);
         for (int P = lane_id(); P < Ld.N; P += WL) {
             double gP = 0.0, HP = 0.0;
             for (int e = gp(R.tab.off)[P]; e < gp(R.tab.off)[P + 1]; ++e) {
@@ -1274,15 +1326,15 @@ __global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv,
             const S gs = (S)gP, hs = (S)(HP - (x * x + y * y) * gP);
             dg[P] = gs;
             dh[P] = hs;
-            const double wg = w * (double)gs;
-            m[4] += wg; m[5] += wg * x; m[6] += wg * y; m[7] += 0.5 * (wg * (x * x + y * y) + w * (double)hs);
+            acc_m9(m + 9, w, x, y, (double)gs, (double)hs);
         }
-        wave_sum<8>(m);
+        wave_sum<18>(m);
         int nf = 0;
         if (ph.map_moments) {
             const double rho = m[0], u = m[1] / rho, v = m[2] / rho;
             const double T = (2.0 * m[3] / rho - (u * u + v * v)) / ((3.0 + ph.K) * ph.R);
-            const double dM[4] = {m[0] - m[4], m[1] - m[5], m[2] - m[6], m[3] - m[7]};
+            double dM[9];
+            for (int k = 0; k < 9; ++k) dM[k] = m[k] - m[9 + k];
             map_correct_apply<S>(Ld, dg, dh, dM, T, ph, nf);
         }
         nf = __any(nf);
@@ -1435,7 +1487,6 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
                                               const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
                                               const double* __restrict__ params, Phys ph, unsigned long long* neg) {
     const S s = (S)(0.5 * ph.dt);
-    const double cK = 3.0 - ph.D + ph.K;
     for (int it = item0(); it < n; it += istride()) {
         const XFaceItem F = items[it];
         const LevelDesc& LA = lvs[F.levA];
@@ -1446,9 +1497,9 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
         load_side<S>(sR, LB, F.R, cell_slot, cell_nbr, geom, F.dRx, F.dRy);
         const double TL = params[(size_t)F.L * NPARAM + P_T], TR = params[(size_t)F.R * NPARAM + P_T];
         // pass 1: provisional refined states and native target moments
-        double m[16];
+        double m[36];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) m[k] = 0.0;
+        for (int k = 0; k < 36; ++k) m[k] = 0.0;
         for (int P = lane_id(); P < LI.N; P += WL) {
             const double x = gp(LI.xi_x)[P], y = gp(LI.xi_y)[P], w = gp(LI.w)[P];
 #pragma unroll
@@ -1462,30 +1513,21 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
                 const double xa = gp(Ln.xi_x)[a], ya = gp(Ln.xi_y)[a];
                 const double ga = (double)f[0], ha = (double)f[1];
                 const double hP = ha + ((xa * xa + ya * ya) - (x * x + y * y)) * ga;
-                double* mm = m + 8 * side;
-                mm[0] += w * ga; mm[1] += w * x * ga; mm[2] += w * y * ga;
-                mm[3] += 0.5 * w * ((x * x + y * y) * ga + hP);
-                mm[4] += w * ga; mm[5] += w * xa * ga; mm[6] += w * ya * ga;
-                mm[7] += 0.5 * w * ((xa * xa + ya * ya) * ga + ha);
+                double* mm = m + 18 * side;
+                acc_m9(mm, w, x, y, ga, hP);          // provisional, on V_int
+                acc_m9(mm + 9, w, xa, ya, ga, ha);    // native (the parent's weight is the children's sum)
             }
         }
-        wave_sum<16>(m);
-        double aL[4] = {0, 0, 0, 0}, aR[4] = {0, 0, 0, 0};
+        wave_sum<36>(m);
+        MapCoef cL{}, cR{};
         if (ph.map_moments) {
             for (int side = 0; side < 2; ++side) {
-                const double* mm = m + 8 * side;
-                const double T = side ? TR : TL;
-                const double dM[4] = {mm[4] - mm[0], mm[5] - mm[1], mm[6] - mm[2], mm[7] - mm[3]};
-                const double rhs[4] = {dM[0], dM[1], dM[2], dM[3] - 0.5 * cK * ph.R * T * dM[0]};
-                double* aa = side ? aR : aL;
-                for (int r = 0; r < 4; ++r) {
-                    double acc = 0.0;
-                    for (int c = 0; c < 4; ++c) acc += LI.Minv[r * 4 + c] * rhs[c];
-                    aa[r] = acc;
-                }
+                const double* mm = m + 18 * side;
+                double dM[9];
+                for (int k = 0; k < 9; ++k) dM[k] = mm[9 + k] - mm[k];
+                (side ? cR : cL) = map_coeffs(LI, dM, side ? TR : TL, ph);
             }
         }
-        const double khL = cK * ph.R * TL, khR = cK * ph.R * TR;
         const double u0 = 0.5 * (params[(size_t)F.L * NPARAM + P_U] + params[(size_t)F.R * NPARAM + P_U]);
         const double v0 = 0.5 * (params[(size_t)F.L * NPARAM + P_V] + params[(size_t)F.R * NPARAM + P_V]);
         auto rg = rowp<S>(LI.Fg, (size_t)F.scratch * LI.stride);
@@ -1507,12 +1549,12 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
                 const int a = gp(tb.idx)[gp(tb.off)[P]];
                 S f[2], sx[2], sy[2];
                 side_refined<S>(sd, Ln, LI, a, P, f, sx, sy);
-                const double* aa = side ? aR : aL;
-                const double dg = aa[0] + aa[1] * xd + aa[2] * yd + aa[3] * (xd * xd + yd * yd);
-                const S gp = f[0];
+                double dg, dh;
+                map_delta(side ? cR : cL, xd, yd, dg, dh);
+                const S gprov = f[0];
                 f[0] = (S)((double)f[0] + dg);
-                f[1] = (S)((double)f[1] + (side ? khR : khL) * dg);
-                if (f[0] < S(0) && gp >= S(0)) nf = 1;
+                f[1] = (S)((double)f[1] + dh);
+                if (f[0] < S(0) && gprov >= S(0)) nf = 1;
                 e[side][0] = f[0] + ((S)sd.dx - x * s) * sx[0] + ((S)sd.dy - y * s) * sy[0];
                 e[side][1] = f[1] + ((S)sd.dx - x * s) * sx[1] + ((S)sd.dy - y * s) * sy[1];
             }
@@ -1530,7 +1572,9 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
         double Tf = 1.0;
         const Eq<S> eq = eq_cast<S>(face_target<S, 1>(LI, fm, u0, v0, ph, ph.compat && ph.face_compat, c1, c2, &Tf));
         // pass 3: interface microflux per unit area and its moments F_int
-        double Fm[4] = {0, 0, 0, 0};
+        double Fm[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Fm[k] = 0.0;
         const S k1 = (S)c1, k2 = (S)c2;
         for (int P = lane_id(); P < LI.N; P += WL) {
             const double xd = gp(LI.xi_x)[P], yd = gp(LI.xi_y)[P], w = gp(LI.w)[P];
@@ -1541,16 +1585,14 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
             const S fh = dn * (k1 * rh[P] + k2 * hs);
             rg[P] = fg;
             rh[P] = fh;
-            const double wg = w * (double)fg;
-            Fm[0] += wg; Fm[1] += wg * xd; Fm[2] += wg * yd;
-            Fm[3] += 0.5 * (wg * (xd * xd + yd * yd) + w * (double)fh);
+            acc_m9(Fm, w, xd, yd, (double)fg, (double)fh);
         }
-        wave_sum<4>(Fm);
+        wave_sum<9>(Fm);
         __threadfence_block();   // pass 4 reads interface rows written by other lanes
         // pass 4: coarsen to both native levels (provisional) and their moments
-        double pm[8];
+        double pm[18];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) pm[k] = 0.0;
+        for (int k = 0; k < 18; ++k) pm[k] = 0.0;
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const LevelDesc& Ln = side ? LB : LA;
@@ -1571,36 +1613,29 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
                 const S gs = (S)gA, hs = (S)(HA - (x * x + y * y) * gA);
                 og[a] = gs;
                 oh[a] = hs;
-                const double wg = w * (double)gs;
-                double* mm = pm + 4 * side;
-                mm[0] += wg; mm[1] += wg * x; mm[2] += wg * y; mm[3] += 0.5 * (wg * (x * x + y * y) + w * (double)hs);
+                acc_m9(pm + 9 * side, w, x, y, (double)gs, (double)hs);
             }
         }
-        wave_sum<8>(pm);
-        // pass 5: four-moment flux correction to F_int (T_tar = face T), times area
+        wave_sum<18>(pm);
+        // pass 5: flux correction to F_int (T_tar = face T for four moments), times area
         const S ar = (S)F.area;
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             const LevelDesc& Ln = side ? LB : LA;
             auto og = rowp<S>(Ln.Fg, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
             auto oh = rowp<S>(Ln.Fh, (size_t)(side ? F.rowB : F.rowA) * Ln.stride);
-            double aa[4] = {0, 0, 0, 0};
+            MapCoef mc{};
             if (ph.map_moments) {
-                const double* mm = pm + 4 * side;
-                const double dM[4] = {Fm[0] - mm[0], Fm[1] - mm[1], Fm[2] - mm[2], Fm[3] - mm[3]};
-                const double rhs[4] = {dM[0], dM[1], dM[2], dM[3] - 0.5 * cK * ph.R * Tf * dM[0]};
-                for (int r = 0; r < 4; ++r) {
-                    double acc = 0.0;
-                    for (int c = 0; c < 4; ++c) acc += Ln.Minv[r * 4 + c] * rhs[c];
-                    aa[r] = acc;
-                }
+                double dM[9];
+                for (int k = 0; k < 9; ++k) dM[k] = Fm[k] - pm[9 * side + k];
+                mc = map_coeffs(Ln, dM, Tf, ph);
             }
-            const double kh = cK * ph.R * Tf;
             for (int a = lane_id(); a < Ln.N; a += WL) {
                 const double x = gp(Ln.xi_x)[a], y = gp(Ln.xi_y)[a];
-                const double dg = aa[0] + aa[1] * x + aa[2] * y + aa[3] * (x * x + y * y);
+                double dg, dh;
+                map_delta(mc, x, y, dg, dh);
                 og[a] = ar * (S)((double)og[a] + dg);
-                oh[a] = ar * (S)((double)oh[a] + kh * dg);
+                oh[a] = ar * (S)((double)oh[a] + dh);
             }
         }
         nf = __any(nf);

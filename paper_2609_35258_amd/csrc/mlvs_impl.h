@@ -52,6 +52,9 @@ struct LevelDesc {
                             // rows (neighbours on other levels mapped onto this level)
     void* Fg;  void* Fh;    // face rows (flux)        [rows][stride]
     double Minv[16];        // inverse of the state-independent 4x4 mapping matrix
+    double G6inv[36];       // nine-moment mapping: inverse of the 6x6 g matrix,
+    double B36[18];         //   coupling of the g correction into the h moments,
+    double H3inv[9];        //   inverse of the 3x3 h matrix
 };
 
 struct Phys {

@@ -1,6 +1,6 @@
 """GPU parity of the multi-level path (FP64) against the oracle.
 
-Covers: the level switch (projection + four-moment mapping correction), the
+Covers: the level switch (projection + four- or nine-moment mapping correction), the
 step with neighbours on other levels and cross-level faces on V_int, the
 criterion masks, the grouping into levels, and conservation to round-off.
 """
@@ -33,14 +33,17 @@ def _catalog(nv, n_levels, seed):
     return np.stack(ks)
 
 
-@pytest.mark.parametrize("n_levels,axis,seed", [(2, 0, 1), (3, 1, 7), (4, 0, 12)])
-def test_fixed_catalog_remap_and_steps(n_levels, axis, seed):
+@pytest.mark.parametrize("n_levels,axis,seed,map_moments", [(2, 0, 1, 4), (3, 1, 7, 4), (4, 0, 12, 4),
+                                                             (3, 1, 7, 9), (4, 0, 12, 9)])
+def test_fixed_catalog_remap_and_steps(n_levels, axis, seed, map_moments):
+    # map_moments 9: nine-moment mapping of level switches, neighbours and
+    # cross-level states and fluxes (second g moments and energy flux kept too)
     p = _sine()
-    print("case fixed catalog", n_levels, axis, seed, flush=True)
+    print("case fixed catalog", n_levels, axis, seed, map_moments, flush=True)
     kap = _catalog(p.nv, n_levels, seed)
     cl = W.striped_levels(p.ni, p.nj, n_levels, axis)
-    o = Oracle(p, compat=4)
-    g = _gpu(p, compat=4)
+    o = Oracle(p, compat=4, map_moments=map_moments)
+    g = _gpu(p, compat=4, map_moments=map_moments)
     o.set_levels(list(kap), cl)
     g.set_levels(kap, cl)
     assert np.array_equal(g.cell_levels(), cl)
@@ -119,16 +122,16 @@ def test_criterion_masks_match(flux_test):
     g.close()
 
 
-@pytest.mark.parametrize("chunk", [None, "64"])
-def test_adaptive_run_matches_oracle(chunk, monkeypatch):
+@pytest.mark.parametrize("chunk,map_moments", [(None, 4), ("64", 4), (None, 9)])
+def test_adaptive_run_matches_oracle(chunk, map_moments, monkeypatch):
     # chunk "64": levels of different sizes split into different numbers of
     # velocity chunks in the reconstruction and update launches
     if chunk:
         monkeypatch.setenv("MLVS_CHUNK", chunk)
     p = _sine(nv=24, seed=9)
     ap = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=1e-3, tau_clust=0.02, flux_test=True, interval=2)
-    o = Oracle(p, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 1e-3, 0.02, True, 2))
-    g = _gpu(p, compat=4, adapt=ap)
+    o = Oracle(p, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 1e-3, 0.02, True, 2), map_moments=map_moments)
+    g = _gpu(p, compat=4, adapt=ap, map_moments=map_moments)
     t0 = g.totals()
     for k in range(5):
         o.step()
