@@ -69,8 +69,11 @@ typedef struct {
  *             twice the smallest centre-to-face distance.
  *  precision  64 (g~, h~ stored in double) or 32 (stored in float; moment
  *             sums, corrections and totals in double).
- *  compat     0 or 4: four-moment compatibility correction of the Shakhov
- *             target (Sec. 3.3.1, Eq. eq_four_moment_constraint).
+ *  compat     0, 4 or 8: compatibility correction of the Shakhov target
+ *             (Sec. 3.3.1): four moments (mass, momentum, energy; Eq.
+ *             eq_four_moment_constraint) or eight (also the heat flux (1-Pr) q
+ *             and a zero deviatoric stress; Eqs. eq_eight_basis,
+ *             eq_eight_moment_constraint).  8 needs dim = 2.
  *  face_compat 1: also correct the face target used in Eq. recover_phi.
  *  map_moments 0, 4 or 9: linear mapping correction for level switches,
  *             neighbour mapping and cross-level states and fluxes (Sec. 3.3.2):

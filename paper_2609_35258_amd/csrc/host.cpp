@@ -1590,7 +1590,8 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         if (!phys || !mesh || !vg || !out) fail(MLVS_E_ARG, "null argument");
         if (phys->dim != 1 && phys->dim != 2) fail(MLVS_E_ARG, "dim must be 1 or 2");
         if (phys->precision != 32 && phys->precision != 64) fail(MLVS_E_ARG, "precision must be 32 or 64");
-        if (phys->compat != 0 && phys->compat != 4) fail(MLVS_E_ARG, "compat must be 0 or 4");
+        if (phys->compat != 0 && phys->compat != 4 && phys->compat != 8) fail(MLVS_E_ARG, "compat must be 0, 4 or 8");
+        if (phys->compat == 8 && phys->dim != 2) fail(MLVS_E_ARG, "compat 8 needs dim = 2");
         if (phys->map_moments != 0 && phys->map_moments != 4 && phys->map_moments != 9)
             fail(MLVS_E_ARG, "map_moments must be 0, 4 or 9");
         if (phys->map_moments == 9 && phys->dim != 2) fail(MLVS_E_ARG, "map_moments 9 needs dim = 2");

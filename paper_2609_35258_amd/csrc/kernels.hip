@@ -157,16 +157,21 @@ __device__ __forceinline__ void raw_to_state(const double* m, double u0, double 
 // Reduced Shakhov target (Eq. g_h_eq_Pr) in evaluation form.  With
 // c = xi - u:  g = rn e^{-c^2/2RT} (1 + X.c (c^2/RT - D - 2)),
 // h = RT rn e^{-c^2/2RT} (cK + X.c ((c^2/RT - D) cK - 2K)), X = (1-Pr) q/(5 p RT),
-// cK = K + 3 - D; the compatibility factor 1 + a . [1, xi_x, xi_y, E_xi]
-// (Eq. gh_model_correction) is folded into b0 + b1 xi_x + b2 xi_y + b3 |xi|^2.
+// cK = K + 3 - D; the compatibility factor 1 + a . phi (Eq. gh_model_correction)
+// with the four-moment basis [1, xi_x, xi_y, E_xi] is folded into b0 + b1 xi_x +
+// b2 xi_y + b3 |xi|^2; the eight-moment basis (Eq. eq_eight_basis) adds
+// [E_c c_x, E_c c_y, c_x^2 - c_y^2, c_x c_y], E_c = (cK RT + c^2)/2, folded into
+// (e4 c_x + e5 c_y)(cK RT + c^2) + e6 (c_x^2 - c_y^2) + e7 c_x c_y.
 template <typename C>
 struct Eq {
     C rn, ux, uy, i2RT, iRT, RT, Xqx, Xqy;
     C b0, b1, b2, b3;
+    C e4, e5, e6, e7, cKRT;
     C cK, Dp2, Dd, K2;
-    bool corr;
+    bool corr, c8;
 };
 
+// a: the compatibility coefficients (4, or 8 when ph.compat is 8), or null.
 __device__ __forceinline__ Eq<double> make_eq(double rho, double u, double v, double T, double qx, double qy,
                                               const double* a, const Phys& ph) {
     Eq<double> e;
@@ -189,6 +194,12 @@ __device__ __forceinline__ Eq<double> make_eq(double rho, double u, double v, do
     e.b1 = a ? a[1] : 0.0;
     e.b2 = a ? a[2] : 0.0;
     e.b3 = a ? 0.5 * a[3] : 0.0;
+    e.c8 = a != nullptr && ph.compat == 8;
+    e.e4 = e.c8 ? 0.5 * a[4] : 0.0;
+    e.e5 = e.c8 ? 0.5 * a[5] : 0.0;
+    e.e6 = e.c8 ? a[6] : 0.0;
+    e.e7 = e.c8 ? a[7] : 0.0;
+    e.cKRT = (3.0 - D + ph.K) * RT;
     return e;
 }
 
@@ -199,8 +210,10 @@ __device__ __forceinline__ Eq<C> eq_cast(const Eq<double>& d) {
     e.rn = uni((C)d.rn); e.ux = uni((C)d.ux); e.uy = uni((C)d.uy); e.i2RT = uni((C)d.i2RT);
     e.iRT = uni((C)d.iRT); e.RT = uni((C)d.RT); e.Xqx = uni((C)d.Xqx); e.Xqy = uni((C)d.Xqy);
     e.b0 = uni((C)d.b0); e.b1 = uni((C)d.b1); e.b2 = uni((C)d.b2); e.b3 = uni((C)d.b3);
+    e.e4 = uni((C)d.e4); e.e5 = uni((C)d.e5); e.e6 = uni((C)d.e6); e.e7 = uni((C)d.e7); e.cKRT = uni((C)d.cKRT);
     e.cK = (C)d.cK; e.Dp2 = (C)d.Dp2; e.Dd = (C)d.Dd; e.K2 = (C)d.K2;
     e.corr = d.corr;
+    e.c8 = d.c8;
     return e;
 }
 
@@ -217,7 +230,8 @@ __device__ __forceinline__ void eq_eval(const Eq<C>& e, C x, C y, C& g, C& h) {
     g = ge * (C(1) + Xc * (c2r - e.Dp2));
     h = ge * e.RT * (e.cK + Xc * ((c2r - e.Dd) * e.cK - e.K2));
     if (e.corr) {
-        const C f = e.b0 + e.b1 * x + e.b2 * y + e.b3 * (x * x + y * y);
+        C f = e.b0 + e.b1 * x + e.b2 * y + e.b3 * (x * x + y * y);
+        if (e.c8) f += (e.e4 * cx + e.e5 * cy) * (e.cKRT + c2) + e.e6 * (cx * cx - cy * cy) + e.e7 * cx * cy;
         g *= f;
         h *= f;
     }
@@ -298,6 +312,79 @@ __device__ __forceinline__ void compat_solve(const LevelDesc& L, const Eq<S>& eu
     for (int k = 0; k < 4; ++k) a_out[k] = uni(a_out[k]);
 }
 
+// Eight-moment compatibility correction (Sec. 3.3.1, Eqs. eq_eight_basis,
+// E_c_definition, eq_eight_moment_constraint; D = 2): basis phi = [1, xi_x,
+// xi_y, E_xi, E_c c_x, E_c c_y, c_x^2 - c_y^2, c_x c_y], constraint rows
+// psi_g = [1, xi_x, xi_y, |xi|^2/2, c^2 c_x/2, c^2 c_y/2, c_x^2 - c_y^2, c_x c_y]
+// on g and psi_h = [0, 0, 0, 1/2, c_x/2, c_y/2, 0, 0] on h: mass, momentum,
+// energy, the heat flux and a zero deviatoric stress.  Part 1 (wave per item):
+// A[k][m] = sum w (psi_g,k g_S + psi_h,k h_S) phi_m, row-major; column 0 holds
+// the target's own moments (phi_0 = 1).
+template <typename S, int U>
+__device__ __forceinline__ void compat_sums8(const LevelDesc& L, const Eq<S>& eu, double u, double v, double T,
+                                             const Phys& ph, double (&A)[64]) {
+#pragma unroll
+    for (int k = 0; k < 64; ++k) A[k] = 0.0;
+    const double cKRT = (3.0 - ph.D + ph.K) * ph.R * T;
+    const int N = L.N;
+    for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
+        double xv[U], yv[U], wv[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int i = i0 + q * WL, ic = clampi(i, N);
+            xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
+            wv[q] = i < N ? gp(L.w)[ic] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const double x = xv[q], y = yv[q];
+            S g, h;
+            eq_eval<S>(eu, (S)x, (S)y, g, h);
+            const double wg = wv[q] * (double)g, wh = wv[q] * (double)h;
+            const double cx = x - u, cy = y - v, c2 = cx * cx + cy * cy, x2 = x * x + y * y;
+            const double Ec = 0.5 * (cKRT + c2);
+            const double phi[8] = {1.0, x, y, 0.5 * (cKRT + x2), Ec * cx, Ec * cy, cx * cx - cy * cy, cx * cy};
+            const double kern[8] = {wg, wg * x, wg * y, 0.5 * (wg * x2 + wh), 0.5 * (wg * c2 + wh) * cx,
+                                    0.5 * (wg * c2 + wh) * cy, wg * (cx * cx - cy * cy), wg * cx * cy};
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+#pragma unroll
+                for (int mm = 0; mm < 8; ++mm) A[k * 8 + mm] += kern[k] * phi[mm];
+        }
+    }
+    wave_sum<64>(A);
+}
+
+// Part 2 (one lane): solve A a = target - A[:, 0] with target [rho, rho u, rho v,
+// rho E, q_tar, 0, 0] (q_tar the Shakhov target's own heat flux (1 - Pr) q).
+__device__ __forceinline__ void compat_from_sums8(const double* As, double rho, double u, double v, double T,
+                                                  double qtx, double qty, const Phys& ph, double* a_out) {
+    double A[8][8], b[8];
+    for (int k = 0; k < 8; ++k)
+        for (int mm = 0; mm < 8; ++mm) A[k][mm] = As[k * 8 + mm];
+    const double rhoE = 0.5 * rho * (u * u + v * v) + 0.5 * (3.0 + ph.K) * rho * ph.R * T;
+    const double tgt[8] = {rho, rho * u, rho * v, rhoE, qtx, qty, 0.0, 0.0};
+    for (int k = 0; k < 8; ++k) b[k] = tgt[k] - As[k * 8];
+    solve_fixed<8>(A, b);
+    for (int k = 0; k < 8; ++k) a_out[k] = b[k];
+}
+
+// The correction in one wave for the compatibility order of ph (4 or 8
+// moments; every lane solves the same system).  qx, qy: the target's q.
+template <typename S, int U>
+__device__ __forceinline__ void compat_solve_any(const LevelDesc& L, const Eq<S>& eu, double rho, double u, double v,
+                                                 double T, double qx, double qy, const Phys& ph, double* a_out) {
+    if (ph.compat == 8) {
+        double A[64];
+        compat_sums8<S, U>(L, eu, u, v, T, ph, A);
+        compat_from_sums8(A, rho, u, v, T, (1.0 - ph.Pr) * qx, (1.0 - ph.Pr) * qy, ph, a_out);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a_out[k] = uni(a_out[k]);
+    } else {
+        compat_solve<S, U>(L, eu, rho, u, v, T, ph, a_out);
+    }
+}
+
 // Eleven raw moments of (g, h) at velocity (x, y) taken about a shift (the
 // layout raw_to_state reads), accumulated in double.
 template <typename S>
@@ -361,15 +448,16 @@ __device__ __forceinline__ CellState cell_state(const double* cm, const Phys& ph
 // the rows phi_bar+ = alpha phi~ + beta phi_S* (Eq. g_h_eq_Pr with the
 // correction of Sec. 3.3.1).  The raw moments of g~, h~ come from cmom (the
 // previous update, or k_raw_moments after the state was set from outside).
-template <typename S, int U, int MINW>
+template <typename S, int U, int MINW, int CM>
 __global__ __launch_bounds__(GBS, MINW) void k_cell_prep(const LevelDesc* __restrict__ lvs,
                                                          const int* __restrict__ cell_lev,
                                                          const int* __restrict__ cell_slot, int n_cells, Phys ph,
                                                          double* __restrict__ params,
                                                          const double* __restrict__ cmom, int CH) {
+    constexpr int NS = CM == 8 ? 64 : 13;      // compatibility sums per item
     __shared__ CellState sh_c[GW];
     __shared__ Eq<double> sh_e[GW];
-    __shared__ double sh_s[GW][13];
+    __shared__ double sh_s[GW][NS];
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave index (uniform)
     const int t = threadIdx.x;
     for (int g0 = wg_index() * GW; g0 < n_cells; g0 += gridDim.x * GW) {
@@ -387,11 +475,16 @@ __global__ __launch_bounds__(GBS, MINW) void k_cell_prep(const LevelDesc* __rest
         // velocity pass: the compatibility sums, one wave per cell
         if (ph.compat && c < n_cells) {
             const LevelDesc& L = lvs[cell_lev[c]];
-            double sm[13];
-            compat_sums<S, U>(L, eq_cast<S>(sh_e[w]), sm);
-            if (lane_id() < 13) {
+            double sm[NS];
+            if constexpr (CM == 8) {
+                const CellState& cs = sh_c[w];
+                compat_sums8<S, U>(L, eq_cast<S>(sh_e[w]), cs.u, cs.v, cs.T, ph, sm);
+            } else {
+                compat_sums<S, U>(L, eq_cast<S>(sh_e[w]), sm);
+            }
+            if (lane_id() < NS) {
 #pragma unroll
-                for (int k = 0; k < 13; ++k)
+                for (int k = 0; k < NS; ++k)
                     if (lane_id() == k) sh_s[w][k] = sm[k];
             }
         }
@@ -399,9 +492,13 @@ __global__ __launch_bounds__(GBS, MINW) void k_cell_prep(const LevelDesc* __rest
         // scalar: solve, corrected target, parameters
         if (t < GW && g0 + t < n_cells) {
             const CellState cs = sh_c[t];
-            double a[4] = {0.0, 0.0, 0.0, 0.0};
+            double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             if (ph.compat) {
-                compat_from_sums(sh_s[t], cs.rho, cs.u, cs.v, cs.T, ph, a);
+                if constexpr (CM == 8)
+                    compat_from_sums8(sh_s[t], cs.rho, cs.u, cs.v, cs.T, (1.0 - ph.Pr) * cs.qx,
+                                      (1.0 - ph.Pr) * cs.qy, ph, a);
+                else
+                    compat_from_sums(sh_s[t], cs.rho, cs.u, cs.v, cs.T, ph, a);
                 sh_e[t] = make_eq(cs.rho, cs.u, cs.v, cs.T, cs.qx, cs.qy, a, ph);
             }
             double* pr = params + (size_t)(g0 + t) * NPARAM;
@@ -501,10 +598,10 @@ __global__ __launch_bounds__(BS) void k_init_eq(const LevelDesc* __restrict__ lv
     for (int c = item0(); c < n_cells; c += istride()) {
         const LevelDesc& L = lvs[cell_lev[c]];
         const double rho = st[4 * c], u = st[4 * c + 1], v = ph.D == 2 ? st[4 * c + 2] : 0.0, T = st[4 * c + 3];
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (ph.compat) {
             const Eq<S> eu = eq_cast<S>(make_eq(rho, u, v, T, 0.0, 0.0, nullptr, ph));
-            compat_solve<S, 4>(L, eu, rho, u, v, T, ph, a);
+            compat_solve_any<S, 4>(L, eu, rho, u, v, T, 0.0, 0.0, ph, a);
         }
         const Eq<S> e = eq_cast<S>(make_eq(rho, u, v, T, 0.0, 0.0, ph.compat ? a : nullptr, ph));
         const size_t row = (size_t)cell_slot[c] * L.stride;
@@ -762,10 +859,10 @@ __device__ __forceinline__ Eq<double> face_target(const LevelDesc& L, double* m,
     const double tau = viscosity(T, ph) / (rho * ph.R * T);
     qx = 2.0 * tau * qx / (2.0 * tau + s * ph.Pr);
     qy = 2.0 * tau * qy / (2.0 * tau + s * ph.Pr);
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (compat) {
         const Eq<S> eu = eq_cast<S>(make_eq(rho, u, v, T, qx, qy, nullptr, ph));
-        compat_solve<S, U>(L, eu, rho, u, v, T, ph, a);
+        compat_solve_any<S, U>(L, eu, rho, u, v, T, qx, qy, ph, a);
     }
     c1 = 2.0 * tau / (2.0 * tau + s);
     c2 = s / (2.0 * tau + s);
@@ -975,13 +1072,14 @@ __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restri
 //     state -- diffuse wall rho_w g_eq(u_w, T_w) with rho_w from zero net mass
 //     flux, far-field Maxwellian, or the cell's phi_bar+ (zero-gradient
 //     outflow).
-template <typename S, int U, int MINW>
+template <typename S, int U, int MINW, int CM>
 __global__ __launch_bounds__(GBS, MINW) void k_face_target(const LevelDesc* __restrict__ lvs,
                                                            const FaceItem* __restrict__ items, int n,
                                                            const BCDev* __restrict__ bcs, Phys ph,
                                                            const double* __restrict__ fmom,
                                                            double* __restrict__ fpar, int CH) {
-    __shared__ double sh_m[GW][13];
+    constexpr int NS = CM == 8 ? 64 : 13;      // compatibility sums per face
+    __shared__ double sh_m[GW][NS];
     __shared__ FaceState sh_f[GW];
     __shared__ Eq<double> sh_e[GW];
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave index (uniform)
@@ -1015,11 +1113,16 @@ __global__ __launch_bounds__(GBS, MINW) void k_face_target(const LevelDesc* __re
             const LevelDesc& L = lvs[F.lev];
             if (F.R >= 0) {
                 if (ph.compat && ph.face_compat) {
-                    double sm[13];
-                    compat_sums<S, U>(L, eq_cast<S>(sh_e[w]), sm);
-                    if (lane_id() < 13) {
+                    double sm[NS];
+                    if constexpr (CM == 8) {
+                        const FaceState& fs = sh_f[w];
+                        compat_sums8<S, U>(L, eq_cast<S>(sh_e[w]), fs.u, fs.v, fs.T, ph, sm);
+                    } else {
+                        compat_sums<S, U>(L, eq_cast<S>(sh_e[w]), sm);
+                    }
+                    if (lane_id() < NS) {
 #pragma unroll
-                        for (int k = 0; k < 13; ++k)
+                        for (int k = 0; k < NS; ++k)
                             if (lane_id() == k) sh_m[w][k] = sm[k];
                     }
                 }
@@ -1058,8 +1161,12 @@ __global__ __launch_bounds__(GBS, MINW) void k_face_target(const LevelDesc* __re
             double kind = 0.0, c1 = fs.c1, c2 = fs.c2;
             if (F.R >= 0) {
                 if (ph.compat && ph.face_compat) {
-                    double a[4];
-                    compat_from_sums(sh_m[t], fs.rho, fs.u, fs.v, fs.T, ph, a);
+                    double a[8];
+                    if constexpr (CM == 8)
+                        compat_from_sums8(sh_m[t], fs.rho, fs.u, fs.v, fs.T, (1.0 - ph.Pr) * fs.qx,
+                                          (1.0 - ph.Pr) * fs.qy, ph, a);
+                    else
+                        compat_from_sums(sh_m[t], fs.rho, fs.u, fs.v, fs.T, ph, a);
                     e = make_eq(fs.rho, fs.u, fs.v, fs.T, fs.qx, fs.qy, a, ph);
                 }
                 c1 *= F.area;
@@ -1076,6 +1183,8 @@ __global__ __launch_bounds__(GBS, MINW) void k_face_target(const LevelDesc* __re
             o[FP_IRT] = e.iRT; o[FP_XQX] = e.Xqx; o[FP_XQY] = e.Xqy;
             o[FP_B0] = e.b0; o[FP_B1] = e.b1; o[FP_B2] = e.b2; o[FP_B3] = e.b3;
             o[FP_CORR] = e.corr ? 1.0 : 0.0;
+            o[FP_E4] = e.e4; o[FP_E5] = e.e5; o[FP_E6] = e.e6; o[FP_E7] = e.e7; o[FP_CKRT] = e.cKRT;
+            o[FP_C8] = e.c8 ? 1.0 : 0.0;
         }
         __syncthreads();
     }
@@ -1089,6 +1198,8 @@ __device__ __forceinline__ Eq<S> load_face_eq(const double* fp, const Phys& ph) 
     d.b0 = fp[FP_B0]; d.b1 = fp[FP_B1]; d.b2 = fp[FP_B2]; d.b3 = fp[FP_B3];
     d.cK = ph.K + 3.0 - ph.D; d.Dp2 = ph.D + 2.0; d.Dd = ph.D; d.K2 = 2.0 * ph.K;
     d.corr = fp[FP_CORR] != 0.0;
+    d.e4 = fp[FP_E4]; d.e5 = fp[FP_E5]; d.e6 = fp[FP_E6]; d.e7 = fp[FP_E7]; d.cKRT = fp[FP_CKRT];
+    d.c8 = fp[FP_C8] != 0.0;
     return eq_cast<S>(d);
 }
 
@@ -1371,6 +1482,27 @@ constexpr int N_VARIANTS = 4;
         }                                                                                       \
     } while (0)
 
+#define MLVS_LAUNCH_UWC(prec, KERNEL, U_, W_, C_, ...)                                           \
+    do {                                                                                        \
+        if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, U_, W_, C_>), __VA_ARGS__);          \
+        else hipLaunchKernelGGL((KERNEL<double, U_, W_, C_>), __VA_ARGS__);                      \
+    } while (0)
+#define MLVS_DISPATCH_VC1(prec, var, C_, KERNEL, ...)                                            \
+    do {                                                                                        \
+        switch (var) {                                                                          \
+        case 0: MLVS_LAUNCH_UWC(prec, KERNEL, 1, 4, C_, __VA_ARGS__); break;                     \
+        case 2: MLVS_LAUNCH_UWC(prec, KERNEL, 4, 2, C_, __VA_ARGS__); break;                     \
+        case 3: MLVS_LAUNCH_UWC(prec, KERNEL, 4, 4, C_, __VA_ARGS__); break;                     \
+        default: MLVS_LAUNCH_UWC(prec, KERNEL, 2, 4, C_, __VA_ARGS__); break;                    \
+        }                                                                                       \
+    } while (0)
+// ... and for the kernels instantiated per compatibility order (4 or 8 moments)
+#define MLVS_DISPATCH_VC(prec, var, cm, KERNEL, ...)                                             \
+    do {                                                                                        \
+        if ((cm) == 8) MLVS_DISPATCH_VC1(prec, var, 8, KERNEL, __VA_ARGS__);                     \
+        else MLVS_DISPATCH_VC1(prec, var, 4, KERNEL, __VA_ARGS__);                               \
+    } while (0)
+
 int variant_count() { return N_VARIANTS; }
 
 #define MLVS_DISPATCH(prec, KERNEL, ...)                                                        \
@@ -1382,8 +1514,8 @@ int variant_count() { return N_VARIANTS; }
 hipError_t launch_cell_prep(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
                             int n_cells, Phys ph, double* params, const double* cmom, int CH, int var) {
     if (n_cells <= 0) return hipSuccess;
-    MLVS_DISPATCH_V(prec, var, k_cell_prep, dim3(grid_for(n_cells, GW)), dim3(GBS), 0, st, lv, cell_lev, cell_slot,
-                    n_cells, ph, params, cmom, CH);
+    MLVS_DISPATCH_VC(prec, var, ph.compat, k_cell_prep, dim3(grid_for(n_cells, GW)), dim3(GBS), 0, st, lv, cell_lev,
+                     cell_slot, n_cells, ph, params, cmom, CH);
     return hipGetLastError();
 }
 
@@ -1425,8 +1557,8 @@ hipError_t launch_face_rec(int prec, hipStream_t st, const LevelDesc* lv, const 
 hipError_t launch_face_target(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
                               const BCDev* bcs, Phys ph, const double* fmom, double* fpar, int CH, int var) {
     if (n <= 0) return hipSuccess;
-    MLVS_DISPATCH_V(prec, var, k_face_target, dim3(grid_for(n, GW)), dim3(GBS), 0, st, lv, items, n, bcs, ph, fmom,
-                    fpar, CH);
+    MLVS_DISPATCH_VC(prec, var, ph.compat, k_face_target, dim3(grid_for(n, GW)), dim3(GBS), 0, st, lv, items, n, bcs,
+                     ph, fmom, fpar, CH);
     return hipGetLastError();
 }
 

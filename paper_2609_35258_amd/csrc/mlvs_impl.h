@@ -29,13 +29,15 @@ enum { NFMOM = NMOM };
 
 // Per-face record written by the face-target stage and read by the update
 // (double).  KIND: 0 interior, else the boundary kind; C1, C2: the weights of
-// phi_bar_f and of the target (area included); RN..B3: the target in the
-// evaluation form of the kernels; CORR: 1 if the compatibility factor applies.
+// phi_bar_f and of the target (area included); RN..B3, E4..CKRT: the target in
+// the evaluation form of the kernels; CORR: 1 if the compatibility factor
+// applies; C8: 1 if it has the eight-moment terms.
 enum {
     FP_KIND = 0, FP_ROW, FP_NX, FP_NY, FP_C1, FP_C2,
     FP_RN, FP_UX, FP_UY, FP_I2RT, FP_RT, FP_IRT, FP_XQX, FP_XQY,
     FP_B0, FP_B1, FP_B2, FP_B3, FP_CORR,
-    NFP = 20
+    FP_E4, FP_E5, FP_E6, FP_E7, FP_CKRT, FP_C8,   // eight-moment terms (see Eq in kernels.hip)
+    NFP = 26
 };
 
 // One velocity space (a representative level or an interface level).

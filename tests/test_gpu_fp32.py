@@ -58,6 +58,17 @@ def test_fp32_cylinder_fields_and_heat_flux():
     g.close()
 
 
+def test_fp32_cylinder_eight_moment_compat():
+    p = W.cylinder(24, 10, Kn=0.1, nv=41, vmax=10.0)
+    o = Oracle(p, compat=8)
+    g = _gpu(p, precision=32, compat=8)
+    for _ in range(6):
+        o.step()
+    g.step(6)
+    _check_fields(o, g)
+    g.close()
+
+
 def test_fp32_multilevel_conservation():
     p = W.perturb(W.periodic_box(12, 6, Lx=1.0, Ly=0.5, Kn=0.05, nv=24, vmax=5.0, kind="sine", amp=0.5), seed=3)
     ap = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=1e-3, tau_clust=0.02, flux_test=True, interval=5)

@@ -33,17 +33,19 @@ def _catalog(nv, n_levels, seed):
     return np.stack(ks)
 
 
-@pytest.mark.parametrize("n_levels,axis,seed,map_moments", [(2, 0, 1, 4), (3, 1, 7, 4), (4, 0, 12, 4),
-                                                             (3, 1, 7, 9), (4, 0, 12, 9)])
-def test_fixed_catalog_remap_and_steps(n_levels, axis, seed, map_moments):
+@pytest.mark.parametrize("n_levels,axis,seed,map_moments,compat", [(2, 0, 1, 4, 4), (3, 1, 7, 4, 4), (4, 0, 12, 4, 4),
+                                                                    (3, 1, 7, 9, 4), (4, 0, 12, 9, 4),
+                                                                    (3, 0, 5, 4, 8), (3, 1, 7, 9, 8)])
+def test_fixed_catalog_remap_and_steps(n_levels, axis, seed, map_moments, compat):
     # map_moments 9: nine-moment mapping of level switches, neighbours and
-    # cross-level states and fluxes (second g moments and energy flux kept too)
+    # cross-level states and fluxes (second g moments and energy flux kept too);
+    # compat 8: eight-moment correction of cell, face and cross-level targets
     p = _sine()
-    print("case fixed catalog", n_levels, axis, seed, map_moments, flush=True)
+    print("case fixed catalog", n_levels, axis, seed, map_moments, compat, flush=True)
     kap = _catalog(p.nv, n_levels, seed)
     cl = W.striped_levels(p.ni, p.nj, n_levels, axis)
-    o = Oracle(p, compat=4, map_moments=map_moments)
-    g = _gpu(p, compat=4, map_moments=map_moments)
+    o = Oracle(p, compat=compat, map_moments=map_moments)
+    g = _gpu(p, compat=compat, map_moments=map_moments)
     o.set_levels(list(kap), cl)
     g.set_levels(kap, cl)
     assert np.array_equal(g.cell_levels(), cl)

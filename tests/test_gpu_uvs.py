@@ -84,6 +84,19 @@ def test_periodic_sine_no_face_compat():
     _run_parity(p, 5, face_compat=False)
 
 
+@pytest.mark.parametrize("case", ["cavity", "cylinder", "periodic"])
+def test_eight_moment_compat(case):
+    # eight-moment compatibility correction of the cell and face targets:
+    # heat flux (1 - Pr) q and zero deviatoric stress imposed as well
+    if case == "cavity":
+        p = W.cavity(12, Kn=0.075, nv=12)
+    elif case == "cylinder":
+        p = W.cylinder(24, 10, Kn=0.1, nv=21, vmax=10.0)
+    else:
+        p = W.perturb(W.periodic_box(10, 6, Lx=1.0, Ly=0.6, Kn=0.02, nv=15, vmax=4.0, kind="sine"), seed=11)
+    _run_parity(p, 4, compat=8)
+
+
 def test_periodic_totals_round_off_gpu():
     p = W.perturb(W.periodic_box(16, 8, Lx=1.0, Ly=0.5, Kn=0.02, nv=17, vmax=4.0, kind="sine"), seed=5)
     g = _gpu(p)

@@ -61,3 +61,18 @@ def test_errors_are_reported_not_raised():
     st = L.mlvs_vgrid_newton_cotes(1, 1.0, None, None)
     assert st == -1
     assert b"Newton" in L.mlvs_last_error() or len(L.mlvs_last_error()) > 0
+
+
+@pytest.mark.parametrize("dim,compat,map_moments,msg", [(1, 8, 4, b"compat 8 needs dim = 2"),
+                                                          (2, 6, 4, b"compat must be 0, 4 or 8"),
+                                                          (1, 4, 9, b"map_moments 9 needs dim = 2")])
+def test_create_rejects_bad_orders(dim, compat, map_moments, msg):
+    # argument checks run before anything touches a device
+    L = m.lib()
+    phys = m.mlvs_physics(dim, 1, 0.5, 2.0 / 3.0, 0.81, 1.0, 1.0, 0.0, 0.5, 64, compat, 1, map_moments)
+    mesh, vg = m.mlvs_mesh(), m.mlvs_vgrid()
+    h = ctypes.c_void_p()
+    st = L.mlvs_create(ctypes.byref(phys), ctypes.byref(mesh), ctypes.byref(vg), None, None, ctypes.byref(h))
+    assert st != 0
+    assert msg in L.mlvs_last_error()
+    assert not h.value
