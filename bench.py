@@ -55,9 +55,9 @@ def run_gpu(p, steps, warmup, precision, adapt, graph=True, tune=True):
 
 
 def stage_profile(s, reps=20):
-    """Mean ms per launch of each stage (HIP events on the context stream)."""
+    """Mean ms per launch of each stage the step launches (HIP events on the context stream)."""
     out = {}
-    for st in ("cell", "ghost", "face_rec", "face_target", "xface", "update"):
+    for st in s.step_stages():
         items, pts = s.stage_size(st)
         if items == 0:
             continue
@@ -73,7 +73,11 @@ def stage_profile(s, reps=20):
 #                by two cells: 4 faces x 2 / 2) + write g~,h~             -> 10 values
 #   xface:       per V_int point, read both sides' phi_bar+ (2x2) + write one native row (2) -> 6 values
 #   ghost:       read source phi_bar+ + write mapped row                 -> 4 values
-ALG_VALUES = {"cell": 4, "face_rec": 4, "face_target": 0, "update": 10, "xface": 6, "ghost": 4}
+#   face (fused face_rec + face_target)                                  -> 4 values
+#   update_cell (fused update + next cell stage): the update's 10 + write the
+#                new phi_bar+ g,h (the new state is the update's own output) -> 12 values
+ALG_VALUES = {"cell": 4, "face_rec": 4, "face_target": 0, "update": 10, "xface": 6, "ghost": 4, "face": 4,
+              "update_cell": 12}
 
 
 def cpu_baseline(p, sample_steps=2, sample_cells=256):
@@ -187,7 +191,10 @@ CYL_INTERVAL = 100
 
 # launch variant index -> (velocity points per lane per load batch, minimum waves per SIMD)
 VARIANTS = {0: (1, 4), 1: (2, 4), 2: (4, 2), 3: (4, 4)}
-STAGE_KERNEL = {"cell": "k_cell_prep", "face_rec": "k_face_rec", "face_target": "k_face_target",
+# kernels instantiated per compatibility order carry it as a last template argument
+STAGE_CM = ("cell", "face_target", "face", "update_cell")
+STAGE_KERNEL = {"face": "k_face_full", "update_cell": "k_update_cell",
+                "cell": "k_cell_prep", "face_rec": "k_face_rec", "face_target": "k_face_target",
                 "update": "k_update", "xface": "k_xface"}
 
 
@@ -201,7 +208,8 @@ def measured_traffic(workload, stage, precision, variant):
         return None
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     u, w = VARIANTS[variant]
-    name = "mlvs::%s<%s,%d,%d>" % (STAGE_KERNEL[stage], "double" if precision == 64 else "float", u, w)
+    name = "mlvs::%s<%s,%d,%d%s>" % (STAGE_KERNEL[stage], "double" if precision == 64 else "float", u, w,
+                                     ",4" if stage in STAGE_CM else "")
     for line in open(path):
         f = line.split()
         if len(f) == 4 and not line.startswith("#") and f[0] == h and f[1] == workload and f[2] == name:

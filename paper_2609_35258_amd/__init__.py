@@ -117,6 +117,7 @@ _PROTOS = {
     "mlvs_time_stage": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_double_p]),
     "mlvs_stage_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                                        _c_double_p]),
+    "mlvs_step_stages": (ctypes.c_int, [ctypes.c_void_p, _c_int32_p, ctypes.POINTER(ctypes.c_int)]),
     "mlvs_neg_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "mlvs_mlp_nparams": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
     "mlvs_features": (ctypes.c_int, [ctypes.c_void_p, _c_float_p]),
@@ -430,7 +431,16 @@ class Solver:
         _check(lib().mlvs_counters(self.h, ctypes.byref(st), ctypes.byref(up), ctypes.byref(ip), ctypes.byref(ad)))
         return {"steps": st.value, "cell_updates": up.value, "iface_points": ip.value, "adaptations": ad.value}
 
-    STAGES = {"cell": 0, "ghost": 1, "face_rec": 2, "face_target": 3, "xface": 4, "update": 5, "criterion": 6}
+    STAGES = {"cell": 0, "ghost": 1, "face_rec": 2, "face_target": 3, "xface": 4, "update": 5, "criterion": 6,
+              "face": 7, "update_cell": 8}
+    STAGE_NAMES = {v: k for k, v in STAGES.items()}
+
+    def step_stages(self):
+        """Names of the stages one step launches, in order."""
+        n = ctypes.c_int()
+        buf = (ctypes.c_int32 * 8)()
+        _check(lib().mlvs_step_stages(self.h, buf, ctypes.byref(n)))
+        return [self.STAGE_NAMES[buf[k]] for k in range(n.value)]
 
     def time_stage(self, stage, reps: int = 10):
         """Mean ms per launch of one stage, timed with HIP events on the context stream."""

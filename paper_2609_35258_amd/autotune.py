@@ -16,7 +16,7 @@ import json
 import os
 from typing import Dict, Iterable, Optional
 
-TUNABLE = ("cell", "face_rec", "face_target", "xface", "update")
+TUNABLE = ("cell", "face_rec", "face_target", "xface", "update", "face", "update_cell")
 
 
 def default_cache() -> str:
@@ -40,9 +40,12 @@ def shape_key(solver, stage: str, precision: int) -> Optional[str]:
     return "%s|fp%d|%s|items~%d|pts<=%d" % (_arch(), precision, stage, 1 << max(items - 1, 1).bit_length(), bucket)
 
 
-def autotune(solver, precision: int, stages: Iterable[str] = TUNABLE, reps: int = 5,
+def autotune(solver, precision: int, stages: Optional[Iterable[str]] = None, reps: int = 5,
              cache: Optional[str] = None, force: bool = False) -> Dict[str, dict]:
-    """Choose the fastest variant per stage; returns {stage: {variant, ms, key, from_cache}}."""
+    """Choose the fastest variant per stage; returns {stage: {variant, ms, key, from_cache}}.
+    stages: default, the tunable stages the solver's step launches."""
+    if stages is None:
+        stages = [st for st in solver.step_stages() if st in TUNABLE]
     path = cache or default_cache()
     table = {}
     if os.path.exists(path):

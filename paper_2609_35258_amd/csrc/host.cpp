@@ -461,7 +461,29 @@ struct MeshH {
     std::vector<int> nbr;              // [c][4]
     std::vector<CellGeom> geom;
     double hmin = 1e300;
+    // Traversal order of the streaming stages: cells tile by tile (tw x th
+    // cells, row-major inside a tile and over tiles), so that the cells a
+    // stretch of consecutive work items touches, stencils included, stay in one
+    // XCD's L2.  order[k] is the k-th cell, rank its inverse.
+    std::vector<int> order, rank;
 };
+
+// Tiled traversal order of an ni x nj structured mesh (tw = 0: row-major).
+void tile_order(MeshH& M, int tw, int th) {
+    const int ni = M.ni, nj = M.nj;
+    M.order.clear();
+    M.order.reserve(M.n_cells);
+    if (tw <= 0 || th <= 0) {
+        for (int c = 0; c < M.n_cells; ++c) M.order.push_back(c);
+    } else {
+        for (int tj = 0; tj < nj; tj += th)
+            for (int ti = 0; ti < ni; ti += tw)
+                for (int j = tj; j < std::min(nj, tj + th); ++j)
+                    for (int i = ti; i < std::min(ni, ti + tw); ++i) M.order.push_back(i + ni * j);
+    }
+    M.rank.assign(M.n_cells, 0);
+    for (int k = 0; k < M.n_cells; ++k) M.rank[M.order[k]] = k;
+}
 
 void build_mesh(MeshH& M, const mlvs_mesh& in, int dim) {
     const int ni = in.ni, nj = in.nj;
@@ -622,6 +644,7 @@ struct mlvs_ctx_s {
     int64_t n_cross = 0;
     // device copies
     int *d_cell_lev = nullptr, *d_cell_slot = nullptr, *d_cell_nbr = nullptr, *d_cell_frow = nullptr;
+    int* d_order = nullptr;            // the mesh's traversal order (MeshH::order)
     CellGeom* d_geom = nullptr;
     double* d_params = nullptr;
     double* d_cmom = nullptr;          // [chunks][n_cells][NMOM] raw moments of the stored state
@@ -657,7 +680,12 @@ struct mlvs_ctx_s {
     int64_t last_fallback = 0;
     // step graph: the launches of one step captured once per level set
     bool use_graph = false;
-    int variant[8] = {1, 1, 1, 1, 1, 1, 1, 1};   // per stage launch variant (autotuned)
+    int variant[9] = {1, 1, 1, 1, 1, 1, 1, 1, 1};   // per stage launch variant (autotuned)
+    // Fused step (every level fits one velocity chunk): reconstruction and
+    // target in one launch, and the update carries the next step's cell stage.
+    bool fuse_allowed = true;          // MLVS_FUSE=0 turns the fused step off
+    bool fused = false;
+    bool prep_valid = false;           // phi_bar+ rows and parameters match the stored state
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     // counters
@@ -793,9 +821,13 @@ void build_items(mlvs_ctx c) {
             }
             cell_nbr[4 * cc + k] = -2 - row;
         }
-    // interior faces
+    // interior faces, in the traversal order of their left cells
+    std::vector<int> forder(M.faces.size());
+    for (size_t f = 0; f < M.faces.size(); ++f) forder[f] = (int)f;
+    std::stable_sort(forder.begin(), forder.end(),
+                     [&](int a, int b) { return M.rank[M.faces[a].L] < M.rank[M.faces[b].L]; });
     int n_cross = 0;
-    for (size_t f = 0; f < M.faces.size(); ++f) {
+    for (int f : forder) {
         const FaceH& F = M.faces[f];
         const int lL = c->cell_level[F.L], lR = c->cell_level[F.R];
         int kL = -1, kR = -1;
@@ -841,7 +873,11 @@ void build_items(mlvs_ctx c) {
     for (int cc = 0; cc < n; ++cc) c->step_points += c->levels[c->cell_level[cc]]->N;
     c->step_iface_points = 0.0;
     for (auto& it : xitems) c->step_iface_points += level_by_index(c, it.levI).N;
-    for (size_t b = 0; b < M.bfaces.size(); ++b) {
+    std::vector<int> border(M.bfaces.size());
+    for (size_t b = 0; b < M.bfaces.size(); ++b) border[b] = (int)b;
+    std::stable_sort(border.begin(), border.end(),
+                     [&](int a, int b) { return M.rank[M.bfaces[a].L] < M.rank[M.bfaces[b].L]; });
+    for (int b : border) {
         const FaceH& F = M.bfaces[b];
         const int lc = c->cell_level[F.L];
         FaceItem it{};
@@ -893,6 +929,7 @@ void build_items(mlvs_ctx c) {
     const size_t o_nbr = stg.put(cell_nbr);
     const size_t o_lev = stg.put(c->cell_level);
     const size_t o_slot = stg.put(c->cell_slot);
+    const size_t o_order = stg.put(M.order);
     const size_t o_ptb = stg.put(ptb), o_poff = stg.put(poff), o_kap = stg.put(kap);
     char* base = static_cast<char*>(c->dm.alloc(stg.buf.size()));
     c->item_allocs.push_back(base);
@@ -938,6 +975,7 @@ void build_items(mlvs_ctx c) {
     c->d_cell_nbr = reinterpret_cast<int*>(base + o_nbr);
     c->d_cell_lev = reinterpret_cast<int*>(base + o_lev);
     c->d_cell_slot = reinterpret_cast<int*>(base + o_slot);
+    c->d_order = reinterpret_cast<int*>(base + o_order);
     if (c->base.Nb > 0) {
         c->d_ptb_all = reinterpret_cast<int*>(base + o_ptb);
         c->d_ptb_off = reinterpret_cast<int*>(base + o_poff);
@@ -946,12 +984,14 @@ void build_items(mlvs_ctx c) {
     int nmax = 1;
     for (int l = 0; l < K; ++l) nmax = std::max(nmax, c->levels[l]->N);
     c->nch = (nmax + c->chunk - 1) / c->chunk;
+    c->fused = c->fuse_allowed && c->nch == 1;
     c->d_fmom = static_cast<double*>(
         c->dm.alloc(sizeof(double) * NFMOM * c->nch * std::max<size_t>(faces.size(), 1)));
     c->item_allocs.push_back(c->d_fmom);
     c->d_cmom = static_cast<double*>(c->dm.alloc(sizeof(double) * NMOM * c->nch * (size_t)std::max(n, 1)));
     c->item_allocs.push_back(c->d_cmom);
     c->mom_valid = false;
+    c->prep_valid = false;
     c->d_fpar = static_cast<double*>(c->dm.alloc(sizeof(double) * NFP * std::max<size_t>(faces.size(), 1)));
     c->item_allocs.push_back(c->d_fpar);
 }
@@ -960,7 +1000,10 @@ void assign_slots(mlvs_ctx c) {
     const int K = (int)c->levels.size();
     std::vector<int> cnt(K, 0);
     c->cell_slot.resize(c->mesh.n_cells);
-    for (int cc = 0; cc < c->mesh.n_cells; ++cc) c->cell_slot[cc] = cnt[c->cell_level[cc]]++;
+    for (int k = 0; k < c->mesh.n_cells; ++k) {
+        const int cc = c->mesh.order[k];
+        c->cell_slot[cc] = cnt[c->cell_level[cc]]++;
+    }
     for (int l = 0; l < K; ++l) c->levels[l]->n_cells = cnt[l];
 }
 
@@ -978,6 +1021,7 @@ void ensure_moments(mlvs_ctx c) {
 }
 hipError_t launch_stage(mlvs_ctx c, int stage);
 hipError_t launch_step_kernels(mlvs_ctx c);
+std::vector<int> step_stages(mlvs_ctx c);
 
 }  // namespace
 
@@ -1074,6 +1118,7 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
     build_items(c);
     sync(c);
     c->mom_valid = false;
+    c->prep_valid = false;
     return changed;
 }
 
@@ -1611,6 +1656,16 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         c->adaptive = adapt != nullptr;
         if (adapt) c->ap = *adapt;
         build_mesh(c->mesh, *mesh, phys->dim);
+        {
+            // traversal tiles (MLVS_TILE=WxH overrides; 0 = row-major)
+            int tw = 16, th = 8;
+            if (const char* e = std::getenv("MLVS_TILE")) {
+                if (std::sscanf(e, "%dx%d", &tw, &th) != 2) tw = th = 0;
+                if (tw < 0 || th < 0 || tw > 4096 || th > 4096) fail(MLVS_E_ARG, "bad MLVS_TILE");
+            }
+            if (phys->dim != 2) tw = th = 0;
+            tile_order(c->mesh, tw, th);
+        }
         c->bcs.assign(mesh->bcs, mesh->bcs + mesh->n_bc);
         for (auto& b : c->bcs)
             if (b.kind < 1 || b.kind > 3) fail(MLVS_E_ARG, "unknown boundary kind %d", b.kind);
@@ -1645,6 +1700,7 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         c->d_neg = static_cast<unsigned long long*>(c->dm.alloc(8));
         hip_check(hipMemsetAsync(c->d_neg, 0, 8, c->st), "memset");
         // velocity chunk of the streaming stages (MLVS_CHUNK overrides; multiple of 64)
+        if (const char* e = std::getenv("MLVS_FUSE")) c->fuse_allowed = std::atoi(e) != 0;
         if (const char* e = std::getenv("MLVS_CHUNK")) {
             const int v = std::atoi(e);
             if (v < 64 || v % 64 != 0) fail(MLVS_E_ARG, "MLVS_CHUNK must be a positive multiple of 64");
@@ -1689,6 +1745,7 @@ mlvs_status mlvs_init_equilibrium(mlvs_ctx c, const double* st) {
         c->dm.release(d);
         c->state_ready = true;
         c->mom_valid = false;
+    c->prep_valid = false;
         c->step_count = 0;
     });
 }
@@ -1742,8 +1799,8 @@ mlvs_status mlvs_info(mlvs_ctx c, double* dt, int64_t* n_cells, int32_t* n_block
 
 mlvs_status mlvs_variants(int stage, int* count) {
     return guarded([&] {
-        if (!count || stage < 0 || stage > 6) fail(MLVS_E_ARG, "bad arguments");
-        *count = (stage == 0 || stage == 2 || stage == 3 || stage == 4 || stage == 5) ? variant_count() : 1;
+        if (!count || stage < 0 || stage > 8) fail(MLVS_E_ARG, "bad arguments");
+        *count = (stage == 1 || stage == 6) ? 1 : variant_count();
     });
 }
 
@@ -1780,7 +1837,8 @@ mlvs_status mlvs_counters(mlvs_ctx c, int64_t* steps, double* cell_updates, doub
 
 mlvs_status mlvs_time_stage(mlvs_ctx c, int stage, int reps, double* ms) {
     return guarded([&] {
-        if (!c || !ms || reps < 1 || stage < 0 || stage > 6) fail(MLVS_E_ARG, "bad arguments");
+        if (!c || !ms || reps < 1 || stage < 0 || stage > 8) fail(MLVS_E_ARG, "bad arguments");
+        if ((stage == 7 || stage == 8) && !c->fused) fail(MLVS_E_STATE, "fused stages need levels of one chunk");
         if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
         if (stage == 6 && !c->adaptive) fail(MLVS_E_STATE, "criterion needs adaptation parameters");
         ensure_moments(c);
@@ -1788,7 +1846,7 @@ mlvs_status mlvs_time_stage(mlvs_ctx c, int stage, int reps, double* ms) {
         // advances the state, which is saved here and put back afterwards
         std::vector<std::pair<void*, void*>> saved;    // (live buffer, copy)
         std::vector<size_t> saved_bytes;
-        if (stage == 5) {
+        if (stage == 5 || stage == 8) {
             auto keep = [&](void* p, size_t nb) {
                 if (!p || nb == 0) return;
                 void* q = c->dm.alloc(nb);
@@ -1802,6 +1860,14 @@ mlvs_status mlvs_time_stage(mlvs_ctx c, int stage, int reps, double* ms) {
                 keep(L->h, nb);
             }
             keep(c->d_cmom, sizeof(double) * NMOM * c->nch * (size_t)c->mesh.n_cells);
+            if (stage == 8) {          // the next step's cell stage: phi_bar+ rows and parameters
+                for (auto& L : c->levels) {
+                    const size_t nb = (size_t)L->n_cells * L->stride * c->elt();
+                    keep(L->fg, nb);
+                    keep(L->fh, nb);
+                }
+                keep(c->d_params, sizeof(double) * NPARAM * (size_t)c->mesh.n_cells);
+            }
         }
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "event");
@@ -1829,18 +1895,28 @@ mlvs_status mlvs_time_stage(mlvs_ctx c, int stage, int reps, double* ms) {
     });
 }
 
+mlvs_status mlvs_step_stages(mlvs_ctx c, int* stages, int* count) {
+    return guarded([&] {
+        if (!c || !count) fail(MLVS_E_ARG, "null argument");
+        const std::vector<int> st = step_stages(c);
+        if (stages)
+            for (size_t k = 0; k < st.size(); ++k) stages[k] = st[k];
+        *count = (int)st.size();
+    });
+}
+
 mlvs_status mlvs_stage_size(mlvs_ctx c, int stage, int64_t* items, double* points) {
     return guarded([&] {
-        if (!c || stage < 0 || stage > 6) fail(MLVS_E_ARG, "bad arguments");
+        if (!c || stage < 0 || stage > 8) fail(MLVS_E_ARG, "bad arguments");
         int64_t ni = 0;
         double np = 0.0;
         switch (stage) {
-        case 0: case 5: case 6:
+        case 0: case 5: case 6: case 8:
             ni = c->mesh.n_cells;
             np = stage == 6 ? (double)c->mesh.n_cells * c->base.N : c->step_points;
             break;
         case 1: ni = c->n_ghosts; for (auto& L : c->levels) np += (double)L->n_ghost * L->N; break;
-        case 2: case 3: {
+        case 2: case 3: case 7: {
             // same-level interior faces and boundary faces: each carries its level's points
             ni = c->n_faces + c->n_bfaces;
             for (auto& f : c->mesh.faces) {
@@ -1941,6 +2017,7 @@ mlvs_status mlvs_set_f(mlvs_ctx c, int64_t cell, const double* g, const double* 
         copy_cell(c, cell, nullptr, nullptr, g, h);
         c->state_ready = true;
         c->mom_valid = false;
+    c->prep_valid = false;
     });
 }
 
@@ -1999,6 +2076,7 @@ mlvs_status mlvs_set_state(mlvs_ctx c, const double* g, const double* h) {
         bulk_state(c, nullptr, nullptr, g, h);
         c->state_ready = true;
         c->mom_valid = false;
+    c->prep_valid = false;
     });
 }
 
@@ -2052,6 +2130,12 @@ void do_step(mlvs_ctx c) {
         if (mlvs_adapt(c, nullptr) != MLVS_OK) throw Fail{MLVS_E_STATE, g_last_error};
     }
     ensure_moments(c);
+    if (c->fused && !c->prep_valid) {
+        // the fused step starts from a prepared cell stage (the previous fused
+        // update prepares the next one)
+        hip_check(launch_stage(c, 0), "cell stage launch");
+        c->prep_valid = true;
+    }
     if (c->use_graph) {
         if (!c->gexec) {
             hip_check(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -2067,13 +2151,20 @@ void do_step(mlvs_ctx c) {
     } else {
         hip_check(launch_step_kernels(c), "step launch");
     }
+    c->prep_valid = c->fused;
     ++c->step_count;
     c->cnt_updates += c->step_points;
     c->cnt_iface += c->step_iface_points;
 }
 
+// The stages one step launches, in order.
+std::vector<int> step_stages(mlvs_ctx c) {
+    if (c->fused) return {1, 7, 4, 8};
+    return {0, 1, 2, 3, 4, 5};
+}
+
 hipError_t launch_step_kernels(mlvs_ctx c) {
-    for (int stage = 0; stage <= 5; ++stage) {
+    for (int stage : step_stages(c)) {
         const hipError_t e = launch_stage(c, stage);
         if (e != hipSuccess) return e;
     }
@@ -2082,13 +2173,14 @@ hipError_t launch_step_kernels(mlvs_ctx c) {
 
 // Stages of the step: 0 cell, 1 neighbour mapping (ghost rows), 2 face
 // reconstruction and 3 face target (same-level and boundary faces), 4
-// cross-level faces, 5 update.  6 (criterion) is timed apart.
+// cross-level faces, 5 update; fused forms 7 (2 + 3) and 8 (5 + the next
+// step's 0).  6 (criterion) is timed apart.
 hipError_t launch_stage(mlvs_ctx c, int stage) {
     const int n = c->mesh.n_cells;
     const int nf = c->n_faces + c->n_bfaces;
     switch (stage) {
-    case 0: return launch_cell_prep(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->ph, c->d_params,
-                                    c->d_cmom, c->chunk, c->variant[0]);
+    case 0: return launch_cell_prep(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, c->d_order, n, c->ph,
+                                    c->d_params, c->d_cmom, c->chunk, c->variant[0]);
     case 1: return launch_ghost(c->prec, c->st, c->d_lv, c->d_ghosts, c->n_ghosts, c->d_cell_lev, c->d_cell_slot,
                                 c->d_params, c->ph, c->d_neg);
     case 2: return launch_face_rec(c->prec, c->st, c->d_lv, c->d_faces, nf, c->d_cell_slot, c->d_cell_nbr, c->d_geom,
@@ -2097,9 +2189,14 @@ hipError_t launch_stage(mlvs_ctx c, int stage) {
                                       c->d_fpar, c->chunk, c->variant[3]);
     case 4: return launch_xface(c->prec, c->st, c->d_lv, c->d_xfaces, c->n_xfaces, c->d_cell_slot, c->d_cell_nbr,
                                 c->d_geom, c->d_params, c->ph, c->d_neg, c->variant[4]);
-    case 5: return launch_update(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom,
+    case 5: return launch_update(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, c->d_order, n, c->d_geom,
                                  c->d_cell_frow, c->d_faces, c->d_fpar, c->d_params, c->ph, c->d_cmom, c->chunk,
                                  c->nch, c->variant[5]);
+    case 7: return launch_face_full(c->prec, c->st, c->d_lv, c->d_faces, nf, c->d_cell_slot, c->d_cell_nbr,
+                                    c->d_geom, c->d_params, c->d_bcs, c->ph, c->d_fpar, c->variant[7]);
+    case 8: return launch_update_cell(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, c->d_order, n,
+                                      c->d_geom, c->d_cell_frow, c->d_faces, c->d_fpar, c->d_params, c->ph,
+                                      c->d_cmom, c->variant[8]);
     default: return hipErrorInvalidValue;
     }
 }

@@ -397,14 +397,21 @@ __device__ __forceinline__ void acc_raw(double* m, double w, double x, double y,
 }
 
 // ---------------------------------------------------------------------------
-// Staged kernels.  A workgroup of GW waves takes GW items.  Velocity passes run
-// with one wave per item (lanes over the item's points); the per-item scalar
-// steps (state, relaxation time, the small solves) run once per item on one
-// lane of wave 0, and the two kinds of step hand their results over through
-// LDS.  The scalar work is not repeated on 64 lanes.
+// Staged kernels.  A workgroup of GWV waves takes GW = GWV x IPW items.
+// Velocity passes run with one wave per item (lanes over the item's points,
+// IPW items per wave in turn); the per-item scalar steps (state, relaxation
+// time, the small solves) run once per item on one lane of wave 0, and the two
+// kinds of step hand their results over through LDS.  The scalar work is not
+// repeated on 64 lanes.
 // ---------------------------------------------------------------------------
-constexpr int GW = 8;
-constexpr int GBS = GW * WL;
+#ifndef MLVS_STAGED_IPW
+#define MLVS_STAGED_IPW 1
+#endif
+constexpr int GWV = 8;
+constexpr int IPW = MLVS_STAGED_IPW;
+constexpr int GW = GWV * IPW;
+constexpr int GBS = GWV * WL;
+static_assert(GW <= WL, "the scalar steps of a workgroup run on the lanes of one wave");
 
 // Velocity chunks.  Streaming stages that reuse neighbours' rows (face
 // reconstruction, update) split each item's points into chunks of CH points
@@ -448,10 +455,74 @@ __device__ __forceinline__ CellState cell_state(const double* cm, const Phys& ph
 // the rows phi_bar+ = alpha phi~ + beta phi_S* (Eq. g_h_eq_Pr with the
 // correction of Sec. 3.3.1).  The raw moments of g~, h~ come from cmom (the
 // previous update, or k_raw_moments after the state was set from outside).
+// The phi_bar+ row of one cell (Eq. bar_phi_transport): phi_bar+ = alpha
+// phi~ + beta phi_S* at every point of its level, phi_S* the (corrected)
+// target e.
+template <typename S, int U>
+__device__ __forceinline__ void phibar_points(const LevelDesc& L, size_t row, const Eq<double>& ed, double alpha,
+                                              double beta) {
+    const int N = L.N;
+    auto g = rowp<S>(L.g, row);
+    auto h = rowp<S>(L.h, row);
+    auto fg = rowp<S>(L.fg, row);
+    auto fh = rowp<S>(L.fh, row);
+    const Eq<S> e = eq_cast<S>(ed);
+    const S al = uni((S)alpha), be = uni((S)beta);
+    for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
+        S gv[U], hv[U], xv[U], yv[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int ic = clampi(i0 + q * WL, N);
+            gv[q] = g[ic]; hv[q] = h[ic];
+            xv[q] = (S)gp(L.xi_x)[ic]; yv[q] = (S)gp(L.xi_y)[ic];
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            S gs, hs;
+            eq_eval<S>(e, xv[q], yv[q], gs, hs);
+            gv[q] = al * gv[q] + be * gs;
+            hv[q] = al * hv[q] + be * hs;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int i = i0 + q * WL;
+            if (i < N) { fg[i] = gv[q]; fh[i] = hv[q]; }
+        }
+    }
+}
+
+// The corrected cell target in one wave (every lane holds the result): the
+// compatibility sums over the level's points and the small solve (four or
+// eight moments), for a cell whose state and uncorrected target are given.
+template <typename S, int U, int CM>
+__device__ __forceinline__ void cell_target_wave(const LevelDesc& L, const CellState& cs, const Phys& ph,
+                                                 Eq<double>& e, double (&a)[8]) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = 0.0;
+    if (!ph.compat) return;
+    if constexpr (CM == 8) {
+        double A[64];
+        compat_sums8<S, U>(L, eq_cast<S>(e), cs.u, cs.v, cs.T, ph, A);
+        compat_from_sums8(A, cs.rho, cs.u, cs.v, cs.T, (1.0 - ph.Pr) * cs.qx, (1.0 - ph.Pr) * cs.qy, ph, a);
+    } else {
+        double sm[13];
+        compat_sums<S, U>(L, eq_cast<S>(e), sm);
+        compat_from_sums(sm, cs.rho, cs.u, cs.v, cs.T, ph, a);
+    }
+    e = make_eq(cs.rho, cs.u, cs.v, cs.T, cs.qx, cs.qy, a, ph);
+}
+
+__device__ __forceinline__ void write_params(double* pr, const CellState& cs, const double* a) {
+    pr[P_RHO] = cs.rho; pr[P_U] = cs.u; pr[P_V] = cs.v; pr[P_T] = cs.T; pr[P_QX] = cs.qx;
+    pr[P_QY] = cs.qy; pr[P_TAU] = cs.tau; pr[P_A0] = a[0]; pr[P_A1] = a[1]; pr[P_A2] = a[2];
+    pr[P_A3] = a[3]; pr[P_ALPHA] = cs.alpha; pr[P_BETA] = cs.beta;
+}
+
 template <typename S, int U, int MINW, int CM>
 __global__ __launch_bounds__(GBS, MINW) void k_cell_prep(const LevelDesc* __restrict__ lvs,
                                                          const int* __restrict__ cell_lev,
-                                                         const int* __restrict__ cell_slot, int n_cells, Phys ph,
+                                                         const int* __restrict__ cell_slot,
+                                                         const int* __restrict__ order, int n_cells, Phys ph,
                                                          double* __restrict__ params,
                                                          const double* __restrict__ cmom, int CH) {
     constexpr int NS = CM == 8 ? 64 : 13;      // compatibility sums per item
@@ -463,7 +534,7 @@ __global__ __launch_bounds__(GBS, MINW) void k_cell_prep(const LevelDesc* __rest
     for (int g0 = wg_index() * GW; g0 < n_cells; g0 += gridDim.x * GW) {
         // scalar: state and the uncorrected target, one lane per cell
         if (t < GW && g0 + t < n_cells) {
-            const int ci = g0 + t;
+            const int ci = order[g0 + t];
             double cm[NMOM];
             sum_chunks(cmom, ci, n_cells, lvs[cell_lev[ci]].N, CH, cm);
             const CellState cs = cell_state(cm, ph);
@@ -471,21 +542,24 @@ __global__ __launch_bounds__(GBS, MINW) void k_cell_prep(const LevelDesc* __rest
             sh_e[t] = make_eq(cs.rho, cs.u, cs.v, cs.T, cs.qx, cs.qy, nullptr, ph);
         }
         __syncthreads();
-        const int c = g0 + w;
         // velocity pass: the compatibility sums, one wave per cell
-        if (ph.compat && c < n_cells) {
-            const LevelDesc& L = lvs[cell_lev[c]];
-            double sm[NS];
-            if constexpr (CM == 8) {
-                const CellState& cs = sh_c[w];
-                compat_sums8<S, U>(L, eq_cast<S>(sh_e[w]), cs.u, cs.v, cs.T, ph, sm);
-            } else {
-                compat_sums<S, U>(L, eq_cast<S>(sh_e[w]), sm);
-            }
-            if (lane_id() < NS) {
+        for (int kk = 0; kk < IPW; ++kk) {
+            const int j = w + GWV * kk;
+            const int c = g0 + j < n_cells ? order[g0 + j] : n_cells;
+            if (ph.compat && c < n_cells) {
+                const LevelDesc& L = lvs[cell_lev[c]];
+                double sm[NS];
+                if constexpr (CM == 8) {
+                    const CellState& cs = sh_c[j];
+                    compat_sums8<S, U>(L, eq_cast<S>(sh_e[j]), cs.u, cs.v, cs.T, ph, sm);
+                } else {
+                    compat_sums<S, U>(L, eq_cast<S>(sh_e[j]), sm);
+                }
+                if (lane_id() < NS) {
 #pragma unroll
-                for (int k = 0; k < NS; ++k)
-                    if (lane_id() == k) sh_s[w][k] = sm[k];
+                    for (int k = 0; k < NS; ++k)
+                        if (lane_id() == k) sh_s[j][k] = sm[k];
+                }
             }
         }
         __syncthreads();
@@ -501,44 +575,16 @@ __global__ __launch_bounds__(GBS, MINW) void k_cell_prep(const LevelDesc* __rest
                     compat_from_sums(sh_s[t], cs.rho, cs.u, cs.v, cs.T, ph, a);
                 sh_e[t] = make_eq(cs.rho, cs.u, cs.v, cs.T, cs.qx, cs.qy, a, ph);
             }
-            double* pr = params + (size_t)(g0 + t) * NPARAM;
-            pr[P_RHO] = cs.rho; pr[P_U] = cs.u; pr[P_V] = cs.v; pr[P_T] = cs.T; pr[P_QX] = cs.qx;
-            pr[P_QY] = cs.qy; pr[P_TAU] = cs.tau; pr[P_A0] = a[0]; pr[P_A1] = a[1]; pr[P_A2] = a[2];
-            pr[P_A3] = a[3]; pr[P_ALPHA] = cs.alpha; pr[P_BETA] = cs.beta;
+            write_params(params + (size_t)order[g0 + t] * NPARAM, cs, a);
         }
         __syncthreads();
         // velocity pass: the phi_bar+ rows
-        if (c < n_cells) {
+        for (int kk = 0; kk < IPW; ++kk) {
+            const int j = w + GWV * kk;
+            const int c = g0 + j < n_cells ? order[g0 + j] : n_cells;
+            if (c >= n_cells) break;
             const LevelDesc& L = lvs[cell_lev[c]];
-            const int N = L.N;
-            const size_t row = (size_t)cell_slot[c] * L.stride;
-            auto g = rowp<S>(L.g, row);
-            auto h = rowp<S>(L.h, row);
-            auto fg = rowp<S>(L.fg, row);
-            auto fh = rowp<S>(L.fh, row);
-            const Eq<S> e = eq_cast<S>(sh_e[w]);
-            const S al = uni((S)sh_c[w].alpha), be = uni((S)sh_c[w].beta);
-            for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
-                S gv[U], hv[U], xv[U], yv[U];
-#pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    const int ic = clampi(i0 + q * WL, N);
-                    gv[q] = g[ic]; hv[q] = h[ic];
-                    xv[q] = (S)gp(L.xi_x)[ic]; yv[q] = (S)gp(L.xi_y)[ic];
-                }
-#pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    S gs, hs;
-                    eq_eval<S>(e, xv[q], yv[q], gs, hs);
-                    gv[q] = al * gv[q] + be * gs;
-                    hv[q] = al * hv[q] + be * hs;
-                }
-#pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    const int i = i0 + q * WL;
-                    if (i < N) { fg[i] = gv[q]; fh[i] = hv[q]; }
-                }
-            }
+            phibar_points<S, U>(L, (size_t)cell_slot[c] * L.stride, sh_e[j], sh_c[j].alpha, sh_c[j].beta);
         }
         __syncthreads();
     }
@@ -960,6 +1006,87 @@ __device__ __forceinline__ void stencil_ext1(const Side<S>& a, const Stencil<S>&
 // (about the mean of the two cell velocities); boundary faces reduce the
 // outgoing mass flux.  Per-face results go to fmom[item][NFMOM] (the moments,
 // then the velocity shift they are taken about).
+template <typename S, int U>
+__device__ __forceinline__ void face_rec_points(const LevelDesc& L, const FaceItem& F, const int* cell_slot,
+                                                const int* cell_nbr, const CellGeom* geom, const double* params,
+                                                const Phys& ph, int beg, int N, double (&m)[11], double& u0,
+                                                double& v0) {
+    const S s = (S)(0.5 * ph.dt);
+    auto rg = rowp<S>(L.Fg, (size_t)F.row * L.stride);
+    auto rh = rowp<S>(L.Fh, (size_t)F.row * L.stride);
+    Side<S> sL;
+    load_side<S>(sL, L, F.L, cell_slot, cell_nbr, geom, F.dLx, F.dLy);
+    const bool interior = F.R >= 0;
+    Side<S> sR = sL;
+    u0 = 0.0;
+    v0 = 0.0;
+    if (interior) {
+        load_side<S>(sR, L, F.R, cell_slot, cell_nbr, geom, F.dRx, F.dRy);
+        u0 = 0.5 * (params[(size_t)F.L * NPARAM + P_U] + params[(size_t)F.R * NPARAM + P_U]);
+        v0 = 0.5 * (params[(size_t)F.L * NPARAM + P_V] + params[(size_t)F.R * NPARAM + P_V]);
+    }
+#pragma unroll
+    for (int k = 0; k < 11; ++k) m[k] = 0.0;
+    for (int i0 = beg + lane_id(); i0 < N; i0 += WL * U) {
+        double xv[U], yv[U], wv[U];
+        bool up[U];
+        // points are stored by velocity angle, so a chunk almost always has
+        // one upwind side for the whole wavefront: then that side's stencil
+        // is used with scalar offsets and coefficients
+        bool allL = true, allR = true;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int i = i0 + q * WL, ic = clampi(i, N);
+            xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
+            wv[q] = i < N ? gp(L.w)[ic] : 0.0;
+            const double dn = xv[q] * F.nx + yv[q] * F.ny;
+            up[q] = dn >= 0.0;
+            allL = allL && (i >= N || dn > 0.0);
+            allR = allR && (i >= N || dn < 0.0);
+        }
+        const int side = !interior ? 0 : (__all(allL) ? 0 : (__all(allR) ? 1 : 2));
+        S eg[U], eh[U];
+        if (side < 2) {
+            const Side<S>& sd = side == 0 ? sL : sR;
+            Stencil<S> st[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) load_stencil1<S>(sd, clampi(i0 + q * WL, N), st[q]);
+#pragma unroll
+            for (int q = 0; q < U; ++q) stencil_ext1<S>(sd, st[q], (S)xv[q], (S)yv[q], s, eg[q], eh[q]);
+        } else {
+            Stencil<S> st[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) load_stencil<S>(sL, sR, up[q], clampi(i0 + q * WL, N), st[q]);
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int ic = clampi(i0 + q * WL, N);
+                const S x = (S)xv[q], y = (S)yv[q];
+                stencil_ext<S>(sL, sR, up[q], st[q], x, y, s, eg[q], eh[q]);
+                const double dn = xv[q] * F.nx + yv[q] * F.ny;
+                if (dn == 0.0) {                    // both sides, averaged
+                    Stencil<S> sb;
+                    load_stencil<S>(sL, sR, false, ic, sb);
+                    S bg, bh;
+                    stencil_ext<S>(sL, sR, false, sb, x, y, s, bg, bh);
+                    eg[q] = S(0.5) * (eg[q] + bg);
+                    eh[q] = S(0.5) * (eh[q] + bh);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int i = i0 + q * WL;
+            if (i < N) { rg[i] = eg[q]; rh[i] = eh[q]; }
+            if (interior) {
+                acc_raw<S>(m, wv[q], xv[q] - u0, yv[q] - v0, eg[q], eh[q]);
+            } else {
+                const double dn = xv[q] * F.nx + yv[q] * F.ny;
+                if (dn > 0) m[0] += wv[q] * dn * (double)eg[q];
+            }
+        }
+    }
+}
+
 template <typename S, int U, int MINW>
 __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restrict__ lvs,
                                                        const FaceItem* __restrict__ items, int nF,
@@ -968,7 +1095,6 @@ __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restri
                                                        const CellGeom* __restrict__ geom,
                                                        const double* __restrict__ params, Phys ph,
                                                        double* __restrict__ fmom, int CH, int nch) {
-    const S s = (S)(0.5 * ph.dt);
     const int n = nF * nch;
     for (int it = item0(); it < n; it += istride()) {
         const int kc = it / nF, f = it - kc * nF;
@@ -977,80 +1103,9 @@ __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restri
         const int beg = kc * CH;
         if (beg >= L.N) continue;
         const int N = min(L.N, beg + CH);      // end of this chunk
-        auto rg = rowp<S>(L.Fg, (size_t)F.row * L.stride);
-        auto rh = rowp<S>(L.Fh, (size_t)F.row * L.stride);
-        Side<S> sL;
-        load_side<S>(sL, L, F.L, cell_slot, cell_nbr, geom, F.dLx, F.dLy);
+        double m[11], u0, v0;
+        face_rec_points<S, U>(L, F, cell_slot, cell_nbr, geom, params, ph, beg, N, m, u0, v0);
         double* out = fmom + (size_t)it * NFMOM;
-        const bool interior = F.R >= 0;
-        Side<S> sR = sL;
-        double u0 = 0.0, v0 = 0.0;
-        if (interior) {
-            load_side<S>(sR, L, F.R, cell_slot, cell_nbr, geom, F.dRx, F.dRy);
-            u0 = 0.5 * (params[(size_t)F.L * NPARAM + P_U] + params[(size_t)F.R * NPARAM + P_U]);
-            v0 = 0.5 * (params[(size_t)F.L * NPARAM + P_V] + params[(size_t)F.R * NPARAM + P_V]);
-        }
-        double m[11];
-#pragma unroll
-        for (int k = 0; k < 11; ++k) m[k] = 0.0;
-        for (int i0 = beg + lane_id(); i0 < N; i0 += WL * U) {
-            double xv[U], yv[U], wv[U];
-            bool up[U];
-            // points are stored by velocity angle, so a chunk almost always has
-            // one upwind side for the whole wavefront: then that side's stencil
-            // is used with scalar offsets and coefficients
-            bool allL = true, allR = true;
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const int i = i0 + q * WL, ic = clampi(i, N);
-                xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
-                wv[q] = i < N ? gp(L.w)[ic] : 0.0;
-                const double dn = xv[q] * F.nx + yv[q] * F.ny;
-                up[q] = dn >= 0.0;
-                allL = allL && (i >= N || dn > 0.0);
-                allR = allR && (i >= N || dn < 0.0);
-            }
-            const int side = !interior ? 0 : (__all(allL) ? 0 : (__all(allR) ? 1 : 2));
-            S eg[U], eh[U];
-            if (side < 2) {
-                const Side<S>& sd = side == 0 ? sL : sR;
-                Stencil<S> st[U];
-#pragma unroll
-                for (int q = 0; q < U; ++q) load_stencil1<S>(sd, clampi(i0 + q * WL, N), st[q]);
-#pragma unroll
-                for (int q = 0; q < U; ++q) stencil_ext1<S>(sd, st[q], (S)xv[q], (S)yv[q], s, eg[q], eh[q]);
-            } else {
-                Stencil<S> st[U];
-#pragma unroll
-                for (int q = 0; q < U; ++q) load_stencil<S>(sL, sR, up[q], clampi(i0 + q * WL, N), st[q]);
-#pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    const int ic = clampi(i0 + q * WL, N);
-                    const S x = (S)xv[q], y = (S)yv[q];
-                    stencil_ext<S>(sL, sR, up[q], st[q], x, y, s, eg[q], eh[q]);
-                    const double dn = xv[q] * F.nx + yv[q] * F.ny;
-                    if (dn == 0.0) {                    // both sides, averaged
-                        Stencil<S> sb;
-                        load_stencil<S>(sL, sR, false, ic, sb);
-                        S bg, bh;
-                        stencil_ext<S>(sL, sR, false, sb, x, y, s, bg, bh);
-                        eg[q] = S(0.5) * (eg[q] + bg);
-                        eh[q] = S(0.5) * (eh[q] + bh);
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const int i = i0 + q * WL;
-                if (i < N) { rg[i] = eg[q]; rh[i] = eh[q]; }
-                if (interior) {
-                    acc_raw<S>(m, wv[q], xv[q] - u0, yv[q] - v0, eg[q], eh[q]);
-                } else {
-                    const double dn = xv[q] * F.nx + yv[q] * F.ny;
-                    if (dn > 0) m[0] += wv[q] * dn * (double)eg[q];
-                }
-            }
-        }
         wave_sum<11>(m);
         if (lane_id() < 11) {
 #pragma unroll
@@ -1072,6 +1127,47 @@ __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restri
 //     state -- diffuse wall rho_w g_eq(u_w, T_w) with rho_w from zero net mass
 //     flux, far-field Maxwellian, or the cell's phi_bar+ (zero-gradient
 //     outflow).
+// Incoming mass flux sum w (xi . n) g_w over xi . n < 0 of a diffuse wall's
+// Maxwellian es (unit density), in one wave (every lane holds the result).
+template <typename S, int U>
+__device__ __forceinline__ double wall_inflow(const LevelDesc& L, const FaceItem& F, const Eq<S>& es) {
+    const int N = L.N;
+    double m1[1] = {0.0};
+    for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
+        double xv[U], yv[U], wv[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int i = i0 + q * WL, ic = clampi(i, N);
+            xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
+            wv[q] = i < N ? gp(L.w)[ic] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const double dn = xv[q] * F.nx + yv[q] * F.ny;
+            if (dn < 0) {
+                S gs, hs;
+                eq_eval<S>(es, (S)xv[q], (S)yv[q], gs, hs);
+                m1[0] += wv[q] * dn * (double)gs;
+            }
+        }
+    }
+    wave_sum<1>(m1);
+    return m1[0];
+}
+
+// The record the update reads for one face (layout FP_*).
+__device__ __forceinline__ void write_face_record(double* o, double kind, const FaceItem& F, double c1, double c2,
+                                                  const Eq<double>& e) {
+    o[FP_KIND] = kind; o[FP_ROW] = (double)F.row; o[FP_NX] = F.nx; o[FP_NY] = F.ny;
+    o[FP_C1] = c1; o[FP_C2] = c2;
+    o[FP_RN] = e.rn; o[FP_UX] = e.ux; o[FP_UY] = e.uy; o[FP_I2RT] = e.i2RT; o[FP_RT] = e.RT;
+    o[FP_IRT] = e.iRT; o[FP_XQX] = e.Xqx; o[FP_XQY] = e.Xqy;
+    o[FP_B0] = e.b0; o[FP_B1] = e.b1; o[FP_B2] = e.b2; o[FP_B3] = e.b3;
+    o[FP_CORR] = e.corr ? 1.0 : 0.0;
+    o[FP_E4] = e.e4; o[FP_E5] = e.e5; o[FP_E6] = e.e6; o[FP_E7] = e.e7; o[FP_CKRT] = e.cKRT;
+    o[FP_C8] = e.c8 ? 1.0 : 0.0;
+}
+
 template <typename S, int U, int MINW, int CM>
 __global__ __launch_bounds__(GBS, MINW) void k_face_target(const LevelDesc* __restrict__ lvs,
                                                            const FaceItem* __restrict__ items, int n,
@@ -1085,7 +1181,6 @@ __global__ __launch_bounds__(GBS, MINW) void k_face_target(const LevelDesc* __re
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave index (uniform)
     const int t = threadIdx.x;
     for (int g0 = wg_index() * GW; g0 < n; g0 += gridDim.x * GW) {
-        const int it = g0 + w;
         // face state and uncorrected target
         if (t < GW && g0 + t < n) {
             const FaceItem F = items[g0 + t];
@@ -1108,48 +1203,30 @@ __global__ __launch_bounds__(GBS, MINW) void k_face_target(const LevelDesc* __re
         }
         __syncthreads();
         // compatibility sums (interior) or the wall's incoming mass flux
-        if (it < n) {
+        for (int kk = 0; kk < IPW; ++kk) {
+            const int j = w + GWV * kk;
+            const int it = g0 + j;
+            if (it >= n) break;
             const FaceItem F = items[it];
             const LevelDesc& L = lvs[F.lev];
             if (F.R >= 0) {
                 if (ph.compat && ph.face_compat) {
                     double sm[NS];
                     if constexpr (CM == 8) {
-                        const FaceState& fs = sh_f[w];
-                        compat_sums8<S, U>(L, eq_cast<S>(sh_e[w]), fs.u, fs.v, fs.T, ph, sm);
+                        const FaceState& fs = sh_f[j];
+                        compat_sums8<S, U>(L, eq_cast<S>(sh_e[j]), fs.u, fs.v, fs.T, ph, sm);
                     } else {
-                        compat_sums<S, U>(L, eq_cast<S>(sh_e[w]), sm);
+                        compat_sums<S, U>(L, eq_cast<S>(sh_e[j]), sm);
                     }
                     if (lane_id() < NS) {
 #pragma unroll
                         for (int k = 0; k < NS; ++k)
-                            if (lane_id() == k) sh_m[w][k] = sm[k];
+                            if (lane_id() == k) sh_m[j][k] = sm[k];
                     }
                 }
             } else if (bcs[-1 - F.R].kind == 1) {
-                const Eq<S> es = eq_cast<S>(sh_e[w]);
-                const int N = L.N;
-                double m1[1] = {0.0};
-                for (int i0 = lane_id(); i0 < N; i0 += WL * U) {
-                    double xv[U], yv[U], wv[U];
-#pragma unroll
-                    for (int q = 0; q < U; ++q) {
-                        const int i = i0 + q * WL, ic = clampi(i, N);
-                        xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
-                        wv[q] = i < N ? gp(L.w)[ic] : 0.0;
-                    }
-#pragma unroll
-                    for (int q = 0; q < U; ++q) {
-                        const double dn = xv[q] * F.nx + yv[q] * F.ny;
-                        if (dn < 0) {
-                            S gs, hs;
-                            eq_eval<S>(es, (S)xv[q], (S)yv[q], gs, hs);
-                            m1[0] += wv[q] * dn * (double)gs;
-                        }
-                    }
-                }
-                wave_sum<1>(m1);
-                if (lane_id() == 0) sh_m[w][1] = m1[0];   // [0] keeps the outgoing flux
+                const double m1 = wall_inflow<S, U>(L, F, eq_cast<S>(sh_e[j]));
+                if (lane_id() == 0) sh_m[j][1] = m1;      // [0] keeps the outgoing flux
             }
         }
         __syncthreads();
@@ -1176,17 +1253,64 @@ __global__ __launch_bounds__(GBS, MINW) void k_face_target(const LevelDesc* __re
                 kind = (double)bc.kind;
                 if (bc.kind == 1) c2 = F.area * (-sh_m[t][0] / sh_m[t][1]);
             }
-            double* o = fpar + (size_t)(g0 + t) * NFP;
-            o[FP_KIND] = kind; o[FP_ROW] = (double)F.row; o[FP_NX] = F.nx; o[FP_NY] = F.ny;
-            o[FP_C1] = c1; o[FP_C2] = c2;
-            o[FP_RN] = e.rn; o[FP_UX] = e.ux; o[FP_UY] = e.uy; o[FP_I2RT] = e.i2RT; o[FP_RT] = e.RT;
-            o[FP_IRT] = e.iRT; o[FP_XQX] = e.Xqx; o[FP_XQY] = e.Xqy;
-            o[FP_B0] = e.b0; o[FP_B1] = e.b1; o[FP_B2] = e.b2; o[FP_B3] = e.b3;
-            o[FP_CORR] = e.corr ? 1.0 : 0.0;
-            o[FP_E4] = e.e4; o[FP_E5] = e.e5; o[FP_E6] = e.e6; o[FP_E7] = e.e7; o[FP_CKRT] = e.cKRT;
-            o[FP_C8] = e.c8 ? 1.0 : 0.0;
+            write_face_record(fpar + (size_t)(g0 + t) * NFP, kind, F, c1, c2, e);
         }
         __syncthreads();
+    }
+}
+
+// Reconstruction and target of one face in one wave: all of the face's points
+// in one pass, then the face state, the corrected target and the record from
+// the wave's own sums (every lane holds them; lane 0 writes).  The form for
+// level sets whose levels fit one velocity chunk, where the reconstruction has
+// no chunk partials to add and the staged target's per-workgroup hand-overs
+// would dominate.  Same arithmetic as k_face_rec + k_face_target.
+template <typename S, int U, int MINW, int CM>
+__global__ __launch_bounds__(BS, MINW) void k_face_full(const LevelDesc* __restrict__ lvs,
+                                                        const FaceItem* __restrict__ items, int nF,
+                                                        const int* __restrict__ cell_slot,
+                                                        const int* __restrict__ cell_nbr,
+                                                        const CellGeom* __restrict__ geom,
+                                                        const double* __restrict__ params,
+                                                        const BCDev* __restrict__ bcs, Phys ph,
+                                                        double* __restrict__ fpar) {
+    for (int f = item0(); f < nF; f += istride()) {
+        const FaceItem F = items[f];
+        const LevelDesc& L = lvs[F.lev];
+        double m[11], u0, v0;
+        face_rec_points<S, U>(L, F, cell_slot, cell_nbr, geom, params, ph, 0, L.N, m, u0, v0);
+        wave_sum<11>(m);
+        double kind = 0.0, c1, c2;
+        Eq<double> e;
+        if (F.R >= 0) {
+            const FaceState fs = face_state(m, u0, v0, ph);
+            e = make_eq(fs.rho, fs.u, fs.v, fs.T, fs.qx, fs.qy, nullptr, ph);
+            if (ph.compat && ph.face_compat) {
+                double a[8];
+                if constexpr (CM == 8) {
+                    double A[64];
+                    compat_sums8<S, U>(L, eq_cast<S>(e), fs.u, fs.v, fs.T, ph, A);
+                    compat_from_sums8(A, fs.rho, fs.u, fs.v, fs.T, (1.0 - ph.Pr) * fs.qx, (1.0 - ph.Pr) * fs.qy,
+                                      ph, a);
+                } else {
+                    double sm[13];
+                    compat_sums<S, U>(L, eq_cast<S>(e), sm);
+                    compat_from_sums(sm, fs.rho, fs.u, fs.v, fs.T, ph, a);
+                }
+                e = make_eq(fs.rho, fs.u, fs.v, fs.T, fs.qx, fs.qy, a, ph);
+            }
+            c1 = fs.c1 * F.area;
+            c2 = fs.c2 * F.area;
+        } else {
+            const BCDev bc = bcs[-1 - F.R];
+            kind = (double)bc.kind;
+            e = bc.kind == 2 ? make_eq(bc.rho, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph)
+                             : make_eq(1.0, bc.u, bc.v, bc.T, 0.0, 0.0, nullptr, ph);
+            c1 = F.area;
+            c2 = F.area;
+            if (bc.kind == 1) c2 = F.area * (-m[0] / wall_inflow<S, U>(L, F, eq_cast<S>(e)));
+        }
+        if (lane_id() == 0) write_face_record(fpar + (size_t)f * NFP, kind, F, c1, c2, e);
     }
 }
 
@@ -1214,131 +1338,188 @@ __device__ __forceinline__ Eq<S> load_face_eq(const double* fp, const Phys& ph) 
 // Face codes (cell_frow): -1 none; else 4 x + 2 final + neg, x the face item
 // (final = 0) or the level row of a final flux (final = 1).
 // ---------------------------------------------------------------------------
-template <typename S, int U, int MINW>
-__global__ __launch_bounds__(BS, MINW) void k_update(const LevelDesc* __restrict__ lvs,
-                                                     const int* __restrict__ cell_lev,
-                                                     const int* __restrict__ cell_slot, int n_cells,
-                                                     const CellGeom* __restrict__ geom,
-                                                     const int* __restrict__ cell_frow,
-                                                     const FaceItem* __restrict__ items,
-                                                     const double* __restrict__ fpar,
-                                                     const double* __restrict__ params, Phys ph,
-                                                     double* __restrict__ cmom, int CH, int nch) {
+// One cell over points [beg, N) of its level; m: the raw moments of the new
+// state about the step's cell velocity (u0, v0).
+template <typename S, int U>
+__device__ __forceinline__ void update_points(const LevelDesc& L, int c, const int* cell_slot, const CellGeom* geom,
+                                              const int* cell_frow, const FaceItem* items, const double* fpar,
+                                              const double* params, const Phys& ph, int beg, int N,
+                                              double (&m)[11], double& u0, double& v0) {
     const S c43 = (S)(4.0 / 3.0), c13 = (S)(1.0 / 3.0);
-    const int n = n_cells * nch;
-    for (int it = item0(); it < n; it += istride()) {
-        const int kc = it / n_cells, c = it - kc * n_cells;
-        const LevelDesc& L = lvs[cell_lev[c]];
-        const int beg = kc * CH;
-        if (beg >= L.N) continue;
-        const int N = min(L.N, beg + CH);      // end of this chunk
-        const size_t row = (size_t)cell_slot[c] * L.stride;
-        auto g = rowp<S>(L.g, row);
-        auto h = rowp<S>(L.h, row);
-        auto fg = rowp<S>(L.fg, row);
-        auto fh = rowp<S>(L.fh, row);
-        int code[4];
+    const size_t row = (size_t)cell_slot[c] * L.stride;
+    auto g = rowp<S>(L.g, row);
+    auto h = rowp<S>(L.h, row);
+    auto fg = rowp<S>(L.fg, row);
+    auto fh = rowp<S>(L.fh, row);
+    int code[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) code[k] = cell_frow[4 * c + k];
-        const S kv = uni((S)(ph.dt / geom[c].vol));
-        const double u0 = params[(size_t)c * NPARAM + P_U], v0 = params[(size_t)c * NPARAM + P_V];
-        double m[11];
+    for (int k = 0; k < 4; ++k) code[k] = cell_frow[4 * c + k];
+    const S kv = uni((S)(ph.dt / geom[c].vol));
+    u0 = params[(size_t)c * NPARAM + P_U];
+    v0 = params[(size_t)c * NPARAM + P_V];
 #pragma unroll
-        for (int k = 0; k < 11; ++k) m[k] = 0.0;
-        for (int i0 = beg + lane_id(); i0 < N; i0 += WL * U) {
-            double xv[U], yv[U], wv[U];
-            S bg[U], bh[U], go[U], ho[U], ag[U], ah[U];
+    for (int k = 0; k < 11; ++k) m[k] = 0.0;
+    for (int i0 = beg + lane_id(); i0 < N; i0 += WL * U) {
+        double xv[U], yv[U], wv[U];
+        S bg[U], bh[U], go[U], ho[U], ag[U], ah[U];
 #pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const int i = i0 + q * WL, ic = clampi(i, N);
-                xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
-                wv[q] = i < N ? gp(L.w)[ic] : 0.0;
-                bg[q] = fg[ic]; bh[q] = fh[ic];
-                go[q] = g[ic]; ho[q] = h[ic];
-                ag[q] = S(0); ah[q] = S(0);
-            }
+        for (int q = 0; q < U; ++q) {
+            const int i = i0 + q * WL, ic = clampi(i, N);
+            xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
+            wv[q] = i < N ? gp(L.w)[ic] : 0.0;
+            bg[q] = fg[ic]; bh[q] = fh[ic];
+            go[q] = g[ic]; ho[q] = h[ic];
+            ag[q] = S(0); ah[q] = S(0);
+        }
 #pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                const int cd = code[f];
-                if (cd < 0) continue;
-                const S sgn = (cd & 1) ? S(-1) : S(1);
-                if (cd & 2) {
-                    const size_t r = (size_t)(cd >> 2) * L.stride;
-                    auto Fg = rowp<S>(L.Fg, r);
-                    auto Fh = rowp<S>(L.Fh, r);
-                    S vg[U], vh[U];
-#pragma unroll
-                    for (int q = 0; q < U; ++q) {
-                        const int ic = clampi(i0 + q * WL, N);
-                        vg[q] = Fg[ic]; vh[q] = Fh[ic];
-                    }
-#pragma unroll
-                    for (int q = 0; q < U; ++q) { ag[q] += sgn * vg[q]; ah[q] += sgn * vh[q]; }
-                    continue;
-                }
-                const double* fp = fpar + (size_t)(cd >> 2) * NFP;
-                const int kind = __builtin_amdgcn_readfirstlane((int)fp[FP_KIND]);
-                const size_t r = (size_t)items[cd >> 2].row * L.stride;
+        for (int f = 0; f < 4; ++f) {
+            const int cd = code[f];
+            if (cd < 0) continue;
+            const S sgn = (cd & 1) ? S(-1) : S(1);
+            if (cd & 2) {
+                const size_t r = (size_t)(cd >> 2) * L.stride;
                 auto Fg = rowp<S>(L.Fg, r);
                 auto Fh = rowp<S>(L.Fh, r);
-                const double nx = fp[FP_NX], ny = fp[FP_NY];
-                const S k1 = uni((S)fp[FP_C1]), k2 = uni((S)fp[FP_C2]);
                 S vg[U], vh[U];
 #pragma unroll
                 for (int q = 0; q < U; ++q) {
                     const int ic = clampi(i0 + q * WL, N);
                     vg[q] = Fg[ic]; vh[q] = Fh[ic];
                 }
-                if (kind == 3) {            // outflow: incoming = the cell's phi_bar+
 #pragma unroll
-                    for (int q = 0; q < U; ++q) {
-                        const double dnd = xv[q] * nx + yv[q] * ny;
-                        const S dn = (S)dnd;
-                        const S pg = dnd > 0 ? vg[q] : bg[q], ph_ = dnd > 0 ? vh[q] : bh[q];
-                        ag[q] += sgn * (k1 * dn * pg);
-                        ah[q] += sgn * (k1 * dn * ph_);
-                    }
-                    continue;
-                }
-                const Eq<S> e = load_face_eq<S>(fp, ph);
+                for (int q = 0; q < U; ++q) { ag[q] += sgn * vg[q]; ah[q] += sgn * vh[q]; }
+                continue;
+            }
+            const double* fp = fpar + (size_t)(cd >> 2) * NFP;
+            const int kind = __builtin_amdgcn_readfirstlane((int)fp[FP_KIND]);
+            const size_t r = (size_t)items[cd >> 2].row * L.stride;
+            auto Fg = rowp<S>(L.Fg, r);
+            auto Fh = rowp<S>(L.Fh, r);
+            const double nx = fp[FP_NX], ny = fp[FP_NY];
+            const S k1 = uni((S)fp[FP_C1]), k2 = uni((S)fp[FP_C2]);
+            S vg[U], vh[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int ic = clampi(i0 + q * WL, N);
+                vg[q] = Fg[ic]; vh[q] = Fh[ic];
+            }
+            if (kind == 3) {            // outflow: incoming = the cell's phi_bar+
 #pragma unroll
                 for (int q = 0; q < U; ++q) {
                     const double dnd = xv[q] * nx + yv[q] * ny;
                     const S dn = (S)dnd;
-                    S gs, hs;
-                    eq_eval<S>(e, (S)xv[q], (S)yv[q], gs, hs);
-                    S pg, ph_;
-                    if (kind == 0) {
-                        pg = k1 * vg[q] + k2 * gs;
-                        ph_ = k1 * vh[q] + k2 * hs;
-                    } else {
-                        pg = dnd > 0 ? k1 * vg[q] : k2 * gs;
-                        ph_ = dnd > 0 ? k1 * vh[q] : k2 * hs;
-                    }
-                    ag[q] += sgn * (dn * pg);
-                    ah[q] += sgn * (dn * ph_);
+                    const S pg = dnd > 0 ? vg[q] : bg[q], ph_ = dnd > 0 ? vh[q] : bh[q];
+                    ag[q] += sgn * (k1 * dn * pg);
+                    ah[q] += sgn * (k1 * dn * ph_);
                 }
+                continue;
             }
-            S gn[U], hn[U];
+            const Eq<S> e = load_face_eq<S>(fp, ph);
 #pragma unroll
             for (int q = 0; q < U; ++q) {
-                gn[q] = c43 * bg[q] - c13 * go[q] - kv * ag[q];
-                hn[q] = c43 * bh[q] - c13 * ho[q] - kv * ah[q];
-            }
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const int i = i0 + q * WL;
-                if (i < N) { g[i] = gn[q]; h[i] = hn[q]; }
-                acc_raw<S>(m, wv[q], xv[q] - u0, yv[q] - v0, gn[q], hn[q]);
+                const double dnd = xv[q] * nx + yv[q] * ny;
+                const S dn = (S)dnd;
+                S gs, hs;
+                eq_eval<S>(e, (S)xv[q], (S)yv[q], gs, hs);
+                S pg, ph_;
+                if (kind == 0) {
+                    pg = k1 * vg[q] + k2 * gs;
+                    ph_ = k1 * vh[q] + k2 * hs;
+                } else {
+                    pg = dnd > 0 ? k1 * vg[q] : k2 * gs;
+                    ph_ = dnd > 0 ? k1 * vh[q] : k2 * hs;
+                }
+                ag[q] += sgn * (dn * pg);
+                ah[q] += sgn * (dn * ph_);
             }
         }
+        S gn[U], hn[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            gn[q] = c43 * bg[q] - c13 * go[q] - kv * ag[q];
+            hn[q] = c43 * bh[q] - c13 * ho[q] - kv * ah[q];
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int i = i0 + q * WL;
+            if (i < N) { g[i] = gn[q]; h[i] = hn[q]; }
+            acc_raw<S>(m, wv[q], xv[q] - u0, yv[q] - v0, gn[q], hn[q]);
+        }
+    }
+}
+
+template <typename S, int U, int MINW>
+__global__ __launch_bounds__(BS, MINW) void k_update(const LevelDesc* __restrict__ lvs,
+                                                     const int* __restrict__ cell_lev,
+                                                     const int* __restrict__ cell_slot,
+                                                     const int* __restrict__ order, int n_cells,
+                                                     const CellGeom* __restrict__ geom,
+                                                     const int* __restrict__ cell_frow,
+                                                     const FaceItem* __restrict__ items,
+                                                     const double* __restrict__ fpar,
+                                                     const double* __restrict__ params, Phys ph,
+                                                     double* __restrict__ cmom, int CH, int nch) {
+    const int n = n_cells * nch;
+    for (int it = item0(); it < n; it += istride()) {
+        const int kc = it / n_cells, c = order[it - kc * n_cells];
+        const LevelDesc& L = lvs[cell_lev[c]];
+        const int beg = kc * CH;
+        if (beg >= L.N) continue;
+        const int N = min(L.N, beg + CH);      // end of this chunk
+        double m[11], u0, v0;
+        update_points<S, U>(L, c, cell_slot, geom, cell_frow, items, fpar, params, ph, beg, N, m, u0, v0);
         wave_sum<11>(m);
         if (lane_id() == 0) {
-            double* o = cmom + (size_t)it * NMOM;
+            double* o = cmom + ((size_t)kc * n_cells + c) * NMOM;
             for (int k = 0; k < 11; ++k) o[k] = m[k];
             o[M_U0] = u0;
             o[M_V0] = v0;
         }
+    }
+}
+
+// The update followed, in the same wave, by the next step's cell stage for
+// the same cell: the new state's moments (the wave's own sums), W, tau, q and
+// the corrected target, the parameters, and the phi_bar+ row from the new
+// state, which the wave re-reads point by point from what its own lanes just
+// wrote.  Only the cell's own rows and parameters are touched, and no other
+// cell's update reads them, so the next step's cell stage is complete when
+// this launch ends.  The form for level sets whose levels fit one velocity
+// chunk.  Same arithmetic as k_update + k_cell_prep.
+template <typename S, int U, int MINW, int CM>
+__global__ __launch_bounds__(BS, MINW) void k_update_cell(const LevelDesc* __restrict__ lvs,
+                                                          const int* __restrict__ cell_lev,
+                                                          const int* __restrict__ cell_slot,
+                                                          const int* __restrict__ order, int n_cells,
+                                                          const CellGeom* __restrict__ geom,
+                                                          const int* __restrict__ cell_frow,
+                                                          const FaceItem* __restrict__ items,
+                                                          const double* __restrict__ fpar,
+                                                          double* __restrict__ params, Phys ph,
+                                                          double* __restrict__ cmom) {
+    for (int it = item0(); it < n_cells; it += istride()) {
+        const int c = order[it];
+        const LevelDesc& L = lvs[cell_lev[c]];
+        double cm[NMOM], u0, v0;
+        double m[11];
+        update_points<S, U>(L, c, cell_slot, geom, cell_frow, items, fpar, params, ph, 0, L.N, m, u0, v0);
+        wave_sum<11>(m);
+#pragma unroll
+        for (int k = 0; k < 11; ++k) cm[k] = m[k];
+        cm[M_U0] = u0;
+        cm[M_V0] = v0;
+        if (lane_id() == 0) {
+            double* o = cmom + (size_t)c * NMOM;
+            for (int k = 0; k < 11; ++k) o[k] = m[k];
+            o[M_U0] = u0;
+            o[M_V0] = v0;
+        }
+        const CellState cs = cell_state(cm, ph);
+        Eq<double> e = make_eq(cs.rho, cs.u, cs.v, cs.T, cs.qx, cs.qy, nullptr, ph);
+        double a[8];
+        cell_target_wave<S, U, CM>(L, cs, ph, e, a);
+        if (lane_id() == 0) write_params(params + (size_t)c * NPARAM, cs, a);
+        phibar_points<S, U>(L, (size_t)cell_slot[c] * L.stride, e, cs.alpha, cs.beta);
     }
 }
 
@@ -1512,10 +1693,11 @@ int variant_count() { return N_VARIANTS; }
     } while (0)
 
 hipError_t launch_cell_prep(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
-                            int n_cells, Phys ph, double* params, const double* cmom, int CH, int var) {
+                            const int* order, int n_cells, Phys ph, double* params, const double* cmom, int CH,
+                            int var) {
     if (n_cells <= 0) return hipSuccess;
     MLVS_DISPATCH_VC(prec, var, ph.compat, k_cell_prep, dim3(grid_for(n_cells, GW)), dim3(GBS), 0, st, lv, cell_lev,
-                     cell_slot, n_cells, ph, params, cmom, CH);
+                     cell_slot, order, n_cells, ph, params, cmom, CH);
     return hipGetLastError();
 }
 
@@ -1562,12 +1744,32 @@ hipError_t launch_face_target(int prec, hipStream_t st, const LevelDesc* lv, con
     return hipGetLastError();
 }
 
+hipError_t launch_face_full(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
+                            const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
+                            const BCDev* bcs, Phys ph, double* fpar, int var) {
+    if (n <= 0) return hipSuccess;
+    MLVS_DISPATCH_VC(prec, var, ph.compat, k_face_full, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot,
+                     cell_nbr, geom, params, bcs, ph, fpar);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_cell(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
+                              const int* cell_slot, const int* order, int n_cells, const CellGeom* geom,
+                              const int* cell_frow, const FaceItem* items, const double* fpar, double* params,
+                              Phys ph, double* cmom, int var) {
+    if (n_cells <= 0) return hipSuccess;
+    MLVS_DISPATCH_VC(prec, var, ph.compat, k_update_cell, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev,
+                     cell_slot, order, n_cells, geom, cell_frow, items, fpar, params, ph, cmom);
+    return hipGetLastError();
+}
+
 hipError_t launch_update(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
-                         int n_cells, const CellGeom* geom, const int* cell_frow, const FaceItem* items,
-                         const double* fpar, const double* params, Phys ph, double* cmom, int CH, int nch, int var) {
+                         const int* order, int n_cells, const CellGeom* geom, const int* cell_frow,
+                         const FaceItem* items, const double* fpar, const double* params, Phys ph, double* cmom,
+                         int CH, int nch, int var) {
     if (n_cells <= 0) return hipSuccess;
     MLVS_DISPATCH_V(prec, var, k_update, dim3(grid_for(n_cells * nch)), dim3(BS), 0, st, lv, cell_lev, cell_slot,
-                    n_cells, geom, cell_frow, items, fpar, params, ph, cmom, CH, nch);
+                    order, n_cells, geom, cell_frow, items, fpar, params, ph, cmom, CH, nch);
     return hipGetLastError();
 }
 

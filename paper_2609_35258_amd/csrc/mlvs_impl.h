@@ -109,9 +109,10 @@ struct RemapItem {     // cell moved from an old level to a new one
 
 // Launch wrappers (kernels.hip).  `S` selects float (32) or double (64) storage.
 int variant_count();
+// order: the cells in traversal order (a permutation of 0..n_cells-1)
 hipError_t launch_cell_prep(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
-                            const int* cell_slot, int n_cells, Phys ph, double* params, const double* cmom,
-                            int CH, int var = 1);
+                            const int* cell_slot, const int* order, int n_cells, Phys ph, double* params,
+                            const double* cmom, int CH, int var = 1);
 hipError_t launch_raw_moments(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
                               const int* cell_slot, int n_cells, const double* params, double* cmom, int CH,
                               int nch);
@@ -126,10 +127,20 @@ hipError_t launch_face_target(int prec, hipStream_t st, const LevelDesc* lv, con
 hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFaceItem* items, int n,
                         const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
                         const double* params, Phys ph, unsigned long long* neg, int var = 1);
+// Fused forms for level sets that fit one velocity chunk: reconstruction +
+// target in one wave per face; update + the next step's cell stage in one
+// wave per cell.
+hipError_t launch_face_full(int prec, hipStream_t st, const LevelDesc* lv, const FaceItem* items, int n,
+                            const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
+                            const BCDev* bcs, Phys ph, double* fpar, int var = 1);
+hipError_t launch_update_cell(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
+                              const int* cell_slot, const int* order, int n_cells, const CellGeom* geom,
+                              const int* cell_frow, const FaceItem* items, const double* fpar, double* params,
+                              Phys ph, double* cmom, int var = 1);
 hipError_t launch_update(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
-                         const int* cell_slot, int n_cells, const CellGeom* geom, const int* cell_frow,
-                         const FaceItem* items, const double* fpar, const double* params, Phys ph, double* cmom,
-                         int CH, int nch, int var = 1);
+                         const int* cell_slot, const int* order, int n_cells, const CellGeom* geom,
+                         const int* cell_frow, const FaceItem* items, const double* fpar, const double* params,
+                         Phys ph, double* cmom, int CH, int nch, int var = 1);
 hipError_t launch_init_eq(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
                           const int* cell_slot, int n_cells, const double* rho_u_v_T, Phys ph,
                           double* params);
