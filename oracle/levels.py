@@ -172,6 +172,46 @@ def mapping_correct4(lev: Level, gp, hp, target, T_tar, R, K, D=2):
     return gp + dg, hp + cK * R * T_tar * dg
 
 
+def mapping_correct_exp(lev: Level, gp, hp, target, tol=1e-14, max_iter=30):
+    """Exponential moment-constrained correction (Sec. 3.3, Eq.
+    exponential_moment_correction), the sign-preserving alternative to the
+    linear correction the paper proposes for when the linear one turns a
+    nonnegative provisional distribution negative.
+
+    g* = g^p exp(a . phi), h* = h^p exp(a . phi), phi = [1, xi_x, xi_y,
+    |xi|^2], with a chosen so that the four mapped moments (mass, momentum,
+    total energy, Eq. mapping_four_targets) equal the target.  The system
+    F(a) = moments4(g^p e^{a.phi}, h^p e^{a.phi}) - target = 0 is solved by
+    Newton's method from a = 0, with the Jacobian
+        J_km = sum_i w_i (psi_k g^p_i + psi^h_k h^p_i) e^{a.phi_i} phi_m(xi_i),
+    psi = [1, xi_x, xi_y, |xi|^2/2], psi^h = [0, 0, 0, 1/2].  The iteration
+    stops when every |F_k| <= tol * S_k, S_k = sum_i w_i |psi_k g^p_i +
+    psi^h_k h^p_i| e^{a.phi_i} (the size of the terms summed), or after
+    max_iter steps.  Returns (g*, h*, a, converged).
+    """
+    xi, w = lev.xi, lev.w
+    x2 = np.sum(xi * xi, axis=1)
+    one = np.ones_like(x2)
+    phi = np.column_stack([one, xi[:, 0], xi[:, 1], x2])
+    psig = np.column_stack([one, xi[:, 0], xi[:, 1], 0.5 * x2])
+    psih = np.column_stack([0.0 * one, 0.0 * one, 0.0 * one, 0.5 * one])
+    tgt = np.asarray(target, float)[:4]
+    a = np.zeros(4)
+    converged = False
+    for _ in range(max_iter + 1):
+        e = np.exp(phi @ a)
+        kern = (psig * (w * gp * e)[:, None] + psih * (w * hp * e)[:, None])     # (N, 4)
+        F = kern.sum(axis=0) - tgt
+        S = np.abs(kern).sum(axis=0)
+        if np.all(np.abs(F) <= tol * S):
+            converged = True
+            break
+        J = kern.T @ phi
+        a = a - np.linalg.solve(J, F)
+    e = np.exp(phi @ a)
+    return gp * e, hp * e, a, converged
+
+
 def moments9(xi, w, g, h):
     """(rho, rho u, rho v, rho E, Gxx, Gyy, Gxy, Jx, Jy) (Eqs. mapping_nine_targets,
     source_second_raw_moments, source_energy_flux_moments)."""

@@ -66,7 +66,7 @@ def van_leer(a, b):
 class Solver:
     def __init__(self, problem, compat: int = 4, face_compat: bool = True,
                  adapt: Optional[AdaptParams] = None, dt: Optional[float] = None,
-                 map_moments: int = 4):
+                 map_moments: int = 4, positivity: str = "keep"):
         self.p = problem
         self.mesh = Mesh(problem)
         self.D = problem.dim
@@ -77,6 +77,16 @@ class Solver:
         self.compat = compat
         self.face_compat = face_compat
         self.map_moments = map_moments
+        # positivity check after a distribution mapping (reading R22): "keep"
+        # counts violations and keeps the linear result; "exp" replaces it by
+        # the exponential correction (level switches and neighbour rows)
+        if positivity not in ("keep", "exp"):
+            raise ValueError("positivity must be 'keep' or 'exp'")
+        if positivity == "exp" and map_moments != 4:
+            raise ValueError("the exponential fallback restores the four conserved moments (map_moments 4)")
+        self.positivity = positivity
+        self.exp_count = 0
+        self.exp_fail = 0
         xi, w, nx, ny = base_grid(problem)
         self.xi_base_D = xi
         xi2 = xi if self.D == 2 else np.column_stack([xi[:, 0], np.zeros(len(xi))])
@@ -156,8 +166,10 @@ class Solver:
             self.iface_cache[key] = lv.Level(self.base, lv.interface_kappa(ka, kb))
         return self.iface_cache[key]
 
-    def map_pair(self, src, dst, g, h, T_tar, target=None):
-        """Projection + linear mapping correction (targets = source moments by default)."""
+    def map_pair(self, src, dst, g, h, T_tar, target=None, fallback=False):
+        """Projection + linear mapping correction (targets = source moments by
+        default); fallback: distribution maps that may take the exponential
+        correction when the linear one breaks positivity."""
         gp, hp = lv.project(src, dst, g, h)
         if target is None:
             target = lv.moments4(src.xi, src.w, g, h) if self.map_moments == 4 else lv.moments9(src.xi, src.w, g, h)
@@ -169,7 +181,26 @@ class Solver:
             gs, hs = lv.mapping_correct9(dst, gp, hp, target)
         if np.min(gs) < 0 <= np.min(gp):
             self.neg_count += 1
+        if fallback:
+            gs, hs = self.positivity_fallback(dst, gp, hp, gs, hs, target)
         return gs, hs
+
+    def positivity_fallback(self, dst, gp, hp, gs, hs, target):
+        """Exponential correction in place of a linear one that made a
+        nonnegative provisional g^p negative somewhere (positivity mode "exp";
+        h* = h^p e^{a.phi} keeps the sign of h^p, which the projection itself
+        can make negative).  A Newton iteration that does not converge keeps
+        the linear result and is counted."""
+        if self.positivity != "exp":
+            return gs, hs
+        if np.min(gp) < 0 or np.min(gs) >= 0:
+            return gs, hs
+        ge, he, _, ok = lv.mapping_correct_exp(dst, gp, hp, target[:4])
+        if not ok:
+            self.exp_fail += 1
+            return gs, hs
+        self.exp_count += 1
+        return ge, he
 
     # -- adaptation -------------------------------------------------------------
     def set_levels(self, kappas, cell_level):
@@ -194,8 +225,11 @@ class Solver:
             else:
                 gs, hs = lv.mapping_correct9(new, gp, hp, lv.moments9(old.xi, old.w, g, h))
             if np.min(gs) < 0 <= np.min(gp):
-                # positivity check: counted, the corrected (conservative) values are kept
+                # positivity check: counted; the linear result is kept unless
+                # the exponential fallback is on
                 self.neg_count += 1
+            if self.map_moments == 4:
+                gs, hs = self.positivity_fallback(new, gp, hp, gs, hs, lv.moments4(old.xi, old.w, g, h))
             self.g[c], self.h[c] = gs, hs
         self.levels = new_levels
         self.cell_level = new_cell_level
@@ -240,7 +274,7 @@ class Solver:
         if lc == ln or self.D == 1:
             return self.fbp[n]
         src, dst = self.levels[ln], self.levels[lc]
-        return self.map_pair(src, dst, self.fbp[n][0], self.fbp[n][1], self.cst[n][2])
+        return self.map_pair(src, dst, self.fbp[n][0], self.fbp[n][1], self.cst[n][2], fallback=True)
 
     def slope_stage(self):
         """Limited gradient sigma of phi_bar+ per cell on its native level."""

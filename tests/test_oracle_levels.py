@@ -340,3 +340,54 @@ def test_cluster_hand_example():
     assert len(reps) == 2
     assert list(reps[0]) == [3, 2] and list(reps[1]) == [0, 0]
     assert list(cl) == [0, 0, 1, 0]
+
+
+# ---------------------------------------------------------------------------
+# exponential moment-constrained correction (positivity fallback)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [3, 11])
+def test_exp_correction_maps_maxwellian_to_shifted_maxwellian(seed):
+    """With the temperature fixed, M(rho2, u2)/M(rho1, u1) = exp of a linear
+    function of xi: the exponential correction of the discrete M1 to the
+    discrete moments of M2 must return M2 at every point, with the closed-form
+    coefficients a0 = ln(rho2/rho1) - (|u2|^2 - |u1|^2)/(2RT), (a1, a2) =
+    (u2 - u1)/(RT), a3 = 0."""
+    base = _base(32)
+    L = lv.Level(base, _kappa(base, seed))
+    R, T, K = 0.5, 1.1, 1
+    cK = 3.0 - 2 + K
+    u1, u2 = np.array([0.3, -0.2]), np.array([0.45, 0.1])
+    rho1, rho2 = 1.0, 1.3
+    g1, _ = kin.maxwell(L.xi, rho1, u1, T, R, K)
+    g2, _ = kin.maxwell(L.xi, rho2, u2, T, R, K)
+    h1, h2 = cK * R * T * g1, cK * R * T * g2
+    tgt = lv.moments4(L.xi, L.w, g2, h2)
+    gs, hs, a, ok = lv.mapping_correct_exp(L, g1, h1, tgt)
+    assert ok
+    assert np.max(np.abs(gs - g2)) <= 1e-11 * np.max(g2)
+    assert np.max(np.abs(hs - h2)) <= 1e-11 * np.max(h2)
+    a_ref = [math.log(rho2 / rho1) - (u2 @ u2 - u1 @ u1) / (2 * R * T), (u2[0] - u1[0]) / (R * T),
+             (u2[1] - u1[1]) / (R * T), 0.0]
+    assert np.allclose(a, a_ref, rtol=0, atol=1e-10)
+
+
+def test_exp_correction_hits_targets_keeps_sign_and_is_noop_on_its_own_moments():
+    base = _base(32)
+    L = lv.Level(base, _kappa(base, 5))
+    g, h = random_positive_rows(9, 2, L.N)
+    g = g * np.exp(-0.05 * np.sum(L.xi ** 2, axis=1))
+    h = h * np.exp(-0.05 * np.sum(L.xi ** 2, axis=1))
+    m0 = lv.moments4(L.xi, L.w, g, h)
+    gs, hs, a, ok = lv.mapping_correct_exp(L, g, h, m0)
+    assert ok and np.array_equal(a, np.zeros(4)) and np.array_equal(gs, g) and np.array_equal(hs, h)
+    tgt = m0 * np.array([1.02, 1.0, 1.0, 0.99]) + np.array([0.0, 0.03 * m0[0], -0.02 * m0[0], 0.0])
+    gs, hs, a, ok = lv.mapping_correct_exp(L, g, h, tgt)
+    assert ok
+    assert np.allclose(lv.moments4(L.xi, L.w, gs, hs), tgt, rtol=1e-13, atol=1e-14 * abs(tgt[0]))
+    assert np.all(gs > 0) and np.all(hs > 0)
+    # a zero provisional value stays zero
+    g0 = g.copy()
+    g0[::7] = 0.0
+    gz, _, _, ok = lv.mapping_correct_exp(L, g0, h, lv.moments4(L.xi, L.w, g0, h) * np.array([1.01, 1, 1, 1]))
+    assert ok and np.all(gz[::7] == 0.0) and np.all(gz >= 0)

@@ -223,3 +223,29 @@ def test_runtime_model_fit_reproduces_paper():
     assert np.allclose(est, model, atol=0.15)
     wins, thr = costmodel.multilevel_wins(714.698 / 7921, 1033 / 7921, 537 / 10176, 0.30264)
     assert wins and abs(thr - 0.133) < 1e-3
+
+
+def test_exponential_positivity_fallback_on_level_switches_and_neighbour_rows():
+    """Positivity mode "exp": level switches whose linear correction turns a
+    nonnegative g negative take the exponential correction instead; the
+    switched state is then nonnegative, the conserved totals stay exact to
+    round-off, and mode "keep" on the same switch leaves negative values."""
+    p = W.perturb(W.periodic_box(10, 4, Lx=1.0, Ly=0.4, Kn=0.05, nv=24, vmax=5.0, kind="sine", amp=0.5), seed=2)
+    nb = p.nv // 2
+    kap = [np.zeros(nb * nb, np.uint8)] + [W.random_kappa(nb, nb, 7 + k) for k in range(2)]
+    cl = W.striped_levels(p.ni, p.nj, 3, 1)
+    keep = Solver(p, compat=4, positivity="keep")
+    keep.set_levels(kap, cl)
+    assert keep.neg_count > 0 and min(np.min(g) for g in keep.g) < 0
+    o = Solver(p, compat=4, positivity="exp")
+    t0 = o.totals()
+    o.set_levels(kap, cl)
+    assert o.exp_count == keep.neg_count and o.exp_fail == 0
+    assert min(np.min(g) for g in o.g) >= 0
+    assert np.max(np.abs(o.totals() - t0)) < 1e-14 * np.max(np.abs(t0))
+    n0 = o.exp_count
+    o.step()                                   # neighbour rows mapped across levels
+    assert o.exp_count > n0
+    assert np.max(np.abs(o.totals() - t0)) < 1e-14 * np.max(np.abs(t0))
+    with pytest.raises(ValueError):
+        Solver(p, compat=4, positivity="exp", map_moments=9)
