@@ -80,12 +80,23 @@ typedef struct {
  *             four moments (mass, momentum, energy; Eqs. raw_four_g_basis,
  *             raw_four_gh_coupling) or nine (also the second g moments and the
  *             energy flux; Eqs. raw_six_g_basis, raw_three_h_basis,
- *             mapping_h_residual_correction).  9 needs dim = 2. */
+ *             mapping_h_residual_correction).  9 needs dim = 2.
+ *  positivity 0 or 1: what a level switch or a neighbour row does when its
+ *             linear mapping correction turns a nonnegative provisional g
+ *             negative somewhere (Sec. 3.3, the positivity check after the
+ *             correction): 0 keeps the linear result (counted, see
+ *             mlvs_neg_count); 1 replaces it by the exponential
+ *             moment-constrained correction g* = g^p exp(a . phi), h* = h^p
+ *             exp(a . phi), phi = [1, xi_x, xi_y, |xi|^2], with a from Newton's
+ *             method on the four conserved moments (Eq.
+ *             exponential_moment_correction; see mlvs_positivity_counts).
+ *             1 needs map_moments = 4. */
 typedef struct {
     int dim, K;
     double R, Pr, omega, mu_ref, T_ref;
     double dt, cfl;
     int precision, compat, face_compat, map_moments;
+    int positivity;
 } mlvs_physics;
 
 /* Structured mesh: node coordinates row-major by j, (nj+1) x (ni+1) values
@@ -253,6 +264,11 @@ mlvs_status mlvs_memory(mlvs_ctx ctx, size_t* device_bytes);
 /* Number of corrections since creation whose result had a negative g where
  * the provisional distribution had none (positivity check; values kept). */
 mlvs_status mlvs_neg_count(mlvs_ctx ctx, int64_t* count);
+
+/* Exponential fallbacks (positivity = 1) since creation: maps that took the
+ * exponential correction, and maps whose Newton iteration did not converge
+ * (those keep the linear result). */
+mlvs_status mlvs_positivity_counts(mlvs_ctx ctx, int64_t* applied, int64_t* failed);
 
 /* ---- learned level selector ------------------------------------------------
  * Network 10 -> 64 -> 64 -> K (ReLU, softmax), parameters as float in the

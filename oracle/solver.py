@@ -185,6 +185,10 @@ class Solver:
             gs, hs = self.positivity_fallback(dst, gp, hp, gs, hs, target)
         return gs, hs
 
+    # values within POS_EPS max|g^p| of zero count as zero in the positivity
+    # check, so that round-off alone never decides between the two corrections
+    POS_EPS = 1e-10
+
     def positivity_fallback(self, dst, gp, hp, gs, hs, target):
         """Exponential correction in place of a linear one that made a
         nonnegative provisional g^p negative somewhere (positivity mode "exp";
@@ -193,7 +197,8 @@ class Solver:
         the linear result and is counted."""
         if self.positivity != "exp":
             return gs, hs
-        if np.min(gp) < 0 or np.min(gs) >= 0:
+        eps = self.POS_EPS * np.max(np.abs(gp))
+        if np.min(gp) < -eps or np.min(gs) >= -eps:
             return gs, hs
         ge, he, _, ok = lv.mapping_correct_exp(dst, gp, hp, target[:4])
         if not ok:

@@ -33,7 +33,8 @@ class mlvs_physics(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("K", ctypes.c_int), ("R", ctypes.c_double), ("Pr", ctypes.c_double),
                 ("omega", ctypes.c_double), ("mu_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
                 ("dt", ctypes.c_double), ("cfl", ctypes.c_double), ("precision", ctypes.c_int),
-                ("compat", ctypes.c_int), ("face_compat", ctypes.c_int), ("map_moments", ctypes.c_int)]
+                ("compat", ctypes.c_int), ("face_compat", ctypes.c_int), ("map_moments", ctypes.c_int),
+                ("positivity", ctypes.c_int)]
 
 
 class mlvs_mesh(ctypes.Structure):
@@ -119,6 +120,8 @@ _PROTOS = {
                                        _c_double_p]),
     "mlvs_step_stages": (ctypes.c_int, [ctypes.c_void_p, _c_int32_p, ctypes.POINTER(ctypes.c_int)]),
     "mlvs_neg_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "mlvs_positivity_counts": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.POINTER(ctypes.c_int64)]),
     "mlvs_mlp_nparams": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
     "mlvs_features": (ctypes.c_int, [ctypes.c_void_p, _c_float_p]),
     "mlvs_labels": (ctypes.c_int, [ctypes.c_void_p, _c_int32_p]),
@@ -241,7 +244,7 @@ class Solver:
                  bc_imin, bc_imax, bc_jmin, bc_jmax, vx, vwx, vy, vwy, R: float, Pr: float, K: int,
                  omega: float, mu_ref: float, T_ref: float, cfl: float, dt: float = 0.0,
                  precision: int = 64, compat: int = 4, face_compat: bool = True, map_moments: int = 4,
-                 adapt: Optional[dict] = None, device=None, graph: bool = False):
+                 adapt: Optional[dict] = None, device=None, graph: bool = False, positivity: str = "keep"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the MLVS library runs on the device only")
@@ -285,8 +288,10 @@ class Solver:
         mesh = mlvs_mesh(ni, nj, _dp(keep(node_x)), _dp(keep(node_y)), int(periodic_i), int(periodic_j),
                          i32(bc_imin), i32(bc_imax), i32(bc_jmin), i32(bc_jmax), len(bcs), bc_arr)
         vg = mlvs_vgrid(len(vx), len(vy), _dp(keep(vx)), _dp(keep(vwx)), _dp(keep(vy)), _dp(keep(vwy)))
+        if positivity not in ("keep", "exp"):
+            raise ValueError("positivity must be 'keep' or 'exp'")
         phys = mlvs_physics(dim, K, R, Pr, omega, mu_ref, T_ref, dt, cfl, precision, compat, int(face_compat),
-                            map_moments)
+                            map_moments, 1 if positivity == "exp" else 0)
         ap = None
         if adapt is not None:
             ap = mlvs_adapt_params(adapt["C_split"], adapt["C_merge"], adapt.get("eps_merge", 0.0),
@@ -311,7 +316,8 @@ class Solver:
 
     @classmethod
     def from_problem(cls, p, precision: int = 64, compat: int = 4, face_compat: bool = True,
-                     map_moments: int = 4, adapt: Optional[dict] = None, dt: float = 0.0, graph: bool = False):
+                     map_moments: int = 4, adapt: Optional[dict] = None, dt: float = 0.0, graph: bool = False,
+                     positivity: str = "keep"):
         """Build from a problem description (attributes as in the workload generators)."""
         if p.vel_kind == "gh":
             x, w = gauss_hermite(p.nv, p.R, p.gh_scale_T)
@@ -326,7 +332,7 @@ class Solver:
                 bcs=p.bcs, bc_imin=p.bc_imin, bc_imax=p.bc_imax, bc_jmin=p.bc_jmin, bc_jmax=p.bc_jmax,
                 vx=x, vwx=w, vy=y, vwy=wy, R=p.R, Pr=p.Pr, K=p.K, omega=p.omega, mu_ref=mu, T_ref=p.T_ref,
                 cfl=p.cfl, dt=dt, precision=precision, compat=compat, face_compat=face_compat,
-                map_moments=map_moments, adapt=adapt, graph=graph)
+                map_moments=map_moments, adapt=adapt, graph=graph, positivity=positivity)
         s.init_equilibrium(np.stack([p.rho0.ravel(), p.u0.ravel(), p.v0.ravel(), p.T0.ravel()], axis=1))
         return s
 
@@ -466,6 +472,12 @@ class Solver:
         v = ctypes.c_int64()
         _check(lib().mlvs_neg_count(self.h, ctypes.byref(v)))
         return v.value
+
+    def positivity_counts(self):
+        """(maps that took the exponential correction, maps whose Newton iteration failed)."""
+        a, f = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().mlvs_positivity_counts(self.h, ctypes.byref(a), ctypes.byref(f)))
+        return a.value, f.value
 
     def close(self):
         if getattr(self, "h", None):

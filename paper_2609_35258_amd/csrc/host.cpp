@@ -1640,6 +1640,9 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         if (phys->map_moments != 0 && phys->map_moments != 4 && phys->map_moments != 9)
             fail(MLVS_E_ARG, "map_moments must be 0, 4 or 9");
         if (phys->map_moments == 9 && phys->dim != 2) fail(MLVS_E_ARG, "map_moments 9 needs dim = 2");
+        if (phys->positivity != 0 && phys->positivity != 1) fail(MLVS_E_ARG, "positivity must be 0 or 1");
+        if (phys->positivity == 1 && phys->map_moments != 4)
+            fail(MLVS_E_ARG, "the exponential fallback needs map_moments = 4");
         if (!(phys->R > 0) || !(phys->mu_ref > 0) || !(phys->T_ref > 0)) fail(MLVS_E_ARG, "bad physical constants");
         if (mesh->ni < 1 || mesh->nj < 1 || !mesh->node_x || !mesh->node_y) fail(MLVS_E_ARG, "bad mesh");
         if (phys->dim == 1 && mesh->nj != 1) fail(MLVS_E_ARG, "1-D meshes need nj = 1");
@@ -1686,6 +1689,7 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         ph.mu_ref = phys->mu_ref; ph.T_ref = phys->T_ref;
         ph.dt = phys->dt > 0 ? phys->dt : phys->cfl * c->mesh.hmin / vmax;
         ph.compat = phys->compat; ph.face_compat = phys->face_compat; ph.map_moments = phys->map_moments;
+        ph.positivity = phys->positivity;
         // device geometry
         c->d_geom = upload(c->dm, c->mesh.geom, c->st);
         c->d_nbr_cell = upload(c->dm, c->mesh.nbr, c->st);
@@ -1697,8 +1701,9 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         c->d_bcs = upload(c->dm, bd, c->st);
         c->d_params = static_cast<double*>(c->dm.alloc(sizeof(double) * NPARAM * c->mesh.n_cells));
         hip_check(hipMemsetAsync(c->d_params, 0, sizeof(double) * NPARAM * c->mesh.n_cells, c->st), "memset");
-        c->d_neg = static_cast<unsigned long long*>(c->dm.alloc(8));
-        hip_check(hipMemsetAsync(c->d_neg, 0, 8, c->st), "memset");
+        // counters: [0] positivity violations, [1] exponential fallbacks, [2] failed ones
+        c->d_neg = static_cast<unsigned long long*>(c->dm.alloc(24));
+        hip_check(hipMemsetAsync(c->d_neg, 0, 24, c->st), "memset");
         // velocity chunk of the streaming stages (MLVS_CHUNK overrides; multiple of 64)
         if (const char* e = std::getenv("MLVS_FUSE")) c->fuse_allowed = std::atoi(e) != 0;
         if (const char* e = std::getenv("MLVS_CHUNK")) {
@@ -1937,6 +1942,17 @@ mlvs_status mlvs_memory(mlvs_ctx c, size_t* bytes) {
     return guarded([&] {
         if (!c || !bytes) fail(MLVS_E_ARG, "null argument");
         *bytes = c->dm.bytes;
+    });
+}
+
+mlvs_status mlvs_positivity_counts(mlvs_ctx c, int64_t* applied, int64_t* failed) {
+    return guarded([&] {
+        if (!c || !applied || !failed) fail(MLVS_E_ARG, "null argument");
+        unsigned long long v[3] = {0, 0, 0};
+        hip_check(hipMemcpyAsync(v, c->d_neg, 24, hipMemcpyDeviceToHost, c->st), "D2H");
+        sync(c);
+        *applied = (int64_t)v[1];
+        *failed = (int64_t)v[2];
     });
 }
 

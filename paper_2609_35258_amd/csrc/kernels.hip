@@ -82,6 +82,20 @@ __device__ __forceinline__ void wave_sum(double (&v)[NV]) {
     }
 }
 
+// Maximum of NV doubles over the wavefront (all lanes active), same exchanges.
+template <int NV>
+__device__ __forceinline__ void wave_max(double (&v)[NV]) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+        x = fmax(x, dpp_mov<0xB1>(x));
+        x = fmax(x, dpp_mov<0x4E>(x));
+        x = fmax(x, dpp_mov<0x141>(x));
+        x = fmax(x, dpp_mov<0x140>(x));
+        v[k] = fmax(fmax(read_lane(x, 0), read_lane(x, 16)), fmax(read_lane(x, 32), read_lane(x, 48)));
+    }
+}
+
 // Device buffers reached through the level descriptors are global memory; the
 // address-space cast lets the compiler use global (not flat) loads and stores.
 template <typename T>
@@ -687,6 +701,66 @@ __device__ __forceinline__ void acc_m9(double* m, double w, double x, double y, 
 // energy and energy-flux residuals left by dg.
 struct MapCoef { double a[6], b[3]; bool nine; };
 
+// Exponential moment-constrained correction (Sec. 3.3, Eq.
+// exponential_moment_correction) of a provisional pair held in the rows:
+// g* = g^p e^{a.phi}, h* = h^p e^{a.phi}, phi = [1, x, y, x^2 + y^2], with a
+// from Newton's method from a = 0 on the four conserved moments
+// F_k(a) = sum w (psi_k g^p + psi^h_k h^p) e^{a.phi} - tgt_k, psi = [1, x, y,
+// |xi|^2/2], psi^h = [0, 0, 0, 1/2], Jacobian J_km = sum w (psi_k g^p +
+// psi^h_k h^p) e^{a.phi} phi_m.  Converged when every |F_k| <= 1e-14 S_k, S_k
+// the sum of the terms' magnitudes; then the rows are rewritten and true is
+// returned; otherwise (after EXP_MAXIT steps) the rows are left as they were.
+constexpr int EXP_MAXIT = 30;
+constexpr double POS_EPS = 1e-10;
+template <typename S>
+__device__ bool map_exp(const LevelDesc& D, gptr<S> gdst, gptr<S> hdst, const double* tgt) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    bool ok = false;
+    for (int it = 0; it <= EXP_MAXIT; ++it) {
+        double s[24];                      // F[4], S[4], J[4][4]
+#pragma unroll
+        for (int k = 0; k < 24; ++k) s[k] = 0.0;
+        for (int i = lane_id(); i < D.N; i += WL) {
+            const double x = gp(D.xi_x)[i], y = gp(D.xi_y)[i], w = gp(D.w)[i];
+            const double x2 = x * x + y * y;
+            const double e = exp(a[0] + a[1] * x + a[2] * y + a[3] * x2);
+            const double wg = w * (double)gdst[i] * e, wh = w * (double)hdst[i] * e;
+            const double k4[4] = {wg, wg * x, wg * y, 0.5 * x2 * wg + 0.5 * wh};
+            const double ph4[4] = {1.0, x, y, x2};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                s[k] += k4[k];
+                s[4 + k] += fabs(k4[k]);
+#pragma unroll
+                for (int mm = 0; mm < 4; ++mm) s[8 + 4 * k + mm] += k4[k] * ph4[mm];
+            }
+        }
+        wave_sum<24>(s);
+        double F[4], J[4][4];
+        bool conv = true;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            F[k] = s[k] - tgt[k];
+            conv = conv && fabs(F[k]) <= 1e-14 * s[4 + k];
+#pragma unroll
+            for (int mm = 0; mm < 4; ++mm) J[k][mm] = s[8 + 4 * k + mm];
+        }
+        if (conv) { ok = true; break; }
+        if (it == EXP_MAXIT) break;
+        solve_fixed<4>(J, F);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] = uni(a[k] - F[k]);
+    }
+    if (!ok) return false;
+    for (int i = lane_id(); i < D.N; i += WL) {
+        const double x = gp(D.xi_x)[i], y = gp(D.xi_y)[i];
+        const double e = exp(a[0] + a[1] * x + a[2] * y + a[3] * (x * x + y * y));
+        gdst[i] = (S)((double)gdst[i] * e);
+        hdst[i] = (S)((double)hdst[i] * e);
+    }
+    return true;
+}
+
 __device__ __forceinline__ MapCoef map_coeffs(const LevelDesc& D, const double* dM, double Ttar, const Phys& ph) {
     MapCoef m{};
     m.nine = ph.map_moments == 9;
@@ -737,8 +811,33 @@ __device__ __forceinline__ void map_delta(const MapCoef& m, double x, double y, 
 
 template <typename S>
 __device__ __forceinline__ void map_correct_apply(const LevelDesc& D, gptr<S> gdst, gptr<S> hdst, const double* dM,
-                                                  double Ttar, const Phys& ph, int& negflag) {
+                                                  const double* tgt, double Ttar, const Phys& ph, int& negflag,
+                                                  unsigned long long* cnt) {
     const MapCoef mc = map_coeffs(D, dM, Ttar, ph);
+    if (ph.positivity) {
+        // positivity check of the linear result before it is written: a
+        // nonnegative provisional g turned negative takes the exponential
+        // correction (the rows still hold the provisional pair)
+        // (values within POS_EPS max|g^p| of zero count as zero, so that
+        // round-off alone never decides between the two corrections)
+        double v[3] = {0.0, -1e300, -1e300};      // max |g^p|, -min g^p, -min g_lin
+        for (int i = lane_id(); i < D.N; i += WL) {
+            double dg, dh;
+            map_delta(mc, gp(D.xi_x)[i], gp(D.xi_y)[i], dg, dh);
+            const S gprov = gdst[i];
+            v[0] = fmax(v[0], fabs((double)gprov));
+            v[1] = fmax(v[1], -(double)gprov);
+            v[2] = fmax(v[2], -(double)(S)((double)gprov + dg));
+        }
+        wave_max<3>(v);
+        const double eps = POS_EPS * v[0];
+        if (v[1] <= eps && v[2] > eps) {
+            negflag = 1;
+            const bool ok = map_exp<S>(D, gdst, hdst, tgt);
+            if (lane_id() == 0) atomicAdd(cnt + (ok ? 1 : 2), 1ull);
+            if (ok) return;
+        }
+    }
     for (int i = lane_id(); i < D.N; i += WL) {
         const double x = gp(D.xi_x)[i], y = gp(D.xi_y)[i];
         double dg, dh;
@@ -792,7 +891,7 @@ __global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs,
         if (ph.map_moments) {
             double dM[9];
             for (int k = 0; k < 9; ++k) dM[k] = m[k] - m[9 + k];
-            map_correct_apply<S>(Ld, dg, dh, dM, params[(size_t)G.n * NPARAM + P_T], ph, nf);
+            map_correct_apply<S>(Ld, dg, dh, dM, m, params[(size_t)G.n * NPARAM + P_T], ph, nf, neg);
         }
         nf = __any(nf);
         if (lane_id() == 0 && nf) atomicAdd(neg, 1ull);
@@ -1627,7 +1726,7 @@ __global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv,
             const double T = (2.0 * m[3] / rho - (u * u + v * v)) / ((3.0 + ph.K) * ph.R);
             double dM[9];
             for (int k = 0; k < 9; ++k) dM[k] = m[k] - m[9 + k];
-            map_correct_apply<S>(Ld, dg, dh, dM, T, ph, nf);
+            map_correct_apply<S>(Ld, dg, dh, dM, m, T, ph, nf, neg);
         }
         nf = __any(nf);
         if (lane_id() == 0 && nf) atomicAdd(neg, 1ull);

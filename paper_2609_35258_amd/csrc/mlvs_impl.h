@@ -63,6 +63,7 @@ struct Phys {
     int D, K;
     double R, Pr, omega, mu_ref, T_ref, dt;
     int compat, face_compat, map_moments;
+    int positivity;                 // 1: exponential fallback of distribution maps
 };
 
 // Encoded neighbour: >= 0 same-level cell id; -1 none (boundary);

@@ -148,3 +148,38 @@ def test_adaptive_run_matches_oracle(chunk, map_moments, monkeypatch):
     assert len(o.levels) >= 2
     assert np.max(np.abs(g.totals() - t0)) < 1e-13
     g.close()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_exponential_positivity_fallback_matches_oracle(precision):
+    """Positivity mode "exp": level switches and neighbour rows whose linear
+    correction turns a nonnegative g negative take the exponential correction
+    (Newton on the four conserved moments) on both sides; the switched state
+    is nonnegative and matches the oracle, totals stay exact."""
+    p = W.perturb(W.periodic_box(10, 4, Lx=1.0, Ly=0.4, Kn=0.05, nv=24, vmax=5.0, kind="sine", amp=0.5), seed=2)
+    print("case exp fallback", precision, flush=True)
+    nb = p.nv // 2
+    kap = np.stack([np.zeros(nb * nb, np.uint8)] + [W.random_kappa(nb, nb, 7 + k) for k in range(2)])
+    cl = W.striped_levels(p.ni, p.nj, 3, 1)
+    o = Oracle(p, compat=4, positivity="exp")
+    g = _gpu(p, precision=precision, compat=4, positivity="exp")
+    t0 = g.totals()
+    o.set_levels(list(kap), cl)
+    g.set_levels(kap, cl)
+    applied, failed = g.positivity_counts()
+    assert failed == 0 and applied > 0
+    if precision == 64:
+        assert applied == o.exp_count
+    st = g.get_state()
+    assert min(np.min(x[0]) / np.max(x[0]) for x in st) >= -o.POS_EPS
+    tol = TOL if precision == 64 else 1e-5
+    e = state_error(st, o.g, o.h)
+    assert max(e) < tol, ("switch", e)
+    for k in range(3):
+        o.step()
+        g.step(1)
+        e = state_error(g.get_state(), o.g, o.h)
+        assert max(e) < (TOL if precision == 64 else 2e-5), (k, e)
+    assert g.positivity_counts()[0] > applied
+    assert np.max(np.abs(g.totals() - t0)) < (1e-13 if precision == 64 else 1e-5 * np.max(np.abs(t0)))
+    g.close()
