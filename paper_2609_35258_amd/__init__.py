@@ -388,6 +388,15 @@ class Solver:
         off = np.concatenate([[0], np.cumsum(n)])
         return [(g[off[c]:off[c + 1]], h[off[c]:off[c + 1]]) for c in range(self.n_cells)]
 
+    def get_cell(self, cell: int):
+        """(g, h) of one cell on its level, FP64 on the host (synchronises)."""
+        n = ctypes.c_int32()
+        _check(lib().mlvs_get_f(self.h, int(cell), None, None, ctypes.byref(n)))
+        g = np.zeros(n.value)
+        h = np.zeros(n.value)
+        _check(lib().mlvs_get_f(self.h, int(cell), _dp(g), _dp(h), ctypes.byref(n)))
+        return g, h
+
     def set_state(self, gs, hs):
         g = np.ascontiguousarray(np.concatenate(gs), dtype=np.float64)
         h = np.ascontiguousarray(np.concatenate(hs), dtype=np.float64)

@@ -238,6 +238,25 @@ def random_kappa(nbx: int, nby: int, seed: int, p8: float = 0.25, p4: float = 0.
     return k.ravel()
 
 
+def patch(problem: Problem, i0: int, j0: int, ni: int = 5, nj: int = 5) -> Problem:
+    """The ni x nj cells of a structured problem starting at cell (i0, j0), as a
+    problem of its own: the same nodes and physics, outflow on every side, not
+    periodic (initial state: the original one on those cells)."""
+    sl = (slice(j0, j0 + nj), slice(i0, i0 + ni))
+    p = dataclasses.replace(problem)
+    p.X = problem.X[j0:j0 + nj + 1, i0:i0 + ni + 1].copy()
+    p.Y = problem.Y[j0:j0 + nj + 1, i0:i0 + ni + 1].copy()
+    p.periodic_i = p.periodic_j = False
+    p.bcs = [BC(OUTFLOW)]
+    p.bc_imin = np.zeros(nj, np.int32)
+    p.bc_imax = np.zeros(nj, np.int32)
+    p.bc_jmin = np.zeros(ni, np.int32)
+    p.bc_jmax = np.zeros(ni, np.int32)
+    p.rho0, p.u0, p.v0, p.T0 = (problem.rho0[sl].copy(), problem.u0[sl].copy(), problem.v0[sl].copy(),
+                                problem.T0[sl].copy())
+    return p
+
+
 def striped_levels(ni: int, nj: int, n_levels: int, axis: int = 0) -> np.ndarray:
     """Cell -> level index in stripes along one mesh axis (cell c = i + ni*j)."""
     i = np.arange(ni)[None, :].repeat(nj, 0)
