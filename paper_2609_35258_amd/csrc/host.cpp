@@ -220,6 +220,7 @@ struct Level {
     bool geo_in_arena = false;             // device geometry lives in a build's staging block
     // device
     double *d_x = nullptr, *d_y = nullptr, *d_w = nullptr;
+    float* d_xy = nullptr;                 // (xi_x, xi_y) pairs in float, for FP32 storage
     int* d_pt_of_base = nullptr;
     int stride = 0;
     int n_cells = 0, n_rows = 0, n_ghost = 0;
@@ -698,7 +699,16 @@ struct mlvs_ctx_s {
 
 namespace {
 
+// (xi_x, xi_y) pairs rounded to float: the FP32 form's reconstruction and
+// phi_bar+ rows read one 8-byte pair per point instead of two doubles.
+std::vector<float> xy_pairs(const Level& L) {
+    std::vector<float> v(2 * (size_t)L.N);
+    for (int i = 0; i < L.N; ++i) { v[2 * i] = (float)L.xi_x[i]; v[2 * i + 1] = (float)L.xi_y[i]; }
+    return v;
+}
+
 void upload_level_geometry(mlvs_ctx c, Level& L) {
+    L.d_xy = upload(c->dm, xy_pairs(L), c->st);
     L.d_x = upload(c->dm, L.xi_x, c->st);
     L.d_y = upload(c->dm, L.xi_y, c->st);
     L.d_w = upload(c->dm, L.w, c->st);
@@ -708,9 +718,11 @@ void upload_level_geometry(mlvs_ctx c, Level& L) {
 
 void free_level(mlvs_ctx c, Level& L) {
     if (!L.geo_in_arena)
-        for (void* p : {(void*)L.d_x, (void*)L.d_y, (void*)L.d_w, (void*)L.d_pt_of_base}) c->dm.release(p);
+        for (void* p : {(void*)L.d_x, (void*)L.d_y, (void*)L.d_w, (void*)L.d_xy, (void*)L.d_pt_of_base})
+            c->dm.release(p);
     for (void* p : {L.g, L.h, L.fg, L.fh, L.Fg, L.Fh}) c->dm.release(p);
     L.d_x = L.d_y = L.d_w = nullptr;
+    L.d_xy = nullptr;
     L.d_pt_of_base = nullptr;
     L.g = L.h = L.fg = L.fh = L.Fg = L.Fh = nullptr;
 }
@@ -900,13 +912,14 @@ void build_items(mlvs_ctx c) {
         L.Fg = c->dm.alloc(nr); L.Fh = c->dm.alloc(nr);
         L.fg = c->dm.alloc(nf); L.fh = c->dm.alloc(nf);
     }
-    struct GeoOff { size_t x, y, w, ptb; };
+    struct GeoOff { size_t x, y, w, ptb, xy; };
     std::vector<GeoOff> igeo;
     for (auto& Lp : c->ifaces) {
         Level& L = *Lp;
         const size_t nr = (size_t)std::max(L.n_rows, 1) * L.stride * c->elt();
         L.Fg = c->dm.alloc(nr); L.Fh = c->dm.alloc(nr);
-        igeo.push_back({stg.put(L.xi_x), stg.put(L.xi_y), stg.put(L.w), stg.put(L.pt_of_base)});
+        igeo.push_back({stg.put(L.xi_x), stg.put(L.xi_y), stg.put(L.w), stg.put(L.pt_of_base),
+                        stg.put(xy_pairs(L))});
     }
     c->n_faces = (int)faces.size();
     c->n_bfaces = (int)bfaces.size();
@@ -939,6 +952,7 @@ void build_items(mlvs_ctx c) {
         L.d_y = reinterpret_cast<double*>(base + igeo[i].y);
         L.d_w = reinterpret_cast<double*>(base + igeo[i].w);
         L.d_pt_of_base = reinterpret_cast<int*>(base + igeo[i].ptb);
+        L.d_xy = reinterpret_cast<float*>(base + igeo[i].xy);
         L.geo_in_arena = true;
     }
     for (size_t i = 0; i < gitems.size(); ++i) gitems[i].tab = gtab[i].at(base);
@@ -954,7 +968,7 @@ void build_items(mlvs_ctx c) {
         Level& L = level_by_index(c, i);
         LevelDesc d{};
         d.N = L.N; d.stride = L.stride; d.n_rows_state = L.n_cells;
-        d.xi_x = L.d_x; d.xi_y = L.d_y; d.w = L.d_w;
+        d.xi_x = L.d_x; d.xi_y = L.d_y; d.w = L.d_w; d.xy32 = L.d_xy;
         d.g = L.g; d.h = L.h; d.fg = L.fg; d.fh = L.fh; d.Fg = L.Fg; d.Fh = L.Fh;
         std::copy(L.Minv, L.Minv + 16, d.Minv);
         std::copy(L.G6inv, L.G6inv + 36, d.G6inv);
@@ -1042,11 +1056,12 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
     // one staged block: the new levels' geometry (kept with the level set) and
     // the remap's descriptors, tables and work list
     Stage stg;
-    struct GeoOff { size_t x, y, w, ptb; };
+    struct GeoOff { size_t x, y, w, ptb, xy; };
     std::vector<GeoOff> geo;
     for (auto& L : c->levels) {
         L->stride = (L->N + 63) / 64 * 64;
-        geo.push_back({stg.put(L->xi_x), stg.put(L->xi_y), stg.put(L->w), stg.put(L->pt_of_base)});
+        geo.push_back({stg.put(L->xi_x), stg.put(L->xi_y), stg.put(L->w), stg.put(L->pt_of_base),
+                       stg.put(xy_pairs(*L))});
         alloc_state(c, *L);
     }
     std::vector<RemapItem> items(n);
@@ -1085,6 +1100,7 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
         L.d_y = reinterpret_cast<double*>(base + geo[l].y);
         L.d_w = reinterpret_cast<double*>(base + geo[l].w);
         L.d_pt_of_base = reinterpret_cast<int*>(base + geo[l].ptb);
+        L.d_xy = reinterpret_cast<float*>(base + geo[l].xy);
         L.geo_in_arena = true;
     }
     for (int cc = 0; cc < n; ++cc)
@@ -1095,6 +1111,7 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
         for (auto& Lp : ls) {
             LevelDesc x{};
             x.N = Lp->N; x.stride = Lp->stride; x.xi_x = Lp->d_x; x.xi_y = Lp->d_y; x.w = Lp->d_w;
+            x.xy32 = Lp->d_xy;
             x.g = Lp->g; x.h = Lp->h;
             std::copy(Lp->Minv, Lp->Minv + 16, x.Minv);
             std::copy(Lp->G6inv, Lp->G6inv + 36, x.G6inv);

@@ -106,6 +106,22 @@ __device__ __forceinline__ gptr<T> gp(T* p) { return (gptr<T>)p; }
 template <typename S>
 __device__ __forceinline__ gptr<S> rowp(void* base, size_t off) { return gp(reinterpret_cast<S*>(base)) + off; }
 
+// The velocity of point i as the storage precision's kernels read it: FP64
+// storage reads the double coordinates, FP32 storage one (x, y) float pair
+// (half the bytes and one load instead of two; the rounding is that of the
+// stored values).
+template <typename S>
+__device__ __forceinline__ void load_xy(const LevelDesc& L, int i, double& x, double& y) {
+    if constexpr (sizeof(S) == 4) {
+        const unsigned long long b = gp(reinterpret_cast<const unsigned long long*>(L.xy32))[i];
+        x = __uint_as_float((unsigned)b);
+        y = __uint_as_float((unsigned)(b >> 32));
+    } else {
+        x = gp(L.xi_x)[i];
+        y = gp(L.xi_y)[i];
+    }
+}
+
 // Gaussian elimination with partial pivoting on a register-resident N x N
 // system (all indices compile-time: no scratch).  The pivot search keeps the
 // first largest entry, as LAPACK does.  A singular system yields a = 0.
@@ -488,7 +504,9 @@ __device__ __forceinline__ void phibar_points(const LevelDesc& L, size_t row, co
         for (int q = 0; q < U; ++q) {
             const int ic = clampi(i0 + q * WL, N);
             gv[q] = g[ic]; hv[q] = h[ic];
-            xv[q] = (S)gp(L.xi_x)[ic]; yv[q] = (S)gp(L.xi_y)[ic];
+            double xd, yd;
+            load_xy<S>(L, ic, xd, yd);
+            xv[q] = (S)xd; yv[q] = (S)yd;
         }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
@@ -1136,7 +1154,7 @@ __device__ __forceinline__ void face_rec_points(const LevelDesc& L, const FaceIt
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const int i = i0 + q * WL, ic = clampi(i, N);
-            xv[q] = gp(L.xi_x)[ic]; yv[q] = gp(L.xi_y)[ic];
+            load_xy<S>(L, ic, xv[q], yv[q]);
             wv[q] = i < N ? gp(L.w)[ic] : 0.0;
             const double dn = xv[q] * F.nx + yv[q] * F.ny;
             up[q] = dn >= 0.0;
@@ -1179,7 +1197,11 @@ __device__ __forceinline__ void face_rec_points(const LevelDesc& L, const FaceIt
             if (interior) {
                 acc_raw<S>(m, wv[q], xv[q] - u0, yv[q] - v0, eg[q], eh[q]);
             } else {
-                const double dn = xv[q] * F.nx + yv[q] * F.ny;
+                // the outgoing mass flux in the update's own arithmetic (double
+                // velocities), so that a diffuse wall's zero net mass flux holds
+                // in the update for either storage precision
+                const int ic = clampi(i0 + q * WL, N);
+                const double dn = gp(L.xi_x)[ic] * F.nx + gp(L.xi_y)[ic] * F.ny;
                 if (dn > 0) m[0] += wv[q] * dn * (double)eg[q];
             }
         }

@@ -49,6 +49,7 @@ struct LevelDesc {
     const double* xi_x;
     const double* xi_y;
     const double* w;
+    const float* xy32;      // (xi_x, xi_y) pairs rounded to float (FP32 storage reads these)
     void* g;   void* h;     // state g~, h~           [cells][stride]
     void* fg;  void* fh;    // phi_bar+ of the step: [cells][stride] followed by the ghost
                             // rows (neighbours on other levels mapped onto this level)

@@ -104,3 +104,12 @@ def test_periodic_totals_round_off_gpu():
     g.step(20)
     assert np.max(np.abs(g.totals() - t0)) < 1e-13
     g.close()
+
+
+@pytest.mark.parametrize("ni,nj,nv", [(1, 1, 6), (2, 1, 8), (1, 3, 10), (3, 2, 7)])
+def test_degenerate_meshes_and_short_rows(ni, nj, nv):
+    # a single periodic cell (its own neighbour on every side), meshes one or
+    # two cells wide, and velocity rows shorter than a wavefront (36 to 100
+    # points, odd and even)
+    p = W.perturb(W.periodic_box(ni, nj, Lx=0.2 * ni, Ly=0.2 * nj, Kn=0.05, nv=nv, vmax=4.0, kind="sine"), seed=ni + nj)
+    _run_parity(p, 3)
