@@ -467,6 +467,7 @@ struct MeshH {
     // stretch of consecutive work items touches, stencils included, stay in one
     // XCD's L2.  order[k] is the k-th cell, rank its inverse.
     std::vector<int> order, rank;
+    std::vector<int> face_order, bface_order;   // faces and boundary faces by the rank of their left cell
 };
 
 // Tiled traversal order of an ni x nj structured mesh (tw = 0: row-major).
@@ -484,6 +485,13 @@ void tile_order(MeshH& M, int tw, int th) {
     }
     M.rank.assign(M.n_cells, 0);
     for (int k = 0; k < M.n_cells; ++k) M.rank[M.order[k]] = k;
+    auto by_rank = [&M](const std::vector<FaceH>& fs, std::vector<int>& out) {
+        out.resize(fs.size());
+        for (size_t f = 0; f < fs.size(); ++f) out[f] = (int)f;
+        std::stable_sort(out.begin(), out.end(), [&](int a, int b) { return M.rank[fs[a].L] < M.rank[fs[b].L]; });
+    };
+    by_rank(M.faces, M.face_order);
+    by_rank(M.bfaces, M.bface_order);
 }
 
 void build_mesh(MeshH& M, const mlvs_mesh& in, int dim) {
@@ -834,12 +842,8 @@ void build_items(mlvs_ctx c) {
             cell_nbr[4 * cc + k] = -2 - row;
         }
     // interior faces, in the traversal order of their left cells
-    std::vector<int> forder(M.faces.size());
-    for (size_t f = 0; f < M.faces.size(); ++f) forder[f] = (int)f;
-    std::stable_sort(forder.begin(), forder.end(),
-                     [&](int a, int b) { return M.rank[M.faces[a].L] < M.rank[M.faces[b].L]; });
     int n_cross = 0;
-    for (int f : forder) {
+    for (int f : M.face_order) {
         const FaceH& F = M.faces[f];
         const int lL = c->cell_level[F.L], lR = c->cell_level[F.R];
         int kL = -1, kR = -1;
@@ -885,11 +889,7 @@ void build_items(mlvs_ctx c) {
     for (int cc = 0; cc < n; ++cc) c->step_points += c->levels[c->cell_level[cc]]->N;
     c->step_iface_points = 0.0;
     for (auto& it : xitems) c->step_iface_points += level_by_index(c, it.levI).N;
-    std::vector<int> border(M.bfaces.size());
-    for (size_t b = 0; b < M.bfaces.size(); ++b) border[b] = (int)b;
-    std::stable_sort(border.begin(), border.end(),
-                     [&](int a, int b) { return M.rank[M.bfaces[a].L] < M.rank[M.bfaces[b].L]; });
-    for (int b : border) {
+    for (int b : M.bface_order) {
         const FaceH& F = M.bfaces[b];
         const int lc = c->cell_level[F.L];
         FaceItem it{};
@@ -1235,15 +1235,31 @@ void cluster(int Nb, double tau, const std::vector<uint8_t>& uniq, const std::ve
     std::vector<int> centres;
     std::vector<int> cl_of_u(U, -1);
     std::vector<std::vector<uint8_t>> kmin;
+    // Distance sum_b |ka_b - kb_b| in blocks of 256 masks (vectorisable), given
+    // up as soon as it exceeds cap: only centres within the threshold can be
+    // joined, and a later centre must be strictly nearer to replace the best so
+    // far (ties go to the lowest id), so the result is the nearest centre
+    // within the threshold exactly as a full scan finds it.
+    auto dist_capped = [Nb](const uint8_t* a, const uint8_t* b, long cap) {
+        long d = 0;
+        for (int b0 = 0; b0 < Nb; b0 += 256) {
+            const int b1 = std::min(Nb, b0 + 256);
+            int s = 0;
+            for (int k = b0; k < b1; ++k) s += std::abs((int)a[k] - (int)b[k]);
+            d += s;
+            if (d > cap) return d;
+        }
+        return d;
+    };
     for (int u : order) {
         const uint8_t* ku = &uniq[(size_t)u * Nb];
         int best = -1;
         long bestd = 0;
         for (size_t cid = 0; cid < centres.size(); ++cid) {
-            const uint8_t* kc = &uniq[(size_t)centres[cid] * Nb];
-            long d = 0;
-            for (int b = 0; b < Nb; ++b) d += std::abs((int)ku[b] - (int)kc[b]);
-            if (best < 0 || d < bestd) { best = (int)cid; bestd = d; }
+            const long cap = best < 0 ? thr : bestd - 1;
+            if (cap < 0) break;
+            const long d = dist_capped(ku, &uniq[(size_t)centres[cid] * Nb], cap);
+            if (d <= cap) { best = (int)cid; bestd = d; }
         }
         if (best >= 0 && bestd <= thr) {
             cl_of_u[u] = best;
