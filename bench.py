@@ -327,7 +327,7 @@ def main():
         print(json.dumps({"cylinder": cylinder_case(steps=args.cylinder_steps, mode=args.cylinder_mode)}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding).",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
     import torch
