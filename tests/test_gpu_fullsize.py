@@ -7,12 +7,14 @@ configuration bench.py times (graph-captured steps, autotuned launch variants,
   GPU step against one oracle step from the same state and level catalogue,
   every cell, <= 1e-12 of the largest value.
 * Cylinder 256x128 O-grid, 101^2 Newton-Cotes, FP32, UVS and MLVS (the
-  benchmark's base-grid warm-up, then criterion levels): sampled cells.  The
-  oracle steps the 5x5-cell patch of the O-grid centred on each sampled cell
-  from the GPU's state, with the GPU's time step.  A cell's update reads
-  nothing farther than two cells away (the upwind neighbour's slope), so the
-  patch's own boundary does not reach the centre; the centre after one step
-  agrees to 1e-6 of its largest value (FP32 storage against FP64).
+  benchmark's base-grid warm-up, then criterion levels), and the slot jet
+  512x256, 161^2 Newton-Cotes (25921 points, about 110 GB of device state in
+  the UVS form), FP32, UVS and MLVS: sampled cells.  The oracle steps the
+  5x5-cell patch of the mesh around each sampled cell from the GPU's state,
+  with the GPU's time step.  A cell's update reads nothing farther than two
+  cells away (the upwind neighbour's slope), so the patch's own boundary does
+  not reach the centre; the centre after one step agrees to 1e-6 of its
+  largest value (FP32 storage against FP64).
 """
 import numpy as np
 import pytest
@@ -60,21 +62,21 @@ def test_cavity_full_size_bench_configuration(tmp_path):
 # sampled cells (i, j) of the O-grid: near the wall, in the shock layer, in the
 # wake and in the far field, away from the periodic seam
 SAMPLES = [(40, 2), (128, 3), (5, 17), (200, 40), (100, 77), (250, 125)]
+# of the jet: at the slot, in the jet, at the side and far walls
+JET_SAMPLES = [(2, 128), (3, 127), (5, 131), (7, 120), (2, 2), (509, 253)]
 
 
-@pytest.mark.parametrize("mode", ["uvs", "mlvs"])
-def test_cylinder_full_size_sampled_cells(mode, tmp_path):
+def _sampled_parity(p, mode, samples, warm):
     from paper_2609_35258_amd import autotune
+    import torch
     m = _m()
-    p = W.cylinder(256, 128, Kn=0.1, nv=101, vmax=10.0)
     ap = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, flux_test=True, interval=0)
-    print("case cylinder 256x128 fp32", mode, flush=True)
     g = m.Solver.from_problem(p, precision=32, compat=4, adapt=ap if mode == "mlvs" else None, graph=True)
-    g.step(100)                                 # base-grid warm-up of the benchmark
+    g.step(warm)                                # base-grid warm-up
     if mode == "mlvs":
         g.adapt()
     g.step(2)
-    autotune.autotune(g, 32, cache=str(tmp_path / "t.json"))
+    autotune.autotune(g, 32, cache=None)
     ni = p.ni
     if mode == "mlvs":
         npts, _, ncross = g.level_info()
@@ -82,7 +84,7 @@ def test_cylinder_full_size_sampled_cells(mode, tmp_path):
         levels = g.cell_levels()
         assert len(npts) >= 2 and ncross > 0
     patches = {}
-    for (i, j) in SAMPLES:
+    for (i, j) in samples:
         i0, j0 = i - 2, max(j - 2, 0)
         i0, j0 = min(max(i0, 0), ni - 5), min(j0, p.nj - 5)
         cells = [(i0 + a) + ni * (j0 + b) for b in range(5) for a in range(5)]
@@ -103,3 +105,17 @@ def test_cylinder_full_size_sampled_cells(mode, tmp_path):
         print("cell", (i, j), "points", len(ga), "error", eg, eh, flush=True)
         assert max(eg, eh) < 1e-6, ((i, j), eg, eh)
     g.close()
+    del g
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("mode", ["uvs", "mlvs"])
+def test_cylinder_full_size_sampled_cells(mode):
+    print("case cylinder 256x128 fp32", mode, flush=True)
+    _sampled_parity(W.cylinder(256, 128, Kn=0.1, nv=101, vmax=10.0), mode, SAMPLES, 100)
+
+
+@pytest.mark.parametrize("mode", ["uvs", "mlvs"])
+def test_jet_full_size_sampled_cells(mode):
+    print("case jet 512x256 161^2 fp32", mode, flush=True)
+    _sampled_parity(W.jet(512, 256, Kn_jet=1e-3, nv=161, vmax=7.0), mode, JET_SAMPLES, 100)
