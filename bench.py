@@ -108,14 +108,15 @@ def cpu_baseline(p, sample_steps=2, sample_cells=256):
 LEARNED_ADAPT = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, flux_test=True, interval=0)
 
 
-def learned_vs_criterion(precision=32, n_theta=64, n_r=32, nv=41, warm=200, snaps=16, every=10, rounds=6):
+def learned_vs_criterion(precision=32, n_theta=256, n_r=128, nv=101, warm=100, snaps=32, every=10, rounds=6):
     """Learned vs criterion adaptation on the same GPU.
 
-    Supersonic cylinder (Ma 3, Kn 0.1, Shakhov) reduced to n_theta x n_r cells
-    and an nv^2 Newton-Cotes base grid.  A criterion run builds the catalogue
-    (one full adaptation after `warm` steps) and collects (features, criterion
-    label) snapshots every `every` steps; the network is trained on the GPU on
-    the earlier 80% of the snapshots.  A second solver starts from the same
+    Supersonic cylinder (Ma 3, Kn 0.1, Shakhov), n_theta x n_r cells and an
+    nv^2 Newton-Cotes base grid (by default the full-size case: 32 snapshots of
+    32768 cells, about 1e6 samples).  A criterion run builds the catalogue (one
+    full adaptation after `warm` base-grid steps) and collects (features,
+    criterion label) snapshots every `every` steps; the network is trained on
+    the GPU on the earlier 80% of the snapshots.  A second solver starts from the same
     state and levels with the selector on.  Both then run `rounds` rounds of
     `every` steps plus one adaptation: full criterion adaptation (the paper's
     method, catalogue rebuilt) vs learned adaptation (frozen catalogue, tail-mass
@@ -187,6 +188,58 @@ def learned_vs_criterion(precision=32, n_theta=64, n_r=32, nv=41, warm=200, snap
 
 CYL_ADAPT = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, flux_test=True, interval=0)
 CYL_INTERVAL = 100
+
+
+def jet_case(steps=100, warmup=100, precision=32):
+    """Under-expanded slot jet into near vacuum at full size (512 x 256 cells,
+    161^2 = 25921-point Newton-Cotes base grid on [-7,7]^2, about 110 GB of
+    device state in the UVS form, FP32 storage), MLVS against UVS.  Both take
+    `warmup` untimed base-grid steps from the initial state; the MLVS run then
+    adapts (criterion levels) at the start of the timed steps, adaptation
+    included in the timing.  Graph-captured steps, autotuned variants."""
+    import torch
+    import paper_2609_35258_amd as m
+    from paper_2609_35258_amd import autotune
+    p = W.jet(512, 256, Kn_jet=1e-3, nv=161, vmax=7.0)
+    s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=CYL_ADAPT, graph=True)
+    s.step(warmup)
+    s.adapt()
+    s.step(2)
+    autotune.autotune(s, precision)
+    torch.cuda.synchronize()
+    c0 = s.counters()
+    t0 = time.perf_counter()
+    s.adapt()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t_m = time.perf_counter() - t0
+    upd = s.counters()["cell_updates"] - c0["cell_updates"]
+    npts, ncells, ncross = s.level_info()
+    f_m = s.moments()
+    mem_m = s.memory()
+    prof = stage_profile(s, reps=3)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    u, t_u, upd_u, _ = run_gpu(p, steps, warmup + 2, precision, None)
+    f_u = u.moments()
+    mem_u = u.memory()
+    prof_u = stage_profile(u, reps=3)
+    u.close()
+    del u
+    torch.cuda.empty_cache()
+    err = {name: float(np.sqrt(np.sum((f_m[:, k] - f_u[:, k]) ** 2) / np.sum(f_u[:, k] ** 2)))
+           for k, name in ((0, "rho"), (1, "u"), (3, "T"))}
+    return {"workload": "slot jet 512x256 on [0,32]x[-8,8], sonic slot |y| <= 0.5, background rho 0.01, Kn_jet "
+                        "1e-3, Shakhov Pr 2/3, 161x161 Newton-Cotes on [-7,7]^2, fp%d; %d base-grid steps, then %d "
+                        "timed steps; MLVS C_split 0.01 C_merge 0.005 eps 2e-5 tau 0.05" % (precision, warmup, steps),
+            "value": upd / t_m, "ms_per_step": 1e3 * t_m / steps, "levels": len(npts),
+            "level_points": [int(x) for x in npts], "level_cells": [int(x) for x in ncells],
+            "nbar": float(np.sum(npts * ncells) / np.sum(ncells)), "n_cross": int(ncross),
+            "roofline": roofline(prof, precision),
+            "uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps, "roofline": roofline(prof_u, precision),
+                    "device_bytes": int(mem_u), "time_to_solution_ratio": t_u / t_m, "memory_ratio": mem_u / mem_m,
+                    "mlvs_vs_uvs_rel_l2": err}}
 
 
 # launch variant index -> (velocity points per lane per load batch, minimum waves per SIMD)
@@ -306,6 +359,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-cylinder", action="store_true")
+    ap.add_argument("--no-jet", action="store_true")
     ap.add_argument("--cylinder-only", action="store_true",
                     help="only the full-size cylinder comparison (profiling runs)")
     ap.add_argument("--cylinder-steps", type=int, default=200)
@@ -374,6 +428,8 @@ def main():
         u.close()
     if not args.no_cylinder:
         out["cylinder"] = cylinder_case(steps=args.cylinder_steps)
+    if not args.no_jet:
+        out["jet"] = jet_case()
     if not args.no_learned:
         out["learned"] = learned_vs_criterion()
     if not args.no_cpu_baseline:
