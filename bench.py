@@ -190,7 +190,7 @@ CYL_ADAPT = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, fl
 CYL_INTERVAL = 100
 
 
-def jet_case(steps=100, warmup=100, precision=32):
+def jet_case(steps=100, warmup=100, precision=32, mode="both"):
     """Under-expanded slot jet into near vacuum at full size (512 x 256 cells,
     161^2 = 25921-point Newton-Cotes base grid on [-7,7]^2, about 110 GB of
     device state in the UVS form, FP32 storage), MLVS against UVS.  Both take
@@ -201,6 +201,14 @@ def jet_case(steps=100, warmup=100, precision=32):
     import paper_2609_35258_amd as m
     from paper_2609_35258_amd import autotune
     p = W.jet(512, 256, Kn_jet=1e-3, nv=161, vmax=7.0)
+    if mode == "uvs":
+        u, t_u, upd_u, _ = run_gpu(p, steps, warmup + 2, precision, None)
+        prof_u = stage_profile(u, reps=3)
+        var_u = {k: v["variant"] for k, v in getattr(u, "tuned", {}).items()}
+        u.close()
+        return {"uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps,
+                        "roofline": roofline(prof_u, precision, var_u,
+                                             "jet512x256-nc161-fp32-uvs" if precision == 32 else None)}}
     s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=CYL_ADAPT, graph=True)
     s.step(warmup)
     s.adapt()
@@ -221,10 +229,14 @@ def jet_case(steps=100, warmup=100, precision=32):
     s.close()
     del s
     torch.cuda.empty_cache()
+    if mode == "mlvs":
+        return {"value": upd / t_m, "ms_per_step": 1e3 * t_m / steps, "nbar": float(np.sum(npts * ncells) / np.sum(ncells)),
+                "roofline": roofline(prof, precision)}
     u, t_u, upd_u, _ = run_gpu(p, steps, warmup + 2, precision, None)
     f_u = u.moments()
     mem_u = u.memory()
     prof_u = stage_profile(u, reps=3)
+    var_u = {k: v["variant"] for k, v in getattr(u, "tuned", {}).items()}
     u.close()
     del u
     torch.cuda.empty_cache()
@@ -237,7 +249,9 @@ def jet_case(steps=100, warmup=100, precision=32):
             "level_points": [int(x) for x in npts], "level_cells": [int(x) for x in ncells],
             "nbar": float(np.sum(npts * ncells) / np.sum(ncells)), "n_cross": int(ncross),
             "roofline": roofline(prof, precision),
-            "uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps, "roofline": roofline(prof_u, precision),
+            "uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps,
+                    "roofline": roofline(prof_u, precision, var_u,
+                                         "jet512x256-nc161-fp32-uvs" if precision == 32 else None),
                     "device_bytes": int(mem_u), "time_to_solution_ratio": t_u / t_m, "memory_ratio": mem_u / mem_m,
                     "mlvs_vs_uvs_rel_l2": err}}
 
@@ -360,6 +374,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-cylinder", action="store_true")
     ap.add_argument("--no-jet", action="store_true")
+    ap.add_argument("--jet-only", action="store_true", help="only the full-size jet comparison (profiling runs)")
+    ap.add_argument("--jet-mode", choices=("both", "mlvs", "uvs"), default="both")
     ap.add_argument("--cylinder-only", action="store_true",
                     help="only the full-size cylinder comparison (profiling runs)")
     ap.add_argument("--cylinder-steps", type=int, default=200)
@@ -376,6 +392,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": args.copy_probe}))
+        return
+    if args.jet_only:
+        print(json.dumps({"jet": jet_case(mode=args.jet_mode)}), flush=True)
         return
     if args.cylinder_only:
         print(json.dumps({"cylinder": cylinder_case(steps=args.cylinder_steps, mode=args.cylinder_mode)}), flush=True)
