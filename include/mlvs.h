@@ -241,7 +241,7 @@ mlvs_status mlvs_counters(mlvs_ctx ctx, int64_t* steps, double* cell_updates, do
  * faces: face state, corrected target, recovery weights), 4 cross-level
  * faces, 5 update (fluxes and new state; the state is saved before and put
  * back after the timed launches), 6 criterion, and the fused forms of the
- * step whose levels fit one velocity chunk: 7 face reconstruction and target
+ * step whose levels have at most 1024 points: 7 face reconstruction and target
  * in one launch, 8 update followed by the next step's cell stage (state, rows
  * and parameters saved and put back as for 5; MLVS_E_STATE when the step is
  * not fused).  Needs a step taken since the last level change for
@@ -249,7 +249,7 @@ mlvs_status mlvs_counters(mlvs_ctx ctx, int64_t* steps, double* cell_updates, do
 mlvs_status mlvs_time_stage(mlvs_ctx ctx, int stage, int reps, double* ms_per_launch);
 
 /* The stages one step launches, in order (numbering as in mlvs_time_stage):
- * 0 1 2 3 4 5, or 1 7 4 8 when every level fits one velocity chunk (the
+ * 0 1 2 3 4 5, or 1 7 4 8 when every level has at most 1024 points (the
  * fused step; MLVS_FUSE=0 in the environment at create turns it off).
  * stages: caller-owned array of at least 8 ints, or null to query *count. */
 mlvs_status mlvs_step_stages(mlvs_ctx ctx, int* stages, int* count);

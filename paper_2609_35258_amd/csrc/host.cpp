@@ -660,7 +660,8 @@ struct mlvs_ctx_s {
     std::vector<char> stage_keep;      // host image of the last staged upload
     void* levels_block = nullptr;      // device block with the current levels' geometry
     double* d_fmom = nullptr;          // [chunks][faces + boundary faces][NFMOM] face moments
-    int chunk = 1024;                  // velocity points per chunk (multiple of 64)
+    int chunk = 1024;                  // velocity points per chunk (multiple of 64), set per level set
+    int chunk_env = 0;                 // MLVS_CHUNK: a fixed chunk instead of the chosen one
     int nch = 1;                       // chunks of the largest level
     double* d_fpar = nullptr;          // [faces + boundary faces][NFP] face records
     bool mom_valid = false;            // d_cmom matches the stored state
@@ -997,8 +998,22 @@ void build_items(mlvs_ctx c) {
     }
     int nmax = 1;
     for (int l = 0; l < K; ++l) nmax = std::max(nmax, c->levels[l]->N);
+    // Velocity chunk of the streaming stages: whole rows (one item per face
+    // and per cell) unless there are too few faces to fill the GPU with
+    // waves, then the fewest chunks that do.  Levels of at most
+    // FUSE_MAX_POINTS points always take whole rows and the fused step.
+    constexpr int FUSE_MAX_POINTS = 1024, MIN_ITEMS = 16384;
+    const int nf_all = std::max<int>((int)faces.size(), 1);
+    if (c->chunk_env > 0) {
+        c->chunk = c->chunk_env;
+    } else {
+        int parts = 1;
+        if (nmax > FUSE_MAX_POINTS && nf_all < MIN_ITEMS)
+            parts = std::min((MIN_ITEMS + nf_all - 1) / nf_all, (nmax + 63) / 64);
+        c->chunk = ((nmax + parts - 1) / parts + 63) / 64 * 64;
+    }
     c->nch = (nmax + c->chunk - 1) / c->chunk;
-    c->fused = c->fuse_allowed && c->nch == 1;
+    c->fused = c->fuse_allowed && c->nch == 1 && nmax <= FUSE_MAX_POINTS;
     c->d_fmom = static_cast<double*>(
         c->dm.alloc(sizeof(double) * NFMOM * c->nch * std::max<size_t>(faces.size(), 1)));
     c->item_allocs.push_back(c->d_fmom);
@@ -1742,7 +1757,7 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         if (const char* e = std::getenv("MLVS_CHUNK")) {
             const int v = std::atoi(e);
             if (v < 64 || v % 64 != 0) fail(MLVS_E_ARG, "MLVS_CHUNK must be a positive multiple of 64");
-            c->chunk = v;
+            c->chunk_env = v;
         }
         // one level: the base grid itself
         std::vector<uint8_t> k0(B.Nb, 0);
