@@ -1,6 +1,6 @@
 """Parity at the full sizes of the benchmark workloads, in the launch
 configuration bench.py times (graph-captured steps, autotuned launch variants,
-1024-point velocity chunks, tiled traversal).
+velocity chunks chosen per level set, tiled traversal).
 
 * Cavity 64x64, 28^2 Gauss-Hermite, FP64, MLVS with the benchmark's
   adaptation settings: after the warm-up and the adaptation at step 100, one
