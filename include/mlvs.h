@@ -187,6 +187,12 @@ mlvs_status mlvs_criterion(mlvs_ctx ctx, uint8_t* out);
  * out [n_cells][6] host.  Synchronises. */
 mlvs_status mlvs_moments(mlvs_ctx ctx, double* out);
 
+/* Per-cell deviatoric stress (sigma_xx, sigma_xy, sigma_yy) = (P_xx - p,
+ * P_xy, P_yy - p), P_ab = sum w c_a c_b g~ with c = xi - u and p = rho R T
+ * (the viscous stress of the paper's cavity and cylinder results): out
+ * [n_cells][3] host.  dim = 2 only.  Synchronises. */
+mlvs_status mlvs_stress(mlvs_ctx ctx, double* out);
+
 /* sum_cells |V| (rho, rho u, rho v, rho E), FP64, fixed-order tree sum. */
 mlvs_status mlvs_totals(mlvs_ctx ctx, double out[4]);
 

@@ -119,6 +119,7 @@ _PROTOS = {
     "mlvs_stage_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                                        _c_double_p]),
     "mlvs_step_stages": (ctypes.c_int, [ctypes.c_void_p, _c_int32_p, ctypes.POINTER(ctypes.c_int)]),
+    "mlvs_stress": (ctypes.c_int, [ctypes.c_void_p, _c_double_p]),
     "mlvs_neg_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "mlvs_positivity_counts": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                               ctypes.POINTER(ctypes.c_int64)]),
@@ -387,6 +388,12 @@ class Solver:
         _check(lib().mlvs_get_state(self.h, _dp(g), _dp(h)))
         off = np.concatenate([[0], np.cumsum(n)])
         return [(g[off[c]:off[c + 1]], h[off[c]:off[c + 1]]) for c in range(self.n_cells)]
+
+    def stress(self):
+        """Per-cell deviatoric stress (sigma_xx, sigma_xy, sigma_yy), shape (n_cells, 3)."""
+        out = np.zeros((self.n_cells, 3))
+        _check(lib().mlvs_stress(self.h, _dp(out)))
+        return out
 
     def get_cell(self, cell: int):
         """(g, h) of one cell on its level, FP64 on the host (synchronises)."""

@@ -1825,6 +1825,21 @@ mlvs_status mlvs_moments(mlvs_ctx c, double* out) {
     });
 }
 
+mlvs_status mlvs_stress(mlvs_ctx c, double* out) {
+    return guarded([&] {
+        if (!c || !out) fail(MLVS_E_ARG, "null argument");
+        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
+        if (c->ph.D != 2) fail(MLVS_E_STATE, "the stress output needs dim = 2");
+        const int n = c->mesh.n_cells;
+        double* d = static_cast<double*>(c->dm.alloc(sizeof(double) * 3 * n));
+        hip_check(launch_cell_moments(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom, c->ph,
+                                      nullptr, nullptr, nullptr, d), "moments launch");
+        hip_check(hipMemcpyAsync(out, d, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->st), "D2H");
+        sync(c);
+        c->dm.release(d);
+    });
+}
+
 mlvs_status mlvs_totals(mlvs_ctx c, double out[4]) {
     return guarded([&] {
         if (!c || !out) fail(MLVS_E_ARG, "null argument");

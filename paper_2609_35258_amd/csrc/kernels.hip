@@ -1657,7 +1657,7 @@ __global__ __launch_bounds__(BS) void k_cell_moments(const LevelDesc* __restrict
                                                      const int* __restrict__ cell_slot, int n_cells,
                                                      const CellGeom* __restrict__ geom, Phys ph,
                                                      double* __restrict__ out6, double* __restrict__ tot4,
-                                                     double* __restrict__ out8) {
+                                                     double* __restrict__ out8, double* __restrict__ out3) {
     for (int c = item0(); c < n_cells; c += istride()) {
         const LevelDesc& L = lvs[cell_lev[c]];
         const size_t row = (size_t)cell_slot[c] * L.stride;
@@ -1684,6 +1684,14 @@ __global__ __launch_bounds__(BS) void k_cell_moments(const LevelDesc* __restrict
                 o[0] = rho; o[1] = u; o[2] = v; o[3] = T; o[4] = f * qx; o[5] = f * qy;
                 o[6] = (m[3] - rho * u * u) - rho * ph.R * T;
                 o[7] = m[4] - rho * u * v;
+            }
+            if (out3) {
+                // deviatoric stress (sigma_xx, sigma_xy, sigma_yy) = (P_xx - p, P_xy, P_yy - p)
+                double* o = out3 + 3 * (size_t)c;
+                const double p = rho * ph.R * T;
+                o[0] = (m[3] - rho * u * u) - p;
+                o[1] = m[4] - rho * u * v;
+                o[2] = (m[5] - rho * v * v) - p;
             }
             if (tot4) {
                 const double V = geom[c].vol;
@@ -1901,10 +1909,10 @@ hipError_t launch_update(int prec, hipStream_t st, const LevelDesc* lv, const in
 
 hipError_t launch_cell_moments(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
                                const int* cell_slot, int n_cells, const CellGeom* geom, Phys ph, double* out6,
-                               double* tot4, double* out8) {
+                               double* tot4, double* out8, double* out3) {
     if (n_cells <= 0) return hipSuccess;
     MLVS_DISPATCH(prec, k_cell_moments, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
-                  geom, ph, out6, tot4, out8);
+                  geom, ph, out6, tot4, out8, out3);
     return hipGetLastError();
 }
 

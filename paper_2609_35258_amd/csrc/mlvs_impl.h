@@ -148,7 +148,7 @@ hipError_t launch_init_eq(int prec, hipStream_t st, const LevelDesc* lv, const i
                           double* params);
 hipError_t launch_cell_moments(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
                                const int* cell_slot, int n_cells, const CellGeom* geom, Phys ph,
-                               double* out6, double* out_tot4, double* out8 = nullptr);
+                               double* out6, double* out_tot4, double* out8 = nullptr, double* out3 = nullptr);
 hipError_t launch_sum_rows(hipStream_t st, const double* in, int n, int width, double* out);
 hipError_t launch_remap(int prec, hipStream_t st, const LevelDesc* old_lv, const LevelDesc* new_lv,
                         const RemapItem* items, int n, Phys ph, unsigned long long* neg);

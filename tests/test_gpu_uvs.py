@@ -113,3 +113,26 @@ def test_degenerate_meshes_and_short_rows(ni, nj, nv):
     # points, odd and even)
     p = W.perturb(W.periodic_box(ni, nj, Lx=0.2 * ni, Ly=0.2 * nj, Kn=0.05, nv=nv, vmax=4.0, kind="sine"), seed=ni + nj)
     _run_parity(p, 3)
+
+
+def test_stress_matches_oracle():
+    # deviatoric stress of the cavity after a few steps, against the oracle's
+    # state (P_ab = sum w c_a c_b g, minus p on the diagonal)
+    p = W.cavity(12, Kn=0.075, nv=12)
+    o = Oracle(p, compat=4)
+    g = _gpu(p)
+    for _ in range(5):
+        o.step()
+    g.step(5)
+    ref = np.zeros((p.n_cells, 3))
+    for c in range(p.n_cells):
+        xi, w = o.vset(o.cell_level[c])
+        rho, u, T = o.macro(xi, w, o.g[c], o.h[c])
+        cc = xi - u[None, :]
+        pr = rho * p.R * T
+        ref[c] = [np.sum(w * cc[:, 0] ** 2 * o.g[c]) - pr, np.sum(w * cc[:, 0] * cc[:, 1] * o.g[c]),
+                  np.sum(w * cc[:, 1] ** 2 * o.g[c]) - pr]
+    got = g.stress()
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref)) + 1e-14
+    assert np.max(np.abs(ref[:, 1])) > 1e-6          # the lid shears the cavity
+    g.close()
