@@ -9,7 +9,9 @@ Scheme (Sec. 2.2): with s = dt/2,
           phi~ = phi - dt/2 Omega, phi_bar+ = phi + s/2 Omega, phi~+ = phi + dt/2 Omega);
   slopes: per index direction a van Leer limited one-sided slope pair,
           combined into a gradient through the two direction vectors
-          (reading of Eq. reconstruction for structured meshes);
+          (reading of Eq. reconstruction for structured meshes); on
+          unstructured meshes least squares with Venkatakrishnan's limiter
+          (oracle.umesh);
   face:   phi_bar_f = phi_bar+_up + (x_f - x_up - xi s) . sigma_up
           (Eqs. bar_phi_transport, reconstruction; both sides averaged where
           xi . n = 0), W_f and q_bar (Eq. W_from_bar),
@@ -39,6 +41,7 @@ import numpy as np
 from . import kinetic as kin
 from . import levels as lv
 from .mesh import Mesh
+from .umesh import UMesh, lsq_limited_slope
 from .quadrature import base_grid
 
 WALL, FARFIELD, OUTFLOW = 1, 2, 3
@@ -68,7 +71,8 @@ class Solver:
                  adapt: Optional[AdaptParams] = None, dt: Optional[float] = None,
                  map_moments: int = 4, positivity: str = "keep"):
         self.p = problem
-        self.mesh = Mesh(problem)
+        self.unstructured = bool(getattr(problem, "unstructured", False))
+        self.mesh = UMesh(problem) if self.unstructured else Mesh(problem)
         self.D = problem.dim
         self.R, self.Pr, self.K = problem.R, problem.Pr, problem.K
         self.omega, self.T_ref = problem.omega, problem.T_ref
@@ -106,6 +110,9 @@ class Solver:
         self.h = [None] * self.mesh.n_cells
         pj = problem
         for c in range(self.mesh.n_cells):
+            if self.unstructured:
+                self.init_cell(c, pj.rho0[c], np.array([pj.u0[c], pj.v0[c]]), pj.T0[c])
+                continue
             i, j = c % self.mesh.ni, c // self.mesh.ni
             self.init_cell(c, pj.rho0[j, i], np.array([pj.u0[j, i], pj.v0[j, i]]), pj.T0[j, i])
 
@@ -285,6 +292,13 @@ class Solver:
         """Limited gradient sigma of phi_bar+ per cell on its native level."""
         m = self.mesh
         self.sig = [None] * m.n_cells
+        if self.unstructured:
+            for c in range(m.n_cells):
+                nv = [None if nb < 0 else self.neighbour_on(c, nb) for (nb, _, _) in m.cell_faces[c]]
+                self.sig[c] = [lsq_limited_slope(m, c, self.fbp[c][comp],
+                                                 [None if v is None else v[comp] for v in nv])
+                               for comp in (0, 1)]
+            return
         for c in range(m.n_cells):
             fc = self.fbp[c]
             dirs = [(0, 1)] if self.D == 1 else [(0, 1), (2, 3)]

@@ -276,3 +276,219 @@ def mlp_init_params(K: int, seed: int, H: int = 64, NF: int = 10) -> np.ndarray:
     W3 = rng.normal(size=(K, H)) * math.sqrt(2.0 / H)
     return np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), W3.ravel(), np.zeros(K),
                            np.zeros(NF), np.ones(NF)])
+
+
+# ---------------------------------------------------------------------------
+# unstructured meshes
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class UProblem:
+    """An unstructured-mesh problem: polygons (triangles or quadrilaterals,
+    counter-clockwise), the boundary id of every edge that belongs to one cell
+    only, initial state per cell, physics as in Problem."""
+
+    name: str
+    nodes: np.ndarray        # (n_nodes, 2)
+    cell_ptr: np.ndarray     # (n_cells + 1,) int32 offsets into cell_node
+    cell_node: np.ndarray    # int32 node ids, 3 or 4 per cell
+    bedges: np.ndarray       # (n_bedges, 3) int32: node a, node b, bc id
+    bcs: List[BC]
+    rho0: np.ndarray         # (n_cells,)
+    u0: np.ndarray
+    v0: np.ndarray
+    T0: np.ndarray
+    R: float
+    Pr: float
+    K: int
+    omega: float
+    T_ref: float
+    rho_ref: float
+    L_ref: float
+    Kn: float
+    cfl: float
+    vel_kind: str
+    nv: int
+    vmax: float
+    gh_scale_T: float = 1.0
+    dim: int = 2
+    unstructured: bool = True
+
+    @property
+    def n_cells(self) -> int:
+        return len(self.cell_ptr) - 1
+
+    def centroids(self) -> np.ndarray:
+        """Vertex means of the cells (set-up only: seeding and region tests)."""
+        out = np.zeros((self.n_cells, 2))
+        for c in range(self.n_cells):
+            out[c] = self.nodes[self.cell_node[self.cell_ptr[c]:self.cell_ptr[c + 1]]].mean(axis=0)
+        return out
+
+
+def two_cavity(n: int = 48, nv: int = 101, vmax: float = 7.0, Kn_left: float = 1e-3,
+               ratio: float = 1e-3, seed: int = 0, jitter: float = 0.15) -> UProblem:
+    """Gas expansion between two square cavities (side 1) joined by a channel of
+    length 1 and width 1/8: left cavity [-1.5,-0.5]x[-0.5,0.5], channel
+    [-0.5,0.5]x[-1/16,1/16], right cavity [0.5,1.5]x[-0.5,0.5].  Lattice
+    spacing 1/n (n a multiple of 16); cavity squares are cut into two
+    triangles along a seeded random diagonal, channel squares stay
+    quadrilaterals, and every node off the boundary is moved by a seeded
+    uniform offset of at most jitter/n per axis.  Diffuse walls at T = 1;
+    gas at rest, T = 1, rho = 1 for x < 0 and `ratio` for x > 0 (R = 0.5, so
+    sqrt(2 R T_w) = 1)."""
+    if n % 16 != 0:
+        raise ValueError("n must be a multiple of 16")
+    h = 1.0 / n
+    ni, nj = 3 * n, n
+    half = n // 16
+    def inside(i, j):            # lattice square (i, j) by its lower-left corner
+        if i < 0 or j < 0 or i >= ni or j >= nj:
+            return 0
+        if i < n or i >= 2 * n:
+            return 1             # cavity
+        return 2 if (n // 2 - half) <= j < (n // 2 + half) else 0
+    rng = np.random.default_rng(seed)
+    node_id = -np.ones((nj + 1, ni + 1), np.int64)
+    sq = [(i, j, inside(i, j)) for j in range(nj) for i in range(ni) if inside(i, j)]
+    for (i, j, _) in sq:
+        for (a, b) in ((i, j), (i + 1, j), (i + 1, j + 1), (i, j + 1)):
+            node_id[b, a] = 0
+    pts = []
+    for b in range(nj + 1):
+        for a in range(ni + 1):
+            if node_id[b, a] == 0:
+                node_id[b, a] = len(pts)
+                pts.append((-1.5 + a * h, -0.5 + b * h))
+    nodes = np.array(pts)
+    # boundary edges: lattice edges with a domain square on one side only
+    bedges = []
+    on_bnd = np.zeros(len(nodes), bool)
+    for (i, j, _) in sq:
+        for (di, dj, a0, a1) in ((0, -1, (i, j), (i + 1, j)), (1, 0, (i + 1, j), (i + 1, j + 1)),
+                                 (0, 1, (i + 1, j + 1), (i, j + 1)), (-1, 0, (i, j + 1), (i, j))):
+            if not inside(i + di, j + dj):
+                p, q = node_id[a0[1], a0[0]], node_id[a1[1], a1[0]]
+                bedges.append((p, q, 0))
+                on_bnd[p] = on_bnd[q] = True
+    off = rng.uniform(-jitter * h, jitter * h, size=nodes.shape)
+    off[on_bnd] = 0.0
+    nodes = nodes + off
+    cells = []
+    for (i, j, kind) in sq:
+        a, b = node_id[j, i], node_id[j, i + 1]
+        c, d = node_id[j + 1, i + 1], node_id[j + 1, i]
+        if kind == 2:
+            cells.append((a, b, c, d))
+        elif rng.random() < 0.5:
+            cells.append((a, b, c)); cells.append((a, c, d))
+        else:
+            cells.append((a, b, d)); cells.append((b, c, d))
+    cell_ptr = np.zeros(len(cells) + 1, np.int32)
+    cell_ptr[1:] = np.cumsum([len(c) for c in cells])
+    cell_node = np.array([v for c in cells for v in c], np.int32)
+    xc = np.array([nodes[list(c)].mean(axis=0) for c in cells])
+    left = xc[:, 0] < 0.0
+    nc = len(cells)
+    R = 0.5
+    return UProblem("two_cavity", nodes, cell_ptr, cell_node, np.array(bedges, np.int32).reshape(-1, 3),
+                    [BC(WALL, T=1.0)], np.where(left, 1.0, ratio), np.zeros(nc), np.zeros(nc), np.ones(nc),
+                    R=R, Pr=2.0 / 3.0, K=0, omega=0.81, T_ref=1.0, rho_ref=1.0, L_ref=1.0, Kn=Kn_left,
+                    cfl=0.5, vel_kind="nc", nv=nv, vmax=vmax)
+
+
+def as_unstructured(problem: Problem, split: str = "none", seed: int = 0) -> UProblem:
+    """A non-periodic structured problem as an unstructured one: the same
+    nodes, each quadrilateral kept ("none"), cut along its (i,j)-(i+1,j+1)
+    diagonal ("diag") or along a seeded random diagonal ("random").  Cell
+    order: (i, j) row-major, the two triangles of a cut cell in a row."""
+    if problem.periodic_i or problem.periodic_j or problem.dim != 2:
+        raise ValueError("needs a non-periodic 2-D problem")
+    ni, nj = problem.ni, problem.nj
+    nodes = np.stack([problem.X.ravel(), problem.Y.ravel()], axis=1)
+    nid = lambda i, j: j * (ni + 1) + i
+    rng = np.random.default_rng(seed)
+    cells, src = [], []
+    for j in range(nj):
+        for i in range(ni):
+            a, b, c, d = nid(i, j), nid(i + 1, j), nid(i + 1, j + 1), nid(i, j + 1)
+            if split == "none":
+                cells.append((a, b, c, d)); src.append(i + ni * j)
+            elif split == "diag" or rng.random() < 0.5:
+                cells += [(a, b, c), (a, c, d)]; src += [i + ni * j] * 2
+            else:
+                cells += [(a, b, d), (b, c, d)]; src += [i + ni * j] * 2
+    bedges = []
+    for j in range(nj):
+        bedges.append((nid(0, j + 1), nid(0, j), int(problem.bc_imin[j])))
+        bedges.append((nid(ni, j), nid(ni, j + 1), int(problem.bc_imax[j])))
+    for i in range(ni):
+        bedges.append((nid(i, 0), nid(i + 1, 0), int(problem.bc_jmin[i])))
+        bedges.append((nid(i + 1, nj), nid(i, nj), int(problem.bc_jmax[i])))
+    cell_ptr = np.zeros(len(cells) + 1, np.int32)
+    cell_ptr[1:] = np.cumsum([len(c) for c in cells])
+    src = np.array(src)
+    f = lambda a: np.asarray(a).ravel()[src].copy()
+    return UProblem(problem.name + "_u", nodes, cell_ptr, np.array([v for c in cells for v in c], np.int32),
+                    np.array(bedges, np.int32), list(problem.bcs), f(problem.rho0), f(problem.u0),
+                    f(problem.v0), f(problem.T0), R=problem.R, Pr=problem.Pr, K=problem.K,
+                    omega=problem.omega, T_ref=problem.T_ref, rho_ref=problem.rho_ref, L_ref=problem.L_ref,
+                    Kn=problem.Kn, cfl=problem.cfl, vel_kind=problem.vel_kind, nv=problem.nv,
+                    vmax=problem.vmax, gh_scale_T=problem.gh_scale_T)
+
+
+def cell_neighbours(p: UProblem):
+    """Cells sharing an edge with each cell (set-up only: patch extraction)."""
+    owner = {}
+    for c in range(p.n_cells):
+        vs = p.cell_node[p.cell_ptr[c]:p.cell_ptr[c + 1]]
+        for k in range(len(vs)):
+            key = tuple(sorted((int(vs[k]), int(vs[(k + 1) % len(vs)]))))
+            owner.setdefault(key, []).append(c)
+    nb = [[] for _ in range(p.n_cells)]
+    for cs in owner.values():
+        if len(cs) == 2:
+            nb[cs[0]].append(cs[1]); nb[cs[1]].append(cs[0])
+    return nb
+
+
+def upatch(p: UProblem, centre: int, hops: int = 2):
+    """The cells within `hops` edge-neighbour steps of `centre`, as a problem of
+    its own (edges to cells left out become outflow boundaries; the original
+    boundary edges keep their ids).  Returns (problem, cells), cells[k] being
+    the original id of the patch's cell k (centre first)."""
+    nb = cell_neighbours(p)
+    cells, seen, front = [centre], {centre}, [centre]
+    for _ in range(hops):
+        nxt = []
+        for c in front:
+            for n in nb[c]:
+                if n not in seen:
+                    seen.add(n); cells.append(n); nxt.append(n)
+        front = nxt
+    used = sorted({int(v) for c in cells for v in p.cell_node[p.cell_ptr[c]:p.cell_ptr[c + 1]]})
+    remap = {v: k for k, v in enumerate(used)}
+    polys = [[remap[int(v)] for v in p.cell_node[p.cell_ptr[c]:p.cell_ptr[c + 1]]] for c in cells]
+    orig_b = {tuple(sorted((int(a), int(b)))): int(i) for a, b, i in p.bedges}
+    count = {}
+    for poly in polys:
+        for k in range(len(poly)):
+            key = tuple(sorted((poly[k], poly[(k + 1) % len(poly)])))
+            count[key] = count.get(key, 0) + 1
+    bcs = list(p.bcs) + [BC(OUTFLOW)]
+    inv = {k: v for v, k in remap.items()}
+    bedges = []
+    for poly in polys:
+        for k in range(len(poly)):
+            a, b = poly[k], poly[(k + 1) % len(poly)]
+            if count[tuple(sorted((a, b)))] == 1:
+                bid = orig_b.get(tuple(sorted((inv[a], inv[b]))), len(bcs) - 1)
+                bedges.append((a, b, bid))
+    cell_ptr = np.zeros(len(polys) + 1, np.int32)
+    cell_ptr[1:] = np.cumsum([len(q) for q in polys])
+    idx = np.array(cells)
+    q = dataclasses.replace(p, name=p.name + "_patch", nodes=p.nodes[used].copy(), cell_ptr=cell_ptr,
+                            cell_node=np.array([v for poly in polys for v in poly], np.int32),
+                            bedges=np.array(bedges, np.int32).reshape(-1, 3), bcs=bcs,
+                            rho0=p.rho0[idx].copy(), u0=p.u0[idx].copy(), v0=p.v0[idx].copy(),
+                            T0=p.T0[idx].copy())
+    return q, idx
