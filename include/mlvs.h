@@ -112,6 +112,29 @@ typedef struct {
     const mlvs_bc* bcs;
 } mlvs_mesh;
 
+/* Unstructured 2-D mesh (Sec. 2.2; the paper's two-cavity expansion runs on
+ * one).  Cells are counter-clockwise triangles or quadrilaterals: cell c has
+ * the nodes cell_node[cell_ptr[c] .. cell_ptr[c+1]-1] (3 or 4 of them,
+ * cell_ptr[0] = 0).  An edge shared by two cells is an interior face; an edge
+ * of one cell only is a boundary face and must appear in bedge as (node a,
+ * node b, boundary id into bcs), in either node order.  An edge of three or
+ * more cells, a clockwise or degenerate cell, an unlisted boundary edge or an
+ * id out of range is MLVS_E_ARG.  Every array is read during the call only.
+ * Slopes: least squares over the face neighbours (a boundary face adds a
+ * zero-gradient ghost at the mirror point), limited with Venkatakrishnan's
+ * function at the face centres, eps^2 = |V_c|^(3/2) phi_ref^2 with phi_ref the
+ * largest |phi| of the cell and its neighbours (Eq. reconstruction). */
+typedef struct {
+    int n_nodes, n_cells;
+    const double *node_x, *node_y;    /* [n_nodes] */
+    const int32_t *cell_ptr;          /* [n_cells + 1] */
+    const int32_t *cell_node;         /* [cell_ptr[n_cells]] */
+    int n_bedges;
+    const int32_t* bedge;             /* [n_bedges][3] */
+    int n_bc;
+    const mlvs_bc* bcs;
+} mlvs_umesh;
+
 /* Tensor base velocity grid V_base: xi_b = (x[ix], y[iy]), w_b = wx[ix] * wy[iy].
  * 1-D: ny = 1, y = {0}, wy = {1}. */
 typedef struct {
@@ -162,6 +185,14 @@ mlvs_status mlvs_mu_ref_from_kn(double Kn, double rho, double T, double R, doubl
  * velocity space).  Multi-level mode needs dim == 2. */
 mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const mlvs_vgrid* vgrid,
                         const mlvs_adapt_params* adapt, const mlvs_device* dev, mlvs_ctx* out);
+
+/* The same on an unstructured mesh (dim = 2).  Cells keep their input ids in
+ * every per-cell array of the ABI.  The learned selector's features (their
+ * density gradient uses index directions) are not defined here: mlvs_features
+ * and adaptation with a selector installed are MLVS_E_STATE on such a
+ * context. */
+mlvs_status mlvs_create_unstructured(const mlvs_physics* phys, const mlvs_umesh* mesh, const mlvs_vgrid* vgrid,
+                                     const mlvs_adapt_params* adapt, const mlvs_device* dev, mlvs_ctx* out);
 
 /* Initial state: g~ = g_eq, h~ = h_eq at (rho, u, v, T) per cell, with the
  * compatibility correction when enabled.  rho_u_v_T: [n_cells][4] host. */

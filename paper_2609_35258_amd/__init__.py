@@ -44,6 +44,13 @@ class mlvs_mesh(ctypes.Structure):
                 ("n_bc", ctypes.c_int), ("bcs", ctypes.POINTER(mlvs_bc))]
 
 
+class mlvs_umesh(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int), ("n_cells", ctypes.c_int), ("node_x", _c_double_p),
+                ("node_y", _c_double_p), ("cell_ptr", _c_int32_p), ("cell_node", _c_int32_p),
+                ("n_bedges", ctypes.c_int), ("bedge", _c_int32_p), ("n_bc", ctypes.c_int),
+                ("bcs", ctypes.POINTER(mlvs_bc))]
+
+
 class mlvs_vgrid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("x", _c_double_p), ("wx", _c_double_p),
                 ("y", _c_double_p), ("wy", _c_double_p)]
@@ -92,6 +99,9 @@ _PROTOS = {
     "mlvs_create": (ctypes.c_int, [ctypes.POINTER(mlvs_physics), ctypes.POINTER(mlvs_mesh),
                                    ctypes.POINTER(mlvs_vgrid), ctypes.POINTER(mlvs_adapt_params),
                                    ctypes.POINTER(mlvs_device), ctypes.POINTER(ctypes.c_void_p)]),
+    "mlvs_create_unstructured": (ctypes.c_int, [ctypes.POINTER(mlvs_physics), ctypes.POINTER(mlvs_umesh),
+                                                ctypes.POINTER(mlvs_vgrid), ctypes.POINTER(mlvs_adapt_params),
+                                                ctypes.POINTER(mlvs_device), ctypes.POINTER(ctypes.c_void_p)]),
     "mlvs_init_equilibrium": (ctypes.c_int, [ctypes.c_void_p, _c_double_p]),
     "mlvs_set_levels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_uint8_p, _c_int32_p]),
     "mlvs_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -241,11 +251,15 @@ def mlp_train(params, K, X, y, epochs=10, batch=4096, lr=1e-3, val_frac=0.2, see
 class Solver:
     """One MLVS-DUGKS context on the current torch CUDA (HIP) device and stream."""
 
-    def __init__(self, *, dim: int, node_x, node_y, periodic_i: bool, periodic_j: bool, bcs: Sequence,
-                 bc_imin, bc_imax, bc_jmin, bc_jmax, vx, vwx, vy, vwy, R: float, Pr: float, K: int,
-                 omega: float, mu_ref: float, T_ref: float, cfl: float, dt: float = 0.0,
+    def __init__(self, *, dim: int, bcs: Sequence, vx, vwx, vy, vwy, R: float, Pr: float, K: int,
+                 omega: float, mu_ref: float, T_ref: float, cfl: float, node_x=None, node_y=None,
+                 periodic_i: bool = False, periodic_j: bool = False, bc_imin=None, bc_imax=None, bc_jmin=None,
+                 bc_jmax=None, umesh: Optional[dict] = None, dt: float = 0.0,
                  precision: int = 64, compat: int = 4, face_compat: bool = True, map_moments: int = 4,
                  adapt: Optional[dict] = None, device=None, graph: bool = False, positivity: str = "keep"):
+        """Structured mesh: node_x, node_y ((nj+1, ni+1)), periodic flags and the
+        bc_* id arrays.  Unstructured mesh: umesh = dict(nodes (n, 2), cell_ptr,
+        cell_node, bedges (m, 3)) as in mlvs_umesh."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the MLVS library runs on the device only")
@@ -271,9 +285,6 @@ class Solver:
         self._alloc_cb = _ALLOC(_alloc)
         self._free_cb = _FREE(_free)
         dev = mlvs_device(ctypes.c_void_p(self.stream.cuda_stream), self._alloc_cb, self._free_cb, None)
-        node_x = np.ascontiguousarray(node_x, dtype=np.float64)
-        node_y = np.ascontiguousarray(node_y, dtype=np.float64)
-        nj, ni = node_x.shape[0] - 1, node_x.shape[1] - 1
         self._arrays = []
 
         def keep(a, dt_=np.float64):
@@ -286,8 +297,20 @@ class Solver:
             bc_arr[k] = mlvs_bc(int(b.kind), float(b.rho), float(b.u), float(b.v), float(b.T))
         self._bc_arr = bc_arr
         i32 = lambda a: keep(a, np.int32).ctypes.data_as(_c_int32_p)
-        mesh = mlvs_mesh(ni, nj, _dp(keep(node_x)), _dp(keep(node_y)), int(periodic_i), int(periodic_j),
-                         i32(bc_imin), i32(bc_imax), i32(bc_jmin), i32(bc_jmax), len(bcs), bc_arr)
+        if umesh is None:
+            node_x = np.ascontiguousarray(node_x, dtype=np.float64)
+            node_y = np.ascontiguousarray(node_y, dtype=np.float64)
+            nj, ni = node_x.shape[0] - 1, node_x.shape[1] - 1
+            mesh = mlvs_mesh(ni, nj, _dp(keep(node_x)), _dp(keep(node_y)), int(periodic_i), int(periodic_j),
+                             i32(bc_imin), i32(bc_imax), i32(bc_jmin), i32(bc_jmax), len(bcs), bc_arr)
+            n_cells = ni * nj
+        else:
+            nodes = np.asarray(umesh["nodes"], np.float64)
+            ptr = np.asarray(umesh["cell_ptr"], np.int32)
+            be = np.asarray(umesh["bedges"], np.int32).reshape(-1, 3)
+            n_cells = len(ptr) - 1
+            mesh = mlvs_umesh(len(nodes), n_cells, _dp(keep(nodes[:, 0])), _dp(keep(nodes[:, 1])), i32(ptr),
+                              i32(umesh["cell_node"]), len(be), i32(be), len(bcs), bc_arr)
         vg = mlvs_vgrid(len(vx), len(vy), _dp(keep(vx)), _dp(keep(vwx)), _dp(keep(vy)), _dp(keep(vwy)))
         if positivity not in ("keep", "exp"):
             raise ValueError("positivity must be 'keep' or 'exp'")
@@ -299,12 +322,13 @@ class Solver:
                                    adapt["tau_clust"], int(adapt.get("flux_test", False)),
                                    int(adapt.get("interval", 0)))
         h = ctypes.c_void_p()
-        _check(L.mlvs_create(ctypes.byref(phys), ctypes.byref(mesh), ctypes.byref(vg),
-                             ctypes.byref(ap) if ap is not None else None, ctypes.byref(dev), ctypes.byref(h)))
+        create = L.mlvs_create if umesh is None else L.mlvs_create_unstructured
+        _check(create(ctypes.byref(phys), ctypes.byref(mesh), ctypes.byref(vg),
+                      ctypes.byref(ap) if ap is not None else None, ctypes.byref(dev), ctypes.byref(h)))
         self.h = h
         if graph:
             _check(L.mlvs_set_graph(self.h, 1))
-        self.n_cells = ni * nj
+        self.n_cells = n_cells
         self.dim = dim
         dt_ = ctypes.c_double()
         nc = ctypes.c_int64()
@@ -329,6 +353,13 @@ class Solver:
         else:
             y, wy = x, w
         mu = mu_ref_from_kn(p.Kn, p.rho_ref, p.T_ref, p.R, p.L_ref, p.omega)
+        if getattr(p, "unstructured", False):
+            s = cls(dim=2, umesh=dict(nodes=p.nodes, cell_ptr=p.cell_ptr, cell_node=p.cell_node, bedges=p.bedges),
+                    bcs=p.bcs, vx=x, vwx=w, vy=y, vwy=wy, R=p.R, Pr=p.Pr, K=p.K, omega=p.omega, mu_ref=mu,
+                    T_ref=p.T_ref, cfl=p.cfl, dt=dt, precision=precision, compat=compat, face_compat=face_compat,
+                    map_moments=map_moments, adapt=adapt, graph=graph, positivity=positivity)
+            s.init_equilibrium(np.stack([p.rho0, p.u0, p.v0, p.T0], axis=1))
+            return s
         s = cls(dim=p.dim, node_x=p.X, node_y=p.Y, periodic_i=p.periodic_i, periodic_j=p.periodic_j,
                 bcs=p.bcs, bc_imin=p.bc_imin, bc_imax=p.bc_imax, bc_jmin=p.bc_jmin, bc_jmax=p.bc_jmax,
                 vx=x, vwx=w, vy=y, vwy=wy, R=p.R, Pr=p.Pr, K=p.K, omega=p.omega, mu_ref=mu, T_ref=p.T_ref,

@@ -454,6 +454,7 @@ struct FaceH {
 struct MeshH {
     int ni = 0, nj = 0, dim = 2, n_cells = 0;
     bool per_i = false, per_j = false;
+    bool unstructured = false;         // polygons: slots are local edges, slopes by least squares
     std::vector<double> vol, xc, yc;
     std::vector<FaceH> faces;          // interior faces
     std::vector<FaceH> bfaces;         // boundary faces (outward normal)
@@ -470,6 +471,8 @@ struct MeshH {
     std::vector<int> face_order, bface_order;   // faces and boundary faces by the rank of their left cell
 };
 
+void finish_order(MeshH& M);
+
 // Tiled traversal order of an ni x nj structured mesh (tw = 0: row-major).
 void tile_order(MeshH& M, int tw, int th) {
     const int ni = M.ni, nj = M.nj;
@@ -483,6 +486,11 @@ void tile_order(MeshH& M, int tw, int th) {
                 for (int j = tj; j < std::min(nj, tj + th); ++j)
                     for (int i = ti; i < std::min(ni, ti + tw); ++i) M.order.push_back(i + ni * j);
     }
+    finish_order(M);
+}
+
+// rank and face orders from M.order
+void finish_order(MeshH& M) {
     M.rank.assign(M.n_cells, 0);
     for (int k = 0; k < M.n_cells; ++k) M.rank[M.order[k]] = k;
     auto by_rank = [&M](const std::vector<FaceH>& fs, std::vector<int>& out) {
@@ -628,6 +636,161 @@ void build_mesh(MeshH& M, const mlvs_mesh& in, int dim) {
         for (int k = 0; k < 4; ++k)
             if (have[k]) M.hmin = std::min(M.hmin, 2.0 * std::hypot(cenx[k] - M.xc[c], ceny[k] - M.yc[c]));
     }
+}
+
+// Unstructured mesh (triangles and quadrilaterals).  Slot k of a cell is its
+// k-th edge (node k to node k+1).  An edge shared by two cells is an interior
+// face whose left cell is the one met first in cell order, with that cell's
+// outward normal; an edge of one cell is a boundary face and must be listed
+// with its boundary id.  Slopes: least squares over the face neighbours (a
+// boundary face adds a zero-gradient ghost at x_c + 2 (x_f - x_c)), limited by
+// Venkatakrishnan's function at every face centre, eps^2 = |V|^(3/2) times the
+// square of the stencil's largest |phi| (applied in the kernels).
+void build_umesh(MeshH& M, const mlvs_umesh& in) {
+    const int n = in.n_cells;
+    M.unstructured = true;
+    M.dim = 2; M.n_cells = n; M.ni = n; M.nj = 1;
+    M.vol.resize(n); M.xc.resize(n); M.yc.resize(n);
+    M.face_of_cell.assign(4 * n, -1);
+    M.bface_of_cell.assign(4 * n, -1);
+    auto node = [&](int v) {
+        if (v < 0 || v >= in.n_nodes) fail(MLVS_E_ARG, "node id %d out of range", v);
+        return std::make_pair(in.node_x[v], in.node_y[v]);
+    };
+    std::vector<int> nedge(n);
+    for (int c = 0; c < n; ++c) {
+        const int b = in.cell_ptr[c], e = in.cell_ptr[c + 1];
+        if (e - b != 3 && e - b != 4) fail(MLVS_E_ARG, "cell %d has %d nodes (3 or 4 supported)", c, e - b);
+        nedge[c] = e - b;
+        double a = 0, cx = 0, cy = 0;
+        for (int k = 0; k < e - b; ++k) {
+            const auto p0 = node(in.cell_node[b + k]), p1 = node(in.cell_node[b + (k + 1) % (e - b)]);
+            const double cr = p0.first * p1.second - p1.first * p0.second;
+            a += cr; cx += (p0.first + p1.first) * cr; cy += (p0.second + p1.second) * cr;
+        }
+        a *= 0.5;
+        if (!(a > 0)) fail(MLVS_E_ARG, "cell %d is not counter-clockwise", c);
+        M.vol[c] = a; M.xc[c] = cx / (6.0 * a); M.yc[c] = cy / (6.0 * a);
+    }
+    std::map<std::pair<int, int>, int> bid;
+    for (int k = 0; k < in.n_bedges; ++k) {
+        const int a = in.bedge[3 * k], b = in.bedge[3 * k + 1];
+        bid[std::make_pair(std::min(a, b), std::max(a, b))] = in.bedge[3 * k + 2];
+    }
+    // pair the edges: first owner -> (cell, slot)
+    std::map<std::pair<int, int>, std::pair<int, int>> open;
+    std::vector<std::array<int, 4>> fslot;        // interior face: L, kL, R, kR
+    for (int c = 0; c < n; ++c) {
+        const int b = in.cell_ptr[c], ne = nedge[c];
+        for (int k = 0; k < ne; ++k) {
+            const int v0 = in.cell_node[b + k], v1 = in.cell_node[b + (k + 1) % ne];
+            const auto key = std::make_pair(std::min(v0, v1), std::max(v0, v1));
+            if (v0 == v1) fail(MLVS_E_ARG, "cell %d has a repeated node", c);
+            auto it = open.find(key);
+            if (it == open.end()) {
+                open[key] = std::make_pair(c, k);
+            } else {
+                if (it->second.first < 0) fail(MLVS_E_ARG, "edge (%d, %d) is shared by more than two cells", v0, v1);
+                fslot.push_back({it->second.first, it->second.second, c, k});
+                it->second.first = -1;
+            }
+        }
+    }
+    auto edge_geom = [&](int c, int k, FaceH& f) {
+        const int b = in.cell_ptr[c], ne = nedge[c];
+        const auto p0 = node(in.cell_node[b + k]), p1 = node(in.cell_node[b + (k + 1) % ne]);
+        const double tx = p1.first - p0.first, ty = p1.second - p0.second;
+        f.area = std::hypot(tx, ty);
+        f.nx = ty / f.area; f.ny = -tx / f.area;        // outward for a counter-clockwise polygon
+        f.cx = 0.5 * (p0.first + p1.first); f.cy = 0.5 * (p0.second + p1.second);
+    };
+    std::sort(fslot.begin(), fslot.end());            // by left cell, then slot
+    for (auto& q : fslot) {
+        FaceH f{};
+        edge_geom(q[0], q[1], f);
+        f.L = q[0]; f.R = q[2]; f.bc = -1;
+        f.dLx = f.cx - M.xc[f.L]; f.dLy = f.cy - M.yc[f.L];
+        f.dRx = f.cx - M.xc[f.R]; f.dRy = f.cy - M.yc[f.R];
+        M.faces.push_back(f);
+        M.face_of_cell[4 * q[0] + q[1]] = (int)M.faces.size() - 1;
+        M.face_of_cell[4 * q[2] + q[3]] = (int)M.faces.size() - 1;
+    }
+    std::vector<std::pair<int, int>> bslot;
+    for (auto& kv : open)
+        if (kv.second.first >= 0) bslot.push_back(kv.second);
+    std::sort(bslot.begin(), bslot.end());
+    for (auto& q : bslot) {
+        const int b = in.cell_ptr[q.first], ne = nedge[q.first];
+        const int v0 = in.cell_node[b + q.second], v1 = in.cell_node[b + (q.second + 1) % ne];
+        auto it = bid.find(std::make_pair(std::min(v0, v1), std::max(v0, v1)));
+        if (it == bid.end()) fail(MLVS_E_ARG, "edge (%d, %d) has one cell and no boundary id", v0, v1);
+        FaceH f{};
+        edge_geom(q.first, q.second, f);
+        f.L = q.first; f.R = -1; f.bc = it->second;
+        f.dLx = f.cx - M.xc[f.L]; f.dLy = f.cy - M.yc[f.L];
+        if (f.bc < 0 || f.bc >= in.n_bc) fail(MLVS_E_ARG, "boundary id %d out of range", f.bc);
+        M.bfaces.push_back(f);
+        M.bface_of_cell[4 * q.first + q.second] = (int)M.bfaces.size() - 1;
+    }
+    // neighbours, least-squares coefficients, limiter geometry
+    M.nbr.assign(4 * n, -1);
+    M.geom.assign(n, CellGeom{});
+    for (int c = 0; c < n; ++c) {
+        CellGeom& g = M.geom[c];
+        g.vol = M.vol[c];
+        double ox[4] = {0, 0, 0, 0}, oy[4] = {0, 0, 0, 0};    // least-squares offsets
+        bool inner[4] = {false, false, false, false};
+        double A00 = 0, A01 = 0, A11 = 0;
+        for (int k = 0; k < 4; ++k) {
+            g.G[k] = 0.0; g.dist[k] = 1.0; g.inv_dist[k] = 1.0;
+            const int f = M.face_of_cell[4 * c + k], b = M.bface_of_cell[4 * c + k];
+            if (f >= 0) {
+                const FaceH& F = M.faces[f];
+                const bool isL = F.L == c;
+                g.fox[k] = isL ? F.dLx : F.dRx; g.foy[k] = isL ? F.dLy : F.dRy;
+                const int nb = isL ? F.R : F.L;
+                M.nbr[4 * c + k] = nb;
+                ox[k] = M.xc[nb] - M.xc[c]; oy[k] = M.yc[nb] - M.yc[c];
+                inner[k] = true;
+                g.dist[k] = std::hypot(ox[k], oy[k]); g.inv_dist[k] = 1.0 / g.dist[k];
+            } else if (b >= 0) {
+                g.fox[k] = M.bfaces[b].dLx; g.foy[k] = M.bfaces[b].dLy;
+                ox[k] = 2.0 * g.fox[k]; oy[k] = 2.0 * g.foy[k];
+            } else {
+                continue;
+            }
+            A00 += ox[k] * ox[k]; A01 += ox[k] * oy[k]; A11 += oy[k] * oy[k];
+            M.hmin = std::min(M.hmin, 2.0 * std::hypot(g.fox[k], g.foy[k]));
+        }
+        const double det = A00 * A11 - A01 * A01;
+        if (!(det > 0)) fail(MLVS_E_ARG, "cell %d: singular least-squares matrix", c);
+        for (int k = 0; k < 4; ++k) {
+            g.lx[k] = inner[k] ? (A11 * ox[k] - A01 * oy[k]) / det : 0.0;
+            g.ly[k] = inner[k] ? (-A01 * ox[k] + A00 * oy[k]) / det : 0.0;
+        }
+        const double h = std::sqrt(M.vol[c]);
+        g.eps2 = h * h * h;
+    }
+    // traversal order: Morton order of the cell centroids
+    double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+    for (int c = 0; c < n; ++c) {
+        x0 = std::min(x0, M.xc[c]); x1 = std::max(x1, M.xc[c]);
+        y0 = std::min(y0, M.yc[c]); y1 = std::max(y1, M.yc[c]);
+    }
+    const double span = std::max(std::max(x1 - x0, y1 - y0), 1e-300);
+    std::vector<std::pair<uint64_t, int>> key(n);
+    for (int c = 0; c < n; ++c) {
+        const uint32_t qx = (uint32_t)std::min(65535.0, std::floor((M.xc[c] - x0) / span * 65535.0));
+        const uint32_t qy = (uint32_t)std::min(65535.0, std::floor((M.yc[c] - y0) / span * 65535.0));
+        uint64_t z = 0;
+        for (int bit = 0; bit < 16; ++bit)
+            z |= (uint64_t)((qx >> bit) & 1u) << (2 * bit) | (uint64_t)((qy >> bit) & 1u) << (2 * bit + 1);
+        key[c] = std::make_pair(z, c);
+    }
+    std::sort(key.begin(), key.end());
+    M.order.resize(n);
+    for (int k = 0; k < n; ++k) M.order[k] = key[k].second;
+    finish_order(M);
 }
 
 }  // namespace
@@ -849,8 +1012,10 @@ void build_items(mlvs_ctx c) {
         const int lL = c->cell_level[F.L], lR = c->cell_level[F.R];
         int kL = -1, kR = -1;
         for (int k = 0; k < 4; ++k) {
-            if (M.face_of_cell[4 * F.L + k] == (int)f && (k == 1 || k == 3)) kL = k;
-            if (M.face_of_cell[4 * F.R + k] == (int)f && (k == 0 || k == 2)) kR = k;
+            // (a periodic mesh one cell wide has a face twice in one cell: then
+            // E/N is the left side, W/S the right one)
+            if (M.face_of_cell[4 * F.L + k] == (int)f && (M.unstructured || k == 1 || k == 3)) kL = k;
+            if (M.face_of_cell[4 * F.R + k] == (int)f && (M.unstructured || k == 0 || k == 2)) kR = k;
         }
         if (lL == lR) {
             FaceItem it{};
@@ -1332,6 +1497,7 @@ void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
 }
 
 void compute_features(mlvs_ctx c, float* d_out) {
+    if (c->mesh.unstructured) fail(MLVS_E_STATE, "the selector's features need a structured mesh");
     const int n = c->mesh.n_cells;
     double* d8 = static_cast<double*>(c->dm.alloc(sizeof(double) * 8 * (size_t)n));
     hip_check(launch_cell_moments(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom, c->ph,
@@ -1676,11 +1842,13 @@ mlvs_status mlvs_mu_ref_from_kn(double Kn, double rho, double T, double R, doubl
     });
 }
 
-mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const mlvs_vgrid* vg,
-                        const mlvs_adapt_params* adapt, const mlvs_device* dev, mlvs_ctx* out) {
+// One of mesh (structured) and umesh (unstructured) is given.
+static mlvs_status create_impl(const mlvs_physics* phys, const mlvs_mesh* mesh, const mlvs_umesh* umesh,
+                               const mlvs_vgrid* vg, const mlvs_adapt_params* adapt, const mlvs_device* dev,
+                               mlvs_ctx* out) {
     mlvs_ctx c = nullptr;
     mlvs_status s = guarded([&] {
-        if (!phys || !mesh || !vg || !out) fail(MLVS_E_ARG, "null argument");
+        if (!phys || (!mesh && !umesh) || !vg || !out) fail(MLVS_E_ARG, "null argument");
         if (phys->dim != 1 && phys->dim != 2) fail(MLVS_E_ARG, "dim must be 1 or 2");
         if (phys->precision != 32 && phys->precision != 64) fail(MLVS_E_ARG, "precision must be 32 or 64");
         if (phys->compat != 0 && phys->compat != 4 && phys->compat != 8) fail(MLVS_E_ARG, "compat must be 0, 4 or 8");
@@ -1692,9 +1860,21 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         if (phys->positivity == 1 && phys->map_moments != 4)
             fail(MLVS_E_ARG, "the exponential fallback needs map_moments = 4");
         if (!(phys->R > 0) || !(phys->mu_ref > 0) || !(phys->T_ref > 0)) fail(MLVS_E_ARG, "bad physical constants");
-        if (mesh->ni < 1 || mesh->nj < 1 || !mesh->node_x || !mesh->node_y) fail(MLVS_E_ARG, "bad mesh");
-        if (phys->dim == 1 && mesh->nj != 1) fail(MLVS_E_ARG, "1-D meshes need nj = 1");
-        if ((int64_t)mesh->ni * mesh->nj > (1 << 30)) fail(MLVS_E_ARG, "mesh too large");
+        if (mesh) {
+            if (mesh->ni < 1 || mesh->nj < 1 || !mesh->node_x || !mesh->node_y) fail(MLVS_E_ARG, "bad mesh");
+            if (phys->dim == 1 && mesh->nj != 1) fail(MLVS_E_ARG, "1-D meshes need nj = 1");
+            if ((int64_t)mesh->ni * mesh->nj > (1 << 30)) fail(MLVS_E_ARG, "mesh too large");
+        } else {
+            if (phys->dim != 2) fail(MLVS_E_ARG, "unstructured meshes need dim = 2");
+            if (umesh->n_cells < 1 || umesh->n_nodes < 3 || !umesh->node_x || !umesh->node_y || !umesh->cell_ptr ||
+                !umesh->cell_node || (umesh->n_bedges > 0 && !umesh->bedge) || umesh->n_bedges < 0 ||
+                (umesh->n_bc > 0 && !umesh->bcs) || umesh->n_bc < 0)
+                fail(MLVS_E_ARG, "bad mesh");
+            if (umesh->n_cells > (1 << 28)) fail(MLVS_E_ARG, "mesh too large");
+            if (umesh->cell_ptr[0] != 0) fail(MLVS_E_ARG, "cell_ptr[0] must be 0");
+            for (int k = 0; k < umesh->n_cells; ++k)
+                if (umesh->cell_ptr[k + 1] < umesh->cell_ptr[k]) fail(MLVS_E_ARG, "cell_ptr must not decrease");
+        }
         if (!vg->x || !vg->wx || vg->nx < 2 || vg->ny < 1 || !vg->y || !vg->wy) fail(MLVS_E_ARG, "bad velocity grid");
         if (phys->dim == 1 && vg->ny != 1) fail(MLVS_E_ARG, "1-D needs ny = 1");
         if (adapt && phys->dim != 2) fail(MLVS_E_ARG, "multi-level velocity spaces need dim = 2");
@@ -1706,8 +1886,9 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         if (dev) { c->dm.dev = *dev; c->st = (hipStream_t)dev->stream; }
         c->adaptive = adapt != nullptr;
         if (adapt) c->ap = *adapt;
-        build_mesh(c->mesh, *mesh, phys->dim);
-        {
+        if (umesh) build_umesh(c->mesh, *umesh);
+        else build_mesh(c->mesh, *mesh, phys->dim);
+        if (mesh) {
             // traversal tiles (MLVS_TILE=WxH overrides; 0 = row-major)
             int tw = 16, th = 8;
             if (const char* e = std::getenv("MLVS_TILE")) {
@@ -1717,7 +1898,8 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
             if (phys->dim != 2) tw = th = 0;
             tile_order(c->mesh, tw, th);
         }
-        c->bcs.assign(mesh->bcs, mesh->bcs + mesh->n_bc);
+        if (mesh) c->bcs.assign(mesh->bcs, mesh->bcs + mesh->n_bc);
+        else c->bcs.assign(umesh->bcs, umesh->bcs + umesh->n_bc);
         for (auto& b : c->bcs)
             if (b.kind < 1 || b.kind > 3) fail(MLVS_E_ARG, "unknown boundary kind %d", b.kind);
         Base& B = c->base;
@@ -1738,6 +1920,7 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         ph.dt = phys->dt > 0 ? phys->dt : phys->cfl * c->mesh.hmin / vmax;
         ph.compat = phys->compat; ph.face_compat = phys->face_compat; ph.map_moments = phys->map_moments;
         ph.positivity = phys->positivity;
+        ph.mesh_kind = c->mesh.unstructured ? 1 : 0;
         // device geometry
         c->d_geom = upload(c->dm, c->mesh.geom, c->st);
         c->d_nbr_cell = upload(c->dm, c->mesh.nbr, c->st);
@@ -1775,6 +1958,18 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
         delete c;
     }
     return s;
+}
+
+mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const mlvs_vgrid* vg,
+                        const mlvs_adapt_params* adapt, const mlvs_device* dev, mlvs_ctx* out) {
+    if (!mesh) return guarded([&] { fail(MLVS_E_ARG, "null argument"); });
+    return create_impl(phys, mesh, nullptr, vg, adapt, dev, out);
+}
+
+mlvs_status mlvs_create_unstructured(const mlvs_physics* phys, const mlvs_umesh* mesh, const mlvs_vgrid* vg,
+                                     const mlvs_adapt_params* adapt, const mlvs_device* dev, mlvs_ctx* out) {
+    if (!mesh) return guarded([&] { fail(MLVS_E_ARG, "null argument"); });
+    return create_impl(phys, nullptr, mesh, vg, adapt, dev, out);
 }
 
 void mlvs_destroy(mlvs_ctx c) {

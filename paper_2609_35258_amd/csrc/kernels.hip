@@ -12,6 +12,7 @@
 #include "mlvs_impl.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace mlvs {
 
@@ -1043,8 +1044,8 @@ __device__ __forceinline__ Eq<double> face_target(const LevelDesc& L, double* m,
 template <typename S>
 struct Stencil { S v[2][5]; };
 
-template <typename S>
-__device__ __forceinline__ void load_stencil(const Side<S>& a, const Side<S>& b, bool useA, int i, Stencil<S>& st) {
+template <typename S, typename SD>
+__device__ __forceinline__ void load_stencil(const SD& a, const SD& b, bool useA, int i, Stencil<S>& st) {
 #pragma unroll
     for (int comp = 0; comp < 2; ++comp) {
         const auto B = a.base[comp] + i;
@@ -1096,8 +1097,8 @@ __device__ __forceinline__ FaceState face_state(const double* mm, double u0, dou
 }
 
 // The same with one side for the whole wavefront (no per-lane choice).
-template <typename S>
-__device__ __forceinline__ void load_stencil1(const Side<S>& a, int i, Stencil<S>& st) {
+template <typename S, typename SD>
+__device__ __forceinline__ void load_stencil1(const SD& a, int i, Stencil<S>& st) {
 #pragma unroll
     for (int comp = 0; comp < 2; ++comp) {
         const auto B = a.base[comp] + i;
@@ -1121,6 +1122,133 @@ __device__ __forceinline__ void stencil_ext1(const Side<S>& a, const Stencil<S>&
     eh = e[1];
 }
 
+// ---------------------------------------------------------------------------
+// Unstructured meshes (triangles and quadrilaterals): the stencil is the cell
+// and its face neighbours (slot k = the cell's k-th edge; a missing neighbour
+// reads the cell's own row, a zero difference).  The gradient is the least-
+// squares fit over the face neighbours, a boundary face adding a zero-gradient
+// ghost at the mirror point (its weight sits in the precomputed coefficients),
+// limited by psi = min(1, min over faces of V(d+, d-)) with Venkatakrishnan's
+// V(d+, d-) = (d+^2 + eps^2 + 2 d- d+) / (d+^2 + 2 d-^2 + d- d+ + eps^2),
+// d- = grad . (x_f - x_c), d+ the largest (d- > 0) or smallest (d- < 0)
+// neighbour difference including zero; faces with d- = 0 impose nothing.
+// eps^2 = |V_c|^(3/2) phi_ref^2, phi_ref the largest |phi| of the stencil
+// (relative, since distribution values span many orders of magnitude).
+// ---------------------------------------------------------------------------
+template <typename S>
+struct USide {
+    gptr<const S> base[2];
+    size_t off[5];                  // own row, then the four slots
+    S lx[4], ly[4];                 // least-squares coefficients per slot
+    S fx[4], fy[4];                 // x_f - x_c per slot (0: no face)
+    S eps2;                         // |V_c|^(3/2), to be scaled by phi_ref^2
+    S dx, dy;                       // x_f - x_cell of the face being reconstructed
+};
+
+template <typename S>
+__device__ __forceinline__ void load_side(USide<S>& sd, const LevelDesc& L, int cell, const int* cell_slot,
+                                          const int* cell_nbr, const CellGeom* geom, double dx, double dy) {
+    sd.base[0] = gp(reinterpret_cast<const S*>(L.fg));
+    sd.base[1] = gp(reinterpret_cast<const S*>(L.fh));
+    const size_t own = (size_t)cell_slot[cell] * L.stride;
+    sd.off[0] = own;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sd.off[k + 1] = nb_off(L, cell_nbr[4 * cell + k], cell_slot, own);
+    const CellGeom& gm = geom[cell];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        sd.lx[k] = (S)gm.lx[k]; sd.ly[k] = (S)gm.ly[k];
+        sd.fx[k] = (S)gm.fox[k]; sd.fy[k] = (S)gm.foy[k];
+    }
+    sd.eps2 = (S)gm.eps2;
+    sd.dx = (S)dx; sd.dy = (S)dy;
+}
+
+// Limited gradient (sx, sy) from the stencil values v (own, slots 0..3).  The
+// smallest V is tracked as a fraction (cross-multiplied compares, positive
+// denominators), so one division gives psi.
+template <typename S>
+__device__ __forceinline__ void venkat_slope(const S (&lx)[4], const S (&ly)[4], const S (&fx)[4], const S (&fy)[4],
+                                             S eps2, const S (&v)[5], S& sx, S& sy) {
+    const S fc = v[0];
+    S gx = S(0), gy = S(0), dmax = S(0), dmin = S(0), ref = fabs(fc);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const S d = v[k + 1] - fc;
+        gx += lx[k] * d;
+        gy += ly[k] * d;
+        dmax = d > dmax ? d : dmax;
+        dmin = d < dmin ? d : dmin;
+        ref = fmax(ref, fabs(v[k + 1]));
+    }
+    eps2 = eps2 * ref * ref;
+    S bn = S(1), bd = S(1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const S dm = gx * fx[k] + gy * fy[k];
+        const S dp = dm > S(0) ? dmax : dmin;
+        const S num = dp * dp + eps2 + S(2) * dm * dp;
+        const S den = dp * dp + S(2) * dm * dm + dm * dp + eps2;
+        if (dm != S(0) && num * bd < bn * den) { bn = num; bd = den; }
+    }
+    const S psi = bn / bd;
+    sx = psi * gx;
+    sy = psi * gy;
+}
+
+template <typename S>
+__device__ __forceinline__ void side_slope(const USide<S>& sd, int i, S (&f)[2], S (&sx)[2], S (&sy)[2]) {
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        const auto B = sd.base[comp] + i;
+        S v[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) v[k] = B[sd.off[k]];
+        f[comp] = v[0];
+        venkat_slope<S>(sd.lx, sd.ly, sd.fx, sd.fy, sd.eps2, v, sx[comp], sy[comp]);
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ void stencil_ext(const USide<S>& a, const USide<S>& b, bool useA, const Stencil<S>& st,
+                                            S x, S y, S s, S& eg, S& eh) {
+    S lx[4], ly[4], fx[4], fy[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        lx[k] = useA ? a.lx[k] : b.lx[k]; ly[k] = useA ? a.ly[k] : b.ly[k];
+        fx[k] = useA ? a.fx[k] : b.fx[k]; fy[k] = useA ? a.fy[k] : b.fy[k];
+    }
+    const S eps2 = useA ? a.eps2 : b.eps2;
+    const S ax = (useA ? a.dx : b.dx) - x * s, ay = (useA ? a.dy : b.dy) - y * s;
+    S e[2];
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        S sx, sy;
+        venkat_slope<S>(lx, ly, fx, fy, eps2, st.v[comp], sx, sy);
+        e[comp] = st.v[comp][0] + ax * sx + ay * sy;
+    }
+    eg = e[0];
+    eh = e[1];
+}
+
+template <typename S>
+__device__ __forceinline__ void stencil_ext1(const USide<S>& a, const Stencil<S>& st, S x, S y, S s, S& eg, S& eh) {
+    const S ax = a.dx - x * s, ay = a.dy - y * s;
+    S e[2];
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        S sx, sy;
+        venkat_slope<S>(a.lx, a.ly, a.fx, a.fy, a.eps2, st.v[comp], sx, sy);
+        e[comp] = st.v[comp][0] + ax * sx + ay * sy;
+    }
+    eg = e[0];
+    eh = e[1];
+}
+
+// The side type of a mesh kind (0 structured, 1 unstructured).
+template <typename S, int MK>
+using SideOf = typename std::conditional<MK == 1, USide<S>, Side<S>>::type;
+
 // Face stage, part 1 (reconstruction): for every same-level interior face and
 // every boundary face, the interface value phi_bar_f = phi_bar+_up + (x_f -
 // x_up - xi s) . sigma_up (both sides averaged where xi . n = 0) is written to
@@ -1128,7 +1256,7 @@ __device__ __forceinline__ void stencil_ext1(const Side<S>& a, const Stencil<S>&
 // (about the mean of the two cell velocities); boundary faces reduce the
 // outgoing mass flux.  Per-face results go to fmom[item][NFMOM] (the moments,
 // then the velocity shift they are taken about).
-template <typename S, int U>
+template <typename S, int U, int MK>
 __device__ __forceinline__ void face_rec_points(const LevelDesc& L, const FaceItem& F, const int* cell_slot,
                                                 const int* cell_nbr, const CellGeom* geom, const double* params,
                                                 const Phys& ph, int beg, int N, double (&m)[11], double& u0,
@@ -1136,10 +1264,10 @@ __device__ __forceinline__ void face_rec_points(const LevelDesc& L, const FaceIt
     const S s = (S)(0.5 * ph.dt);
     auto rg = rowp<S>(L.Fg, (size_t)F.row * L.stride);
     auto rh = rowp<S>(L.Fh, (size_t)F.row * L.stride);
-    Side<S> sL;
+    SideOf<S, MK> sL;
     load_side<S>(sL, L, F.L, cell_slot, cell_nbr, geom, F.dLx, F.dLy);
     const bool interior = F.R >= 0;
-    Side<S> sR = sL;
+    SideOf<S, MK> sR = sL;
     u0 = 0.0;
     v0 = 0.0;
     if (interior) {
@@ -1169,7 +1297,7 @@ __device__ __forceinline__ void face_rec_points(const LevelDesc& L, const FaceIt
         const int side = !interior ? 0 : (__all(allL) ? 0 : (__all(allR) ? 1 : 2));
         S eg[U], eh[U];
         if (side < 2) {
-            const Side<S>& sd = side == 0 ? sL : sR;
+            const SideOf<S, MK>& sd = side == 0 ? sL : sR;
             Stencil<S> st[U];
 #pragma unroll
             for (int q = 0; q < U; ++q) load_stencil1<S>(sd, clampi(i0 + q * WL, N), st[q]);
@@ -1213,7 +1341,7 @@ __device__ __forceinline__ void face_rec_points(const LevelDesc& L, const FaceIt
     }
 }
 
-template <typename S, int U, int MINW>
+template <typename S, int U, int MINW, int MK>
 __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restrict__ lvs,
                                                        const FaceItem* __restrict__ items, int nF,
                                                        const int* __restrict__ cell_slot,
@@ -1230,7 +1358,7 @@ __global__ __launch_bounds__(BS, MINW) void k_face_rec(const LevelDesc* __restri
         if (beg >= L.N) continue;
         const int N = min(L.N, beg + CH);      // end of this chunk
         double m[11], u0, v0;
-        face_rec_points<S, U>(L, F, cell_slot, cell_nbr, geom, params, ph, beg, N, m, u0, v0);
+        face_rec_points<S, U, MK>(L, F, cell_slot, cell_nbr, geom, params, ph, beg, N, m, u0, v0);
         double* out = fmom + (size_t)it * NFMOM;
         wave_sum<11>(m);
         if (lane_id() < 11) {
@@ -1391,7 +1519,7 @@ __global__ __launch_bounds__(GBS, MINW) void k_face_target(const LevelDesc* __re
 // level sets whose levels fit one velocity chunk, where the reconstruction has
 // no chunk partials to add and the staged target's per-workgroup hand-overs
 // would dominate.  Same arithmetic as k_face_rec + k_face_target.
-template <typename S, int U, int MINW, int CM>
+template <typename S, int U, int MINW, int CM, int MK>
 __global__ __launch_bounds__(BS, MINW) void k_face_full(const LevelDesc* __restrict__ lvs,
                                                         const FaceItem* __restrict__ items, int nF,
                                                         const int* __restrict__ cell_slot,
@@ -1404,7 +1532,7 @@ __global__ __launch_bounds__(BS, MINW) void k_face_full(const LevelDesc* __restr
         const FaceItem F = items[f];
         const LevelDesc& L = lvs[F.lev];
         double m[11], u0, v0;
-        face_rec_points<S, U>(L, F, cell_slot, cell_nbr, geom, params, ph, 0, L.N, m, u0, v0);
+        face_rec_points<S, U, MK>(L, F, cell_slot, cell_nbr, geom, params, ph, 0, L.N, m, u0, v0);
         wave_sum<11>(m);
         double kind = 0.0, c1, c2;
         Eq<double> e;
@@ -1818,6 +1946,51 @@ constexpr int N_VARIANTS = 4;
         else MLVS_DISPATCH_VC1(prec, var, 4, KERNEL, __VA_ARGS__);                               \
     } while (0)
 
+// ... and per mesh kind (unstructured meshes: the (1, 4) and (2, 4) pairs only)
+#define MLVS_LAUNCH_UWM(prec, KERNEL, U_, W_, M_, ...)                                           \
+    do {                                                                                        \
+        if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, U_, W_, M_>), __VA_ARGS__);          \
+        else hipLaunchKernelGGL((KERNEL<double, U_, W_, M_>), __VA_ARGS__);                      \
+    } while (0)
+#define MLVS_DISPATCH_VM(prec, var, mk, KERNEL, ...)                                             \
+    do {                                                                                        \
+        if (mk) {                                                                               \
+            if ((var) == 0) MLVS_LAUNCH_UWM(prec, KERNEL, 1, 4, 1, __VA_ARGS__);                 \
+            else MLVS_LAUNCH_UWM(prec, KERNEL, 2, 4, 1, __VA_ARGS__);                            \
+        } else {                                                                                \
+            switch (var) {                                                                      \
+            case 0: MLVS_LAUNCH_UWM(prec, KERNEL, 1, 4, 0, __VA_ARGS__); break;                  \
+            case 2: MLVS_LAUNCH_UWM(prec, KERNEL, 4, 2, 0, __VA_ARGS__); break;                  \
+            case 3: MLVS_LAUNCH_UWM(prec, KERNEL, 4, 4, 0, __VA_ARGS__); break;                  \
+            default: MLVS_LAUNCH_UWM(prec, KERNEL, 2, 4, 0, __VA_ARGS__); break;                 \
+            }                                                                                   \
+        }                                                                                       \
+    } while (0)
+#define MLVS_LAUNCH_UWCM(prec, KERNEL, U_, W_, C_, M_, ...)                                      \
+    do {                                                                                        \
+        if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, U_, W_, C_, M_>), __VA_ARGS__);      \
+        else hipLaunchKernelGGL((KERNEL<double, U_, W_, C_, M_>), __VA_ARGS__);                  \
+    } while (0)
+#define MLVS_DISPATCH_VCM1(prec, var, C_, mk, KERNEL, ...)                                       \
+    do {                                                                                        \
+        if (mk) {                                                                               \
+            if ((var) == 0) MLVS_LAUNCH_UWCM(prec, KERNEL, 1, 4, C_, 1, __VA_ARGS__);            \
+            else MLVS_LAUNCH_UWCM(prec, KERNEL, 2, 4, C_, 1, __VA_ARGS__);                       \
+        } else {                                                                                \
+            switch (var) {                                                                      \
+            case 0: MLVS_LAUNCH_UWCM(prec, KERNEL, 1, 4, C_, 0, __VA_ARGS__); break;             \
+            case 2: MLVS_LAUNCH_UWCM(prec, KERNEL, 4, 2, C_, 0, __VA_ARGS__); break;             \
+            case 3: MLVS_LAUNCH_UWCM(prec, KERNEL, 4, 4, C_, 0, __VA_ARGS__); break;             \
+            default: MLVS_LAUNCH_UWCM(prec, KERNEL, 2, 4, C_, 0, __VA_ARGS__); break;            \
+            }                                                                                   \
+        }                                                                                       \
+    } while (0)
+#define MLVS_DISPATCH_VCM(prec, var, cm, mk, KERNEL, ...)                                        \
+    do {                                                                                        \
+        if ((cm) == 8) MLVS_DISPATCH_VCM1(prec, var, 8, mk, KERNEL, __VA_ARGS__);                \
+        else MLVS_DISPATCH_VCM1(prec, var, 4, mk, KERNEL, __VA_ARGS__);                          \
+    } while (0)
+
 int variant_count() { return N_VARIANTS; }
 
 #define MLVS_DISPATCH(prec, KERNEL, ...)                                                        \
@@ -1865,8 +2038,8 @@ hipError_t launch_face_rec(int prec, hipStream_t st, const LevelDesc* lv, const 
                            const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
                            Phys ph, double* fmom, int CH, int nch, int var) {
     if (n <= 0) return hipSuccess;
-    MLVS_DISPATCH_V(prec, var, k_face_rec, dim3(grid_for(n * nch)), dim3(BS), 0, st, lv, items, n, cell_slot,
-                    cell_nbr, geom, params, ph, fmom, CH, nch);
+    MLVS_DISPATCH_VM(prec, var, ph.mesh_kind, k_face_rec, dim3(grid_for(n * nch)), dim3(BS), 0, st, lv, items, n,
+                     cell_slot, cell_nbr, geom, params, ph, fmom, CH, nch);
     return hipGetLastError();
 }
 
@@ -1882,8 +2055,8 @@ hipError_t launch_face_full(int prec, hipStream_t st, const LevelDesc* lv, const
                             const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
                             const BCDev* bcs, Phys ph, double* fpar, int var) {
     if (n <= 0) return hipSuccess;
-    MLVS_DISPATCH_VC(prec, var, ph.compat, k_face_full, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot,
-                     cell_nbr, geom, params, bcs, ph, fpar);
+    MLVS_DISPATCH_VCM(prec, var, ph.compat, ph.mesh_kind, k_face_full, dim3(grid_for(n)), dim3(BS), 0, st, lv, items,
+                      n, cell_slot, cell_nbr, geom, params, bcs, ph, fpar);
     return hipGetLastError();
 }
 
@@ -1938,8 +2111,8 @@ hipError_t launch_remap(int prec, hipStream_t st, const LevelDesc* old_lv, const
 // ---------------------------------------------------------------------------
 
 // phi_bar+ and slope of one side at interface point P (parent a on the native level).
-template <typename S>
-__device__ __forceinline__ void side_refined(const Side<S>& sd, const LevelDesc& Ln, const LevelDesc& LI, int a,
+template <typename S, typename SD>
+__device__ __forceinline__ void side_refined(const SD& sd, const LevelDesc& Ln, const LevelDesc& LI, int a,
                                              int P, S (&f)[2], S (&sx)[2], S (&sy)[2]) {
     side_slope<S>(sd, a, f, sx, sy);
     const double xa = gp(Ln.xi_x)[a], ya = gp(Ln.xi_y)[a], xP = gp(LI.xi_x)[P], yP = gp(LI.xi_y)[P];
@@ -1949,7 +2122,7 @@ __device__ __forceinline__ void side_refined(const Side<S>& sd, const LevelDesc&
     sy[1] = sy[1] + dq * sy[0];
 }
 
-template <typename S, int U, int MINW>
+template <typename S, int U, int MINW, int MK>
 __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict__ lvs, const XFaceItem* __restrict__ items,
                                               int n, const int* __restrict__ cell_slot,
                                               const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
@@ -1960,7 +2133,7 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
         const LevelDesc& LA = lvs[F.levA];
         const LevelDesc& LB = lvs[F.levB];
         const LevelDesc& LI = lvs[F.levI];
-        Side<S> sL, sR;
+        SideOf<S, MK> sL, sR;
         load_side<S>(sL, LA, F.L, cell_slot, cell_nbr, geom, F.dLx, F.dLy);
         load_side<S>(sR, LB, F.R, cell_slot, cell_nbr, geom, F.dRx, F.dRy);
         const double TL = params[(size_t)F.L * NPARAM + P_T], TR = params[(size_t)F.R * NPARAM + P_T];
@@ -1972,7 +2145,7 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
             const double x = gp(LI.xi_x)[P], y = gp(LI.xi_y)[P], w = gp(LI.w)[P];
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
-                const Side<S>& sd = side ? sR : sL;
+                const SideOf<S, MK>& sd = side ? sR : sL;
                 const LevelDesc& Ln = side ? LB : LA;
                 const PairTable& tb = side ? F.IfromB : F.IfromA;
                 const int a = gp(tb.idx)[gp(tb.off)[P]];
@@ -2011,7 +2184,7 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
             S e[2][2];
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
-                const Side<S>& sd = side ? sR : sL;
+                const SideOf<S, MK>& sd = side ? sR : sL;
                 const LevelDesc& Ln = side ? LB : LA;
                 const PairTable& tb = side ? F.IfromB : F.IfromA;
                 const int a = gp(tb.idx)[gp(tb.off)[P]];
@@ -2306,8 +2479,8 @@ hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFa
                         const int* cell_slot, const int* cell_nbr, const CellGeom* geom, const double* params,
                         Phys ph, unsigned long long* neg, int var) {
     if (n <= 0) return hipSuccess;
-    MLVS_DISPATCH_V(prec, var, k_xface, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot, cell_nbr, geom, params,
-                  ph, neg);
+    MLVS_DISPATCH_VM(prec, var, ph.mesh_kind, k_xface, dim3(grid_for(n)), dim3(BS), 0, st, lv, items, n, cell_slot,
+                     cell_nbr, geom, params, ph, neg);
     return hipGetLastError();
 }
 

@@ -65,6 +65,7 @@ struct Phys {
     double R, Pr, omega, mu_ref, T_ref, dt;
     int compat, face_compat, map_moments;
     int positivity;                 // 1: exponential fallback of distribution maps
+    int mesh_kind;                  // 0 structured (van Leer per index direction), 1 unstructured
 };
 
 // Encoded neighbour: >= 0 same-level cell id; -1 none (boundary);
@@ -74,6 +75,10 @@ struct CellGeom {
     double G[4];       // inverse of [t_i; t_j] (row-major)
     double dist[4];    // |x_n - x_c| for W, E, S, N (1 when absent)
     double inv_dist[4];  // 1 / dist
+    // unstructured meshes (slot k = the cell's k-th edge):
+    double lx[4], ly[4];    // least-squares gradient = sum_k (lx, ly)[k] (phi_k - phi_c) (0: no neighbour)
+    double fox[4], foy[4];  // x_f - x_c of each face (0: no face)
+    double eps2;            // Venkatakrishnan's eps^2
 };
 
 struct FaceItem {      // same-level interior face (R >= 0) or boundary face (R = -1 - bc id)

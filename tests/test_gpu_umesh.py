@@ -1,0 +1,173 @@
+"""GPU parity of the unstructured-mesh path (triangles and quadrilaterals,
+least-squares slopes with Venkatakrishnan's limiter) against the oracle.
+
+* Two-cavity expansion (1000:1 density jump, mixed triangles and channel
+  quadrilaterals) and a lid-driven cavity cut into triangles: FP64 UVS steps,
+  <= 1e-12 of the largest value, in velocity chunks of 64 (staged step) and
+  whole rows (fused step).
+* Multi-level FP64: a fixed catalogue from the oracle's criterion and
+  grouping on a perturbed state (four- and nine-moment mapping, four- and
+  eight-moment compatibility), and criterion adaptation inside the step
+  loop.
+* FP32 storage: fields within 1e-5 relative L2 after a few steps.
+* Full size (two-cavity at lattice spacing 1/48: 9504 cells, 101^2 velocity
+  points, FP32, UVS and MLVS): sampled cells against an oracle step of the
+  two-neighbour-ring patch around each (a cell's update reads its faces'
+  upwind cells and their face neighbours only), <= 1e-6 of the largest value.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import levels as lv
+from oracle.solver import AdaptParams
+from oracle.solver import Solver as Oracle
+from tests.parity import rel_l2, state_error
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _gpu(p, **kw):
+    import paper_2609_35258_amd as m
+    return m.Solver.from_problem(p, **kw)
+
+
+def _tri_cavity(n=8, nv=12):
+    p = W.perturb(W.cavity(n, Kn=0.05, nv=nv, vel_kind="nc", vmax=5.0), seed=4, amp=0.05)
+    return W.as_unstructured(p, split="random", seed=5)
+
+
+@pytest.mark.parametrize("chunk", ["64", None])
+@pytest.mark.parametrize("case", ["two_cavity", "tri_cavity"])
+def test_uvs_fp64(case, chunk, monkeypatch):
+    if chunk:
+        monkeypatch.setenv("MLVS_CHUNK", chunk)
+    else:
+        monkeypatch.delenv("MLVS_CHUNK", raising=False)
+    p = W.two_cavity(16, nv=16, vmax=7.0) if case == "two_cavity" else _tri_cavity()
+    print("case uvs", case, chunk, p.n_cells, flush=True)
+    o = Oracle(p, compat=4)
+    g = _gpu(p, compat=4)
+    assert abs(g.dt - o.dt) < 1e-15 * o.dt
+    t0 = g.totals()
+    for k in range(3):
+        o.step()
+        g.step(1)
+        e = state_error(g.get_state(), o.g, o.h)
+        assert max(e) < TOL, (k, e)
+    assert abs(g.totals()[0] - t0[0]) < 1e-13 * t0[0]
+    g.close()
+
+
+def _perturbed(ratio=0.05):
+    return W.perturb(W.two_cavity(16, nv=16, vmax=7.0, ratio=ratio), seed=3, amp=0.3)
+
+
+@pytest.mark.parametrize("map_moments,compat", [(4, 4), (9, 8)])
+def test_mlvs_fixed_catalog_fp64(map_moments, compat, monkeypatch):
+    # catalogue from the oracle's criterion + grouping on a perturbed state
+    monkeypatch.setenv("MLVS_CHUNK", "64")
+    p = _perturbed()
+    print("case mlvs fixed", map_moments, compat, flush=True)
+    o1 = Oracle(p, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 1e-3, 0.02, True, 100))
+    kap, cl = lv.cluster_masks(o1.criterion_masks(), 0.02)
+    assert len(kap) >= 3
+    o = Oracle(p, compat=compat, map_moments=map_moments)
+    g = _gpu(p, compat=compat, map_moments=map_moments)
+    o.set_levels(kap, cl)
+    g.set_levels(np.stack(kap), cl)
+    e = state_error(g.get_state(), o.g, o.h)
+    assert max(e) < TOL, ("remap", e)
+    _, _, ncross = g.level_info()
+    assert ncross > 0
+    t0 = g.totals()
+    for k in range(3):
+        o.step()
+        g.step(1)
+        e = state_error(g.get_state(), o.g, o.h)
+        assert max(e) < TOL, (k, e)
+    assert abs(g.totals()[0] - t0[0]) < 1e-13 * t0[0]       # walls exchange momentum and energy only
+    g.close()
+
+
+def test_mlvs_criterion_adaptation_fp64():
+    p = _perturbed()
+    print("case mlvs adapt", flush=True)
+    ap = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=1e-3, tau_clust=0.02, flux_test=True, interval=2)
+    o = Oracle(p, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 1e-3, 0.02, True, 2))
+    g = _gpu(p, compat=4, adapt=ap)
+    for k in range(3):
+        o.step()
+        g.step(1)
+        assert np.array_equal(g.cell_levels(), o.cell_level), k
+        e = state_error(g.get_state(), o.g, o.h)
+        assert max(e) < TOL, (k, e)
+    npts, _, ncross = g.level_info()
+    print("levels", list(npts), "cross", ncross, flush=True)
+    assert len(npts) >= 2
+    g.close()
+
+
+def test_fp32_two_cavity_fields():
+    p = W.two_cavity(16, nv=16, vmax=7.0)
+    print("case fp32", flush=True)
+    o = Oracle(p, compat=4)
+    g = _gpu(p, compat=4, precision=32)
+    for _ in range(3):
+        o.step()
+    g.step(3)
+    fo, fg = o.fields(), g.moments()
+    for k in (0, 1, 3):
+        e = rel_l2(fg[:, k], fo[:, k], o.mesh.vol)
+        assert e < 1e-5, (k, e)
+    g.close()
+
+
+def _nearest(p, pts):
+    xc = p.centroids()
+    return [int(np.argmin(np.sum((xc - np.asarray(q)) ** 2, axis=1))) for q in pts]
+
+
+# left cavity, channel entrance, jump, channel exit, right cavity, a wall corner
+SAMPLE_POINTS = [(-1.0, 0.2), (-0.51, 0.01), (0.0, 0.0), (0.02, -0.05), (0.52, 0.03), (1.2, -0.3), (1.49, 0.49)]
+
+
+@pytest.mark.parametrize("mode", ["uvs", "mlvs"])
+def test_two_cavity_full_size_sampled_cells(mode):
+    from paper_2609_35258_amd import autotune
+    import torch
+    p = W.two_cavity(48, nv=101, vmax=7.0)
+    print("case two-cavity 9504 cells 101^2 fp32", mode, flush=True)
+    ap = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, flux_test=True, interval=0)
+    g = _gpu(p, precision=32, compat=4, adapt=ap if mode == "mlvs" else None, graph=True)
+    g.step(100)
+    if mode == "mlvs":
+        g.adapt()
+        npts, _, ncross = g.level_info()
+        kap = np.stack([g.level_kappa(k) for k in range(len(npts))])
+        levels = g.cell_levels()
+        print("levels", list(npts), "cross", ncross, flush=True)
+        assert len(npts) >= 2 and ncross > 0
+    g.step(2)
+    autotune.autotune(g, 32, cache=None)
+    patches = []
+    for c in _nearest(p, SAMPLE_POINTS):
+        q, cells = W.upatch(p, c, hops=2)
+        patches.append((c, q, cells, [g.get_cell(int(x)) for x in cells]))
+    g.step(1)
+    for c, q, cells, before in patches:
+        o = Oracle(q, compat=4, dt=g.dt)
+        if mode == "mlvs":
+            o.set_levels(list(kap), levels[cells])
+        o.g = [x[0].copy() for x in before]
+        o.h = [x[1].copy() for x in before]
+        o.step()
+        ga, ha = g.get_cell(c)
+        eg = np.max(np.abs(ga - o.g[0])) / np.max(np.abs(o.g[0]))
+        eh = np.max(np.abs(ha - o.h[0])) / np.max(np.abs(o.h[0]))
+        print("cell", c, "points", len(ga), "patch", len(cells), "error", eg, eh, flush=True)
+        assert max(eg, eh) < 1e-6, (c, eg, eh)
+    g.close()
+    del g
+    torch.cuda.empty_cache()

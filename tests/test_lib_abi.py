@@ -76,3 +76,45 @@ def test_create_rejects_bad_orders(dim, compat, map_moments, msg):
     assert st != 0
     assert msg in L.mlvs_last_error()
     assert not h.value
+
+
+def _umesh_call(nodes, polys, bedges):
+    L = m.lib()
+    phys = m.mlvs_physics(2, 0, 0.5, 2.0 / 3.0, 0.81, 1.0, 1.0, 0.0, 0.5, 64, 4, 1, 4)
+    x = np.linspace(-3, 3, 4)
+    w = np.full(4, 2.0)
+    keep = [np.ascontiguousarray(a) for a in (x, w)]
+    vg = m.mlvs_vgrid(4, 4, *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in (x, w, x, w)])
+    nodes = np.ascontiguousarray(nodes, np.float64)
+    nx, ny = np.ascontiguousarray(nodes[:, 0]), np.ascontiguousarray(nodes[:, 1])
+    ptr = np.concatenate([[0], np.cumsum([len(p) for p in polys])]).astype(np.int32)
+    cn = np.array([v for p in polys for v in p], np.int32)
+    be = np.ascontiguousarray(np.array(bedges, np.int32).reshape(-1, 3))
+    bcs = (m.mlvs_bc * 1)(m.mlvs_bc(1, 1.0, 0.0, 0.0, 1.0))
+    i32 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    mesh = m.mlvs_umesh(len(nodes), len(polys), dp(nx), dp(ny), i32(ptr), i32(cn), len(be), i32(be), 1, bcs)
+    h = ctypes.c_void_p()
+    st = L.mlvs_create_unstructured(ctypes.byref(phys), ctypes.byref(mesh), ctypes.byref(vg), None, None,
+                                    ctypes.byref(h))
+    del keep
+    return st, L.mlvs_last_error(), h
+
+
+SQ = [(0, 0), (1, 0), (1, 1), (0, 1), (2, 0), (2, 1)]
+
+
+@pytest.mark.parametrize("polys,bedges,msg", [
+    ([(0, 3, 2, 1)], [(0, 1, 0), (1, 2, 0), (2, 3, 0), (3, 0, 0)], b"not counter-clockwise"),
+    ([(0, 1, 2, 3)], [(0, 1, 0), (1, 2, 0), (2, 3, 0)], b"no boundary id"),
+    ([(0, 1, 2), (0, 1, 3), (0, 1, 5)], [], b"more than two cells"),
+    ([(0, 1, 4, 5, 2)], [], b"3 or 4 supported"),
+    ([(0, 1, 2, 3)], [(0, 1, 0), (1, 2, 0), (2, 3, 0), (3, 0, 7)], b"out of range"),
+    ([(0, 1, 9)], [], b"out of range"),
+])
+def test_create_unstructured_rejects_bad_meshes(polys, bedges, msg):
+    # mesh checks run before anything touches a device
+    st, err, h = _umesh_call(SQ, polys, bedges)
+    assert st != 0
+    assert msg in err, err
+    assert not h.value
