@@ -256,16 +256,103 @@ def jet_case(steps=100, warmup=100, precision=32, mode="both"):
                     "mlvs_vs_uvs_rel_l2": err}}
 
 
+TC_ADAPT = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, flux_test=True, interval=5)
+
+
+def two_cavity_case(steps=200, warmup=100, precision=32, mode="both", interval=5):
+    """Gas expansion between two cavities joined by a channel at full size
+    (unstructured: 9216 triangles + 288 quadrilaterals, lattice spacing 1/48;
+    101^2 Newton-Cotes base grid on [-7,7]^2; 1000:1 density jump at x = 0;
+    FP32 storage), MLVS against UVS.  Both run `warmup` untimed then `steps`
+    timed steps from the initial state; the MLVS run adapts at step 0 and every
+    `interval` steps (the paper's 5), adaptation included in the timing."""
+    import torch
+    import paper_2609_35258_amd as m
+    from paper_2609_35258_amd import autotune
+    p = W.two_cavity(48, nv=101, vmax=7.0)
+    wl = "twocavity48-nc101-fp32-uvs" if precision == 32 else None
+    # the update reads each cell's face rows: 3.03 faces per cell on this mesh
+    nf = float(np.sum(np.diff(p.cell_ptr))) / p.n_cells
+    alg = {"update": 6 + nf, "update_cell": 8 + nf}
+    if mode == "uvs":
+        u, t_u, upd_u, _ = run_gpu(p, steps, warmup, precision, None)
+        prof_u = stage_profile(u, reps=5)
+        var_u = {k: v["variant"] for k, v in getattr(u, "tuned", {}).items()}
+        u.close()
+        return {"uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps,
+                        "roofline": roofline(prof_u, precision, var_u, wl, alg, 1)}}
+    ap = dict(TC_ADAPT, interval=interval)
+    s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=ap, graph=True)
+    s.step(warmup)
+    autotune.autotune(s, precision)
+    torch.cuda.synchronize()
+    c0 = s.counters()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t_m = time.perf_counter() - t0
+    upd = s.counters()["cell_updates"] - c0["cell_updates"]
+    npts, ncells, ncross = s.level_info()
+    f_m = s.moments()
+    mem_m = s.memory()
+    prof = stage_profile(s, reps=5)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    if mode == "mlvs":
+        return {"value": upd / t_m, "ms_per_step": 1e3 * t_m / steps, "nbar": float(np.sum(npts * ncells) / np.sum(ncells)),
+                "roofline": roofline(prof, precision, None, None, alg, 1)}
+    u, t_u, upd_u, _ = run_gpu(p, steps, warmup, precision, None)
+    f_u = u.moments()
+    mem_u = u.memory()
+    prof_u = stage_profile(u, reps=5)
+    var_u = {k: v["variant"] for k, v in getattr(u, "tuned", {}).items()}
+    u.close()
+    del u
+    torch.cuda.empty_cache()
+    vol = cell_areas(p)
+    rl2 = lambda a, b: float(np.sqrt(np.sum(vol * (a - b) ** 2) / np.sum(vol * b ** 2)))
+    err = {"rho": rl2(f_m[:, 0], f_u[:, 0]), "p": rl2(f_m[:, 0] * f_m[:, 3], f_u[:, 0] * f_u[:, 3]),
+           "u": float(np.sqrt(np.sum(vol[:, None] * (f_m[:, 1:3] - f_u[:, 1:3]) ** 2)
+                              / np.sum(vol[:, None] * f_u[:, 1:3] ** 2))),
+           "T": rl2(f_m[:, 3], f_u[:, 3])}
+    return {"workload": "two-cavity expansion, unstructured 9504 cells (9216 triangles + 288 quadrilaterals, "
+                        "spacing 1/48), 1000:1 density jump, Kn_left 1e-3, Shakhov Pr 2/3, 101x101 Newton-Cotes "
+                        "on [-7,7]^2, fp%d; %d untimed then %d timed steps from the initial state; MLVS C_split "
+                        "0.01 C_merge 0.005 eps 2e-5 tau 0.05, adaptation every %d steps" % (
+                            precision, warmup, steps, interval),
+            "value": upd / t_m, "ms_per_step": 1e3 * t_m / steps, "levels": len(npts),
+            "level_points": [int(x) for x in npts], "level_cells": [int(x) for x in ncells],
+            "nbar": float(np.sum(npts * ncells) / np.sum(ncells)), "n_cross": int(ncross),
+            "roofline": roofline(prof, precision, None, None, alg, 1),
+            "uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps,
+                    "roofline": roofline(prof_u, precision, var_u, wl, alg, 1),
+                    "device_bytes": int(mem_u), "time_to_solution_ratio": t_u / t_m, "memory_ratio": mem_u / mem_m,
+                    "mlvs_vs_uvs_rel_l2": err}}
+
+
+def cell_areas(p):
+    """Shoelace areas of an unstructured problem's cells (weights of the field differences)."""
+    out = np.zeros(p.n_cells)
+    for c in range(p.n_cells):
+        v = p.nodes[p.cell_node[p.cell_ptr[c]:p.cell_ptr[c + 1]]]
+        x, y = v[:, 0], v[:, 1]
+        out[c] = 0.5 * abs(np.dot(x, np.roll(y, -1)) - np.dot(np.roll(x, -1), y))
+    return out
+
+
 # launch variant index -> (velocity points per lane per load batch, minimum waves per SIMD)
 VARIANTS = {0: (1, 4), 1: (2, 4), 2: (4, 2), 3: (4, 4)}
-# kernels instantiated per compatibility order carry it as a last template argument
+# kernels instantiated per compatibility order carry it as a template argument,
+# and the face kernels the mesh kind (0 structured, 1 unstructured) after it
 STAGE_CM = ("cell", "face_target", "face", "update_cell")
+STAGE_MK = ("face_rec", "face", "xface")
 STAGE_KERNEL = {"face": "k_face_full", "update_cell": "k_update_cell",
                 "cell": "k_cell_prep", "face_rec": "k_face_rec", "face_target": "k_face_target",
                 "update": "k_update", "xface": "k_xface"}
 
 
-def measured_traffic(workload, stage, precision, variant):
+def measured_traffic(workload, stage, precision, variant, mk=0):
     """HBM-side bytes per dispatch of the stage's kernel from profiles/traffic.txt
     (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when absent or
     when the kernel source has changed since the counters were taken."""
@@ -275,8 +362,10 @@ def measured_traffic(workload, stage, precision, variant):
         return None
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     u, w = VARIANTS[variant]
-    name = "mlvs::%s<%s,%d,%d%s>" % (STAGE_KERNEL[stage], "double" if precision == 64 else "float", u, w,
-                                     ",4" if stage in STAGE_CM else "")
+    if mk and stage in STAGE_MK and variant != 0:
+        u, w = VARIANTS[1]                 # unstructured face kernels: the (1, 4) and (2, 4) pairs only
+    name = "mlvs::%s<%s,%d,%d%s%s>" % (STAGE_KERNEL[stage], "double" if precision == 64 else "float", u, w,
+                                       ",4" if stage in STAGE_CM else "", ",%d" % mk if stage in STAGE_MK else "")
     for line in open(path):
         f = line.split()
         if len(f) == 4 and not line.startswith("#") and f[0] == h and f[1] == workload and f[2] == name:
@@ -284,16 +373,18 @@ def measured_traffic(workload, stage, precision, variant):
     return None
 
 
-def roofline(prof, precision, variants=None, workload=None):
-    """Roofline entry for the dominant stage: algorithmic bytes / mean launch time."""
+def roofline(prof, precision, variants=None, workload=None, alg=None, mk=0):
+    """Roofline entry for the dominant stage: algorithmic bytes / mean launch time.
+    alg: per-stage overrides of ALG_VALUES; mk: mesh kind (1 unstructured)."""
+    av = dict(ALG_VALUES, **(alg or {}))
     evsz = 8 if precision == 64 else 4
-    dom = max((k for k in prof if ALG_VALUES[k] > 0), key=lambda k: prof[k]["ms"])
+    dom = max((k for k in prof if av[k] > 0), key=lambda k: prof[k]["ms"])
     d = prof[dom]
-    achieved = d["points"] * ALG_VALUES[dom] * evsz / (d["ms"] * 1e-3) / 1e9
-    t = measured_traffic(workload, dom, precision, (variants or {}).get(dom)) if workload else None
+    achieved = d["points"] * av[dom] * evsz / (d["ms"] * 1e-3) / 1e9
+    t = measured_traffic(workload, dom, precision, (variants or {}).get(dom), mk) if workload else None
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": t,
-            "algorithmic_bytes": d["points"] * ALG_VALUES[dom] * evsz,
+            "algorithmic_bytes": d["points"] * av[dom] * evsz,
             "stage_ms": {k: round(v["ms"], 5) for k, v in prof.items()}}
 
 
@@ -374,6 +465,10 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-cylinder", action="store_true")
     ap.add_argument("--no-jet", action="store_true")
+    ap.add_argument("--no-two-cavity", action="store_true")
+    ap.add_argument("--two-cavity-only", action="store_true", help="only the two-cavity comparison")
+    ap.add_argument("--tc-mode", default="both", choices=["both", "uvs", "mlvs"])
+    ap.add_argument("--tc-interval", type=int, default=5)
     ap.add_argument("--jet-only", action="store_true", help="only the full-size jet comparison (profiling runs)")
     ap.add_argument("--jet-mode", choices=("both", "mlvs", "uvs"), default="both")
     ap.add_argument("--cylinder-only", action="store_true",
@@ -395,6 +490,9 @@ def main():
         return
     if args.jet_only:
         print(json.dumps({"jet": jet_case(mode=args.jet_mode)}), flush=True)
+        return
+    if args.two_cavity_only:
+        print(json.dumps({"two_cavity": two_cavity_case(mode=args.tc_mode, interval=args.tc_interval)}), flush=True)
         return
     if args.cylinder_only:
         print(json.dumps({"cylinder": cylinder_case(steps=args.cylinder_steps, mode=args.cylinder_mode)}), flush=True)
@@ -449,6 +547,8 @@ def main():
         out["cylinder"] = cylinder_case(steps=args.cylinder_steps)
     if not args.no_jet:
         out["jet"] = jet_case()
+    if not args.no_two_cavity:
+        out["two_cavity"] = two_cavity_case()
     if not args.no_learned:
         out["learned"] = learned_vs_criterion()
     if not args.no_cpu_baseline:

@@ -861,6 +861,11 @@ struct mlvs_ctx_s {
     bool prep_valid = false;           // phi_bar+ rows and parameters match the stored state
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // cross-level faces run on a second stream (default priority) beside the
+    // same-level face stages, forked after the ghost rows and joined before the
+    // update
+    hipStream_t side_st = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // counters
     double cnt_updates = 0.0, cnt_iface = 0.0;
     int64_t cnt_adapt = 0;
@@ -1213,7 +1218,7 @@ void ensure_moments(mlvs_ctx c) {
                                  c->d_params, c->d_cmom, c->chunk, c->nch), "moments launch");
     c->mom_valid = true;
 }
-hipError_t launch_stage(mlvs_ctx c, int stage);
+hipError_t launch_stage(mlvs_ctx c, int stage, hipStream_t on = nullptr);
 hipError_t launch_step_kernels(mlvs_ctx c);
 std::vector<int> step_stages(mlvs_ctx c);
 
@@ -1473,11 +1478,18 @@ void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
     dedupe(c, uniq, first, count, uidx);
     std::vector<std::vector<uint8_t>> reps;
     cluster(c->base.Nb, c->ap.tau_clust, uniq, first, count, reps, level_of_u);
-    std::vector<std::unique_ptr<Level>> nl;
-    for (auto& k : reps) nl.push_back(build_level(c->base, k));
     std::vector<int> cl(c->mesh.n_cells);
     for (int i = 0; i < c->mesh.n_cells; ++i) cl[i] = level_of_u[uidx[i]];
-    const int64_t changed = install_levels(c, std::move(nl), cl);
+    // the same catalogue in the same order and the same assignment: nothing to
+    // remap or rebuild (the captured step stays valid)
+    bool same = reps.size() == c->levels.size() && cl == c->cell_level;
+    for (size_t l = 0; same && l < reps.size(); ++l) same = reps[l] == c->levels[l]->kappa;
+    int64_t changed = 0;
+    if (!same) {
+        std::vector<std::unique_ptr<Level>> nl;
+        for (auto& k : reps) nl.push_back(build_level(c->base, k));
+        changed = install_levels(c, std::move(nl), cl);
+    }
     c->last_unique = (int64_t)first.size();
     ++c->cnt_adapt;
     if (rep) {
@@ -1921,6 +1933,9 @@ static mlvs_status create_impl(const mlvs_physics* phys, const mlvs_mesh* mesh, 
         ph.compat = phys->compat; ph.face_compat = phys->face_compat; ph.map_moments = phys->map_moments;
         ph.positivity = phys->positivity;
         ph.mesh_kind = c->mesh.unstructured ? 1 : 0;
+        hip_check(hipStreamCreateWithFlags(&c->side_st, hipStreamNonBlocking), "stream create");
+        hip_check(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "event create");
+        hip_check(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "event create");
         // device geometry
         c->d_geom = upload(c->dm, c->mesh.geom, c->st);
         c->d_nbr_cell = upload(c->dm, c->mesh.nbr, c->st);
@@ -1954,6 +1969,9 @@ static mlvs_status create_impl(const mlvs_physics* phys, const mlvs_mesh* mesh, 
         *out = c;
     });
     if (s != MLVS_OK && c) {
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+        if (c->side_st) (void)hipStreamDestroy(c->side_st);
         c->dm.release_all();
         delete c;
     }
@@ -1975,7 +1993,11 @@ mlvs_status mlvs_create_unstructured(const mlvs_physics* phys, const mlvs_umesh*
 void mlvs_destroy(mlvs_ctx c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
+    if (c->side_st) (void)hipStreamSynchronize(c->side_st);
     drop_graph(c);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->side_st) (void)hipStreamDestroy(c->side_st);
     c->dm.release_all();
     delete c;
 }
@@ -2438,9 +2460,21 @@ std::vector<int> step_stages(mlvs_ctx c) {
 }
 
 hipError_t launch_step_kernels(mlvs_ctx c) {
+    // cross-level faces (stage 4) beside the same-level face stages: both read
+    // the cell stage's rows and the ghost rows, and they write distinct rows
+    const bool fork = c->n_xfaces > 0 && c->side_st;
     for (int stage : step_stages(c)) {
-        const hipError_t e = launch_stage(c, stage);
-        if (e != hipSuccess) return e;
+        hipError_t e = hipSuccess;
+        if (fork && stage == 4) continue;
+        if (fork && (stage == 2 || stage == 7)) {
+            if ((e = hipEventRecord(c->ev_fork, c->st)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(c->side_st, c->ev_fork, 0)) != hipSuccess) return e;
+            if ((e = launch_stage(c, 4, c->side_st)) != hipSuccess) return e;
+            if ((e = hipEventRecord(c->ev_join, c->side_st)) != hipSuccess) return e;
+        }
+        if (fork && (stage == 5 || stage == 8))
+            if ((e = hipStreamWaitEvent(c->st, c->ev_join, 0)) != hipSuccess) return e;
+        if ((e = launch_stage(c, stage)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -2449,7 +2483,7 @@ hipError_t launch_step_kernels(mlvs_ctx c) {
 // reconstruction and 3 face target (same-level and boundary faces), 4
 // cross-level faces, 5 update; fused forms 7 (2 + 3) and 8 (5 + the next
 // step's 0).  6 (criterion) is timed apart.
-hipError_t launch_stage(mlvs_ctx c, int stage) {
+hipError_t launch_stage(mlvs_ctx c, int stage, hipStream_t on) {
     const int n = c->mesh.n_cells;
     const int nf = c->n_faces + c->n_bfaces;
     switch (stage) {
@@ -2461,7 +2495,7 @@ hipError_t launch_stage(mlvs_ctx c, int stage) {
                                    c->d_params, c->ph, c->d_fmom, c->chunk, c->nch, c->variant[2]);
     case 3: return launch_face_target(c->prec, c->st, c->d_lv, c->d_faces, nf, c->d_bcs, c->ph, c->d_fmom,
                                       c->d_fpar, c->chunk, c->variant[3]);
-    case 4: return launch_xface(c->prec, c->st, c->d_lv, c->d_xfaces, c->n_xfaces, c->d_cell_slot, c->d_cell_nbr,
+    case 4: return launch_xface(c->prec, on ? on : c->st, c->d_lv, c->d_xfaces, c->n_xfaces, c->d_cell_slot, c->d_cell_nbr,
                                 c->d_geom, c->d_params, c->ph, c->d_neg, c->variant[4]);
     case 5: return launch_update(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, c->d_order, n, c->d_geom,
                                  c->d_cell_frow, c->d_faces, c->d_fpar, c->d_params, c->ph, c->d_cmom, c->chunk,
