@@ -362,8 +362,8 @@ def measured_traffic(workload, stage, precision, variant, mk=0):
         return None
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     u, w = VARIANTS[variant]
-    if mk and stage in STAGE_MK and variant != 0:
-        u, w = VARIANTS[1]                 # unstructured face kernels: the (1, 4) and (2, 4) pairs only
+    if mk and stage in STAGE_MK:
+        u, w = VARIANTS[0]                 # unstructured face kernels: the (1, 4) pair for every variant
     name = "mlvs::%s<%s,%d,%d%s%s>" % (STAGE_KERNEL[stage], "double" if precision == 64 else "float", u, w,
                                        ",4" if stage in STAGE_CM else "", ",%d" % mk if stage in STAGE_MK else "")
     for line in open(path):

@@ -1946,7 +1946,8 @@ constexpr int N_VARIANTS = 4;
         else MLVS_DISPATCH_VC1(prec, var, 4, KERNEL, __VA_ARGS__);                               \
     } while (0)
 
-// ... and per mesh kind (unstructured meshes: the (1, 4) and (2, 4) pairs only)
+// ... and per mesh kind (unstructured meshes: the (1, 4) pair for every
+// variant; with two points per lane the larger limiter stencil spills)
 #define MLVS_LAUNCH_UWM(prec, KERNEL, U_, W_, M_, ...)                                           \
     do {                                                                                        \
         if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, U_, W_, M_>), __VA_ARGS__);          \
@@ -1955,8 +1956,7 @@ constexpr int N_VARIANTS = 4;
 #define MLVS_DISPATCH_VM(prec, var, mk, KERNEL, ...)                                             \
     do {                                                                                        \
         if (mk) {                                                                               \
-            if ((var) == 0) MLVS_LAUNCH_UWM(prec, KERNEL, 1, 4, 1, __VA_ARGS__);                 \
-            else MLVS_LAUNCH_UWM(prec, KERNEL, 2, 4, 1, __VA_ARGS__);                            \
+            MLVS_LAUNCH_UWM(prec, KERNEL, 1, 4, 1, __VA_ARGS__);                                 \
         } else {                                                                                \
             switch (var) {                                                                      \
             case 0: MLVS_LAUNCH_UWM(prec, KERNEL, 1, 4, 0, __VA_ARGS__); break;                  \
@@ -1974,8 +1974,7 @@ constexpr int N_VARIANTS = 4;
 #define MLVS_DISPATCH_VCM1(prec, var, C_, mk, KERNEL, ...)                                       \
     do {                                                                                        \
         if (mk) {                                                                               \
-            if ((var) == 0) MLVS_LAUNCH_UWCM(prec, KERNEL, 1, 4, C_, 1, __VA_ARGS__);            \
-            else MLVS_LAUNCH_UWCM(prec, KERNEL, 2, 4, C_, 1, __VA_ARGS__);                       \
+            MLVS_LAUNCH_UWCM(prec, KERNEL, 1, 4, C_, 1, __VA_ARGS__);                            \
         } else {                                                                                \
             switch (var) {                                                                      \
             case 0: MLVS_LAUNCH_UWCM(prec, KERNEL, 1, 4, C_, 0, __VA_ARGS__); break;             \
