@@ -331,6 +331,54 @@ def two_cavity_case(steps=200, warmup=100, precision=32, mode="both", interval=5
                     "mlvs_vs_uvs_rel_l2": err}}
 
 
+def two_cavity_to_time(t_end=4.0, precision=32, interval=5):
+    """The two-cavity expansion run to dimensionless time t_end (the paper
+    compares MLVS and UVS at t = 4), both forms timed over the whole run from
+    the initial state (MLVS adaptation every `interval` steps included), with
+    the area-weighted field differences and the level configuration at t_end."""
+    import torch
+    import paper_2609_35258_amd as m
+    from paper_2609_35258_amd import autotune
+    p = W.two_cavity(48, nv=101, vmax=7.0)
+    vol = cell_areas(p)
+    out = {}
+    for mode in ("mlvs", "uvs"):
+        s = m.Solver.from_problem(p, precision=precision, compat=4,
+                                  adapt=dict(TC_ADAPT, interval=interval) if mode == "mlvs" else None, graph=True)
+        n = int(round(t_end / s.dt))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(10)
+        autotune.autotune(s, precision)
+        done = 10
+        while done < n:
+            k = min(1000, n - done)
+            s.step(k)
+            done += k
+            torch.cuda.synchronize()
+            print("two-cavity %s step %d of %d, %.1f s" % (mode, done, n, time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
+        t = time.perf_counter() - t0
+        npts, ncells, _ = s.level_info()
+        out[mode] = {"seconds": t, "steps": n, "fields": s.moments(), "memory": s.memory(),
+                     "levels": [int(x) for x in npts], "cells": [int(x) for x in ncells],
+                     "nbar": float(np.sum(npts * ncells) / np.sum(ncells))}
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    fm, fu = out["mlvs"]["fields"], out["uvs"]["fields"]
+    rl2 = lambda a, b: float(np.sqrt(np.sum(vol[:, None] * (a - b) ** 2) / np.sum(vol[:, None] * b ** 2)))
+    err = {"rho": rl2(fm[:, :1], fu[:, :1]), "p": rl2((fm[:, 0] * fm[:, 3])[:, None], (fu[:, 0] * fu[:, 3])[:, None]),
+           "u": rl2(fm[:, 1:3], fu[:, 1:3]), "T": rl2(fm[:, 3:4], fu[:, 3:4]), "q": rl2(fm[:, 4:6], fu[:, 4:6])}
+    return {"workload": "two-cavity expansion to t = %g (%d steps), 9504 unstructured cells, 101^2, fp%d, MLVS "
+                        "adaptation every %d steps; whole runs timed" % (t_end, out["uvs"]["steps"], precision, interval),
+            "mlvs_seconds": out["mlvs"]["seconds"], "uvs_seconds": out["uvs"]["seconds"],
+            "speedup": out["uvs"]["seconds"] / out["mlvs"]["seconds"],
+            "memory_ratio": out["uvs"]["memory"] / out["mlvs"]["memory"],
+            "levels": out["mlvs"]["levels"], "level_cells": out["mlvs"]["cells"], "nbar": out["mlvs"]["nbar"],
+            "mlvs_vs_uvs_rel_l2": err}
+
+
 def cell_areas(p):
     """Shoelace areas of an unstructured problem's cells (weights of the field differences)."""
     out = np.zeros(p.n_cells)
@@ -469,6 +517,8 @@ def main():
     ap.add_argument("--two-cavity-only", action="store_true", help="only the two-cavity comparison")
     ap.add_argument("--tc-mode", default="both", choices=["both", "uvs", "mlvs"])
     ap.add_argument("--tc-interval", type=int, default=5)
+    ap.add_argument("--tc-t-end", type=float, default=0.0,
+                    help="with --two-cavity-only: run both forms to this time instead (the paper's t = 4)")
     ap.add_argument("--jet-only", action="store_true", help="only the full-size jet comparison (profiling runs)")
     ap.add_argument("--jet-mode", choices=("both", "mlvs", "uvs"), default="both")
     ap.add_argument("--cylinder-only", action="store_true",
@@ -492,6 +542,10 @@ def main():
         print(json.dumps({"jet": jet_case(mode=args.jet_mode)}), flush=True)
         return
     if args.two_cavity_only:
+        if args.tc_t_end > 0:
+            print(json.dumps({"two_cavity_to_time": two_cavity_to_time(args.tc_t_end, interval=args.tc_interval)}),
+                  flush=True)
+            return
         print(json.dumps({"two_cavity": two_cavity_case(mode=args.tc_mode, interval=args.tc_interval)}), flush=True)
         return
     if args.cylinder_only:

@@ -14,6 +14,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -451,6 +452,23 @@ struct FaceH {
     double nx, ny, area, cx, cy, dLx, dLy, dRx, dRy;
 };
 
+// Grow-only pinned host buffer (device-to-host copies of the unique masks).
+struct PinnedBuf {
+    uint8_t* p = nullptr;
+    size_t cap = 0;
+    uint8_t* ensure(size_t n) {
+        if (n > cap) {
+            if (p) (void)hipHostFree(p);
+            p = nullptr;
+            cap = 0;
+            hip_check(hipHostMalloc((void**)&p, std::max<size_t>(n, 1), hipHostMallocDefault), "pinned alloc");
+            cap = std::max<size_t>(n, 1);
+        }
+        return p;
+    }
+    ~PinnedBuf() { if (p) (void)hipHostFree(p); }
+};
+
 struct MeshH {
     int ni = 0, nj = 0, dim = 2, n_cells = 0;
     bool per_i = false, per_j = false;
@@ -842,6 +860,8 @@ struct mlvs_ctx_s {
     // criterion inputs: base grid and per-level maps / masks
     double *d_bx = nullptr, *d_by = nullptr, *d_bw = nullptr;
     int *d_ptb_all = nullptr, *d_ptb_off = nullptr;
+    double* d_x2b_all = nullptr;       // per level and base point: |xi_p|^2 of its level point p
+    PinnedBuf pin_masks;               // host copy of the unique masks (adaptation)
     uint8_t* d_kappa_all = nullptr;
     uint8_t* d_kcell = nullptr;
     unsigned long long* d_hash = nullptr;
@@ -1096,11 +1116,14 @@ void build_items(mlvs_ctx c) {
     c->n_bfaces = (int)bfaces.size();
     faces.insert(faces.end(), bfaces.begin(), bfaces.end());
     std::vector<int> ptb, poff;
+    std::vector<double> x2b;
     std::vector<uint8_t> kap;
     if (c->base.Nb > 0) {
         for (int l = 0; l < K; ++l) {
             poff.push_back((int)ptb.size());
             ptb.insert(ptb.end(), c->levels[l]->pt_of_base.begin(), c->levels[l]->pt_of_base.end());
+            const Level& Lv = *c->levels[l];
+            for (int p : Lv.pt_of_base) x2b.push_back(Lv.xi_x[p] * Lv.xi_x[p] + Lv.xi_y[p] * Lv.xi_y[p]);
             kap.insert(kap.end(), c->levels[l]->kappa.begin(), c->levels[l]->kappa.end());
         }
     }
@@ -1114,7 +1137,7 @@ void build_items(mlvs_ctx c) {
     const size_t o_lev = stg.put(c->cell_level);
     const size_t o_slot = stg.put(c->cell_slot);
     const size_t o_order = stg.put(M.order);
-    const size_t o_ptb = stg.put(ptb), o_poff = stg.put(poff), o_kap = stg.put(kap);
+    const size_t o_ptb = stg.put(ptb), o_poff = stg.put(poff), o_kap = stg.put(kap), o_x2b = stg.put(x2b);
     char* base = static_cast<char*>(c->dm.alloc(stg.buf.size()));
     c->item_allocs.push_back(base);
     for (size_t i = 0; i < c->ifaces.size(); ++i) {
@@ -1164,6 +1187,7 @@ void build_items(mlvs_ctx c) {
     if (c->base.Nb > 0) {
         c->d_ptb_all = reinterpret_cast<int*>(base + o_ptb);
         c->d_ptb_off = reinterpret_cast<int*>(base + o_poff);
+        c->d_x2b_all = reinterpret_cast<double*>(base + o_x2b);
         c->d_kappa_all = reinterpret_cast<uint8_t*>(base + o_kap);
     }
     int nmax = 1;
@@ -1337,14 +1361,14 @@ void run_criterion(mlvs_ctx c) {
     if (!c->d_kcell) c->d_kcell = static_cast<uint8_t*>(c->dm.alloc((size_t)n * Nb));
     if (!c->d_hash) c->d_hash = static_cast<unsigned long long*>(c->dm.alloc(sizeof(unsigned long long) * n));
     hip_check(launch_criterion(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_ptb_all, c->d_ptb_off,
-                               c->d_kappa_all, c->d_bx, c->d_by, c->d_bw, c->base.nx, c->base.ny, c->ap.C_split,
+                               c->d_x2b_all, c->d_kappa_all, c->d_bx, c->d_by, c->d_bw, c->base.nx, c->base.ny, c->ap.C_split,
                                c->ap.C_merge, c->ap.eps_merge, c->ap.flux_test, c->d_kcell, c->d_hash),
               "criterion launch");
 }
 
 // Deduplicate the per-cell masks: returns unique masks (row-major), their first
 // cell and count, and the unique index of every cell.
-void dedupe(mlvs_ctx c, std::vector<uint8_t>& uniq, std::vector<int>& first, std::vector<int64_t>& count,
+void dedupe(mlvs_ctx c, const uint8_t*& uniq, std::vector<int>& first, std::vector<int64_t>& count,
             std::vector<int>& uidx) {
     const int n = c->mesh.n_cells, Nb = c->base.Nb;
     std::vector<unsigned long long> hs(n);
@@ -1375,9 +1399,10 @@ void dedupe(mlvs_ctx c, std::vector<uint8_t>& uniq, std::vector<int>& first, std
     hip_check(launch_gather_rows_u8(c->st, c->d_kcell, Nb, d_rows, U, d_u), "gather");
     hip_check(launch_compare_rows_u8(c->st, c->d_kcell, Nb, d_rep, d_u, n, d_mis), "compare");
     unsigned long long mis = 0;
-    uniq.resize((size_t)U * Nb);
+    uint8_t* hu = c->pin_masks.ensure((size_t)U * Nb);
     hip_check(hipMemcpyAsync(&mis, d_mis, 8, hipMemcpyDeviceToHost, c->st), "D2H");
-    hip_check(hipMemcpyAsync(uniq.data(), d_u, (size_t)U * Nb, hipMemcpyDeviceToHost, c->st), "D2H");
+    hip_check(hipMemcpyAsync(hu, d_u, (size_t)U * Nb, hipMemcpyDeviceToHost, c->st), "D2H");
+    uniq = hu;
     sync(c);
     c->dm.release(d_rows); c->dm.release(d_rep); c->dm.release(d_u); c->dm.release(d_mis);
     if (mis != 0) {
@@ -1386,7 +1411,8 @@ void dedupe(mlvs_ctx c, std::vector<uint8_t>& uniq, std::vector<int>& first, std
         hip_check(hipMemcpyAsync(all.data(), c->d_kcell, all.size(), hipMemcpyDeviceToHost, c->st), "D2H");
         sync(c);
         std::map<std::vector<uint8_t>, int> ex;
-        uniq.clear(); first.clear(); count.clear();
+        std::vector<uint8_t> un;
+        first.clear(); count.clear();
         for (int i = 0; i < n; ++i) {
             std::vector<uint8_t> row(all.begin() + (size_t)i * Nb, all.begin() + (size_t)(i + 1) * Nb);
             auto it = ex.find(row);
@@ -1395,19 +1421,42 @@ void dedupe(mlvs_ctx c, std::vector<uint8_t>& uniq, std::vector<int>& first, std
                 uidx[i] = (int)first.size();
                 first.push_back(i);
                 count.push_back(1);
-                uniq.insert(uniq.end(), row.begin(), row.end());
+                un.insert(un.end(), row.begin(), row.end());
             } else {
                 uidx[i] = it->second;
                 ++count[it->second];
             }
         }
+        uint8_t* hx = c->pin_masks.ensure(un.size());
+        std::copy(un.begin(), un.end(), hx);
+        uniq = hx;
     }
+}
+
+// Run f(lo, hi) over [0, n) split into contiguous ranges on up to 8 host
+// threads (one range when n is small).  f must only write its own range.
+template <class F>
+void parallel_ranges(int n, F&& f) {
+    const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+    const int nt = (int)std::min<long>(hw, std::max(1, n / 64));
+    if (nt <= 1) { f(0, n); return; }
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back([&, t] { f((int)((long)n * t / nt), (int)((long)n * (t + 1) / nt)); });
+    f(0, (int)((long)n / nt));
+    for (auto& x : th) x.join();
 }
 
 // Leader clustering of the unique masks (descending frequency, ties by first
 // cell), integer graded distance, enclosing mask = elementwise min, identical
 // enclosing masks merged.
-void cluster(int Nb, double tau, const std::vector<uint8_t>& uniq, const std::vector<int>& first,
+//
+// Each mask joins the nearest centre founded before it in that order (within
+// the threshold; a later centre must be strictly nearer, so ties go to the
+// lowest id) or founds a new one; centres are their founding masks.  Done as
+// one pass per new centre over every later mask (threaded): a mask has then
+// been compared with exactly the centres founded before it, in founding
+// order, as a mask-by-mask scan compares it.
+void cluster(int Nb, double tau, const uint8_t* uniq, const std::vector<int>& first,
              const std::vector<int64_t>& count, std::vector<std::vector<uint8_t>>& reps, std::vector<int>& level_of_u) {
     const int U = (int)first.size();
     std::vector<int> order(U);
@@ -1417,14 +1466,8 @@ void cluster(int Nb, double tau, const std::vector<uint8_t>& uniq, const std::ve
         return first[a] < first[b];
     });
     const long thr = (long)std::floor(tau * 3.0 * Nb + 1e-9);
-    std::vector<int> centres;
-    std::vector<int> cl_of_u(U, -1);
-    std::vector<std::vector<uint8_t>> kmin;
     // Distance sum_b |ka_b - kb_b| in blocks of 256 masks (vectorisable), given
-    // up as soon as it exceeds cap: only centres within the threshold can be
-    // joined, and a later centre must be strictly nearer to replace the best so
-    // far (ties go to the lowest id), so the result is the nearest centre
-    // within the threshold exactly as a full scan finds it.
+    // up as soon as it exceeds cap.
     auto dist_capped = [Nb](const uint8_t* a, const uint8_t* b, long cap) {
         long d = 0;
         for (int b0 = 0; b0 < Nb; b0 += 256) {
@@ -1436,25 +1479,45 @@ void cluster(int Nb, double tau, const std::vector<uint8_t>& uniq, const std::ve
         }
         return d;
     };
-    for (int u : order) {
-        const uint8_t* ku = &uniq[(size_t)u * Nb];
-        int best = -1;
-        long bestd = 0;
-        for (size_t cid = 0; cid < centres.size(); ++cid) {
-            const long cap = best < 0 ? thr : bestd - 1;
-            if (cap < 0) break;
-            const long d = dist_capped(ku, &uniq[(size_t)centres[cid] * Nb], cap);
-            if (d <= cap) { best = (int)cid; bestd = d; }
-        }
-        if (best >= 0 && bestd <= thr) {
-            cl_of_u[u] = best;
-            for (int b = 0; b < Nb; ++b) kmin[best][b] = std::min(kmin[best][b], ku[b]);
-        } else {
-            centres.push_back(u);
-            cl_of_u[u] = (int)centres.size() - 1;
-            kmin.emplace_back(ku, ku + Nb);
-        }
+    std::vector<int> best(U, -1);          // by position in `order`
+    std::vector<long> bestd(U, 0);
+    std::vector<int> centres;              // founding positions
+    int i = 0;
+    while (i < U) {
+        int j = i;
+        while (j < U && best[j] >= 0) ++j;   // positions i..j-1 are final
+        if (j == U) break;
+        const int cid = (int)centres.size();
+        centres.push_back(j);
+        best[j] = cid;
+        bestd[j] = 0;
+        const uint8_t* kc = &uniq[(size_t)order[j] * Nb];
+        parallel_ranges(U - j - 1, [&](int lo, int hi) {
+            for (int k = j + 1 + lo; k < j + 1 + hi; ++k) {
+                const long cap = best[k] < 0 ? thr : bestd[k] - 1;
+                if (cap < 0) continue;
+                const long d = dist_capped(&uniq[(size_t)order[k] * Nb], kc, cap);
+                if (d <= cap) { best[k] = cid; bestd[k] = d; }
+            }
+        });
+        i = j + 1;
     }
+    // enclosing masks: elementwise min over each cluster's members
+    const int K = (int)centres.size();
+    std::vector<std::vector<uint8_t>> kmin(K);
+    for (int c = 0; c < K; ++c) {
+        const uint8_t* kc = &uniq[(size_t)order[centres[c]] * Nb];
+        kmin[c].assign(kc, kc + Nb);
+    }
+    parallel_ranges(Nb, [&](int lo, int hi) {
+        for (int k = 0; k < U; ++k) {
+            const uint8_t* ku = &uniq[(size_t)order[k] * Nb];
+            uint8_t* km = kmin[best[k]].data();
+            for (int b = lo; b < hi; ++b) km[b] = std::min(km[b], ku[b]);
+        }
+    });
+    std::vector<int> cl_of_u(U, -1);
+    for (int k = 0; k < U; ++k) cl_of_u[order[k]] = best[k];
     std::vector<int> level_of_cl(kmin.size());
     reps.clear();
     for (size_t k = 0; k < kmin.size(); ++k) {
@@ -1472,7 +1535,7 @@ void adapt_learned(mlvs_ctx c, mlvs_adapt_report* rep);
 
 void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
     run_criterion(c);
-    std::vector<uint8_t> uniq;
+    const uint8_t* uniq = nullptr;
     std::vector<int> first, uidx, level_of_u;
     std::vector<int64_t> count;
     dedupe(c, uniq, first, count, uidx);
@@ -1553,9 +1616,9 @@ void adapt_learned(mlvs_ctx c, mlvs_adapt_report* rep) {
         if (!c->d_hash) c->d_hash = static_cast<unsigned long long*>(c->dm.alloc(sizeof(unsigned long long) * n));
         int* d_list = upload(c->dm, rej, c->st);
         hip_check(launch_criterion(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, (int)rej.size(),
-                                   c->d_ptb_all, c->d_ptb_off, c->d_kappa_all, c->d_bx, c->d_by, c->d_bw, c->base.nx,
-                                   c->base.ny, c->ap.C_split, c->ap.C_merge, c->ap.eps_merge, c->ap.flux_test,
-                                   c->d_kcell, c->d_hash, d_list), "criterion launch");
+                                   c->d_ptb_all, c->d_ptb_off, c->d_x2b_all, c->d_kappa_all, c->d_bx, c->d_by, c->d_bw,
+                                   c->base.nx, c->base.ny, c->ap.C_split, c->ap.C_merge, c->ap.eps_merge,
+                                   c->ap.flux_test, c->d_kcell, c->d_hash, d_list), "criterion launch");
         std::vector<int> order = level_order(c);
         int* d_order = upload(c->dm, order, c->st);
         hip_check(launch_labels(c->st, c->d_kcell, n, Nb, c->d_kappa_all, d_order, K, d_pred), "labels launch");

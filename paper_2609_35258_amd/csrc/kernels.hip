@@ -2295,6 +2295,7 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
 
 struct CritCtx {
     const int* ptb;           // base -> level point of the cell's level
+    const double* x2b;        // base -> |xi_p|^2 of that level point (read in base order)
     const uint8_t* prev;      // kappa of the cell's current level
     const double *bx, *by, *bw;
     int nx, nbx;
@@ -2317,8 +2318,7 @@ __device__ __forceinline__ bool crit_merges(const CritCtx& cc, const LevelDesc& 
             const int b = ix + cc.nx * iy;
             const int p = cc.ptb[b];
             const double gpv = (double)g[p];
-            const double xp = gp(L.xi_x)[p], yp = gp(L.xi_y)[p];
-            const double Hb = (double)h[p] + (xp * xp + yp * yp) * gpv;
+            const double Hb = (double)h[p] + cc.x2b[b] * gpv;
             const double w = cc.bw[b], x = cc.bx[b], y = cc.by[b];
             m1 += w * gpv;
             m2 += 0.5 * w * Hb;
@@ -2363,6 +2363,7 @@ template <typename S>
 __global__ __launch_bounds__(BS, 4) void k_criterion(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
                                                   const int* __restrict__ cell_slot, int n_cells,
                                                   const int* __restrict__ ptb_all, const int* __restrict__ ptb_off,
+                                                  const double* __restrict__ x2b_all,
                                                   const uint8_t* __restrict__ kappa_all, const double* __restrict__ bx,
                                                   const double* __restrict__ by, const double* __restrict__ bw,
                                                   int nx, int ny, double C_split, double C_merge, double eps_merge,
@@ -2380,6 +2381,7 @@ __global__ __launch_bounds__(BS, 4) void k_criterion(const LevelDesc* __restrict
         auto h = rowp<S>(L.h, row);
         CritCtx cc;
         cc.ptb = ptb_all + (size_t)ptb_off[lev];
+        cc.x2b = x2b_all + (size_t)ptb_off[lev];
         cc.prev = kappa_all + (size_t)lev * Nb;
         cc.bx = bx; cc.by = by; cc.bw = bw; cc.nx = nx; cc.nbx = nbx;
         cc.C_split = C_split; cc.C_merge = C_merge; cc.eps_merge = eps_merge; cc.flux_test = flux_test;
@@ -2389,8 +2391,7 @@ __global__ __launch_bounds__(BS, 4) void k_criterion(const LevelDesc* __restrict
         for (int b = lane_id(); b < Nbase; b += WL) {
             const int p = cc.ptb[b];
             const double gpv = (double)g[p];
-            const double xp = gp(L.xi_x)[p], yp = gp(L.xi_y)[p];
-            const double Hb = (double)h[p] + (xp * xp + yp * yp) * gpv;
+            const double Hb = (double)h[p] + cc.x2b[b] * gpv;
             const double w = bw[b], x = bx[b], y = by[b];
             t[0] += w * gpv;
             t[1] += 0.5 * w * Hb;
@@ -2484,14 +2485,15 @@ hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFa
 }
 
 hipError_t launch_criterion(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
-                            int n_cells, const int* pt_of_base_all, const int* pt_off, const uint8_t* kappa_all,
+                            int n_cells, const int* pt_of_base_all, const int* pt_off, const double* x2_of_base_all,
+                            const uint8_t* kappa_all,
                             const double* bxi_x, const double* bxi_y, const double* bw, int nx, int ny,
                             double C_split, double C_merge, double eps_merge, int flux_test, uint8_t* kappa_out,
                             unsigned long long* hash_out, const int* cell_list) {
     if (n_cells <= 0) return hipSuccess;
     MLVS_DISPATCH(prec, k_criterion, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
-                  pt_of_base_all, pt_off, kappa_all, bxi_x, bxi_y, bw, nx, ny, C_split, C_merge, eps_merge, flux_test,
-                  kappa_out, hash_out, cell_list);
+                  pt_of_base_all, pt_off, x2_of_base_all, kappa_all, bxi_x, bxi_y, bw, nx, ny, C_split, C_merge,
+                  eps_merge, flux_test, kappa_out, hash_out, cell_list);
     return hipGetLastError();
 }
 

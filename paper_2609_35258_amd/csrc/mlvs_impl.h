@@ -159,7 +159,8 @@ hipError_t launch_remap(int prec, hipStream_t st, const LevelDesc* old_lv, const
                         const RemapItem* items, int n, Phys ph, unsigned long long* neg);
 hipError_t launch_criterion(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
                             const int* cell_slot, int n_cells, const int* pt_of_base_all,
-                            const int* pt_off, const uint8_t* kappa_all, const double* bxi_x,
+                            const int* pt_off, const double* x2_of_base_all, const uint8_t* kappa_all,
+                            const double* bxi_x,
                             const double* bxi_y, const double* bw, int nx, int ny,
                             double C_split, double C_merge, double eps_merge, int flux_test,
                             uint8_t* kappa_out, unsigned long long* hash_out, const int* cell_list = nullptr);
