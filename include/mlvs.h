@@ -187,10 +187,8 @@ mlvs_status mlvs_create(const mlvs_physics* phys, const mlvs_mesh* mesh, const m
                         const mlvs_adapt_params* adapt, const mlvs_device* dev, mlvs_ctx* out);
 
 /* The same on an unstructured mesh (dim = 2).  Cells keep their input ids in
- * every per-cell array of the ABI.  The learned selector's features (their
- * density gradient uses index directions) are not defined here: mlvs_features
- * and adaptation with a selector installed are MLVS_E_STATE on such a
- * context. */
+ * every per-cell array of the ABI.  The learned selector's density-gradient
+ * feature is the least-squares gradient over the face neighbours here. */
 mlvs_status mlvs_create_unstructured(const mlvs_physics* phys, const mlvs_umesh* mesh, const mlvs_vgrid* vgrid,
                                      const mlvs_adapt_params* adapt, const mlvs_device* dev, mlvs_ctx* out);
 
@@ -314,7 +312,9 @@ mlvs_status mlvs_positivity_counts(mlvs_ctx ctx, int64_t* applied, int64_t* fail
  * Features per cell: log rho, u/sqrt(R T_ref), v/sqrt(R T_ref), log(T/T_ref),
  * q_x/(p sqrt(RT)), q_y/(p sqrt(RT)), sigma_xx/p, sigma_xy/p,
  * log(1 + dx |grad rho|/rho), log10(lambda/dx) with lambda = (mu/p)
- * sqrt(pi R T/2), dx = sqrt(|V|).  Labels: the fewest-point level of the
+ * sqrt(pi R T/2), dx = sqrt(|V|); grad rho by central differences per index
+ * direction (structured meshes) or least squares over the face neighbours
+ * (unstructured meshes).  Labels: the fewest-point level of the
  * current catalogue whose enclosing mask is no coarser than the cell's own
  * criterion mask anywhere (the criterion is the judge), -1 if none. */
 typedef struct {

@@ -119,8 +119,16 @@ def cell_stress(xi, w, g, rho, u, T, R):
 
 def cell_gradient(mesh, rho):
     """|grad rho| per cell: per index direction the central difference (one-sided
-    next to a boundary, zero without neighbours), mapped through [t_i; t_j]^-1."""
+    next to a boundary, zero without neighbours), mapped through [t_i; t_j]^-1.
+    Unstructured meshes: the unlimited least-squares gradient over the face
+    neighbours (a boundary face a zero-gradient ghost at the mirror point)."""
     out = np.zeros(mesh.n_cells)
+    if getattr(mesh, "kind", "") == "unstructured":
+        from .umesh import lsq_gradient
+        for c in range(mesh.n_cells):
+            nv = [None if nb < 0 else np.array([rho[nb]]) for nb, _, _ in mesh.cell_faces[c]]
+            out[c] = float(np.hypot(*lsq_gradient(mesh, c, np.array([rho[c]]), nv)[0]))
+        return out
     for c in range(mesh.n_cells):
         s = np.zeros(2)
         for d in range(2):

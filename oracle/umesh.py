@@ -154,6 +154,19 @@ def venkat(dp, dm, eps2):
     return out
 
 
+def lsq_gradient(mesh, c, fc, nvals):
+    """Unlimited least-squares gradient of one quantity of cell c: fc (N,),
+    nvals per local face the neighbour values (N,) or None (boundary face,
+    zero-gradient ghost at the mirror point).  Returns (N, 2)."""
+    A = np.zeros((2, 2))
+    rhs = np.zeros((len(fc), 2))
+    for (nb, fo, d), v in zip(mesh.cell_faces[c], nvals):
+        A += np.outer(d, d)
+        if v is not None:
+            rhs += np.outer(v - fc, d)
+    return rhs @ np.linalg.inv(A).T
+
+
 def lsq_limited_slope(mesh, c, fc, nvals, eps2=None):
     """Limited gradient of one quantity of cell c at every velocity point.
 

@@ -1572,13 +1572,12 @@ void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
 }
 
 void compute_features(mlvs_ctx c, float* d_out) {
-    if (c->mesh.unstructured) fail(MLVS_E_STATE, "the selector's features need a structured mesh");
     const int n = c->mesh.n_cells;
     double* d8 = static_cast<double*>(c->dm.alloc(sizeof(double) * 8 * (size_t)n));
     hip_check(launch_cell_moments(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom, c->ph,
                                   nullptr, nullptr, d8), "moments launch");
     hip_check(launch_features(c->st, d8, c->d_nbr_cell, c->d_geom, n, c->ph.R, c->ph.T_ref, c->ph.mu_ref,
-                              c->ph.omega, d_out), "features launch");
+                              c->ph.omega, c->mesh.unstructured ? 1 : 0, d_out), "features launch");
     sync(c);
     c->dm.release(d8);
 }

@@ -172,7 +172,7 @@ hipError_t launch_compare_rows_u8(hipStream_t st, const uint8_t* all, int width,
 // learned selector (selector.hip)
 int mlp_nparams(int K);
 hipError_t launch_features(hipStream_t st, const double* f8, const int* nbr_cell, const CellGeom* geom, int n,
-                           double R, double T_ref, double mu_ref, double omega, float* out);
+                           double R, double T_ref, double mu_ref, double omega, int unstructured, float* out);
 hipError_t launch_mlp_fwd_bwd(hipStream_t st, const float* P, int K, const float* X, const int* y, const int* idx,
                               int B, float* XN, float* A1, float* A2, float* D1, float* D2, float* D3, float* prob,
                               float* lossv, double* loss_sum);

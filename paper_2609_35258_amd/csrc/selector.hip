@@ -35,7 +35,7 @@ int mlp_nparams(int K) { return mlp_offsets(K, 8); }
 // ---------------------------------------------------------------------------
 __global__ void k_features(const double* __restrict__ f8, const int* __restrict__ nbr_cell,
                            const CellGeom* __restrict__ geom, int n_cells, double R, double T_ref,
-                           double mu_ref, double omega, float* __restrict__ out) {
+                           double mu_ref, double omega, int unstructured, float* __restrict__ out) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
     const double* m = f8 + 8 * (size_t)c;
@@ -52,8 +52,21 @@ __global__ void k_features(const double* __restrict__ f8, const int* __restrict_
         else if (lo >= 0) sdir[d] = (rho - f8[8 * (size_t)lo]) / g.dist[2 * d];
         else sdir[d] = 0.0;
     }
-    const double gx = g.G[0] * sdir[0] + g.G[1] * sdir[1];
-    const double gy = g.G[2] * sdir[0] + g.G[3] * sdir[1];
+    double gx = g.G[0] * sdir[0] + g.G[1] * sdir[1];
+    double gy = g.G[2] * sdir[0] + g.G[3] * sdir[1];
+    if (unstructured) {
+        // least squares over the face neighbours (slot k: the k-th edge); a
+        // boundary ghost carries no difference
+        gx = 0.0;
+        gy = 0.0;
+        for (int k = 0; k < 4; ++k) {
+            const int nb = nbr_cell[4 * c + k];
+            if (nb < 0) continue;
+            const double d = f8[8 * (size_t)nb] - rho;
+            gx += g.lx[k] * d;
+            gy += g.ly[k] * d;
+        }
+    }
     const double grad = sqrt(gx * gx + gy * gy);
     const double mu = mu_ref * pow(T / T_ref, omega);
     const double lam = (mu / p) * sqrt(M_PI * R * T / 2.0);
@@ -308,10 +321,10 @@ __global__ void k_labels(const uint8_t* __restrict__ kcell, int n_cells, int Nb,
 // launch wrappers
 // ---------------------------------------------------------------------------
 hipError_t launch_features(hipStream_t st, const double* f8, const int* nbr_cell, const CellGeom* geom, int n,
-                           double R, double T_ref, double mu_ref, double omega, float* out) {
+                           double R, double T_ref, double mu_ref, double omega, int unstructured, float* out) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_features, dim3((n + 255) / 256), dim3(256), 0, st, f8, nbr_cell, geom, n, R, T_ref, mu_ref,
-                       omega, out);
+                       omega, unstructured, out);
     return hipGetLastError();
 }
 

@@ -71,6 +71,23 @@ def test_features_match_oracle():
     g.close()
 
 
+def test_features_match_oracle_unstructured():
+    # the density gradient by least squares over the face neighbours
+    p = W.perturb(W.two_cavity(16, nv=16, vmax=7.0, ratio=0.3), seed=6, amp=0.1)
+    o = Oracle(p, compat=4)
+    g = _m().Solver.from_problem(p, compat=4)
+    o.step(); g.step(1)
+    f = o.fields()
+    xi, w = o.vset(0)
+    sig = np.array([mlp.cell_stress(xi, w, o.g[c], f[c, 0], f[c, 1:3], f[c, 3], p.R) for c in range(p.n_cells)])
+    grad = mlp.cell_gradient(o.mesh, f[:, 0])
+    ref = mlp.features(f[:, 0], f[:, 1], f[:, 2], f[:, 3], f[:, 4], f[:, 5], sig[:, 0], sig[:, 1], grad,
+                       o.mesh.vol, p.R, p.T_ref, o.mu(f[:, 3]))
+    got = g.features()
+    assert np.allclose(got, ref, rtol=2e-5, atol=2e-6)
+    g.close()
+
+
 def _catalogue_problem(seed=4):
     p = W.perturb(W.periodic_box(12, 6, Lx=1.0, Ly=0.5, Kn=0.05, nv=32, vmax=5.0, kind="sine", amp=0.5), seed=seed)
     o1 = Oracle(p, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 1e-3, 0.03, True, 100))
@@ -125,6 +142,38 @@ def test_learned_adaptation_run():
         g.step(5)
     print("learned adaptations", reps, flush=True)
     assert np.max(np.abs(g.totals() - t0)) < 1e-12
+    assert all(r["n_fallback"] < g.n_cells for r in reps)
+    g.close()
+
+
+def test_learned_adaptation_run_unstructured():
+    # the learned path on the two-cavity mesh: train on snapshots, then adapt
+    m = _m()
+    p = W.perturb(W.two_cavity(16, nv=16, vmax=7.0, ratio=0.05), seed=3, amp=0.3)
+    ap = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=1e-3, tau_clust=0.02, flux_test=True, interval=0)
+    g = m.Solver.from_problem(p, compat=4, adapt=ap)
+    g.step(2)
+    g.adapt()
+    K = len(g.level_info()[0])
+    assert 2 <= K <= 16, K
+    X, Y = [], []
+    for snap in range(8):
+        g.step(5)
+        X.append(g.features())
+        Y.append(g.labels())
+    X = np.concatenate(X)
+    Y = np.concatenate(Y)
+    ok = Y >= 0
+    params, rep = m.mlp_train(W.mlp_init_params(K, 0), K, X[ok], Y[ok], epochs=30, batch=256, lr=3e-3,
+                              val_frac=0.2, seed=1)
+    print("training", rep, flush=True)
+    assert rep["loss_last"] < rep["loss_first"]
+    t0 = g.totals()
+    g.selector_set(params, K)
+    reps = [g.adapt() for _ in range(2)]
+    g.step(3)
+    print("learned adaptations", reps, flush=True)
+    assert abs(g.totals()[0] - t0[0]) < 1e-12 * t0[0]
     assert all(r["n_fallback"] < g.n_cells for r in reps)
     g.close()
 

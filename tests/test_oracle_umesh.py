@@ -81,6 +81,18 @@ def test_least_squares_exact_for_linear_fields(split):
         assert np.allclose(sig, b, rtol=0, atol=1e-12)
 
 
+def test_unlimited_least_squares_gradient_exact_for_linear_fields():
+    p = W.two_cavity(16)
+    m = UMesh(p)
+    b = np.array([0.4, -1.3])
+    for c in range(0, m.n_cells, 5):
+        if any(nb < 0 for nb, _, _ in m.cell_faces[c]):
+            continue
+        fc = np.array([2.0 + b @ m.xc[c]])
+        nv = [np.array([2.0 + b @ m.xc[nb]]) for nb, _, _ in m.cell_faces[c]]
+        assert np.allclose(um.lsq_gradient(m, c, fc, nv), b[None, :], rtol=0, atol=1e-12)
+
+
 def test_venkatakrishnan_closed_forms():
     d = np.array([1e-3, 0.5, 3.0])
     # V(d+, d-) = (y^2 + 2y)/(y^2 + y + 2) with y = d+/d- when eps = 0
