@@ -458,11 +458,13 @@ struct PinnedBuf {
     size_t cap = 0;
     uint8_t* ensure(size_t n) {
         if (n > cap) {
+            // pinning is slow: grow geometrically, from 4 MiB
+            const size_t want = std::max(n, std::max(2 * cap, (size_t)4 << 20));
             if (p) (void)hipHostFree(p);
             p = nullptr;
             cap = 0;
-            hip_check(hipHostMalloc((void**)&p, std::max<size_t>(n, 1), hipHostMallocDefault), "pinned alloc");
-            cap = std::max<size_t>(n, 1);
+            hip_check(hipHostMalloc((void**)&p, want, hipHostMallocDefault), "pinned alloc");
+            cap = want;
         }
         return p;
     }
@@ -1434,11 +1436,12 @@ void dedupe(mlvs_ctx c, const uint8_t*& uniq, std::vector<int>& first, std::vect
 }
 
 // Run f(lo, hi) over [0, n) split into contiguous ranges on up to 8 host
-// threads (one range when n is small).  f must only write its own range.
+// threads, each range at least `grain` long (one range when n is small: a
+// thread costs tens of microseconds).  f must only write its own range.
 template <class F>
-void parallel_ranges(int n, F&& f) {
+void parallel_ranges(int n, int grain, F&& f) {
     const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
-    const int nt = (int)std::min<long>(hw, std::max(1, n / 64));
+    const int nt = (int)std::min<long>(hw, std::max(1, n / std::max(grain, 1)));
     if (nt <= 1) { f(0, n); return; }
     std::vector<std::thread> th;
     for (int t = 1; t < nt; ++t) th.emplace_back([&, t] { f((int)((long)n * t / nt), (int)((long)n * (t + 1) / nt)); });
@@ -1492,7 +1495,7 @@ void cluster(int Nb, double tau, const uint8_t* uniq, const std::vector<int>& fi
         best[j] = cid;
         bestd[j] = 0;
         const uint8_t* kc = &uniq[(size_t)order[j] * Nb];
-        parallel_ranges(U - j - 1, [&](int lo, int hi) {
+        parallel_ranges(U - j - 1, std::max(64, (1 << 18) / std::max(Nb, 1)), [&](int lo, int hi) {
             for (int k = j + 1 + lo; k < j + 1 + hi; ++k) {
                 const long cap = best[k] < 0 ? thr : bestd[k] - 1;
                 if (cap < 0) continue;
@@ -1509,7 +1512,7 @@ void cluster(int Nb, double tau, const uint8_t* uniq, const std::vector<int>& fi
         const uint8_t* kc = &uniq[(size_t)order[centres[c]] * Nb];
         kmin[c].assign(kc, kc + Nb);
     }
-    parallel_ranges(Nb, [&](int lo, int hi) {
+    parallel_ranges(Nb, std::max(64, (1 << 18) / std::max(U, 1)), [&](int lo, int hi) {
         for (int k = 0; k < U; ++k) {
             const uint8_t* ku = &uniq[(size_t)order[k] * Nb];
             uint8_t* km = kmin[best[k]].data();
