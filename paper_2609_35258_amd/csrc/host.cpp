@@ -1034,6 +1034,7 @@ void build_items(mlvs_ctx c) {
         }
     // interior faces, in the traversal order of their left cells
     int n_cross = 0;
+    std::map<std::pair<int, int>, int> iface_of_pair;
     for (int f : M.face_order) {
         const FaceH& F = M.faces[f];
         const int lL = c->cell_level[F.L], lR = c->cell_level[F.R];
@@ -1060,12 +1061,22 @@ void build_items(mlvs_ctx c) {
             it.rowB = rows[lR]++;
             it.nx = F.nx; it.ny = F.ny; it.area = F.area;
             it.dLx = F.dLx; it.dLy = F.dLy; it.dRx = F.dRx; it.dRy = F.dRy;
-            std::vector<uint8_t> kI(c->base.Nb);
-            const auto& kA = c->levels[lL]->kappa;
-            const auto& kB = c->levels[lR]->kappa;
-            for (int b = 0; b < c->base.Nb; ++b) kI[b] = std::min(kA[b], kB[b]);
+            // the interface level depends on the level pair only
+            const auto pk = std::make_pair(std::min(lL, lR), std::max(lL, lR));
             int iidx = -1;
-            Level* I = find_iface(c, kI, iidx);
+            Level* I = nullptr;
+            auto ip = iface_of_pair.find(pk);
+            if (ip == iface_of_pair.end()) {
+                std::vector<uint8_t> kI(c->base.Nb);
+                const auto& kA = c->levels[lL]->kappa;
+                const auto& kB = c->levels[lR]->kappa;
+                for (int b = 0; b < c->base.Nb; ++b) kI[b] = std::min(kA[b], kB[b]);
+                I = find_iface(c, kI, iidx);
+                iface_of_pair[pk] = iidx;
+            } else {
+                iidx = ip->second;
+                I = &level_by_index(c, iidx);
+            }
             it.levI = iidx;
             it.scratch = I->n_rows++;
             xitems.push_back(it);
