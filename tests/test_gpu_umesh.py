@@ -60,6 +60,29 @@ def test_uvs_fp64(case, chunk, monkeypatch):
     g.close()
 
 
+@pytest.mark.parametrize("mode", ["uvs", "mlvs"])
+def test_o_grid_with_least_squares_slopes_fp64(mode):
+    # the body-fitted cylinder O-grid taken as an unstructured mesh: least
+    # squares + Venkatakrishnan in place of van Leer per index direction
+    p = W.perturb(W.cylinder(16, 8, Kn=0.1, nv=32, vmax=10.0), seed=3, amp=0.1)
+    q = W.as_unstructured(p)
+    print("case o-grid unstructured", mode, flush=True)
+    o = Oracle(q, compat=4)
+    g = _gpu(q, compat=4)
+    if mode == "mlvs":
+        o1 = Oracle(q, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 1e-3, 0.02, True, 100))
+        kap, cl = lv.cluster_masks(o1.criterion_masks(), 0.02)
+        assert len(kap) >= 2
+        o.set_levels(kap, cl)
+        g.set_levels(np.stack(kap), cl)
+    for k in range(3):
+        o.step()
+        g.step(1)
+        e = state_error(g.get_state(), o.g, o.h)
+        assert max(e) < TOL, (k, e)
+    g.close()
+
+
 def _perturbed(ratio=0.05):
     return W.perturb(W.two_cavity(16, nv=16, vmax=7.0, ratio=ratio), seed=3, amp=0.3)
 

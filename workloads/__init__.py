@@ -397,15 +397,21 @@ def two_cavity(n: int = 48, nv: int = 101, vmax: float = 7.0, Kn_left: float = 1
 
 
 def as_unstructured(problem: Problem, split: str = "none", seed: int = 0) -> UProblem:
-    """A non-periodic structured problem as an unstructured one: the same
-    nodes, each quadrilateral kept ("none"), cut along its (i,j)-(i+1,j+1)
-    diagonal ("diag") or along a seeded random diagonal ("random").  Cell
-    order: (i, j) row-major, the two triangles of a cut cell in a row."""
-    if problem.periodic_i or problem.periodic_j or problem.dim != 2:
-        raise ValueError("needs a non-periodic 2-D problem")
+    """A structured problem as an unstructured one: the same nodes, each
+    quadrilateral kept ("none"), cut along its (i,j)-(i+1,j+1) diagonal
+    ("diag") or along a seeded random diagonal ("random").  Cell order: (i, j)
+    row-major, the two triangles of a cut cell in a row.  A direction periodic
+    in i whose seam nodes coincide (an O-grid) is closed by sharing those
+    nodes; other periodic meshes are not supported."""
+    if problem.periodic_j or problem.dim != 2:
+        raise ValueError("needs a 2-D problem not periodic in j")
     ni, nj = problem.ni, problem.nj
+    if problem.periodic_i and not (np.allclose(problem.X[:, 0], problem.X[:, ni])
+                                   and np.allclose(problem.Y[:, 0], problem.Y[:, ni])):
+        raise ValueError("periodic in i without coinciding seam nodes")
     nodes = np.stack([problem.X.ravel(), problem.Y.ravel()], axis=1)
-    nid = lambda i, j: j * (ni + 1) + i
+    wrap = problem.periodic_i
+    nid = lambda i, j: j * (ni + 1) + (0 if (wrap and i == ni) else i)
     rng = np.random.default_rng(seed)
     cells, src = [], []
     for j in range(nj):
@@ -418,7 +424,7 @@ def as_unstructured(problem: Problem, split: str = "none", seed: int = 0) -> UPr
             else:
                 cells += [(a, b, d), (b, c, d)]; src += [i + ni * j] * 2
     bedges = []
-    for j in range(nj):
+    for j in range(nj if not wrap else 0):
         bedges.append((nid(0, j + 1), nid(0, j), int(problem.bc_imin[j])))
         bedges.append((nid(ni, j), nid(ni, j + 1), int(problem.bc_imax[j])))
     for i in range(ni):
