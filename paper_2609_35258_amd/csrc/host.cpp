@@ -15,6 +15,10 @@
 #include <stdexcept>
 #include <string>
 #include <thread>
+#include <unistd.h>
+#include <mutex>
+#include <condition_variable>
+#include <functional>
 #include <unordered_map>
 #include <vector>
 
@@ -1446,18 +1450,93 @@ void dedupe(mlvs_ctx c, const uint8_t*& uniq, std::vector<int>& first, std::vect
     }
 }
 
-// Run f(lo, hi) over [0, n) split into contiguous ranges on up to 8 host
-// threads, each range at least `grain` long (one range when n is small: a
-// thread costs tens of microseconds).  f must only write its own range.
+// Host worker threads for the adaptation's parallel passes, started on first
+// use and kept (starting a thread costs tens of microseconds, and an
+// adaptation runs several passes).  run(nt, f) calls f(t) for t in [0, nt),
+// t = 0 on the calling thread, and returns when every call has returned;
+// calls of run are serialised.
+class HostPool {
+public:
+    static HostPool& get() {
+        static HostPool pool;
+        return pool;
+    }
+    int size() const { return (int)workers_.size() + 1; }
+    void run(int nt, const std::function<void(int)>& f) {
+        std::lock_guard<std::mutex> serial(run_m_);
+        if (getpid() != pid_) {                    // a forked child has no workers
+            for (int t = 0; t < nt; ++t) f(t);
+            return;
+        }
+        nt = std::min(nt, size());
+        if (nt <= 1) { f(0); return; }
+        {
+            std::lock_guard<std::mutex> g(m_);
+            job_ = &f;
+            active_ = nt - 1;
+            pending_ = nt - 1;
+            ++gen_;
+        }
+        cv_.notify_all();
+        f(0);
+        std::unique_lock<std::mutex> lk(m_);
+        done_.wait(lk, [&] { return pending_ == 0; });
+        job_ = nullptr;
+    }
+    ~HostPool() {
+        {
+            std::lock_guard<std::mutex> g(m_);
+            stop_ = true;
+            ++gen_;
+        }
+        cv_.notify_all();
+        for (auto& t : workers_) t.join();
+    }
+
+private:
+    HostPool() : pid_(getpid()) {
+        const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+        for (unsigned i = 1; i < hw; ++i) workers_.emplace_back([this, i] { loop((int)i); });
+    }
+    void loop(int idx) {
+        unsigned long long seen = 0;
+        for (;;) {
+            const std::function<void(int)>* f = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(m_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+                if (idx > active_) continue;           // not needed in this run
+                f = job_;
+            }
+            (*f)(idx);
+            std::lock_guard<std::mutex> g(m_);
+            if (--pending_ == 0) done_.notify_one();
+        }
+    }
+    std::vector<std::thread> workers_;
+    std::mutex m_, run_m_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)>* job_ = nullptr;
+    int active_ = 0, pending_ = 0;
+    unsigned long long gen_ = 0;
+    bool stop_ = false;
+    pid_t pid_;
+};
+
+// Run f(lo, hi) over [0, n) split into contiguous ranges on the host pool,
+// each range at least `grain` long (one range on the calling thread when n is
+// small).  f must only write its own range.
 template <class F>
 void parallel_ranges(int n, int grain, F&& f) {
-    const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
-    const int nt = (int)std::min<long>(hw, std::max(1, n / std::max(grain, 1)));
+    HostPool& P = HostPool::get();
+    const int nt = (int)std::min<long>(P.size(), std::max(1, n / std::max(grain, 1)));
     if (nt <= 1) { f(0, n); return; }
-    std::vector<std::thread> th;
-    for (int t = 1; t < nt; ++t) th.emplace_back([&, t] { f((int)((long)n * t / nt), (int)((long)n * (t + 1) / nt)); });
-    f(0, (int)((long)n / nt));
-    for (auto& x : th) x.join();
+    const std::function<void(int)> job = [&](int t) {
+        f((int)((long)n * t / nt), (int)((long)n * (t + 1) / nt));
+    };
+    P.run(nt, job);
 }
 
 // Leader clustering of the unique masks (descending frequency, ties by first
