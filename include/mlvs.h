@@ -202,7 +202,11 @@ mlvs_status mlvs_init_equilibrium(mlvs_ctx ctx, const double* rho_u_v_T);
  * level_switch_conservation). */
 mlvs_status mlvs_set_levels(mlvs_ctx ctx, int n_levels, const uint8_t* kappa, const int32_t* cell_level);
 
-/* Advance n_steps time steps (stream-ordered, asynchronous). */
+/* Advance n_steps time steps (stream-ordered, asynchronous).  Cross-level
+ * faces run on a second stream of the context (default priority), forked
+ * from the context stream after the neighbour mapping and joined back before
+ * the update of the same step, so every step stays ordered on the caller's
+ * stream. */
 mlvs_status mlvs_step(mlvs_ctx ctx, int n_steps);
 
 /* Criterion + grouping + remap now (Secs. 3.2, 3.4).  report may be NULL. */
