@@ -380,6 +380,57 @@ def two_cavity_to_time(t_end=4.0, precision=32, interval=5, map_moments=4):
             "mlvs_vs_uvs_rel_l2": err}
 
 
+def long_run(kind="cylinder", steps=10000, warmup=100, precision=32):
+    """A whole run of the cylinder (10,000 steps, about one flow-through) or the
+    jet (2,000 steps) from the freestream or background state, MLVS against
+    UVS, each timed over the whole run: `warmup` base-grid steps, then the
+    MLVS run adapts at the start of every block of 100 steps (adaptation
+    included).  Field differences at the end."""
+    import torch
+    import paper_2609_35258_amd as m
+    from paper_2609_35258_amd import autotune
+    p = (W.cylinder(256, 128, Kn=0.1, nv=101, vmax=10.0) if kind == "cylinder"
+         else W.jet(512, 256, Kn_jet=1e-3, nv=161, vmax=7.0))
+    out = {}
+    for mode in ("mlvs", "uvs"):
+        s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=CYL_ADAPT if mode == "mlvs" else None,
+                                  graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(10)
+        autotune.autotune(s, precision)
+        s.step(warmup - 10)
+        done = warmup
+        while done < steps:
+            if mode == "mlvs":
+                s.adapt()
+            k = min(CYL_INTERVAL, steps - done)
+            s.step(k)
+            done += k
+            if done % 500 == 0 or done == steps:
+                torch.cuda.synchronize()
+                print("%s %s step %d of %d, %.1f s" % (kind, mode, done, steps, time.perf_counter() - t0),
+                      file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        npts, ncells, ncross = s.level_info()
+        out[mode] = {"seconds": t, "fields": s.moments(), "memory": s.memory(), "levels": [int(x) for x in npts],
+                     "nbar": float(np.sum(npts * ncells) / np.sum(ncells)), "n_cross": int(ncross)}
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    fm, fu = out["mlvs"]["fields"], out["uvs"]["fields"]
+    rl2 = lambda a, b: float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+    err = {"rho": rl2(fm[:, 0], fu[:, 0]), "u": rl2(fm[:, 1:3], fu[:, 1:3]), "T": rl2(fm[:, 3], fu[:, 3]),
+           "q": rl2(fm[:, 4:6], fu[:, 4:6])}
+    return {"workload": "%s, %d steps (%d on the base grid first), fp%d, MLVS adaptation every %d steps; whole runs "
+                        "timed" % (kind, steps, warmup, precision, CYL_INTERVAL),
+            "mlvs_seconds": out["mlvs"]["seconds"], "uvs_seconds": out["uvs"]["seconds"],
+            "speedup": out["uvs"]["seconds"] / out["mlvs"]["seconds"],
+            "memory_ratio": out["uvs"]["memory"] / out["mlvs"]["memory"], "levels": out["mlvs"]["levels"],
+            "nbar": out["mlvs"]["nbar"], "n_cross": out["mlvs"]["n_cross"], "mlvs_vs_uvs_rel_l2": err}
+
+
 def cell_areas(p):
     """Shoelace areas of an unstructured problem's cells (weights of the field differences)."""
     out = np.zeros(p.n_cells)
@@ -517,6 +568,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-cylinder", action="store_true")
     ap.add_argument("--no-jet", action="store_true")
+    ap.add_argument("--long", choices=("cylinder", "jet"), default=None,
+                    help="only a whole run of that case, MLVS against UVS (10,000 cylinder or 2,000 jet steps)")
     ap.add_argument("--no-two-cavity", action="store_true")
     ap.add_argument("--two-cavity-only", action="store_true", help="only the two-cavity comparison")
     ap.add_argument("--tc-mode", default="both", choices=["both", "uvs", "mlvs"])
@@ -545,6 +598,9 @@ def main():
         return
     if args.jet_only:
         print(json.dumps({"jet": jet_case(mode=args.jet_mode)}), flush=True)
+        return
+    if args.long:
+        print(json.dumps({"long_run": long_run(args.long, 10000 if args.long == "cylinder" else 2000)}), flush=True)
         return
     if args.two_cavity_only:
         if args.tc_t_end > 0:
