@@ -431,6 +431,61 @@ def long_run(kind="cylinder", steps=10000, warmup=100, precision=32):
             "nbar": out["mlvs"]["nbar"], "n_cross": out["mlvs"]["n_cross"], "mlvs_vs_uvs_rel_l2": err}
 
 
+def tau_sweep(steps=2000, warmup=100, taus=(1.0, 0.07, 0.05, 0.04, 0.035), precision=32):
+    """Clustering-threshold sweep on the full cylinder (the paper's threshold
+    study): for each tau_clust an MLVS run of `steps` steps (`warmup` on the
+    base grid, then adaptation every 100 steps), timed whole, against one UVS
+    run of the same steps; levels, cross faces and field differences at the
+    end, and the cheapest setting within 1e-3 on rho and T."""
+    import torch
+    import paper_2609_35258_amd as m
+    from paper_2609_35258_amd import autotune
+    p = W.cylinder(256, 128, Kn=0.1, nv=101, vmax=10.0)
+
+    def run(adapt):
+        s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=adapt, graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(10)
+        autotune.autotune(s, precision)
+        s.step(warmup - 10)
+        done = warmup
+        while done < steps:
+            if adapt is not None:
+                s.adapt()
+            k = min(CYL_INTERVAL, steps - done)
+            s.step(k)
+            done += k
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        npts, ncells, ncross = s.level_info()
+        r = {"seconds": t, "fields": s.moments(), "levels": len(npts),
+             "nbar": float(np.sum(npts * ncells) / np.sum(ncells)), "n_cross": int(ncross)}
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        return r
+
+    ref = run(None)
+    print("tau sweep: UVS %.1f s" % ref["seconds"], file=sys.stderr, flush=True)
+    fu = ref["fields"]
+    rl2 = lambda a, b: float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+    rows = []
+    for tau in taus:
+        r = run(dict(CYL_ADAPT, tau_clust=tau))
+        fm = r.pop("fields")
+        r.update(tau_clust=tau, speedup=ref["seconds"] / r["seconds"],
+                 rel_l2={"rho": rl2(fm[:, 0], fu[:, 0]), "u": rl2(fm[:, 1:3], fu[:, 1:3]), "T": rl2(fm[:, 3], fu[:, 3]),
+                         "q": rl2(fm[:, 4:6], fu[:, 4:6])})
+        print("tau %g: %.1f s, %d levels" % (tau, r["seconds"], r["levels"]), file=sys.stderr, flush=True)
+        rows.append(r)
+    ok = [r for r in rows if r["rel_l2"]["rho"] <= 1e-3 and r["rel_l2"]["T"] <= 1e-3]
+    best = min(ok, key=lambda r: r["seconds"])["tau_clust"] if ok else None
+    return {"workload": "cylinder 256x128, 101^2, fp%d, %d steps (%d on the base grid), adaptation every %d steps"
+                        % (precision, steps, warmup, CYL_INTERVAL),
+            "uvs_seconds": ref["seconds"], "runs": rows, "cheapest_within_1e-3_rho_T": best}
+
+
 def cell_areas(p):
     """Shoelace areas of an unstructured problem's cells (weights of the field differences)."""
     out = np.zeros(p.n_cells)
@@ -568,6 +623,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-cylinder", action="store_true")
     ap.add_argument("--no-jet", action="store_true")
+    ap.add_argument("--tau-sweep", action="store_true", help="only the clustering-threshold sweep on the cylinder")
     ap.add_argument("--long", choices=("cylinder", "jet"), default=None,
                     help="only a whole run of that case, MLVS against UVS (10,000 cylinder or 2,000 jet steps)")
     ap.add_argument("--no-two-cavity", action="store_true")
@@ -598,6 +654,9 @@ def main():
         return
     if args.jet_only:
         print(json.dumps({"jet": jet_case(mode=args.jet_mode)}), flush=True)
+        return
+    if args.tau_sweep:
+        print(json.dumps({"tau_sweep": tau_sweep()}), flush=True)
         return
     if args.long:
         print(json.dumps({"long_run": long_run(args.long, 10000 if args.long == "cylinder" else 2000)}), flush=True)
