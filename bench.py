@@ -331,7 +331,7 @@ def two_cavity_case(steps=200, warmup=100, precision=32, mode="both", interval=5
                     "mlvs_vs_uvs_rel_l2": err}}
 
 
-def two_cavity_to_time(t_end=4.0, precision=32, interval=5, map_moments=4, tau_clust=0.05):
+def two_cavity_to_time(t_end=4.0, precision=32, interval=5, map_moments=4, tau_clust=0.05, scale=1.0):
     """The two-cavity expansion run to dimensionless time t_end (the paper
     compares MLVS and UVS at t = 4), both forms timed over the whole run from
     the initial state (MLVS adaptation every `interval` steps included), with
@@ -344,7 +344,9 @@ def two_cavity_to_time(t_end=4.0, precision=32, interval=5, map_moments=4, tau_c
     out = {}
     for mode in ("mlvs", "uvs"):
         s = m.Solver.from_problem(p, precision=precision, compat=4, map_moments=map_moments,
-                                  adapt=dict(TC_ADAPT, interval=interval, tau_clust=tau_clust) if mode == "mlvs" else None,
+                                  adapt=dict(TC_ADAPT, interval=interval, tau_clust=tau_clust,
+                                             C_split=scale * TC_ADAPT["C_split"], C_merge=scale * TC_ADAPT["C_merge"],
+                                             eps_merge=scale * TC_ADAPT["eps_merge"]) if mode == "mlvs" else None,
                                   graph=True)
         n = int(round(t_end / s.dt))
         torch.cuda.synchronize()
@@ -372,8 +374,8 @@ def two_cavity_to_time(t_end=4.0, precision=32, interval=5, map_moments=4, tau_c
     err = {"rho": rl2(fm[:, :1], fu[:, :1]), "p": rl2((fm[:, 0] * fm[:, 3])[:, None], (fu[:, 0] * fu[:, 3])[:, None]),
            "u": rl2(fm[:, 1:3], fu[:, 1:3]), "T": rl2(fm[:, 3:4], fu[:, 3:4]), "q": rl2(fm[:, 4:6], fu[:, 4:6])}
     return {"workload": "two-cavity expansion to t = %g (%d steps), 9504 unstructured cells, 101^2, fp%d, MLVS "
-                        "adaptation every %d steps, %d-moment mapping, tau_clust %g; whole runs timed" % (
-                            t_end, out["uvs"]["steps"], precision, interval, map_moments, tau_clust),
+                        "adaptation every %d steps, %d-moment mapping, tau_clust %g, criterion thresholds x %g; whole "
+                        "runs timed" % (t_end, out["uvs"]["steps"], precision, interval, map_moments, tau_clust, scale),
             "mlvs_seconds": out["mlvs"]["seconds"], "uvs_seconds": out["uvs"]["seconds"],
             "speedup": out["uvs"]["seconds"] / out["mlvs"]["seconds"],
             "memory_ratio": out["uvs"]["memory"] / out["mlvs"]["memory"],
@@ -633,6 +635,7 @@ def main():
     ap.add_argument("--tc-interval", type=int, default=5)
     ap.add_argument("--tc-map", type=int, default=4, choices=[4, 9])
     ap.add_argument("--tc-tau", type=float, default=0.05)
+    ap.add_argument("--tc-scale", type=float, default=1.0, help="factor on C_split, C_merge and eps_merge")
     ap.add_argument("--tc-t-end", type=float, default=0.0,
                     help="with --two-cavity-only: run both forms to this time instead (the paper's t = 4)")
     ap.add_argument("--jet-only", action="store_true", help="only the full-size jet comparison (profiling runs)")
@@ -667,7 +670,8 @@ def main():
         if args.tc_t_end > 0:
             print(json.dumps({"two_cavity_to_time": two_cavity_to_time(args.tc_t_end, interval=args.tc_interval,
                                                                        map_moments=args.tc_map,
-                                                                       tau_clust=args.tc_tau)}), flush=True)
+                                                                       tau_clust=args.tc_tau,
+                                                                       scale=args.tc_scale)}), flush=True)
             return
         print(json.dumps({"two_cavity": two_cavity_case(mode=args.tc_mode, interval=args.tc_interval)}), flush=True)
         return
