@@ -210,6 +210,7 @@ T* upload(DevMem& dm, const std::vector<T>& v, hipStream_t st) {
 struct Base {
     int nx = 0, ny = 0, N = 0, nbx = 0, nby = 0, Nb = 0;
     std::vector<double> x, y, w;     // per base point
+    std::vector<double> axes;        // the tensor grid's axes: x [nx], wx [nx], y [ny], wy [ny]
 };
 
 struct Level {
@@ -864,7 +865,7 @@ struct mlvs_ctx_s {
     unsigned long long* d_neg = nullptr;
     bool state_ready = false;
     // criterion inputs: base grid and per-level maps / masks
-    double *d_bx = nullptr, *d_by = nullptr, *d_bw = nullptr;
+    double *d_bx = nullptr, *d_by = nullptr, *d_bw = nullptr, *d_axes = nullptr;
     int *d_ptb_all = nullptr, *d_ptb_off = nullptr;
     double* d_x2b_all = nullptr;       // per level and base point: |xi_p|^2 of its level point p
     PinnedBuf pin_masks;               // host copy of the unique masks (adaptation)
@@ -1378,7 +1379,8 @@ void run_criterion(mlvs_ctx c) {
     if (!c->d_kcell) c->d_kcell = static_cast<uint8_t*>(c->dm.alloc((size_t)n * Nb));
     if (!c->d_hash) c->d_hash = static_cast<unsigned long long*>(c->dm.alloc(sizeof(unsigned long long) * n));
     hip_check(launch_criterion(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_ptb_all, c->d_ptb_off,
-                               c->d_x2b_all, c->d_kappa_all, c->d_bx, c->d_by, c->d_bw, c->base.nx, c->base.ny, c->ap.C_split,
+                               c->d_x2b_all, c->d_kappa_all, c->d_bx, c->d_by, c->d_bw, c->d_axes, c->base.nx, c->base.ny,
+                               c->ap.C_split,
                                c->ap.C_merge, c->ap.eps_merge, c->ap.flux_test, c->d_kcell, c->d_hash),
               "criterion launch");
 }
@@ -1709,7 +1711,7 @@ void adapt_learned(mlvs_ctx c, mlvs_adapt_report* rep) {
         int* d_list = upload(c->dm, rej, c->st);
         hip_check(launch_criterion(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, (int)rej.size(),
                                    c->d_ptb_all, c->d_ptb_off, c->d_x2b_all, c->d_kappa_all, c->d_bx, c->d_by, c->d_bw,
-                                   c->base.nx, c->base.ny, c->ap.C_split, c->ap.C_merge, c->ap.eps_merge,
+                                   c->d_axes, c->base.nx, c->base.ny, c->ap.C_split, c->ap.C_merge, c->ap.eps_merge,
                                    c->ap.flux_test, c->d_kcell, c->d_hash, d_list), "criterion launch");
         std::vector<int> order = level_order(c);
         int* d_order = upload(c->dm, order, c->st);
@@ -2081,6 +2083,10 @@ static mlvs_status create_impl(const mlvs_physics* phys, const mlvs_mesh* mesh, 
                 B.w.push_back(vg->wx[ix] * (phys->dim == 2 ? vg->wy[iy] : 1.0));
                 vmax = std::max(vmax, std::hypot(B.x.back(), B.y.back()));
             }
+        for (int ix = 0; ix < B.nx; ++ix) B.axes.push_back(vg->x[ix]);
+        for (int ix = 0; ix < B.nx; ++ix) B.axes.push_back(vg->wx[ix]);
+        for (int iy = 0; iy < B.ny; ++iy) B.axes.push_back(phys->dim == 2 ? vg->y[iy] : 0.0);
+        for (int iy = 0; iy < B.ny; ++iy) B.axes.push_back(phys->dim == 2 ? vg->wy[iy] : 1.0);
         Phys& ph = c->ph;
         ph.D = phys->dim; ph.K = phys->K; ph.R = phys->R; ph.Pr = phys->Pr; ph.omega = phys->omega;
         ph.mu_ref = phys->mu_ref; ph.T_ref = phys->T_ref;
@@ -2097,6 +2103,7 @@ static mlvs_status create_impl(const mlvs_physics* phys, const mlvs_mesh* mesh, 
         c->d_bx = upload(c->dm, B.x, c->st);
         c->d_by = upload(c->dm, B.y, c->st);
         c->d_bw = upload(c->dm, B.w, c->st);
+        c->d_axes = upload(c->dm, B.axes, c->st);
         std::vector<BCDev> bd;
         for (auto& b : c->bcs) bd.push_back(BCDev{b.kind, 0, b.rho, b.u, b.v, b.T});
         c->d_bcs = upload(c->dm, bd, c->st);

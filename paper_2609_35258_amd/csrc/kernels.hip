@@ -2293,7 +2293,15 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
     return z ^ (z >> 31);
 }
 
+// The tensor base grid's axes (x, wx, y, wy), staged in LDS by the criterion
+// kernel when each axis has at most CRIT_AXIS nodes: the block tests then read
+// node coordinates and weights from LDS instead of per-point arrays (their
+// scattered per-lane reads made the address unit the bottleneck).
+constexpr int CRIT_AXIS = 512;
+__shared__ double crit_axes[4 * CRIT_AXIS];
+
 struct CritCtx {
+    bool axes_lds;            // crit_axes holds the axes
     const int* ptb;           // base -> level point of the cell's level
     const double* x2b;        // base -> |xi_p|^2 of that level point (read in base order)
     const uint8_t* prev;      // kappa of the cell's current level
@@ -2319,7 +2327,14 @@ __device__ __forceinline__ bool crit_merges(const CritCtx& cc, const LevelDesc& 
             const int p = cc.ptb[b];
             const double gpv = (double)g[p];
             const double Hb = (double)h[p] + cc.x2b[b] * gpv;
-            const double w = cc.bw[b], x = cc.bx[b], y = cc.by[b];
+            double w, x, y;
+            if (cc.axes_lds) {
+                x = crit_axes[ix];
+                y = crit_axes[2 * CRIT_AXIS + iy];
+                w = crit_axes[CRIT_AXIS + ix] * crit_axes[3 * CRIT_AXIS + iy];
+            } else {
+                w = cc.bw[b]; x = cc.bx[b]; y = cc.by[b];
+            }
             m1 += w * gpv;
             m2 += 0.5 * w * Hb;
             if (cc.flux_test) {
@@ -2366,11 +2381,24 @@ __global__ __launch_bounds__(BS, 4) void k_criterion(const LevelDesc* __restrict
                                                   const double* __restrict__ x2b_all,
                                                   const uint8_t* __restrict__ kappa_all, const double* __restrict__ bx,
                                                   const double* __restrict__ by, const double* __restrict__ bw,
+                                                  const double* __restrict__ axes,
                                                   int nx, int ny, double C_split, double C_merge, double eps_merge,
                                                   int flux_test, uint8_t* __restrict__ kout,
                                                   unsigned long long* __restrict__ hout,
                                                   const int* __restrict__ cell_list) {
     const int nbx = nx / 2, nby = ny / 2, Nb = nbx * nby, Nbase = nx * ny;
+    const bool axes_lds = axes != nullptr && nx <= CRIT_AXIS && ny <= CRIT_AXIS;
+    if (axes_lds) {
+        for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+            crit_axes[i] = axes[i];
+            crit_axes[CRIT_AXIS + i] = axes[nx + i];
+        }
+        for (int i = threadIdx.x; i < ny; i += blockDim.x) {
+            crit_axes[2 * CRIT_AXIS + i] = axes[2 * nx + i];
+            crit_axes[3 * CRIT_AXIS + i] = axes[2 * nx + ny + i];
+        }
+    }
+    __syncthreads();
     const int n8x = nbx / 4, n8y = nby / 4, n4x = nbx / 2, n4y = nby / 2;
     for (int ci = item0(); ci < n_cells; ci += istride()) {
         const int c = cell_list ? cell_list[ci] : ci;
@@ -2380,6 +2408,7 @@ __global__ __launch_bounds__(BS, 4) void k_criterion(const LevelDesc* __restrict
         auto g = rowp<S>(L.g, row);
         auto h = rowp<S>(L.h, row);
         CritCtx cc;
+        cc.axes_lds = axes_lds;
         cc.ptb = ptb_all + (size_t)ptb_off[lev];
         cc.x2b = x2b_all + (size_t)ptb_off[lev];
         cc.prev = kappa_all + (size_t)lev * Nb;
@@ -2487,12 +2516,12 @@ hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFa
 hipError_t launch_criterion(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
                             int n_cells, const int* pt_of_base_all, const int* pt_off, const double* x2_of_base_all,
                             const uint8_t* kappa_all,
-                            const double* bxi_x, const double* bxi_y, const double* bw, int nx, int ny,
-                            double C_split, double C_merge, double eps_merge, int flux_test, uint8_t* kappa_out,
+                            const double* bxi_x, const double* bxi_y, const double* bw, const double* axes, int nx,
+                            int ny, double C_split, double C_merge, double eps_merge, int flux_test, uint8_t* kappa_out,
                             unsigned long long* hash_out, const int* cell_list) {
     if (n_cells <= 0) return hipSuccess;
     MLVS_DISPATCH(prec, k_criterion, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
-                  pt_of_base_all, pt_off, x2_of_base_all, kappa_all, bxi_x, bxi_y, bw, nx, ny, C_split, C_merge,
+                  pt_of_base_all, pt_off, x2_of_base_all, kappa_all, bxi_x, bxi_y, bw, axes, nx, ny, C_split, C_merge,
                   eps_merge, flux_test, kappa_out, hash_out, cell_list);
     return hipGetLastError();
 }

@@ -161,7 +161,7 @@ hipError_t launch_criterion(int prec, hipStream_t st, const LevelDesc* lv, const
                             const int* cell_slot, int n_cells, const int* pt_of_base_all,
                             const int* pt_off, const double* x2_of_base_all, const uint8_t* kappa_all,
                             const double* bxi_x,
-                            const double* bxi_y, const double* bw, int nx, int ny,
+                            const double* bxi_y, const double* bw, const double* axes, int nx, int ny,
                             double C_split, double C_merge, double eps_merge, int flux_test,
                             uint8_t* kappa_out, unsigned long long* hash_out, const int* cell_list = nullptr);
 hipError_t launch_gather_rows_u8(hipStream_t st, const uint8_t* src, int width, const int* rows, int n,
