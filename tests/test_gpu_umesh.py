@@ -10,6 +10,9 @@ least-squares slopes with Venkatakrishnan's limiter) against the oracle.
   eight-moment compatibility), and criterion adaptation inside the step
   loop.
 * FP32 storage: fields within 1e-5 relative L2 after a few steps.
+* Degenerate meshes: one triangle with boundary faces only, two triangles, a
+  quadrilateral beside a triangle; the cylinder O-grid taken as an
+  unstructured mesh (seam closed by shared nodes).
 * Full size (two-cavity at lattice spacing 1/48: 9504 cells, 101^2 velocity
   points, FP32, UVS and MLVS): sampled cells against an oracle step of the
   two-neighbour-ring patch around each (a cell's update reads its faces'
@@ -80,6 +83,40 @@ def test_o_grid_with_least_squares_slopes_fp64(mode):
         g.step(1)
         e = state_error(g.get_state(), o.g, o.h)
         assert max(e) < TOL, (k, e)
+    g.close()
+
+
+def _tiny(polys, nodes, bedges, rho):
+    n = len(polys)
+    ptr = np.concatenate([[0], np.cumsum([len(q) for q in polys])]).astype(np.int32)
+    return W.UProblem("tiny", np.asarray(nodes, float), ptr, np.array([v for q in polys for v in q], np.int32),
+                      np.asarray(bedges, np.int32).reshape(-1, 3), [W.BC(W.WALL, T=1.0), W.BC(W.WALL, u=0.1, T=1.2)],
+                      np.asarray(rho, float), np.full(n, 0.05), np.zeros(n), np.ones(n), R=0.5, Pr=2.0 / 3.0, K=0,
+                      omega=0.81, T_ref=1.0, rho_ref=1.0, L_ref=1.0, Kn=0.1, cfl=0.5, vel_kind="nc", nv=12, vmax=5.0)
+
+
+@pytest.mark.parametrize("case", ["one_triangle", "two_triangles", "quad_and_triangle"])
+def test_degenerate_small_meshes_fp64(case):
+    # a cell whose faces are all boundary faces (least squares from the
+    # mirror ghosts alone), a two-cell mesh, and a mixed quad/triangle pair
+    if case == "one_triangle":
+        p = _tiny([(0, 1, 2)], [(0, 0), (1, 0), (0.3, 0.8)], [(0, 1, 0), (1, 2, 1), (2, 0, 0)], [1.0])
+    elif case == "two_triangles":
+        p = _tiny([(0, 1, 2), (0, 2, 3)], [(0, 0), (1, 0), (1, 1), (0, 1)],
+                  [(0, 1, 0), (1, 2, 0), (2, 3, 1), (3, 0, 0)], [1.0, 0.5])
+    else:
+        p = _tiny([(0, 1, 4, 3), (1, 2, 4)], [(0, 0), (1, 0), (1.6, 0.2), (0, 1), (1, 1)],
+                  [(0, 1, 0), (1, 2, 0), (2, 4, 1), (4, 3, 1), (3, 0, 0)], [1.0, 0.7])
+    print("case tiny", case, flush=True)
+    o = Oracle(p, compat=4)
+    g = _gpu(p, compat=4)
+    t0 = g.totals()
+    for k in range(3):
+        o.step()
+        g.step(1)
+        e = state_error(g.get_state(), o.g, o.h)
+        assert max(e) < TOL, (case, k, e)
+    assert abs(g.totals()[0] - t0[0]) < 1e-13 * t0[0]
     g.close()
 
 
