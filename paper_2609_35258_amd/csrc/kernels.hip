@@ -2460,23 +2460,33 @@ __global__ __launch_bounds__(BS, 4) void k_criterion(const LevelDesc* __restrict
                         if (cnt++ == k) { X0 = xx; Y0 = yy; yy = nby; break; }
                     }
             }
-            // explicit coarse-to-fine descent (at most 1 + 4 + 16 candidates)
-            int stk_s[24], stk_x[24], stk_y[24], sp = 0;
-            stk_s[sp] = s0; stk_x[sp] = X0; stk_y[sp] = Y0; ++sp;
-            while (sp > 0) {
-                --sp;
-                const int s = stk_s[sp], X = stk_x[sp], Y = stk_y[sp];
-                const bool mg = crit_merges<S>(cc, L, g, h, s, X, Y);
+            // coarse to fine (at most 1 + 4 + 16 tests): a block that merges sets
+            // its 2x2 blocks, one that does not is split into its four children.
+            // Written as nested loops rather than a stack, so that every test
+            // has a constant block size and nothing lives in scratch memory.
+            auto fill = [&](int s, int X, int Y, uint8_t v) {
                 const int csz = 1 << (s - 1);
-                if (mg || s == 1) {
-                    const uint8_t v = mg ? (uint8_t)s : (uint8_t)0;
-                    for (int cy = Y * csz; cy < Y * csz + csz; ++cy)
-                        for (int cx = X * csz; cx < X * csz + csz; ++cx) ko[cx + nbx * cy] = v;
-                } else {
-                    for (int k = 3; k >= 0; --k) {
-                        stk_s[sp] = s - 1; stk_x[sp] = 2 * X + (k & 1); stk_y[sp] = 2 * Y + (k >> 1); ++sp;
-                    }
+                for (int cy = Y * csz; cy < Y * csz + csz; ++cy)
+                    for (int cx = X * csz; cx < X * csz + csz; ++cx) ko[cx + nbx * cy] = v;
+            };
+            auto test2 = [&](int X, int Y) {
+                ko[X + nbx * Y] = crit_merges<S>(cc, L, g, h, 1, X, Y) ? (uint8_t)1 : (uint8_t)0;
+            };
+            auto test4 = [&](int X, int Y) {
+                if (crit_merges<S>(cc, L, g, h, 2, X, Y)) {
+                    fill(2, X, Y, 2);
+                    return;
                 }
+                for (int k = 0; k < 4; ++k) test2(2 * X + (k & 1), 2 * Y + (k >> 1));
+            };
+            if (s0 == 3) {
+                if (crit_merges<S>(cc, L, g, h, 3, X0, Y0)) fill(3, X0, Y0, 3);
+                else
+                    for (int k = 0; k < 4; ++k) test4(2 * X0 + (k & 1), 2 * Y0 + (k >> 1));
+            } else if (s0 == 2) {
+                test4(X0, Y0);
+            } else {
+                test2(X0, Y0);
             }
         }
         __threadfence_block();
