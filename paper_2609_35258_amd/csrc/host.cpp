@@ -379,6 +379,11 @@ struct HostTable {
     std::vector<double> frac;
 };
 
+// build_level through the context's cache (a level is a function of the base
+// grid and its mask alone).  The returned level is a fresh copy with no
+// device memory.
+std::unique_ptr<Level> level_of_mask(mlvs_ctx c, const std::vector<uint8_t>& kappa);
+
 HostTable make_table(const Level& dst, const Level& src) {
     HostTable t;
     t.off.push_back(0);
@@ -868,6 +873,9 @@ struct mlvs_ctx_s {
     double *d_bx = nullptr, *d_by = nullptr, *d_bw = nullptr, *d_axes = nullptr;
     int *d_ptb_all = nullptr, *d_ptb_off = nullptr;
     double* d_x2b_all = nullptr;       // per level and base point: |xi_p|^2 of its level point p
+    // host geometry of recently built levels by their mask (levels recur from
+    // one adaptation to the next); copies carry no device memory
+    std::map<std::vector<uint8_t>, std::unique_ptr<Level>> level_cache;
     PinnedBuf pin_masks;               // host copy of the unique masks (adaptation)
     uint8_t* d_kappa_all = nullptr;
     uint8_t* d_kcell = nullptr;
@@ -968,7 +976,7 @@ void free_items(mlvs_ctx c) {
 Level* find_iface(mlvs_ctx c, const std::vector<uint8_t>& k, int& idx) {
     for (size_t i = 0; i < c->ifaces.size(); ++i)
         if (c->ifaces[i]->kappa == k) { idx = (int)(c->levels.size() + i); return c->ifaces[i].get(); }
-    auto L = build_level(c->base, k);
+    auto L = level_of_mask(c, k);
     L->is_iface = true;
     L->stride = (L->N + 63) / 64 * 64;
     c->ifaces.push_back(std::move(L));
@@ -979,6 +987,15 @@ Level* find_iface(mlvs_ctx c, const std::vector<uint8_t>& k, int& idx) {
 Level& level_by_index(mlvs_ctx c, int i) {
     if (i < (int)c->levels.size()) return *c->levels[i];
     return *c->ifaces[i - c->levels.size()];
+}
+
+std::unique_ptr<Level> level_of_mask(mlvs_ctx c, const std::vector<uint8_t>& kappa) {
+    auto it = c->level_cache.find(kappa);
+    if (it == c->level_cache.end()) {
+        if (c->level_cache.size() >= 64) c->level_cache.clear();
+        it = c->level_cache.emplace(kappa, build_level(c->base, kappa)).first;
+    }
+    return std::make_unique<Level>(*it->second);
 }
 
 // Build face/ghost/cross-face work lists, flux rows and per-cell codes for the
@@ -1645,7 +1662,7 @@ void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
     int64_t changed = 0;
     if (!same) {
         std::vector<std::unique_ptr<Level>> nl;
-        for (auto& k : reps) nl.push_back(build_level(c->base, k));
+        for (auto& k : reps) nl.push_back(level_of_mask(c, k));
         changed = install_levels(c, std::move(nl), cl);
     }
     c->last_unique = (int64_t)first.size();
