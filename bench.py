@@ -383,7 +383,7 @@ def two_cavity_to_time(t_end=4.0, precision=32, interval=5, map_moments=4, tau_c
             "mlvs_vs_uvs_rel_l2": err}
 
 
-def long_run(kind="cylinder", steps=10000, warmup=100, precision=32):
+def long_run(kind="cylinder", steps=10000, warmup=100, precision=32, map_moments=4):
     """A whole run of the cylinder (10,000 steps, about one flow-through) or the
     jet (2,000 steps) from the freestream or background state, MLVS against
     UVS, each timed over the whole run: `warmup` base-grid steps, then the
@@ -396,8 +396,8 @@ def long_run(kind="cylinder", steps=10000, warmup=100, precision=32):
          else W.jet(512, 256, Kn_jet=1e-3, nv=161, vmax=7.0))
     out = {}
     for mode in ("mlvs", "uvs"):
-        s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=CYL_ADAPT if mode == "mlvs" else None,
-                                  graph=True)
+        s = m.Solver.from_problem(p, precision=precision, compat=4, map_moments=map_moments,
+                                  adapt=CYL_ADAPT if mode == "mlvs" else None, graph=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.step(10)
@@ -426,8 +426,8 @@ def long_run(kind="cylinder", steps=10000, warmup=100, precision=32):
     rl2 = lambda a, b: float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
     err = {"rho": rl2(fm[:, 0], fu[:, 0]), "u": rl2(fm[:, 1:3], fu[:, 1:3]), "T": rl2(fm[:, 3], fu[:, 3]),
            "q": rl2(fm[:, 4:6], fu[:, 4:6])}
-    return {"workload": "%s, %d steps (%d on the base grid first), fp%d, MLVS adaptation every %d steps; whole runs "
-                        "timed" % (kind, steps, warmup, precision, CYL_INTERVAL),
+    return {"workload": "%s, %d steps (%d on the base grid first), fp%d, MLVS adaptation every %d steps, %d-moment "
+                        "mapping; whole runs timed" % (kind, steps, warmup, precision, CYL_INTERVAL, map_moments),
             "mlvs_seconds": out["mlvs"]["seconds"], "uvs_seconds": out["uvs"]["seconds"],
             "speedup": out["uvs"]["seconds"] / out["mlvs"]["seconds"],
             "memory_ratio": out["uvs"]["memory"] / out["mlvs"]["memory"], "levels": out["mlvs"]["levels"],
@@ -627,6 +627,7 @@ def main():
     ap.add_argument("--no-cylinder", action="store_true")
     ap.add_argument("--no-jet", action="store_true")
     ap.add_argument("--tau-sweep", action="store_true", help="only the clustering-threshold sweep on the cylinder")
+    ap.add_argument("--long-map", type=int, default=4, choices=[4, 9], help="mapping order of the --long runs")
     ap.add_argument("--long", choices=("cylinder", "jet"), default=None,
                     help="only a whole run of that case, MLVS against UVS (10,000 cylinder or 2,000 jet steps)")
     ap.add_argument("--no-two-cavity", action="store_true")
@@ -664,7 +665,8 @@ def main():
         print(json.dumps({"tau_sweep": tau_sweep()}), flush=True)
         return
     if args.long:
-        print(json.dumps({"long_run": long_run(args.long, 10000 if args.long == "cylinder" else 2000)}), flush=True)
+        print(json.dumps({"long_run": long_run(args.long, 10000 if args.long == "cylinder" else 2000,
+                                               map_moments=args.long_map)}), flush=True)
         return
     if args.two_cavity_only:
         if args.tc_t_end > 0:
