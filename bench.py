@@ -500,7 +500,7 @@ def cell_areas(p):
 
 
 # launch variant index -> (velocity points per lane per load batch, minimum waves per SIMD)
-VARIANTS = {0: (1, 4), 1: (2, 4), 2: (4, 2), 3: (4, 4)}
+VARIANTS = {0: (1, 4), 1: (2, 4), 2: (4, 2), 3: (4, 4), 4: (1, 2)}
 # kernels instantiated per compatibility order carry it as a template argument,
 # and the face kernels the mesh kind (0 structured, 1 unstructured) after it
 STAGE_CM = ("cell", "face_target", "face", "update_cell")

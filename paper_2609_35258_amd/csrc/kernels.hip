@@ -1909,7 +1909,8 @@ static inline int grid_for(int n, int per = MAXW) {
 
 // Tunable kernels are instantiated for several (points per lane per chunk U,
 // minimum waves per SIMD) pairs; the variant index selects one at launch.
-constexpr int N_VARIANTS = 4;
+// (1, 2) gives the FP64 fused kernels 256 VGPRs, where (1, 4) spills.
+constexpr int N_VARIANTS = 5;
 #define MLVS_LAUNCH_UW(prec, KERNEL, U_, W_, ...)                                                \
     do {                                                                                        \
         if ((prec) == 32) hipLaunchKernelGGL((KERNEL<float, U_, W_>), __VA_ARGS__);              \
@@ -1921,6 +1922,7 @@ constexpr int N_VARIANTS = 4;
         case 0: MLVS_LAUNCH_UW(prec, KERNEL, 1, 4, __VA_ARGS__); break;                          \
         case 2: MLVS_LAUNCH_UW(prec, KERNEL, 4, 2, __VA_ARGS__); break;                          \
         case 3: MLVS_LAUNCH_UW(prec, KERNEL, 4, 4, __VA_ARGS__); break;                          \
+        case 4: MLVS_LAUNCH_UW(prec, KERNEL, 1, 2, __VA_ARGS__); break;                          \
         default: MLVS_LAUNCH_UW(prec, KERNEL, 2, 4, __VA_ARGS__); break;                         \
         }                                                                                       \
     } while (0)
@@ -1936,6 +1938,7 @@ constexpr int N_VARIANTS = 4;
         case 0: MLVS_LAUNCH_UWC(prec, KERNEL, 1, 4, C_, __VA_ARGS__); break;                     \
         case 2: MLVS_LAUNCH_UWC(prec, KERNEL, 4, 2, C_, __VA_ARGS__); break;                     \
         case 3: MLVS_LAUNCH_UWC(prec, KERNEL, 4, 4, C_, __VA_ARGS__); break;                     \
+        case 4: MLVS_LAUNCH_UWC(prec, KERNEL, 1, 2, C_, __VA_ARGS__); break;                     \
         default: MLVS_LAUNCH_UWC(prec, KERNEL, 2, 4, C_, __VA_ARGS__); break;                    \
         }                                                                                       \
     } while (0)
@@ -1962,6 +1965,7 @@ constexpr int N_VARIANTS = 4;
             case 0: MLVS_LAUNCH_UWM(prec, KERNEL, 1, 4, 0, __VA_ARGS__); break;                  \
             case 2: MLVS_LAUNCH_UWM(prec, KERNEL, 4, 2, 0, __VA_ARGS__); break;                  \
             case 3: MLVS_LAUNCH_UWM(prec, KERNEL, 4, 4, 0, __VA_ARGS__); break;                  \
+            case 4: MLVS_LAUNCH_UWM(prec, KERNEL, 1, 2, 0, __VA_ARGS__); break;                  \
             default: MLVS_LAUNCH_UWM(prec, KERNEL, 2, 4, 0, __VA_ARGS__); break;                 \
             }                                                                                   \
         }                                                                                       \
@@ -1980,6 +1984,7 @@ constexpr int N_VARIANTS = 4;
             case 0: MLVS_LAUNCH_UWCM(prec, KERNEL, 1, 4, C_, 0, __VA_ARGS__); break;             \
             case 2: MLVS_LAUNCH_UWCM(prec, KERNEL, 4, 2, C_, 0, __VA_ARGS__); break;             \
             case 3: MLVS_LAUNCH_UWCM(prec, KERNEL, 4, 4, C_, 0, __VA_ARGS__); break;             \
+            case 4: MLVS_LAUNCH_UWCM(prec, KERNEL, 1, 2, C_, 0, __VA_ARGS__); break;             \
             default: MLVS_LAUNCH_UWCM(prec, KERNEL, 2, 4, C_, 0, __VA_ARGS__); break;            \
             }                                                                                   \
         }                                                                                       \

@@ -36,7 +36,11 @@ def test_variants_give_identical_results_and_autotune_runs(tmp_path):
     import paper_2609_35258_amd.autotune as at
     p = W.cylinder(16, 8, Kn=0.1, nv=21, vmax=10.0)
     ref = None
-    for v in range(4):
+    s = _gpu(p, precision=32)
+    nvar = s.variants("face_rec")
+    s.close()
+    assert nvar == 5
+    for v in range(nvar):
         s = _gpu(p, precision=32)
         for st in at.TUNABLE:
             if s.variants(st) > 1:
