@@ -61,6 +61,32 @@ def test_variants_give_identical_results_and_autotune_runs(tmp_path):
     s.close()
 
 
+@pytest.mark.parametrize("precision,compat", [(64, 4), (64, 8), (32, 4)])
+def test_fused_kernels_identical_across_variants(precision, compat, monkeypatch):
+    """Every launch variant of the fused face and update kernels gives the same
+    state bit for bit, across adaptations and cross-level faces."""
+    p = W.perturb(W.periodic_box(12, 6, Lx=1.0, Ly=0.5, Kn=0.05, nv=24, vmax=5.0, kind="sine", amp=0.5), seed=4)
+    ap = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=1e-3, tau_clust=0.02, flux_test=True, interval=3)
+    monkeypatch.setenv("MLVS_FUSE", "1")
+    ref = None
+    s = _gpu(p, precision=precision, compat=compat, adapt=ap, graph=True)
+    nvar = s.variants("face")
+    s.close()
+    for v in range(nvar):
+        s = _gpu(p, precision=precision, compat=compat, adapt=ap, graph=True)
+        assert s.step_stages() == ["ghost", "face", "xface", "update_cell"]
+        s.set_variant("face", v)
+        s.set_variant("update_cell", v)
+        s.step(7)
+        assert s.counters()["adaptations"] >= 2
+        st_ = s.get_state()
+        if ref is None:
+            ref = st_
+        else:
+            assert all(np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1]) for x, y in zip(st_, ref)), v
+        s.close()
+
+
 @pytest.mark.parametrize("precision,compat,chunk", [(64, 4, None), (32, 4, None), (64, 8, None), (64, 4, "64")])
 def test_fused_step_matches_staged_step(precision, compat, chunk, monkeypatch):
     """The fused step (reconstruction + target in one launch, the update
