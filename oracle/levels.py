@@ -255,6 +255,64 @@ def refine_to_base(lev: Level, g, h):
     return gb, hb
 
 
+def indicators(base: BaseGrid, gb, hb):
+    """Per-point contributions M1 = w g / rho_tot and M2 = w (h + |xi|^2 g) / (2 E_tot)
+    of a distribution on V_base (Eq. M2), signed as written."""
+    w, xi = base.w, base.xi
+    x2 = np.sum(xi * xi, axis=1)
+    rho_tot = np.sum(w * gb)
+    E_tot = np.sum(0.5 * w * (hb + x2 * gb))
+    return w * gb / rho_tot, 0.5 * w * (hb + x2 * gb) / E_tot
+
+
+def block_indicator(base: BaseGrid, M1, M2, s, bx, by):
+    """I_B = max(sum_B M1, sum_B M2) over the 2^s block (Eq. block-contribution-indicator)."""
+    pts = base.block_points(s, bx, by)
+    return max(float(np.sum(M1[pts])), float(np.sum(M2[pts])))
+
+
+def transport_moments(base: BaseGrid, gb, hb):
+    """The four transported densities m_r = (g, xi_x g, xi_y g, (h + |xi|^2 g)/2) per point."""
+    xi = base.xi
+    x2 = np.sum(xi * xi, axis=1)
+    return np.stack([gb, xi[:, 0] * gb, xi[:, 1] * gb, 0.5 * (hb + x2 * gb)])
+
+
+def flux_scale(base: BaseGrid, gb, hb):
+    """S_r = max_d sum_i w_i |xi_{i,d}| |m_r(xi_i)| over the whole space (reading of
+    the normalisation in Eq. merge-transport-error)."""
+    w, xi = base.w, base.xi
+    m = transport_moments(base, gb, hb)
+    return np.max(np.stack([np.sum(w * np.abs(xi[:, d]) * np.abs(m), axis=1) for d in (0, 1)]), axis=0)
+
+
+def block_flux_error(base: BaseGrid, gb, hb, S, s, bx, by):
+    """eps_B of Eq. merge-transport-error for the 2^s block: the largest normalised
+    difference, over the four densities, both axes and both half-ranges, between
+    the half-range fluxes sum_{i in B, sgn xi_d >= 0} w xi_d m_r of the fine points
+    and that of the block's merged point (w_B = sum w, xi_B the weighted mean,
+    g_B and H_B = (h + |xi|^2 g)_B weighted means, as in the coarsening of
+    Sec. 3.3.2)."""
+    w, xi = base.w, base.xi
+    x2 = np.sum(xi * xi, axis=1)
+    m = transport_moments(base, gb, hb)
+    pts = base.block_points(s, bx, by)
+    wp = w[pts]
+    WB = wp.sum()
+    xB = (wp[:, None] * xi[pts]).sum(0) / WB
+    gB = np.sum(wp * gb[pts]) / WB
+    HB = np.sum(wp * (hb[pts] + x2[pts] * gb[pts])) / WB
+    mB = np.array([gB, xB[0] * gB, xB[1] * gB, 0.5 * HB])
+    err = 0.0
+    for d in (0, 1):
+        for sgn in (1.0, -1.0):
+            sel = sgn * xi[pts, d] >= 0
+            Ff = np.sum((wp * xi[pts, d])[None, :] * m[:, pts] * sel[None, :], axis=1)
+            Fm = WB * xB[d] * mB if sgn * xB[d] >= 0 else np.zeros(4)
+            err = max(err, float(np.max(np.abs(Ff - Fm) / S)))
+    return err
+
+
 def criterion(lev: Level, g, h, C_split, C_merge, eps_merge, flux_test):
     """Per-cell coarsening index kappa on V_base's 2x2 blocks.
 
@@ -268,40 +326,17 @@ def criterion(lev: Level, g, h, C_split, C_merge, eps_merge, flux_test):
     base = lev.base
     prev = lev.kappa
     gb, hb = refine_to_base(lev, g, h)
-    w, xi = base.w, base.xi
-    x2 = np.sum(xi * xi, axis=1)
-    rho_tot = np.sum(w * gb)
-    E_tot = np.sum(0.5 * w * (hb + x2 * gb))
-    M1 = w * gb / rho_tot
-    M2 = 0.5 * w * (hb + x2 * gb) / E_tot
-    m = np.stack([gb, xi[:, 0] * gb, xi[:, 1] * gb, 0.5 * (hb + x2 * gb)])     # (4, N)
-    S = np.max(np.stack([np.sum(w * np.abs(xi[:, d]) * np.abs(m), axis=1) for d in (0, 1)]), axis=0)
+    M1, M2 = indicators(base, gb, hb)
+    S = flux_scale(base, gb, hb)
     kappa = np.zeros(base.Nb, np.uint8)
 
     def merges(s, bx, by):
-        pts = base.block_points(s, bx, by)
-        I = max(np.sum(M1[pts]), np.sum(M2[pts]))
+        I = block_indicator(base, M1, M2, s, bx, by)
         prev_merged = bool(np.all(prev[base.block_children2(s, bx, by)] >= s))
         cand = I < C_merge or (C_merge <= I <= C_split and prev_merged)
         if cand and flux_test:
-            cand = flux_error(pts) <= eps_merge
+            cand = block_flux_error(base, gb, hb, S, s, bx, by) <= eps_merge
         return cand
-
-    def flux_error(pts):
-        wp = w[pts]
-        WB = wp.sum()
-        xB = (wp[:, None] * xi[pts]).sum(0) / WB
-        gB = np.sum(wp * gb[pts]) / WB
-        HB = np.sum(wp * (hb[pts] + x2[pts] * gb[pts])) / WB
-        mB = np.array([gB, xB[0] * gB, xB[1] * gB, 0.5 * HB])
-        err = 0.0
-        for d in (0, 1):
-            for sgn in (1.0, -1.0):
-                sel = sgn * xi[pts, d] >= 0
-                Ff = np.sum((wp * xi[pts, d])[None, :] * m[:, pts] * sel[None, :], axis=1)
-                Fm = WB * xB[d] * mB if sgn * xB[d] >= 0 else np.zeros(4)
-                err = max(err, float(np.max(np.abs(Ff - Fm) / S)))
-        return err
 
     def set_k(s, bx, by, val):
         kappa[base.block_children2(s, bx, by)] = val

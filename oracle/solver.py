@@ -192,8 +192,10 @@ class Solver:
             gs, hs = self.positivity_fallback(dst, gp, hp, gs, hs, target)
         return gs, hs
 
-    # values within POS_EPS max|g^p| of zero count as zero in the positivity
-    # check, so that round-off alone never decides between the two corrections
+    # positivity band (reading R22): values above -POS_EPS max|g^p| count as
+    # nonnegative in the positivity check.  A tolerance of the check (a value
+    # that small is no physical negative), not a rounding bound; it is pinned
+    # on both sides in the tests.
     POS_EPS = 1e-10
 
     def positivity_fallback(self, dst, gp, hp, gs, hs, target):
