@@ -206,8 +206,25 @@ mlvs_status mlvs_set_levels(mlvs_ctx ctx, int n_levels, const uint8_t* kappa, co
  * faces run on a second stream of the context (default priority), forked
  * from the context stream after the neighbour mapping and joined back before
  * the update of the same step, so every step stays ordered on the caller's
- * stream. */
+ * stream.  In strict mode (mlvs_set_strict) the call synchronises and can
+ * return MLVS_E_NUMERIC; the state is then left as computed. */
 mlvs_status mlvs_step(mlvs_ctx ctx, int n_steps);
+
+/* Strict mode (Sec. 3.3: the positivity check after every correction, here
+ * made an error instead of a count).  flags is a bit set:
+ *  1  before the first step of each mlvs_step call and after every step, the
+ *     state of every cell is formed from the moments of its g~, h~ (Eqs.
+ *     W_from_tilde, discrete_W); a moment that is not finite, or rho <= 0 or
+ *     T <= 0, makes mlvs_step return MLVS_E_NUMERIC at that step, with the
+ *     number of such cells and the first one's index, rho and T in
+ *     mlvs_last_error().  Each step then synchronises the context stream.
+ *  2  a mapping correction that makes a nonnegative provisional g negative
+ *     (mlvs_neg_count), or an exponential correction whose Newton iteration
+ *     does not converge, during an mlvs_step call makes that call return
+ *     MLVS_E_NUMERIC after its last step.
+ * 0 (the default) turns both off: such events are only counted.  Other
+ * values are MLVS_E_ARG. */
+mlvs_status mlvs_set_strict(mlvs_ctx ctx, int flags);
 
 /* Criterion + grouping + remap now (Secs. 3.2, 3.4).  report may be NULL. */
 mlvs_status mlvs_adapt(mlvs_ctx ctx, mlvs_adapt_report* report);
@@ -364,13 +381,44 @@ mlvs_status mlvs_mlp_predict(const float* params, int K, const float* X, int B, 
                              int32_t* classes, float* probs);
 
 /* Install a trained selector for the current catalogue (K == number of
- * levels).  Afterwards adaptations (mlvs_adapt, and those mlvs_step runs at
- * its interval) keep this catalogue frozen: each cell's level is predicted
- * from its features (BF16 inference); a prediction is rejected when a block
- * the predicted level merges has I_B > C_split on the cell's distribution
- * (tail-mass check); rejected cells take the criterion's label.  params NULL
- * removes the selector. */
+ * levels) and enable learned adaptation.  Afterwards adaptations (mlvs_adapt,
+ * and those mlvs_step runs at its interval) keep this catalogue frozen: each
+ * cell's level is predicted from its features (BF16 inference); a prediction
+ * is rejected when a block the predicted level merges has I_B > C_split on
+ * the cell's distribution (tail-mass check); rejected cells take the
+ * criterion's label.  params NULL removes the selector (and disables learned
+ * adaptation). */
 mlvs_status mlvs_selector_set(mlvs_ctx ctx, const float* params, int K);
+
+/* Record one training snapshot from the context's own state: the features of
+ * every cell and its criterion-judged label against the current catalogue
+ * (as mlvs_features and mlvs_labels), appended to a host-side store owned by
+ * the context.  reset = 1 empties the store first.  The store belongs to one
+ * catalogue: a snapshot taken after the catalogue changed is MLVS_E_STATE
+ * unless reset = 1.  *n_samples (may be NULL) receives the stored sample
+ * count.  Synchronises. */
+mlvs_status mlvs_selector_snapshot(mlvs_ctx ctx, int reset, int64_t* n_samples);
+
+/* Train the selector on the recorded snapshots (samples whose label is -1
+ * are skipped; the last val_frac of the rest, in recording order, is held
+ * out) with the device training kernels, starting from He-normal weights
+ * drawn from cfg->seed (splitmix64 stream, Box-Muller), and install the
+ * result for the current catalogue, which must be the one the snapshots
+ * refer to (MLVS_E_STATE otherwise, or when no snapshot was recorded).
+ * Learned adaptation stays as mlvs_selector_enable left it (off after
+ * create).  rep may be NULL.  Uses hipMalloc and the null stream;
+ * synchronous. */
+mlvs_status mlvs_selector_train(mlvs_ctx ctx, const mlvs_train_cfg* cfg, mlvs_train_report* rep);
+
+/* on = 1: adaptations use the installed network (as described for
+ * mlvs_selector_set); MLVS_E_STATE when none is installed or its class count
+ * differs from the catalogue's level count.  on = 0: adaptations run the
+ * criterion and rebuild the catalogue (the network stays installed). */
+mlvs_status mlvs_selector_enable(mlvs_ctx ctx, int on);
+
+/* The installed network: *K its class count (0: none); out (may be NULL)
+ * receives mlvs_mlp_nparams(*K) floats in the layout above.  Synchronises. */
+mlvs_status mlvs_selector_params(mlvs_ctx ctx, float* out, int* K);
 
 void        mlvs_destroy(mlvs_ctx ctx);
 const char* mlvs_last_error(void);

@@ -143,6 +143,12 @@ _PROTOS = {
     "mlvs_mlp_predict": (ctypes.c_int, [_c_float_p, ctypes.c_int, _c_float_p, ctypes.c_int, ctypes.c_int,
                                         _c_int32_p, _c_float_p]),
     "mlvs_selector_set": (ctypes.c_int, [ctypes.c_void_p, _c_float_p, ctypes.c_int]),
+    "mlvs_selector_snapshot": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
+    "mlvs_selector_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(mlvs_train_cfg),
+                                           ctypes.POINTER(mlvs_train_report)]),
+    "mlvs_selector_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "mlvs_selector_params": (ctypes.c_int, [ctypes.c_void_p, _c_float_p, ctypes.POINTER(ctypes.c_int)]),
+    "mlvs_set_strict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "mlvs_destroy": (None, [ctypes.c_void_p]),
     "mlvs_last_error": (ctypes.c_char_p, []),
 }
@@ -472,6 +478,36 @@ class Solver:
             return
         self._sel = np.ascontiguousarray(params, np.float32)
         _check(lib().mlvs_selector_set(self.h, _fp(self._sel), int(K)))
+
+    def selector_snapshot(self, reset: bool = False) -> int:
+        """Record features and criterion labels of every cell; returns the stored sample count."""
+        n = ctypes.c_int64()
+        _check(lib().mlvs_selector_snapshot(self.h, int(reset), ctypes.byref(n)))
+        return n.value
+
+    def selector_train(self, epochs=10, batch=4096, lr=1e-3, val_frac=0.2, seed=0):
+        """Train the context's selector on its recorded snapshots; returns the report dict."""
+        cfg = mlvs_train_cfg(int(epochs), int(batch), float(lr), 0.9, 0.999, 1e-8, float(val_frac), int(seed))
+        rep = mlvs_train_report()
+        _check(lib().mlvs_selector_train(self.h, ctypes.byref(cfg), ctypes.byref(rep)))
+        return {k: getattr(rep, k) for k, _ in mlvs_train_report._fields_}
+
+    def selector_enable(self, on: bool = True):
+        _check(lib().mlvs_selector_enable(self.h, int(on)))
+
+    def selector_params(self):
+        """(params as float32, K) of the installed network, or (None, 0)."""
+        K = ctypes.c_int()
+        _check(lib().mlvs_selector_params(self.h, None, ctypes.byref(K)))
+        if K.value == 0:
+            return None, 0
+        out = np.zeros(mlp_nparams(K.value), np.float32)
+        _check(lib().mlvs_selector_params(self.h, _fp(out), ctypes.byref(K)))
+        return out, K.value
+
+    def set_strict(self, flags: int):
+        """Strict mode bits: 1 state checks after every step, 2 positivity violations are errors."""
+        _check(lib().mlvs_set_strict(self.h, int(flags)))
 
     def memory(self):
         v = ctypes.c_size_t()

@@ -5,13 +5,17 @@ For each tunable stage the library holds several instantiations of the kernel
 i.e. memory-level parallelism against a register budget per lane).  The tuner
 times every variant on the solver's current
 state with HIP events (``Solver.time_stage``), keeps the fastest, and caches
-the choice in a JSON file keyed by GPU architecture, storage precision and the
-stage's work shape (items, mean velocity points per item), so later runs of
-the same shape skip the sweep.  Variants only change scheduling, never the
+the choice in a JSON file keyed by GPU architecture, storage precision, the
+stage's work shape (items, mean velocity points per item), the number of
+variants the stage has and a hash of the built library, so later runs of the
+same shape with the same kernels skip the sweep, and a rebuilt library or a
+new variant sweeps again.  Variants only change scheduling, never the
 results.
 """
 from __future__ import annotations
 
+import functools
+import hashlib
 import json
 import os
 from typing import Dict, Iterable, Optional
@@ -30,6 +34,16 @@ def _arch() -> str:
     return getattr(props, "gcnArchName", props.name).split(":")[0]
 
 
+@functools.lru_cache(maxsize=1)
+def _lib_tag() -> str:
+    from . import LIB_PATH
+    h = hashlib.sha256()
+    with open(LIB_PATH, "rb") as f:
+        for block in iter(lambda: f.read(1 << 20), b""):
+            h.update(block)
+    return h.hexdigest()[:12]
+
+
 def shape_key(solver, stage: str, precision: int) -> Optional[str]:
     items, pts = solver.stage_size(stage)
     if items == 0:
@@ -37,7 +51,8 @@ def shape_key(solver, stage: str, precision: int) -> Optional[str]:
     per = int(round(pts / items))
     # bucket the size so nearby shapes share an entry
     bucket = 1 << max(per - 1, 1).bit_length()
-    return "%s|fp%d|%s|items~%d|pts<=%d" % (_arch(), precision, stage, 1 << max(items - 1, 1).bit_length(), bucket)
+    return "%s|fp%d|%s|items~%d|pts<=%d|variants%d|lib%s" % (
+        _arch(), precision, stage, 1 << max(items - 1, 1).bit_length(), bucket, solver.variants(stage), _lib_tag())
 
 
 def autotune(solver, precision: int, stages: Optional[Iterable[str]] = None, reps: int = 5,

@@ -901,6 +901,16 @@ struct mlvs_ctx_s {
     // update
     hipStream_t side_st = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // strict mode (mlvs_set_strict): bit 1 checks the state after every step,
+    // bit 2 turns new positivity violations into errors
+    int strict = 0;
+    unsigned long long* d_check = nullptr;   // [0] cells that failed, [1] smallest such cell
+    // selector training data recorded by mlvs_selector_snapshot (host):
+    // features [n][10], criterion labels [n], and the catalogue they refer to
+    std::vector<float> snap_X;
+    std::vector<int32_t> snap_Y;
+    std::vector<uint8_t> snap_cat;
+    bool sel_on = false;               // learned adaptation enabled
     // counters
     double cnt_updates = 0.0, cnt_iface = 0.0;
     int64_t cnt_adapt = 0;
@@ -1402,6 +1412,34 @@ void run_criterion(mlvs_ctx c) {
               "criterion launch");
 }
 
+// Strict mode: check every cell's state from the raw moments the last update
+// (or the moment pass after an outside write) left; `step` numbers the step
+// of the current call (-1: the state before the first step).
+void strict_check(mlvs_ctx c, int step) {
+    const unsigned long long init[2] = {0ull, ~0ull};
+    hip_check(hipMemcpyAsync(c->d_check, init, sizeof init, hipMemcpyHostToDevice, c->st), "H2D");
+    hip_check(launch_check_state(c->st, c->d_lv, c->d_cell_lev, c->mesh.n_cells, c->ph, c->d_cmom, c->chunk,
+                                 c->d_check), "check launch");
+    unsigned long long rec[2] = {0, 0};
+    hip_check(hipMemcpyAsync(rec, c->d_check, sizeof rec, hipMemcpyDeviceToHost, c->st), "D2H");
+    sync(c);
+    if (rec[0] == 0) return;
+    const int n = c->mesh.n_cells;
+    const int cell = (int)rec[1];
+    std::vector<double> f(6 * (size_t)n);
+    double* d = static_cast<double*>(c->dm.alloc(sizeof(double) * 6 * (size_t)n));
+    hip_check(launch_cell_moments(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_geom, c->ph, d,
+                                  nullptr), "moments launch");
+    hip_check(hipMemcpyAsync(f.data(), d, sizeof(double) * 6 * (size_t)n, hipMemcpyDeviceToHost, c->st), "D2H");
+    sync(c);
+    c->dm.release(d);
+    if (step < 0)
+        fail(MLVS_E_NUMERIC, "strict mode: %llu cells hold a non-finite or non-positive state before the first step "
+             "(first: cell %d, rho = %g, T = %g)", rec[0], cell, f[6 * (size_t)cell], f[6 * (size_t)cell + 3]);
+    fail(MLVS_E_NUMERIC, "strict mode: %llu cells hold a non-finite or non-positive state after step %d of this call "
+         "(first: cell %d, rho = %g, T = %g)", rec[0], step, cell, f[6 * (size_t)cell], f[6 * (size_t)cell + 3]);
+}
+
 // Deduplicate the per-cell masks: returns unique masks (row-major), their first
 // cell and count, and the unique index of every cell.
 void dedupe(mlvs_ctx c, const uint8_t*& uniq, std::vector<int>& first, std::vector<int64_t>& count,
@@ -1694,6 +1732,13 @@ void compute_features(mlvs_ctx c, float* d_out) {
     c->dm.release(d8);
 }
 
+// The catalogue as bytes: the number of levels, then every level's mask.
+std::vector<uint8_t> catalogue_key(mlvs_ctx c) {
+    std::vector<uint8_t> k(1, (uint8_t)c->levels.size());
+    for (auto& L : c->levels) k.insert(k.end(), L->kappa.begin(), L->kappa.end());
+    return k;
+}
+
 std::vector<int> level_order(mlvs_ctx c) {
     std::vector<int> order(c->levels.size());
     for (size_t l = 0; l < order.size(); ++l) order[l] = (int)l;
@@ -1876,9 +1921,15 @@ mlvs_status mlvs_mlp_predict(const float* params, int K, const float* X, int B, 
     });
 }
 
-mlvs_status mlvs_mlp_train(float* params, int K, const float* X, const int32_t* y, int64_t n,
-                           const mlvs_train_cfg* cfg, mlvs_train_report* rep) {
-    return guarded([&] {
+}  // extern "C"
+
+namespace {
+
+// Training loop on the device (FP32 forward/backward/Adam kernels, hipMalloc
+// and the null stream): params in/out on the host, samples X [n][10], y [n].
+void train_network(float* params, int K, const float* X, const int32_t* y, int64_t n, const mlvs_train_cfg* cfg,
+                   mlvs_train_report* rep) {
+    {
         check_mlp_args(K);
         if (!params || !X || !y || !cfg || n < 2 || n > (int64_t)1 << 30) fail(MLVS_E_ARG, "bad arguments");
         if (cfg->epochs < 1 || cfg->batch < 1 || !(cfg->val_frac >= 0.0 && cfg->val_frac < 1.0))
@@ -1978,7 +2029,46 @@ mlvs_status mlvs_mlp_train(float* params, int K, const float* X, const int32_t* 
             rep->steps = total_steps;
             rep->ms = ms;
         }
-    });
+    }
+}
+
+// He-normal initial weights (fan-in scaling, zero biases, identity
+// standardisation) from a splitmix64 stream and the Box-Muller transform.
+std::vector<float> he_init(int K, uint64_t seed) {
+    const int np = mlp_nparams(K);
+    std::vector<float> P(np, 0.f);
+    uint64_t st = seed ^ 0x6a09e667f3bcc909ull;
+    auto next = [&]() {
+        uint64_t z = (st += 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        return z ^ (z >> 31);
+    };
+    auto normal = [&]() {
+        const double u1 = ((next() >> 11) + 0.5) * 0x1.0p-53, u2 = (next() >> 11) * 0x1.0p-53;
+        return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+    };
+    const int H = 64, NF = 10;
+    size_t o = 0;
+    auto fill = [&](int rows, int fan_in) {
+        const double sd = std::sqrt(2.0 / fan_in);
+        for (int k = 0; k < rows * fan_in; ++k) P[o++] = (float)(sd * normal());
+        o += rows;   // biases stay zero
+    };
+    fill(H, NF);
+    fill(H, H);
+    fill(K, H);
+    for (int k = 0; k < NF; ++k) P[o + NF + k] = 1.f;   // mean 0, std 1 (set again by training)
+    return P;
+}
+
+}  // namespace
+
+extern "C" {
+
+mlvs_status mlvs_mlp_train(float* params, int K, const float* X, const int32_t* y, int64_t n,
+                           const mlvs_train_cfg* cfg, mlvs_train_report* rep) {
+    return guarded([&] { train_network(params, K, X, y, n, cfg, rep); });
 }
 
 mlvs_status mlvs_selector_set(mlvs_ctx c, const float* params, int K) {
@@ -1988,6 +2078,7 @@ mlvs_status mlvs_selector_set(mlvs_ctx c, const float* params, int K) {
             c->dm.release(c->d_sel);
             c->d_sel = nullptr;
             c->sel_K = 0;
+            c->sel_on = false;
             return;
         }
         check_mlp_args(K);
@@ -2000,6 +2091,97 @@ mlvs_status mlvs_selector_set(mlvs_ctx c, const float* params, int K) {
         hip_check(hipMemcpyAsync(c->d_sel, params, 4 * (size_t)np, hipMemcpyHostToDevice, c->st), "H2D");
         sync(c);
         c->sel_K = K;
+        c->sel_on = true;
+    });
+}
+
+mlvs_status mlvs_selector_snapshot(mlvs_ctx c, int reset, int64_t* n_samples) {
+    return guarded([&] {
+        if (!c) fail(MLVS_E_ARG, "null context");
+        if (!c->adaptive) fail(MLVS_E_STATE, "context was created without adaptation parameters");
+        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
+        if (c->phys.dim != 2) fail(MLVS_E_STATE, "features need dim = 2");
+        const std::vector<uint8_t> cat = catalogue_key(c);
+        if (reset) {
+            c->snap_X.clear();
+            c->snap_Y.clear();
+            c->snap_cat.clear();
+        }
+        if (!c->snap_Y.empty() && cat != c->snap_cat)
+            fail(MLVS_E_STATE, "the catalogue changed since the first recorded snapshot (reset the store)");
+        const int n = c->mesh.n_cells;
+        float* d_feat = static_cast<float*>(c->dm.alloc(sizeof(float) * 10 * (size_t)n));
+        int* d_lab = static_cast<int*>(c->dm.alloc(sizeof(int) * (size_t)n));
+        compute_features(c, d_feat);
+        run_criterion(c);
+        std::vector<int> order = level_order(c);
+        int* d_order = upload(c->dm, order, c->st);
+        hip_check(launch_labels(c->st, c->d_kcell, n, c->base.Nb, c->d_kappa_all, d_order, (int)order.size(), d_lab),
+                  "labels launch");
+        const size_t o = c->snap_Y.size();
+        c->snap_X.resize(10 * (o + n));
+        c->snap_Y.resize(o + n);
+        hip_check(hipMemcpyAsync(c->snap_X.data() + 10 * o, d_feat, sizeof(float) * 10 * (size_t)n,
+                                 hipMemcpyDeviceToHost, c->st), "D2H");
+        hip_check(hipMemcpyAsync(c->snap_Y.data() + o, d_lab, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost, c->st),
+                  "D2H");
+        sync(c);
+        c->dm.release(d_feat);
+        c->dm.release(d_lab);
+        c->dm.release(d_order);
+        c->snap_cat = cat;
+        if (n_samples) *n_samples = (int64_t)c->snap_Y.size();
+    });
+}
+
+mlvs_status mlvs_selector_train(mlvs_ctx c, const mlvs_train_cfg* cfg, mlvs_train_report* rep) {
+    return guarded([&] {
+        if (!c || !cfg) fail(MLVS_E_ARG, "null argument");
+        if (!c->adaptive) fail(MLVS_E_STATE, "context was created without adaptation parameters");
+        if (c->snap_Y.empty()) fail(MLVS_E_STATE, "no snapshots recorded");
+        if (catalogue_key(c) != c->snap_cat)
+            fail(MLVS_E_STATE, "the catalogue changed since the snapshots were recorded");
+        const int K = (int)c->levels.size();
+        check_mlp_args(K);
+        std::vector<float> X;
+        std::vector<int32_t> y;
+        X.reserve(c->snap_X.size());
+        y.reserve(c->snap_Y.size());
+        for (size_t i = 0; i < c->snap_Y.size(); ++i)
+            if (c->snap_Y[i] >= 0) {
+                y.push_back(c->snap_Y[i]);
+                X.insert(X.end(), c->snap_X.begin() + 10 * i, c->snap_X.begin() + 10 * (i + 1));
+            }
+        std::vector<float> P = he_init(K, cfg->seed);
+        train_network(P.data(), K, X.data(), y.data(), (int64_t)y.size(), cfg, rep);
+        const int np = mlp_nparams(K);
+        c->dm.release(c->d_sel);
+        c->d_sel = static_cast<float*>(c->dm.alloc(4 * (size_t)np));
+        hip_check(hipMemcpyAsync(c->d_sel, P.data(), 4 * (size_t)np, hipMemcpyHostToDevice, c->st), "H2D");
+        sync(c);
+        c->sel_K = K;
+    });
+}
+
+mlvs_status mlvs_selector_enable(mlvs_ctx c, int on) {
+    return guarded([&] {
+        if (!c || (on != 0 && on != 1)) fail(MLVS_E_ARG, "bad arguments");
+        if (on && !c->d_sel) fail(MLVS_E_STATE, "no network installed (mlvs_selector_train or mlvs_selector_set)");
+        if (on && c->sel_K != (int)c->levels.size())
+            fail(MLVS_E_STATE, "the network has %d classes but the catalogue %d levels", c->sel_K,
+                 (int)c->levels.size());
+        c->sel_on = on != 0;
+    });
+}
+
+mlvs_status mlvs_selector_params(mlvs_ctx c, float* out, int* K) {
+    return guarded([&] {
+        if (!c || !K) fail(MLVS_E_ARG, "null argument");
+        *K = c->sel_K;
+        if (!out || !c->d_sel) return;
+        hip_check(hipMemcpyAsync(out, c->d_sel, 4 * (size_t)mlp_nparams(c->sel_K), hipMemcpyDeviceToHost, c->st),
+                  "D2H");
+        sync(c);
     });
 }
 
@@ -2203,7 +2385,37 @@ mlvs_status mlvs_step(mlvs_ctx c, int n_steps) {
     return guarded([&] {
         if (!c || n_steps < 0) fail(MLVS_E_ARG, "bad arguments");
         if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
-        for (int k = 0; k < n_steps; ++k) do_step(c);
+        unsigned long long neg0[3] = {0, 0, 0};
+        if (c->strict & 2) {
+            hip_check(hipMemcpyAsync(neg0, c->d_neg, sizeof neg0, hipMemcpyDeviceToHost, c->st), "D2H");
+            sync(c);
+        }
+        if (c->strict & 1) {
+            ensure_moments(c);
+            strict_check(c, -1);
+        }
+        for (int k = 0; k < n_steps; ++k) {
+            do_step(c);
+            if (c->strict & 1) strict_check(c, k);
+        }
+        if (c->strict & 2) {
+            unsigned long long neg1[3] = {0, 0, 0};
+            hip_check(hipMemcpyAsync(neg1, c->d_neg, sizeof neg1, hipMemcpyDeviceToHost, c->st), "D2H");
+            sync(c);
+            if (neg1[0] != neg0[0] || neg1[2] != neg0[2])
+                fail(MLVS_E_NUMERIC,
+                     "strict mode: %llu mapping corrections made a nonnegative g negative, %llu exponential "
+                     "corrections did not converge during this call",
+                     neg1[0] - neg0[0], neg1[2] - neg0[2]);
+        }
+    });
+}
+
+mlvs_status mlvs_set_strict(mlvs_ctx c, int flags) {
+    return guarded([&] {
+        if (!c || flags < 0 || flags > 3) fail(MLVS_E_ARG, "bad arguments");
+        if ((flags & 1) && !c->d_check) c->d_check = static_cast<unsigned long long*>(c->dm.alloc(16));
+        c->strict = flags;
     });
 }
 
@@ -2578,7 +2790,7 @@ mlvs_status mlvs_adapt(mlvs_ctx c, mlvs_adapt_report* rep) {
         if (!c) fail(MLVS_E_ARG, "null context");
         if (!c->adaptive) fail(MLVS_E_STATE, "context was created without adaptation parameters");
         if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
-        if (c->sel_K > 0) adapt_learned(c, rep);
+        if (c->sel_K > 0 && c->sel_on) adapt_learned(c, rep);
         else adapt_now(c, rep);
     });
 }

@@ -735,7 +735,13 @@ struct MapCoef { double a[6], b[3]; bool nine; };
 // the sum of the terms' magnitudes; then the rows are rewritten and true is
 // returned; otherwise (after EXP_MAXIT steps) the rows are left as they were.
 constexpr int EXP_MAXIT = 30;
+// Band of the positivity check, relative to max |g^p| of the row: values
+// above -band count as nonnegative.  A tolerance of the check, not a rounding
+// bound: 1e-10 with double rows (two implementations of the step agree far
+// closer than that after many steps); with float rows 1e-6, about sixteen
+// units of float rounding, so that storage rounding alone never decides.
 constexpr double POS_EPS = 1e-10;
+constexpr double POS_EPS32 = 1e-6;
 template <typename S>
 __device__ bool map_exp(const LevelDesc& D, gptr<S> gdst, gptr<S> hdst, const double* tgt) {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
@@ -841,9 +847,8 @@ __device__ __forceinline__ void map_correct_apply(const LevelDesc& D, gptr<S> gd
     if (ph.positivity) {
         // positivity check of the linear result before it is written: a
         // nonnegative provisional g turned negative takes the exponential
-        // correction (the rows still hold the provisional pair)
-        // (values within POS_EPS max|g^p| of zero count as zero, so that
-        // round-off alone never decides between the two corrections)
+        // correction (the rows still hold the provisional pair); values
+        // within the band of zero count as zero
         double v[3] = {0.0, -1e300, -1e300};      // max |g^p|, -min g^p, -min g_lin
         for (int i = lane_id(); i < D.N; i += WL) {
             double dg, dh;
@@ -854,7 +859,7 @@ __device__ __forceinline__ void map_correct_apply(const LevelDesc& D, gptr<S> gd
             v[2] = fmax(v[2], -(double)(S)((double)gprov + dg));
         }
         wave_max<3>(v);
-        const double eps = POS_EPS * v[0];
+        const double eps = (sizeof(S) == 4 ? POS_EPS32 : POS_EPS) * v[0];
         if (v[1] <= eps && v[2] > eps) {
             negflag = 1;
             const bool ok = map_exp<S>(D, gdst, hdst, tgt);
@@ -1832,6 +1837,29 @@ __global__ __launch_bounds__(BS) void k_cell_moments(const LevelDesc* __restrict
 
 // Fixed-order sum of n rows of `width` doubles (one workgroup).
 // Fixed-order sum of n rows of `width` (<= 4) doubles by one wavefront.
+// Strict mode: the state of every cell from the raw moments of its stored
+// g~, h~ (the chunk partials the update leaves, summed in chunk order), and a
+// flag when a moment is not finite or rho or T is not positive.  rec[0] counts
+// such cells, rec[1] holds the smallest such cell index (atomic min).
+__global__ __launch_bounds__(BS) void k_check_state(const LevelDesc* __restrict__ lvs,
+                                                    const int* __restrict__ cell_lev, int n_cells, Phys ph,
+                                                    const double* __restrict__ cmom, int CH,
+                                                    unsigned long long* __restrict__ rec) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n_cells; c += gridDim.x * blockDim.x) {
+        double cm[NMOM];
+        sum_chunks(cmom, c, n_cells, lvs[cell_lev[c]].N, CH, cm);
+        bool bad = false;
+        for (int k = 0; k < 11; ++k) bad = bad || !isfinite(cm[k]);
+        double rho, u, v, T, qx, qy;
+        raw_to_state(cm, cm[M_U0], cm[M_V0], ph, rho, u, v, T, qx, qy);
+        bad = bad || !(rho > 0.0) || !(T > 0.0) || !isfinite(rho) || !isfinite(T) || !isfinite(u) || !isfinite(v);
+        if (bad) {
+            atomicAdd(rec, 1ull);
+            atomicMin(rec + 1, (unsigned long long)c);
+        }
+    }
+}
+
 __global__ void k_sum_rows(const double* __restrict__ in, int n, int width, double* __restrict__ out) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int r = lane_id(); r < n; r += WL)
@@ -2090,6 +2118,14 @@ hipError_t launch_cell_moments(int prec, hipStream_t st, const LevelDesc* lv, co
     if (n_cells <= 0) return hipSuccess;
     MLVS_DISPATCH(prec, k_cell_moments, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
                   geom, ph, out6, tot4, out8, out3);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_state(hipStream_t st, const LevelDesc* lv, const int* cell_lev, int n_cells, Phys ph,
+                              const double* cmom, int CH, unsigned long long* rec) {
+    if (n_cells <= 0) return hipSuccess;
+    const int blocks = (n_cells + BS - 1) / BS;
+    k_check_state<<<blocks < 65535 ? blocks : 65535, BS, 0, st>>>(lv, cell_lev, n_cells, ph, cmom, CH, rec);
     return hipGetLastError();
 }
 

@@ -155,6 +155,10 @@ hipError_t launch_cell_moments(int prec, hipStream_t st, const LevelDesc* lv, co
                                const int* cell_slot, int n_cells, const CellGeom* geom, Phys ph,
                                double* out6, double* out_tot4, double* out8 = nullptr, double* out3 = nullptr);
 hipError_t launch_sum_rows(hipStream_t st, const double* in, int n, int width, double* out);
+// Strict-mode state check (rec[0] count of bad cells, rec[1] smallest bad cell;
+// the caller clears rec to {0, ~0}).
+hipError_t launch_check_state(hipStream_t st, const LevelDesc* lv, const int* cell_lev, int n_cells, Phys ph,
+                              const double* cmom, int CH, unsigned long long* rec);
 hipError_t launch_remap(int prec, hipStream_t st, const LevelDesc* old_lv, const LevelDesc* new_lv,
                         const RemapItem* items, int n, Phys ph, unsigned long long* neg);
 hipError_t launch_criterion(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,

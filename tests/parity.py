@@ -1,5 +1,7 @@
-"""Helpers shared by the GPU parity tests (no method arithmetic here)."""
+"""Helpers shared by the GPU parity tests (method arithmetic only through the oracle)."""
 import numpy as np
+
+from oracle import levels as lv
 
 
 def state_error(gpu_state, oracle_g, oracle_h):
@@ -19,3 +21,31 @@ def state_error(gpu_state, oracle_g, oracle_h):
 def rel_l2(a, b, vol):
     """Volume-weighted relative L2 difference."""
     return float(np.sqrt(np.sum(vol * (a - b) ** 2) / np.sum(vol * b ** 2)))
+
+
+def near_threshold(o, C_split, C_merge, eps_merge=None, rel=1e-9):
+    """Per cell and 2x2 block of V_base: True where the criterion's decision
+    rests on a tie, i.e. a block containing it has an indicator I_B within rel
+    of C_split or C_merge, or (eps_merge given) a transport error eps_B within
+    rel of eps_merge (oracle side, Sec. 3.2)."""
+    out = []
+    base = o.base
+    for c in range(o.mesh.n_cells):
+        L = o.levels[o.cell_level[c]]
+        gb, hb = lv.refine_to_base(L, o.g[c], o.h[c])
+        M1, M2 = lv.indicators(base, gb, hb)
+        S = lv.flux_scale(base, gb, hb) if eps_merge else None
+        amb = np.zeros(base.Nb, bool)
+        for s in (1, 2, 3):
+            n = 1 << (s - 1)
+            for by in range(base.nby // n):
+                for bx in range(base.nbx // n):
+                    I = lv.block_indicator(base, M1, M2, s, bx, by)
+                    tie = any(abs(I - C) <= rel * C for C in (C_split, C_merge))
+                    if eps_merge and not tie:
+                        e = lv.block_flux_error(base, gb, hb, S, s, bx, by)
+                        tie = abs(e - eps_merge) <= rel * eps_merge
+                    if tie:
+                        amb[base.block_children2(s, bx, by)] = True
+        out.append(amb)
+    return np.array(out)

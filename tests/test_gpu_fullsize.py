@@ -83,6 +83,16 @@ def _sampled_parity(p, mode, samples, warm):
         kap = np.stack([g.level_kappa(k) for k in range(len(npts))])
         levels = g.cell_levels()
         assert len(npts) >= 2 and ncross > 0
+        # plus the first cell (away from the mesh edges) with a cross-level
+        # face towards +i and the first with one towards +j
+        Lg = levels.reshape(p.nj, ni)
+        inner = np.zeros_like(Lg, bool)
+        inner[2:-3, 2:-3] = True
+        for d in (1, 0):
+            cross = inner & (Lg != np.roll(Lg, -1, axis=d))
+            jj, ii = np.nonzero(cross)
+            assert len(ii) > 0, "no cross-level face along axis %d" % d
+            samples = list(samples) + [(int(ii[0]), int(jj[0]))]
     patches = {}
     for (i, j) in samples:
         i0, j0 = i - 2, max(j - 2, 0)

@@ -11,7 +11,7 @@ import workloads as W
 from oracle import levels as lv
 from oracle.solver import AdaptParams
 from oracle.solver import Solver as Oracle
-from tests.parity import state_error
+from tests.parity import near_threshold, state_error
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -85,28 +85,7 @@ def test_criterion_catalog_cylinder_walls_and_far_field():
 
 
 def _near_threshold(o, C_split, C_merge, rel=1e-9):
-    """Blocks whose indicator lies within rel of a threshold, per cell (oracle side)."""
-    out = []
-    base = o.base
-    for c in range(o.mesh.n_cells):
-        L = o.levels[o.cell_level[c]]
-        gb, hb = lv.refine_to_base(L, o.g[c], o.h[c])
-        w, xi = base.w, base.xi
-        x2 = np.sum(xi * xi, 1)
-        M1 = w * gb / np.sum(w * gb)
-        M2 = 0.5 * w * (hb + x2 * gb) / np.sum(0.5 * w * (hb + x2 * gb))
-        amb = np.zeros(base.Nb, bool)
-        for s in (1, 2, 3):
-            n = 1 << (s - 1)
-            for by in range(base.nby // n):
-                for bx in range(base.nbx // n):
-                    pts = base.block_points(s, bx, by)
-                    I = max(M1[pts].sum(), M2[pts].sum())
-                    for C in (C_split, C_merge):
-                        if abs(I - C) <= rel * C:
-                            amb[base.block_children2(s, bx, by)] = True
-        out.append(amb)
-    return np.array(out)
+    return near_threshold(o, C_split, C_merge, rel=rel)
 
 
 @pytest.mark.parametrize("flux_test", [False, True])

@@ -12,6 +12,7 @@ from oracle import levels as lv
 from oracle import mlp
 from oracle.solver import AdaptParams
 from oracle.solver import Solver as Oracle
+from tests.parity import near_threshold
 
 pytestmark = pytest.mark.gpu
 
@@ -105,7 +106,83 @@ def test_labels_match_oracle():
     ko = o.criterion_masks()
     lab_o = mlp.label_from_masks(ko, np.stack(kap), [L.N for L in o.levels])
     lab_g = g.labels()
-    assert np.mean(lab_g == lab_o) > 0.98, (lab_g, lab_o)
+    # labels are integers: equal on every cell whose mask rests on no tie of an
+    # indicator or transport error with a threshold
+    amb = near_threshold(o, 5e-3, 2.5e-3, 1e-3).any(axis=1)
+    diff = (lab_g != lab_o) & ~amb
+    assert not diff.any(), (np.nonzero(diff)[0], lab_g[diff], lab_o[diff])
+    assert amb.mean() < 0.05, amb.mean()
+    g.close()
+
+
+def test_adam_steps_match_oracle():
+    # two full-batch training steps on the device (forward, backward, Adam)
+    # against the oracle's gradient and Adam update from the same start
+    K = 3
+    th, X, y = _net(K, B=512, seed=5)
+    X = X.astype(np.float32)
+    lr = 1e-2
+    P, rep = _m().mlp_train(th.astype(np.float32), K, X, y, epochs=2, batch=len(y), lr=lr, val_frac=0.0, seed=7)
+    assert rep["steps"] == 2
+    t = th.astype(np.float32).astype(np.float64)
+    X64 = X.astype(np.float64)
+    # the device sets the standardisation block from the training samples first
+    mu = X64.mean(axis=0)
+    sd = np.sqrt(((X64 - mu) ** 2).mean(axis=0))
+    t[-20:-10] = mu.astype(np.float32)
+    t[-10:] = sd.astype(np.float32)
+    m1 = np.zeros_like(t)
+    v1 = np.zeros_like(t)
+    gmin = np.full_like(t, np.inf)
+    for step in (1, 2):
+        _, gr, _ = mlp.loss_and_grad(t, X64, y, K)
+        gmin = np.minimum(gmin, np.abs(gr) / np.max(np.abs(gr)))
+        t, m1, v1 = mlp.adam_step(t, gr, m1, v1, step, lr=lr)
+    n_tr = len(t) - 20
+    err = np.abs(P[:n_tr] - t[:n_tr])
+    # each Adam step moves a weight by about lr sign(g); where the gradient is
+    # not tiny (Adam's eps and FP32 rounding decide there) the two sides agree
+    # to a small fraction of that (FP32 against FP64 gradients)
+    clear = gmin[:n_tr] > 1e-5
+    assert clear.mean() > 0.9
+    assert np.max(err[clear]) < 2e-3 * lr, np.max(err[clear])
+    assert np.max(err) <= 2.0 * lr * (1 + 1e-6)
+    assert np.allclose(P[n_tr:], t[n_tr:], rtol=1e-6, atol=0)
+
+
+def test_selector_trained_from_context_snapshots():
+    """The context-bound selector calls: record snapshots of the context's own
+    state, train on them, switch learned adaptation on and off."""
+    m = _m()
+    p = W.perturb(W.periodic_box(24, 8, Lx=1.0, Ly=1.0 / 3, Kn=0.05, nv=32, vmax=5.0, kind="sine", amp=0.5), seed=8)
+    ap = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=1e-3, tau_clust=0.05, flux_test=True, interval=0)
+    g = m.Solver.from_problem(p, compat=4, adapt=ap)
+    g.step(2)
+    g.adapt()
+    K = len(g.level_info()[0])
+    assert K >= 2
+    with pytest.raises(m.MLVSError):
+        g.selector_train(epochs=1)                 # nothing recorded yet
+    with pytest.raises(m.MLVSError):
+        g.selector_enable(True)                    # no network
+    n = 0
+    for snap in range(12):
+        g.step(5)
+        n = g.selector_snapshot(reset=(snap == 0))
+    assert n == 12 * g.n_cells
+    rep = g.selector_train(epochs=40, batch=256, lr=3e-3, val_frac=0.2, seed=1)
+    print("training", rep, flush=True)
+    assert rep["loss_last"] < rep["loss_first"] and rep["val_acc"] > 0.6
+    P, Kp = g.selector_params()
+    assert Kp == K and len(P) == m.mlp_nparams(K) and np.all(np.isfinite(P))
+    t0 = g.totals()
+    g.selector_enable(True)
+    r1 = g.adapt()
+    assert r1["n_unique"] == -1 and r1["n_fallback"] < g.n_cells
+    g.step(3)
+    assert np.max(np.abs(g.totals() - t0)) < 1e-12
+    g.selector_enable(False)
+    assert g.adapt()["n_unique"] >= 1
     g.close()
 
 

@@ -118,3 +118,14 @@ def test_create_unstructured_rejects_bad_meshes(polys, bedges, msg):
     assert st != 0
     assert msg in err, err
     assert not h.value
+
+
+def test_context_calls_reject_a_null_context():
+    # argument checks of the context-bound calls run before any device work
+    L = m.lib()
+    cfg = m.mlvs_train_cfg(1, 16, 1e-3, 0.9, 0.999, 1e-8, 0.2, 0)
+    assert L.mlvs_set_strict(None, 1) == -1
+    assert L.mlvs_selector_enable(None, 1) == -1
+    assert L.mlvs_selector_snapshot(None, 0, None) == -1
+    assert L.mlvs_selector_train(None, ctypes.byref(cfg), None) == -1
+    assert L.mlvs_selector_params(None, None, None) == -1
