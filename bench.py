@@ -1,13 +1,16 @@
 """Benchmark: MLVS-DUGKS cell-velocity updates/s on one MI355X, MLVS vs UVS.
 
-Workload (synthetic, deterministic): 2-D lid-driven cavity, 64 x 64 uniform
-cells on [0,1]^2, lid Mach 0.16, Kn 0.075, Shakhov Pr 2/3, 28 x 28
-Gauss-Hermite base velocity grid, FP64.  MLVS: criterion C_split 5e-3,
-C_merge 2.5e-3, transport-error test eps 5e-5, tau_clust 0.05, adaptation
-every 100 steps (levels built from the distributions); UVS: the same run on
-the fixed base grid.  A step is one pass of the whole hot path (adaptation at
-its interval, cell stage, neighbour mapping, same-level / boundary /
-cross-level faces, update).  Prints one JSON line.
+Headline workload (synthetic, deterministic): the under-expanded slot jet
+into near vacuum, 512 x 256 uniform cells on [0,32] x [-8,8], sonic slot
+|y| <= 0.5 at x = 0, background density 0.01 (pressure ratio 100), Kn_jet
+1e-3, Shakhov Pr 2/3, 161 x 161 Newton-Cotes base grid on [-7,7]^2 (25921
+points), FP32 storage.  MLVS: criterion C_split 0.01, C_merge 0.005,
+transport-error test 2e-5, tau_clust 0.05, adaptation every 5 steps.  The
+solver first takes 100 untimed steps on the base grid from the initial state
+(levels built from a uniform background would not resolve the jet), then
+--warmup untimed and --steps timed MLVS steps, adaptation (criterion,
+grouping, remap) inside the timed window.  UVS: the same steps on the fixed
+base grid.  A step is one pass of the whole hot path.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -30,10 +33,6 @@ HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 ADAPT = dict(C_split=5e-3, C_merge=2.5e-3, eps_merge=5e-5, tau_clust=0.05, flux_test=True, interval=100)
-
-
-def workload(args):
-    return W.cavity(args.n, Kn=0.075, nv=args.nv)
 
 
 def run_gpu(p, steps, warmup, precision, adapt, graph=True, tune=True):
@@ -65,46 +64,6 @@ def stage_profile(s, reps=20):
     return out
 
 
-# algorithmic bytes per velocity point of each stage (FP64 values, 8 B; FP32, 4 B):
-#   cell:        read g~,h~ + write phi_bar+ g,h                         -> 4 values
-#   face_rec:    read phi_bar+ g,h of the upwind cell + write phi_bar_f  -> 4 values
-#   face_target: per-face records only (ALU: the target's moment pass)    -> 0 values
-#   update:      read g~,h~ and phi_bar+ g,h, the cell's face rows (each shared
-#                by two cells: 4 faces x 2 / 2) + write g~,h~             -> 10 values
-#   xface:       per V_int point, read both sides' phi_bar+ (2x2) + write one native row (2) -> 6 values
-#   ghost:       read source phi_bar+ + write mapped row                 -> 4 values
-#   face (fused face_rec + face_target)                                  -> 4 values
-#   update_cell (fused update + next cell stage): the update's 10 + write the
-#                new phi_bar+ g,h (the new state is the update's own output) -> 12 values
-ALG_VALUES = {"cell": 4, "face_rec": 4, "face_target": 0, "update": 10, "xface": 6, "ghost": 4, "face": 4,
-              "update_cell": 12}
-
-
-def cpu_baseline(p, sample_steps=2, sample_cells=256):
-    """The oracle as it stands on the same workload: full-size steps from the
-    initial state plus the criterion on a sample of cells (scaled to the whole
-    mesh), the adaptation amortised over its interval."""
-    from oracle import levels as lv
-    from oracle.solver import Solver as Oracle
-    o = Oracle(p, compat=4)
-    t0 = time.perf_counter()
-    for c in range(min(sample_cells, o.mesh.n_cells)):
-        lv.criterion(o.levels[0], o.g[c], o.h[c], ADAPT["C_split"], ADAPT["C_merge"], ADAPT["eps_merge"],
-                     ADAPT["flux_test"])
-    t_crit = (time.perf_counter() - t0) * o.mesh.n_cells / min(sample_cells, o.mesh.n_cells)
-    t0 = time.perf_counter()
-    for _ in range(sample_steps):
-        o.step()
-    t_step = (time.perf_counter() - t0) / sample_steps
-    pts = float(o.mesh.n_cells * o.levels[0].N)
-    rate = pts / (t_step + t_crit / ADAPT["interval"])
-    return {"value": rate, "unit": "cell-velocity updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%dx%d cavity, %d-point base grid: %d oracle steps (%.2f s/step) + criterion on %d cells "
-                      "(scaled to %d cells: %.1f s), adaptation amortised over %d steps"
-                      % (p.ni, p.nj, o.levels[0].N, sample_steps, t_step, sample_cells, o.mesh.n_cells,
-                         t_crit, ADAPT["interval"])}
-
-
 LEARNED_ADAPT = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, flux_test=True, interval=0)
 
 
@@ -114,9 +73,9 @@ def learned_vs_criterion(precision=32, n_theta=256, n_r=128, nv=101, warm=100, s
     Supersonic cylinder (Ma 3, Kn 0.1, Shakhov), n_theta x n_r cells and an
     nv^2 Newton-Cotes base grid (by default the full-size case: 32 snapshots of
     32768 cells, about 1e6 samples).  A criterion run builds the catalogue (one
-    full adaptation after `warm` base-grid steps) and collects (features,
-    criterion label) snapshots every `every` steps; the network is trained on
-    the GPU on the earlier 80% of the snapshots.  A second solver starts from the same
+    full adaptation after `warm` base-grid steps) and records (features,
+    criterion label) snapshots every `every` steps in the context; the context
+    trains its network on the GPU on the earlier 80% of the snapshots.  A second solver starts from the same
     state and levels with the selector on.  Both then run `rounds` rounds of
     `every` steps plus one adaptation: full criterion adaptation (the paper's
     method, catalogue rebuilt) vs learned adaptation (frozen catalogue, tail-mass
@@ -128,16 +87,11 @@ def learned_vs_criterion(precision=32, n_theta=256, n_r=128, nv=101, warm=100, s
     crit.step(warm)
     crit.adapt()
     K = len(crit.level_info()[0])
-    X, Y = [], []
-    for _ in range(snaps):
+    for k in range(snaps):
         crit.step(every)
-        X.append(crit.features())
-        Y.append(crit.labels())
-    X = np.concatenate(X)
-    Y = np.concatenate(Y)
-    ok = Y >= 0
-    params, trep = m.mlp_train(W.mlp_init_params(K, 0), K, X[ok], Y[ok], epochs=30, batch=1024, lr=3e-3,
-                               val_frac=0.2, seed=0)
+        n_samples = crit.selector_snapshot(reset=(k == 0))
+    trep = crit.selector_train(epochs=30, batch=1024, lr=3e-3, val_frac=0.2, seed=0)
+    params, _ = crit.selector_params()
     lrn = m.Solver.from_problem(p, precision=precision, compat=4, adapt=LEARNED_ADAPT)
     lrn.set_levels(np.stack([crit.level_kappa(k) for k in range(K)]), crit.cell_levels())
     st = crit.get_state()
@@ -146,8 +100,8 @@ def learned_vs_criterion(precision=32, n_theta=256, n_r=128, nv=101, warm=100, s
     n = p.n_cells
     out = {"workload": "cylinder %dx%d, Ma 3, Kn 0.1, %dx%d Newton-Cotes on [-10,10]^2, fp%d, C_split 0.01, "
                        "C_merge 0.005, eps_merge 2e-5, tau_clust 0.05" % (n_theta, n_r, nv, nv, precision),
-           "K": K, "samples": int(ok.sum()), "train": {k: trep[k] for k in ("loss_first", "loss_last", "train_acc",
-                                                                           "val_acc", "ms")}}
+           "K": K, "samples": int(trep["n_train"] + trep["n_val"]), "snapshot_rows": int(n_samples),
+           "train": {k: trep[k] for k in ("loss_first", "loss_last", "train_acc", "val_acc", "ms")}}
     mis, fb, t_c, t_l, run_c, run_l = [], [], [], [], 0.0, 0.0
     for _ in range(rounds):
         feats, lab = lrn.features(), lrn.labels()
@@ -190,72 +144,6 @@ CYL_ADAPT = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, fl
 CYL_INTERVAL = 100
 
 
-def jet_case(steps=100, warmup=100, precision=32, mode="both"):
-    """Under-expanded slot jet into near vacuum at full size (512 x 256 cells,
-    161^2 = 25921-point Newton-Cotes base grid on [-7,7]^2, about 110 GB of
-    device state in the UVS form, FP32 storage), MLVS against UVS.  Both take
-    `warmup` untimed base-grid steps from the initial state; the MLVS run then
-    adapts (criterion levels) at the start of the timed steps, adaptation
-    included in the timing.  Graph-captured steps, autotuned variants."""
-    import torch
-    import paper_2609_35258_amd as m
-    from paper_2609_35258_amd import autotune
-    p = W.jet(512, 256, Kn_jet=1e-3, nv=161, vmax=7.0)
-    if mode == "uvs":
-        u, t_u, upd_u, _ = run_gpu(p, steps, warmup + 2, precision, None)
-        prof_u = stage_profile(u, reps=3)
-        var_u = {k: v["variant"] for k, v in getattr(u, "tuned", {}).items()}
-        u.close()
-        return {"uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps,
-                        "roofline": roofline(prof_u, precision, var_u,
-                                             "jet512x256-nc161-fp32-uvs" if precision == 32 else None)}}
-    s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=CYL_ADAPT, graph=True)
-    s.step(warmup)
-    s.adapt()
-    s.step(2)
-    autotune.autotune(s, precision)
-    torch.cuda.synchronize()
-    c0 = s.counters()
-    t0 = time.perf_counter()
-    s.adapt()
-    s.step(steps)
-    torch.cuda.synchronize()
-    t_m = time.perf_counter() - t0
-    upd = s.counters()["cell_updates"] - c0["cell_updates"]
-    npts, ncells, ncross = s.level_info()
-    f_m = s.moments()
-    mem_m = s.memory()
-    prof = stage_profile(s, reps=3)
-    s.close()
-    del s
-    torch.cuda.empty_cache()
-    if mode == "mlvs":
-        return {"value": upd / t_m, "ms_per_step": 1e3 * t_m / steps, "nbar": float(np.sum(npts * ncells) / np.sum(ncells)),
-                "roofline": roofline(prof, precision)}
-    u, t_u, upd_u, _ = run_gpu(p, steps, warmup + 2, precision, None)
-    f_u = u.moments()
-    mem_u = u.memory()
-    prof_u = stage_profile(u, reps=3)
-    var_u = {k: v["variant"] for k, v in getattr(u, "tuned", {}).items()}
-    u.close()
-    del u
-    torch.cuda.empty_cache()
-    err = {name: float(np.sqrt(np.sum((f_m[:, k] - f_u[:, k]) ** 2) / np.sum(f_u[:, k] ** 2)))
-           for k, name in ((0, "rho"), (1, "u"), (3, "T"))}
-    return {"workload": "slot jet 512x256 on [0,32]x[-8,8], sonic slot |y| <= 0.5, background rho 0.01, Kn_jet "
-                        "1e-3, Shakhov Pr 2/3, 161x161 Newton-Cotes on [-7,7]^2, fp%d; %d base-grid steps, then %d "
-                        "timed steps; MLVS C_split 0.01 C_merge 0.005 eps 2e-5 tau 0.05" % (precision, warmup, steps),
-            "value": upd / t_m, "ms_per_step": 1e3 * t_m / steps, "levels": len(npts),
-            "level_points": [int(x) for x in npts], "level_cells": [int(x) for x in ncells],
-            "nbar": float(np.sum(npts * ncells) / np.sum(ncells)), "n_cross": int(ncross),
-            "roofline": roofline(prof, precision),
-            "uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps,
-                    "roofline": roofline(prof_u, precision, var_u,
-                                         "jet512x256-nc161-fp32-uvs" if precision == 32 else None),
-                    "device_bytes": int(mem_u), "time_to_solution_ratio": t_u / t_m, "memory_ratio": mem_u / mem_m,
-                    "mlvs_vs_uvs_rel_l2": err}}
-
-
 TC_ADAPT = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, flux_test=True, interval=5)
 
 
@@ -270,17 +158,13 @@ def two_cavity_case(steps=200, warmup=100, precision=32, mode="both", interval=5
     import paper_2609_35258_amd as m
     from paper_2609_35258_amd import autotune
     p = W.two_cavity(48, nv=101, vmax=7.0)
-    wl = "twocavity48-nc101-fp32-uvs" if precision == 32 else None
-    # the update reads each cell's face rows: 3.03 faces per cell on this mesh
-    nf = float(np.sum(np.diff(p.cell_ptr))) / p.n_cells
-    alg = {"update": 6 + nf, "update_cell": 8 + nf}
     if mode == "uvs":
         u, t_u, upd_u, _ = run_gpu(p, steps, warmup, precision, None)
         prof_u = stage_profile(u, reps=5)
         var_u = {k: v["variant"] for k, v in getattr(u, "tuned", {}).items()}
         u.close()
         return {"uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps,
-                        "roofline": roofline(prof_u, precision, var_u, wl, alg, 1)}}
+                        "roofline": method_roofline(prof_u, precision, upd_u / steps, 1e3 * t_u / steps)}}
     ap = dict(TC_ADAPT, interval=interval)
     s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=ap, graph=True)
     s.step(warmup)
@@ -301,7 +185,7 @@ def two_cavity_case(steps=200, warmup=100, precision=32, mode="both", interval=5
     torch.cuda.empty_cache()
     if mode == "mlvs":
         return {"value": upd / t_m, "ms_per_step": 1e3 * t_m / steps, "nbar": float(np.sum(npts * ncells) / np.sum(ncells)),
-                "roofline": roofline(prof, precision, None, None, alg, 1)}
+                "roofline": method_roofline(prof, precision, upd / steps, 1e3 * t_m / steps)}
     u, t_u, upd_u, _ = run_gpu(p, steps, warmup, precision, None)
     f_u = u.moments()
     mem_u = u.memory()
@@ -324,9 +208,9 @@ def two_cavity_case(steps=200, warmup=100, precision=32, mode="both", interval=5
             "value": upd / t_m, "ms_per_step": 1e3 * t_m / steps, "levels": len(npts),
             "level_points": [int(x) for x in npts], "level_cells": [int(x) for x in ncells],
             "nbar": float(np.sum(npts * ncells) / np.sum(ncells)), "n_cross": int(ncross),
-            "roofline": roofline(prof, precision, None, None, alg, 1),
+            "roofline": method_roofline(prof, precision, upd / steps, 1e3 * t_m / steps),
             "uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps,
-                    "roofline": roofline(prof_u, precision, var_u, wl, alg, 1),
+                    "roofline": method_roofline(prof_u, precision, upd_u / steps, 1e3 * t_u / steps),
                     "device_bytes": int(mem_u), "time_to_solution_ratio": t_u / t_m, "memory_ratio": mem_u / mem_m,
                     "mlvs_vs_uvs_rel_l2": err}}
 
@@ -531,25 +415,7 @@ def measured_traffic(workload, stage, precision, variant, mk=0):
     return None
 
 
-def roofline(prof, precision, variants=None, workload=None, alg=None, mk=0):
-    """Roofline entry for the dominant stage: algorithmic bytes / mean launch time.
-    alg: per-stage overrides of ALG_VALUES; mk: mesh kind (1 unstructured)."""
-    av = dict(ALG_VALUES, **(alg or {}))
-    evsz = 8 if precision == 64 else 4
-    # cross-level faces run on a second stream beside the face stages, off the
-    # step's critical path: they are not the dominant kernel even when their
-    # lone launch is long
-    dom = max((k for k in prof if av[k] > 0 and (k != "xface" or len(prof) == 1)), key=lambda k: prof[k]["ms"])
-    d = prof[dom]
-    achieved = d["points"] * av[dom] * evsz / (d["ms"] * 1e-3) / 1e9
-    t = measured_traffic(workload, dom, precision, (variants or {}).get(dom), mk) if workload else None
-    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": t,
-            "algorithmic_bytes": d["points"] * av[dom] * evsz,
-            "stage_ms": {k: round(v["ms"], 5) for k, v in prof.items()}}
-
-
-def cylinder_case(steps=200, warmup=100, precision=32, mode="both"):
+def cylinder_case(steps=200, warmup=100, precision=32, mode="both", Kn=0.1):
     """Supersonic cylinder at full size (256 x 128 O-grid, Ma 3, Kn 0.1, 101^2
     Newton-Cotes base grid, FP32 storage), MLVS against UVS.  Both start from
     the freestream and take `warmup` untimed steps on the base grid (an
@@ -559,15 +425,16 @@ def cylinder_case(steps=200, warmup=100, precision=32, mode="both"):
     import torch
     import paper_2609_35258_amd as m
     from paper_2609_35258_amd import autotune
-    p = W.cylinder(256, 128, Kn=0.1, nv=101, vmax=10.0)
-    uvs_wl = "cylinder256x128-nc101-fp32-uvs" if precision == 32 else None
+    p = W.cylinder(256, 128, Kn=Kn, nv=101, vmax=10.0)
+    uvs_wl = "cylinder256x128-nc101-fp32-uvs" if precision == 32 and Kn == 0.1 else None
     if mode == "uvs":
         u, t_u, upd_u, _ = run_gpu(p, steps, warmup + 2, precision, None)
         prof_u = stage_profile(u, reps=5)
         var_u = {k: v["variant"] for k, v in getattr(u, "tuned", {}).items()}
         u.close()
         return {"uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps,
-                        "roofline": roofline(prof_u, precision, var_u, uvs_wl)}}
+                        "roofline": method_roofline(prof_u, precision, upd_u / steps, 1e3 * t_u / steps, uvs_wl,
+                                                    var_u)}}
     s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=CYL_ADAPT, graph=True)
     s.step(warmup)
     s.adapt()
@@ -589,7 +456,7 @@ def cylinder_case(steps=200, warmup=100, precision=32, mode="both"):
     s.close()
     if mode == "mlvs":
         return {"value": upd / t_m, "ms_per_step": 1e3 * t_m / steps, "nbar": float(np.sum(npts * ncells) / np.sum(ncells)),
-                "roofline": roofline(prof, precision)}
+                "roofline": method_roofline(prof, precision, upd / steps, 1e3 * t_m / steps)}
     u, t_u, upd_u, _ = run_gpu(p, steps, warmup + 2, precision, None)
     f_u = u.moments()
     mem_u = u.memory()
@@ -598,39 +465,405 @@ def cylinder_case(steps=200, warmup=100, precision=32, mode="both"):
     u.close()
     err = {name: float(np.sqrt(np.sum((f_m[:, k] - f_u[:, k]) ** 2) / np.sum(f_u[:, k] ** 2)))
            for k, name in ((0, "rho"), (1, "u"), (3, "T"))}
-    return {"workload": "cylinder O-grid 256x128, Ma 3, Kn 0.1, Shakhov Pr 2/3, 101x101 Newton-Cotes on "
+    return {"workload": "cylinder O-grid 256x128, Ma 3, Kn %g, Shakhov Pr 2/3, 101x101 Newton-Cotes on "
                         "[-10,10]^2, fp%d; %d base-grid steps from a freestream start, then %d timed steps; MLVS "
                         "C_split 0.01 C_merge 0.005 eps 2e-5 tau 0.05, adaptation every %d steps"
-                        % (precision, warmup, steps, CYL_INTERVAL),
+                        % (Kn, precision, warmup, steps, CYL_INTERVAL),
             "value": upd / t_m, "ms_per_step": 1e3 * t_m / steps, "levels": len(npts),
             "level_points": [int(x) for x in npts], "level_cells": [int(x) for x in ncells],
             "nbar": float(np.sum(npts * ncells) / np.sum(ncells)), "n_cross": int(ncross),
-            "roofline": roofline(prof, precision),
+            "roofline": method_roofline(prof, precision, upd / steps, 1e3 * t_m / steps),
             "uvs": {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps,
-                    "roofline": roofline(prof_u, precision, var_u, uvs_wl),
+                    "roofline": method_roofline(prof_u, precision, upd_u / steps, 1e3 * t_u / steps, uvs_wl, var_u),
                     "time_to_solution_ratio": t_u / t_m, "memory_ratio": mem_u / mem_m,
                     "mlvs_vs_uvs_rel_l2": err}}
+
+
+JET_ADAPT = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, flux_test=True, interval=5)
+JET_BASE_STEPS = 100
+JET_WL = "jet512x256-nc161-fp32"
+# the method's own bytes per cell-velocity update: read and write g~, h~ once
+# (4 values), and the design floor with the second read the two velocity
+# reductions force (6 values)
+METHOD_VALUES, FLOOR_VALUES = 4, 6
+
+
+def method_roofline(prof, precision, updates_per_step, step_ms, workload=None, variants=None, interval=0):
+    """Roofline of the step: the method's algorithmic bytes per step (16 B per
+    FP32, 32 B per FP64 cell-velocity update times the updates of one step)
+    over the mean launch time of the step's longest kernel, and over the whole
+    step; the criterion counts with its share per step when adaptation runs
+    every `interval` steps.  traffic: the copy-calibrated FETCH_SIZE and
+    WRITE_SIZE bytes per launch of that kernel from profiles/traffic.txt
+    (null when the kernels changed since they were taken)."""
+    evsz = 8 if precision == 64 else 4
+    per_step = {}
+    for k, v in prof.items():
+        share = (1.0 / interval) if k == "criterion" else 1.0
+        if k == "criterion" and not interval:
+            continue
+        if k == "xface" and len(prof) > 1:
+            continue                        # second stream, beside the face stages
+        per_step[k] = v["ms"] * share
+    dom = max(per_step, key=per_step.get)
+    alg = METHOD_VALUES * evsz * updates_per_step
+    achieved = alg / (prof[dom]["ms"] * 1e-3) / 1e9
+    t = measured_traffic(workload, dom, precision, (variants or {}).get(dom)) if workload else None
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": t, "algorithmic_bytes": alg,
+            "basis": "%d B per cell-velocity update (read and write g~, h~ once) x %.4g updates per step, over "
+                     "the mean launch time of %s" % (METHOD_VALUES * evsz, updates_per_step, dom),
+            "step": {"ms": step_ms, "achieved": alg / (step_ms * 1e-3) / 1e9,
+                     "frac": alg / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "floor_frac": FLOOR_VALUES * evsz * updates_per_step / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "stage_ms": {k: round(v["ms"], 5) for k, v in prof.items()}}
+
+
+def _fields_error(fa, fb, vol=None):
+    """Relative L2 (volume-weighted) of rho, u (vector), T, p and q (vector) of fa against fb."""
+    vol = np.ones(len(fa)) if vol is None else vol
+    rl2 = lambda a, b: float(np.sqrt(np.sum(vol[:, None] * (a - b) ** 2) / np.sum(vol[:, None] * b ** 2)))
+    pa, pb = (fa[:, 0] * fa[:, 3])[:, None], (fb[:, 0] * fb[:, 3])[:, None]
+    return {"rho": rl2(fa[:, :1], fb[:, :1]), "u": rl2(fa[:, 1:3], fb[:, 1:3]), "T": rl2(fa[:, 3:4], fb[:, 3:4]),
+            "p": rl2(pa, pb), "q": rl2(fa[:, 4:6], fb[:, 4:6])}
+
+
+def jet_headline(steps, warmup, interval=5, precision=32, with_uvs=True, tune=True, with_mlvs=True):
+    """The headline: full-size jet, MLVS with adaptation every `interval`
+    steps inside the timed window, against UVS over the same steps."""
+    import torch
+    import paper_2609_35258_amd as m
+    from paper_2609_35258_amd import autotune
+    p = W.jet(512, 256, Kn_jet=1e-3, nv=161, vmax=7.0)
+    if not with_mlvs:
+        return {"uvs": _jet_uvs(p, steps, warmup, precision, tune)[0]}, None
+    s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=dict(JET_ADAPT, interval=0), graph=True)
+    s.step(JET_BASE_STEPS)
+    s.set_adapt(dict(JET_ADAPT, interval=interval))
+    s.step(max(warmup, 1))
+    tuned = autotune.autotune(s, precision) if tune else {}
+    torch.cuda.synchronize()
+    c0 = s.counters()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t_m = time.perf_counter() - t0
+    c1 = s.counters()
+    upd = c1["cell_updates"] - c0["cell_updates"]
+    n_adapt = c1["adaptations"] - c0["adaptations"]
+    print("jet MLVS: %d steps, %d adaptations, %.3f s" % (steps, n_adapt, t_m), file=sys.stderr, flush=True)
+    npts, ncells, ncross = s.level_info()
+    f_m = s.moments()
+    mem_m = s.memory()
+    prof = stage_profile(s, reps=3)
+    prof["criterion"] = {"ms": s.time_stage("criterion", 2), "items": p.n_cells, "points": upd / max(steps, 1)}
+    # adaptation cost (criterion, grouping, level install), timed as whole calls
+    t_ad, split = [], []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        r = s.adapt()
+        torch.cuda.synchronize()
+        t_ad.append(1e3 * (time.perf_counter() - ta))
+        split.append({k: round(r[k], 3) for k in ("ms_criterion", "ms_dedupe", "ms_cluster", "ms_install")}
+                     | {"n_unique": r["n_unique"], "n_changed": r["n_changed"]})
+    variants = {k: v["variant"] for k, v in tuned.items()}
+    kap = np.stack([s.level_kappa(k) for k in range(len(npts))])
+    levels = s.cell_levels()
+    sample = _jet_patch(p, s, levels)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    ups = upd / steps
+    out = {"value": upd / t_m, "ms_per_step": 1e3 * t_m / steps, "updates_per_step": ups,
+           "adaptations_timed": int(n_adapt), "adapt_ms": t_ad, "adapt_split": split, "levels": len(npts),
+           "level_points": [int(x) for x in npts], "level_cells": [int(x) for x in ncells],
+           "nbar": float(np.sum(npts * ncells) / np.sum(ncells)), "n_cross": int(ncross), "device_bytes": int(mem_m),
+           "variants": variants,
+           "roofline": method_roofline(prof, precision, ups, 1e3 * t_m / steps,
+                                       JET_WL + "-mlvs" if precision == 32 else None, variants, interval)}
+    if with_uvs:
+        out["uvs"], f_u, mem_u, t_u = _jet_uvs(p, steps, warmup, precision, tune)
+        err = _fields_error(f_m, f_u)
+        out["uvs"].update({"time_to_solution_ratio": t_u / t_m, "memory_ratio": mem_u / mem_m,
+                           "mlvs_vs_uvs_rel_l2": err,
+                           "meets_1e-3_gate_rho_T": bool(err["rho"] <= 1e-3 and err["T"] <= 1e-3)})
+    return out, (p, kap, levels, sample)
+
+
+def _jet_uvs(p, steps, warmup, precision, tune):
+    """The UVS form of the headline over the same steps: (result, fields, bytes, seconds)."""
+    import torch
+    import paper_2609_35258_amd as m
+    from paper_2609_35258_amd import autotune
+    u = m.Solver.from_problem(p, precision=precision, compat=4, adapt=None, graph=True)
+    u.step(JET_BASE_STEPS + max(warmup, 1))
+    tuned_u = autotune.autotune(u, precision) if tune else {}
+    torch.cuda.synchronize()
+    c0 = u.counters()
+    t0 = time.perf_counter()
+    u.step(steps)
+    torch.cuda.synchronize()
+    t_u = time.perf_counter() - t0
+    upd_u = u.counters()["cell_updates"] - c0["cell_updates"]
+    f_u = u.moments()
+    mem_u = u.memory()
+    prof_u = stage_profile(u, reps=3)
+    var_u = {k: v["variant"] for k, v in tuned_u.items()}
+    u.close()
+    del u
+    torch.cuda.empty_cache()
+    res = {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps, "device_bytes": int(mem_u), "variants": var_u,
+           "roofline": method_roofline(prof_u, precision, upd_u / steps, 1e3 * t_u / steps,
+                                       JET_WL + "-uvs" if precision == 32 else None, var_u)}
+    return res, f_u, mem_u, t_u
+
+
+def _jet_patch(p, s, levels, size=12):
+    """The 12 x 12-cell window of the jet with the most distinct levels (ties:
+    the first in row-major order), with its cells' states: the CPU baseline's
+    sample."""
+    ni, nj = p.ni, p.nj
+    L = levels.reshape(nj, ni)
+    best, key = None, None
+    for j0 in range(0, nj - size + 1, size):
+        for i0 in range(0, ni - size + 1, size):
+            w = L[j0:j0 + size, i0:i0 + size]
+            k = (len(np.unique(w)), int(np.sum(w[:, 1:] != w[:, :-1]) + np.sum(w[1:, :] != w[:-1, :])))
+            if key is None or k > key:
+                best, key = (i0, j0), k
+    i0, j0 = best
+    cells = [(i0 + a) + ni * (j0 + b) for b in range(size) for a in range(size)]
+    return {"i0": i0, "j0": j0, "size": size, "cells": cells, "state": [s.get_cell(c) for c in cells],
+            "dt": s.dt}
+
+
+def _oracle_patch_work(args):
+    """One CPU worker: an oracle MLVS step of the patch (from the GPU's state and
+    levels) plus the criterion on `n_crit` of its cells.  Returns (seconds of
+    the step, seconds per criterion cell, cell-velocity updates of the step)."""
+    path, n_crit = args
+    from oracle import levels as lv_
+    from oracle.solver import AdaptParams, Solver as Oracle
+    d = np.load(path, allow_pickle=False)
+    p = W.jet(512, 256, Kn_jet=1e-3, nv=161, vmax=7.0)
+    q = W.patch(p, int(d["i0"]), int(d["j0"]), int(d["size"]), int(d["size"]))
+    o = Oracle(q, compat=4, dt=float(d["dt"]),
+               adapt=AdaptParams(JET_ADAPT["C_split"], JET_ADAPT["C_merge"], JET_ADAPT["eps_merge"],
+                                 JET_ADAPT["tau_clust"], True, 0))
+    o.set_levels(list(d["kap"]), d["levels"])
+    off = d["off"]
+    o.g = [d["g"][off[c]:off[c + 1]].copy() for c in range(len(off) - 1)]
+    o.h = [d["h"][off[c]:off[c + 1]].copy() for c in range(len(off) - 1)]
+    ap = o.adapt_params
+    t0 = time.perf_counter()
+    for c in range(n_crit):
+        lv_.criterion(o.levels[o.cell_level[c]], o.g[c], o.h[c], ap.C_split, ap.C_merge, ap.eps_merge, True)
+    t_crit = (time.perf_counter() - t0) / max(n_crit, 1)
+    t0 = time.perf_counter()
+    o.step_count = 1                     # no adaptation inside the timed step
+    o.adapt_params = None
+    o.step()
+    t_step = time.perf_counter() - t0
+    return t_step, t_crit, float(sum(len(g) for g in o.g))
+
+
+def _host_cpu():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"nproc": avail, "cpu_count": os.cpu_count(), "model": model}
+
+
+def cpu_baseline(jet_sample, interval=5, n_crit=4, max_workers=16):
+    """The oracle as it stands, timed on the host: an MLVS step of a 12 x 12-cell
+    window of the headline jet (the GPU's state, levels and time step) plus the
+    criterion on a few of its cells, amortised over the adaptation interval;
+    once on one core and once on every core of the process's CPU share (the
+    same task in each of min(16, available) worker processes)."""
+    import multiprocessing as mp
+    import tempfile
+    p, kap, levels, sample = jet_sample
+    cells = sample["cells"]
+    g = np.concatenate([st[0] for st in sample["state"]])
+    h = np.concatenate([st[1] for st in sample["state"]])
+    off = np.concatenate([[0], np.cumsum([len(st[0]) for st in sample["state"]])])
+    host = _host_cpu()
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "patch.npz")
+        np.savez(path, i0=sample["i0"], j0=sample["j0"], size=sample["size"], dt=sample["dt"], kap=kap,
+                 levels=np.asarray(levels)[cells], g=g, h=h, off=off)
+        ctx = mp.get_context("spawn")
+        # one thread per worker process (numpy's BLAS would otherwise start its own)
+        saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+        os.environ.update({k: "1" for k in saved})
+        try:
+            with ctx.Pool(1) as pool:
+                t1, c1, n1 = pool.map(_oracle_patch_work, [(path, n_crit)])[0]
+            P = max(1, min(max_workers, host["nproc"] or 1))
+            t0 = time.perf_counter()
+            with ctx.Pool(P) as pool:
+                res = pool.map(_oracle_patch_work, [(path, n_crit)] * P)
+            wall = time.perf_counter() - t0
+        finally:
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+    ncell = len(cells)
+    rate1 = n1 / (t1 + c1 * ncell / interval)
+    # all cores: every worker did the same step and criterion cells
+    tP = max(r[0] for r in res)
+    cP = max(r[1] for r in res)
+    rateP = P * n1 / (tP + cP * ncell / interval)
+    return {"value": rateP, "unit": "cell-velocity updates/s", "cores": P, "kind": "oracle",
+            "sample": "oracle MLVS step of the 12x12-cell window at cells (%d..%d, %d..%d) of the jet (%d levels in "
+                      "it, %.4g cell-velocity updates, the GPU's state and levels) plus the criterion on %d of its "
+                      "cells, amortised over %d steps; %d worker processes each running that task (one oracle and one "
+                      "BLAS thread per process), slowest worker's times" % (
+                          sample["i0"], sample["i0"] + 11, sample["j0"], sample["j0"] + 11,
+                          len(np.unique(np.asarray(levels)[cells])), n1, n_crit, interval, P),
+            "host": host,
+            "single_core": {"value": rate1, "cores": 1, "step_s": t1, "criterion_s_per_cell": c1},
+            "all_cores": {"value": rateP, "cores": P, "step_s": tP, "criterion_s_per_cell": cP, "wall_s": wall}}
+
+
+def fp32_vs_fp64(steps=200, warmup=100):
+    """FP32 storage against the FP64 path at full size (the cylinder, 256 x 128,
+    101^2, Ma 3, Kn 0.1): both from the freestream, `warmup` base-grid steps,
+    then the FP64 run adapts once and the FP32 run takes the same catalogue and
+    cell levels (so only the precision differs), then `steps` more steps; the
+    per-field relative L2 of the FP32 fields against the FP64 ones at the end,
+    UVS and MLVS, and the drift of the conserved totals."""
+    import torch
+    import paper_2609_35258_amd as m
+    p = W.cylinder(256, 128, Kn=0.1, nv=101, vmax=10.0)
+    out = {}
+    for mode in ("uvs", "mlvs"):
+        runs = {}
+        cat = None
+        for prec in (64, 32):
+            s = m.Solver.from_problem(p, precision=prec, compat=4, adapt=CYL_ADAPT if mode == "mlvs" else None,
+                                      graph=True)
+            t0 = s.totals()
+            s.step(warmup)
+            if mode == "mlvs":
+                if cat is None:
+                    s.adapt()
+                    npts = s.level_info()[0]
+                    cat = (np.stack([s.level_kappa(k) for k in range(len(npts))]), s.cell_levels())
+                else:
+                    s.set_levels(*cat)
+            s.step(steps)
+            runs[prec] = (s.moments(), s.totals(), t0)
+            s.close()
+            del s
+            torch.cuda.empty_cache()
+        f64, f32 = runs[64][0], runs[32][0]
+        tot32, t032 = runs[32][1], runs[32][2]
+        out[mode] = {"rel_l2": _fields_error(f32, f64),
+                     "mass_drift_fp32": float(abs(tot32[0] - t032[0]) / abs(t032[0]))}
+    out["workload"] = ("cylinder 256x128, 101^2, Ma 3, Kn 0.1: %d base-grid steps, then %d steps (MLVS: the FP64 "
+                       "run's catalogue installed in both)" % (warmup, steps))
+    return out
+
+
+def sod_case(steps=100):
+    """Configuration 1: the 1-D Sod tube, 200 cells, 101-point Boole grid, BGK,
+    plain UVS-DUGKS in FP64 (no compatibility correction), Kn 1e-3 and 1e-1."""
+    import torch
+    import paper_2609_35258_amd as m
+    out = {}
+    for Kn in (1e-3, 1e-1):
+        p = W.sod_1d(200, Kn=Kn, nv=101, vmax=10.0)
+        s = m.Solver.from_problem(p, precision=64, compat=0, face_compat=False, graph=True)
+        s.step(5)
+        torch.cuda.synchronize()
+        c0 = s.counters()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out["Kn=%g" % Kn] = {"value": (s.counters()["cell_updates"] - c0["cell_updates"]) / t,
+                             "ms_per_step": 1e3 * t / steps}
+        s.close()
+    out["note"] = "2.0e4 cell-velocity points per step: launch-bound"
+    return out
+
+
+def cavity_case(steps=200, warmup=100):
+    """Configuration 2: the 64 x 64 lid-driven cavity, 28^2 Gauss-Hermite, FP64,
+    MLVS with criterion levels (adaptation every 100 steps) and with a fixed
+    three-level catalogue, against UVS.  Its 51 MB state stays in the 256 MB
+    Infinity Cache: the step is bound by FP64 VALU issue, not HBM."""
+    import torch
+    import paper_2609_35258_amd as m
+    from paper_2609_35258_amd import autotune
+    p = W.cavity(64, Kn=0.075, nv=28)
+    out = {"workload": "lid-driven cavity 64x64, Kn 0.075, lid Ma 0.16, Shakhov Pr 2/3, 28x28 Gauss-Hermite, fp64; "
+                       "%d untimed then %d timed steps" % (warmup, steps),
+           "bound": "cache-resident (51 MB state in the 256 MB Infinity Cache); FP64 VALU issue"}
+    runs = {}
+    for mode in ("mlvs", "fixed3", "uvs"):
+        s = m.Solver.from_problem(p, precision=64, compat=4, adapt=ADAPT if mode == "mlvs" else None, graph=True)
+        if mode == "fixed3":
+            # three nested levels: 8x8 merges far out, 4x4 and 2x2 closer in
+            nb = p.nv // 2
+            bx, by = np.meshgrid(np.arange(nb), np.arange(nb))
+            r = np.maximum(np.abs(bx - (nb - 1) / 2), np.abs(by - (nb - 1) / 2))
+            kap = []
+            for rmax in (6, 4, 2):
+                k = np.zeros((nb, nb), np.uint8)
+                k[r > rmax] = 1
+                kap.append(k.ravel())
+            cl = W.striped_levels(p.ni, p.nj, 3, 1)
+            s.set_levels(np.stack(kap), cl)
+        s.step(warmup)
+        autotune.autotune(s, 64)
+        torch.cuda.synchronize()
+        c0 = s.counters()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        npts, ncells, _ = s.level_info()
+        runs[mode] = (s.moments(), t)
+        out[mode] = {"value": (s.counters()["cell_updates"] - c0["cell_updates"]) / t, "ms_per_step": 1e3 * t / steps,
+                     "levels": [int(x) for x in npts], "nbar": float(np.sum(npts * ncells) / np.sum(ncells))}
+        s.close()
+    for mode in ("mlvs", "fixed3"):
+        out[mode]["time_to_solution_ratio"] = runs["uvs"][1] / runs[mode][1]
+        out[mode]["mlvs_vs_uvs_rel_l2"] = _fields_error(runs[mode][0], runs["uvs"][0])
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--n", type=int, default=64)
-    ap.add_argument("--nv", type=int, default=28)
-    ap.add_argument("--precision", type=int, default=64)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--steps", type=int, default=50, help="timed MLVS (and UVS) steps of the headline jet")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed MLVS steps after the base-grid steps")
+    ap.add_argument("--interval", type=int, default=5, help="adaptation interval of the headline MLVS run")
     ap.add_argument("--no-uvs", action="store_true")
-    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sections", action="store_true", help="only the headline (and the CPU baseline)")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--no-cylinder", action="store_true")
-    ap.add_argument("--no-jet", action="store_true")
+    ap.add_argument("--jet-only", action="store_true", help="only the headline jet (profiling runs)")
+    ap.add_argument("--jet-mode", choices=("both", "mlvs", "uvs"), default="both")
     ap.add_argument("--tau-sweep", action="store_true", help="only the clustering-threshold sweep on the cylinder")
     ap.add_argument("--long-map", type=int, default=4, choices=[4, 9], help="mapping order of the --long runs")
     ap.add_argument("--long", choices=("cylinder", "jet"), default=None,
                     help="only a whole run of that case, MLVS against UVS (10,000 cylinder or 2,000 jet steps)")
-    ap.add_argument("--no-two-cavity", action="store_true")
     ap.add_argument("--two-cavity-only", action="store_true", help="only the two-cavity comparison")
     ap.add_argument("--tc-mode", default="both", choices=["both", "uvs", "mlvs"])
     ap.add_argument("--tc-interval", type=int, default=5)
@@ -639,16 +872,18 @@ def main():
     ap.add_argument("--tc-scale", type=float, default=1.0, help="factor on C_split, C_merge and eps_merge")
     ap.add_argument("--tc-t-end", type=float, default=0.0,
                     help="with --two-cavity-only: run both forms to this time instead (the paper's t = 4)")
-    ap.add_argument("--jet-only", action="store_true", help="only the full-size jet comparison (profiling runs)")
-    ap.add_argument("--jet-mode", choices=("both", "mlvs", "uvs"), default="both")
     ap.add_argument("--cylinder-only", action="store_true",
                     help="only the full-size cylinder comparison (profiling runs)")
     ap.add_argument("--cylinder-steps", type=int, default=200)
+    ap.add_argument("--cylinder-kn", type=float, default=0.1)
     ap.add_argument("--cylinder-mode", choices=("both", "mlvs", "uvs"), default="both")
-    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; run it without --gpus or with "
+              "--gpus 1.", file=sys.stderr)
+        sys.exit(2)
     if args.copy_probe:
         import torch
         a = torch.empty(args.copy_probe // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -657,9 +892,6 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": args.copy_probe}))
-        return
-    if args.jet_only:
-        print(json.dumps({"jet": jet_case(mode=args.jet_mode)}), flush=True)
         return
     if args.tau_sweep:
         print(json.dumps({"tau_sweep": tau_sweep()}), flush=True)
@@ -678,64 +910,48 @@ def main():
         print(json.dumps({"two_cavity": two_cavity_case(mode=args.tc_mode, interval=args.tc_interval)}), flush=True)
         return
     if args.cylinder_only:
-        print(json.dumps({"cylinder": cylinder_case(steps=args.cylinder_steps, mode=args.cylinder_mode)}), flush=True)
+        print(json.dumps({"cylinder": cylinder_case(steps=args.cylinder_steps, mode=args.cylinder_mode,
+                                                    Kn=args.cylinder_kn)}), flush=True)
         return
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: the library has no multi-GPU path.",
-              file=sys.stderr)
-        sys.exit(2)
-    import torch
-    p = workload(args)
-    s, t_mlvs, upd, ipts = run_gpu(p, args.steps, args.warmup, args.precision, ADAPT, not args.no_graph,
-                                   not args.no_tune)
-    value = upd / t_mlvs
-    npts, ncells, ncross = s.level_info()
-    nbar = float(np.sum(npts * ncells) / np.sum(ncells))
-    fields_m = s.moments()
-    mem_m = s.memory()
-    prof = stage_profile(s)
-    variants = {k: v["variant"] for k, v in getattr(s, "tuned", {}).items()}
-    roof = roofline(prof, args.precision, variants,
-                    "cavity64-gh28-fp64-mlvs" if (args.n, args.nv, args.precision) == (64, 28, 64) else None)
-    out = {"metric": "DUGKS cell-velocity updates/s (MLVS-DUGKS hot path, adaptation included)",
-           "value": value, "unit": "cell-velocity updates/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": 1e3 * t_mlvs / args.steps, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == 64 else "f32",
-           "data": "synthetic",
-           "config": {"workload": "lid-driven cavity %dx%d, Kn 0.075, lid Ma 0.16, Shakhov Pr 2/3, %dx%d "
-                                  "Gauss-Hermite base grid, MLVS (criterion levels, interval 100)"
-                                  % (args.n, args.n, args.nv, args.nv),
-                      "n_cells": p.n_cells, "base_points": args.nv * args.nv, "levels": len(npts),
-                      "level_points": [int(x) for x in npts], "level_cells": [int(x) for x in ncells],
-                      "nbar": nbar, "n_cross": int(ncross), "iface_points_per_s": ipts / t_mlvs,
-                      "graph": not args.no_graph,
-                      "variants": {k: v["variant"] for k, v in getattr(s, "tuned", {}).items()}},
-           "roofline": roof}
-    s.close()
-    if not args.no_uvs:
-        u, t_uvs, upd_u, _ = run_gpu(p, args.steps, args.warmup, args.precision, None, not args.no_graph,
-                                     not args.no_tune)
-        fields_u = u.moments()
-        mem_u = u.memory()
-        vol = np.ones(p.n_cells)
-        err = {}
-        for k, name in ((0, "rho"), (1, "u"), (3, "T")):
-            a, b = fields_m[:, k], fields_u[:, k]
-            err[name] = float(np.sqrt(np.sum(vol * (a - b) ** 2) / np.sum(vol * b ** 2)))
-        out["uvs"] = {"value": upd_u / t_uvs, "ms_per_step": 1e3 * t_uvs / args.steps,
-                      "time_to_solution_ratio": t_uvs / t_mlvs, "memory_ratio": mem_u / mem_m,
-                      "mlvs_vs_uvs_rel_l2": err}
-        u.close()
-    if not args.no_cylinder:
-        out["cylinder"] = cylinder_case(steps=args.cylinder_steps)
-    if not args.no_jet:
-        out["jet"] = jet_case()
-    if not args.no_two_cavity:
-        out["two_cavity"] = two_cavity_case()
-    if not args.no_learned:
-        out["learned"] = learned_vs_criterion()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p)
+    if args.jet_only and args.jet_mode == "uvs":
+        print(json.dumps({"jet": jet_headline(args.steps, args.warmup, with_mlvs=False, tune=not args.no_tune)[0]}),
+              flush=True)
+        return
+    head, sample = jet_headline(args.steps, args.warmup, args.interval, with_uvs=not args.no_uvs
+                                and args.jet_mode != "mlvs", tune=not args.no_tune)
+    out = {"metric": "DUGKS cell·velocity updates/s, MLVS vs UVS time-to-solution at ≤1e-3 rel L2",
+           "value": head["value"], "unit": "cell-velocity updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "slot jet 512x256 on [0,32]x[-8,8], sonic slot |y| <= 0.5, background rho 0.01 "
+                                  "(pressure ratio 100), Kn_jet 1e-3, Shakhov Pr 2/3, 161x161 Newton-Cotes on "
+                                  "[-7,7]^2, FP32 storage; MLVS C_split 0.01 C_merge 0.005 eps_merge 2e-5 tau_clust "
+                                  "0.05, adaptation every %d steps inside the timed steps; %d untimed base-grid "
+                                  "steps from the initial state, then %d untimed and %d timed MLVS steps"
+                                  % (args.interval, JET_BASE_STEPS, max(args.warmup, 1), args.steps),
+                      "n_cells": 131072, "base_points": 25921, "interval": args.interval,
+                      "adaptations_timed": head["adaptations_timed"], "adapt_ms": head["adapt_ms"],
+                      "adapt_split": head["adapt_split"],
+                      "levels": head["levels"], "level_points": head["level_points"],
+                      "level_cells": head["level_cells"], "nbar": head["nbar"], "n_cross": head["n_cross"],
+                      "updates_per_step": head["updates_per_step"], "device_bytes": head["device_bytes"],
+                      "graph": True, "variants": head["variants"]},
+           "roofline": head["roofline"]}
+    if "uvs" in head:
+        out["uvs"] = head["uvs"]
+    if not (args.no_sections or args.jet_only):
+        for name, fn in (("sod", sod_case), ("cavity", cavity_case),
+                         ("cylinder", lambda: cylinder_case(steps=args.cylinder_steps)),
+                         ("fp32_vs_fp64", fp32_vs_fp64), ("two_cavity", two_cavity_case)):
+            t0 = time.perf_counter()
+            out[name] = fn()
+            print("section %s: %.1f s" % (name, time.perf_counter() - t0), file=sys.stderr, flush=True)
+        if not args.no_learned:
+            out["learned"] = learned_vs_criterion()
+    if not (args.no_cpu_baseline or args.jet_only):
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(sample, interval=args.interval)
+        print("cpu baseline: %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

@@ -167,6 +167,10 @@ typedef struct {
     double nbar;           /* cell-weighted mean number of velocity points  */
     int64_t neg_count;     /* corrections that produced negative g          */
     int64_t n_fallback;    /* learned adaptation: cells sent to the criterion */
+    /* host wall time of the parts of a criterion adaptation (ms): criterion
+     * kernel (stream synchronised after it), deduplication of the masks,
+     * clustering, level installation (remap, work lists); 0 for learned ones */
+    double ms_criterion, ms_dedupe, ms_cluster, ms_install;
 } mlvs_adapt_report;
 
 /* Quadrature helpers (Sec. 2.3).  Newton-Cotes on [-a, a]: composite Boole
@@ -225,6 +229,13 @@ mlvs_status mlvs_step(mlvs_ctx ctx, int n_steps);
  * 0 (the default) turns both off: such events are only counted.  Other
  * values are MLVS_E_ARG. */
 mlvs_status mlvs_set_strict(mlvs_ctx ctx, int flags);
+
+/* Replace the adaptation parameters (meaning as at create).  They apply from
+ * the next adaptation on; mlvs_step adapts before every step whose index,
+ * counted from create, is a multiple of the new interval.  MLVS_E_STATE if
+ * the context was created without adaptation parameters; MLVS_E_ARG for
+ * interval < 0 or C_merge > C_split. */
+mlvs_status mlvs_set_adapt(mlvs_ctx ctx, const mlvs_adapt_params* adapt);
 
 /* Criterion + grouping + remap now (Secs. 3.2, 3.4).  report may be NULL. */
 mlvs_status mlvs_adapt(mlvs_ctx ctx, mlvs_adapt_report* report);

@@ -293,21 +293,22 @@ def block_flux_error(base: BaseGrid, gb, hb, S, s, bx, by):
     and that of the block's merged point (w_B = sum w, xi_B the weighted mean,
     g_B and H_B = (h + |xi|^2 g)_B weighted means, as in the coarsening of
     Sec. 3.3.2)."""
-    w, xi = base.w, base.xi
-    x2 = np.sum(xi * xi, axis=1)
-    m = transport_moments(base, gb, hb)
     pts = base.block_points(s, bx, by)
-    wp = w[pts]
+    xp = base.xi[pts]
+    wp = base.w[pts]
+    gp, hp = gb[pts], hb[pts]
+    x2 = np.sum(xp * xp, axis=1)
+    m = np.stack([gp, xp[:, 0] * gp, xp[:, 1] * gp, 0.5 * (hp + x2 * gp)])     # m_r on the block's points
     WB = wp.sum()
-    xB = (wp[:, None] * xi[pts]).sum(0) / WB
-    gB = np.sum(wp * gb[pts]) / WB
-    HB = np.sum(wp * (hb[pts] + x2[pts] * gb[pts])) / WB
+    xB = (wp[:, None] * xp).sum(0) / WB
+    gB = np.sum(wp * gp) / WB
+    HB = np.sum(wp * (hp + x2 * gp)) / WB
     mB = np.array([gB, xB[0] * gB, xB[1] * gB, 0.5 * HB])
     err = 0.0
     for d in (0, 1):
         for sgn in (1.0, -1.0):
-            sel = sgn * xi[pts, d] >= 0
-            Ff = np.sum((wp * xi[pts, d])[None, :] * m[:, pts] * sel[None, :], axis=1)
+            sel = sgn * xp[:, d] >= 0
+            Ff = np.sum((wp * xp[:, d])[None, :] * m * sel[None, :], axis=1)
             Fm = WB * xB[d] * mB if sgn * xB[d] >= 0 else np.zeros(4)
             err = max(err, float(np.max(np.abs(Ff - Fm) / S)))
     return err

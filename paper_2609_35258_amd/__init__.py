@@ -72,7 +72,8 @@ class mlvs_device(ctypes.Structure):
 class mlvs_adapt_report(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int), ("n_unique", ctypes.c_int64), ("n_changed", ctypes.c_int64),
                 ("n_cross", ctypes.c_int64), ("nbar", ctypes.c_double), ("neg_count", ctypes.c_int64),
-                ("n_fallback", ctypes.c_int64)]
+                ("n_fallback", ctypes.c_int64), ("ms_criterion", ctypes.c_double), ("ms_dedupe", ctypes.c_double),
+                ("ms_cluster", ctypes.c_double), ("ms_install", ctypes.c_double)]
 
 
 class mlvs_train_cfg(ctypes.Structure):
@@ -149,6 +150,7 @@ _PROTOS = {
     "mlvs_selector_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "mlvs_selector_params": (ctypes.c_int, [ctypes.c_void_p, _c_float_p, ctypes.POINTER(ctypes.c_int)]),
     "mlvs_set_strict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "mlvs_set_adapt": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(mlvs_adapt_params)]),
     "mlvs_destroy": (None, [ctypes.c_void_p]),
     "mlvs_last_error": (ctypes.c_char_p, []),
 }
@@ -451,6 +453,12 @@ class Solver:
         cl = np.ascontiguousarray(cell_level, np.int32)
         n = len(k) // max(self.n_blocks, 1)
         _check(lib().mlvs_set_levels(self.h, n, k.ctypes.data_as(_c_uint8_p), cl.ctypes.data_as(_c_int32_p)))
+
+    def set_adapt(self, adapt: dict):
+        """Replace the adaptation parameters (dict as at creation)."""
+        ap = mlvs_adapt_params(adapt["C_split"], adapt["C_merge"], adapt.get("eps_merge", 0.0), adapt["tau_clust"],
+                               int(adapt.get("flux_test", False)), int(adapt.get("interval", 0)))
+        _check(lib().mlvs_set_adapt(self.h, ctypes.byref(ap)))
 
     def adapt(self):
         rep = mlvs_adapt_report()

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -30,6 +31,20 @@ using namespace mlvs;
 namespace {
 
 thread_local std::string g_last_error;
+
+// MLVS_TIMING=1 in the environment: host wall-clock marks of the adaptation's
+// parts on stderr (diagnostics only).
+struct Marks {
+    bool on = std::getenv("MLVS_TIMING") != nullptr;
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    void mark(const char* what, hipStream_t st) {
+        if (!on) return;
+        (void)hipStreamSynchronize(st);
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[mlvs] %-28s %9.3f ms\n", what, std::chrono::duration<double, std::milli>(now - t).count());
+        t = now;
+    }
+};
 
 struct Fail {
     int code;
@@ -211,7 +226,47 @@ struct Base {
     int nx = 0, ny = 0, N = 0, nbx = 0, nby = 0, Nb = 0;
     std::vector<double> x, y, w;     // per base point
     std::vector<double> axes;        // the tensor grid's axes: x [nx], wx [nx], y [ny], wy [ny]
+    std::vector<double> ctab;        // criterion: per aligned block of scales 1, 2, 3 (see block_tables)
 };
+
+// Criterion tables of the aligned blocks of V_base (scale 1: N_b 2x2 blocks,
+// then the eligible 4x4 and 8x8 blocks), 15 values each: sum w, the velocity
+// centroid (sum w xi_x, sum w xi_y) / sum w, then for d = x, y and the
+// half-ranges s = (xi_d >= 0, xi_d <= 0) P[d][s] = sum w xi_d, then
+// Q[d][s][e] = sum w xi_d xi_e.
+void block_tables(Base& B) {
+    B.ctab.clear();
+    const int n4x = B.nbx / 2, n4y = B.nby / 2, n8x = B.nbx / 4, n8y = B.nby / 4;
+    auto put = [&](int s, int X, int Y) {
+        double t[15] = {0};
+        const int size = 1 << s;
+        for (int iy = Y * size; iy < Y * size + size; ++iy)
+            for (int ix = X * size; ix < X * size + size; ++ix) {
+                const int b = ix + B.nx * iy;
+                const double w = B.w[b], xd[2] = {B.x[b], B.y[b]};
+                t[0] += w;
+                t[1] += w * xd[0];
+                t[2] += w * xd[1];
+                for (int d = 0; d < 2; ++d)
+                    for (int sg = 0; sg < 2; ++sg) {
+                        if (!(sg == 0 ? xd[d] >= 0 : -xd[d] >= 0)) continue;
+                        t[3 + 2 * d + sg] += w * xd[d];
+                        t[7 + 4 * d + 2 * sg] += w * xd[d] * xd[0];
+                        t[7 + 4 * d + 2 * sg + 1] += w * xd[d] * xd[1];
+                    }
+            }
+        t[1] /= t[0];
+        t[2] /= t[0];
+        B.ctab.insert(B.ctab.end(), t, t + 15);
+    };
+    for (int Y = 0; Y < B.nby; ++Y)
+        for (int X = 0; X < B.nbx; ++X) put(1, X, Y);
+    for (int Y = 0; Y < n4y; ++Y)
+        for (int X = 0; X < n4x; ++X) put(2, X, Y);
+    for (int Y = 0; Y < n8y; ++Y)
+        for (int X = 0; X < n8x; ++X) put(3, X, Y);
+    if (B.ctab.empty()) B.ctab.assign(15, 0.0);
+}
 
 struct Level {
     std::vector<uint8_t> kappa;
@@ -220,6 +275,7 @@ struct Level {
     std::vector<int> pt_of_base;
     std::vector<int> mem_off, mem_idx;     // base members per point (ascending)
     std::vector<int> canon_of;             // device point -> canonical point (I/O order)
+    std::vector<double> crit_tab;          // per point: |xi_p|^2, sum w|x|, w|y|, w x^2, w|xy|, w y^2 over members
     double Minv[16];
     double G6inv[36], B36[18], H3inv[9];   // nine-moment mapping (see build_level)
     bool is_iface = false;
@@ -342,6 +398,21 @@ std::unique_ptr<Level> build_level(const Base& B, const std::vector<uint8_t>& ka
         L->xi_y[p] = sy / ws;
         L->mem_off[p + 1] = (int)L->mem_idx.size();
     }
+    // criterion tables of the points (normalisations S_r of Eq. merge-transport-error)
+    L->crit_tab.assign(6 * (size_t)L->N, 0.0);
+    for (int p = 0; p < L->N; ++p) {
+        double* t = &L->crit_tab[6 * (size_t)p];
+        t[0] = L->xi_x[p] * L->xi_x[p] + L->xi_y[p] * L->xi_y[p];
+        for (int k = L->mem_off[p]; k < L->mem_off[p + 1]; ++k) {
+            const int b = L->mem_idx[k];
+            const double w = B.w[b], ax = std::fabs(B.x[b]), ay = std::fabs(B.y[b]);
+            t[1] += w * ax;
+            t[2] += w * ay;
+            t[3] += w * ax * ax;
+            t[4] += w * ax * ay;
+            t[5] += w * ay * ay;
+        }
+    }
     // state-independent four-moment mapping matrix (Eqs. raw_four_g_basis, raw_four_gh_coupling)
     double A[16] = {0};
     for (int p = 0; p < L->N; ++p) {
@@ -386,7 +457,12 @@ std::unique_ptr<Level> level_of_mask(mlvs_ctx c, const std::vector<uint8_t>& kap
 
 HostTable make_table(const Level& dst, const Level& src) {
     HostTable t;
+    t.off.reserve(dst.N + 1);
+    t.idx.reserve(dst.N);
+    t.frac.reserve(dst.N);
     t.off.push_back(0);
+    // stamp[a] = the last dst point that listed source point a (O(members) per point)
+    std::vector<int> stamp(src.N, -1);
     for (int P = 0; P < dst.N; ++P) {
         const int b0 = dst.mem_idx[dst.mem_off[P]];
         const int a0 = src.pt_of_base[b0];
@@ -397,18 +473,12 @@ HostTable make_table(const Level& dst, const Level& src) {
             t.idx.push_back(a0);
             t.frac.push_back(1.0);
         } else {
-            int last = -1;
             for (int e = dst.mem_off[P]; e < dst.mem_off[P + 1]; ++e) {
                 const int a = src.pt_of_base[dst.mem_idx[e]];
-                if (a == last) continue;
-                bool seen = false;
-                for (int q = t.off.back(); q < (int)t.idx.size(); ++q)
-                    if (t.idx[q] == a) { seen = true; break; }
-                if (!seen) {
-                    t.idx.push_back(a);
-                    t.frac.push_back(src.w[a] / dst.w[P]);
-                }
-                last = a;
+                if (stamp[a] == P) continue;
+                stamp[a] = P;
+                t.idx.push_back(a);
+                t.frac.push_back(src.w[a] / dst.w[P]);
             }
         }
         t.off.push_back((int)t.idx.size());
@@ -428,21 +498,52 @@ struct DevTable {
 // build instead of one allocation and copy per array.  Pieces are 256-byte
 // aligned; the block starts with a 256-byte pad so no piece shares the block's
 // address.
+// Staging area of one upload: a host image of a device block, written in
+// place, then copied with one hipMemcpyAsync.  It lives in pinned memory kept
+// by the context between builds (a fresh pageable image cost page faults and
+// reallocation copies on every adaptation, and its copy ran at pageable
+// speed); it grows geometrically and only ever grows.
 struct Stage {
-    std::vector<char> buf;
-    Stage() { buf.assign(256, 0); }
-    size_t put(const void* p, size_t n) {
-        const size_t off = (buf.size() + 255) & ~size_t(255);
-        buf.resize(off + std::max<size_t>(n, 1), 0);
-        if (p && n) std::memcpy(buf.data() + off, p, n);
+    uint8_t* p = nullptr;
+    size_t cap = 0, size = 256;
+    Stage(uint8_t*& buf, size_t& capacity) : p(buf), cap(capacity), bref(buf), cref(capacity) {}
+    ~Stage() { bref = p; cref = cap; }
+    Stage(const Stage&) = delete;
+    Stage& operator=(const Stage&) = delete;
+    void reserve(size_t n) {
+        if (n <= cap) return;
+        const size_t want = std::max(n, std::max(2 * cap, (size_t)16 << 20));
+        uint8_t* q = nullptr;
+        hip_check(hipHostMalloc((void**)&q, want, hipHostMallocDefault), "pinned alloc");
+        if (p) {
+            std::memcpy(q, p, size);
+            (void)hipHostFree(p);
+        }
+        p = q;
+        cap = want;
+    }
+    size_t put(const void* src, size_t n) {
+        const size_t off = (size + 255) & ~size_t(255);
+        reserve(off + std::max<size_t>(n, 1));
+        if (src && n) std::memcpy(p + off, src, n);
+        size = off + std::max<size_t>(n, 1);
         return off;
     }
     template <typename T>
     size_t put(const std::vector<T>& v) { return put(v.data(), sizeof(T) * v.size()); }
     template <typename T>
     void fill(size_t off, const std::vector<T>& v) {
-        if (!v.empty()) std::memcpy(buf.data() + off, v.data(), sizeof(T) * v.size());
+        if (!v.empty()) std::memcpy(p + off, v.data(), sizeof(T) * v.size());
     }
+    // copy the image to dst and wait for the copy (the buffer is reused next time)
+    void upload(void* dst, hipStream_t st) {
+        hip_check(hipMemcpyAsync(dst, p, size, hipMemcpyHostToDevice, st), "upload");
+        hip_check(hipStreamSynchronize(st), "stream synchronize");
+    }
+
+private:
+    uint8_t*& bref;
+    size_t& cref;
 };
 
 struct TabOff {
@@ -850,7 +951,10 @@ struct mlvs_ctx_s {
     CellGeom* d_geom = nullptr;
     double* d_params = nullptr;
     double* d_cmom = nullptr;          // [chunks][n_cells][NMOM] raw moments of the stored state
-    std::vector<char> stage_keep;      // host image of the last staged upload
+    uint8_t* stage_items = nullptr;    // pinned staging areas (Stage) of the work lists and of level installs
+    size_t stage_items_cap = 0;
+    uint8_t* stage_install = nullptr;
+    size_t stage_install_cap = 0;
     void* levels_block = nullptr;      // device block with the current levels' geometry
     double* d_fmom = nullptr;          // [chunks][faces + boundary faces][NFMOM] face moments
     int chunk = 1024;                  // velocity points per chunk (multiple of 64), set per level set
@@ -872,7 +976,9 @@ struct mlvs_ctx_s {
     // criterion inputs: base grid and per-level maps / masks
     double *d_bx = nullptr, *d_by = nullptr, *d_bw = nullptr, *d_axes = nullptr;
     int *d_ptb_all = nullptr, *d_ptb_off = nullptr;
-    double* d_x2b_all = nullptr;       // per level and base point: |xi_p|^2 of its level point p
+    double* d_ptab_all = nullptr;      // per level point: criterion tables (Level::crit_tab), levels in order
+    int* d_ptab_off = nullptr;         // first point of each level in d_ptab_all
+    double* d_ctab = nullptr;          // criterion tables of the base grid's blocks
     // host geometry of recently built levels by their mask (levels recur from
     // one adaptation to the next); copies carry no device memory
     std::map<std::vector<uint8_t>, std::unique_ptr<Level>> level_cache;
@@ -1012,11 +1118,13 @@ std::unique_ptr<Level> level_of_mask(mlvs_ctx c, const std::vector<uint8_t>& kap
 // current level set and upload them (one staged block).  Level state buffers
 // must exist.
 void build_items(mlvs_ctx c) {
+    Marks mk;
     free_items(c);
+    mk.mark("items: free", c->st);
     MeshH& M = c->mesh;
     const int n = M.n_cells;
     const int K = (int)c->levels.size();
-    Stage stg;
+    Stage stg(c->stage_items, c->stage_items_cap);
     std::vector<int> rows(K, 0), ghosts(K, 0);
     std::vector<int> cell_frow(4 * n, -1);
     std::vector<int> cell_nbr(4 * n, -1);
@@ -1064,6 +1172,7 @@ void build_items(mlvs_ctx c) {
             }
             cell_nbr[4 * cc + k] = -2 - row;
         }
+    mk.mark("items: ghosts", c->st);
     // interior faces, in the traversal order of their left cells
     int n_cross = 0;
     std::map<std::pair<int, int>, int> iface_of_pair;
@@ -1116,10 +1225,12 @@ void build_items(mlvs_ctx c) {
             cell_frow[4 * F.R + kR] = face_code(it.rowB, true, true);
         }
     }
+    mk.mark("items: faces", c->st);
     std::vector<std::array<TabOff, 4>> xtab;
     for (auto& it : xitems)
         xtab.push_back({table(it.levI, it.levA), table(it.levI, it.levB), table(it.levA, it.levI),
                         table(it.levB, it.levI)});
+    mk.mark("items: cross-face tables", c->st);
     c->n_cross = n_cross;
     c->step_points = 0.0;
     for (int cc = 0; cc < n; ++cc) c->step_points += c->levels[c->cell_level[cc]]->N;
@@ -1137,6 +1248,7 @@ void build_items(mlvs_ctx c) {
         cell_frow[4 * F.L + kk] = face_code((int)(faces.size() + bfaces.size()), false, false);
         bfaces.push_back(it);
     }
+    mk.mark("items: host lists", c->st);
     // row buffers
     for (int l = 0; l < K; ++l) {
         Level& L = *c->levels[l];
@@ -1157,18 +1269,19 @@ void build_items(mlvs_ctx c) {
         igeo.push_back({stg.put(L.xi_x), stg.put(L.xi_y), stg.put(L.w), stg.put(L.pt_of_base),
                         stg.put(xy_pairs(L))});
     }
+    mk.mark("items: row buffers", c->st);
     c->n_faces = (int)faces.size();
     c->n_bfaces = (int)bfaces.size();
     faces.insert(faces.end(), bfaces.begin(), bfaces.end());
-    std::vector<int> ptb, poff;
-    std::vector<double> x2b;
+    std::vector<int> ptb, poff, toff;
+    std::vector<double> ptab;
     std::vector<uint8_t> kap;
     if (c->base.Nb > 0) {
         for (int l = 0; l < K; ++l) {
             poff.push_back((int)ptb.size());
             ptb.insert(ptb.end(), c->levels[l]->pt_of_base.begin(), c->levels[l]->pt_of_base.end());
-            const Level& Lv = *c->levels[l];
-            for (int p : Lv.pt_of_base) x2b.push_back(Lv.xi_x[p] * Lv.xi_x[p] + Lv.xi_y[p] * Lv.xi_y[p]);
+            toff.push_back((int)(ptab.size() / 6));
+            ptab.insert(ptab.end(), c->levels[l]->crit_tab.begin(), c->levels[l]->crit_tab.end());
             kap.insert(kap.end(), c->levels[l]->kappa.begin(), c->levels[l]->kappa.end());
         }
     }
@@ -1182,8 +1295,9 @@ void build_items(mlvs_ctx c) {
     const size_t o_lev = stg.put(c->cell_level);
     const size_t o_slot = stg.put(c->cell_slot);
     const size_t o_order = stg.put(M.order);
-    const size_t o_ptb = stg.put(ptb), o_poff = stg.put(poff), o_kap = stg.put(kap), o_x2b = stg.put(x2b);
-    char* base = static_cast<char*>(c->dm.alloc(stg.buf.size()));
+    const size_t o_ptb = stg.put(ptb), o_poff = stg.put(poff), o_kap = stg.put(kap), o_ptab = stg.put(ptab),
+                 o_toff = stg.put(toff);
+    char* base = static_cast<char*>(c->dm.alloc(stg.size));
     c->item_allocs.push_back(base);
     for (size_t i = 0; i < c->ifaces.size(); ++i) {
         Level& L = *c->ifaces[i];
@@ -1218,8 +1332,9 @@ void build_items(mlvs_ctx c) {
     stg.fill(o_lv, descs);
     stg.fill(o_gh, gitems);
     stg.fill(o_xf, xitems);
-    hip_check(hipMemcpyAsync(base, stg.buf.data(), stg.buf.size(), hipMemcpyHostToDevice, c->st), "upload");
-    c->stage_keep = std::move(stg.buf);        // the host image stays alive until the next build
+    mk.mark("items: staging", c->st);
+    stg.upload(base, c->st);
+    mk.mark("items: upload", c->st);
     c->d_lv = reinterpret_cast<LevelDesc*>(base + o_lv);
     c->d_faces = reinterpret_cast<FaceItem*>(base + o_faces);
     c->d_ghosts = reinterpret_cast<GhostItem*>(base + o_gh); c->n_ghosts = (int)gitems.size();
@@ -1232,7 +1347,8 @@ void build_items(mlvs_ctx c) {
     if (c->base.Nb > 0) {
         c->d_ptb_all = reinterpret_cast<int*>(base + o_ptb);
         c->d_ptb_off = reinterpret_cast<int*>(base + o_poff);
-        c->d_x2b_all = reinterpret_cast<double*>(base + o_x2b);
+        c->d_ptab_all = reinterpret_cast<double*>(base + o_ptab);
+        c->d_ptab_off = reinterpret_cast<int*>(base + o_toff);
         c->d_kappa_all = reinterpret_cast<uint8_t*>(base + o_kap);
     }
     int nmax = 1;
@@ -1300,6 +1416,7 @@ namespace {
 
 int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const std::vector<int>& new_cell_level) {
     const int n = c->mesh.n_cells;
+    Marks mk;
     // keep the old level set alive for the remap
     std::vector<std::unique_ptr<Level>> old = std::move(c->levels);
     std::vector<int> old_level = c->cell_level, old_slot = c->cell_slot;
@@ -1309,7 +1426,7 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
     assign_slots(c);
     // one staged block: the new levels' geometry (kept with the level set) and
     // the remap's descriptors, tables and work list
-    Stage stg;
+    Stage stg(c->stage_install, c->stage_install_cap);
     struct GeoOff { size_t x, y, w, ptb, xy; };
     std::vector<GeoOff> geo;
     for (auto& L : c->levels) {
@@ -1318,6 +1435,7 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
                        stg.put(xy_pairs(*L))});
         alloc_state(c, *L);
     }
+    mk.mark("install: free items, state", c->st);
     std::vector<RemapItem> items(n);
     std::map<std::pair<int, int>, TabOff> tabs;
     std::vector<TabOff> item_tab(n);
@@ -1347,7 +1465,7 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
     const size_t o_od = stg.put(nullptr, sizeof(LevelDesc) * old.size());
     const size_t o_nd = stg.put(nullptr, sizeof(LevelDesc) * c->levels.size());
     const size_t o_items = stg.put(nullptr, sizeof(RemapItem) * n);
-    char* base = static_cast<char*>(c->dm.alloc(stg.buf.size()));
+    char* base = static_cast<char*>(c->dm.alloc(stg.size));
     for (size_t l = 0; l < c->levels.size(); ++l) {
         Level& L = *c->levels[l];
         L.d_x = reinterpret_cast<double*>(base + geo[l].x);
@@ -1378,16 +1496,20 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
     stg.fill(o_od, descs_of(old));
     stg.fill(o_nd, descs_of(c->levels));
     stg.fill(o_items, items);
-    hip_check(hipMemcpyAsync(base, stg.buf.data(), stg.buf.size(), hipMemcpyHostToDevice, c->st), "upload");
+    stg.upload(base, c->st);
+    mk.mark("install: remap tables", c->st);
     hip_check(launch_remap(c->prec, c->st, reinterpret_cast<LevelDesc*>(base + o_od),
                            reinterpret_cast<LevelDesc*>(base + o_nd), reinterpret_cast<RemapItem*>(base + o_items), n,
                            c->ph, c->d_neg), "remap launch");
     sync(c);
+    mk.mark("install: remap kernel", c->st);
     for (auto& L : old) free_level(c, *L);
     c->dm.release(c->levels_block);            // the old level set's geometry block
     c->levels_block = base;
+    mk.mark("install: free old levels", c->st);
     build_items(c);
     sync(c);
+    mk.mark("install: build_items", c->st);
     c->mom_valid = false;
     c->prep_valid = false;
     return changed;
@@ -1406,9 +1528,9 @@ void run_criterion(mlvs_ctx c) {
     if (!c->d_kcell) c->d_kcell = static_cast<uint8_t*>(c->dm.alloc((size_t)n * Nb));
     if (!c->d_hash) c->d_hash = static_cast<unsigned long long*>(c->dm.alloc(sizeof(unsigned long long) * n));
     hip_check(launch_criterion(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_ptb_all, c->d_ptb_off,
-                               c->d_x2b_all, c->d_kappa_all, c->d_bx, c->d_by, c->d_bw, c->d_axes, c->base.nx, c->base.ny,
-                               c->ap.C_split,
-                               c->ap.C_merge, c->ap.eps_merge, c->ap.flux_test, c->d_kcell, c->d_hash),
+                               c->d_ptab_all, c->d_ptab_off, c->d_kappa_all, c->d_ctab, c->d_axes, c->base.nx,
+                               c->base.ny, c->ap.C_split, c->ap.C_merge, c->ap.eps_merge, c->ap.flux_test, c->d_kcell,
+                               c->d_hash),
               "criterion launch");
 }
 
@@ -1683,14 +1805,26 @@ void cluster(int Nb, double tau, const uint8_t* uniq, const std::vector<int>& fi
 
 void adapt_learned(mlvs_ctx c, mlvs_adapt_report* rep);
 
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
 void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
+    auto t0 = std::chrono::steady_clock::now();
     run_criterion(c);
+    sync(c);
+    const double ms_crit = ms_since(t0);
+    t0 = std::chrono::steady_clock::now();
     const uint8_t* uniq = nullptr;
     std::vector<int> first, uidx, level_of_u;
     std::vector<int64_t> count;
     dedupe(c, uniq, first, count, uidx);
+    const double ms_dedupe = ms_since(t0);
+    t0 = std::chrono::steady_clock::now();
     std::vector<std::vector<uint8_t>> reps;
     cluster(c->base.Nb, c->ap.tau_clust, uniq, first, count, reps, level_of_u);
+    const double ms_cluster = ms_since(t0);
+    t0 = std::chrono::steady_clock::now();
     std::vector<int> cl(c->mesh.n_cells);
     for (int i = 0; i < c->mesh.n_cells; ++i) cl[i] = level_of_u[uidx[i]];
     // the same catalogue in the same order and the same assignment: nothing to
@@ -1703,9 +1837,14 @@ void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
         for (auto& k : reps) nl.push_back(level_of_mask(c, k));
         changed = install_levels(c, std::move(nl), cl);
     }
+    const double ms_install = ms_since(t0);
     c->last_unique = (int64_t)first.size();
     ++c->cnt_adapt;
     if (rep) {
+        rep->ms_criterion = ms_crit;
+        rep->ms_dedupe = ms_dedupe;
+        rep->ms_cluster = ms_cluster;
+        rep->ms_install = ms_install;
         rep->n_levels = (int)c->levels.size();
         rep->n_unique = c->last_unique;
         rep->n_changed = changed;
@@ -1772,8 +1911,9 @@ void adapt_learned(mlvs_ctx c, mlvs_adapt_report* rep) {
         if (!c->d_hash) c->d_hash = static_cast<unsigned long long*>(c->dm.alloc(sizeof(unsigned long long) * n));
         int* d_list = upload(c->dm, rej, c->st);
         hip_check(launch_criterion(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, (int)rej.size(),
-                                   c->d_ptb_all, c->d_ptb_off, c->d_x2b_all, c->d_kappa_all, c->d_bx, c->d_by, c->d_bw,
-                                   c->d_axes, c->base.nx, c->base.ny, c->ap.C_split, c->ap.C_merge, c->ap.eps_merge,
+                                   c->d_ptb_all, c->d_ptb_off, c->d_ptab_all, c->d_ptab_off, c->d_kappa_all,
+                                   c->d_ctab, c->d_axes, c->base.nx, c->base.ny, c->ap.C_split, c->ap.C_merge,
+                                   c->ap.eps_merge,
                                    c->ap.flux_test, c->d_kcell, c->d_hash, d_list), "criterion launch");
         std::vector<int> order = level_order(c);
         int* d_order = upload(c->dm, order, c->st);
@@ -2303,6 +2443,8 @@ static mlvs_status create_impl(const mlvs_physics* phys, const mlvs_mesh* mesh, 
         c->d_by = upload(c->dm, B.y, c->st);
         c->d_bw = upload(c->dm, B.w, c->st);
         c->d_axes = upload(c->dm, B.axes, c->st);
+        block_tables(B);
+        c->d_ctab = upload(c->dm, B.ctab, c->st);
         std::vector<BCDev> bd;
         for (auto& b : c->bcs) bd.push_back(BCDev{b.kind, 0, b.rho, b.u, b.v, b.T});
         c->d_bcs = upload(c->dm, bd, c->st);
@@ -2360,6 +2502,8 @@ void mlvs_destroy(mlvs_ctx c) {
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->side_st) (void)hipStreamDestroy(c->side_st);
     c->dm.release_all();
+    if (c->stage_items) (void)hipHostFree(c->stage_items);
+    if (c->stage_install) (void)hipHostFree(c->stage_install);
     delete c;
 }
 
@@ -2408,6 +2552,16 @@ mlvs_status mlvs_step(mlvs_ctx c, int n_steps) {
                      "corrections did not converge during this call",
                      neg1[0] - neg0[0], neg1[2] - neg0[2]);
         }
+    });
+}
+
+mlvs_status mlvs_set_adapt(mlvs_ctx c, const mlvs_adapt_params* adapt) {
+    return guarded([&] {
+        if (!c || !adapt) fail(MLVS_E_ARG, "null argument");
+        if (!c->adaptive) fail(MLVS_E_STATE, "context was created without adaptation parameters");
+        if (adapt->interval < 0 || adapt->C_merge > adapt->C_split || !(adapt->tau_clust >= 0.0))
+            fail(MLVS_E_ARG, "bad adaptation parameters");
+        c->ap = *adapt;
     });
 }
 
@@ -2790,6 +2944,7 @@ mlvs_status mlvs_adapt(mlvs_ctx c, mlvs_adapt_report* rep) {
         if (!c) fail(MLVS_E_ARG, "null context");
         if (!c->adaptive) fail(MLVS_E_STATE, "context was created without adaptation parameters");
         if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
+        if (rep) *rep = mlvs_adapt_report{};
         if (c->sel_K > 0 && c->sel_on) adapt_learned(c, rep);
         else adapt_now(c, rep);
     });

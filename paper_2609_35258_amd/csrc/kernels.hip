@@ -737,11 +737,12 @@ struct MapCoef { double a[6], b[3]; bool nine; };
 constexpr int EXP_MAXIT = 30;
 // Band of the positivity check, relative to max |g^p| of the row: values
 // above -band count as nonnegative.  A tolerance of the check, not a rounding
-// bound: 1e-10 with double rows (two implementations of the step agree far
-// closer than that after many steps); with float rows 1e-6, about sixteen
-// units of float rounding, so that storage rounding alone never decides.
+// bound (two implementations of the step agree far closer than 1e-10 of the
+// row's peak after many steps).  The same band with float rows: a float
+// provisional value is rounded to about 6e-8 of itself, far below the band
+// except where a large provisional value and its correction cancel to near
+// zero.
 constexpr double POS_EPS = 1e-10;
-constexpr double POS_EPS32 = 1e-6;
 template <typename S>
 __device__ bool map_exp(const LevelDesc& D, gptr<S> gdst, gptr<S> hdst, const double* tgt) {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
@@ -859,7 +860,7 @@ __device__ __forceinline__ void map_correct_apply(const LevelDesc& D, gptr<S> gd
             v[2] = fmax(v[2], -(double)(S)((double)gprov + dg));
         }
         wave_max<3>(v);
-        const double eps = (sizeof(S) == 4 ? POS_EPS32 : POS_EPS) * v[0];
+        const double eps = POS_EPS * v[0];
         if (v[1] <= eps && v[2] > eps) {
             negflag = 1;
             const bool ok = map_exp<S>(D, gdst, hdst, tgt);
@@ -2341,94 +2342,241 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
 constexpr int CRIT_AXIS = 512;
 __shared__ double crit_axes[4 * CRIT_AXIS];
 
+// Inheritance (Sec. 3.3.2) gives every base point under a level point p the
+// level point's g and H = h + |xi_p|^2 g.  Every sum the criterion takes over
+// a block of V_base therefore splits into g_p, H_p times sums that depend on
+// the base grid alone: over a block inside one level point, the block's own
+// tables (ctab); over a block the level splits, the sum of its parts, down to
+// single base points.  A cell's row is read once; nothing is expanded to
+// V_base.
+//
+// Base-grid tables per aligned block (scales 1, 2, 3 one after another):
+// W = sum w, the velocity centroid (sum w xi_x, sum w xi_y) / W, P[d][s] =
+// sum_{s xi_d >= 0} w xi_d, Q[d][s][e] = sum_{s xi_d >= 0} w xi_d xi_e
+// (s = 0: +, 1: -).
+enum { CT_W = 0, CT_WX = 1, CT_WY = 2, CT_P = 3, CT_Q = 7, NCT = 15 };
+// Level-point tables: |xi_p|^2, then over the point's base members sum w|x|,
+// sum w|y|, sum w x^2, sum w|x y|, sum w y^2 (the normalisations S_r).
+enum { PT_X2 = 0, PT_AX = 1, PT_AY = 2, PT_BXX = 3, PT_BXY = 4, PT_BYY = 5, NPT = 6 };
+
 struct CritCtx {
     bool axes_lds;            // crit_axes holds the axes
+    const double* axes;       // x [nx], wx [nx], y [ny], wy [ny] (global)
     const int* ptb;           // base -> level point of the cell's level
-    const double* x2b;        // base -> |xi_p|^2 of that level point (read in base order)
-    const uint8_t* prev;      // kappa of the cell's current level
-    const double *bx, *by, *bw;
-    int nx, nbx;
-    double rho_tot, E_tot, S[4];
-    double C_split, C_merge, eps_merge;
+    const double* ptab;       // level-point tables of the cell's level [N][NPT]
+    const uint8_t* klev;      // kappa of the cell's current level
+    const double *T1, *T2, *T3;   // base-grid block tables of scales 1, 2, 3
+    int nx, ny, nbx, n4x, n8x;
+    double merge_rho, merge_E, split_rho, split_E;   // C_merge rho_tot, C_merge E_tot, C_split ...
+    double epsS[4];                                  // eps_merge S_r
     int flux_test;
 };
 
-template <typename S>
-__device__ __forceinline__ bool crit_merges(const CritCtx& cc, const LevelDesc& L, gptr<S> g, gptr<S> h, int s, int bx,
-                                            int by) {
-    const int size = 1 << s;
-    double m1 = 0.0, m2 = 0.0;
-    double Wb = 0.0, Wx = 0.0, Wy = 0.0, Wg = 0.0, WH = 0.0;
-    double Ff[4][2][2];
+// Sums of one block: sum w g, sum w H, and the half-range fluxes
+// F[r][d][s] = sum_{s xi_d >= 0} w xi_d m_r, m = (g, xi_x g, xi_y g, H/2).
+struct CritAcc {
+    double m1, mH, F[4][2][2];
+};
+
+__device__ __forceinline__ void acc_zero(CritAcc& a) {
+    a.m1 = 0.0;
+    a.mH = 0.0;
+#pragma unroll
     for (int r = 0; r < 4; ++r)
-        for (int d = 0; d < 2; ++d) { Ff[r][d][0] = 0.0; Ff[r][d][1] = 0.0; }
-    for (int iy = by * size; iy < by * size + size; ++iy)
-        for (int ix = bx * size; ix < bx * size + size; ++ix) {
-            const int b = ix + cc.nx * iy;
-            const int p = cc.ptb[b];
-            const double gpv = (double)g[p];
-            const double Hb = (double)h[p] + cc.x2b[b] * gpv;
-            double w, x, y;
-            if (cc.axes_lds) {
-                x = crit_axes[ix];
-                y = crit_axes[2 * CRIT_AXIS + iy];
-                w = crit_axes[CRIT_AXIS + ix] * crit_axes[3 * CRIT_AXIS + iy];
-            } else {
-                w = cc.bw[b]; x = cc.bx[b]; y = cc.by[b];
-            }
-            m1 += w * gpv;
-            m2 += 0.5 * w * Hb;
-            if (cc.flux_test) {
-                Wb += w; Wx += w * x; Wy += w * y; Wg += w * gpv; WH += w * Hb;
-                const double mr[4] = {gpv, x * gpv, y * gpv, 0.5 * Hb};
-                const double xd[2] = {x, y};
-                for (int d = 0; d < 2; ++d)
-                    for (int r = 0; r < 4; ++r) {
-                        const double t = w * xd[d] * mr[r];
-                        if (xd[d] >= 0) Ff[r][d][0] += t;
-                        if (-xd[d] >= 0) Ff[r][d][1] += t;
-                    }
+#pragma unroll
+        for (int d = 0; d < 2; ++d) { a.F[r][d][0] = 0.0; a.F[r][d][1] = 0.0; }
+}
+
+// A block inside one level point: g and H times the block's tables (FULL:
+// also the half-range fluxes).
+template <bool FULL>
+__device__ __forceinline__ void acc_table(CritAcc& a, double gv, double Hv, const double* T) {
+    a.m1 += gv * T[CT_W];
+    a.mH += Hv * T[CT_W];
+    if (!FULL) return;
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            const double P = T[CT_P + 2 * d + sg];
+            a.F[0][d][sg] += gv * P;
+            a.F[1][d][sg] += gv * T[CT_Q + 4 * d + 2 * sg];
+            a.F[2][d][sg] += gv * T[CT_Q + 4 * d + 2 * sg + 1];
+            a.F[3][d][sg] += 0.5 * Hv * P;
+        }
+}
+
+// One base point (ix, iy) carrying g and H.
+template <bool FULL>
+__device__ __forceinline__ void acc_base(CritAcc& a, const CritCtx& cc, double gv, double Hv, int ix, int iy) {
+    double w, x, y;
+    if (cc.axes_lds) {
+        x = crit_axes[ix];
+        y = crit_axes[2 * CRIT_AXIS + iy];
+        w = crit_axes[CRIT_AXIS + ix] * crit_axes[3 * CRIT_AXIS + iy];
+    } else {
+        x = cc.axes[ix];
+        y = cc.axes[2 * cc.nx + iy];
+        w = cc.axes[cc.nx + ix] * cc.axes[2 * cc.nx + cc.ny + iy];
+    }
+    a.m1 += w * gv;
+    a.mH += w * Hv;
+    if (!FULL) return;
+    const double xd[2] = {x, y};
+    const double mr[4] = {gv, x * gv, y * gv, 0.5 * Hv};
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        const double t = w * xd[d];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double v = t * mr[r];
+            if (xd[d] >= 0) a.F[r][d][0] += v;
+            if (-xd[d] >= 0) a.F[r][d][1] += v;
+        }
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ void crit_gh(const CritCtx& cc, gptr<S> g, gptr<S> h, int b, double& gv, double& Hv) {
+    const int p = cc.ptb[b];
+    gv = (double)g[p];
+    Hv = (double)h[p] + cc.ptab[(size_t)p * NPT + PT_X2] * gv;
+}
+
+template <typename S, bool FULL>
+__device__ __forceinline__ void crit_sum2(CritAcc& a, const CritCtx& cc, gptr<S> g, gptr<S> h, int X, int Y) {
+    // every load of the block is issued before its value is needed (the
+    // level's mask decides afterwards whether the block is one point or four):
+    // two dependent load steps instead of three
+    const int b0 = 2 * X + cc.nx * 2 * Y;
+    const int kb = cc.klev[X + cc.nbx * Y];
+    int p[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] = cc.ptb[b0 + (q & 1) + cc.nx * (q >> 1)];
+    double gv[4], Hv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        gv[q] = (double)g[p[q]];
+        Hv[q] = (double)h[p[q]] + cc.ptab[(size_t)p[q] * NPT + PT_X2] * gv[q];
+    }
+    if (kb >= 1) {
+        acc_table<FULL>(a, gv[0], Hv[0], cc.T1 + (size_t)(X + cc.nbx * Y) * NCT);
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc_base<FULL>(a, cc, gv[q], Hv[q], 2 * X + (q & 1), 2 * Y + (q >> 1));
+}
+
+template <typename S, bool FULL>
+__device__ __forceinline__ void crit_sum4(CritAcc& a, const CritCtx& cc, gptr<S> g, gptr<S> h, int X, int Y) {
+    if (cc.klev[2 * X + cc.nbx * 2 * Y] >= 2) {
+        double gv, Hv;
+        crit_gh<S>(cc, g, h, 4 * X + cc.nx * 4 * Y, gv, Hv);
+        acc_table<FULL>(a, gv, Hv, cc.T2 + (size_t)(X + cc.n4x * Y) * NCT);
+        return;
+    }
+    for (int k = 0; k < 4; ++k) crit_sum2<S, FULL>(a, cc, g, h, 2 * X + (k & 1), 2 * Y + (k >> 1));
+}
+
+template <typename S, bool FULL>
+__device__ __forceinline__ void crit_sum8(CritAcc& a, const CritCtx& cc, gptr<S> g, gptr<S> h, int X, int Y) {
+    if (cc.klev[4 * X + cc.nbx * 4 * Y] >= 3) {
+        double gv, Hv;
+        crit_gh<S>(cc, g, h, 8 * X + cc.nx * 8 * Y, gv, Hv);
+        acc_table<FULL>(a, gv, Hv, cc.T3 + (size_t)(X + cc.n8x * Y) * NCT);
+        return;
+    }
+    for (int k = 0; k < 4; ++k) crit_sum4<S, FULL>(a, cc, g, h, 2 * X + (k & 1), 2 * Y + (k >> 1));
+}
+
+template <typename S, bool FULL>
+__device__ __forceinline__ void crit_sum(CritAcc& a, const CritCtx& cc, gptr<S> g, gptr<S> h, int s, int X, int Y) {
+    acc_zero(a);
+    if (s == 3) crit_sum8<S, FULL>(a, cc, g, h, X, Y);
+    else if (s == 2) crit_sum4<S, FULL>(a, cc, g, h, X, Y);
+    else crit_sum2<S, FULL>(a, cc, g, h, X, Y);
+}
+
+// The transport-error test of Eqs. merge-transport-error and
+// combined-merge-condition for a block with full sums a and tables T:
+// max_r |F_fine - F_merged| / S_r <= eps_merge, evaluated as |F_fine -
+// F_merged| <= eps_merge S_r.  The merged point (w_B, xi_B, g_B, H_B) gives
+// F_merged = w_B xi_B,d m_r(B) = xi_B,d (m1, xi_B,x m1, xi_B,y m1, mH/2) on
+// its half-range, with m1 = sum w g and mH = sum w H of the block.
+__device__ __forceinline__ bool crit_flux_ok(const CritCtx& cc, const CritAcc& a, const double* T) {
+    const double xB = T[CT_WX], yB = T[CT_WY];      // the block's velocity centroid
+    const double mB[4] = {a.m1, xB * a.m1, yB * a.m1, 0.5 * a.mH};
+    const double xdB[2] = {xB, yB};
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            const bool on = (sg == 0) ? (xdB[d] >= 0) : (-xdB[d] >= 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double Fm = on ? xdB[d] * mB[r] : 0.0;
+                ok = ok && fabs(a.F[r][d][sg] - Fm) <= cc.epsS[r];
             }
         }
-    const double I = fmax(m1 / cc.rho_tot, m2 / cc.E_tot);
-    bool prev_merged = true;
-    const int csz = size >> 1;
-    for (int cy = by * csz; cy < by * csz + csz; ++cy)
-        for (int cx = bx * csz; cx < bx * csz + csz; ++cx)
-            if (cc.prev[cx + cc.nbx * cy] < s) prev_merged = false;
-    bool cand = (I < cc.C_merge) || (cc.C_merge <= I && I <= cc.C_split && prev_merged);
+    return ok;
+}
+
+// The indicator part of the merge test (Eqs. block-contribution-indicator,
+// block-hysteresis-rule) from the block's mass and energy sums:
+// I = max(m1 / rho_tot, mH / (2 E_tot)) against C_merge and C_split, as
+// products with the totals; prev_merged holds when the cell's current level
+// merges the block (for a consistent mask, when its first 2x2 child c2 has
+// kappa >= s).
+__device__ __forceinline__ bool crit_candidate(const CritCtx& cc, double m1, double mH, int s, int c2) {
+    const double e = 0.5 * mH;
+    const bool below_merge = m1 < cc.merge_rho && e < cc.merge_E;
+    const bool below_split = m1 <= cc.split_rho && e <= cc.split_E;
+    const bool prev_merged = cc.klev[c2] >= s;
+    return below_merge || (below_split && prev_merged);
+}
+
+// The whole merge test of one block, summed from the level's points (the
+// top-level blocks outside the 8x8 lattice).  The sixteen half-range fluxes
+// are summed in a second pass, for candidates only.
+template <typename S>
+__device__ __forceinline__ bool crit_test(const CritCtx& cc, gptr<S> g, gptr<S> h, int s, int X, int Y) {
+    const double* T = (s == 3 ? cc.T3 + (size_t)(X + cc.n8x * Y) * NCT
+                       : s == 2 ? cc.T2 + (size_t)(X + cc.n4x * Y) * NCT : cc.T1 + (size_t)(X + cc.nbx * Y) * NCT);
+    const int c2 = (X << (s - 1)) + cc.nbx * (Y << (s - 1));
+    CritAcc a;
+    crit_sum<S, false>(a, cc, g, h, s, X, Y);
+    bool cand = crit_candidate(cc, a.m1, a.mH, s, c2);
     if (cand && cc.flux_test) {
-        const double xB = Wx / Wb, yB = Wy / Wb, gB = Wg / Wb, HB = WH / Wb;
-        const double mB[4] = {gB, xB * gB, yB * gB, 0.5 * HB};
-        const double xdB[2] = {xB, yB};
-        double err = 0.0;
-        for (int d = 0; d < 2; ++d)
-            for (int sg = 0; sg < 2; ++sg) {
-                const bool on = (sg == 0) ? (xdB[d] >= 0) : (-xdB[d] >= 0);
-                for (int r = 0; r < 4; ++r) {
-                    const double Fm = on ? Wb * xdB[d] * mB[r] : 0.0;
-                    err = fmax(err, fabs(Ff[r][d][sg] - Fm) / cc.S[r]);
-                }
-            }
-        cand = err <= cc.eps_merge;
+        crit_sum<S, true>(a, cc, g, h, s, X, Y);
+        cand = crit_flux_ok(cc, a, T);
     }
     return cand;
 }
 
+// Sum of a value over the four lanes of an aligned group of four, in lane
+// order (the same on all four lanes).
+__device__ __forceinline__ double group4_sum(double v) {
+    const int base = lane_id() & ~3;
+    const double v0 = __shfl(v, base, WL), v1 = __shfl(v, base + 1, WL);
+    const double v2 = __shfl(v, base + 2, WL), v3 = __shfl(v, base + 3, WL);
+    return (v0 + v1) + (v2 + v3);
+}
+
 template <typename S>
-__global__ __launch_bounds__(BS, 4) void k_criterion(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
+__global__ __launch_bounds__(BS, 2) void k_criterion(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
                                                   const int* __restrict__ cell_slot, int n_cells,
                                                   const int* __restrict__ ptb_all, const int* __restrict__ ptb_off,
-                                                  const double* __restrict__ x2b_all,
-                                                  const uint8_t* __restrict__ kappa_all, const double* __restrict__ bx,
-                                                  const double* __restrict__ by, const double* __restrict__ bw,
-                                                  const double* __restrict__ axes,
+                                                  const double* __restrict__ ptab_all,
+                                                  const int* __restrict__ ptab_off,
+                                                  const uint8_t* __restrict__ kappa_all,
+                                                  const double* __restrict__ ctab, const double* __restrict__ axes,
                                                   int nx, int ny, double C_split, double C_merge, double eps_merge,
                                                   int flux_test, uint8_t* __restrict__ kout,
                                                   unsigned long long* __restrict__ hout,
                                                   const int* __restrict__ cell_list) {
-    const int nbx = nx / 2, nby = ny / 2, Nb = nbx * nby, Nbase = nx * ny;
-    const bool axes_lds = axes != nullptr && nx <= CRIT_AXIS && ny <= CRIT_AXIS;
+    const int nbx = nx / 2, nby = ny / 2, Nb = nbx * nby;
+    const bool axes_lds = nx <= CRIT_AXIS && ny <= CRIT_AXIS;
     if (axes_lds) {
         for (int i = threadIdx.x; i < nx; i += blockDim.x) {
             crit_axes[i] = axes[i];
@@ -2450,84 +2598,191 @@ __global__ __launch_bounds__(BS, 4) void k_criterion(const LevelDesc* __restrict
         auto h = rowp<S>(L.h, row);
         CritCtx cc;
         cc.axes_lds = axes_lds;
+        cc.axes = axes;
         cc.ptb = ptb_all + (size_t)ptb_off[lev];
-        cc.x2b = x2b_all + (size_t)ptb_off[lev];
-        cc.prev = kappa_all + (size_t)lev * Nb;
-        cc.bx = bx; cc.by = by; cc.bw = bw; cc.nx = nx; cc.nbx = nbx;
-        cc.C_split = C_split; cc.C_merge = C_merge; cc.eps_merge = eps_merge; cc.flux_test = flux_test;
+        cc.ptab = ptab_all + (size_t)ptab_off[lev] * NPT;
+        cc.klev = kappa_all + (size_t)lev * Nb;
+        cc.T1 = ctab;
+        cc.T2 = ctab + (size_t)Nb * NCT;
+        cc.T3 = cc.T2 + (size_t)n4x * n4y * NCT;
+        cc.nx = nx; cc.ny = ny; cc.nbx = nbx; cc.n4x = n4x; cc.n8x = n8x;
+        cc.flux_test = flux_test;
+        // totals and normalisations over the level's points (Eq. M2; S_r)
         double t[10];
 #pragma unroll
         for (int k = 0; k < 10; ++k) t[k] = 0.0;
-        for (int b = lane_id(); b < Nbase; b += WL) {
-            const int p = cc.ptb[b];
-            const double gpv = (double)g[p];
-            const double Hb = (double)h[p] + cc.x2b[b] * gpv;
-            const double w = bw[b], x = bx[b], y = by[b];
-            t[0] += w * gpv;
-            t[1] += 0.5 * w * Hb;
-            const double mr[4] = {fabs(gpv), fabs(x * gpv), fabs(y * gpv), fabs(0.5 * Hb)};
-            for (int r = 0; r < 4; ++r) {
-                t[2 + r] += w * fabs(x) * mr[r];
-                t[6 + r] += w * fabs(y) * mr[r];
-            }
+        for (int p = lane_id(); p < L.N; p += WL) {
+            const double* pt = cc.ptab + (size_t)p * NPT;
+            const double gv = (double)g[p];
+            const double Hv = (double)h[p] + pt[PT_X2] * gv;
+            const double w = gp(L.w)[p];
+            t[0] += w * gv;
+            t[1] += 0.5 * w * Hv;
+            const double ag = fabs(gv), aH = 0.5 * fabs(Hv);
+            t[2] += ag * pt[PT_AX];
+            t[3] += ag * pt[PT_BXX];
+            t[4] += ag * pt[PT_BXY];
+            t[5] += aH * pt[PT_AX];
+            t[6] += ag * pt[PT_AY];
+            t[7] += ag * pt[PT_BXY];
+            t[8] += ag * pt[PT_BYY];
+            t[9] += aH * pt[PT_AY];
         }
         wave_sum<10>(t);
-        cc.rho_tot = t[0];
-        cc.E_tot = t[1];
-        for (int r = 0; r < 4; ++r) cc.S[r] = fmax(t[2 + r], t[6 + r]);
+        cc.merge_rho = C_merge * t[0];
+        cc.merge_E = C_merge * t[1];
+        cc.split_rho = C_split * t[0];
+        cc.split_E = C_split * t[1];
+        for (int r = 0; r < 4; ++r) cc.epsS[r] = eps_merge * fmax(t[2 + r], t[6 + r]);
         uint8_t* ko = kout + (size_t)c * Nb;
-        // top-level candidates: eligible 8x8 blocks, then 4x4 and 2x2 blocks outside them
+        // Eligible 8x8 blocks, sixteen at a time: four lanes per 8x8 block,
+        // one per 4x4 quarter.  A lane keeps the mass and energy sums of its
+        // quarter's four 2x2 blocks; the quarter's sums are theirs added in
+        // order, the 8x8 block's the four quarters' added in lane order.  The
+        // tests then run coarse to fine (Sec. 3.2): the 8x8 block on all four
+        // lanes, else each quarter on its lane, else the quarter's 2x2 blocks.
         const int n8 = n8x * n8y;
+        for (int t8 = 0; t8 < n8; t8 += WL / 4) {
+            const int tb = t8 + (lane_id() >> 2), k = lane_id() & 3;
+            const bool act = tb < n8;                     // group-uniform
+            const int X8 = act ? tb % n8x : 0, Y8 = act ? tb / n8x : 0;
+            const int X4 = 2 * X8 + (k & 1), Y4 = 2 * Y8 + (k >> 1);
+            const int c4 = 2 * X4 + nbx * 2 * Y4;         // first 2x2 block of the quarter
+            const int k8 = cc.klev[4 * X8 + nbx * 4 * Y8];
+            const int k4 = cc.klev[c4];
+            const double* T2q = cc.T2 + (size_t)(X4 + n4x * Y4) * NCT;
+            const double* T3b = cc.T3 + (size_t)(X8 + n8x * Y8) * NCT;
+            // a quarter inside one level point: its sums from its own tables
+            double gq = 0.0, Hq = 0.0;
+            if (k4 >= 2) crit_gh<S>(cc, g, h, 4 * X4 + nx * 4 * Y4, gq, Hq);
+            double c1[4], cH[4], q1, qH;
+            if (k4 >= 2) {
+                q1 = gq * T2q[CT_W];
+                qH = Hq * T2q[CT_W];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) { c1[j] = 0.0; cH[j] = 0.0; }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    CritAcc a;
+                    acc_zero(a);
+                    crit_sum2<S, false>(a, cc, g, h, 2 * X4 + (j & 1), 2 * Y4 + (j >> 1));
+                    c1[j] = a.m1;
+                    cH[j] = a.mH;
+                }
+                q1 = (c1[0] + c1[1]) + (c1[2] + c1[3]);
+                qH = (cH[0] + cH[1]) + (cH[2] + cH[3]);
+            }
+            // the 8x8 block's sums: its own tables inside one level point,
+            // else the four quarters' sums in lane order
+            double e1 = group4_sum(q1), eH = group4_sum(qH);
+            if (k8 >= 3) {
+                e1 = gq * T3b[CT_W];
+                eH = Hq * T3b[CT_W];
+            }
+            if (!act) continue;
+            bool m8 = crit_candidate(cc, e1, eH, 3, 4 * X8 + nbx * 4 * Y8);
+            if (m8 && cc.flux_test) {
+                CritAcc a;
+                acc_zero(a);
+                if (k8 >= 3) {
+                    acc_table<true>(a, gq, Hq, T3b);
+                } else {
+                    if (k4 >= 2) acc_table<true>(a, gq, Hq, T2q);
+                    else
+#pragma unroll 1
+                        for (int j = 0; j < 4; ++j)
+                            crit_sum2<S, true>(a, cc, g, h, 2 * X4 + (j & 1), 2 * Y4 + (j >> 1));
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int d = 0; d < 2; ++d)
+#pragma unroll
+                            for (int sg = 0; sg < 2; ++sg) a.F[r][d][sg] = group4_sum(a.F[r][d][sg]);
+                }
+                a.m1 = e1;
+                a.mH = eH;
+                m8 = crit_flux_ok(cc, a, T3b);
+            }
+            uint8_t* q0 = ko + c4;
+            if (m8) {
+                q0[0] = q0[1] = q0[nbx] = q0[nbx + 1] = 3;
+                continue;
+            }
+            // the lane's 4x4 quarter
+            bool m4 = crit_candidate(cc, q1, qH, 2, c4);
+            if (m4 && cc.flux_test) {
+                CritAcc a;
+                acc_zero(a);
+                if (k4 >= 2) acc_table<true>(a, gq, Hq, T2q);
+                else
+#pragma unroll 1
+                    for (int j = 0; j < 4; ++j) crit_sum2<S, true>(a, cc, g, h, 2 * X4 + (j & 1), 2 * Y4 + (j >> 1));
+                a.m1 = q1;
+                a.mH = qH;
+                m4 = crit_flux_ok(cc, a, T2q);
+            }
+            if (m4) {
+                q0[0] = q0[1] = q0[nbx] = q0[nbx + 1] = 2;
+                continue;
+            }
+            // its 2x2 blocks (inside one level point: their sums from their tables)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int X2 = 2 * X4 + (j & 1), Y2 = 2 * Y4 + (j >> 1);
+                const double* T1c = cc.T1 + (size_t)(X2 + nbx * Y2) * NCT;
+                if (k4 >= 2) {
+                    c1[j] = gq * T1c[CT_W];
+                    cH[j] = Hq * T1c[CT_W];
+                }
+                bool m2 = crit_candidate(cc, c1[j], cH[j], 1, X2 + nbx * Y2);
+                if (m2 && cc.flux_test) {
+                    CritAcc a;
+                    acc_zero(a);
+                    if (k4 >= 2) acc_table<true>(a, gq, Hq, T1c);
+                    else crit_sum2<S, true>(a, cc, g, h, X2, Y2);
+                    a.m1 = c1[j];
+                    a.mH = cH[j];
+                    m2 = crit_flux_ok(cc, a, T1c);
+                }
+                ko[X2 + nbx * Y2] = m2 ? (uint8_t)1 : (uint8_t)0;
+            }
+        }
+        // top-level 4x4 blocks outside the 8x8 lattice, then 2x2 blocks outside
+        // the 4x4 lattice (odd block counts): one lane per block
         const int n4rest = n4x * n4y - (2 * n8x) * (2 * n8y);
         const int n2rest = nbx * nby - (2 * n4x) * (2 * n4y);
-        const int ntop = n8 + n4rest + n2rest;
-        for (int tb = lane_id(); tb < ntop; tb += WL) {
-            int s0, X0, Y0;
-            if (tb < n8) { s0 = 3; X0 = tb % n8x; Y0 = tb / n8x; }
-            else if (tb < n8 + n4rest) {
-                int k = tb - n8, cnt = 0;
-                s0 = 2; X0 = Y0 = 0;
+        for (int tb = lane_id(); tb < n4rest + n2rest; tb += WL) {
+            int s0, X0 = 0, Y0 = 0;
+            if (tb < n4rest) {
+                int k = tb, cnt = 0;
+                s0 = 2;
                 for (int qy = 0; qy < n4y; ++qy)
                     for (int qx = 0; qx < n4x; ++qx) {
                         if (qx < 2 * n8x && qy < 2 * n8y) continue;
                         if (cnt++ == k) { X0 = qx; Y0 = qy; qy = n4y; break; }
                     }
             } else {
-                int k = tb - n8 - n4rest, cnt = 0;
-                s0 = 1; X0 = Y0 = 0;
+                int k = tb - n4rest, cnt = 0;
+                s0 = 1;
                 for (int yy = 0; yy < nby; ++yy)
                     for (int xx = 0; xx < nbx; ++xx) {
                         if (xx < 2 * n4x && yy < 2 * n4y) continue;
                         if (cnt++ == k) { X0 = xx; Y0 = yy; yy = nby; break; }
                     }
             }
-            // coarse to fine (at most 1 + 4 + 16 tests): a block that merges sets
-            // its 2x2 blocks, one that does not is split into its four children.
-            // Written as nested loops rather than a stack, so that every test
-            // has a constant block size and nothing lives in scratch memory.
-            auto fill = [&](int s, int X, int Y, uint8_t v) {
-                const int csz = 1 << (s - 1);
-                for (int cy = Y * csz; cy < Y * csz + csz; ++cy)
-                    for (int cx = X * csz; cx < X * csz + csz; ++cx) ko[cx + nbx * cy] = v;
-            };
-            auto test2 = [&](int X, int Y) {
-                ko[X + nbx * Y] = crit_merges<S>(cc, L, g, h, 1, X, Y) ? (uint8_t)1 : (uint8_t)0;
-            };
-            auto test4 = [&](int X, int Y) {
-                if (crit_merges<S>(cc, L, g, h, 2, X, Y)) {
-                    fill(2, X, Y, 2);
-                    return;
+            if (s0 == 2) {
+                uint8_t* q0 = ko + 2 * X0 + nbx * 2 * Y0;
+                if (crit_test<S>(cc, g, h, 2, X0, Y0)) {
+                    q0[0] = q0[1] = q0[nbx] = q0[nbx + 1] = 2;
+                } else {
+                    for (int j = 0; j < 4; ++j) {
+                        const int X2 = 2 * X0 + (j & 1), Y2 = 2 * Y0 + (j >> 1);
+                        ko[X2 + nbx * Y2] = crit_test<S>(cc, g, h, 1, X2, Y2) ? (uint8_t)1 : (uint8_t)0;
+                    }
                 }
-                for (int k = 0; k < 4; ++k) test2(2 * X + (k & 1), 2 * Y + (k >> 1));
-            };
-            if (s0 == 3) {
-                if (crit_merges<S>(cc, L, g, h, 3, X0, Y0)) fill(3, X0, Y0, 3);
-                else
-                    for (int k = 0; k < 4; ++k) test4(2 * X0 + (k & 1), 2 * Y0 + (k >> 1));
-            } else if (s0 == 2) {
-                test4(X0, Y0);
             } else {
-                test2(X0, Y0);
+                ko[X0 + nbx * Y0] = crit_test<S>(cc, g, h, 1, X0, Y0) ? (uint8_t)1 : (uint8_t)0;
             }
         }
         __threadfence_block();
@@ -2565,14 +2820,13 @@ hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFa
 }
 
 hipError_t launch_criterion(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
-                            int n_cells, const int* pt_of_base_all, const int* pt_off, const double* x2_of_base_all,
-                            const uint8_t* kappa_all,
-                            const double* bxi_x, const double* bxi_y, const double* bw, const double* axes, int nx,
-                            int ny, double C_split, double C_merge, double eps_merge, int flux_test, uint8_t* kappa_out,
-                            unsigned long long* hash_out, const int* cell_list) {
+                            int n_cells, const int* pt_of_base_all, const int* pt_off, const double* ptab_all,
+                            const int* ptab_off, const uint8_t* kappa_all, const double* ctab, const double* axes,
+                            int nx, int ny, double C_split, double C_merge, double eps_merge, int flux_test,
+                            uint8_t* kappa_out, unsigned long long* hash_out, const int* cell_list) {
     if (n_cells <= 0) return hipSuccess;
     MLVS_DISPATCH(prec, k_criterion, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
-                  pt_of_base_all, pt_off, x2_of_base_all, kappa_all, bxi_x, bxi_y, bw, axes, nx, ny, C_split, C_merge,
+                  pt_of_base_all, pt_off, ptab_all, ptab_off, kappa_all, ctab, axes, nx, ny, C_split, C_merge,
                   eps_merge, flux_test, kappa_out, hash_out, cell_list);
     return hipGetLastError();
 }

@@ -161,11 +161,15 @@ hipError_t launch_check_state(hipStream_t st, const LevelDesc* lv, const int* ce
                               const double* cmom, int CH, unsigned long long* rec);
 hipError_t launch_remap(int prec, hipStream_t st, const LevelDesc* old_lv, const LevelDesc* new_lv,
                         const RemapItem* items, int n, Phys ph, unsigned long long* neg);
+// Criterion (Sec. 3.2).  ptab_all: per level point [|xi_p|^2, sum w|x|, sum
+// w|y|, sum w x^2, sum w|xy|, sum w y^2] over its base members, levels one
+// after another (ptab_off: first point of each level); ctab: per aligned
+// block of scales 1, 2, 3 of the base grid [W, Wx, Wy, P[2][2], Q[2][2][2]]
+// (see kernels.hip); axes: x [nx], wx [nx], y [ny], wy [ny].
 hipError_t launch_criterion(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev,
                             const int* cell_slot, int n_cells, const int* pt_of_base_all,
-                            const int* pt_off, const double* x2_of_base_all, const uint8_t* kappa_all,
-                            const double* bxi_x,
-                            const double* bxi_y, const double* bw, const double* axes, int nx, int ny,
+                            const int* pt_off, const double* ptab_all, const int* ptab_off,
+                            const uint8_t* kappa_all, const double* ctab, const double* axes, int nx, int ny,
                             double C_split, double C_merge, double eps_merge, int flux_test,
                             uint8_t* kappa_out, unsigned long long* hash_out, const int* cell_list = nullptr);
 hipError_t launch_gather_rows_u8(hipStream_t st, const uint8_t* src, int width, const int* rows, int n,
