@@ -141,6 +141,9 @@ _PROTOS = {
                                       ctypes.POINTER(mlvs_train_cfg), ctypes.POINTER(mlvs_train_report)]),
     "mlvs_mlp_eval": (ctypes.c_int, [_c_float_p, ctypes.c_int, _c_float_p, _c_int32_p, ctypes.c_int, _c_float_p,
                                      _c_float_p, _c_double_p]),
+    "mlvs_mlp_eval_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
     "mlvs_mlp_predict": (ctypes.c_int, [_c_float_p, ctypes.c_int, _c_float_p, ctypes.c_int, ctypes.c_int,
                                         _c_int32_p, _c_float_p]),
     "mlvs_selector_set": (ctypes.c_int, [ctypes.c_void_p, _c_float_p, ctypes.c_int]),
@@ -232,6 +235,11 @@ def mlp_eval(params, K, X, y):
     _check(lib().mlvs_mlp_eval(_fp(P), K, _fp(Xf), yy.ctypes.data_as(_c_int32_p), B, _fp(probs), _fp(grad),
                                ctypes.byref(loss)))
     return probs, grad, loss.value
+
+
+def mlp_eval_noalloc(d_params, K, d_X, d_y, B, d_probs=None, d_grad=None, d_loss_sum=None, stream=None):
+    """mlvs_mlp_eval_noalloc on device pointers (ints, e.g. torch tensors' data_ptr()); asynchronous."""
+    _check(lib().mlvs_mlp_eval_noalloc(d_params, int(K), d_X, d_y, int(B), d_probs, d_grad, d_loss_sum, stream))
 
 
 def mlp_predict(params, K, X, bf16=True):

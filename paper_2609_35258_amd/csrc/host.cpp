@@ -2044,6 +2044,18 @@ mlvs_status mlvs_mlp_eval(const float* params, int K, const float* X, const int3
     });
 }
 
+mlvs_status mlvs_mlp_eval_noalloc(const float* d_params, int K, const float* d_X, const int32_t* d_y, int B,
+                                  float* d_probs, float* d_grad, double* d_loss_sum, void* stream) {
+    return guarded([&] {
+        check_mlp_args(K);
+        if (!d_params || !d_X || !d_y) fail(MLVS_E_ARG, "null argument");
+        if (B < 1 || B > NOALLOC_MAX_BATCH)
+            fail(MLVS_E_ARG, "batch of %d samples: this entry point takes 1 to %d", B, NOALLOC_MAX_BATCH);
+        hip_check(launch_mlp_eval_noalloc(static_cast<hipStream_t>(stream), d_params, K, d_X, d_y, B, d_probs, d_grad,
+                                          d_loss_sum), "forward/backward launch");
+    });
+}
+
 mlvs_status mlvs_mlp_predict(const float* params, int K, const float* X, int B, int bf16, int32_t* classes,
                              float* probs) {
     return guarded([&] {

@@ -186,6 +186,13 @@ hipError_t launch_mlp_fwd_bwd(hipStream_t st, const float* P, int K, const float
                               float* lossv, double* loss_sum);
 hipError_t launch_mlp_grad(hipStream_t st, int K, int B, const float* XN, const float* A1, const float* A2,
                            const float* D1, const float* D2, const float* D3, float* G);
+// Forward/backward of a batch of at most NOALLOC_MAX_BATCH samples with the
+// intermediates in the library's fixed device array (no allocation; calls on
+// one GPU share the array).  prob, grad, loss_sum may be null.
+constexpr int NOALLOC_MAX_BATCH = 4096;
+size_t noalloc_scratch_bytes();
+hipError_t launch_mlp_eval_noalloc(hipStream_t st, const float* P, int K, const float* X, const int* y, int B,
+                                   float* prob, float* grad, double* loss_sum);
 hipError_t launch_adam(hipStream_t st, float* P, const float* G, float* M, float* V, int n, float lr, float b1,
                        float b2, float eps, int t);
 hipError_t launch_mlp_predict(hipStream_t st, const float* P, int K, const float* X, int B, int bf16, int* cls,

@@ -8,6 +8,7 @@
 #include "mlvs_impl.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace mlvs {
 
@@ -342,6 +343,73 @@ hipError_t launch_mlp_grad(hipStream_t st, int K, int B, const float* XN, const 
     const int n = mlp_offsets(K, 6);
     hipLaunchKernelGGL(k_mlp_grad, dim3((n + 255) / 256), dim3(256), 0, st, K, B, XN, A1, A2, D1, D2, D3, G);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// forward/backward without device allocation: the intermediate values live in
+// a fixed device array of the library
+// ---------------------------------------------------------------------------
+// Layout (bytes): [0, 256) the loss sum when the caller wants none; then, for
+// at most NOALLOC_MAX_BATCH samples, XN [B][10], A1, A2, D1, D2 [B][64],
+// D3 [B][16], per-sample losses [B] (floats).  Each GPU holds its own copy
+// until the process ends; calls on one GPU share it.
+constexpr size_t NOALLOC_FLOATS_PER_SAMPLE = NF + 4 * NH + KMAX + 1;
+constexpr size_t NOALLOC_BYTES = 256 + sizeof(float) * NOALLOC_FLOATS_PER_SAMPLE * NOALLOC_MAX_BATCH;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// Zero the gradient entries the gradient kernel does not write (the
+// standardisation block): a fill kernel, so the launch sequence holds no
+// memset node when a caller captures it in a graph.
+__global__ void k_fill_zero(float* __restrict__ p, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0.f;
+}
+
+// The array's device address, looked up once per device (with that device
+// current) and kept: in host code the array's name is not a device address.
+static hipError_t scratch_address(unsigned char** out) {
+    constexpr int MAXDEV = 64;
+    static unsigned char* addr[MAXDEV] = {};
+    static std::mutex m;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAXDEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(m);
+    if (!addr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<unsigned char*>(ptr);
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
+size_t noalloc_scratch_bytes() { return NOALLOC_BYTES; }
+
+hipError_t launch_mlp_eval_noalloc(hipStream_t st, const float* P, int K, const float* X, const int* y, int B,
+                                   float* prob, float* grad, double* loss_sum) {
+    if (B < 1 || B > NOALLOC_MAX_BATCH || K < 2 || K > KMAX) return hipErrorInvalidValue;
+    unsigned char* base = nullptr;
+    hipError_t e = scratch_address(&base);
+    if (e != hipSuccess) return e;
+    double* ls = loss_sum ? loss_sum : reinterpret_cast<double*>(base);
+    float* f = reinterpret_cast<float*>(base + 256);
+    const size_t Bs = (size_t)B;
+    float* XN = f;
+    float* A1 = XN + NF * Bs;
+    float* A2 = A1 + NH * Bs;
+    float* D1 = A2 + NH * Bs;
+    float* D2 = D1 + NH * Bs;
+    float* D3 = D2 + NH * Bs;
+    float* LV = D3 + KMAX * Bs;
+    e = launch_mlp_fwd_bwd(st, P, K, X, y, nullptr, B, XN, A1, A2, D1, D2, D3, prob, LV, ls);
+    if (e != hipSuccess || !grad) return e;
+    const int ntr = mlp_offsets(K, 6), np = mlp_nparams(K);
+    hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, st, grad + ntr, np - ntr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_mlp_grad(st, K, B, XN, A1, A2, D1, D2, D3, grad);
 }
 
 hipError_t launch_adam(hipStream_t st, float* P, const float* G, float* M, float* V, int n, float lr, float b1,
