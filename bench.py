@@ -479,6 +479,66 @@ def cylinder_case(steps=200, warmup=100, precision=32, mode="both", Kn=0.1):
                     "mlvs_vs_uvs_rel_l2": err}}
 
 
+def persistent_ab(steps=100, interval=5, precision=32, pure_steps=20):
+    """The staged (or fused) step against the persistent single-launch step on
+    the full-size cylinder (Ma 3, after 100 base-grid steps) and two-cavity
+    (from the initial state) MLVS runs.  Per mode: ms per step with adaptation
+    every `interval` steps inside the timed window, the graph captures and
+    graph launches those steps took, and ms per step without adaptation; the
+    relative L2 difference of the final fields between the two modes."""
+    import torch
+    import paper_2609_35258_amd as m
+    from paper_2609_35258_amd import autotune
+    cases = {"cylinder256x128-nc101": (lambda: W.cylinder(256, 128, Kn=0.1, nv=101, vmax=10.0), CYL_ADAPT, 100),
+             "two_cavity9504-nc101": (lambda: W.two_cavity(48, nv=101, vmax=7.0), TC_ADAPT, 0)}
+    out = {}
+    for name, (make, base_ap, warm) in cases.items():
+        p = make()
+        res, fields = {}, {}
+        for mode in ("staged", "persistent"):
+            s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=dict(base_ap, interval=0), graph=True)
+            s.step(warm)
+            s.adapt()
+            s.set_persistent(mode == "persistent")
+            s.step(2)
+            tuned = autotune.autotune(s, precision)
+            s.set_adapt(dict(base_ap, interval=interval))
+            torch.cuda.synchronize()
+            g0, c0 = s.graph_info(), s.counters()
+            t0 = time.perf_counter()
+            s.step(steps)
+            torch.cuda.synchronize()
+            t_ad = time.perf_counter() - t0
+            g1, c1 = s.graph_info(), s.counters()
+            s.set_adapt(dict(base_ap, interval=0))
+            s.step(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(pure_steps)
+            torch.cuda.synchronize()
+            t_pure = time.perf_counter() - t0
+            npts, ncells, _ = s.level_info()
+            res[mode] = {"ms_per_step_with_adaptation": 1e3 * t_ad / steps,
+                         "ms_per_step_no_adaptation": 1e3 * t_pure / pure_steps,
+                         "adaptations": c1["adaptations"] - c0["adaptations"],
+                         "graph_captures": g1["captures"] - g0["captures"],
+                         "graph_launches": g1["launches"] - g0["launches"],
+                         "stages": s.step_stages(), "grid": g1["grid"], "barrier_error": g1["error"],
+                         "variants": {k: v["variant"] for k, v in tuned.items()},
+                         "levels": len(npts), "nbar": float(np.sum(npts * ncells) / np.sum(ncells))}
+            fields[mode] = s.moments()
+            print("persistent_ab %s %s: %s" % (name, mode, json.dumps(res[mode])), file=sys.stderr, flush=True)
+            s.close()
+            del s
+            torch.cuda.empty_cache()
+        a, b = fields["staged"], fields["persistent"]
+        res["fields_rel_l2"] = {nm: float(np.sqrt(np.sum((b[:, k] - a[:, k]) ** 2) / np.sum(a[:, k] ** 2)))
+                                for k, nm in ((0, "rho"), (1, "u"), (3, "T"))}
+        out[name] = res
+    return {"workload": "fp%d; %d timed steps with adaptation every %d steps, then %d steps without" % (
+        precision, steps, interval, pure_steps), "cases": out}
+
+
 JET_ADAPT = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, flux_test=True, interval=5)
 JET_BASE_STEPS = 100
 JET_WL = "jet512x256-nc161-fp32"
@@ -877,6 +937,8 @@ def main():
     ap.add_argument("--cylinder-steps", type=int, default=200)
     ap.add_argument("--cylinder-kn", type=float, default=0.1)
     ap.add_argument("--cylinder-mode", choices=("both", "mlvs", "uvs"), default="both")
+    ap.add_argument("--persistent-ab", action="store_true",
+                    help="only the staged-against-persistent step comparison (cylinder, two-cavity)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -908,6 +970,9 @@ def main():
                                                                        scale=args.tc_scale)}), flush=True)
             return
         print(json.dumps({"two_cavity": two_cavity_case(mode=args.tc_mode, interval=args.tc_interval)}), flush=True)
+        return
+    if args.persistent_ab:
+        print(json.dumps({"persistent_ab": persistent_ab()}), flush=True)
         return
     if args.cylinder_only:
         print(json.dumps({"cylinder": cylinder_case(steps=args.cylinder_steps, mode=args.cylinder_mode,

@@ -295,6 +295,29 @@ mlvs_status mlvs_set_variant(mlvs_ctx ctx, int stage, int variant);
  * (MLVS_E_STATE otherwise).  Results are identical to direct launches. */
 mlvs_status mlvs_set_graph(mlvs_ctx ctx, int on);
 
+/* Persistent step (the batched form of the step, north of Sec. 4.4's remark
+ * on kernel organisation and synchronisation): on = 1 runs each time step as
+ * ONE launch of a persistent kernel over the context's work lists (neighbour
+ * rows, then cross-level and same-level faces, then update with the next
+ * step's cell stage, stages separated by grid-wide barriers; velocity rows
+ * whole), preceded by a one-thread kernel that clears its barrier counter.
+ * The kernel reads every work-list pointer and item count from a device
+ * block the context rewrites in place at each level install, so with
+ * mlvs_set_graph(ctx, 1) the captured step survives adaptations (captured
+ * again only when the mode or the launch variant changes; see
+ * mlvs_graph_info).  Results equal the fused step's.  on = 0 restores the
+ * staged launches.  Synchronises. */
+mlvs_status mlvs_set_persistent(mlvs_ctx ctx, int on);
+
+/* Step launch statistics: *persistent the mode, *captures the number of step
+ * graphs captured since creation, *launches the graph launches, *grid the
+ * persistent kernel's workgroup count (0 before its first launch), *error the
+ * persistent kernel's sticky error flag (1: a grid barrier gave up waiting,
+ * the step that set it is invalid).  Any pointer may be NULL; reading *error
+ * synchronises. */
+mlvs_status mlvs_graph_info(mlvs_ctx ctx, int* persistent, int64_t* captures, int64_t* launches, int* grid,
+                            int* error);
+
 /* Work counters since creation: steps taken, cell-velocity updates on the
  * cells' own levels (sum over steps of sum over cells of the level size),
  * interface-space points processed on cross-level faces, adaptations. */
@@ -311,13 +334,15 @@ mlvs_status mlvs_counters(mlvs_ctx ctx, int64_t* steps, double* cell_updates, do
  * step whose levels have at most 1024 points: 7 face reconstruction and target
  * in one launch, 8 update followed by the next step's cell stage (state, rows
  * and parameters saved and put back as for 5; MLVS_E_STATE when the step is
- * not fused).  Needs a step taken since the last level change for
- * meaningful inputs.  Synchronises. */
+ * not fused), 9 the persistent step (state saved and put back as for 8;
+ * MLVS_E_STATE when it is off).  Needs a step taken since the last level
+ * change for meaningful inputs.  Synchronises. */
 mlvs_status mlvs_time_stage(mlvs_ctx ctx, int stage, int reps, double* ms_per_launch);
 
 /* The stages one step launches, in order (numbering as in mlvs_time_stage):
  * 0 1 2 3 4 5, or 1 7 4 8 when every level has at most 1024 points (the
- * fused step; MLVS_FUSE=0 in the environment at create turns it off).
+ * fused step; MLVS_FUSE=0 in the environment at create turns it off), or 9
+ * with the persistent step on.
  * stages: caller-owned array of at least 8 ints, or null to query *count. */
 mlvs_status mlvs_step_stages(mlvs_ctx ctx, int* stages, int* count);
 

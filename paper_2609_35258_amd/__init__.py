@@ -124,6 +124,10 @@ _PROTOS = {
     "mlvs_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), _c_double_p, _c_double_p,
                                      ctypes.POINTER(ctypes.c_int64)]),
     "mlvs_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "mlvs_set_persistent": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "mlvs_graph_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int)]),
     "mlvs_variants": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "mlvs_set_variant": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "mlvs_time_stage": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_double_p]),
@@ -537,13 +541,25 @@ class Solver:
         return {"steps": st.value, "cell_updates": up.value, "iface_points": ip.value, "adaptations": ad.value}
 
     STAGES = {"cell": 0, "ghost": 1, "face_rec": 2, "face_target": 3, "xface": 4, "update": 5, "criterion": 6,
-              "face": 7, "update_cell": 8}
+              "face": 7, "update_cell": 8, "persistent": 9}
     STAGE_NAMES = {v: k for k, v in STAGES.items()}
+
+    def set_persistent(self, on: bool = True):
+        _check(lib().mlvs_set_persistent(self.h, int(on)))
+
+    def graph_info(self):
+        """{persistent, captures, launches, grid, error} of the step launches."""
+        pe, gr, er = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        ca, la = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().mlvs_graph_info(self.h, ctypes.byref(pe), ctypes.byref(ca), ctypes.byref(la), ctypes.byref(gr),
+                                     ctypes.byref(er)))
+        return {"persistent": pe.value, "captures": ca.value, "launches": la.value, "grid": gr.value,
+                "error": er.value}
 
     def step_stages(self):
         """Names of the stages one step launches, in order."""
         n = ctypes.c_int()
-        buf = (ctypes.c_int32 * 8)()
+        buf = (ctypes.c_int32 * 10)()
         _check(lib().mlvs_step_stages(self.h, buf, ctypes.byref(n)))
         return [self.STAGE_NAMES[buf[k]] for k in range(n.value)]
 

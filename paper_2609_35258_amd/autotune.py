@@ -20,7 +20,7 @@ import json
 import os
 from typing import Dict, Iterable, Optional
 
-TUNABLE = ("cell", "face_rec", "face_target", "xface", "update", "face", "update_cell")
+TUNABLE = ("cell", "face_rec", "face_target", "xface", "update", "face", "update_cell", "persistent")
 
 
 def default_cache() -> str:

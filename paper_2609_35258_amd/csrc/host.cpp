@@ -994,7 +994,15 @@ struct mlvs_ctx_s {
     int64_t last_fallback = 0;
     // step graph: the launches of one step captured once per level set
     bool use_graph = false;
-    int variant[9] = {1, 1, 1, 1, 1, 1, 1, 1, 1};   // per stage launch variant (autotuned)
+    int variant[10] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 0};   // per stage launch variant (autotuned)
+    // persistent step (mlvs_set_persistent): one launch per step over the work
+    // lists of a device-resident StepArgs, rewritten in place by every level
+    // install, so the captured step survives adaptations
+    bool persistent = false;
+    StepArgs* d_args = nullptr;
+    unsigned int* d_sync = nullptr;    // [0] barrier arrivals, [1] sticky error flag
+    int persistent_grid = 0;
+    int64_t n_captures = 0, n_graph_launches = 0;
     // Fused step (every level fits one velocity chunk): reconstruction and
     // target in one launch, and the update carries the next step's cell stage.
     bool fuse_allowed = true;          // MLVS_FUSE=0 turns the fused step off
@@ -1070,7 +1078,9 @@ void drop_graph(mlvs_ctx c) {
 }
 
 void free_items(mlvs_ctx c) {
-    drop_graph(c);
+    // the persistent step reads its work lists through d_args: its captured
+    // graph stays valid; the staged step's launches name the lists directly
+    if (!c->persistent) drop_graph(c);
     for (auto& t : c->tables) {
         c->dm.release(t.off);
         c->dm.release(t.idx);
@@ -1112,6 +1122,35 @@ std::unique_ptr<Level> level_of_mask(mlvs_ctx c, const std::vector<uint8_t>& kap
         it = c->level_cache.emplace(kappa, build_level(c->base, kappa)).first;
     }
     return std::make_unique<Level>(*it->second);
+}
+
+// The persistent step's device-resident arguments: the current work lists,
+// buffers and counts, written in place (stream-ordered, outside any capture).
+void update_step_args(mlvs_ctx c) {
+    if (!c->d_args) return;
+    StepArgs A{};
+    A.lvs = c->d_lv;
+    A.ghosts = c->d_ghosts;
+    A.faces = c->d_faces;
+    A.xfaces = c->d_xfaces;
+    A.order = c->d_order;
+    A.cell_lev = c->d_cell_lev;
+    A.cell_slot = c->d_cell_slot;
+    A.cell_nbr = c->d_cell_nbr;
+    A.cell_frow = c->d_cell_frow;
+    A.geom = c->d_geom;
+    A.bcs = c->d_bcs;
+    A.params = c->d_params;
+    A.cmom = c->d_cmom;
+    A.fpar = c->d_fpar;
+    A.neg = c->d_neg;
+    A.sync = c->d_sync;
+    A.n_ghosts = c->n_ghosts;
+    A.n_faces = c->n_faces + c->n_bfaces;
+    A.n_xfaces = c->n_xfaces;
+    A.n_cells = c->mesh.n_cells;
+    hip_check(hipMemcpyAsync(c->d_args, &A, sizeof A, hipMemcpyHostToDevice, c->st), "step args upload");
+    hip_check(hipStreamSynchronize(c->st), "stream synchronize");
 }
 
 // Build face/ghost/cross-face work lists, flux rows and per-cell codes for the
@@ -1367,6 +1406,7 @@ void build_items(mlvs_ctx c) {
             parts = std::min((MIN_ITEMS + nf_all - 1) / nf_all, (nmax + 63) / 64);
         c->chunk = ((nmax + parts - 1) / parts + 63) / 64 * 64;
     }
+    if (c->persistent) c->chunk = (nmax + 63) / 64 * 64;    // whole rows (the fused bodies)
     c->nch = (nmax + c->chunk - 1) / c->chunk;
     c->fused = c->fuse_allowed && c->nch == 1 && nmax <= FUSE_MAX_POINTS;
     c->d_fmom = static_cast<double*>(
@@ -1378,6 +1418,7 @@ void build_items(mlvs_ctx c) {
     c->prep_valid = false;
     c->d_fpar = static_cast<double*>(c->dm.alloc(sizeof(double) * NFP * std::max<size_t>(faces.size(), 1)));
     c->item_allocs.push_back(c->d_fpar);
+    update_step_args(c);                  // last: every pointer it records is allocated
 }
 
 void assign_slots(mlvs_ctx c) {
@@ -2465,6 +2506,9 @@ static mlvs_status create_impl(const mlvs_physics* phys, const mlvs_mesh* mesh, 
         // counters: [0] positivity violations, [1] exponential fallbacks, [2] failed ones
         c->d_neg = static_cast<unsigned long long*>(c->dm.alloc(24));
         hip_check(hipMemsetAsync(c->d_neg, 0, 24, c->st), "memset");
+        c->d_args = static_cast<StepArgs*>(c->dm.alloc(sizeof(StepArgs)));
+        c->d_sync = static_cast<unsigned int*>(c->dm.alloc(8));
+        hip_check(hipMemsetAsync(c->d_sync, 0, 8, c->st), "memset");
         // velocity chunk of the streaming stages (MLVS_CHUNK overrides; multiple of 64)
         if (const char* e = std::getenv("MLVS_FUSE")) c->fuse_allowed = std::atoi(e) != 0;
         if (const char* e = std::getenv("MLVS_CHUNK")) {
@@ -2641,8 +2685,8 @@ mlvs_status mlvs_info(mlvs_ctx c, double* dt, int64_t* n_cells, int32_t* n_block
 
 mlvs_status mlvs_variants(int stage, int* count) {
     return guarded([&] {
-        if (!count || stage < 0 || stage > 8) fail(MLVS_E_ARG, "bad arguments");
-        *count = (stage == 1 || stage == 6) ? 1 : variant_count();
+        if (!count || stage < 0 || stage > 9) fail(MLVS_E_ARG, "bad arguments");
+        *count = (stage == 1 || stage == 6) ? 1 : stage == 9 ? persistent_variant_count() : variant_count();
     });
 }
 
@@ -2653,6 +2697,35 @@ mlvs_status mlvs_set_variant(mlvs_ctx c, int stage, int v) {
         sync(c);
         drop_graph(c);
         c->variant[stage] = v;
+    });
+}
+
+mlvs_status mlvs_set_persistent(mlvs_ctx c, int on) {
+    return guarded([&] {
+        if (!c || (on != 0 && on != 1)) fail(MLVS_E_ARG, "bad arguments");
+        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
+        sync(c);
+        if ((on != 0) == c->persistent) return;
+        drop_graph(c);
+        c->persistent = on != 0;
+        build_items(c);               // chunks (whole rows) and the device-resident arguments
+    });
+}
+
+mlvs_status mlvs_graph_info(mlvs_ctx c, int* persistent, int64_t* captures, int64_t* launches, int* grid,
+                            int* error) {
+    return guarded([&] {
+        if (!c) fail(MLVS_E_ARG, "null context");
+        if (persistent) *persistent = c->persistent ? 1 : 0;
+        if (captures) *captures = c->n_captures;
+        if (launches) *launches = c->n_graph_launches;
+        if (grid) *grid = c->persistent_grid;
+        if (error) {
+            unsigned int v[2] = {0, 0};
+            hip_check(hipMemcpyAsync(v, c->d_sync, sizeof v, hipMemcpyDeviceToHost, c->st), "D2H");
+            sync(c);
+            *error = (int)v[1];
+        }
     });
 }
 
@@ -2679,8 +2752,13 @@ mlvs_status mlvs_counters(mlvs_ctx c, int64_t* steps, double* cell_updates, doub
 
 mlvs_status mlvs_time_stage(mlvs_ctx c, int stage, int reps, double* ms) {
     return guarded([&] {
-        if (!c || !ms || reps < 1 || stage < 0 || stage > 8) fail(MLVS_E_ARG, "bad arguments");
+        if (!c || !ms || reps < 1 || stage < 0 || stage > 9) fail(MLVS_E_ARG, "bad arguments");
         if ((stage == 7 || stage == 8) && !c->fused) fail(MLVS_E_STATE, "fused stages need levels of one chunk");
+        if (stage == 9 && !c->persistent) fail(MLVS_E_STATE, "the persistent step is off (mlvs_set_persistent)");
+        if (stage == 9 && !c->prep_valid) {
+            hip_check(launch_stage(c, 0), "cell stage launch");
+            c->prep_valid = true;
+        }
         if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
         if (stage == 6 && !c->adaptive) fail(MLVS_E_STATE, "criterion needs adaptation parameters");
         ensure_moments(c);
@@ -2688,7 +2766,7 @@ mlvs_status mlvs_time_stage(mlvs_ctx c, int stage, int reps, double* ms) {
         // advances the state, which is saved here and put back afterwards
         std::vector<std::pair<void*, void*>> saved;    // (live buffer, copy)
         std::vector<size_t> saved_bytes;
-        if (stage == 5 || stage == 8) {
+        if (stage == 5 || stage == 8 || stage == 9) {
             auto keep = [&](void* p, size_t nb) {
                 if (!p || nb == 0) return;
                 void* q = c->dm.alloc(nb);
@@ -2702,7 +2780,7 @@ mlvs_status mlvs_time_stage(mlvs_ctx c, int stage, int reps, double* ms) {
                 keep(L->h, nb);
             }
             keep(c->d_cmom, sizeof(double) * NMOM * c->nch * (size_t)c->mesh.n_cells);
-            if (stage == 8) {          // the next step's cell stage: phi_bar+ rows and parameters
+            if (stage == 8 || stage == 9) {   // the next step's cell stage: phi_bar+ rows and parameters
                 for (auto& L : c->levels) {
                     const size_t nb = (size_t)L->n_cells * L->stride * c->elt();
                     keep(L->fg, nb);
@@ -2749,11 +2827,11 @@ mlvs_status mlvs_step_stages(mlvs_ctx c, int* stages, int* count) {
 
 mlvs_status mlvs_stage_size(mlvs_ctx c, int stage, int64_t* items, double* points) {
     return guarded([&] {
-        if (!c || stage < 0 || stage > 8) fail(MLVS_E_ARG, "bad arguments");
+        if (!c || stage < 0 || stage > 9) fail(MLVS_E_ARG, "bad arguments");
         int64_t ni = 0;
         double np = 0.0;
         switch (stage) {
-        case 0: case 5: case 6: case 8:
+        case 0: case 5: case 6: case 8: case 9:
             ni = c->mesh.n_cells;
             np = stage == 6 ? (double)c->mesh.n_cells * c->base.N : c->step_points;
             break;
@@ -2984,9 +3062,9 @@ void do_step(mlvs_ctx c) {
         if (mlvs_adapt(c, nullptr) != MLVS_OK) throw Fail{MLVS_E_STATE, g_last_error};
     }
     ensure_moments(c);
-    if (c->fused && !c->prep_valid) {
-        // the fused step starts from a prepared cell stage (the previous fused
-        // update prepares the next one)
+    if ((c->fused || c->persistent) && !c->prep_valid) {
+        // the fused and persistent steps start from a prepared cell stage (the
+        // previous step's update prepares the next one)
         hip_check(launch_stage(c, 0), "cell stage launch");
         c->prep_valid = true;
     }
@@ -3000,12 +3078,14 @@ void do_step(mlvs_ctx c) {
             hip_check(e2, "end capture");
             c->graph = g;
             hip_check(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0), "graph instantiate");
+            ++c->n_captures;
         }
         hip_check(hipGraphLaunch(c->gexec, c->st), "graph launch");
+        ++c->n_graph_launches;
     } else {
         hip_check(launch_step_kernels(c), "step launch");
     }
-    c->prep_valid = c->fused;
+    c->prep_valid = c->fused || c->persistent;
     ++c->step_count;
     c->cnt_updates += c->step_points;
     c->cnt_iface += c->step_iface_points;
@@ -3013,11 +3093,13 @@ void do_step(mlvs_ctx c) {
 
 // The stages one step launches, in order.
 std::vector<int> step_stages(mlvs_ctx c) {
+    if (c->persistent) return {9};
     if (c->fused) return {1, 7, 4, 8};
     return {0, 1, 2, 3, 4, 5};
 }
 
 hipError_t launch_step_kernels(mlvs_ctx c) {
+    if (c->persistent) return launch_stage(c, 9);
     // cross-level faces (stage 4) beside the same-level face stages: both read
     // the cell stage's rows and the ghost rows, and they write distinct rows
     const bool fork = c->n_xfaces > 0 && c->side_st;
@@ -3060,6 +3142,8 @@ hipError_t launch_stage(mlvs_ctx c, int stage, hipStream_t on) {
                                  c->nch, c->variant[5]);
     case 7: return launch_face_full(c->prec, c->st, c->d_lv, c->d_faces, nf, c->d_cell_slot, c->d_cell_nbr,
                                     c->d_geom, c->d_params, c->d_bcs, c->ph, c->d_fpar, c->variant[7]);
+    case 9: return launch_step_persistent(c->prec, c->st, c->d_args, c->d_sync, c->ph, c->variant[9],
+                                          &c->persistent_grid);
     case 8: return launch_update_cell(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, c->d_order, n,
                                       c->d_geom, c->d_cell_frow, c->d_faces, c->d_fpar, c->d_params, c->ph,
                                       c->d_cmom, c->variant[8]);

@@ -880,12 +880,14 @@ __device__ __forceinline__ void map_correct_apply(const LevelDesc& D, gptr<S> gd
     }
 }
 
+// Items [first, n) with stride `stride` (one wave per item): the loop of the
+// kernel below, and one stage of the persistent step.
 template <typename S>
-__global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs, const GhostItem* __restrict__ items,
-                                              int n, const int* __restrict__ cell_lev,
-                                              const int* __restrict__ cell_slot, const double* __restrict__ params,
-                                              Phys ph, unsigned long long* neg) {
-    for (int it = item0(); it < n; it += istride()) {
+__device__ __forceinline__ void ghost_items(const LevelDesc* __restrict__ lvs, const GhostItem* __restrict__ items,
+                                            int n, const int* __restrict__ cell_lev,
+                                            const int* __restrict__ cell_slot, const double* __restrict__ params,
+                                            Phys ph, unsigned long long* neg, int first, int stride) {
+    for (int it = first; it < n; it += stride) {
         const GhostItem G = items[it];
         const LevelDesc& Ls = lvs[cell_lev[G.n]];
         const LevelDesc& Ld = lvs[G.dst];
@@ -926,6 +928,14 @@ __global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs,
         nf = __any(nf);
         if (lane_id() == 0 && nf) atomicAdd(neg, 1ull);
     }
+}
+
+template <typename S>
+__global__ __launch_bounds__(BS) void k_ghost(const LevelDesc* __restrict__ lvs, const GhostItem* __restrict__ items,
+                                              int n, const int* __restrict__ cell_lev,
+                                              const int* __restrict__ cell_slot, const double* __restrict__ params,
+                                              Phys ph, unsigned long long* neg) {
+    ghost_items<S>(lvs, items, n, cell_lev, cell_slot, params, ph, neg, item0(), istride());
 }
 
 // ---------------------------------------------------------------------------
@@ -1525,16 +1535,13 @@ __global__ __launch_bounds__(GBS, MINW) void k_face_target(const LevelDesc* __re
 // level sets whose levels fit one velocity chunk, where the reconstruction has
 // no chunk partials to add and the staged target's per-workgroup hand-overs
 // would dominate.  Same arithmetic as k_face_rec + k_face_target.
-template <typename S, int U, int MINW, int CM, int MK>
-__global__ __launch_bounds__(BS, MINW) void k_face_full(const LevelDesc* __restrict__ lvs,
-                                                        const FaceItem* __restrict__ items, int nF,
-                                                        const int* __restrict__ cell_slot,
-                                                        const int* __restrict__ cell_nbr,
-                                                        const CellGeom* __restrict__ geom,
-                                                        const double* __restrict__ params,
-                                                        const BCDev* __restrict__ bcs, Phys ph,
-                                                        double* __restrict__ fpar) {
-    for (int f = item0(); f < nF; f += istride()) {
+template <typename S, int U, int CM, int MK>
+__device__ __forceinline__ void face_full_items(const LevelDesc* __restrict__ lvs, const FaceItem* __restrict__ items,
+                                                int nF, const int* __restrict__ cell_slot,
+                                                const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
+                                                const double* __restrict__ params, const BCDev* __restrict__ bcs,
+                                                Phys ph, double* __restrict__ fpar, int first, int stride) {
+    for (int f = first; f < nF; f += stride) {
         const FaceItem F = items[f];
         const LevelDesc& L = lvs[F.lev];
         double m[11], u0, v0;
@@ -1572,6 +1579,19 @@ __global__ __launch_bounds__(BS, MINW) void k_face_full(const LevelDesc* __restr
         }
         if (lane_id() == 0) write_face_record(fpar + (size_t)f * NFP, kind, F, c1, c2, e);
     }
+}
+
+template <typename S, int U, int MINW, int CM, int MK>
+__global__ __launch_bounds__(BS, MINW) void k_face_full(const LevelDesc* __restrict__ lvs,
+                                                        const FaceItem* __restrict__ items, int nF,
+                                                        const int* __restrict__ cell_slot,
+                                                        const int* __restrict__ cell_nbr,
+                                                        const CellGeom* __restrict__ geom,
+                                                        const double* __restrict__ params,
+                                                        const BCDev* __restrict__ bcs, Phys ph,
+                                                        double* __restrict__ fpar) {
+    face_full_items<S, U, CM, MK>(lvs, items, nF, cell_slot, cell_nbr, geom, params, bcs, ph, fpar, item0(),
+                                  istride());
 }
 
 template <typename S>
@@ -1746,18 +1766,14 @@ __global__ __launch_bounds__(BS, MINW) void k_update(const LevelDesc* __restrict
 // cell's update reads them, so the next step's cell stage is complete when
 // this launch ends.  The form for level sets whose levels fit one velocity
 // chunk.  Same arithmetic as k_update + k_cell_prep.
-template <typename S, int U, int MINW, int CM>
-__global__ __launch_bounds__(BS, MINW) void k_update_cell(const LevelDesc* __restrict__ lvs,
-                                                          const int* __restrict__ cell_lev,
-                                                          const int* __restrict__ cell_slot,
-                                                          const int* __restrict__ order, int n_cells,
-                                                          const CellGeom* __restrict__ geom,
-                                                          const int* __restrict__ cell_frow,
-                                                          const FaceItem* __restrict__ items,
-                                                          const double* __restrict__ fpar,
-                                                          double* __restrict__ params, Phys ph,
-                                                          double* __restrict__ cmom) {
-    for (int it = item0(); it < n_cells; it += istride()) {
+template <typename S, int U, int CM>
+__device__ __forceinline__ void update_cell_items(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
+                                                  const int* __restrict__ cell_slot, const int* __restrict__ order,
+                                                  int n_cells, const CellGeom* __restrict__ geom,
+                                                  const int* __restrict__ cell_frow, const FaceItem* __restrict__ items,
+                                                  const double* __restrict__ fpar, double* __restrict__ params,
+                                                  Phys ph, double* __restrict__ cmom, int first, int stride) {
+    for (int it = first; it < n_cells; it += stride) {
         const int c = order[it];
         const LevelDesc& L = lvs[cell_lev[c]];
         double cm[NMOM], u0, v0;
@@ -1781,6 +1797,21 @@ __global__ __launch_bounds__(BS, MINW) void k_update_cell(const LevelDesc* __res
         if (lane_id() == 0) write_params(params + (size_t)c * NPARAM, cs, a);
         phibar_points<S, U>(L, (size_t)cell_slot[c] * L.stride, e, cs.alpha, cs.beta);
     }
+}
+
+template <typename S, int U, int MINW, int CM>
+__global__ __launch_bounds__(BS, MINW) void k_update_cell(const LevelDesc* __restrict__ lvs,
+                                                          const int* __restrict__ cell_lev,
+                                                          const int* __restrict__ cell_slot,
+                                                          const int* __restrict__ order, int n_cells,
+                                                          const CellGeom* __restrict__ geom,
+                                                          const int* __restrict__ cell_frow,
+                                                          const FaceItem* __restrict__ items,
+                                                          const double* __restrict__ fpar,
+                                                          double* __restrict__ params, Phys ph,
+                                                          double* __restrict__ cmom) {
+    update_cell_items<S, U, CM>(lvs, cell_lev, cell_slot, order, n_cells, geom, cell_frow, items, fpar, params, ph,
+                                cmom, item0(), istride());
 }
 
 // ---------------------------------------------------------------------------
@@ -2163,13 +2194,14 @@ __device__ __forceinline__ void side_refined(const SD& sd, const LevelDesc& Ln, 
     sy[1] = sy[1] + dq * sy[0];
 }
 
-template <typename S, int U, int MINW, int MK>
-__global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict__ lvs, const XFaceItem* __restrict__ items,
-                                              int n, const int* __restrict__ cell_slot,
-                                              const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
-                                              const double* __restrict__ params, Phys ph, unsigned long long* neg) {
+template <typename S, int U, int MK>
+__device__ __forceinline__ void xface_items(const LevelDesc* __restrict__ lvs, const XFaceItem* __restrict__ items,
+                                            int n, const int* __restrict__ cell_slot,
+                                            const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
+                                            const double* __restrict__ params, Phys ph, unsigned long long* neg,
+                                            int first, int stride) {
     const S s = (S)(0.5 * ph.dt);
-    for (int it = item0(); it < n; it += istride()) {
+    for (int it = first; it < n; it += stride) {
         const XFaceItem F = items[it];
         const LevelDesc& LA = lvs[F.levA];
         const LevelDesc& LB = lvs[F.levB];
@@ -2323,6 +2355,14 @@ __global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict_
         nf = __any(nf);
         if (lane_id() == 0 && nf) atomicAdd(neg, 1ull);
     }
+}
+
+template <typename S, int U, int MINW, int MK>
+__global__ __launch_bounds__(BS, MINW) void k_xface(const LevelDesc* __restrict__ lvs, const XFaceItem* __restrict__ items,
+                                              int n, const int* __restrict__ cell_slot,
+                                              const int* __restrict__ cell_nbr, const CellGeom* __restrict__ geom,
+                                              const double* __restrict__ params, Phys ph, unsigned long long* neg) {
+    xface_items<S, U, MK>(lvs, items, n, cell_slot, cell_nbr, geom, params, ph, neg, item0(), istride());
 }
 
 // ---------------------------------------------------------------------------
@@ -2808,6 +2848,110 @@ __global__ void k_compare_rows_u8(const uint8_t* __restrict__ all, int width, co
         for (int k = lane_id(); k < width; k += WL) bad |= (a[k] != r[k]);
         if (__any(bad) && lane_id() == 0) atomicAdd(mismatch, 1ull);
     }
+}
+
+// ---------------------------------------------------------------------------
+// the persistent step: one launch per step
+// ---------------------------------------------------------------------------
+// Grid-wide barrier.  Every workgroup of the launch is resident (the grid is
+// sized from this kernel's occupancy), so all of them arrive.  The agent-scope
+// fences write the arriving workgroup's results back past its XCD's L2 and
+// make the others' visible after the wait.  The wait is bounded: past the
+// bound the sticky error flag sync[1] is set and the barrier is left, the step
+// is then invalid and the host reports it; no wave waits for ever.
+__device__ __forceinline__ void grid_barrier(unsigned int* sync, unsigned int& phase) {
+    __syncthreads();
+    ++phase;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned int target = phase * gridDim.x;
+        atomicAdd(sync, 1u);
+        unsigned int k = 0;
+        while (__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(32);
+            if (++k > (1u << 21)) {
+                atomicOr(sync + 1, 1u);
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// The fused step of one time step (neighbour rows; cross-level and
+// same-level faces; update with the next step's cell stage) as one launch
+// over the work lists of StepArgs, whose pointers and counts are read from
+// device memory: a captured launch stays valid when an adaptation replaces
+// the level set.  Stages are separated by grid barriers.  The cross-level
+// faces (few, long) take the first slots of the face stage's index space.
+// Same arithmetic as the four fused-step kernels.
+template <typename S, int U, int MINW, int CM, int MK>
+__global__ __launch_bounds__(BS, MINW) void k_step_persistent(const StepArgs* __restrict__ A, Phys ph) {
+    const int first = item0(), stride = istride();
+    unsigned int phase = 0;
+    ghost_items<S>(A->lvs, A->ghosts, A->n_ghosts, A->cell_lev, A->cell_slot, A->params, ph, A->neg, first, stride);
+    grid_barrier(A->sync, phase);
+    const int nx = A->n_xfaces;
+    xface_items<S, U, MK>(A->lvs, A->xfaces, nx, A->cell_slot, A->cell_nbr, A->geom, A->params, ph, A->neg, first,
+                          stride);
+    const int fstart = ((first - nx) % stride + stride) % stride;
+    face_full_items<S, U, CM, MK>(A->lvs, A->faces, A->n_faces, A->cell_slot, A->cell_nbr, A->geom, A->params,
+                                  A->bcs, ph, A->fpar, fstart, stride);
+    grid_barrier(A->sync, phase);
+    update_cell_items<S, U, CM>(A->lvs, A->cell_lev, A->cell_slot, A->order, A->n_cells, A->geom, A->cell_frow,
+                                A->faces, A->fpar, A->params, ph, A->cmom, first, stride);
+}
+
+// Arrivals of the barrier counter back to zero before a launch (a kernel, so
+// the captured step holds no memset node).
+__global__ void k_sync_reset(unsigned int* sync) {
+    if (threadIdx.x == 0) sync[0] = 0u;
+}
+
+template <typename KF>
+static hipError_t persistent_grid(KF kernel, int* grid) {
+    int dev = 0, ncu = 0, nb = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, BS, 0);
+    if (e != hipSuccess) return e;
+    const int g = ncu * nb / NXCD * NXCD;
+    if (g < NXCD) return hipErrorInvalidConfiguration;
+    *grid = g;
+    return hipSuccess;
+}
+
+#define MLVS_PERSISTENT(S_, U_, C_, MK_)                                                         \
+    do {                                                                                        \
+        auto kf = k_step_persistent<S_, U_, 2, C_, MK_>;                                         \
+        if ((e = persistent_grid(kf, &g)) != hipSuccess) return e;                               \
+        hipLaunchKernelGGL(kf, dim3(g), dim3(BS), 0, st, A, ph);                                 \
+    } while (0)
+#define MLVS_PERSISTENT_C(S_, U_, MK_)                                                           \
+    do {                                                                                        \
+        if (ph.compat == 8) MLVS_PERSISTENT(S_, U_, 8, MK_);                                     \
+        else MLVS_PERSISTENT(S_, U_, 4, MK_);                                                    \
+    } while (0)
+#define MLVS_PERSISTENT_U(S_)                                                                    \
+    do {                                                                                        \
+        if (ph.mesh_kind) MLVS_PERSISTENT_C(S_, 1, 1);                                           \
+        else if (var == 1) MLVS_PERSISTENT_C(S_, 2, 0);                                          \
+        else MLVS_PERSISTENT_C(S_, 1, 0);                                                        \
+    } while (0)
+
+int persistent_variant_count() { return 2; }
+
+hipError_t launch_step_persistent(int prec, hipStream_t st, const StepArgs* A, unsigned int* sync, Phys ph, int var,
+                                  int* grid_used) {
+    hipError_t e = hipSuccess;
+    int g = 0;
+    hipLaunchKernelGGL(k_sync_reset, dim3(1), dim3(64), 0, st, sync);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (prec == 32) MLVS_PERSISTENT_U(float);
+    else MLVS_PERSISTENT_U(double);
+    if (grid_used) *grid_used = g;
+    return hipGetLastError();
 }
 
 hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFaceItem* items, int n,

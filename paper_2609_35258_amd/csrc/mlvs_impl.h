@@ -114,6 +114,28 @@ struct RemapItem {     // cell moved from an old level to a new one
     PairTable tab;     // dst <- src (null off => identical spaces: copy)
 };
 
+// The persistent step's arguments, in device memory so that a captured
+// launch reads the current level set's work lists and counts.
+struct StepArgs {
+    const LevelDesc* lvs;
+    const GhostItem* ghosts;
+    const FaceItem* faces;       // same-level interior faces, then boundary faces
+    const XFaceItem* xfaces;
+    const int* order;            // cells in traversal order
+    const int* cell_lev;
+    const int* cell_slot;
+    const int* cell_nbr;
+    const int* cell_frow;
+    const CellGeom* geom;
+    const BCDev* bcs;
+    double* params;
+    double* cmom;
+    double* fpar;
+    unsigned long long* neg;
+    unsigned int* sync;          // [0] barrier arrivals (cleared before each launch), [1] sticky error flag
+    int n_ghosts, n_faces, n_xfaces, n_cells;
+};
+
 // Launch wrappers (kernels.hip).  `S` selects float (32) or double (64) storage.
 int variant_count();
 // order: the cells in traversal order (a permutation of 0..n_cells-1)
@@ -134,6 +156,13 @@ hipError_t launch_face_target(int prec, hipStream_t st, const LevelDesc* lv, con
 hipError_t launch_xface(int prec, hipStream_t st, const LevelDesc* lv, const XFaceItem* items, int n,
                         const int* cell_slot, const int* cell_nbr, const CellGeom* geom,
                         const double* params, Phys ph, unsigned long long* neg, int var = 1);
+// The persistent step (one launch per time step over the work lists in A,
+// preceded by a one-thread kernel that clears the barrier counter in sync):
+// `var` 0 or 1 (one or two velocity points per lane and load batch).  The
+// grid is the kernel's occupancy times the number of compute units.
+int persistent_variant_count();
+hipError_t launch_step_persistent(int prec, hipStream_t st, const StepArgs* A, unsigned int* sync, Phys ph, int var,
+                                  int* grid_used);
 // Fused forms for level sets that fit one velocity chunk: reconstruction +
 // target in one wave per face; update + the next step's cell stage in one
 // wave per cell.
