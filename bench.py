@@ -42,6 +42,7 @@ def run_gpu(p, steps, warmup, precision, adapt, graph=True, tune=True):
     s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=adapt, graph=graph)
     s.step(warmup)
     if tune:
+        s.tiles = autotune.autotune_tiles(s, precision)
         s.tuned = autotune.autotune(s, precision)
     torch.cuda.synchronize()
     c0 = s.counters()
@@ -439,6 +440,7 @@ def cylinder_case(steps=200, warmup=100, precision=32, mode="both", Kn=0.1):
     s.step(warmup)
     s.adapt()
     s.step(2)
+    autotune.autotune_tiles(s, precision)
     autotune.autotune(s, precision)
     torch.cuda.synchronize()
     c0 = s.counters()
@@ -601,6 +603,7 @@ def jet_headline(steps, warmup, interval=5, precision=32, with_uvs=True, tune=Tr
     s.step(JET_BASE_STEPS)
     s.set_adapt(dict(JET_ADAPT, interval=interval))
     s.step(max(warmup, 1))
+    tiles = autotune.autotune_tiles(s, precision) if tune else {}
     tuned = autotune.autotune(s, precision) if tune else {}
     torch.cuda.synchronize()
     c0 = s.counters()
@@ -639,7 +642,7 @@ def jet_headline(steps, warmup, interval=5, precision=32, with_uvs=True, tune=Tr
            "adaptations_timed": int(n_adapt), "adapt_ms": t_ad, "adapt_split": split, "levels": len(npts),
            "level_points": [int(x) for x in npts], "level_cells": [int(x) for x in ncells],
            "nbar": float(np.sum(npts * ncells) / np.sum(ncells)), "n_cross": int(ncross), "device_bytes": int(mem_m),
-           "variants": variants,
+           "variants": variants, "tiles": _tiles_summary(tiles),
            "roofline": method_roofline(prof, precision, ups, 1e3 * t_m / steps,
                                        JET_WL + "-mlvs" if precision == 32 else None, variants, interval)}
     if with_uvs:
@@ -651,6 +654,14 @@ def jet_headline(steps, warmup, interval=5, precision=32, with_uvs=True, tune=Tr
     return out, (p, kap, levels, sample)
 
 
+def _tiles_summary(t):
+    """The tile tuner's choice and its step time per candidate (ms)."""
+    if not t:
+        return None
+    return {"chosen": t["tiles"], "from_cache": t["from_cache"],
+            "step_ms": {"%dx%d" % tuple(c): round(ms, 3) for c, ms in zip(t.get("candidates", []), t["all_ms"])}}
+
+
 def _jet_uvs(p, steps, warmup, precision, tune):
     """The UVS form of the headline over the same steps: (result, fields, bytes, seconds)."""
     import torch
@@ -658,6 +669,7 @@ def _jet_uvs(p, steps, warmup, precision, tune):
     from paper_2609_35258_amd import autotune
     u = m.Solver.from_problem(p, precision=precision, compat=4, adapt=None, graph=True)
     u.step(JET_BASE_STEPS + max(warmup, 1))
+    tiles_u = autotune.autotune_tiles(u, precision) if tune else {}
     tuned_u = autotune.autotune(u, precision) if tune else {}
     torch.cuda.synchronize()
     c0 = u.counters()
@@ -674,6 +686,7 @@ def _jet_uvs(p, steps, warmup, precision, tune):
     del u
     torch.cuda.empty_cache()
     res = {"value": upd_u / t_u, "ms_per_step": 1e3 * t_u / steps, "device_bytes": int(mem_u), "variants": var_u,
+           "tiles": _tiles_summary(tiles_u),
            "roofline": method_roofline(prof_u, precision, upd_u / steps, 1e3 * t_u / steps,
                                        JET_WL + "-uvs" if precision == 32 else None, var_u)}
     return res, f_u, mem_u, t_u
@@ -1000,7 +1013,7 @@ def main():
                       "levels": head["levels"], "level_points": head["level_points"],
                       "level_cells": head["level_cells"], "nbar": head["nbar"], "n_cross": head["n_cross"],
                       "updates_per_step": head["updates_per_step"], "device_bytes": head["device_bytes"],
-                      "graph": True, "variants": head["variants"]},
+                      "graph": True, "variants": head["variants"], "tiles": head["tiles"]},
            "roofline": head["roofline"]}
     if "uvs" in head:
         out["uvs"] = head["uvs"]

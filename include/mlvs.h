@@ -318,6 +318,21 @@ mlvs_status mlvs_set_persistent(mlvs_ctx ctx, int on);
 mlvs_status mlvs_graph_info(mlvs_ctx ctx, int* persistent, int64_t* captures, int64_t* launches, int* grid,
                             int* error);
 
+/* Traversal tiles of a 2-D structured mesh: cells (and the faces, by their
+ * left cells) are visited tw x th cells at a time, row-major inside a tile and
+ * over tiles, and each level stores its cells' rows in that order, so a run
+ * of consecutive work items reads a compact patch of rows and its stencil halo
+ * (L2 reuse on one XCD).  tw = th = 0: row-major.  The default is 16 x 8
+ * (environment MLVS_TILE=WxH at creation overrides it).  Changing the tiles
+ * reorders every level's state rows on the device (a copy, values unchanged)
+ * and drops a captured step graph; results of later steps do not depend on
+ * the tiles.  Errors: MLVS_E_ARG for tw or th outside [0, 4096] or only one of
+ * them 0; MLVS_E_STATE for unstructured or 1-D meshes. */
+mlvs_status mlvs_set_tiling(mlvs_ctx ctx, int tw, int th);
+/* The current traversal tiles (0, 0: row-major or an unstructured mesh's
+ * Morton order).  Either pointer may be NULL. */
+mlvs_status mlvs_tiling(mlvs_ctx ctx, int* tw, int* th);
+
 /* Work counters since creation: steps taken, cell-velocity updates on the
  * cells' own levels (sum over steps of sum over cells of the level size),
  * interface-space points processed on cross-level faces, adaptations. */

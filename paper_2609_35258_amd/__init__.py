@@ -125,6 +125,8 @@ _PROTOS = {
                                      ctypes.POINTER(ctypes.c_int64)]),
     "mlvs_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "mlvs_set_persistent": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "mlvs_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "mlvs_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "mlvs_graph_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_int)]),
@@ -350,6 +352,7 @@ class Solver:
             _check(L.mlvs_set_graph(self.h, 1))
         self.n_cells = n_cells
         self.dim = dim
+        self.structured = umesh is None and dim == 2       # traversal tiles apply
         dt_ = ctypes.c_double()
         nc = ctypes.c_int64()
         nb = ctypes.c_int32()
@@ -546,6 +549,16 @@ class Solver:
 
     def set_persistent(self, on: bool = True):
         _check(lib().mlvs_set_persistent(self.h, int(on)))
+
+    def set_tiling(self, tw: int, th: int):
+        """Traversal tiles (tw x th cells; 0, 0 row-major) of a structured mesh;
+        reorders the state rows on the device, values unchanged."""
+        _check(lib().mlvs_set_tiling(self.h, int(tw), int(th)))
+
+    def tiling(self):
+        tw, th = ctypes.c_int(), ctypes.c_int()
+        _check(lib().mlvs_tiling(self.h, ctypes.byref(tw), ctypes.byref(th)))
+        return tw.value, th.value
 
     def graph_info(self):
         """{persistent, captures, launches, grid, error} of the step launches."""

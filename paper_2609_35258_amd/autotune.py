@@ -1,4 +1,5 @@
-"""Autotuner for the launch variants of the step's kernels.
+"""Autotuner for the launch variants of the step's kernels and the traversal
+tiles of structured meshes.
 
 For each tunable stage the library holds several instantiations of the kernel
 (pairs of velocity points per lane per load batch and minimum waves per SIMD,
@@ -11,6 +12,13 @@ variants the stage has and a hash of the built library, so later runs of the
 same shape with the same kernels skip the sweep, and a rebuilt library or a
 new variant sweeps again.  Variants only change scheduling, never the
 results.
+
+The traversal tiles (``Solver.set_tiling``: tw x th cells visited, and their
+rows stored, together) set which stencil rows meet in one XCD's L2.  The tile
+tuner times one whole step (the sum over the stages the step launches of
+their mean launch time) for each candidate shape on the current state and
+level set, keeps the fastest and caches it keyed by the mesh, the step's
+stages and the mean level size.  Tiles do not change the results either.
 """
 from __future__ import annotations
 
@@ -20,6 +28,7 @@ import json
 import os
 from typing import Dict, Iterable, Optional
 
+TILES = ((16, 8), (32, 8), (8, 8), (32, 4), (64, 4), (16, 16), (8, 16), (0, 0))
 TUNABLE = ("cell", "face_rec", "face_target", "xface", "update", "face", "update_cell", "persistent")
 
 
@@ -62,13 +71,7 @@ def autotune(solver, precision: int, stages: Optional[Iterable[str]] = None, rep
     if stages is None:
         stages = [st for st in solver.step_stages() if st in TUNABLE]
     path = cache or default_cache()
-    table = {}
-    if os.path.exists(path):
-        try:
-            with open(path) as f:
-                table = json.load(f)
-        except (OSError, ValueError):
-            table = {}
+    table = _load(path)
     out = {}
     for st in stages:
         key = shape_key(solver, st, precision)
@@ -87,10 +90,66 @@ def autotune(solver, precision: int, stages: Optional[Iterable[str]] = None, rep
         solver.set_variant(st, best)
         table[key] = {"variant": best, "ms": times[best], "all_ms": times}
         out[st] = dict(table[key], key=key, from_cache=False)
+    _store(path, table)
+    return out
+
+
+def _load(path):
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                return json.load(f)
+        except (OSError, ValueError):
+            pass
+    return {}
+
+
+def _store(path, table):
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         with open(path, "w") as f:
             json.dump(table, f, indent=1, sort_keys=True)
     except OSError:
         pass
-    return out
+
+
+def step_ms(solver, reps: int = 3) -> float:
+    """Mean time of one step as the sum of its stages' mean launch times."""
+    total = 0.0
+    for st in solver.step_stages():
+        if solver.stage_size(st)[0] == 0:
+            continue
+        solver.time_stage(st, 1)
+        total += solver.time_stage(st, reps)
+    return total
+
+
+def autotune_tiles(solver, precision: int, candidates: Iterable = TILES, reps: int = 3,
+                   cache: Optional[str] = None, force: bool = False) -> dict:
+    """Choose the traversal tiles with the shortest step; returns {tiles, ms,
+    all_ms, key, from_cache}, or {} where tiles do not apply (unstructured or
+    1-D meshes)."""
+    if not getattr(solver, "structured", False):
+        return {}
+    import numpy as np
+    npts, ncells, _ = solver.level_info()
+    nbar = int(round(float(np.sum(np.asarray(npts) * np.asarray(ncells)) / max(int(np.sum(ncells)), 1))))
+    key = "%s|fp%d|tiles|cells%d|%s|pts<=%d|lib%s" % (
+        _arch(), precision, solver.n_cells, "+".join(solver.step_stages()), 1 << max(nbar - 1, 1).bit_length(),
+        _lib_tag())
+    path = cache or default_cache()
+    table = _load(path)
+    if key in table and not force:
+        solver.set_tiling(*table[key]["tiles"])
+        return dict(table[key], key=key, from_cache=True)
+    cands = [tuple(t) for t in candidates]
+    times = []
+    for t in cands:
+        solver.set_tiling(*t)
+        times.append(step_ms(solver, reps))
+    best = min(range(len(cands)), key=lambda k: times[k])
+    solver.set_tiling(*cands[best])
+    table[key] = {"tiles": list(cands[best]), "ms": times[best], "all_ms": times,
+                  "candidates": [list(t) for t in cands]}
+    _store(path, table)
+    return dict(table[key], key=key, from_cache=False)

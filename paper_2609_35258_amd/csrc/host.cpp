@@ -999,6 +999,7 @@ struct mlvs_ctx_s {
     // lists of a device-resident StepArgs, rewritten in place by every level
     // install, so the captured step survives adaptations
     bool persistent = false;
+    int tile_w = 0, tile_h = 0;        // traversal tiles of a structured mesh (mlvs_set_tiling)
     StepArgs* d_args = nullptr;
     unsigned int* d_sync = nullptr;    // [0] barrier arrivals, [1] sticky error flag
     int persistent_grid = 0;
@@ -1433,6 +1434,66 @@ void assign_slots(mlvs_ctx c) {
 }
 
 void sync(mlvs_ctx c) { hip_check(hipStreamSynchronize(c->st), "stream synchronize"); }
+
+void build_items(mlvs_ctx c);
+
+// After a new traversal order: slots in that order, every level's state rows
+// and prepared cell-stage rows gathered to their new slots, the cell-indexed
+// moments and parameters kept, so the next step computes exactly what it
+// would have computed before (a copy, no arithmetic).
+void retile_rows(mlvs_ctx c) {
+    const int n = c->mesh.n_cells;
+    const std::vector<int> old_slot = c->cell_slot;
+    assign_slots(c);
+    const int K = (int)c->levels.size();
+    std::vector<std::vector<int>> src(K);
+    for (int l = 0; l < K; ++l) src[l].assign(c->levels[l]->n_cells, 0);
+    for (int cc = 0; cc < n; ++cc) src[c->cell_level[cc]][c->cell_slot[cc]] = old_slot[cc];
+    struct Old { void *g, *h, *fg, *fh; };
+    std::vector<Old> old(K);
+    for (int l = 0; l < K; ++l) {
+        Level& L = *c->levels[l];
+        old[l] = {L.g, L.h, L.fg, L.fh};
+        L.fg = L.fh = nullptr;             // kept here until copied; build_items allocates new rows
+        alloc_state(c, L);
+    }
+    const bool mom = c->mom_valid, prep = c->prep_valid;
+    const size_t cm_bytes = sizeof(double) * NMOM * c->nch * (size_t)std::max(n, 1);
+    void* cm = nullptr;
+    if (mom && c->d_cmom) {
+        cm = c->dm.alloc(cm_bytes);
+        hip_check(hipMemcpyAsync(cm, c->d_cmom, cm_bytes, hipMemcpyDeviceToDevice, c->st), "D2D");
+    }
+    const int nch = c->nch;
+    build_items(c);
+    std::vector<size_t> off(K + 1, 0);
+    for (int l = 0; l < K; ++l) off[l + 1] = off[l] + src[l].size();
+    int* d_src = static_cast<int*>(c->dm.alloc(sizeof(int) * std::max<size_t>(off[K], 1)));
+    std::vector<int> flat;
+    flat.reserve(off[K]);
+    for (auto& v : src) flat.insert(flat.end(), v.begin(), v.end());
+    hip_check(hipMemcpyAsync(d_src, flat.data(), sizeof(int) * flat.size(), hipMemcpyHostToDevice, c->st), "H2D");
+    for (int l = 0; l < K; ++l) {
+        Level& L = *c->levels[l];
+        const int w16 = (int)((size_t)L.stride * c->elt() / 16);
+        const int* rows = d_src + off[l];
+        hip_check(launch_gather_rows_16(c->st, old[l].g, w16, rows, L.n_cells, L.g), "gather launch");
+        hip_check(launch_gather_rows_16(c->st, old[l].h, w16, rows, L.n_cells, L.h), "gather launch");
+        if (prep && old[l].fg) {
+            hip_check(launch_gather_rows_16(c->st, old[l].fg, w16, rows, L.n_cells, L.fg), "gather launch");
+            hip_check(launch_gather_rows_16(c->st, old[l].fh, w16, rows, L.n_cells, L.fh), "gather launch");
+        }
+    }
+    const bool keep_mom = cm && c->nch == nch;
+    if (keep_mom) hip_check(hipMemcpyAsync(c->d_cmom, cm, cm_bytes, hipMemcpyDeviceToDevice, c->st), "D2D");
+    sync(c);
+    for (int l = 0; l < K; ++l)
+        for (void* p : {old[l].g, old[l].h, old[l].fg, old[l].fh}) c->dm.release(p);
+    c->dm.release(cm);
+    c->dm.release(d_src);
+    c->mom_valid = keep_mom;
+    c->prep_valid = prep && keep_mom;
+}
 
 void do_step(mlvs_ctx c);
 // The cell stage reads the raw moments of the stored state from d_cmom; the
@@ -2458,6 +2519,8 @@ static mlvs_status create_impl(const mlvs_physics* phys, const mlvs_mesh* mesh, 
             }
             if (phys->dim != 2) tw = th = 0;
             tile_order(c->mesh, tw, th);
+            c->tile_w = tw;
+            c->tile_h = th;
         }
         if (mesh) c->bcs.assign(mesh->bcs, mesh->bcs + mesh->n_bc);
         else c->bcs.assign(umesh->bcs, umesh->bcs + umesh->n_bc);
@@ -2712,6 +2775,28 @@ mlvs_status mlvs_set_persistent(mlvs_ctx c, int on) {
     });
 }
 
+mlvs_status mlvs_set_tiling(mlvs_ctx c, int tw, int th) {
+    return guarded([&] {
+        if (!c) fail(MLVS_E_ARG, "null context");
+        if (tw < 0 || th < 0 || tw > 4096 || th > 4096 || ((tw == 0) != (th == 0)))
+            fail(MLVS_E_ARG, "bad tiles %d x %d", tw, th);
+        if (c->mesh.unstructured || c->phys.dim != 2) fail(MLVS_E_STATE, "tiles apply to 2-D structured meshes");
+        if (tw == c->tile_w && th == c->tile_h) return;
+        tile_order(c->mesh, tw, th);
+        c->tile_w = tw;
+        c->tile_h = th;
+        retile_rows(c);
+    });
+}
+
+mlvs_status mlvs_tiling(mlvs_ctx c, int* tw, int* th) {
+    return guarded([&] {
+        if (!c) fail(MLVS_E_ARG, "null context");
+        if (tw) *tw = c->tile_w;
+        if (th) *th = c->tile_h;
+    });
+}
+
 mlvs_status mlvs_graph_info(mlvs_ctx c, int* persistent, int64_t* captures, int64_t* launches, int* grid,
                             int* error) {
     return guarded([&] {
@@ -2755,11 +2840,11 @@ mlvs_status mlvs_time_stage(mlvs_ctx c, int stage, int reps, double* ms) {
         if (!c || !ms || reps < 1 || stage < 0 || stage > 9) fail(MLVS_E_ARG, "bad arguments");
         if ((stage == 7 || stage == 8) && !c->fused) fail(MLVS_E_STATE, "fused stages need levels of one chunk");
         if (stage == 9 && !c->persistent) fail(MLVS_E_STATE, "the persistent step is off (mlvs_set_persistent)");
+        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
         if (stage == 9 && !c->prep_valid) {
             hip_check(launch_stage(c, 0), "cell stage launch");
             c->prep_valid = true;
         }
-        if (!c->state_ready) fail(MLVS_E_STATE, "state not initialised");
         if (stage == 6 && !c->adaptive) fail(MLVS_E_STATE, "criterion needs adaptation parameters");
         ensure_moments(c);
         // every stage but the update only rewrites its own outputs; the update

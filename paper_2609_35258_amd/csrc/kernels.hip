@@ -2839,6 +2839,16 @@ __global__ void k_gather_rows_u8(const uint8_t* __restrict__ src, int width, con
         for (int k = lane_id(); k < width; k += WL) dst[(size_t)r * width + k] = src[(size_t)rows[r] * width + k];
 }
 
+// Row gather in 16-byte units: dst row r is src row rows[r].
+__global__ void k_gather_rows_16(const uint4* __restrict__ src, int width16, const int* __restrict__ rows, int n,
+                                 uint4* __restrict__ dst) {
+    for (int r = item0(); r < n; r += istride()) {
+        const uint4* a = src + (size_t)rows[r] * width16;
+        uint4* b = dst + (size_t)r * width16;
+        for (int k = lane_id(); k < width16; k += WL) b[k] = a[k];
+    }
+}
+
 __global__ void k_compare_rows_u8(const uint8_t* __restrict__ all, int width, const int* __restrict__ rep_of_cell,
                                   const uint8_t* __restrict__ reps, int n, unsigned long long* mismatch) {
     for (int c = item0(); c < n; c += istride()) {
@@ -2972,6 +2982,13 @@ hipError_t launch_criterion(int prec, hipStream_t st, const LevelDesc* lv, const
     MLVS_DISPATCH(prec, k_criterion, dim3(grid_for(n_cells)), dim3(BS), 0, st, lv, cell_lev, cell_slot, n_cells,
                   pt_of_base_all, pt_off, ptab_all, ptab_off, kappa_all, ctab, axes, nx, ny, C_split, C_merge,
                   eps_merge, flux_test, kappa_out, hash_out, cell_list);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows_16(hipStream_t st, const void* src, int width16, const int* rows, int n, void* dst) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_rows_16, dim3(grid_for(n)), dim3(BS), 0, st, static_cast<const uint4*>(src), width16,
+                       rows, n, static_cast<uint4*>(dst));
     return hipGetLastError();
 }
 

@@ -201,6 +201,8 @@ hipError_t launch_criterion(int prec, hipStream_t st, const LevelDesc* lv, const
                             const uint8_t* kappa_all, const double* ctab, const double* axes, int nx, int ny,
                             double C_split, double C_merge, double eps_merge, int flux_test,
                             uint8_t* kappa_out, unsigned long long* hash_out, const int* cell_list = nullptr);
+// dst row r (width16 units of 16 bytes) = src row rows[r], r < n
+hipError_t launch_gather_rows_16(hipStream_t st, const void* src, int width16, const int* rows, int n, void* dst);
 hipError_t launch_gather_rows_u8(hipStream_t st, const uint8_t* src, int width, const int* rows, int n,
                                  uint8_t* dst);
 hipError_t launch_compare_rows_u8(hipStream_t st, const uint8_t* all, int width, const int* rep_of_cell,
