@@ -358,7 +358,9 @@ class Solver:
 
     def step(self):
         ap = self.adapt_params
-        if ap is not None and self.step_count % ap.interval == 0:
+        # reading R23: step 0 and every `interval` steps; interval 0 adapts
+        # only when adapt() is called
+        if ap is not None and ap.interval > 0 and self.step_count % ap.interval == 0:
             self.adapt()
         m = self.mesh
         dt = self.dt

@@ -214,6 +214,21 @@ def test_tau_one_gives_a_single_shared_level():
     assert all(np.allclose(x, y, rtol=0, atol=1e-15) for x, y in zip(b.g, c.g))
 
 
+def test_interval_zero_adapts_only_when_asked():
+    # reading R23: with interval 0 the steps never adapt by themselves; the
+    # result equals the same steps without adaptation parameters
+    p = _mlvs_problem()
+    a = Solver(p, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 0.0, 0.05, False, 0))
+    b = Solver(p, compat=4)
+    for _ in range(2):
+        a.step()
+        b.step()
+    assert len(a.levels) == 1 and a.step_count == 2
+    assert all(np.array_equal(x, y) for x, y in zip(a.g, b.g))
+    a.adapt()
+    assert any(L.N < a.base.N for L in a.levels)
+
+
 def test_runtime_model_fit_reproduces_paper():
     rows = np.loadtxt(os.path.join(GOLD, "h9_threshold.txt"))
     tau, nrep, nbar, ncross, meas, model = rows.T
