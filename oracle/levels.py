@@ -79,6 +79,13 @@ class Level:
             wg = base.w[g]
             self.w[p] = wg.sum()
             self.xi[p] = (wg[:, None] * base.xi[g]).sum(0) / self.w[p]
+            if len(g) > 1:
+                # reading R34: a component of a merged point that cancels by the
+                # grid's symmetry is zero, not the rounding residue of the mean,
+                # so that xi . n = 0 on faces along the axes (Eq. reconstruction,
+                # reading R6) is decided as in exact arithmetic
+                ext = np.max(np.abs(base.xi[g]), axis=0)
+                self.xi[p][np.abs(self.xi[p]) <= 1e-12 * ext] = 0.0
 
     def key(self):
         return self.kappa.tobytes()

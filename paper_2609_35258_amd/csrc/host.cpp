@@ -321,6 +321,29 @@ void check_kappa(const Base& B, const uint8_t* k) {
         }
 }
 
+// Velocity and weight of a point made of the base points g: the w-weighted
+// mean and the sum.  A component of a merged point that cancels by the grid's
+// symmetry (within 1e-12 of the members' largest |coordinate|) is exactly
+// zero rather than the rounding residue of the mean, so that xi . n = 0 on
+// faces along the axes is decided as in exact arithmetic.
+void merged_point(const Base& B, const std::vector<int>& g, double& ws, double& x, double& y) {
+    double sx = 0.0, sy = 0.0, ex = 0.0, ey = 0.0;
+    ws = 0.0;
+    for (int b : g) ws += B.w[b];
+    for (int b : g) {
+        sx += B.w[b] * B.x[b];
+        sy += B.w[b] * B.y[b];
+        ex = std::max(ex, std::fabs(B.x[b]));
+        ey = std::max(ey, std::fabs(B.y[b]));
+    }
+    x = sx / ws + 0.0;                  // + 0.0: no negative zeros
+    y = sy / ws + 0.0;
+    if (g.size() > 1) {
+        if (std::fabs(x) <= 1e-12 * ex) x = 0.0;
+        if (std::fabs(y) <= 1e-12 * ey) y = 0.0;
+    }
+}
+
 std::unique_ptr<Level> build_level(const Base& B, const std::vector<uint8_t>& kappa) {
     auto L = std::make_unique<Level>();
     L->kappa = kappa;
@@ -361,9 +384,8 @@ std::unique_ptr<Level> build_level(const Base& B, const std::vector<uint8_t>& ka
         const int n = (int)groups.size();
         std::vector<double> ang(n), r2(n);
         for (int p = 0; p < n; ++p) {
-            double ws = 0.0, sx = 0.0, sy = 0.0;
-            for (int b : groups[p]) { ws += B.w[b]; sx += B.w[b] * B.x[b]; sy += B.w[b] * B.y[b]; }
-            const double x = sx / ws + 0.0, y = sy / ws + 0.0;   // + 0.0: no negative zeros
+            double ws, x, y;
+            merged_point(B, groups[p], ws, x, y);
             ang[p] = std::atan2(y, x);
             r2[p] = x * x + y * y;
         }
@@ -386,16 +408,11 @@ std::unique_ptr<Level> build_level(const Base& B, const std::vector<uint8_t>& ka
     L->xi_y.resize(L->N);
     L->w.resize(L->N);
     for (int p = 0; p < L->N; ++p) {
-        double ws = 0.0, sx = 0.0, sy = 0.0;
         for (int b : groups[p]) {
             L->pt_of_base[b] = p;
             L->mem_idx.push_back(b);
-            ws += B.w[b];
         }
-        for (int b : groups[p]) { sx += B.w[b] * B.x[b]; sy += B.w[b] * B.y[b]; }
-        L->w[p] = ws;
-        L->xi_x[p] = sx / ws;
-        L->xi_y[p] = sy / ws;
+        merged_point(B, groups[p], L->w[p], L->xi_x[p], L->xi_y[p]);
         L->mem_off[p + 1] = (int)L->mem_idx.size();
     }
     // criterion tables of the points (normalisations S_r of Eq. merge-transport-error)

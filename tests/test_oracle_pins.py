@@ -308,3 +308,51 @@ def test_positivity_band_both_sides():
         s.exp_count = 0
         s.positivity_fallback(lev, gq, hp, gs, hp.copy(), tgt)
         assert (s.exp_count == 1) == takes
+
+
+def _mirror_problem():
+    """A periodic box on the 28-point Gauss-Hermite grid whose state is mirror
+    symmetric about the horizontal mid-line (rho, u, T even in y, v odd)."""
+    import dataclasses
+    import math
+    p = W.periodic_box(6, 8, Lx=1.0, Ly=1.0, Kn=0.05, nv=28)
+    yc = (np.arange(p.nj) + 0.5) / p.nj
+    xc = (np.arange(p.ni) + 0.5) / p.ni
+    Yc, Xc = np.meshgrid(yc, xc, indexing="ij")
+    return dataclasses.replace(p, vel_kind="gh", gh_scale_T=1.0,
+                               rho0=1.0 + 0.3 * np.cos(2 * math.pi * Yc) + 0.1 * np.sin(2 * math.pi * Xc),
+                               u0=0.2 * np.cos(2 * math.pi * Yc), v0=0.15 * np.sin(2 * math.pi * Yc),
+                               T0=1.0 + 0.2 * np.cos(2 * math.pi * Yc))
+
+
+def test_merged_points_on_a_symmetry_axis_keep_the_mirror_symmetry():
+    # Reading R34.  The 4x4 blocks of nodes 12..15 straddle xi_y = 0 on the
+    # 28-point Gauss-Hermite grid, so their merged points lie on the axis; a
+    # state mirror-symmetric in y then stays symmetric to round-off (the
+    # reflected cell at the reflected velocity), which it does not if the sign
+    # of the mean's rounding residue picks the upwind side at xi . n = 0.
+    from oracle.solver import Solver
+    p = _mirror_problem()
+    o = Solver(p, compat=4)
+    nb = p.nv // 2
+    k = np.zeros((nb, nb), np.uint8)
+    k[6:8, 0:4] = 2                      # quads qy = 3, qx = 0, 1 (blocks by 6..7)
+    k[6:8, 10:14] = 2                    # quads qy = 3, qx = 5, 6
+    kap = k.ravel()
+    lev = lv.Level(o.base, kap)
+    axis = [q for q in range(lev.N) if len(lev.members[q]) == 16]
+    assert len(axis) == 4 and all(lev.xi[q, 1] == 0.0 for q in axis)
+    # the mirror image of every level point is a level point
+    key = {(round(x, 12), round(y, 12)): q for q, (x, y) in enumerate(lev.xi)}
+    mirror = np.array([key[(round(x, 12), round(-y + 0.0, 12))] for x, y in lev.xi])
+    o.set_levels([kap], np.zeros(p.n_cells, np.int64))
+    for _ in range(3):
+        o.step()
+    ni, nj = p.ni, p.nj
+    scale = max(np.max(np.abs(g)) for g in o.g)
+    worst = 0.0
+    for j in range(nj):
+        for i in range(ni):
+            a, b = i + ni * j, i + ni * (nj - 1 - j)
+            worst = max(worst, np.max(np.abs(o.g[a] - o.g[b][mirror])) / scale)
+    assert worst < 1e-13, worst
