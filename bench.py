@@ -598,7 +598,7 @@ def jet_headline(steps, warmup, interval=5, precision=32, with_uvs=True, tune=Tr
     from paper_2609_35258_amd import autotune
     p = W.jet(512, 256, Kn_jet=1e-3, nv=161, vmax=7.0)
     if not with_mlvs:
-        return {"uvs": _jet_uvs(p, steps, warmup, precision, tune)[0]}, None
+        return {"uvs": _jet_uvs(p, steps, warmup, precision, tune)[0]}
     s = m.Solver.from_problem(p, precision=precision, compat=4, adapt=dict(JET_ADAPT, interval=0), graph=True)
     s.step(JET_BASE_STEPS)
     s.set_adapt(dict(JET_ADAPT, interval=interval))
@@ -631,9 +631,6 @@ def jet_headline(steps, warmup, interval=5, precision=32, with_uvs=True, tune=Tr
         split.append({k: round(r[k], 3) for k in ("ms_criterion", "ms_dedupe", "ms_cluster", "ms_install")}
                      | {"n_unique": r["n_unique"], "n_changed": r["n_changed"]})
     variants = {k: v["variant"] for k, v in tuned.items()}
-    kap = np.stack([s.level_kappa(k) for k in range(len(npts))])
-    levels = s.cell_levels()
-    sample = _jet_patch(p, s, levels)
     s.close()
     del s
     torch.cuda.empty_cache()
@@ -651,7 +648,7 @@ def jet_headline(steps, warmup, interval=5, precision=32, with_uvs=True, tune=Tr
         out["uvs"].update({"time_to_solution_ratio": t_u / t_m, "memory_ratio": mem_u / mem_m,
                            "mlvs_vs_uvs_rel_l2": err,
                            "meets_1e-3_gate_rho_T": bool(err["rho"] <= 1e-3 and err["T"] <= 1e-3)})
-    return out, (p, kap, levels, sample)
+    return out
 
 
 def _tiles_summary(t):
@@ -692,42 +689,38 @@ def _jet_uvs(p, steps, warmup, precision, tune):
     return res, f_u, mem_u, t_u
 
 
-def _jet_patch(p, s, levels, size=12):
-    """The 12 x 12-cell window of the jet with the most distinct levels (ties:
-    the first in row-major order), with its cells' states: the CPU baseline's
-    sample."""
-    ni, nj = p.ni, p.nj
-    L = levels.reshape(nj, ni)
-    best, key = None, None
-    for j0 in range(0, nj - size + 1, size):
-        for i0 in range(0, ni - size + 1, size):
-            w = L[j0:j0 + size, i0:i0 + size]
-            k = (len(np.unique(w)), int(np.sum(w[:, 1:] != w[:, :-1]) + np.sum(w[1:, :] != w[:-1, :])))
-            if key is None or k > key:
-                best, key = (i0, j0), k
-    i0, j0 = best
-    cells = [(i0 + a) + ni * (j0 + b) for b in range(size) for a in range(size)]
-    return {"i0": i0, "j0": j0, "size": size, "cells": cells, "state": [s.get_cell(c) for c in cells],
-            "dt": s.dt}
+CPU_WINDOW = dict(i0=0, j0=122, size=12, levels=6, seed=11, amp=0.2, p8=0.55, p4=0.45, p2=0.6)
+
+
+def _cpu_window():
+    """The CPU baseline's sample, from seeded inputs only: the 12 x 12 cells of
+    the jet at its slot (initial state with a seeded perturbation), six seeded
+    random coarsening masks on the 80 x 80 blocks of the 161^2 grid (about 4000
+    points each, the headline's mean level size), and cells assigned to them
+    in seeded 4 x 4-cell blocks, so the window holds cross-level faces."""
+    w = CPU_WINDOW
+    p = W.jet(512, 256, Kn_jet=1e-3, nv=161, vmax=7.0)
+    q = W.perturb(W.patch(p, w["i0"], w["j0"], w["size"], w["size"]), seed=w["seed"], amp=w["amp"])
+    nb = p.nv // 2
+    kap = [W.random_kappa(nb, nb, w["seed"] + k, p8=w["p8"], p4=w["p4"], p2=w["p2"]) for k in range(w["levels"])]
+    rng = np.random.default_rng(w["seed"])
+    nblk = w["size"] // 4
+    blk = rng.integers(0, w["levels"], size=(nblk, nblk))
+    cl = np.repeat(np.repeat(blk, 4, axis=0), 4, axis=1).ravel().astype(np.int32)
+    return q, kap, cl
 
 
 def _oracle_patch_work(args):
-    """One CPU worker: an oracle MLVS step of the patch (from the GPU's state and
-    levels) plus the criterion on `n_crit` of its cells.  Returns (seconds of
-    the step, seconds per criterion cell, cell-velocity updates of the step)."""
-    path, n_crit = args
+    """One CPU worker: an oracle MLVS step of the seeded window plus the
+    criterion on `n_crit` of its cells.  Returns (seconds of the step, seconds
+    per criterion cell, cell-velocity updates of the step, mean level size)."""
+    n_crit, = args
     from oracle import levels as lv_
     from oracle.solver import AdaptParams, Solver as Oracle
-    d = np.load(path, allow_pickle=False)
-    p = W.jet(512, 256, Kn_jet=1e-3, nv=161, vmax=7.0)
-    q = W.patch(p, int(d["i0"]), int(d["j0"]), int(d["size"]), int(d["size"]))
-    o = Oracle(q, compat=4, dt=float(d["dt"]),
-               adapt=AdaptParams(JET_ADAPT["C_split"], JET_ADAPT["C_merge"], JET_ADAPT["eps_merge"],
-                                 JET_ADAPT["tau_clust"], True, 0))
-    o.set_levels(list(d["kap"]), d["levels"])
-    off = d["off"]
-    o.g = [d["g"][off[c]:off[c + 1]].copy() for c in range(len(off) - 1)]
-    o.h = [d["h"][off[c]:off[c + 1]].copy() for c in range(len(off) - 1)]
+    q, kap, cl = _cpu_window()
+    o = Oracle(q, compat=4, adapt=AdaptParams(JET_ADAPT["C_split"], JET_ADAPT["C_merge"], JET_ADAPT["eps_merge"],
+                                              JET_ADAPT["tau_clust"], True, 0))
+    o.set_levels(kap, cl)
     ap = o.adapt_params
     t0 = time.perf_counter()
     for c in range(n_crit):
@@ -738,7 +731,8 @@ def _oracle_patch_work(args):
     o.adapt_params = None
     o.step()
     t_step = time.perf_counter() - t0
-    return t_step, t_crit, float(sum(len(g) for g in o.g))
+    n = float(sum(len(g) for g in o.g))
+    return t_step, t_crit, n, n / len(o.g)
 
 
 def _host_cpu():
@@ -757,55 +751,47 @@ def _host_cpu():
     return {"nproc": avail, "cpu_count": os.cpu_count(), "model": model}
 
 
-def cpu_baseline(jet_sample, interval=5, n_crit=4, max_workers=16):
+def cpu_baseline(interval=5, n_crit=4, max_workers=16):
     """The oracle as it stands, timed on the host: an MLVS step of a 12 x 12-cell
-    window of the headline jet (the GPU's state, levels and time step) plus the
-    criterion on a few of its cells, amortised over the adaptation interval;
-    once on one core and once on every core of the process's CPU share (the
-    same task in each of min(16, available) worker processes)."""
+    window of the jet from seeded inputs (`_cpu_window`) plus the criterion on a
+    few of its cells, amortised over the adaptation interval; once on one core
+    and once on every core of the process's CPU share (the same task in each of
+    min(16, available) worker processes)."""
     import multiprocessing as mp
-    import tempfile
-    p, kap, levels, sample = jet_sample
-    cells = sample["cells"]
-    g = np.concatenate([st[0] for st in sample["state"]])
-    h = np.concatenate([st[1] for st in sample["state"]])
-    off = np.concatenate([[0], np.cumsum([len(st[0]) for st in sample["state"]])])
     host = _host_cpu()
-    with tempfile.TemporaryDirectory() as tmp:
-        path = os.path.join(tmp, "patch.npz")
-        np.savez(path, i0=sample["i0"], j0=sample["j0"], size=sample["size"], dt=sample["dt"], kap=kap,
-                 levels=np.asarray(levels)[cells], g=g, h=h, off=off)
-        ctx = mp.get_context("spawn")
-        # one thread per worker process (numpy's BLAS would otherwise start its own)
-        saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
-        os.environ.update({k: "1" for k in saved})
-        try:
-            with ctx.Pool(1) as pool:
-                t1, c1, n1 = pool.map(_oracle_patch_work, [(path, n_crit)])[0]
-            P = max(1, min(max_workers, host["nproc"] or 1))
-            t0 = time.perf_counter()
-            with ctx.Pool(P) as pool:
-                res = pool.map(_oracle_patch_work, [(path, n_crit)] * P)
-            wall = time.perf_counter() - t0
-        finally:
-            for k, v in saved.items():
-                if v is None:
-                    os.environ.pop(k, None)
-                else:
-                    os.environ[k] = v
-    ncell = len(cells)
+    ctx = mp.get_context("spawn")
+    # one thread per worker process (numpy's BLAS would otherwise start its own)
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    os.environ.update({k: "1" for k in saved})
+    try:
+        with ctx.Pool(1) as pool:
+            t1, c1, n1, nbar = pool.map(_oracle_patch_work, [(n_crit,)])[0]
+        P = max(1, min(max_workers, host["nproc"] or 1))
+        t0 = time.perf_counter()
+        with ctx.Pool(P) as pool:
+            res = pool.map(_oracle_patch_work, [(n_crit,)] * P)
+        wall = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    w = CPU_WINDOW
+    ncell = w["size"] ** 2
     rate1 = n1 / (t1 + c1 * ncell / interval)
     # all cores: every worker did the same step and criterion cells
     tP = max(r[0] for r in res)
     cP = max(r[1] for r in res)
     rateP = P * n1 / (tP + cP * ncell / interval)
     return {"value": rateP, "unit": "cell-velocity updates/s", "cores": P, "kind": "oracle",
-            "sample": "oracle MLVS step of the 12x12-cell window at cells (%d..%d, %d..%d) of the jet (%d levels in "
-                      "it, %.4g cell-velocity updates, the GPU's state and levels) plus the criterion on %d of its "
-                      "cells, amortised over %d steps; %d worker processes each running that task (one oracle and one "
-                      "BLAS thread per process), slowest worker's times" % (
-                          sample["i0"], sample["i0"] + 11, sample["j0"], sample["j0"] + 11,
-                          len(np.unique(np.asarray(levels)[cells])), n1, n_crit, interval, P),
+            "sample": "oracle MLVS step of the 12x12 cells (%d..%d, %d..%d) of the jet at its slot, from seeded "
+                      "inputs: initial state perturbed (seed %d, amplitude %g), %d seeded random levels (mean %.0f "
+                      "points) on seeded 4x4-cell blocks; %.4g cell-velocity updates; plus the criterion on %d cells, "
+                      "amortised over %d steps; %d worker processes each running that task (one oracle and one BLAS "
+                      "thread per process), slowest worker's times" % (
+                          w["i0"], w["i0"] + 11, w["j0"], w["j0"] + 11, w["seed"], w["amp"], w["levels"], nbar, n1,
+                          n_crit, interval, P),
             "host": host,
             "single_core": {"value": rate1, "cores": 1, "step_s": t1, "criterion_s_per_cell": c1},
             "all_cores": {"value": rateP, "cores": P, "step_s": tP, "criterion_s_per_cell": cP, "wall_s": wall}}
@@ -992,10 +978,10 @@ def main():
                                                     Kn=args.cylinder_kn)}), flush=True)
         return
     if args.jet_only and args.jet_mode == "uvs":
-        print(json.dumps({"jet": jet_headline(args.steps, args.warmup, with_mlvs=False, tune=not args.no_tune)[0]}),
+        print(json.dumps({"jet": jet_headline(args.steps, args.warmup, with_mlvs=False, tune=not args.no_tune)}),
               flush=True)
         return
-    head, sample = jet_headline(args.steps, args.warmup, args.interval, with_uvs=not args.no_uvs
+    head = jet_headline(args.steps, args.warmup, args.interval, with_uvs=not args.no_uvs
                                 and args.jet_mode != "mlvs", tune=not args.no_tune)
     out = {"metric": "DUGKS cell·velocity updates/s, MLVS vs UVS time-to-solution at ≤1e-3 rel L2",
            "value": head["value"], "unit": "cell-velocity updates/s", "n_gpus": 1, "steps": args.steps,
@@ -1028,7 +1014,7 @@ def main():
             out["learned"] = learned_vs_criterion()
     if not (args.no_cpu_baseline or args.jet_only):
         t0 = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(sample, interval=args.interval)
+        out["cpu_baseline"] = cpu_baseline(interval=args.interval)
         print("cpu baseline: %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 

@@ -23,14 +23,15 @@ def rel_l2(a, b, vol):
     return float(np.sqrt(np.sum(vol * (a - b) ** 2) / np.sum(vol * b ** 2)))
 
 
-def near_threshold(o, C_split, C_merge, eps_merge=None, rel=1e-9):
+def near_threshold(o, C_split, C_merge, eps_merge=None, rel=1e-9, cells=None):
     """Per cell and 2x2 block of V_base: True where the criterion's decision
     rests on a tie, i.e. a block containing it has an indicator I_B within rel
     of C_split or C_merge, or (eps_merge given) a transport error eps_B within
-    rel of eps_merge (oracle side, Sec. 3.2)."""
+    rel of eps_merge (oracle side, Sec. 3.2).  cells: the oracle cells to
+    examine (default all), one row each."""
     out = []
     base = o.base
-    for c in range(o.mesh.n_cells):
+    for c in (range(o.mesh.n_cells) if cells is None else cells):
         L = o.levels[o.cell_level[c]]
         gb, hb = lv.refine_to_base(L, o.g[c], o.h[c])
         M1, M2 = lv.indicators(base, gb, hb)
@@ -49,3 +50,28 @@ def near_threshold(o, C_split, C_merge, eps_merge=None, rel=1e-9):
                         amb[base.block_children2(s, bx, by)] = True
         out.append(amb)
     return np.array(out)
+
+
+def oracle_catalogue(p, n_masks, seed, C_split, C_merge, eps_merge, amp=0.5):
+    """A level catalogue for the full-size tests from seeded inputs and the
+    oracle alone: the base grid (kappa = 0) followed by the distinct masks the
+    oracle's criterion (Sec. 3.2, with the flux test) gives on `n_masks` single
+    cells of the problem's initial state under a seeded perturbation of
+    amplitude `amp`.  Masks of real distributions keep the velocity space fine
+    where the distribution is large, so every level carries a usable state."""
+    import workloads as W
+    from oracle.solver import Solver as Oracle
+    q = W.perturb(p, seed, amp)
+    rng = np.random.default_rng(seed)
+    nb = int(q.nv) // 2
+    out = [np.zeros(nb * nb, np.uint8)]
+    for c in rng.choice(int(p.n_cells), size=n_masks, replace=False):
+        if getattr(q, "unstructured", False):
+            cell = W.upatch(q, int(c), hops=0)[0]
+        else:
+            cell = W.patch(q, int(c) % q.ni, int(c) // q.ni, 1, 1)
+        o = Oracle(cell, compat=4)
+        k = lv.criterion(o.levels[0], o.g[0], o.h[0], C_split, C_merge, eps_merge, True)
+        if not any(np.array_equal(k, m) for m in out):
+            out.append(k)
+    return np.stack(out)

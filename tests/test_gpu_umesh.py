@@ -14,9 +14,15 @@ least-squares slopes with Venkatakrishnan's limiter) against the oracle.
   quadrilateral beside a triangle; the cylinder O-grid taken as an
   unstructured mesh (seam closed by shared nodes).
 * Full size (two-cavity at lattice spacing 1/48: 9504 cells, 101^2 velocity
-  points, FP32, UVS and MLVS): sampled cells against an oracle step of the
-  two-neighbour-ring patch around each (a cell's update reads its faces'
-  upwind cells and their face neighbours only), <= 1e-6 of the largest value.
+  points, FP32, UVS and MLVS), from seeded inputs only (the initial state with
+  a seeded perturbation; for MLVS the base grid and the oracle's criterion
+  masks of a few seeded single-cell states, on seeded squares of the plane):
+  sampled cells against an oracle step of the two-neighbour-ring patch around
+  each (a cell's update reads its faces' upwind cells and their face
+  neighbours only), <= 1e-6 of the largest value;
+  the base-grid criterion masks of the sampled cells bit for bit (threshold
+  ties excepted); the oracle's own time step from the full mesh equals the
+  GPU's.
 """
 import numpy as np
 import pytest
@@ -194,34 +200,52 @@ SAMPLE_POINTS = [(-1.0, 0.2), (-0.51, 0.01), (0.0, 0.0), (0.02, -0.05), (0.52, 0
 
 
 @pytest.mark.parametrize("mode", ["uvs", "mlvs"])
-def test_two_cavity_full_size_sampled_cells(mode):
+def test_two_cavity_full_size_sampled_cells(mode, tmp_path):
+    from oracle.solver import base_grid
+    from oracle.umesh import UMesh
     from paper_2609_35258_amd import autotune
+    from tests.parity import near_threshold
     import torch
-    p = W.two_cavity(48, nv=101, vmax=7.0)
+    p = W.perturb(W.two_cavity(48, nv=101, vmax=7.0), seed=51, amp=0.1)
     print("case two-cavity 9504 cells 101^2 fp32", mode, flush=True)
+    xi, _, _, _ = base_grid(p)
+    dt = p.cfl * UMesh(p).hmin / float(np.max(np.sqrt(np.sum(xi * xi, axis=1))))
     ap = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, flux_test=True, interval=0)
-    g = _gpu(p, precision=32, compat=4, adapt=ap if mode == "mlvs" else None, graph=True)
-    g.step(100)
-    if mode == "mlvs":
-        g.adapt()
+    g = _gpu(p, precision=32, compat=4, adapt=ap, graph=True)
+    assert abs(g.dt - dt) <= 1e-14 * dt
+    centres = _nearest(p, SAMPLE_POINTS)
+    if mode == "uvs":
+        # the criterion on the base grid, from the same seeded state
+        masks = g.criterion()
+        for c in centres:
+            q, cells = W.upatch(p, c, hops=2)
+            o = Oracle(q, compat=4, dt=dt)
+            ko = lv.criterion(o.levels[0], o.g[0], o.h[0], ap["C_split"], ap["C_merge"], ap["eps_merge"], True)
+            amb = near_threshold(o, ap["C_split"], ap["C_merge"], ap["eps_merge"], cells=[0])[0]
+            diff = (masks[c] != ko) & ~amb
+            print("criterion cell", c, "kappa max", int(ko.max()), "ties", int(amb.sum()), flush=True)
+            assert not diff.any(), (c, int(diff.sum()))
+    else:
+        from tests.parity import oracle_catalogue
+        kap = oracle_catalogue(p, 5, 51, ap["C_split"], ap["C_merge"], ap["eps_merge"])
+        levels = W.point_levels(p.centroids(), len(kap), 51, h=0.125)
+        g.set_levels(kap, levels)
         npts, _, ncross = g.level_info()
-        kap = np.stack([g.level_kappa(k) for k in range(len(npts))])
-        levels = g.cell_levels()
         print("levels", list(npts), "cross", ncross, flush=True)
-        assert len(npts) >= 2 and ncross > 0
-    g.step(2)
-    autotune.autotune(g, 32, cache=None)
-    patches = []
-    for c in _nearest(p, SAMPLE_POINTS):
-        q, cells = W.upatch(p, c, hops=2)
-        patches.append((c, q, cells, [g.get_cell(int(x)) for x in cells]))
+        assert len(npts) == len(kap) >= 2 and ncross > 0
+        # plus a cell beside a cross-level face in the channel
+        nbr = W.cell_neighbours(p)
+        xc = p.centroids()
+        chan = [c for c in range(len(levels)) if abs(xc[c][0]) < 0.45 and any(levels[n] != levels[c] for n in nbr[c])]
+        assert chan, "no cross-level face in the channel"
+        centres = centres + chan[:1]
+    autotune.autotune(g, 32, cache=str(tmp_path / "t.json"))
     g.step(1)
-    for c, q, cells, before in patches:
-        o = Oracle(q, compat=4, dt=g.dt)
+    for c in centres:
+        q, cells = W.upatch(p, c, hops=2)
+        o = Oracle(q, compat=4, dt=dt)
         if mode == "mlvs":
             o.set_levels(list(kap), levels[cells])
-        o.g = [x[0].copy() for x in before]
-        o.h = [x[1].copy() for x in before]
         o.step()
         ga, ha = g.get_cell(c)
         eg = np.max(np.abs(ga - o.g[0])) / np.max(np.abs(o.g[0]))

@@ -266,6 +266,27 @@ def striped_levels(ni: int, nj: int, n_levels: int, axis: int = 0) -> np.ndarray
     return (idx * n_levels // n).ravel().astype(np.int32)
 
 
+def block_levels(ni: int, nj: int, n_levels: int, seed: int, block: int = 8) -> np.ndarray:
+    """Cell -> level index, seeded uniformly per block x block tile of cells
+    (cell c = i + ni*j), so that cross-level faces run along the tile edges."""
+    rng = np.random.default_rng(seed)
+    tiles = rng.integers(0, n_levels, size=((nj + block - 1) // block, (ni + block - 1) // block))
+    i = np.arange(ni)[None, :].repeat(nj, 0)
+    j = np.arange(nj)[:, None].repeat(ni, 1)
+    return tiles[j // block, i // block].ravel().astype(np.int32)
+
+
+def point_levels(xc: np.ndarray, n_levels: int, seed: int, h: float) -> np.ndarray:
+    """Cell -> level index for cells at centroids xc [n][2], seeded uniformly
+    per square of side h of the plane (the unstructured counterpart of
+    block_levels)."""
+    ij = np.floor(np.asarray(xc) / h).astype(np.int64)
+    ij -= ij.min(axis=0)
+    rng = np.random.default_rng(seed)
+    tab = rng.integers(0, n_levels, size=tuple(ij.max(axis=0) + 1))
+    return tab[ij[:, 0], ij[:, 1]].astype(np.int32)
+
+
 def mlp_init_params(K: int, seed: int, H: int = 64, NF: int = 10) -> np.ndarray:
     """Seeded He-normal initial weights of the 10 -> H -> H -> K selector, zero
     biases, identity normalisation (mean 0, std 1); flat layout
