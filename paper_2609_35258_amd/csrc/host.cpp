@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -510,6 +511,95 @@ struct DevTable {
     PairTable view() const { return PairTable{off, idx, frac}; }
 };
 
+// Host worker threads for the adaptation's parallel passes, started on first
+// use and kept (starting a thread costs tens of microseconds, and an
+// adaptation runs several passes).  run(nt, f) calls f(t) for t in [0, nt),
+// t = 0 on the calling thread, and returns when every call has returned;
+// calls of run are serialised.
+class HostPool {
+public:
+    static HostPool& get() {
+        static HostPool pool;
+        return pool;
+    }
+    int size() const { return (int)workers_.size() + 1; }
+    void run(int nt, const std::function<void(int)>& f) {
+        std::lock_guard<std::mutex> serial(run_m_);
+        if (getpid() != pid_) {                    // a forked child has no workers
+            for (int t = 0; t < nt; ++t) f(t);
+            return;
+        }
+        nt = std::min(nt, size());
+        if (nt <= 1) { f(0); return; }
+        {
+            std::lock_guard<std::mutex> g(m_);
+            job_ = &f;
+            active_ = nt - 1;
+            pending_ = nt - 1;
+            ++gen_;
+        }
+        cv_.notify_all();
+        f(0);
+        std::unique_lock<std::mutex> lk(m_);
+        done_.wait(lk, [&] { return pending_ == 0; });
+        job_ = nullptr;
+    }
+    ~HostPool() {
+        {
+            std::lock_guard<std::mutex> g(m_);
+            stop_ = true;
+            ++gen_;
+        }
+        cv_.notify_all();
+        for (auto& t : workers_) t.join();
+    }
+
+private:
+    HostPool() : pid_(getpid()) {
+        const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+        for (unsigned i = 1; i < hw; ++i) workers_.emplace_back([this, i] { loop((int)i); });
+    }
+    void loop(int idx) {
+        unsigned long long seen = 0;
+        for (;;) {
+            const std::function<void(int)>* f = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(m_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+                if (idx > active_) continue;           // not needed in this run
+                f = job_;
+            }
+            (*f)(idx);
+            std::lock_guard<std::mutex> g(m_);
+            if (--pending_ == 0) done_.notify_one();
+        }
+    }
+    std::vector<std::thread> workers_;
+    std::mutex m_, run_m_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)>* job_ = nullptr;
+    int active_ = 0, pending_ = 0;
+    unsigned long long gen_ = 0;
+    bool stop_ = false;
+    pid_t pid_;
+};
+
+// Run f(lo, hi) over [0, n) split into contiguous ranges on the host pool,
+// each range at least `grain` long (one range on the calling thread when n is
+// small).  f must only write its own range.
+template <class F>
+void parallel_ranges(int n, int grain, F&& f) {
+    HostPool& P = HostPool::get();
+    const int nt = (int)std::min<long>(P.size(), std::max(1, n / std::max(grain, 1)));
+    if (nt <= 1) { f(0, n); return; }
+    const std::function<void(int)> job = [&](int t) {
+        f((int)((long)n * t / nt), (int)((long)n * (t + 1) / nt));
+    };
+    P.run(nt, job);
+}
+
 // Host image of the many small arrays a level set needs on the device (work
 // lists, projection tables, descriptors): one device block and one copy per
 // build instead of one allocation and copy per array.  Pieces are 256-byte
@@ -617,6 +707,9 @@ struct MeshH {
     // XCD's L2.  order[k] is the k-th cell, rank its inverse.
     std::vector<int> order, rank;
     std::vector<int> face_order, bface_order;   // faces and boundary faces by the rank of their left cell
+    // the slot (0..3) of each interior face in its left and right cell, and of
+    // each boundary face in its cell (filled on first use; topology only)
+    std::vector<int8_t> face_kL, face_kR, bface_k;
 };
 
 void finish_order(MeshH& M);
@@ -1142,6 +1235,41 @@ std::unique_ptr<Level> level_of_mask(mlvs_ctx c, const std::vector<uint8_t>& kap
     return std::make_unique<Level>(*it->second);
 }
 
+// Build the levels of the masks the cache does not hold yet, in parallel on
+// the host pool (a level is a pure function of the base grid and its mask),
+// so that the level_of_mask calls that follow find them.
+void prefill_levels(mlvs_ctx c, const std::vector<std::vector<uint8_t>>& masks) {
+    std::vector<const std::vector<uint8_t>*> miss;
+    for (auto& k : masks) {
+        if (c->level_cache.count(k)) continue;
+        bool dup = false;
+        for (auto* m : miss) dup = dup || *m == k;
+        if (!dup) miss.push_back(&k);
+    }
+    if (miss.empty()) return;
+    if (c->level_cache.size() + miss.size() > 64) c->level_cache.clear();
+    std::vector<std::unique_ptr<Level>> built(miss.size());
+    const std::function<void(int)> job = [&](int t) {
+        HostPool& P = HostPool::get();
+        for (size_t i = t; i < miss.size(); i += (size_t)std::min<int>(P.size(), (int)miss.size()))
+            built[i] = build_level(c->base, *miss[i]);
+    };
+    HostPool::get().run(std::min<int>(HostPool::get().size(), (int)miss.size()), job);
+    for (size_t i = 0; i < miss.size(); ++i) c->level_cache.emplace(*miss[i], std::move(built[i]));
+}
+
+// The dst <- src tables of a list of level pairs, built in parallel.
+std::vector<HostTable> make_tables(const std::vector<std::pair<const Level*, const Level*>>& pairs) {
+    std::vector<HostTable> out(pairs.size());
+    if (pairs.empty()) return out;
+    const int nt = std::min<int>(HostPool::get().size(), (int)pairs.size());
+    const std::function<void(int)> job = [&](int t) {
+        for (size_t i = t; i < pairs.size(); i += (size_t)nt) out[i] = make_table(*pairs[i].first, *pairs[i].second);
+    };
+    HostPool::get().run(nt, job);
+    return out;
+}
+
 // The persistent step's device-resident arguments: the current work lists,
 // buffers and counts, written in place (stream-ordered, outside any capture).
 void update_step_args(mlvs_ctx c) {
@@ -1185,11 +1313,8 @@ void build_items(mlvs_ctx c) {
     std::vector<int> rows(K, 0), ghosts(K, 0);
     std::vector<int> cell_frow(4 * n, -1);
     std::vector<int> cell_nbr(4 * n, -1);
-    std::vector<FaceItem> faces;
-    std::vector<FaceItem> bfaces;
     std::vector<GhostItem> gitems;
     std::vector<TabOff> gtab;
-    std::vector<XFaceItem> xitems;
     std::map<std::pair<int, int>, int> ghost_of;        // (source cell, dst level) -> row
     std::map<std::pair<int, int>, TabOff> tab_of;       // (dst level idx, src level idx)
     auto table = [&](int dst, int src) {
@@ -1230,80 +1355,195 @@ void build_items(mlvs_ctx c) {
             cell_nbr[4 * cc + k] = -2 - row;
         }
     mk.mark("items: ghosts", c->st);
-    // interior faces, in the traversal order of their left cells
-    int n_cross = 0;
-    std::map<std::pair<int, int>, int> iface_of_pair;
-    for (int f : M.face_order) {
-        const FaceH& F = M.faces[f];
-        const int lL = c->cell_level[F.L], lR = c->cell_level[F.R];
-        int kL = -1, kR = -1;
-        for (int k = 0; k < 4; ++k) {
-            // (a periodic mesh one cell wide has a face twice in one cell: then
-            // E/N is the left side, W/S the right one)
-            if (M.face_of_cell[4 * F.L + k] == (int)f && (M.unstructured || k == 1 || k == 3)) kL = k;
-            if (M.face_of_cell[4 * F.R + k] == (int)f && (M.unstructured || k == 0 || k == 2)) kR = k;
-        }
-        if (lL == lR) {
-            FaceItem it{};
-            it.L = F.L; it.R = F.R; it.lev = lL; it.row = rows[lL]++;
-            it.nx = F.nx; it.ny = F.ny; it.area = F.area;
-            it.dLx = F.dLx; it.dLy = F.dLy; it.dRx = F.dRx; it.dRy = F.dRy;
-            cell_frow[4 * F.L + kL] = face_code((int)faces.size(), false, false);
-            cell_frow[4 * F.R + kR] = face_code((int)faces.size(), false, true);
-            faces.push_back(it);
-        } else {
-            ++n_cross;
-            XFaceItem it{};
-            it.L = F.L; it.R = F.R; it.levA = lL; it.levB = lR;
-            it.rowA = rows[lL]++;
-            it.rowB = rows[lR]++;
-            it.nx = F.nx; it.ny = F.ny; it.area = F.area;
-            it.dLx = F.dLx; it.dLy = F.dLy; it.dRx = F.dRx; it.dRy = F.dRy;
-            // the interface level depends on the level pair only
-            const auto pk = std::make_pair(std::min(lL, lR), std::max(lL, lR));
-            int iidx = -1;
-            Level* I = nullptr;
-            auto ip = iface_of_pair.find(pk);
-            if (ip == iface_of_pair.end()) {
-                std::vector<uint8_t> kI(c->base.Nb);
-                const auto& kA = c->levels[lL]->kappa;
-                const auto& kB = c->levels[lR]->kappa;
-                for (int b = 0; b < c->base.Nb; ++b) kI[b] = std::min(kA[b], kB[b]);
-                I = find_iface(c, kI, iidx);
-                iface_of_pair[pk] = iidx;
-            } else {
-                iidx = ip->second;
-                I = &level_by_index(c, iidx);
+    // face slots of the mesh (topology only, computed once)
+    if (M.face_kL.size() != M.faces.size() || M.bface_k.size() != M.bfaces.size()) {
+        M.face_kL.assign(M.faces.size(), -1);
+        M.face_kR.assign(M.faces.size(), -1);
+        for (size_t f = 0; f < M.faces.size(); ++f) {
+            const FaceH& F = M.faces[f];
+            for (int k = 0; k < 4; ++k) {
+                // (a periodic mesh one cell wide has a face twice in one cell:
+                // then E/N is the left side, W/S the right one)
+                if (M.face_of_cell[4 * F.L + k] == (int)f && (M.unstructured || k == 1 || k == 3)) M.face_kL[f] = (int8_t)k;
+                if (M.face_of_cell[4 * F.R + k] == (int)f && (M.unstructured || k == 0 || k == 2)) M.face_kR[f] = (int8_t)k;
             }
-            it.levI = iidx;
-            it.scratch = I->n_rows++;
-            xitems.push_back(it);
-            cell_frow[4 * F.L + kL] = face_code(it.rowA, true, false);
-            cell_frow[4 * F.R + kR] = face_code(it.rowB, true, true);
+        }
+        M.bface_k.assign(M.bfaces.size(), -1);
+        for (size_t b = 0; b < M.bfaces.size(); ++b)
+            for (int k = 0; k < 4; ++k)
+                if (M.bface_of_cell[4 * M.bfaces[b].L + k] == (int)b) M.bface_k[b] = (int8_t)k;
+    }
+    // Interior faces in the traversal order of their left cells.  Two passes
+    // over contiguous ranges of that order on the host pool: the first counts,
+    // per range, same-level faces, cross-level faces, rows per level and cross
+    // faces per level pair; prefix sums over the ranges then give every range
+    // its starting indices, and the second pass writes the items in place.
+    // The lists, rows and codes are those of one sequential pass.
+    const int NF = (int)M.face_order.size();
+    const int KK = K * K;
+    HostPool& pool = HostPool::get();
+    const int NT = std::max(1, std::min(pool.size(), NF / 8192));
+    struct RangeCount {
+        int same = 0, cross = 0;
+        std::vector<int> rows, pair, first;
+    };
+    std::vector<RangeCount> rc(NT);
+    auto range_of = [&](int t, int& lo, int& hi) {
+        lo = (int)((long)NF * t / NT);
+        hi = (int)((long)NF * (t + 1) / NT);
+    };
+    {
+        const std::function<void(int)> count = [&](int t) {
+            RangeCount& r = rc[t];
+            r.rows.assign(K, 0);
+            r.pair.assign(KK, 0);
+            r.first.assign(KK, INT_MAX);
+            int lo, hi;
+            range_of(t, lo, hi);
+            for (int q = lo; q < hi; ++q) {
+                const FaceH& F = M.faces[M.face_order[q]];
+                const int lL = c->cell_level[F.L], lR = c->cell_level[F.R];
+                if (lL == lR) {
+                    ++r.same;
+                    ++r.rows[lL];
+                } else {
+                    ++r.cross;
+                    ++r.rows[lL];
+                    ++r.rows[lR];
+                    const int pk = std::min(lL, lR) * K + std::max(lL, lR);
+                    if (r.pair[pk]++ == 0) r.first[pk] = q;
+                }
+            }
+        };
+        pool.run(NT, count);
+    }
+    mk.mark("items: faces (count)", c->st);
+    // interface levels, created in the order of their first cross face
+    std::vector<int> pair_iface(KK, -1), pair_first(KK, INT_MAX);
+    for (int t = 0; t < NT; ++t)
+        for (int pk = 0; pk < KK; ++pk) pair_first[pk] = std::min(pair_first[pk], rc[t].first[pk]);
+    std::vector<int> pairs;
+    for (int pk = 0; pk < KK; ++pk)
+        if (pair_first[pk] != INT_MAX) pairs.push_back(pk);
+    std::sort(pairs.begin(), pairs.end(), [&](int a, int b) { return pair_first[a] < pair_first[b]; });
+    std::vector<std::vector<uint8_t>> pair_mask(pairs.size(), std::vector<uint8_t>(c->base.Nb));
+    for (size_t i = 0; i < pairs.size(); ++i) {
+        const auto& kA = c->levels[pairs[i] / K]->kappa;
+        const auto& kB = c->levels[pairs[i] % K]->kappa;
+        for (int b = 0; b < c->base.Nb; ++b) pair_mask[i][b] = std::min(kA[b], kB[b]);
+    }
+    prefill_levels(c, pair_mask);
+    for (size_t i = 0; i < pairs.size(); ++i) {
+        int iidx = -1;
+        find_iface(c, pair_mask[i], iidx);
+        pair_iface[pairs[i]] = iidx;
+    }
+    const int NI = (int)c->ifaces.size();
+    mk.mark("items: faces (interface levels)", c->st);
+    // starting indices of every range
+    struct RangeStart {
+        int same = 0, cross = 0;
+        std::vector<int> rows, scratch;
+    };
+    std::vector<RangeStart> st0(NT);
+    int n_same = 0, n_cross = 0;
+    std::vector<int> scratch_tot(NI, 0);
+    for (int t = 0; t < NT; ++t) {
+        st0[t].same = n_same;
+        st0[t].cross = n_cross;
+        st0[t].rows = rows;
+        st0[t].scratch = scratch_tot;
+        n_same += rc[t].same;
+        n_cross += rc[t].cross;
+        for (int l = 0; l < K; ++l) rows[l] += rc[t].rows[l];
+        for (int pk : pairs) scratch_tot[pair_iface[pk] - K] += rc[t].pair[pk];
+    }
+    for (int i = 0; i < NI; ++i) c->ifaces[i]->n_rows = scratch_tot[i];
+    const int n_bf = (int)M.bface_order.size();
+    const int nF_all = n_same + n_bf;
+    // cross-level face tables, one set per level pair
+    std::vector<std::array<TabOff, 4>> pair_tab(KK);
+    {
+        std::vector<std::pair<int, int>> want;           // (dst, src) level indices not staged yet
+        for (int pk : pairs) {
+            const int a = pk / K, b = pk % K, I = pair_iface[pk];
+            for (auto ds : {std::make_pair(I, a), std::make_pair(I, b), std::make_pair(a, I), std::make_pair(b, I)})
+                if (!tab_of.count(ds) && std::find(want.begin(), want.end(), ds) == want.end()) want.push_back(ds);
+        }
+        std::vector<std::pair<const Level*, const Level*>> lp;
+        for (auto& ds : want) lp.emplace_back(&level_by_index(c, ds.first), &level_by_index(c, ds.second));
+        const std::vector<HostTable> built = make_tables(lp);
+        for (size_t i = 0; i < want.size(); ++i) {
+            TabOff t;
+            t.off = stg.put(built[i].off);
+            t.idx = stg.put(built[i].idx);
+            t.frac = stg.put(built[i].frac);
+            tab_of[want[i]] = t;
+        }
+        for (int pk : pairs) {
+            const int a = pk / K, b = pk % K, I = pair_iface[pk];
+            pair_tab[pk] = {table(I, a), table(I, b), table(a, I), table(b, I)};
         }
     }
-    mk.mark("items: faces", c->st);
-    std::vector<std::array<TabOff, 4>> xtab;
-    for (auto& it : xitems)
-        xtab.push_back({table(it.levI, it.levA), table(it.levI, it.levB), table(it.levA, it.levI),
-                        table(it.levB, it.levI)});
-    mk.mark("items: cross-face tables", c->st);
+    mk.mark("items: faces (cross-face tables)", c->st);
+    // the face items go straight into the staged block
+    const size_t o_faces = stg.put(nullptr, sizeof(FaceItem) * (size_t)nF_all);
+    FaceItem* fitems = reinterpret_cast<FaceItem*>(stg.p + o_faces);
+    std::vector<XFaceItem> xitems(n_cross);
+    std::vector<int> xpair(n_cross);
+    {
+        const std::function<void(int)> fill = [&](int t) {
+            int same = st0[t].same, cross = st0[t].cross;
+            std::vector<int> row = st0[t].rows, scr = st0[t].scratch;
+            int lo, hi;
+            range_of(t, lo, hi);
+            for (int q = lo; q < hi; ++q) {
+                const int f = M.face_order[q];
+                const FaceH& F = M.faces[f];
+                const int lL = c->cell_level[F.L], lR = c->cell_level[F.R];
+                const int kL = M.face_kL[f], kR = M.face_kR[f];
+                if (lL == lR) {
+                    FaceItem& it = fitems[same];
+                    it.L = F.L; it.R = F.R; it.lev = lL; it.row = row[lL]++;
+                    it.nx = F.nx; it.ny = F.ny; it.area = F.area;
+                    it.dLx = F.dLx; it.dLy = F.dLy; it.dRx = F.dRx; it.dRy = F.dRy;
+                    cell_frow[4 * F.L + kL] = face_code(same, false, false);
+                    cell_frow[4 * F.R + kR] = face_code(same, false, true);
+                    ++same;
+                } else {
+                    const int pk = std::min(lL, lR) * K + std::max(lL, lR);
+                    XFaceItem it{};
+                    it.L = F.L; it.R = F.R; it.levA = lL; it.levB = lR;
+                    it.rowA = row[lL]++;
+                    it.rowB = row[lR]++;
+                    it.nx = F.nx; it.ny = F.ny; it.area = F.area;
+                    it.dLx = F.dLx; it.dLy = F.dLy; it.dRx = F.dRx; it.dRy = F.dRy;
+                    it.levI = pair_iface[pk];
+                    it.scratch = scr[pair_iface[pk] - K]++;
+                    cell_frow[4 * F.L + kL] = face_code(it.rowA, true, false);
+                    cell_frow[4 * F.R + kR] = face_code(it.rowB, true, true);
+                    xpair[cross] = pk;
+                    xitems[cross++] = it;
+                }
+            }
+        };
+        pool.run(NT, fill);
+    }
+    mk.mark("items: faces (fill)", c->st);
     c->n_cross = n_cross;
     c->step_points = 0.0;
     for (int cc = 0; cc < n; ++cc) c->step_points += c->levels[c->cell_level[cc]]->N;
     c->step_iface_points = 0.0;
     for (auto& it : xitems) c->step_iface_points += level_by_index(c, it.levI).N;
-    for (int b : M.bface_order) {
+    for (int q = 0; q < n_bf; ++q) {
+        const int b = M.bface_order[q];
         const FaceH& F = M.bfaces[b];
         const int lc = c->cell_level[F.L];
         FaceItem it{};
         it.L = F.L; it.R = -1 - F.bc; it.lev = lc; it.row = rows[lc]++;
         it.nx = F.nx; it.ny = F.ny; it.area = F.area; it.dLx = F.dLx; it.dLy = F.dLy;
-        int kk = -1;
-        for (int k = 0; k < 4; ++k)
-            if (M.bface_of_cell[4 * F.L + k] == (int)b) kk = k;
-        cell_frow[4 * F.L + kk] = face_code((int)(faces.size() + bfaces.size()), false, false);
-        bfaces.push_back(it);
+        cell_frow[4 * F.L + M.bface_k[b]] = face_code(n_same + q, false, false);
+        reinterpret_cast<FaceItem*>(stg.p + o_faces)[n_same + q] = it;
     }
     mk.mark("items: host lists", c->st);
     // row buffers
@@ -1327,9 +1567,8 @@ void build_items(mlvs_ctx c) {
                         stg.put(xy_pairs(L))});
     }
     mk.mark("items: row buffers", c->st);
-    c->n_faces = (int)faces.size();
-    c->n_bfaces = (int)bfaces.size();
-    faces.insert(faces.end(), bfaces.begin(), bfaces.end());
+    c->n_faces = n_same;
+    c->n_bfaces = n_bf;
     std::vector<int> ptb, poff, toff;
     std::vector<double> ptab;
     std::vector<uint8_t> kap;
@@ -1346,7 +1585,6 @@ void build_items(mlvs_ctx c) {
     const size_t o_lv = stg.put(nullptr, sizeof(LevelDesc) * (K + c->ifaces.size()));
     const size_t o_gh = stg.put(nullptr, sizeof(GhostItem) * gitems.size());
     const size_t o_xf = stg.put(nullptr, sizeof(XFaceItem) * xitems.size());
-    const size_t o_faces = stg.put(faces);
     const size_t o_frow = stg.put(cell_frow);
     const size_t o_nbr = stg.put(cell_nbr);
     const size_t o_lev = stg.put(c->cell_level);
@@ -1367,10 +1605,12 @@ void build_items(mlvs_ctx c) {
     }
     for (size_t i = 0; i < gitems.size(); ++i) gitems[i].tab = gtab[i].at(base);
     for (size_t i = 0; i < xitems.size(); ++i) {
-        xitems[i].IfromA = xtab[i][0].at(base);
-        xitems[i].IfromB = xtab[i][1].at(base);
-        xitems[i].AfromI = xtab[i][2].at(base);
-        xitems[i].BfromI = xtab[i][3].at(base);
+        const auto& T = pair_tab[xpair[i]];
+        const bool a_first = xitems[i].levA < xitems[i].levB;     // tables are kept per (low, high) pair
+        xitems[i].IfromA = (a_first ? T[0] : T[1]).at(base);
+        xitems[i].IfromB = (a_first ? T[1] : T[0]).at(base);
+        xitems[i].AfromI = (a_first ? T[2] : T[3]).at(base);
+        xitems[i].BfromI = (a_first ? T[3] : T[2]).at(base);
     }
     // level descriptors: representative levels then interface levels
     std::vector<LevelDesc> descs;
@@ -1415,7 +1655,7 @@ void build_items(mlvs_ctx c) {
     // waves, then the fewest chunks that do.  Levels of at most
     // FUSE_MAX_POINTS points always take whole rows and the fused step.
     constexpr int FUSE_MAX_POINTS = 1024, MIN_ITEMS = 16384;
-    const int nf_all = std::max<int>((int)faces.size(), 1);
+    const int nf_all = std::max<int>(nF_all, 1);
     if (c->chunk_env > 0) {
         c->chunk = c->chunk_env;
     } else {
@@ -1428,13 +1668,13 @@ void build_items(mlvs_ctx c) {
     c->nch = (nmax + c->chunk - 1) / c->chunk;
     c->fused = c->fuse_allowed && c->nch == 1 && nmax <= FUSE_MAX_POINTS;
     c->d_fmom = static_cast<double*>(
-        c->dm.alloc(sizeof(double) * NFMOM * c->nch * std::max<size_t>(faces.size(), 1)));
+        c->dm.alloc(sizeof(double) * NFMOM * c->nch * (size_t)std::max(nF_all, 1)));
     c->item_allocs.push_back(c->d_fmom);
     c->d_cmom = static_cast<double*>(c->dm.alloc(sizeof(double) * NMOM * c->nch * (size_t)std::max(n, 1)));
     c->item_allocs.push_back(c->d_cmom);
     c->mom_valid = false;
     c->prep_valid = false;
-    c->d_fpar = static_cast<double*>(c->dm.alloc(sizeof(double) * NFP * std::max<size_t>(faces.size(), 1)));
+    c->d_fpar = static_cast<double*>(c->dm.alloc(sizeof(double) * NFP * (size_t)std::max(nF_all, 1)));
     c->item_allocs.push_back(c->d_fpar);
     update_step_args(c);                  // last: every pointer it records is allocated
 }
@@ -1560,25 +1800,42 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
     std::vector<TabOff> item_tab(n);
     std::vector<char> has_tab(n, 0);
     int64_t changed = 0;
+    // the (new level, old level) pairs that need a table, built in parallel
+    const int Kn = (int)c->levels.size(), Ko = (int)old.size();
+    std::vector<char> same_mask((size_t)Kn * Ko), need((size_t)Kn * Ko, 0);
+    for (int d = 0; d < Kn; ++d)
+        for (int o = 0; o < Ko; ++o) same_mask[(size_t)d * Ko + o] = old[o]->kappa == c->levels[d]->kappa;
+    for (int cc = 0; cc < n; ++cc) {
+        const size_t k = (size_t)c->cell_level[cc] * Ko + old_level[cc];
+        if (!same_mask[k]) need[k] = 1;
+    }
+    {
+        std::vector<std::pair<int, int>> want;
+        std::vector<std::pair<const Level*, const Level*>> lp;
+        for (int d = 0; d < Kn; ++d)
+            for (int o = 0; o < Ko; ++o)
+                if (need[(size_t)d * Ko + o]) {
+                    want.emplace_back(d, o);
+                    lp.emplace_back(c->levels[d].get(), old[o].get());
+                }
+        const std::vector<HostTable> built = make_tables(lp);
+        for (size_t i = 0; i < want.size(); ++i) {
+            TabOff t;
+            t.off = stg.put(built[i].off);
+            t.idx = stg.put(built[i].idx);
+            t.frac = stg.put(built[i].frac);
+            tabs.emplace(want[i], t);
+        }
+    }
     for (int cc = 0; cc < n; ++cc) {
         RemapItem& r = items[cc];
         r.c = cc;
         r.src_lev = old_level[cc]; r.src_slot = old_slot[cc];
         r.dst_lev = c->cell_level[cc]; r.dst_slot = c->cell_slot[cc];
         r.tab = PairTable{nullptr, nullptr, nullptr};
-        if (old[r.src_lev]->kappa == c->levels[r.dst_lev]->kappa) continue;
+        if (same_mask[(size_t)r.dst_lev * Ko + r.src_lev]) continue;
         ++changed;
-        auto key = std::make_pair(r.dst_lev, r.src_lev);
-        auto it = tabs.find(key);
-        if (it == tabs.end()) {
-            const HostTable ht = make_table(*c->levels[r.dst_lev], *old[r.src_lev]);
-            TabOff t;
-            t.off = stg.put(ht.off);
-            t.idx = stg.put(ht.idx);
-            t.frac = stg.put(ht.frac);
-            it = tabs.emplace(key, t).first;
-        }
-        item_tab[cc] = it->second;
+        item_tab[cc] = tabs.at(std::make_pair(r.dst_lev, r.src_lev));
         has_tab[cc] = 1;
     }
     const size_t o_od = stg.put(nullptr, sizeof(LevelDesc) * old.size());
@@ -1748,95 +2005,6 @@ void dedupe(mlvs_ctx c, const uint8_t*& uniq, std::vector<int>& first, std::vect
     }
 }
 
-// Host worker threads for the adaptation's parallel passes, started on first
-// use and kept (starting a thread costs tens of microseconds, and an
-// adaptation runs several passes).  run(nt, f) calls f(t) for t in [0, nt),
-// t = 0 on the calling thread, and returns when every call has returned;
-// calls of run are serialised.
-class HostPool {
-public:
-    static HostPool& get() {
-        static HostPool pool;
-        return pool;
-    }
-    int size() const { return (int)workers_.size() + 1; }
-    void run(int nt, const std::function<void(int)>& f) {
-        std::lock_guard<std::mutex> serial(run_m_);
-        if (getpid() != pid_) {                    // a forked child has no workers
-            for (int t = 0; t < nt; ++t) f(t);
-            return;
-        }
-        nt = std::min(nt, size());
-        if (nt <= 1) { f(0); return; }
-        {
-            std::lock_guard<std::mutex> g(m_);
-            job_ = &f;
-            active_ = nt - 1;
-            pending_ = nt - 1;
-            ++gen_;
-        }
-        cv_.notify_all();
-        f(0);
-        std::unique_lock<std::mutex> lk(m_);
-        done_.wait(lk, [&] { return pending_ == 0; });
-        job_ = nullptr;
-    }
-    ~HostPool() {
-        {
-            std::lock_guard<std::mutex> g(m_);
-            stop_ = true;
-            ++gen_;
-        }
-        cv_.notify_all();
-        for (auto& t : workers_) t.join();
-    }
-
-private:
-    HostPool() : pid_(getpid()) {
-        const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
-        for (unsigned i = 1; i < hw; ++i) workers_.emplace_back([this, i] { loop((int)i); });
-    }
-    void loop(int idx) {
-        unsigned long long seen = 0;
-        for (;;) {
-            const std::function<void(int)>* f = nullptr;
-            {
-                std::unique_lock<std::mutex> lk(m_);
-                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
-                if (stop_) return;
-                seen = gen_;
-                if (idx > active_) continue;           // not needed in this run
-                f = job_;
-            }
-            (*f)(idx);
-            std::lock_guard<std::mutex> g(m_);
-            if (--pending_ == 0) done_.notify_one();
-        }
-    }
-    std::vector<std::thread> workers_;
-    std::mutex m_, run_m_;
-    std::condition_variable cv_, done_;
-    const std::function<void(int)>* job_ = nullptr;
-    int active_ = 0, pending_ = 0;
-    unsigned long long gen_ = 0;
-    bool stop_ = false;
-    pid_t pid_;
-};
-
-// Run f(lo, hi) over [0, n) split into contiguous ranges on the host pool,
-// each range at least `grain` long (one range on the calling thread when n is
-// small).  f must only write its own range.
-template <class F>
-void parallel_ranges(int n, int grain, F&& f) {
-    HostPool& P = HostPool::get();
-    const int nt = (int)std::min<long>(P.size(), std::max(1, n / std::max(grain, 1)));
-    if (nt <= 1) { f(0, n); return; }
-    const std::function<void(int)> job = [&](int t) {
-        f((int)((long)n * t / nt), (int)((long)n * (t + 1) / nt));
-    };
-    P.run(nt, job);
-}
-
 // Leader clustering of the unique masks (descending frequency, ties by first
 // cell), integer graded distance, enclosing mask = elementwise min, identical
 // enclosing masks merged.
@@ -1953,6 +2121,7 @@ void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
     int64_t changed = 0;
     if (!same) {
         std::vector<std::unique_ptr<Level>> nl;
+        prefill_levels(c, reps);
         for (auto& k : reps) nl.push_back(level_of_mask(c, k));
         changed = install_levels(c, std::move(nl), cl);
     }

@@ -75,3 +75,30 @@ def oracle_catalogue(p, n_masks, seed, C_split, C_merge, eps_merge, amp=0.5):
         if not any(np.array_equal(k, m) for m in out):
             out.append(k)
     return np.stack(out)
+
+
+def oracle_sensitivity(make, steps, eps=1e-15, trials=2, seed=0):
+    """Per step, the largest change (relative to the largest |g|) of the
+    oracle's state when its initial g~, h~ carry relative noise of size eps:
+    the spread the result has anyway under rounding.  make() returns a fresh
+    oracle at the starting state.  Where a configuration is ill-conditioned
+    (a cell whose mass sits almost all in one merged point makes its
+    correction systems nearly singular) this exceeds the usual 1e-12 bound,
+    and a GPU result can differ from the oracle by as much without either
+    being wrong."""
+    ref = make()
+    out = np.zeros(steps)
+    runs = []
+    for t in range(trials):
+        o = make()
+        rng = np.random.default_rng(seed + t)
+        o.g = [x * (1.0 + eps * rng.uniform(-1, 1, x.shape)) for x in o.g]
+        o.h = [x * (1.0 + eps * rng.uniform(-1, 1, x.shape)) for x in o.h]
+        runs.append(o)
+    for k in range(steps):
+        ref.step()
+        scale = max(np.max(np.abs(x)) for x in ref.g)
+        for o in runs:
+            o.step()
+            out[k] = max(out[k], max(np.max(np.abs(a - b)) for a, b in zip(o.g, ref.g)) / scale)
+    return out

@@ -11,7 +11,7 @@ import workloads as W
 from oracle import levels as lv
 from oracle.solver import AdaptParams
 from oracle.solver import Solver as Oracle
-from tests.parity import near_threshold, state_error
+from tests.parity import near_threshold, oracle_sensitivity, state_error
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -44,6 +44,16 @@ def test_fixed_catalog_remap_and_steps(n_levels, axis, seed, map_moments, compat
     print("case fixed catalog", n_levels, axis, seed, map_moments, compat, flush=True)
     kap = _catalog(p.nv, n_levels, seed)
     cl = W.striped_levels(p.ni, p.nj, n_levels, axis)
+
+    def make():
+        o = Oracle(p, compat=compat, map_moments=map_moments)
+        o.set_levels(list(kap), cl)
+        return o
+
+    # the random catalogues merge the distribution's peak into one 8x8 point
+    # for some cells; their solves are then ill-conditioned and the bound is
+    # the oracle's own spread under rounding-level input noise
+    tol = np.maximum(TOL, 10.0 * oracle_sensitivity(make, 4))
     o = Oracle(p, compat=compat, map_moments=map_moments)
     g = _gpu(p, compat=compat, map_moments=map_moments)
     o.set_levels(list(kap), cl)
@@ -58,7 +68,7 @@ def test_fixed_catalog_remap_and_steps(n_levels, axis, seed, map_moments, compat
         o.step()
         g.step(1)
         e = state_error(g.get_state(), o.g, o.h)
-        assert max(e) < TOL, (k, e)
+        assert max(e) < tol[k], (k, e, tol[k])
     assert np.max(np.abs(g.totals() - t0)) < 1e-13
     g.close()
 
