@@ -395,20 +395,23 @@ STAGE_KERNEL = {"face": "k_face_full", "update_cell": "k_update_cell",
                 "update": "k_update", "xface": "k_xface"}
 
 
-def measured_traffic(workload, stage, precision, variant, mk=0):
+def measured_traffic(workload, stage, precision, variant, mk=0, crit=False):
     """HBM-side bytes per dispatch of the stage's kernel from profiles/traffic.txt
     (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when absent or
     when the kernel source has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     src = os.path.join(ROOT, "paper_2609_35258_amd", "csrc", "kernels.hip")
-    if stage not in STAGE_KERNEL or variant is None or not os.path.exists(path):
+    if not os.path.exists(path) or (not crit and (stage not in STAGE_KERNEL or variant is None)):
         return None
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    u, w = VARIANTS[variant]
-    if mk and stage in STAGE_MK:
-        u, w = VARIANTS[0]                 # unstructured face kernels: the (1, 4) pair for every variant
-    name = "mlvs::%s<%s,%d,%d%s%s>" % (STAGE_KERNEL[stage], "double" if precision == 64 else "float", u, w,
-                                       ",4" if stage in STAGE_CM else "", ",%d" % mk if stage in STAGE_MK else "")
+    if crit:
+        name = "mlvs::k_criterion<%s>" % ("double" if precision == 64 else "float")
+    else:
+        u, w = VARIANTS[variant]
+        if mk and stage in STAGE_MK:
+            u, w = VARIANTS[0]             # unstructured face kernels: the (1, 4) pair for every variant
+        name = "mlvs::%s<%s,%d,%d%s%s>" % (STAGE_KERNEL[stage], "double" if precision == 64 else "float", u, w,
+                                           ",4" if stage in STAGE_CM else "", ",%d" % mk if stage in STAGE_MK else "")
     for line in open(path):
         f = line.split()
         if len(f) == 4 and not line.startswith("#") and f[0] == h and f[1] == workload and f[2] == name:
@@ -550,35 +553,62 @@ JET_WL = "jet512x256-nc161-fp32"
 METHOD_VALUES, FLOOR_VALUES = 4, 6
 
 
-def method_roofline(prof, precision, updates_per_step, step_ms, workload=None, variants=None, interval=0):
-    """Roofline of the step: the method's algorithmic bytes per step (16 B per
-    FP32, 32 B per FP64 cell-velocity update times the updates of one step)
-    over the mean launch time of the step's longest kernel, and over the whole
-    step; the criterion counts with its share per step when adaptation runs
-    every `interval` steps.  traffic: the copy-calibrated FETCH_SIZE and
-    WRITE_SIZE bytes per launch of that kernel from profiles/traffic.txt
-    (null when the kernels changed since they were taken)."""
+def method_roofline(prof, precision, updates_per_step, step_ms, workload=None, variants=None, interval=0,
+                    crit_cells=0, crit_blocks=0):
+    """Roofline of the timed window's dominant kernel (the largest share of a
+    step: the criterion counts 1/interval of its launch time).  Algorithmic
+    bytes per launch, by the method's own figures: a step kernel is credited
+    with the step's 16 B per FP32 (32 B per FP64) cell-velocity update (read
+    and write g~, h~ once), the criterion with reading the state once (8 B per
+    FP32, 16 B per FP64 point) and writing one kappa byte per cell and 2x2
+    block.  achieved = those bytes over the kernel's mean launch time; the
+    whole step against the same 16 B and the 24 B floor beside it.  traffic:
+    the copy-calibrated FETCH_SIZE and WRITE_SIZE bytes per launch of that
+    kernel from profiles/traffic.txt (null when the kernels changed since)."""
     evsz = 8 if precision == 64 else 4
     per_step = {}
     for k, v in prof.items():
-        share = (1.0 / interval) if k == "criterion" else 1.0
         if k == "criterion" and not interval:
             continue
         if k == "xface" and len(prof) > 1:
             continue                        # second stream, beside the face stages
-        per_step[k] = v["ms"] * share
+        per_step[k] = v["ms"] * ((1.0 / interval) if k == "criterion" else 1.0)
+
+    def alg_of(k):
+        if k == "criterion":
+            return 2 * evsz * updates_per_step + crit_blocks * crit_cells
+        return METHOD_VALUES * evsz * updates_per_step
+
+    def basis_of(k):
+        if k == "criterion":
+            return ("%d B per cell-velocity point (read g~, h~ once) x %.4g points + one kappa byte per cell and 2x2 "
+                    "block (%d x %d), over the mean launch time of criterion" % (2 * evsz, updates_per_step,
+                                                                                crit_cells, crit_blocks))
+        return ("%d B per cell-velocity update (read and write g~, h~ once) x %.4g updates per step, over the mean "
+                "launch time of %s" % (METHOD_VALUES * evsz, updates_per_step, k))
+
     dom = max(per_step, key=per_step.get)
-    alg = METHOD_VALUES * evsz * updates_per_step
+    alg = alg_of(dom)
     achieved = alg / (prof[dom]["ms"] * 1e-3) / 1e9
-    t = measured_traffic(workload, dom, precision, (variants or {}).get(dom)) if workload else None
+    var = (variants or {}).get(dom)
+    t = measured_traffic(workload, dom, precision, var, crit=(dom == "criterion")) if workload else None
+    step_alg = METHOD_VALUES * evsz * updates_per_step
+    # every stage's launch time and share of a step; achieved and frac only
+    # where the method gives the kernel a figure of its own (the step's
+    # longest streaming kernel carries the step's bytes, the criterion its read)
+    kernels = {}
+    for k in per_step:
+        kernels[k] = {"ms": round(prof[k]["ms"], 5), "ms_per_step": round(per_step[k], 5)}
+        if k in (dom, "criterion"):
+            a = alg_of(k)
+            kernels[k].update({"algorithmic_bytes": a, "achieved_GBs": round(a / (prof[k]["ms"] * 1e-3) / 1e9, 1),
+                               "frac": round(a / (prof[k]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
     return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": t, "algorithmic_bytes": alg,
-            "basis": "%d B per cell-velocity update (read and write g~, h~ once) x %.4g updates per step, over "
-                     "the mean launch time of %s" % (METHOD_VALUES * evsz, updates_per_step, dom),
-            "step": {"ms": step_ms, "achieved": alg / (step_ms * 1e-3) / 1e9,
-                     "frac": alg / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": t, "algorithmic_bytes": alg, "basis": basis_of(dom),
+            "step": {"ms": step_ms, "achieved": step_alg / (step_ms * 1e-3) / 1e9,
+                     "frac": step_alg / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "floor_frac": FLOOR_VALUES * evsz * updates_per_step / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
-            "stage_ms": {k: round(v["ms"], 5) for k, v in prof.items()}}
+            "kernels": kernels}
 
 
 def _fields_error(fa, fb, vol=None):
@@ -641,7 +671,8 @@ def jet_headline(steps, warmup, interval=5, precision=32, with_uvs=True, tune=Tr
            "nbar": float(np.sum(npts * ncells) / np.sum(ncells)), "n_cross": int(ncross), "device_bytes": int(mem_m),
            "variants": variants, "tiles": _tiles_summary(tiles),
            "roofline": method_roofline(prof, precision, ups, 1e3 * t_m / steps,
-                                       JET_WL + "-mlvs" if precision == 32 else None, variants, interval)}
+                                       JET_WL + "-mlvs" if precision == 32 else None, variants, interval,
+                                       crit_cells=p.n_cells, crit_blocks=(p.nv // 2) ** 2)}
     if with_uvs:
         out["uvs"], f_u, mem_u, t_u = _jet_uvs(p, steps, warmup, precision, tune)
         err = _fields_error(f_m, f_u)
