@@ -2721,24 +2721,32 @@ __global__ __launch_bounds__(BS, 2) void k_criterion(const LevelDesc* __restrict
                 eH = Hq * T3b[CT_W];
             }
             if (!act) continue;
-            bool m8 = crit_candidate(cc, e1, eH, 3, 4 * X8 + nbx * 4 * Y8);
+            bool m8 = crit_candidate(cc, e1, eH, 3, 4 * X8 + nbx * 4 * Y8);   // group-uniform
+            bool m4 = crit_candidate(cc, q1, qH, 2, c4);                      // the lane's quarter
+            // The quarter's half-range fluxes serve both the 8x8 test (summed
+            // over the group's four lanes) and the quarter's own test: summed
+            // once, when either needs them.
+            const bool need8 = m8 && cc.flux_test && k8 < 3;
+            CritAcc aq;
+            if (need8 || (m4 && cc.flux_test)) {
+                acc_zero(aq);
+                if (k4 >= 2) acc_table<true>(aq, gq, Hq, T2q);
+                else
+#pragma unroll 1
+                    for (int j = 0; j < 4; ++j) crit_sum2<S, true>(aq, cc, g, h, 2 * X4 + (j & 1), 2 * Y4 + (j >> 1));
+            }
             if (m8 && cc.flux_test) {
                 CritAcc a;
-                acc_zero(a);
                 if (k8 >= 3) {
+                    acc_zero(a);
                     acc_table<true>(a, gq, Hq, T3b);
                 } else {
-                    if (k4 >= 2) acc_table<true>(a, gq, Hq, T2q);
-                    else
-#pragma unroll 1
-                        for (int j = 0; j < 4; ++j)
-                            crit_sum2<S, true>(a, cc, g, h, 2 * X4 + (j & 1), 2 * Y4 + (j >> 1));
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
 #pragma unroll
                         for (int d = 0; d < 2; ++d)
 #pragma unroll
-                            for (int sg = 0; sg < 2; ++sg) a.F[r][d][sg] = group4_sum(a.F[r][d][sg]);
+                            for (int sg = 0; sg < 2; ++sg) a.F[r][d][sg] = group4_sum(aq.F[r][d][sg]);
                 }
                 a.m1 = e1;
                 a.mH = eH;
@@ -2750,17 +2758,10 @@ __global__ __launch_bounds__(BS, 2) void k_criterion(const LevelDesc* __restrict
                 continue;
             }
             // the lane's 4x4 quarter
-            bool m4 = crit_candidate(cc, q1, qH, 2, c4);
             if (m4 && cc.flux_test) {
-                CritAcc a;
-                acc_zero(a);
-                if (k4 >= 2) acc_table<true>(a, gq, Hq, T2q);
-                else
-#pragma unroll 1
-                    for (int j = 0; j < 4; ++j) crit_sum2<S, true>(a, cc, g, h, 2 * X4 + (j & 1), 2 * Y4 + (j >> 1));
-                a.m1 = q1;
-                a.mH = qH;
-                m4 = crit_flux_ok(cc, a, T2q);
+                aq.m1 = q1;
+                aq.mH = qH;
+                m4 = crit_flux_ok(cc, aq, T2q);
             }
             if (m4) {
                 q0[0] = q0[1] = q0[nbx] = q0[nbx + 1] = 2;
