@@ -2466,12 +2466,13 @@ __device__ __forceinline__ void acc_base(CritAcc& a, const CritCtx& cc, double g
     const double mr[4] = {gv, x * gv, y * gv, 0.5 * Hv};
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
+        // w xi_d on the point's half-range (a point with xi_d = 0 adds zero to both)
         const double t = w * xd[d];
+        const double tp = xd[d] >= 0 ? t : 0.0, tn = xd[d] >= 0 ? 0.0 : t;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const double v = t * mr[r];
-            if (xd[d] >= 0) a.F[r][d][0] += v;
-            if (-xd[d] >= 0) a.F[r][d][1] += v;
+            a.F[r][d][0] += tp * mr[r];
+            a.F[r][d][1] += tn * mr[r];
         }
     }
 }
@@ -2604,7 +2605,7 @@ __device__ __forceinline__ double group4_sum(double v) {
 }
 
 template <typename S>
-__global__ __launch_bounds__(BS, 2) void k_criterion(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
+__global__ __launch_bounds__(BS, 3) void k_criterion(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
                                                   const int* __restrict__ cell_slot, int n_cells,
                                                   const int* __restrict__ ptb_all, const int* __restrict__ ptb_off,
                                                   const double* __restrict__ ptab_all,
