@@ -2097,6 +2097,7 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 }
 
 void adapt_now(mlvs_ctx c, mlvs_adapt_report* rep) {
+    sync(c);                  // the timers below cover the adaptation only, not steps still queued
     auto t0 = std::chrono::steady_clock::now();
     run_criterion(c);
     sync(c);
