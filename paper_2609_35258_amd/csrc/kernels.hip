@@ -2605,7 +2605,7 @@ __device__ __forceinline__ double group4_sum(double v) {
 }
 
 template <typename S>
-__global__ __launch_bounds__(BS, 3) void k_criterion(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
+__global__ __launch_bounds__(BS, 2) void k_criterion(const LevelDesc* __restrict__ lvs, const int* __restrict__ cell_lev,
                                                   const int* __restrict__ cell_slot, int n_cells,
                                                   const int* __restrict__ ptb_all, const int* __restrict__ ptb_off,
                                                   const double* __restrict__ ptab_all,
