@@ -1926,21 +1926,52 @@ __global__ __launch_bounds__(BS) void k_remap(const LevelDesc* __restrict__ olv,
         for (int k = 0; k < 18; ++k) m[k] = 0.0;
         for (int i = lane_id(); i < Ls.N; i += WL)
             acc_m9(m, gp(Ls.w)[i], gp(Ls.xi_x)[i], gp(Ls.xi_y)[i], (double)sg[i], (double)sh[i]);
-        for (int P = lane_id(); P < Ld.N; P += WL) {
-            double gP = 0.0, HP = 0.0;
-            for (int e = gp(R.tab.off)[P]; e < gp(R.tab.off)[P + 1]; ++e) {
-                const int a = gp(R.tab.idx)[e];
-                const double fr = gp(R.tab.frac)[e];
+        // Projection, RU destination points per lane at a time: their table
+        // offsets, first entries and source values are loaded together (most
+        // points have one entry: a refinement or an unchanged point), further
+        // entries are added after in table order.
+        constexpr int RU = 4;
+        for (int P0 = lane_id(); P0 < Ld.N; P0 += WL * RU) {
+            int e0[RU], e1[RU], a0[RU];
+            double gP[RU], HP[RU];
+#pragma unroll
+            for (int q = 0; q < RU; ++q) {
+                const int Pc = clampi(P0 + q * WL, Ld.N);
+                e0[q] = gp(R.tab.off)[Pc];
+                e1[q] = gp(R.tab.off)[Pc + 1];
+            }
+#pragma unroll
+            for (int q = 0; q < RU; ++q) a0[q] = gp(R.tab.idx)[e0[q]];
+#pragma unroll
+            for (int q = 0; q < RU; ++q) {
+                const int a = a0[q];
+                const double fr = gp(R.tab.frac)[e0[q]];
                 const double ga = (double)sg[a];
                 const double xa = gp(Ls.xi_x)[a], ya = gp(Ls.xi_y)[a];
-                gP += fr * ga;
-                HP += fr * ((double)sh[a] + (xa * xa + ya * ya) * ga);
+                gP[q] = 0.0;
+                HP[q] = 0.0;
+                gP[q] += fr * ga;
+                HP[q] += fr * ((double)sh[a] + (xa * xa + ya * ya) * ga);
             }
-            const double x = gp(Ld.xi_x)[P], y = gp(Ld.xi_y)[P], w = gp(Ld.w)[P];
-            const S gs = (S)gP, hs = (S)(HP - (x * x + y * y) * gP);
-            dg[P] = gs;
-            dh[P] = hs;
-            acc_m9(m + 9, w, x, y, (double)gs, (double)hs);
+#pragma unroll
+            for (int q = 0; q < RU; ++q) {
+                for (int e = e0[q] + 1; e < e1[q]; ++e) {
+                    const int a = gp(R.tab.idx)[e];
+                    const double fr = gp(R.tab.frac)[e];
+                    const double ga = (double)sg[a];
+                    const double xa = gp(Ls.xi_x)[a], ya = gp(Ls.xi_y)[a];
+                    gP[q] += fr * ga;
+                    HP[q] += fr * ((double)sh[a] + (xa * xa + ya * ya) * ga);
+                }
+                const int P = P0 + q * WL;
+                if (P < Ld.N) {
+                    const double x = gp(Ld.xi_x)[P], y = gp(Ld.xi_y)[P], w = gp(Ld.w)[P];
+                    const S gs = (S)gP[q], hs = (S)(HP[q] - (x * x + y * y) * gP[q]);
+                    dg[P] = gs;
+                    dh[P] = hs;
+                    acc_m9(m + 9, w, x, y, (double)gs, (double)hs);
+                }
+            }
         }
         wave_sum<18>(m);
         int nf = 0;
