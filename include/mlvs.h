@@ -388,7 +388,7 @@ mlvs_status mlvs_positivity_counts(mlvs_ctx ctx, int64_t* applied, int64_t* fail
  * direction (structured meshes) or least squares over the face neighbours
  * (unstructured meshes).  Labels: the fewest-point level of the
  * current catalogue whose enclosing mask is no coarser than the cell's own
- * criterion mask anywhere (the criterion is the judge), -1 if none. */
+ * criterion mask anywhere (the criterion decides), -1 if none. */
 typedef struct {
     int epochs, batch;
     double lr, beta1, beta2, eps;
