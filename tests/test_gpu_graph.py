@@ -177,3 +177,29 @@ def test_persistent_step_large_levels_match_oracle():
     assert np.allclose(g.totals(), t0, rtol=1e-12, atol=1e-14 * np.max(np.abs(t0)))
     assert g.graph_info()["error"] == 0
     g.close()
+
+
+def test_persistent_step_full_size_cylinder_bit_identical_to_staged():
+    """Full-size cylinder (256 x 128, 101^2, FP32, MLVS with adaptation every
+    5 steps after base-grid steps): the persistent single-launch step gives
+    the staged step's state bit for bit across adaptations, with one graph
+    capture where the staged step captures again after each level change."""
+    import torch
+    p = W.cylinder(256, 128, Kn=0.1, nv=101, vmax=10.0)
+    ap = dict(C_split=0.01, C_merge=0.005, eps_merge=2e-5, tau_clust=0.05, flux_test=True, interval=0)
+    runs = []
+    for persistent in (False, True):
+        s = _gpu(p, precision=32, compat=4, adapt=ap, graph=True)
+        s.step(20)
+        s.set_persistent(persistent)
+        s.set_adapt(dict(ap, interval=5))
+        g0 = s.graph_info()
+        s.step(20)
+        g1 = s.graph_info()
+        runs.append((s.get_state(), g1["captures"] - g0["captures"], s.counters()["adaptations"], g1["error"]))
+        s.close()
+        torch.cuda.empty_cache()
+    (sa, ca, na, _), (sb, cb, nb, eb) = runs
+    assert na == nb >= 4 and eb == 0
+    assert cb == 1 and ca >= 1
+    assert all(np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1]) for x, y in zip(sa, sb))
