@@ -1315,7 +1315,7 @@ void build_items(mlvs_ctx c) {
     std::vector<int> cell_nbr(4 * n, -1);
     std::vector<GhostItem> gitems;
     std::vector<TabOff> gtab;
-    std::map<std::pair<int, int>, int> ghost_of;        // (source cell, dst level) -> row
+    std::vector<int> ghost_of((size_t)n * std::max(K, 1), -1);   // [source cell][dst level] -> row
     std::map<std::pair<int, int>, TabOff> tab_of;       // (dst level idx, src level idx)
     auto table = [&](int dst, int src) {
         auto key = std::make_pair(dst, src);
@@ -1339,21 +1339,39 @@ void build_items(mlvs_ctx c) {
             if (nb < 0) continue;
             const int lc = c->cell_level[cc], ln = c->cell_level[nb];
             if (lc == ln) { cell_nbr[4 * cc + k] = nb; continue; }
-            auto key = std::make_pair(nb, lc);
-            int row;
-            auto it = ghost_of.find(key);
-            if (it == ghost_of.end()) {
+            int& row = ghost_of[(size_t)nb * K + lc];
+            if (row < 0) {
                 row = ghosts[lc]++;
-                ghost_of[key] = row;
                 GhostItem G{};
                 G.n = nb; G.dst = lc; G.row = row;
                 gitems.push_back(G);
-                gtab.push_back(table(lc, ln));
-            } else {
-                row = it->second;
             }
             cell_nbr[4 * cc + k] = -2 - row;
         }
+    {
+        // the ghost rows' (dst, src) level tables, built in parallel
+        std::vector<std::pair<int, int>> want;
+        std::vector<char> seen((size_t)std::max(K * K, 1), 0);
+        for (const GhostItem& G : gitems) {
+            const int src = c->cell_level[G.n];
+            if (!seen[(size_t)G.dst * K + src]) {
+                seen[(size_t)G.dst * K + src] = 1;
+                want.emplace_back(G.dst, src);
+            }
+        }
+        std::vector<std::pair<const Level*, const Level*>> lp;
+        for (auto& ds : want) lp.emplace_back(c->levels[ds.first].get(), c->levels[ds.second].get());
+        const std::vector<HostTable> built = make_tables(lp);
+        for (size_t i = 0; i < want.size(); ++i) {
+            TabOff t;
+            t.off = stg.put(built[i].off);
+            t.idx = stg.put(built[i].idx);
+            t.frac = stg.put(built[i].frac);
+            tab_of[want[i]] = t;
+        }
+        gtab.reserve(gitems.size());
+        for (const GhostItem& G : gitems) gtab.push_back(table(G.dst, c->cell_level[G.n]));
+    }
     mk.mark("items: ghosts", c->st);
     // face slots of the mesh (topology only, computed once)
     if (M.face_kL.size() != M.faces.size() || M.bface_k.size() != M.bfaces.size()) {
