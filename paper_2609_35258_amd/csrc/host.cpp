@@ -1091,7 +1091,13 @@ struct mlvs_ctx_s {
     double* d_ctab = nullptr;          // criterion tables of the base grid's blocks
     // host geometry of recently built levels by their mask (levels recur from
     // one adaptation to the next); copies carry no device memory
-    std::map<std::vector<uint8_t>, std::unique_ptr<Level>> level_cache;
+    // built levels by mask (host tables only), least recently used evicted
+    struct CachedLevel {
+        std::unique_ptr<Level> L;
+        uint64_t used = 0;
+    };
+    std::map<std::vector<uint8_t>, CachedLevel> level_cache;
+    uint64_t level_tick = 0;
     PinnedBuf pin_masks;               // host copy of the unique masks (adaptation)
     uint8_t* d_kappa_all = nullptr;
     uint8_t* d_kcell = nullptr;
@@ -1226,13 +1232,26 @@ Level& level_by_index(mlvs_ctx c, int i) {
     return *c->ifaces[i - c->levels.size()];
 }
 
+constexpr size_t LEVEL_CACHE_MAX = 256;
+
+// Make room for `add` more levels: drop the least recently used.
+void level_cache_trim(mlvs_ctx c, size_t add) {
+    while (!c->level_cache.empty() && c->level_cache.size() + add > LEVEL_CACHE_MAX) {
+        auto old = c->level_cache.begin();
+        for (auto it = c->level_cache.begin(); it != c->level_cache.end(); ++it)
+            if (it->second.used < old->second.used) old = it;
+        c->level_cache.erase(old);
+    }
+}
+
 std::unique_ptr<Level> level_of_mask(mlvs_ctx c, const std::vector<uint8_t>& kappa) {
     auto it = c->level_cache.find(kappa);
     if (it == c->level_cache.end()) {
-        if (c->level_cache.size() >= 64) c->level_cache.clear();
-        it = c->level_cache.emplace(kappa, build_level(c->base, kappa)).first;
+        level_cache_trim(c, 1);
+        it = c->level_cache.emplace(kappa, mlvs_ctx_s::CachedLevel{build_level(c->base, kappa), 0}).first;
     }
-    return std::make_unique<Level>(*it->second);
+    it->second.used = ++c->level_tick;
+    return std::make_unique<Level>(*it->second.L);
 }
 
 // Build the levels of the masks the cache does not hold yet, in parallel on
@@ -1241,13 +1260,17 @@ std::unique_ptr<Level> level_of_mask(mlvs_ctx c, const std::vector<uint8_t>& kap
 void prefill_levels(mlvs_ctx c, const std::vector<std::vector<uint8_t>>& masks) {
     std::vector<const std::vector<uint8_t>*> miss;
     for (auto& k : masks) {
-        if (c->level_cache.count(k)) continue;
+        auto hit = c->level_cache.find(k);
+        if (hit != c->level_cache.end()) {
+            hit->second.used = ++c->level_tick;          // in use: not the one to evict
+            continue;
+        }
         bool dup = false;
         for (auto* m : miss) dup = dup || *m == k;
         if (!dup) miss.push_back(&k);
     }
     if (miss.empty()) return;
-    if (c->level_cache.size() + miss.size() > 64) c->level_cache.clear();
+    level_cache_trim(c, miss.size());
     std::vector<std::unique_ptr<Level>> built(miss.size());
     const std::function<void(int)> job = [&](int t) {
         HostPool& P = HostPool::get();
@@ -1255,7 +1278,8 @@ void prefill_levels(mlvs_ctx c, const std::vector<std::vector<uint8_t>>& masks) 
             built[i] = build_level(c->base, *miss[i]);
     };
     HostPool::get().run(std::min<int>(HostPool::get().size(), (int)miss.size()), job);
-    for (size_t i = 0; i < miss.size(); ++i) c->level_cache.emplace(*miss[i], std::move(built[i]));
+    for (size_t i = 0; i < miss.size(); ++i)
+        c->level_cache.emplace(*miss[i], mlvs_ctx_s::CachedLevel{std::move(built[i]), ++c->level_tick});
 }
 
 // The dst <- src tables of a list of level pairs, built in parallel.
