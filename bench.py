@@ -974,6 +974,8 @@ def main():
     ap.add_argument("--cylinder-steps", type=int, default=200)
     ap.add_argument("--cylinder-kn", type=float, default=0.1)
     ap.add_argument("--cylinder-mode", choices=("both", "mlvs", "uvs"), default="both")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="only the learned-vs-criterion comparison (selector training and adaptation)")
     ap.add_argument("--persistent-ab", action="store_true",
                     help="only the staged-against-persistent step comparison (cylinder, two-cavity)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -1010,6 +1012,9 @@ def main():
         return
     if args.persistent_ab:
         print(json.dumps({"persistent_ab": persistent_ab()}), flush=True)
+        return
+    if args.learned_only:
+        print(json.dumps({"learned": learned_vs_criterion()}), flush=True)
         return
     if args.cylinder_only:
         print(json.dumps({"cylinder": cylinder_case(steps=args.cylinder_steps, mode=args.cylinder_mode,

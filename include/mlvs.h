@@ -429,10 +429,9 @@ mlvs_status mlvs_mlp_eval(const float* params, int K, const float* X, const int3
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving or training loops, harnesses that forbid hipMalloc):
  * mlvs_mlp_eval on caller-owned device buffers, with no allocation.  The
- * network's intermediate values (standardised inputs, hidden activations and
- * deltas, output deltas, per-sample losses) live in a fixed device array of
- * the library of about 4.6 MB, which each GPU the library runs on holds until
- * the process ends.  d_params [mlvs_mlp_nparams(K)], d_X [B][10] and d_y [B]
+ * partial gradients and loss sums of the batch's workgroups live in a fixed
+ * device array of the library of about 6.0 MB, which each GPU the library
+ * runs on holds until the process ends.  d_params [mlvs_mlp_nparams(K)], d_X [B][10] and d_y [B]
  * (labels in [0, K), not checked) are device inputs; d_probs [B][K],
  * d_grad [mlvs_mlp_nparams(K)] (zero on the mean/std block) and d_loss_sum
  * (one double: the SUM of the per-sample cross-entropies; the mean is it / B)
@@ -444,8 +443,10 @@ mlvs_status mlvs_mlp_eval(const float* params, int K, const float* X, const int3
 mlvs_status mlvs_mlp_eval_noalloc(const float* d_params, int K, const float* d_X, const int32_t* d_y, int B,
                                   float* d_probs, float* d_grad, double* d_loss_sum, void* stream);
 
-/* Inference: classes [B] (argmax) and optional probs [B][K]; bf16 = 1 rounds
- * weights and activations to bfloat16 (FP32 accumulation). */
+/* Inference: classes [B] (argmax, the lowest class on a tie) and optional
+ * probs [B][K]; bf16 = 1 rounds the standardised inputs, weights and hidden
+ * activations to bfloat16 (nearest even) and accumulates in FP32 on the matrix
+ * cores; bf16 = 0 computes in FP32. */
 mlvs_status mlvs_mlp_predict(const float* params, int K, const float* X, int B, int bf16,
                              int32_t* classes, float* probs);
 

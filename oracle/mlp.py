@@ -48,6 +48,30 @@ def forward(theta, X, K, H=64):
     return z3, p, (Xn, z1, a1, z2, a2)
 
 
+def bf16_round(x):
+    """Round to bfloat16 (8 significant bits), to nearest with ties to even.
+    The value is first taken in FP32, as the inference kernel holds it."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(theta, X, K, H=64):
+    """Inference with BF16 operands (reading of the selector's reduced-precision
+    inference): the standardised inputs are formed in FP32, then the inputs,
+    the three weight matrices and both hidden activations are rounded to
+    bfloat16; biases stay FP32; every sum is taken exactly (FP64).  Returns
+    logits and probabilities."""
+    W1, b1, W2, b2, W3, b3, mu, sd = unpack(theta, K, H)
+    X32 = np.asarray(X, np.float32)
+    Xn = bf16_round((X32 - mu.astype(np.float32)) / sd.astype(np.float32))
+    a1 = bf16_round(np.maximum(Xn @ bf16_round(W1).T + b1, 0.0))
+    a2 = bf16_round(np.maximum(a1 @ bf16_round(W2).T + b2, 0.0))
+    z3 = a2 @ bf16_round(W3).T + b3
+    e = np.exp(z3 - z3.max(axis=1, keepdims=True))
+    return z3, e / e.sum(axis=1, keepdims=True)
+
+
 def loss_and_grad(theta, X, y, K, H=64):
     """Mean softmax cross-entropy and its gradient w.r.t. the trainable parameters
     (the normalisation entries get zero gradient)."""

@@ -2353,17 +2353,12 @@ mlvs_status mlvs_mlp_eval(const float* params, int K, const float* X, const int3
         for (int b = 0; b < B; ++b)
             if (y[b] < 0 || y[b] >= K) fail(MLVS_E_ARG, "label out of range");
         const size_t np = mlp_nparams(K), Bs = (size_t)B;
-        DevBuf P(4 * np), G(4 * np), Xd(40 * Bs), Yd(4 * Bs), XN(40 * Bs), A1(256 * Bs), A2(256 * Bs),
-            D1(256 * Bs), D2(256 * Bs), D3(4 * K * Bs), PR(4 * K * Bs), LV(4 * Bs), LS(8);
+        DevBuf P(4 * np), G(4 * np), Xd(40 * Bs), Yd(4 * Bs), PR(4 * K * Bs), PART(mlp_part_bytes(B, K)), LS(8);
         hip_check(hipMemcpy(P.p, params, 4 * np, hipMemcpyHostToDevice), "H2D");
         hip_check(hipMemcpy(Xd.p, X, 40 * Bs, hipMemcpyHostToDevice), "H2D");
         hip_check(hipMemcpy(Yd.p, y, 4 * Bs, hipMemcpyHostToDevice), "H2D");
-        hip_check(hipMemset(G.p, 0, 4 * np), "memset");
-        hip_check(launch_mlp_fwd_bwd(nullptr, P.as<float>(), K, Xd.as<float>(), Yd.as<int>(), nullptr, B,
-                                     XN.as<float>(), A1.as<float>(), A2.as<float>(), D1.as<float>(), D2.as<float>(),
-                                     D3.as<float>(), PR.as<float>(), LV.as<float>(), LS.as<double>()), "fwd/bwd");
-        hip_check(launch_mlp_grad(nullptr, K, B, XN.as<float>(), A1.as<float>(), A2.as<float>(), D1.as<float>(),
-                                  D2.as<float>(), D3.as<float>(), G.as<float>()), "grad");
+        hip_check(launch_mlp_eval(nullptr, P.as<float>(), K, Xd.as<float>(), Yd.as<int>(), B, PR.as<float>(), PART.p,
+                                  G.as<float>(), LS.as<double>()), "forward/backward");
         hip_check(hipDeviceSynchronize(), "sync");
         if (probs) hip_check(hipMemcpy(probs, PR.p, 4 * K * Bs, hipMemcpyDeviceToHost), "D2H");
         if (grad) hip_check(hipMemcpy(grad, G.p, 4 * np, hipMemcpyDeviceToHost), "D2H");
@@ -2434,11 +2429,9 @@ void train_network(float* params, int K, const float* X, const int32_t* y, int64
             P[np - 10 + k] = (float)(v > 1e-12 ? v : 1.0);
         }
         const int B = (int)std::min<int64_t>(cfg->batch, n_tr);
-        const size_t Bs = (size_t)B, ns = (size_t)n;
-        const int ntr = np - 20;
-        DevBuf Pd(4 * (size_t)np), G(4 * (size_t)np), M(4 * (size_t)np), V(4 * (size_t)np), Xd(40 * ns),
-            Yd(4 * ns), IDX(4 * (size_t)n_tr), XN(40 * Bs), A1(256 * Bs), A2(256 * Bs), D1(256 * Bs),
-            D2(256 * Bs), D3(4 * K * Bs), LV(4 * Bs);
+        const size_t ns = (size_t)n;
+        DevBuf Pd(4 * (size_t)np), M(4 * (size_t)np), V(4 * (size_t)np), Xd(40 * ns), Yd(4 * ns),
+            IDX(4 * (size_t)n_tr), PART(mlp_part_bytes(B, K));
         const int64_t steps_per_epoch = n_tr / B;
         const int64_t total_steps = steps_per_epoch * cfg->epochs;
         DevBuf LS(8 * (size_t)std::max<int64_t>(total_steps, 1));
@@ -2447,7 +2440,6 @@ void train_network(float* params, int K, const float* X, const int32_t* y, int64
         hip_check(hipMemcpy(Yd.p, y, 4 * ns, hipMemcpyHostToDevice), "H2D");
         hip_check(hipMemset(M.p, 0, 4 * (size_t)np), "memset");
         hip_check(hipMemset(V.p, 0, 4 * (size_t)np), "memset");
-        hip_check(hipMemset(G.p, 0, 4 * (size_t)np), "memset");
         std::vector<int> perm(n_tr);
         uint64_t state = cfg->seed ? cfg->seed : 0x2545f4914f6cdd1dull;
         auto next = [&]() {   // splitmix64
@@ -2466,15 +2458,10 @@ void train_network(float* params, int K, const float* X, const int32_t* y, int64
             for (int64_t i = n_tr - 1; i > 0; --i) std::swap(perm[i], perm[next() % (uint64_t)(i + 1)]);
             hip_check(hipMemcpy(IDX.p, perm.data(), 4 * (size_t)n_tr, hipMemcpyHostToDevice), "H2D");
             for (int64_t sidx = 0; sidx < steps_per_epoch; ++sidx, ++t) {
-                hip_check(launch_mlp_fwd_bwd(nullptr, Pd.as<float>(), K, Xd.as<float>(), Yd.as<int>(),
-                                             IDX.as<int>() + sidx * B, B, XN.as<float>(), A1.as<float>(),
-                                             A2.as<float>(), D1.as<float>(), D2.as<float>(), D3.as<float>(), nullptr,
-                                             LV.as<float>(), LS.as<double>() + t), "fwd/bwd");
-                hip_check(launch_mlp_grad(nullptr, K, B, XN.as<float>(), A1.as<float>(), A2.as<float>(),
-                                          D1.as<float>(), D2.as<float>(), D3.as<float>(), G.as<float>()), "grad");
-                hip_check(launch_adam(nullptr, Pd.as<float>(), G.as<float>(), M.as<float>(), V.as<float>(), ntr,
-                                      (float)cfg->lr, (float)cfg->beta1, (float)cfg->beta2, (float)cfg->eps,
-                                      (int)(t + 1)), "adam");
+                hip_check(launch_mlp_train_step(nullptr, Pd.as<float>(), K, Xd.as<float>(), Yd.as<int>(),
+                                                IDX.as<int>() + sidx * B, B, PART.p, LS.as<double>() + t, M.as<float>(),
+                                                V.as<float>(), (float)cfg->lr, (float)cfg->beta1, (float)cfg->beta2,
+                                                (float)cfg->eps, (int)(t + 1)), "training step");
             }
         }
         hip_check(hipEventRecord(e1, nullptr), "event");

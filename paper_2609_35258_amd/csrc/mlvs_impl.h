@@ -212,20 +212,24 @@ hipError_t launch_compare_rows_u8(hipStream_t st, const uint8_t* all, int width,
 int mlp_nparams(int K);
 hipError_t launch_features(hipStream_t st, const double* f8, const int* nbr_cell, const CellGeom* geom, int n,
                            double R, double T_ref, double mu_ref, double omega, int unstructured, float* out);
-hipError_t launch_mlp_fwd_bwd(hipStream_t st, const float* P, int K, const float* X, const int* y, const int* idx,
-                              int B, float* XN, float* A1, float* A2, float* D1, float* D2, float* D3, float* prob,
-                              float* lossv, double* loss_sum);
-hipError_t launch_mlp_grad(hipStream_t st, int K, int B, const float* XN, const float* A1, const float* A2,
-                           const float* D1, const float* D2, const float* D3, float* G);
+// Device bytes of the partial-gradient buffer a batch of B samples needs.
+size_t mlp_part_bytes(int B, int K);
+// Forward and backward of a batch: probabilities (prob [B][K], may be null),
+// the gradient (grad [mlp_nparams(K)], zero on the standardisation block) and
+// the summed loss, through the caller's partial-gradient buffer `part`.
+hipError_t launch_mlp_eval(hipStream_t st, const float* P, int K, const float* X, const int* y, int B, float* prob,
+                           void* part, float* grad, double* loss_sum);
+// One Adam step (step number t >= 1) on the batch idx[0..B) of (X, y).
+hipError_t launch_mlp_train_step(hipStream_t st, float* P, int K, const float* X, const int* y, const int* idx, int B,
+                                 void* part, double* loss_sum, float* M, float* V, float lr, float b1, float b2,
+                                 float eps, int t);
 // Forward/backward of a batch of at most NOALLOC_MAX_BATCH samples with the
-// intermediates in the library's fixed device array (no allocation; calls on
-// one GPU share the array).  prob, grad, loss_sum may be null.
+// partial gradients in the library's fixed device array (no allocation; calls
+// on one GPU share the array).  prob, grad, loss_sum may be null.
 constexpr int NOALLOC_MAX_BATCH = 4096;
 size_t noalloc_scratch_bytes();
 hipError_t launch_mlp_eval_noalloc(hipStream_t st, const float* P, int K, const float* X, const int* y, int B,
                                    float* prob, float* grad, double* loss_sum);
-hipError_t launch_adam(hipStream_t st, float* P, const float* G, float* M, float* V, int n, float lr, float b1,
-                       float b2, float eps, int t);
 hipError_t launch_mlp_predict(hipStream_t st, const float* P, int K, const float* X, int B, int bf16, int* cls,
                               float* prob);
 hipError_t launch_tail_check(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,

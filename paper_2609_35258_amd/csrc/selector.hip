@@ -7,6 +7,7 @@
 // W3 [K][64], b3 [K], mean [10], std [10].
 #include "mlvs_impl.h"
 
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 
@@ -86,20 +87,53 @@ __global__ void k_features(const double* __restrict__ f8, const int* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// network: forward + per-sample deltas (thread per sample), weight gradients
-// (thread per weight, fixed-order sum over the batch), Adam
+// network, training and FP32 evaluation.  A workgroup of four waves takes 16
+// samples at a time, four per wave; a wave's 64 lanes are the 64 hidden units,
+// so each layer is a dot product per lane whose other operand is broadcast
+// from LDS.  W2 and W3 are staged in LDS with a row pitch of 65 floats: a row
+// per lane (forward) and a column per lane (backward) are both read without
+// bank conflicts.  Training adds the backward pass and per-lane gradient
+// accumulators; each workgroup writes one partial gradient, summed in a fixed
+// order (waves, then workgroups), so results do not depend on timing.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float to_bf16(float x) {
-    // round to nearest even on the upper 16 bits
-    unsigned int u = __float_as_uint(x);
-    if ((u & 0x7f800000u) == 0x7f800000u) return x;
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xffff0000u);
+constexpr int MW = 4;                              // waves per workgroup
+constexpr int SPW = 4;                             // samples a wave carries together
+constexpr int CHUNK = MW * SPW;                    // samples per workgroup pass
+constexpr int WP = NH + 1;                         // LDS row pitch of W2 and W3
+constexpr int NTR_MAX = NH * NF + NH + NH * NH + NH + KMAX * NH + KMAX;
+constexpr int MAX_PART = 256;                      // partial gradients per batch
+
+static int mlp_groups(int B) {
+    const int ch = (B + CHUNK - 1) / CHUNK;
+    return ch < MAX_PART ? ch : MAX_PART;
 }
 
-template <bool BF16>
-__device__ __forceinline__ void mlp_fwd_one(const float* __restrict__ P, int K, const float* x, float* z1, float* a1,
-                                            float* z2, float* a2, float* z3) {
+// LDS written by some lanes of a wave and then read by others of the same wave
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float4 lds4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+
+// TRAIN: forward, backward and partial gradients (part [gridDim.x][ntr],
+// lpart [gridDim.x] = sum of the per-sample losses); prob [B][K] optional.
+// Otherwise forward only: cls [B] (first maximum) and prob [B][K] optional.
+template <bool TRAIN>
+__global__ __launch_bounds__(256) void k_mlp_batch(const float* __restrict__ P, int K, const float* __restrict__ X,
+                                                   const int* __restrict__ y, const int* __restrict__ idx, int B,
+                                                   float* __restrict__ prob, int* __restrict__ cls,
+                                                   float* __restrict__ part, double* __restrict__ lpart) {
+    __shared__ float sW2[NH * WP];
+    __shared__ float sW3[KMAX * WP];
+    __shared__ __align__(16) float sA1[MW][SPW][NH];
+    __shared__ __align__(16) float sA2[MW][SPW][NH];
+    __shared__ __align__(16) float sD2[MW][SPW][TRAIN ? NH : 4];
+    __shared__ __align__(16) float sD3[MW][SPW][KMAX];
+    __shared__ float sRed[TRAIN ? NTR_MAX : 1];
+    __shared__ double sLoss[MW];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const float* W1 = P;
     const float* b1 = P + mlp_offsets(K, 1);
     const float* W2 = P + mlp_offsets(K, 2);
@@ -108,138 +142,327 @@ __device__ __forceinline__ void mlp_fwd_one(const float* __restrict__ P, int K, 
     const float* b3 = P + mlp_offsets(K, 5);
     const float* mu = P + mlp_offsets(K, 6);
     const float* sd = P + mlp_offsets(K, 7);
-    float xn[NF];
-    for (int k = 0; k < NF; ++k) {
-        xn[k] = (x[k] - mu[k]) / sd[k];
-        if (BF16) xn[k] = to_bf16(xn[k]);
+    for (int t = tid; t < NH * NH; t += 256) sW2[(t >> 6) * WP + (t & 63)] = W2[t];
+    for (int t = tid; t < KMAX * NH; t += 256) sW3[(t >> 6) * WP + (t & 63)] = t < K * NH ? W3[t] : 0.f;
+    float w1[NF];
+    for (int k = 0; k < NF; ++k) w1[k] = W1[l * NF + k];
+    const float bb1 = b1[l], bb2 = b2[l];
+    // output layer: lane = (class j3, quarter q3 of the 64 inputs)
+    const int j3 = l & 15, q3 = l >> 4;
+    const bool cv = j3 < K;
+    const float bb3 = cv ? b3[j3] : 0.f;
+    __syncthreads();
+
+    float g1[NF], g2[NH], g3[KMAX];
+    for (int k = 0; k < NF; ++k) g1[k] = 0.f;
+    for (int k = 0; k < NH; ++k) g2[k] = 0.f;
+    for (int k = 0; k < KMAX; ++k) g3[k] = 0.f;
+    float gb1 = 0.f, gb2 = 0.f, gb3 = 0.f;
+    double wl = 0.0;
+    const int nch = (B + CHUNK - 1) / CHUNK;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        int bpos[SPW], yy[SPW];
+        bool ok[SPW];
+        float xn[SPW][NF], a1[SPW], a2[SPW], z3[SPW], d3[SPW];
+        for (int i = 0; i < SPW; ++i) {
+            bpos[i] = c * CHUNK + w * SPW + i;
+            ok[i] = bpos[i] < B;
+            const int s = ok[i] ? (idx ? idx[bpos[i]] : bpos[i]) : 0;
+            for (int k = 0; k < NF; ++k) xn[i][k] = ok[i] ? (X[(size_t)s * NF + k] - mu[k]) / sd[k] : 0.f;
+            yy[i] = (TRAIN && ok[i]) ? y[s] : 0;
+        }
+        // first hidden layer (lane = unit)
+        for (int i = 0; i < SPW; ++i) {
+            float z = bb1;
+            for (int k = 0; k < NF; ++k) z = fmaf(w1[k], xn[i][k], z);
+            a1[i] = fmaxf(z, 0.f);
+            sA1[w][i][l] = a1[i];
+        }
+        wave_sync();
+        // second hidden layer: row l of W2 against the broadcast first layer
+        {
+            float z[SPW];
+            for (int i = 0; i < SPW; ++i) z[i] = bb2;
+            for (int k = 0; k < NH; k += 4) {
+                const float* wr = sW2 + l * WP + k;
+                const float w0 = wr[0], w1_ = wr[1], w2_ = wr[2], w3_ = wr[3];
+                for (int i = 0; i < SPW; ++i) {
+                    const float4 a = lds4(&sA1[w][i][k]);
+                    z[i] = fmaf(w0, a.x, z[i]);
+                    z[i] = fmaf(w1_, a.y, z[i]);
+                    z[i] = fmaf(w2_, a.z, z[i]);
+                    z[i] = fmaf(w3_, a.w, z[i]);
+                }
+            }
+            for (int i = 0; i < SPW; ++i) {
+                a2[i] = fmaxf(z[i], 0.f);
+                sA2[w][i][l] = a2[i];
+            }
+        }
+        wave_sync();
+        // output layer: each quarter sums 16 inputs, two exchanges join them
+        for (int i = 0; i < SPW; ++i) {
+            float p = 0.f;
+            for (int kk = 0; kk < 16; kk += 4) {
+                const int k = q3 * 16 + kk;
+                const float4 a = lds4(&sA2[w][i][k]);
+                const float* wr = sW3 + j3 * WP + k;
+                p = fmaf(wr[0], a.x, p);
+                p = fmaf(wr[1], a.y, p);
+                p = fmaf(wr[2], a.z, p);
+                p = fmaf(wr[3], a.w, p);
+            }
+            p += __shfl_xor(p, 16, 64);
+            p += __shfl_xor(p, 32, 64);
+            z3[i] = p + bb3;
+        }
+        // softmax over the K classes (every quarter holds all of them)
+        for (int i = 0; i < SPW; ++i) {
+            float m = cv ? z3[i] : -INFINITY;
+            for (int off = 8; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+            const float e = cv ? expf(z3[i] - m) : 0.f;
+            float se = e;
+            for (int off = 8; off > 0; off >>= 1) se += __shfl_xor(se, off, 64);
+            const float pj = e / se;
+            if (prob && ok[i] && q3 == 0 && cv) prob[(size_t)bpos[i] * K + j3] = pj;
+            if (!TRAIN) {
+                const unsigned long long at = __ballot(q3 == 0 && cv && z3[i] == m);
+                if (ok[i] && l == 0) cls[bpos[i]] = at ? __ffsll(at) - 1 : 0;
+            } else {
+                d3[i] = ok[i] ? (pj - (j3 == yy[i] ? 1.f : 0.f)) / (float)B : 0.f;
+                if (q3 == 0) sD3[w][i][j3] = d3[i];
+                const float lz = z3[i] - m - logf(se);
+                const float ly = __shfl(lz, yy[i], 64);
+                if (ok[i]) wl -= (double)ly;
+            }
+        }
+        if (TRAIN) {
+            wave_sync();
+            // back to the second hidden layer (lane = unit; classes >= K carry 0)
+            float d2[SPW], d1[SPW];
+            for (int i = 0; i < SPW; ++i) {
+                float s = 0.f;
+                for (int j = 0; j < KMAX; j += 4) {
+                    const float4 d = lds4(&sD3[w][i][j]);
+                    s = fmaf(d.x, sW3[(j + 0) * WP + l], s);
+                    s = fmaf(d.y, sW3[(j + 1) * WP + l], s);
+                    s = fmaf(d.z, sW3[(j + 2) * WP + l], s);
+                    s = fmaf(d.w, sW3[(j + 3) * WP + l], s);
+                }
+                d2[i] = a2[i] > 0.f ? s : 0.f;
+                sD2[w][i][l] = d2[i];
+            }
+            wave_sync();
+            // back to the first hidden layer: column l of W2
+            {
+                float s[SPW];
+                for (int i = 0; i < SPW; ++i) s[i] = 0.f;
+                for (int j = 0; j < NH; j += 4) {
+                    const float w0 = sW2[(j + 0) * WP + l], w1_ = sW2[(j + 1) * WP + l];
+                    const float w2_ = sW2[(j + 2) * WP + l], w3_ = sW2[(j + 3) * WP + l];
+                    for (int i = 0; i < SPW; ++i) {
+                        const float4 d = lds4(&sD2[w][i][j]);
+                        s[i] = fmaf(d.x, w0, s[i]);
+                        s[i] = fmaf(d.y, w1_, s[i]);
+                        s[i] = fmaf(d.z, w2_, s[i]);
+                        s[i] = fmaf(d.w, w3_, s[i]);
+                    }
+                }
+                for (int i = 0; i < SPW; ++i) d1[i] = a1[i] > 0.f ? s[i] : 0.f;
+            }
+            // gradient accumulators, samples in order: lane l owns W1 row l,
+            // column l of W2 and W3, and bias entry l of each layer
+            for (int i = 0; i < SPW; ++i) {
+                for (int k = 0; k < NF; ++k) g1[k] = fmaf(d1[i], xn[i][k], g1[k]);
+                gb1 += d1[i];
+                gb2 += d2[i];
+                for (int j = 0; j < NH; j += 4) {
+                    const float4 d = lds4(&sD2[w][i][j]);
+                    g2[j + 0] = fmaf(d.x, a1[i], g2[j + 0]);
+                    g2[j + 1] = fmaf(d.y, a1[i], g2[j + 1]);
+                    g2[j + 2] = fmaf(d.z, a1[i], g2[j + 2]);
+                    g2[j + 3] = fmaf(d.w, a1[i], g2[j + 3]);
+                }
+                for (int j = 0; j < KMAX; j += 4) {
+                    const float4 d = lds4(&sD3[w][i][j]);
+                    g3[j + 0] = fmaf(d.x, a2[i], g3[j + 0]);
+                    g3[j + 1] = fmaf(d.y, a2[i], g3[j + 1]);
+                    g3[j + 2] = fmaf(d.z, a2[i], g3[j + 2]);
+                    g3[j + 3] = fmaf(d.w, a2[i], g3[j + 3]);
+                }
+                gb3 += d3[i];
+            }
+        }
+        wave_sync();
     }
-    for (int j = 0; j < NH; ++j) {
-        float s = b1[j];
-        for (int k = 0; k < NF; ++k) s += (BF16 ? to_bf16(W1[j * NF + k]) : W1[j * NF + k]) * xn[k];
-        z1[j] = s;
-        a1[j] = s > 0.f ? s : 0.f;
-        if (BF16) a1[j] = to_bf16(a1[j]);
+    if (!TRAIN) return;
+    // the workgroup's partial: waves added in order through LDS, the last
+    // wave writes the sum
+    const int o1 = mlp_offsets(K, 1), o2 = mlp_offsets(K, 2), o3 = mlp_offsets(K, 3);
+    const int o4 = mlp_offsets(K, 4), o5 = mlp_offsets(K, 5), ntr = mlp_offsets(K, 6);
+    float* out = part + (size_t)blockIdx.x * ntr;
+    for (int r = 0; r < MW; ++r) {
+        if (w == r) {
+            auto put = [&](int e, float v) {
+                if (r == 0) sRed[e] = v;
+                else if (r < MW - 1) sRed[e] += v;
+                else out[e] = sRed[e] + v;
+            };
+            for (int k = 0; k < NF; ++k) put(l * NF + k, g1[k]);
+            put(o1 + l, gb1);
+            for (int j = 0; j < NH; ++j) put(o2 + j * NH + l, g2[j]);
+            put(o3 + l, gb2);
+            for (int j = 0; j < KMAX; ++j)
+                if (j < K) put(o4 + j * NH + l, g3[j]);
+            if (l < K) put(o5 + l, gb3);
+            if (l == 0) sLoss[r] = wl;
+        }
+        __syncthreads();
     }
-    for (int j = 0; j < NH; ++j) {
-        float s = b2[j];
-        for (int k = 0; k < NH; ++k) s += (BF16 ? to_bf16(W2[j * NH + k]) : W2[j * NH + k]) * a1[k];
-        z2[j] = s;
-        a2[j] = s > 0.f ? s : 0.f;
-        if (BF16) a2[j] = to_bf16(a2[j]);
-    }
-    for (int j = 0; j < K; ++j) {
-        float s = b3[j];
-        for (int k = 0; k < NH; ++k) s += (BF16 ? to_bf16(W3[j * NH + k]) : W3[j * NH + k]) * a2[k];
-        z3[j] = s;
+    if (tid == 0) {
+        double s = sLoss[0];
+        for (int r = 1; r < MW; ++r) s += sLoss[r];
+        lpart[blockIdx.x] = s;
     }
 }
 
-// Forward and backward deltas of one batch.  Stores normalised inputs,
-// activations and the deltas dz1, dz2, dz3 per sample, the probabilities and
-// the per-sample loss (for a fixed-order sum afterwards).
-__global__ void k_mlp_fwd_bwd(const float* __restrict__ P, int K, const float* __restrict__ X,
-                              const int* __restrict__ y, const int* __restrict__ idx, int B, float* __restrict__ XN,
-                              float* __restrict__ A1, float* __restrict__ A2, float* __restrict__ D1,
-                              float* __restrict__ D2, float* __restrict__ D3, float* __restrict__ prob,
-                              float* __restrict__ lossv) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    const int s = idx ? idx[b] : b;
-    float x[NF], z1[NH], a1[NH], z2[NH], a2[NH], z3[KMAX];
-    for (int k = 0; k < NF; ++k) x[k] = X[(size_t)s * NF + k];
-    mlp_fwd_one<false>(P, K, x, z1, a1, z2, a2, z3);
-    const float* mu = P + mlp_offsets(K, 6);
-    const float* sd = P + mlp_offsets(K, 7);
-    for (int k = 0; k < NF; ++k) XN[(size_t)b * NF + k] = (x[k] - mu[k]) / sd[k];
-    float zmax = z3[0];
-    for (int j = 1; j < K; ++j) zmax = fmaxf(zmax, z3[j]);
-    float e[KMAX], se = 0.f;
-    for (int j = 0; j < K; ++j) { e[j] = expf(z3[j] - zmax); se += e[j]; }
-    const int yy = y[s];
-    float d3[KMAX];
-    for (int j = 0; j < K; ++j) {
-        const float pj = e[j] / se;
-        if (prob) prob[(size_t)b * K + j] = pj;
-        d3[j] = (pj - (j == yy ? 1.f : 0.f)) / (float)B;
-        D3[(size_t)b * K + j] = d3[j];
-    }
-    lossv[b] = -(z3[yy] - zmax - logf(se));
-    const float* W2 = P + mlp_offsets(K, 2);
-    const float* W3 = P + mlp_offsets(K, 4);
-    float d2[NH];
-    for (int k = 0; k < NH; ++k) {
-        float s2 = 0.f;
-        for (int j = 0; j < K; ++j) s2 += d3[j] * W3[j * NH + k];
-        d2[k] = z2[k] > 0.f ? s2 : 0.f;
-        D2[(size_t)b * NH + k] = d2[k];
-        A2[(size_t)b * NH + k] = a2[k];
-    }
-    for (int k = 0; k < NH; ++k) {
-        float s1 = 0.f;
-        for (int j = 0; j < NH; ++j) s1 += d2[j] * W2[j * NH + k];
-        D1[(size_t)b * NH + k] = z1[k] > 0.f ? s1 : 0.f;
-        A1[(size_t)b * NH + k] = a1[k];
-    }
-}
-
-// Gradient of every trainable parameter: sum over the batch in sample order.
-__global__ void k_mlp_grad(int K, int B, const float* __restrict__ XN, const float* __restrict__ A1,
-                           const float* __restrict__ A2, const float* __restrict__ D1, const float* __restrict__ D2,
-                           const float* __restrict__ D3, float* __restrict__ G) {
+// Sum of the G partial gradients per parameter, in workgroup order, and the
+// loss sum.  ADAM: the Adam update of the trainable parameters; otherwise the
+// gradient is written out (zero on the standardisation block).
+template <bool ADAM>
+__global__ __launch_bounds__(256) void k_mlp_reduce(const float* __restrict__ part, int G, int ntr, int np,
+                                                    const double* __restrict__ lpart, double* __restrict__ loss_sum,
+                                                    float* __restrict__ grad, float* __restrict__ P,
+                                                    float* __restrict__ M, float* __restrict__ V, float lr, float b1,
+                                                    float b2, float eps, float c1, float c2) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ntr = mlp_offsets(K, 6);
-    if (t >= ntr) return;
-    const float *D, *A;
-    int nd, na, i, j = -1;
-    if (t < mlp_offsets(K, 1)) { D = D1; A = XN; nd = NH; na = NF; i = t / NF; j = t % NF; }
-    else if (t < mlp_offsets(K, 2)) { D = D1; A = nullptr; nd = NH; na = 0; i = t - mlp_offsets(K, 1); }
-    else if (t < mlp_offsets(K, 3)) { D = D2; A = A1; nd = NH; na = NH; i = (t - mlp_offsets(K, 2)) / NH; j = (t - mlp_offsets(K, 2)) % NH; }
-    else if (t < mlp_offsets(K, 4)) { D = D2; A = nullptr; nd = NH; na = 0; i = t - mlp_offsets(K, 3); }
-    else if (t < mlp_offsets(K, 5)) { D = D3; A = A2; nd = K; na = NH; i = (t - mlp_offsets(K, 4)) / NH; j = (t - mlp_offsets(K, 4)) % NH; }
-    else { D = D3; A = nullptr; nd = K; na = 0; i = t - mlp_offsets(K, 5); }
+    if (t == 0 && loss_sum) {
+        double s = 0.0;
+        for (int g = 0; g < G; ++g) s += lpart[g];
+        *loss_sum = s;
+    }
+    if (t >= np) return;
+    if (t >= ntr) {
+        if (!ADAM) grad[t] = 0.f;
+        return;
+    }
     float s = 0.f;
-    for (int b = 0; b < B; ++b) s += D[(size_t)b * nd + i] * (A ? A[(size_t)b * na + j] : 1.f);
-    G[t] = s;
-}
-
-__global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ M,
-                       float* __restrict__ V, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const float g = G[t];
-    const float m = b1 * M[t] + (1.f - b1) * g;
-    const float v = b2 * V[t] + (1.f - b2) * g * g;
+    int g = 0;
+    for (; g + 8 <= G; g += 8) {
+        float v[8];
+        for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(g + u) * ntr + t];
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; g < G; ++g) s += part[(size_t)g * ntr + t];
+    if (!ADAM) {
+        grad[t] = s;
+        return;
+    }
+    const float m = b1 * M[t] + (1.f - b1) * s;
+    const float v = b2 * V[t] + (1.f - b2) * s * s;
     M[t] = m;
     V[t] = v;
     P[t] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
-// Single-wave fixed-order sum of n floats (loss) into double.
-__global__ void k_sumf(const float* __restrict__ x, int n, double* __restrict__ out) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += 64) s += (double)x[i];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (threadIdx.x == 0) *out = s;
+// ---------------------------------------------------------------------------
+// BF16 inference on the matrix cores.  Weights and activations are rounded to
+// bfloat16 (nearest even), products accumulate in FP32
+// (v_mfma_f32_16x16x16_bf16).  A wave takes 16 samples; each layer is computed
+// transposed, units x samples = W (units x inputs) . A^T (inputs x samples),
+// so a layer's accumulator registers (lane: sample l % 16, units 4 (l / 16)
+// + i of a 16-unit block) are exactly the next layer's B operand.  The
+// weights stay in registers as A operands for the whole launch.
+// ---------------------------------------------------------------------------
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float x) {
+    unsigned int u = __float_as_uint(x);
+    if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
 }
 
-// Inference (FP32 or BF16-rounded weights and activations, FP32 accumulation).
-template <bool BF16>
-__global__ void k_mlp_predict(const float* __restrict__ P, int K, const float* __restrict__ X, int B,
-                              int* __restrict__ cls, float* __restrict__ prob) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    float x[NF], z1[NH], a1[NH], z2[NH], a2[NH], z3[KMAX];
-    for (int k = 0; k < NF; ++k) x[k] = X[(size_t)b * NF + k];
-    mlp_fwd_one<BF16>(P, K, x, z1, a1, z2, a2, z3);
-    int best = 0;
-    float zmax = z3[0];
-    for (int j = 1; j < K; ++j)
-        if (z3[j] > zmax) { zmax = z3[j]; best = j; }
-    cls[b] = best;
-    if (prob) {
-        float se = 0.f;
-        for (int j = 0; j < K; ++j) se += expf(z3[j] - zmax);
-        for (int j = 0; j < K; ++j) prob[(size_t)b * K + j] = expf(z3[j] - zmax) / se;
+__global__ __launch_bounds__(256) void k_mlp_predict_bf16(const float* __restrict__ P, int K,
+                                                          const float* __restrict__ X, int B, int* __restrict__ cls,
+                                                          float* __restrict__ prob) {
+    const int l = threadIdx.x & 63, c = l & 15, g = l >> 4;
+    const float* W1 = P;
+    const float* b1 = P + mlp_offsets(K, 1);
+    const float* W2 = P + mlp_offsets(K, 2);
+    const float* b2 = P + mlp_offsets(K, 3);
+    const float* W3 = P + mlp_offsets(K, 4);
+    const float* b3 = P + mlp_offsets(K, 5);
+    const float* mu = P + mlp_offsets(K, 6);
+    const float* sd = P + mlp_offsets(K, 7);
+    // A operands: row (output unit) 16 mb + c, inputs 16 kb + 4 g + i
+    bf16x4 w1a[4], w2a[4][4], w3a[4];
+    f32x4 c1[4], c2[4], c3;
+    for (int mb = 0; mb < 4; ++mb) {
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * g + i;
+            w1a[mb][i] = k < NF ? bf16_bits(W1[(mb * 16 + c) * NF + k]) : (short)0;
+            c1[mb][i] = b1[mb * 16 + k];
+            c2[mb][i] = b2[mb * 16 + k];
+        }
+        for (int kb = 0; kb < 4; ++kb)
+            for (int i = 0; i < 4; ++i) w2a[mb][kb][i] = bf16_bits(W2[(mb * 16 + c) * NH + kb * 16 + 4 * g + i]);
+    }
+    for (int kb = 0; kb < 4; ++kb)
+        for (int i = 0; i < 4; ++i) w3a[kb][i] = c < K ? bf16_bits(W3[c * NH + kb * 16 + 4 * g + i]) : (short)0;
+    for (int i = 0; i < 4; ++i) c3[i] = 4 * g + i < K ? b3[4 * g + i] : 0.f;
+
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nw = (gridDim.x * blockDim.x) >> 6;
+    const int ntile = (B + 15) / 16;
+    for (int t = wave; t < ntile; t += nw) {
+        const int b = t * 16 + c;
+        const bool ok = b < B;
+        bf16x4 xb;
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * g + i;
+            xb[i] = (ok && k < NF) ? bf16_bits((X[(size_t)b * NF + k] - mu[k]) / sd[k]) : (short)0;
+        }
+        bf16x4 a1[4], a2[4];
+        for (int mb = 0; mb < 4; ++mb) {
+            const f32x4 h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1a[mb], xb, c1[mb], 0, 0, 0);
+            for (int i = 0; i < 4; ++i) a1[mb][i] = bf16_bits(fmaxf(h[i], 0.f));
+        }
+        for (int mb = 0; mb < 4; ++mb) {
+            f32x4 h = c2[mb];
+            for (int kb = 0; kb < 4; ++kb) h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w2a[mb][kb], a1[kb], h, 0, 0, 0);
+            for (int i = 0; i < 4; ++i) a2[mb][i] = bf16_bits(fmaxf(h[i], 0.f));
+        }
+        f32x4 z = c3;
+        for (int kb = 0; kb < 4; ++kb) z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w3a[kb], a2[kb], z, 0, 0, 0);
+        // lane (c, g) holds classes 4 g .. 4 g + 3 of sample c: the first
+        // maximum over the four lanes of the sample
+        float bv = -INFINITY;
+        int bj = 0x7fffffff;
+        for (int i = 0; i < 4; ++i)
+            if (4 * g + i < K && z[i] > bv) {
+                bv = z[i];
+                bj = 4 * g + i;
+            }
+        for (int off = 16; off < 64; off <<= 1) {
+            const float ov = __shfl_xor(bv, off, 64);
+            const int oj = __shfl_xor(bj, off, 64);
+            if (ov > bv || (ov == bv && oj < bj)) {
+                bv = ov;
+                bj = oj;
+            }
+        }
+        if (ok && g == 0) cls[b] = bj;
+        if (prob) {
+            float e[4], s = 0.f;
+            for (int i = 0; i < 4; ++i) {
+                e[i] = 4 * g + i < K ? expf(z[i] - bv) : 0.f;
+                s += e[i];
+            }
+            s += __shfl_xor(s, 16, 64);
+            s += __shfl_xor(s, 32, 64);
+            for (int i = 0; i < 4; ++i)
+                if (ok && 4 * g + i < K) prob[(size_t)b * K + 4 * g + i] = e[i] / s;
+        }
     }
 }
 
@@ -329,41 +552,56 @@ hipError_t launch_features(hipStream_t st, const double* f8, const int* nbr_cell
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_fwd_bwd(hipStream_t st, const float* P, int K, const float* X, const int* y, const int* idx,
-                              int B, float* XN, float* A1, float* A2, float* D1, float* D2, float* D3, float* prob,
-                              float* lossv, double* loss_sum) {
-    hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3((B + 127) / 128), dim3(128), 0, st, P, K, X, y, idx, B, XN, A1, A2, D1, D2,
-                       D3, prob, lossv);
-    hipLaunchKernelGGL(k_sumf, dim3(1), dim3(64), 0, st, lossv, B, loss_sum);
+size_t mlp_part_bytes(int B, int K) {
+    return sizeof(float) * (size_t)mlp_groups(B) * (size_t)mlp_offsets(K, 6) + sizeof(double) * MAX_PART;
+}
+
+// part: mlp_part_bytes(B, K) bytes of device memory (partial gradients, then
+// the per-workgroup loss sums)
+static void split_part(void* part, int B, int K, float** pg, double** pl) {
+    *pg = static_cast<float*>(part);
+    *pl = reinterpret_cast<double*>(static_cast<char*>(part) + sizeof(float) * (size_t)mlp_groups(B) *
+                                                                   (size_t)mlp_offsets(K, 6));
+}
+
+hipError_t launch_mlp_eval(hipStream_t st, const float* P, int K, const float* X, const int* y, int B, float* prob,
+                           void* part, float* grad, double* loss_sum) {
+    if (B < 1) return hipErrorInvalidValue;
+    float* pg;
+    double* pl;
+    split_part(part, B, K, &pg, &pl);
+    const int G = mlp_groups(B), ntr = mlp_offsets(K, 6), np = mlp_nparams(K);
+    hipLaunchKernelGGL(k_mlp_batch<true>, dim3(G), dim3(256), 0, st, P, K, X, y, nullptr, B, prob, nullptr, pg, pl);
+    hipLaunchKernelGGL(k_mlp_reduce<false>, dim3((np + 255) / 256), dim3(256), 0, st, pg, G, ntr, np, pl, loss_sum,
+                       grad, nullptr, nullptr, nullptr, 0.f, 0.f, 0.f, 0.f, 1.f, 1.f);
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_grad(hipStream_t st, int K, int B, const float* XN, const float* A1, const float* A2,
-                           const float* D1, const float* D2, const float* D3, float* G) {
-    const int n = mlp_offsets(K, 6);
-    hipLaunchKernelGGL(k_mlp_grad, dim3((n + 255) / 256), dim3(256), 0, st, K, B, XN, A1, A2, D1, D2, D3, G);
+hipError_t launch_mlp_train_step(hipStream_t st, float* P, int K, const float* X, const int* y, const int* idx, int B,
+                                 void* part, double* loss_sum, float* M, float* V, float lr, float b1, float b2,
+                                 float eps, int t) {
+    float* pg;
+    double* pl;
+    split_part(part, B, K, &pg, &pl);
+    const int G = mlp_groups(B), ntr = mlp_offsets(K, 6);
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_mlp_batch<true>, dim3(G), dim3(256), 0, st, P, K, X, y, idx, B, nullptr, nullptr, pg, pl);
+    hipLaunchKernelGGL(k_mlp_reduce<true>, dim3((ntr + 255) / 256), dim3(256), 0, st, pg, G, ntr, ntr, pl, loss_sum,
+                       nullptr, P, M, V, lr, b1, b2, eps, c1, c2);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// forward/backward without device allocation: the intermediate values live in
-// a fixed device array of the library
+// forward/backward without device allocation: the partial gradients live in a
+// fixed device array of the library
 // ---------------------------------------------------------------------------
-// Layout (bytes): [0, 256) the loss sum when the caller wants none; then, for
-// at most NOALLOC_MAX_BATCH samples, XN [B][10], A1, A2, D1, D2 [B][64],
-// D3 [B][16], per-sample losses [B] (floats).  Each GPU holds its own copy
-// until the process ends; calls on one GPU share it.
-constexpr size_t NOALLOC_FLOATS_PER_SAMPLE = NF + 4 * NH + KMAX + 1;
-constexpr size_t NOALLOC_BYTES = 256 + sizeof(float) * NOALLOC_FLOATS_PER_SAMPLE * NOALLOC_MAX_BATCH;
+// Layout (bytes): [0, 256) the loss sum when the caller wants none; then the
+// partial gradients and loss sums of at most MAX_PART workgroups (a batch of
+// at most NOALLOC_MAX_BATCH samples needs no more).  Each GPU holds its own
+// copy until the process ends; calls on one GPU share it.
+static_assert((NOALLOC_MAX_BATCH + CHUNK - 1) / CHUNK <= MAX_PART, "no-allocation batch limit");
+constexpr size_t NOALLOC_BYTES = 256 + sizeof(float) * (size_t)MAX_PART * NTR_MAX + sizeof(double) * MAX_PART;
 static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
-
-// Zero the gradient entries the gradient kernel does not write (the
-// standardisation block): a fill kernel, so the launch sequence holds no
-// memset node when a caller captures it in a graph.
-__global__ void k_fill_zero(float* __restrict__ p, int n) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) p[t] = 0.f;
-}
 
 // The array's device address, looked up once per device (with that device
 // current) and kept: in host code the array's name is not a device address.
@@ -395,35 +633,31 @@ hipError_t launch_mlp_eval_noalloc(hipStream_t st, const float* P, int K, const 
     hipError_t e = scratch_address(&base);
     if (e != hipSuccess) return e;
     double* ls = loss_sum ? loss_sum : reinterpret_cast<double*>(base);
-    float* f = reinterpret_cast<float*>(base + 256);
-    const size_t Bs = (size_t)B;
-    float* XN = f;
-    float* A1 = XN + NF * Bs;
-    float* A2 = A1 + NH * Bs;
-    float* D1 = A2 + NH * Bs;
-    float* D2 = D1 + NH * Bs;
-    float* D3 = D2 + NH * Bs;
-    float* LV = D3 + KMAX * Bs;
-    e = launch_mlp_fwd_bwd(st, P, K, X, y, nullptr, B, XN, A1, A2, D1, D2, D3, prob, LV, ls);
-    if (e != hipSuccess || !grad) return e;
-    const int ntr = mlp_offsets(K, 6), np = mlp_nparams(K);
-    hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, st, grad + ntr, np - ntr);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    return launch_mlp_grad(st, K, B, XN, A1, A2, D1, D2, D3, grad);
-}
-
-hipError_t launch_adam(hipStream_t st, float* P, const float* G, float* M, float* V, int n, float lr, float b1,
-                       float b2, float eps, int t) {
-    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
-    hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, P, G, M, V, n, lr, b1, b2, eps, c1, c2);
+    if (mlp_part_bytes(B, K) > NOALLOC_BYTES - 256) return hipErrorInvalidValue;
+    if (grad) return launch_mlp_eval(st, P, K, X, y, B, prob, base + 256, grad, ls);
+    // no gradient wanted: the partials are formed and left in the array
+    float* pg;
+    double* pl;
+    split_part(base + 256, B, K, &pg, &pl);
+    const int G = mlp_groups(B), ntr = mlp_offsets(K, 6);
+    hipLaunchKernelGGL(k_mlp_batch<true>, dim3(G), dim3(256), 0, st, P, K, X, y, nullptr, B, prob, nullptr, pg, pl);
+    hipLaunchKernelGGL(k_mlp_reduce<false>, dim3(1), dim3(64), 0, st, pg, G, ntr, 0, pl, ls, nullptr, nullptr,
+                       nullptr, nullptr, 0.f, 0.f, 0.f, 0.f, 1.f, 1.f);
     return hipGetLastError();
 }
 
 hipError_t launch_mlp_predict(hipStream_t st, const float* P, int K, const float* X, int B, int bf16, int* cls,
                               float* prob) {
     if (B <= 0) return hipSuccess;
-    if (bf16) hipLaunchKernelGGL(k_mlp_predict<true>, dim3((B + 127) / 128), dim3(128), 0, st, P, K, X, B, cls, prob);
-    else hipLaunchKernelGGL(k_mlp_predict<false>, dim3((B + 127) / 128), dim3(128), 0, st, P, K, X, B, cls, prob);
+    if (bf16) {
+        const int waves = (B + 15) / 16;
+        const int wg = std::min((waves + 3) / 4, 2048);
+        hipLaunchKernelGGL(k_mlp_predict_bf16, dim3(wg), dim3(256), 0, st, P, K, X, B, cls, prob);
+    } else {
+        const int wg = std::min((B + CHUNK - 1) / CHUNK, 4096);
+        hipLaunchKernelGGL(k_mlp_batch<false>, dim3(wg), dim3(256), 0, st, P, K, X, nullptr, nullptr, B, prob, cls,
+                           nullptr, nullptr);
+    }
     return hipGetLastError();
 }
 

@@ -56,6 +56,34 @@ def test_bf16_inference_agrees_with_fp32():
     assert np.max(np.abs(p16 - p32)) < 0.05
 
 
+@pytest.mark.parametrize("K,B", [(2, 33), (5, 2001), (16, 1000)])
+def test_inference_matches_oracle(K, B):
+    # FP32 evaluation against the FP64 forward; BF16 matrix-core inference
+    # against the oracle's BF16 forward (same roundings, exact sums).  Ragged
+    # batches (not a multiple of the 16-sample tile) and 2 to 16 classes.
+    th, X, _ = _net(K, B=B, seed=11 + K)
+    th32 = th.astype(np.float32)
+    X32 = X.astype(np.float32)
+    c32, p32 = _m().mlp_predict(th32, K, X32, bf16=False)
+    c16, p16 = _m().mlp_predict(th32, K, X32, bf16=True)
+    t64 = th32.astype(np.float64)
+    z, po, _ = mlp.forward(t64, X32.astype(np.float64), K)
+    assert np.allclose(p32, po, rtol=0, atol=1e-5)
+    top2 = np.sort(z, axis=1)[:, -2:]
+    clear = (top2[:, 1] - top2[:, 0]) > 1e-4
+    assert np.all(c32[clear] == np.argmax(z, axis=1)[clear])
+    zb, pb = mlp.forward_bf16(t64, X32, K)
+    err = np.abs(p16 - pb)
+    # FP32 accumulation order differs; a hidden activation that lands on the
+    # other side of a bfloat16 rounding boundary moves a probability by ~1e-4
+    print("K", K, "B", B, "bf16 prob error max", err.max(), "median", np.median(err), flush=True)
+    assert err.max() < 2e-3 and np.median(err) < 1e-5
+    top2 = np.sort(zb, axis=1)[:, -2:]
+    clear = (top2[:, 1] - top2[:, 0]) > 1e-2
+    assert clear.mean() > 0.9
+    assert np.all(c16[clear] == np.argmax(zb, axis=1)[clear])
+
+
 def test_features_match_oracle():
     p = W.perturb(W.cylinder(16, 8, Kn=0.1, nv=24, vmax=10.0), seed=5, amp=0.1)
     o = Oracle(p, compat=4)

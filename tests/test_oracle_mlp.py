@@ -1,6 +1,7 @@
 """Pins of the oracle MLP: backprop against central finite differences (FP64),
-softmax normalisation, Adam against its closed-form first step, and the label
-rule on hand-made masks."""
+softmax normalisation, Adam against its closed-form first step, the label
+rule on hand-made masks, and the BF16 inference: the rounding on hand-worked
+values and the forward pass on hand-made networks."""
 import numpy as np
 
 import workloads as W
@@ -62,3 +63,64 @@ def test_label_rule():
     sizes = [100, 60, 10]
     cells = np.array([[3, 3, 3], [1, 2, 0], [0, 3, 3], [2, 1, 1]], np.uint8)
     assert list(mlp.label_from_masks(cells, reps, sizes)) == [2, 1, 0, 1]
+
+
+def test_bf16_round_known_values():
+    # spacing 2^-7 just above 1: halfway cases go to the even significand
+    cases = [(1.0, 1.0),
+             (1.0 + 2.0 ** -8, 1.0),
+             (1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -6),
+             (1.0 + 2.0 ** -8 + 2.0 ** -20, 1.0 + 2.0 ** -7),
+             (np.pi, 3.140625),
+             (-0.1, -0.10009765625),
+             (0.0, 0.0)]
+    x = np.array([c[0] for c in cases])
+    assert np.array_equal(mlp.bf16_round(x), np.array([c[1] for c in cases]))
+
+
+def _tiny_net(K, H, rng):
+    """Integer weights, biases and inputs: every value on the way is a small
+    integer, exact in bfloat16."""
+    th = np.zeros(mlp.n_params(K, H))
+    o = 0
+    for rows, cols in ((H, mlp.NF), (H, H), (K, H)):
+        th[o:o + rows * cols] = rng.integers(-1, 2, size=rows * cols)
+        o += rows * cols
+        th[o:o + rows] = rng.integers(-2, 3, size=rows)
+        o += rows
+    th[o + mlp.NF:] = 1.0                     # mean 0, std 1
+    return th
+
+
+def test_bf16_forward_is_exact_on_representable_values():
+    rng = np.random.default_rng(3)
+    K, H = 4, 8
+    th = _tiny_net(K, H, rng)
+    X = rng.integers(-3, 4, size=(50, mlp.NF)).astype(np.float64)
+    z, p, _ = mlp.forward(th, X, K, H)
+    zb, pb = mlp.forward_bf16(th, X, K, H)
+    assert np.max(np.abs(z)) < 256           # integers below 2^8: exact in bfloat16
+    assert np.array_equal(z, zb) and np.array_equal(p, pb)
+
+
+def test_bf16_forward_rounds_weights_and_activations():
+    K, H = 2, 8
+    base = np.zeros(mlp.n_params(K, H))
+    o_w2 = H * mlp.NF + H
+    o_w3 = o_w2 + H * H + H
+    base[-mlp.NF:] = 1.0
+    base[o_w2] = 1.0                          # W2[0][0]
+    base[o_w3] = 1.0                          # W3[0][0]
+    x = np.zeros((1, mlp.NF))
+    # a weight of 1 + 2^-8 is a tie in bfloat16 and rounds to 1
+    th = base.copy()
+    th[0] = 1.0 + 2.0 ** -8                   # W1[0][0]
+    x[0, 0] = 1.0
+    assert mlp.forward(th, x, K, H)[0][0, 0] == 1.0 + 2.0 ** -8
+    assert mlp.forward_bf16(th, x, K, H)[0][0, 0] == 1.0
+    # exact weights whose sum 1 + 2^-8 is rounded as an activation
+    th = base.copy()
+    th[0], th[1] = 1.0, 2.0 ** -8             # W1[0][0], W1[0][1]
+    x[0, :2] = 1.0
+    assert mlp.forward(th, x, K, H)[0][0, 0] == 1.0 + 2.0 ** -8
+    assert mlp.forward_bf16(th, x, K, H)[0][0, 0] == 1.0
