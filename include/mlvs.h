@@ -486,6 +486,15 @@ mlvs_status mlvs_selector_train(mlvs_ctx ctx, const mlvs_train_cfg* cfg, mlvs_tr
  * criterion and rebuild the catalogue (the network stays installed). */
 mlvs_status mlvs_selector_enable(mlvs_ctx ctx, int on);
 
+/* The tail-mass check of learned adaptation on its own (Sec. 3.2 indicator,
+ * Eq. block-contribution-indicator, applied to a proposed level): levels [n]
+ * is a catalogue level index per cell, proposed for it; accept [n] receives
+ * 1 where no block that level's mask merges carries I_B > C_split on the
+ * cell's current distribution refined to V_base, else 0.  Host arrays, one
+ * entry per cell.  MLVS_E_ARG for a level outside [0, number of levels);
+ * MLVS_E_STATE for dim != 2.  Synchronous on the context's stream. */
+mlvs_status mlvs_selector_check(mlvs_ctx ctx, const int32_t* levels, int32_t* accept);
+
 /* The installed network: *K its class count (0: none); out (may be NULL)
  * receives mlvs_mlp_nparams(*K) floats in the layout above.  Synchronises. */
 mlvs_status mlvs_selector_params(mlvs_ctx ctx, float* out, int* K);

@@ -377,6 +377,29 @@ def criterion(lev: Level, g, h, C_split, C_merge, eps_merge, flux_test):
     return kappa
 
 
+def tail_check(lev: Level, g, h, kappa_prop, C_split):
+    """Tail-mass check of a proposed mask (reading of the learned selector's
+    safeguard): the proposal is rejected when a block it merges carries
+    I_B = max(sum M1, sum M2) > C_split (Eqs. M2, block-contribution-indicator)
+    on the cell's distribution, stored on `lev` and refined to V_base.
+    Returns (accepted, I_max): I_max the largest I_B over the merged blocks,
+    -inf when the mask merges nothing."""
+    base = lev.base
+    gb, hb = refine_to_base(lev, g, h)
+    M1, M2 = indicators(base, gb, hb)
+    I_max = -np.inf
+    for bb in range(base.Nb):
+        s = int(kappa_prop[bb])
+        if s == 0:
+            continue
+        bx, by = bb % base.nbx, bb // base.nbx
+        size = 1 << (s - 1)                 # the block's side in 2x2 blocks
+        if bx % size or by % size:
+            continue                        # visited once, at its first 2x2 block
+        I_max = max(I_max, block_indicator(base, M1, M2, s, bx // size, by // size))
+    return bool(I_max <= C_split), I_max
+
+
 # ---------------------------------------------------------------------------
 # grouping (Sec. 3.2)
 # ---------------------------------------------------------------------------

@@ -158,6 +158,7 @@ _PROTOS = {
                                            ctypes.POINTER(mlvs_train_report)]),
     "mlvs_selector_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "mlvs_selector_params": (ctypes.c_int, [ctypes.c_void_p, _c_float_p, ctypes.POINTER(ctypes.c_int)]),
+    "mlvs_selector_check": (ctypes.c_int, [ctypes.c_void_p, _c_int32_p, _c_int32_p]),
     "mlvs_set_strict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "mlvs_set_adapt": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(mlvs_adapt_params)]),
     "mlvs_destroy": (None, [ctypes.c_void_p]),
@@ -517,6 +518,16 @@ class Solver:
 
     def selector_enable(self, on: bool = True):
         _check(lib().mlvs_selector_enable(self.h, int(on)))
+
+    def selector_check(self, levels):
+        """Tail-mass check of a proposed catalogue level per cell: bool array,
+        True where no block the level merges has I_B > C_split."""
+        lv = np.ascontiguousarray(levels, np.int32)
+        if lv.shape != (self.n_cells,):
+            raise ValueError("one level per cell")
+        acc = np.zeros(self.n_cells, np.int32)
+        _check(lib().mlvs_selector_check(self.h, lv.ctypes.data_as(_c_int32_p), acc.ctypes.data_as(_c_int32_p)))
+        return acc.astype(bool)
 
     def selector_params(self):
         """(params as float32, K) of the installed network, or (None, 0)."""

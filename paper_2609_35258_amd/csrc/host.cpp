@@ -2216,6 +2216,25 @@ std::vector<int> level_order(mlvs_ctx c) {
     return order;
 }
 
+// Tail-mass check of the level d_pred[c] proposed for every cell (d_acc[c] = 1
+// where accepted), on the context's stream.  Cells go in groups of one level
+// and consecutive slots, so a wave reads the level's tables once per group.
+void tail_check(mlvs_ctx c, const int* d_pred, int* d_acc) {
+    const int n = c->mesh.n_cells, K = (int)c->levels.size();
+    std::vector<int> cnt(K, 0);
+    for (int cc = 0; cc < n; ++cc) cnt[c->cell_level[cc]]++;
+    std::vector<int> start(K + 1, 0);
+    for (int l = 0; l < K; ++l) start[l + 1] = start[l] + (cnt[l] + TAIL_GROUP - 1) / TAIL_GROUP * TAIL_GROUP;
+    std::vector<int> grp(start[K], -1);
+    for (int cc = 0; cc < n; ++cc) grp[start[c->cell_level[cc]] + c->cell_slot[cc]] = cc;
+    int* d_grp = upload(c->dm, grp, c->st);
+    hip_check(launch_tail_check(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, d_grp,
+                                start[K] / TAIL_GROUP, c->d_ptb_all, c->d_ptb_off, c->d_kappa_all, d_pred, c->d_bw,
+                                c->base.nx, c->base.ny, c->ap.C_split, d_acc), "tail check launch");
+    sync(c);
+    c->dm.release(d_grp);
+}
+
 // Frozen catalogue: predicted level per cell, tail-mass check, criterion labels
 // for the rejected cells, remap of the cells whose level changes.
 void adapt_learned(mlvs_ctx c, mlvs_adapt_report* rep) {
@@ -2226,9 +2245,7 @@ void adapt_learned(mlvs_ctx c, mlvs_adapt_report* rep) {
     int* d_acc = static_cast<int*>(c->dm.alloc(sizeof(int) * (size_t)n));
     compute_features(c, d_feat);
     hip_check(launch_mlp_predict(c->st, c->d_sel, K, d_feat, n, 1, d_pred, nullptr), "predict launch");
-    hip_check(launch_tail_check(c->prec, c->st, c->d_lv, c->d_cell_lev, c->d_cell_slot, n, c->d_ptb_all,
-                                c->d_ptb_off, c->d_kappa_all, d_pred, c->d_bw, c->base.nx, c->base.ny,
-                                c->ap.C_split, d_acc), "tail check launch");
+    tail_check(c, d_pred, d_acc);
     std::vector<int> pred(n), acc(n);
     hip_check(hipMemcpyAsync(pred.data(), d_pred, sizeof(int) * n, hipMemcpyDeviceToHost, c->st), "D2H");
     hip_check(hipMemcpyAsync(acc.data(), d_acc, sizeof(int) * n, hipMemcpyDeviceToHost, c->st), "D2H");
@@ -2641,6 +2658,24 @@ mlvs_status mlvs_selector_enable(mlvs_ctx c, int on) {
             fail(MLVS_E_STATE, "the network has %d classes but the catalogue %d levels", c->sel_K,
                  (int)c->levels.size());
         c->sel_on = on != 0;
+    });
+}
+
+mlvs_status mlvs_selector_check(mlvs_ctx c, const int32_t* levels, int32_t* accept) {
+    return guarded([&] {
+        if (!c || !levels || !accept) fail(MLVS_E_ARG, "null argument");
+        if (c->ph.D != 2) fail(MLVS_E_STATE, "the tail-mass check needs dim = 2");
+        const int n = c->mesh.n_cells, K = (int)c->levels.size();
+        std::vector<int> lev(levels, levels + n);
+        for (int i = 0; i < n; ++i)
+            if (lev[i] < 0 || lev[i] >= K) fail(MLVS_E_ARG, "level %d of cell %d is not in [0, %d)", lev[i], i, K);
+        int* d_lev = upload(c->dm, lev, c->st);
+        int* d_acc = static_cast<int*>(c->dm.alloc(sizeof(int) * (size_t)n));
+        tail_check(c, d_lev, d_acc);
+        hip_check(hipMemcpyAsync(accept, d_acc, sizeof(int) * (size_t)n, hipMemcpyDeviceToHost, c->st), "D2H");
+        sync(c);
+        c->dm.release(d_lev);
+        c->dm.release(d_acc);
     });
 }
 

@@ -232,9 +232,13 @@ hipError_t launch_mlp_eval_noalloc(hipStream_t st, const float* P, int K, const 
                                    float* prob, float* grad, double* loss_sum);
 hipError_t launch_mlp_predict(hipStream_t st, const float* P, int K, const float* X, int B, int bf16, int* cls,
                               float* prob);
+// Tail-mass check of the proposed level pred[c] of every cell listed in
+// groups [n_groups][TAIL_GROUP]: cells of one level per group, -1 padded.
+constexpr int TAIL_GROUP = 4;
 hipError_t launch_tail_check(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
-                             int n, const int* ptb_all, const int* ptb_off, const uint8_t* kappa_all, const int* pred,
-                             const double* bw, int nx, int ny, double C_split, int* accept);
+                             const int* groups, int n_groups, const int* ptb_all, const int* ptb_off,
+                             const uint8_t* kappa_all, const int* pred, const double* bw, int nx, int ny,
+                             double C_split, int* accept);
 hipError_t launch_labels(hipStream_t st, const uint8_t* kcell, int n, int Nb, const uint8_t* kappa_all,
                          const int* order, int K, int* out);
 

@@ -467,59 +467,112 @@ __global__ __launch_bounds__(256) void k_mlp_predict_bf16(const float* __restric
 }
 
 // ---------------------------------------------------------------------------
-// tail-mass check: reject a predicted level if any block it merges carries an
-// indicator I_B = max(sum M1, sum M2) above C_split on the cell's distribution
+// tail-mass check: reject a proposed level if any block its mask merges
+// carries an indicator I_B = max(sum M1, sum M2) above C_split on the cell's
+// distribution refined to V_base.  A wave takes up to TAIL_GROUP cells of one
+// level, so the level's tables (the point holding each base point, the base
+// weights, the point velocities) are read once for all of them.  The lanes
+// walk V_base in 16 x 16-point tiles, one 2 x 2 block per lane in Morton
+// order: the 4 x 4 and 8 x 8 blocks are runs of 4 and 16 lanes, summed by
+// butterflies.  The totals are constants of the cell and a correctly rounded
+// division is monotone, so max_B (m_B / T) = (max_B m_B) / T: one pass keeps
+// the totals and the largest and smallest merged-block sums, and the decision
+// is taken at the end.
 // ---------------------------------------------------------------------------
 template <typename S>
 __global__ __launch_bounds__(256) void k_tail_check(const LevelDesc* __restrict__ lvs,
                                                     const int* __restrict__ cell_lev,
-                                                    const int* __restrict__ cell_slot, int n_cells,
+                                                    const int* __restrict__ cell_slot,
+                                                    const int* __restrict__ groups, int n_groups,
                                                     const int* __restrict__ ptb_all, const int* __restrict__ ptb_off,
                                                     const uint8_t* __restrict__ kappa_all,
                                                     const int* __restrict__ pred, const double* __restrict__ bw,
                                                     int nx, int ny, double C_split, int* __restrict__ accept) {
+    constexpr int G = TAIL_GROUP;
     const int lane = threadIdx.x & 63;
-    const int c = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-    if (c >= n_cells) return;
-    const int lev = cell_lev[c];
-    const LevelDesc& L = lvs[lev];
-    const size_t row = (size_t)cell_slot[c] * L.stride;
-    const S* g = reinterpret_cast<const S*>(L.g) + row;
-    const S* h = reinterpret_cast<const S*>(L.h) + row;
-    const int* ptb = ptb_all + ptb_off[lev];
+    const int gi = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (gi >= n_groups) return;
     const int nbx = nx / 2, nby = ny / 2, Nb = nbx * nby;
-    const uint8_t* kp = kappa_all + (size_t)pred[c] * Nb;
-    double t[2] = {0.0, 0.0};
-    for (int b = lane; b < nx * ny; b += 64) {
-        const int p = ptb[b];
-        const double gp = (double)g[p];
-        const double xp = L.xi_x[p], yp = L.xi_y[p];
-        t[0] += bw[b] * gp;
-        t[1] += 0.5 * bw[b] * ((double)h[p] + (xp * xp + yp * yp) * gp);
+    int cell[G];
+    for (int k = 0; k < G; ++k) cell[k] = groups[gi * G + k];     // -1: no cell
+    const int lev = cell_lev[cell[0]];
+    const LevelDesc& L = lvs[lev];
+    const S* g[G];
+    const S* h[G];
+    const uint8_t* kp[G];
+    for (int k = 0; k < G; ++k) {
+        const int ck = cell[k] >= 0 ? cell[k] : cell[0];
+        const size_t row = (size_t)cell_slot[ck] * L.stride;
+        g[k] = reinterpret_cast<const S*>(L.g) + row;
+        h[k] = reinterpret_cast<const S*>(L.h) + row;
+        kp[k] = kappa_all + (size_t)pred[ck] * Nb;
     }
-    for (int k = 0; k < 2; ++k)
-        for (int off = 32; off > 0; off >>= 1) t[k] += __shfl_xor(t[k], off, 64);
-    int bad = 0;
-    for (int bb = lane; bb < Nb; bb += 64) {
-        const int s = kp[bb];
-        if (s == 0) continue;
-        const int bx = bb % nbx, by = bb / nbx;
-        const int csz = 1 << (s - 1);
-        if ((bx % csz) != 0 || (by % csz) != 0) continue;       // anchor of its merged block only
-        const int size = 1 << s, X0 = (bx / csz) * size, Y0 = (by / csz) * size;
-        double m1 = 0.0, m2 = 0.0;
-        for (int iy = Y0; iy < Y0 + size; ++iy)
-            for (int ix = X0; ix < X0 + size; ++ix) {
-                const int b = ix + nx * iy, p = ptb[b];
-                const double gp = (double)g[p];
-                const double xp = L.xi_x[p], yp = L.xi_y[p];
-                m1 += bw[b] * gp;
-                m2 += 0.5 * bw[b] * ((double)h[p] + (xp * xp + yp * yp) * gp);
+    const int* ptb = ptb_all + ptb_off[lev];
+    const int mx = (lane & 1) | ((lane >> 1) & 2) | ((lane >> 2) & 4);
+    const int my = ((lane >> 1) & 1) | ((lane >> 2) & 2) | ((lane >> 3) & 4);
+    double T1[G], T2[G], hi1[G], lo1[G], hi2[G], lo2[G];
+    for (int k = 0; k < G; ++k) {
+        T1[k] = T2[k] = 0.0;
+        hi1[k] = hi2[k] = -INFINITY;
+        lo1[k] = lo2[k] = INFINITY;
+    }
+    const int ntx = (nx + 15) >> 4, nty = (ny + 15) >> 4;
+    for (int t = 0; t < ntx * nty; ++t) {
+        const int bx = (t % ntx) * 8 + mx, by = (t / ntx) * 8 + my;
+        double a1[G], a2[G];
+        for (int k = 0; k < G; ++k) a1[k] = a2[k] = 0.0;
+        for (int d = 0; d < 4; ++d) {
+            const int px = 2 * bx + (d & 1), py = 2 * by + (d >> 1);
+            if (px < nx && py < ny) {
+                const int b = px + nx * py;
+                const int p = ptb[b];
+                const double wb = bw[b], xp = L.xi_x[p], yp = L.xi_y[p];
+                const double x2 = xp * xp + yp * yp;
+                for (int k = 0; k < G; ++k) {
+                    const double gp = (double)g[k][p];
+                    a1[k] += wb * gp;
+                    a2[k] += 0.5 * wb * ((double)h[k][p] + x2 * gp);
+                }
             }
-        if (fmax(m1 / t[0], m2 / t[1]) > C_split) bad = 1;
+        }
+        const bool blk = bx < nbx && by < nby;
+        for (int k = 0; k < G; ++k) {
+            T1[k] += a1[k];
+            T2[k] += a2[k];
+            const int s = blk ? kp[k][bx + nbx * by] : 0;
+            const double m1 = blk ? a1[k] : 0.0, m2 = blk ? a2[k] : 0.0;
+            double q1 = m1 + __shfl_xor(m1, 1, 64), q2 = m2 + __shfl_xor(m2, 1, 64);
+            q1 += __shfl_xor(q1, 2, 64);
+            q2 += __shfl_xor(q2, 2, 64);
+            double r1 = q1 + __shfl_xor(q1, 4, 64), r2 = q2 + __shfl_xor(q2, 4, 64);
+            r1 += __shfl_xor(r1, 8, 64);
+            r2 += __shfl_xor(r2, 8, 64);
+            if (s > 0) {
+                const double v1 = s == 1 ? m1 : (s == 2 ? q1 : r1);
+                const double v2 = s == 1 ? m2 : (s == 2 ? q2 : r2);
+                hi1[k] = fmax(hi1[k], v1);
+                lo1[k] = fmin(lo1[k], v1);
+                hi2[k] = fmax(hi2[k], v2);
+                lo2[k] = fmin(lo2[k], v2);
+            }
+        }
     }
-    bad = __any(bad);
-    if (lane == 0) accept[c] = bad ? 0 : 1;
+    for (int k = 0; k < G; ++k)
+        for (int off = 32; off > 0; off >>= 1) {
+            T1[k] += __shfl_xor(T1[k], off, 64);
+            T2[k] += __shfl_xor(T2[k], off, 64);
+            hi1[k] = fmax(hi1[k], __shfl_xor(hi1[k], off, 64));
+            lo1[k] = fmin(lo1[k], __shfl_xor(lo1[k], off, 64));
+            hi2[k] = fmax(hi2[k], __shfl_xor(hi2[k], off, 64));
+            lo2[k] = fmin(lo2[k], __shfl_xor(lo2[k], off, 64));
+        }
+    if (lane == 0)
+        for (int k = 0; k < G; ++k) {
+            if (cell[k] < 0) continue;
+            const double A1 = (T1[k] >= 0.0 ? hi1[k] : lo1[k]) / T1[k];
+            const double A2 = (T2[k] >= 0.0 ? hi2[k] : lo2[k]) / T2[k];
+            accept[cell[k]] = (A1 > C_split || A2 > C_split) ? 0 : 1;
+        }
 }
 
 // Label rule on the device: fewest-point catalogue level whose enclosing mask
@@ -662,14 +715,16 @@ hipError_t launch_mlp_predict(hipStream_t st, const float* P, int K, const float
 }
 
 hipError_t launch_tail_check(int prec, hipStream_t st, const LevelDesc* lv, const int* cell_lev, const int* cell_slot,
-                             int n, const int* ptb_all, const int* ptb_off, const uint8_t* kappa_all, const int* pred,
-                             const double* bw, int nx, int ny, double C_split, int* accept) {
-    if (n <= 0) return hipSuccess;
+                             const int* groups, int n_groups, const int* ptb_all, const int* ptb_off,
+                             const uint8_t* kappa_all, const int* pred, const double* bw, int nx, int ny,
+                             double C_split, int* accept) {
+    if (n_groups <= 0) return hipSuccess;
+    const dim3 grid((n_groups + 3) / 4);
     if (prec == 32)
-        hipLaunchKernelGGL(k_tail_check<float>, dim3((n + 3) / 4), dim3(256), 0, st, lv, cell_lev, cell_slot, n,
+        hipLaunchKernelGGL(k_tail_check<float>, grid, dim3(256), 0, st, lv, cell_lev, cell_slot, groups, n_groups,
                            ptb_all, ptb_off, kappa_all, pred, bw, nx, ny, C_split, accept);
     else
-        hipLaunchKernelGGL(k_tail_check<double>, dim3((n + 3) / 4), dim3(256), 0, st, lv, cell_lev, cell_slot, n,
+        hipLaunchKernelGGL(k_tail_check<double>, grid, dim3(256), 0, st, lv, cell_lev, cell_slot, groups, n_groups,
                            ptb_all, ptb_off, kappa_all, pred, bw, nx, ny, C_split, accept);
     return hipGetLastError();
 }

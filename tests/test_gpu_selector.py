@@ -143,6 +143,41 @@ def test_labels_match_oracle():
     g.close()
 
 
+@pytest.mark.parametrize("precision", [64, 32])
+def test_tail_check_matches_oracle(precision):
+    # the tail-mass check of a seeded proposed level per cell against the
+    # oracle's; base grid 21^2 (one full and one partial 16-point tile per
+    # axis, and an odd edge row and column outside every 2x2 block), a
+    # catalogue of seeded masks with 8x8, 4x4 and 2x2 merges, C_split at the
+    # median of the oracle's largest block indicators so that both outcomes
+    # occur; cells whose indicator ties with C_split are excepted
+    p = W.perturb(W.cylinder(16, 8, Kn=0.1, nv=21, vmax=10.0), seed=6, amp=0.1)
+    nb = 21 // 2
+    kap = np.stack([np.zeros(nb * nb, np.uint8)] + [W.random_kappa(nb, nb, seed=s) for s in (1, 2, 3, 4)])
+    cl = W.block_levels(16, 8, len(kap), seed=6, block=4)
+    o = Oracle(p, compat=4)
+    o.set_levels(list(kap), cl)
+    n = p.n_cells
+    prop = np.random.default_rng(7).integers(0, len(kap), size=n)
+    res = [lv.tail_check(o.levels[o.cell_level[c]], o.g[c], o.h[c], kap[prop[c]], 1.0) for c in range(n)]
+    imax = np.array([r[1] for r in res])
+    C = float(np.median(imax[np.isfinite(imax)]))
+    ok_o = imax <= C
+    g = _m().Solver.from_problem(p, precision=precision, compat=4,
+                                 adapt=dict(C_split=C, C_merge=C / 2, eps_merge=1e-3, tau_clust=0.03,
+                                            flux_test=True, interval=0))
+    g.set_levels(kap, cl)
+    ok_g = g.selector_check(prop)
+    tie = np.abs(imax - C) <= (1e-9 if precision == 64 else 1e-5) * C
+    print("precision", precision, "accepted", ok_g.mean(), "ties", int(tie.sum()), flush=True)
+    assert 0.2 < ok_o.mean() < 0.8
+    diff = (ok_g != ok_o) & ~tie
+    assert not diff.any(), (np.nonzero(diff)[0], imax[diff], C)
+    with pytest.raises(_m().MLVSError):
+        g.selector_check(np.full(n, len(kap)))
+    g.close()
+
+
 def test_adam_steps_match_oracle():
     # two full-batch training steps on the device (forward, backward, Adam)
     # against the oracle's gradient and Adam update from the same start

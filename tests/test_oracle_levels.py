@@ -391,3 +391,65 @@ def test_exp_correction_hits_targets_keeps_sign_and_is_noop_on_its_own_moments()
     g0[::7] = 0.0
     gz, _, _, ok = lv.mapping_correct_exp(L, g0, h, lv.moments4(L.xi, L.w, g0, h) * np.array([1.01, 1, 1, 1]))
     assert ok and np.all(gz[::7] == 0.0) and np.all(gz >= 0)
+
+
+def _point_masses(base, pts, fractions):
+    """g with the given mass fractions on single base points, h = 0."""
+    g = np.zeros(base.N)
+    for q, f in zip(pts, fractions):
+        g[q] = f / base.w[q]
+    return g, np.zeros(base.N)
+
+
+def test_tail_check_point_mass():
+    # all the mass and energy on one point of 2x2 block (1, 1): a proposal
+    # that merges that block (alone or inside the 8x8 block) carries I_B = 1,
+    # any other merge I_B = 0, no merge nothing
+    base = _base(nv=8)
+    lev = lv.Level(base, np.zeros(base.Nb, np.uint8))
+    g, h = _point_masses(base, [3 + 8 * 2], [1.0])
+    k = np.zeros(base.Nb, np.uint8)
+    assert lv.tail_check(lev, g, h, k, 0.5) == (True, -np.inf)
+    k1 = k.copy()
+    k1[1 + base.nbx * 1] = 1
+    assert lv.tail_check(lev, g, h, k1, 0.5) == (False, 1.0)
+    k2 = k.copy()
+    k2[3 + base.nbx * 3] = 1
+    assert lv.tail_check(lev, g, h, k2, 0.5) == (True, 0.0)
+    assert lv.tail_check(lev, g, h, np.full(base.Nb, 3, np.uint8), 0.99) == (False, 1.0)
+
+
+def test_tail_check_takes_the_larger_of_mass_and_energy_fractions():
+    # 30% of the mass at the corner (largest |xi|^2), 70% near the centre:
+    # merging the corner block carries a mass fraction 0.3 but an energy
+    # fraction e0 = 0.3 |xi_0|^2 / (0.3 |xi_0|^2 + 0.7 |xi_1|^2) > 0.9
+    base = _base(nv=8)
+    lev = lv.Level(base, np.zeros(base.Nb, np.uint8))
+    x2 = np.sum(base.xi ** 2, axis=1)
+    p0, p1 = 0, 3 + 8 * 3
+    g, h = _point_masses(base, [p0, p1], [0.3, 0.7])
+    e0 = 0.3 * x2[p0] / (0.3 * x2[p0] + 0.7 * x2[p1])
+    assert e0 > 0.9
+    k = np.zeros(base.Nb, np.uint8)
+    k[0] = 1
+    ok, I = lv.tail_check(lev, g, h, k, 0.5)
+    assert not ok and abs(I - e0) < 1e-14
+    assert lv.tail_check(lev, g, h, k, e0 * (1 + 1e-12))[0]
+
+
+def test_tail_check_refines_a_merged_level():
+    # the cell's own level merges 2x2 block (1, 1); its merged point holds all
+    # the mass, which the refinement spreads over the block's four base points
+    base = _base(nv=8)
+    kc = np.zeros(base.Nb, np.uint8)
+    kc[1 + base.nbx * 1] = 1
+    lev = lv.Level(base, kc)
+    q = lev.pt_of_base[2 + 8 * 2]
+    g, h = np.zeros(lev.N), np.zeros(lev.N)
+    g[q] = 1.0 / lev.w[q]
+    k = np.zeros(base.Nb, np.uint8)
+    k[1 + base.nbx * 1] = 1
+    assert lv.tail_check(lev, g, h, k, 0.5) == (False, 1.0)
+    k[:] = 0
+    k[0 + base.nbx * 1] = 1
+    assert lv.tail_check(lev, g, h, k, 0.5) == (True, 0.0)
