@@ -18,6 +18,9 @@ computes is handed to the oracle.
   of its largest value (FP32 storage against FP64).
 * The criterion (Sec. 3.2) on the base grid at full size: the masks of the
   sampled cells bit for bit, blocks at a threshold tie excepted.
+* The tail-mass check of a seeded proposed level per cell (MLVS cases): the
+  decisions of the sampled cells equal the oracle's, ties with C_split
+  excepted.
 * The time step: the oracle's own, from the full mesh, equals the GPU's.
 """
 import numpy as np
@@ -128,15 +131,23 @@ def _sampled_parity(p, mode, samples, seed, tmp):
             jj, ii = np.nonzero(cross)
             assert len(ii) > 0, "no cross-level face along axis %d" % d
             samples = list(samples) + [(int(ii[0]), int(jj[0]))]
+    if mode == "mlvs":
+        prop = np.random.default_rng(seed).integers(0, len(kap), size=p.n_cells)
+        acc = g.selector_check(prop)
     _tune(g, 32, tmp)
     g.step(1)
     for (i, j) in samples:
         i0, j0, cells = _window(p, i, j)
         o = Oracle(W.patch(p, i0, j0), compat=4, dt=dt)
+        k = (i - i0) + 5 * (j - j0)
         if mode == "mlvs":
             o.set_levels(list(kap), cl[cells])
+            c = i + ni * j
+            ok, I = lv.tail_check(o.levels[o.cell_level[k]], o.g[k], o.h[k], kap[prop[c]], ADAPT["C_split"])
+            print("tail check cell", (i, j), "proposed", int(prop[c]), "I_max", I, "accepted", bool(acc[c]), flush=True)
+            if abs(I - ADAPT["C_split"]) > 1e-5 * ADAPT["C_split"]:
+                assert bool(acc[c]) == ok, ((i, j), I)
         o.step()
-        k = (i - i0) + 5 * (j - j0)
         ga, ha = g.get_cell(i + ni * j)
         eg = np.max(np.abs(ga - o.g[k])) / np.max(np.abs(o.g[k]))
         eh = np.max(np.abs(ha - o.h[k])) / np.max(np.abs(o.h[k]))
