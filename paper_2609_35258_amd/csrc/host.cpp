@@ -1822,6 +1822,13 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
     std::vector<std::unique_ptr<Level>> old = std::move(c->levels);
     std::vector<int> old_level = c->cell_level, old_slot = c->cell_slot;
     free_items(c);
+    // the remap reads the old levels' state and geometry only: their row
+    // buffers go now (a free waits for the device, so none may come while the
+    // remap runs)
+    for (auto& L : old) {
+        for (void* p : {L->fg, L->fh, L->Fg, L->Fh}) c->dm.release(p);
+        L->fg = L->fh = L->Fg = L->Fh = nullptr;
+    }
     c->levels = std::move(nl);
     c->cell_level = new_cell_level;
     assign_slots(c);
@@ -1919,15 +1926,17 @@ int64_t install_levels(mlvs_ctx c, std::vector<std::unique_ptr<Level>> nl, const
     hip_check(launch_remap(c->prec, c->st, reinterpret_cast<LevelDesc*>(base + o_od),
                            reinterpret_cast<LevelDesc*>(base + o_nd), reinterpret_cast<RemapItem*>(base + o_items), n,
                            c->ph, c->d_neg), "remap launch");
-    sync(c);
     mk.mark("install: remap kernel", c->st);
+    // The work lists are built on the host while the remap runs: they read
+    // the new level set only, and their upload waits for the remap on the
+    // stream.  The old state and geometry are freed after both.
+    build_items(c);
+    sync(c);
+    mk.mark("install: build_items", c->st);
     for (auto& L : old) free_level(c, *L);
     c->dm.release(c->levels_block);            // the old level set's geometry block
     c->levels_block = base;
     mk.mark("install: free old levels", c->st);
-    build_items(c);
-    sync(c);
-    mk.mark("install: build_items", c->st);
     c->mom_valid = false;
     c->prep_valid = false;
     return changed;
