@@ -421,7 +421,7 @@ def measured_traffic(workload, stage, precision, variant, mk=0, crit=False):
 
 
 def cylinder_case(steps=200, warmup=100, precision=32, mode="both", Kn=0.1):
-    """Supersonic cylinder at full size (256 x 128 O-grid, Ma 3, Kn 0.1, 101^2
+    """Supersonic cylinder at full size (256 x 128 O-grid, Ma 3, Kn 0.1 or 1, 101^2
     Newton-Cotes base grid, FP32 storage), MLVS against UVS.  Both start from
     the freestream and take `warmup` untimed steps on the base grid (an
     impulsive Ma 3 start is not resolved by levels built from the uniform
@@ -1049,6 +1049,7 @@ def main():
     if not (args.no_sections or args.jet_only):
         for name, fn in (("sod", sod_case), ("cavity", cavity_case),
                          ("cylinder", lambda: cylinder_case(steps=args.cylinder_steps)),
+                         ("cylinder_kn1", lambda: cylinder_case(steps=args.cylinder_steps, Kn=1.0)),
                          ("fp32_vs_fp64", fp32_vs_fp64), ("two_cavity", two_cavity_case)):
             t0 = time.perf_counter()
             out[name] = fn()

@@ -73,10 +73,12 @@ def test_fixed_catalog_remap_and_steps(n_levels, axis, seed, map_moments, compat
     g.close()
 
 
-def test_criterion_catalog_cylinder_walls_and_far_field():
-    # catalogue from the oracle's criterion + grouping on a perturbed Ma-3 start
-    p = W.perturb(W.cylinder(16, 8, Kn=0.1, nv=32, vmax=10.0), seed=3, amp=0.1)
-    print("case cylinder catalog", flush=True)
+@pytest.mark.parametrize("Kn", [0.1, 1.0])
+def test_criterion_catalog_cylinder_walls_and_far_field(Kn):
+    # catalogue from the oracle's criterion + grouping on a perturbed Ma-3
+    # start, at both Knudsen numbers of the cylinder workload
+    p = W.perturb(W.cylinder(16, 8, Kn=Kn, nv=32, vmax=10.0), seed=3, amp=0.1)
+    print("case cylinder catalog, Kn", Kn, flush=True)
     o1 = Oracle(p, compat=4, adapt=AdaptParams(5e-3, 2.5e-3, 1e-3, 0.02, True, 100))
     kap, cl = lv.cluster_masks(o1.criterion_masks(), 0.02)
     assert len(kap) >= 2
