@@ -1997,20 +1997,45 @@ void dedupe(mlvs_ctx c, const uint8_t*& uniq, std::vector<int>& first, std::vect
     std::vector<unsigned long long> hs(n);
     hip_check(hipMemcpyAsync(hs.data(), c->d_hash, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, c->st), "D2H");
     sync(c);
-    std::unordered_map<unsigned long long, int> of;
+    // group the cells by hash in first-occurrence order: an open-addressing
+    // table (multiplicative hash, linear probing), doubled when half full
     uidx.assign(n, -1);
     first.clear();
     count.clear();
+    int bits = 12;
+    std::vector<unsigned long long> key(size_t(1) << bits);
+    std::vector<int> val(size_t(1) << bits, -1);
+    auto slot_of = [&](unsigned long long k) {
+        const size_t mask = (size_t(1) << bits) - 1;
+        size_t j = (size_t)((k * 0x9e3779b97f4a7c15ull) >> (64 - bits));
+        while (val[j] >= 0 && key[j] != k) j = (j + 1) & mask;
+        return j;
+    };
     for (int i = 0; i < n; ++i) {
-        auto it = of.find(hs[i]);
-        if (it == of.end()) {
-            of.emplace(hs[i], (int)first.size());
-            uidx[i] = (int)first.size();
-            first.push_back(i);
-            count.push_back(1);
-        } else {
-            uidx[i] = it->second;
-            ++count[it->second];
+        size_t j = slot_of(hs[i]);
+        if (val[j] >= 0) {
+            uidx[i] = val[j];
+            ++count[val[j]];
+            continue;
+        }
+        const int u = (int)first.size();
+        key[j] = hs[i];
+        val[j] = u;
+        uidx[i] = u;
+        first.push_back(i);
+        count.push_back(1);
+        if (2 * first.size() > val.size()) {      // rehash into twice the size
+            ++bits;
+            std::vector<unsigned long long> ok = std::move(key);
+            std::vector<int> ov = std::move(val);
+            key.assign(size_t(1) << bits, 0ull);
+            val.assign(size_t(1) << bits, -1);
+            for (size_t q = 0; q < ov.size(); ++q)
+                if (ov[q] >= 0) {
+                    const size_t t = slot_of(ok[q]);
+                    key[t] = ok[q];
+                    val[t] = ov[q];
+                }
         }
     }
     const int U = (int)first.size();
