@@ -322,24 +322,30 @@ void check_kappa(const Base& B, const uint8_t* k) {
         }
 }
 
-// Velocity and weight of a point made of the base points g: the w-weighted
-// mean and the sum.  A component of a merged point that cancels by the grid's
-// symmetry (within 1e-12 of the members' largest |coordinate|) is exactly
-// zero rather than the rounding residue of the mean, so that xi . n = 0 on
-// faces along the axes is decided as in exact arithmetic.
-void merged_point(const Base& B, const std::vector<int>& g, double& ws, double& x, double& y) {
+// Velocity and weight of the point made of the 2^s x 2^s block of base points
+// whose first (smallest) index is b0, or of the single point b0 when s = 0:
+// the w-weighted mean and the sum, members taken in ascending index order.  A
+// component of a merged point that cancels by the grid's symmetry (within
+// 1e-12 of the members' largest |coordinate|) is exactly zero rather than the
+// rounding residue of the mean, so that xi . n = 0 on faces along the axes is
+// decided as in exact arithmetic.
+void merged_point(const Base& B, int b0, int s, double& ws, double& x, double& y) {
+    const int size = 1 << s;
     double sx = 0.0, sy = 0.0, ex = 0.0, ey = 0.0;
     ws = 0.0;
-    for (int b : g) ws += B.w[b];
-    for (int b : g) {
-        sx += B.w[b] * B.x[b];
-        sy += B.w[b] * B.y[b];
-        ex = std::max(ex, std::fabs(B.x[b]));
-        ey = std::max(ey, std::fabs(B.y[b]));
-    }
+    for (int iy = 0; iy < size; ++iy)
+        for (int ix = 0; ix < size; ++ix) ws += B.w[b0 + ix + B.nx * iy];
+    for (int iy = 0; iy < size; ++iy)
+        for (int ix = 0; ix < size; ++ix) {
+            const int b = b0 + ix + B.nx * iy;
+            sx += B.w[b] * B.x[b];
+            sy += B.w[b] * B.y[b];
+            ex = std::max(ex, std::fabs(B.x[b]));
+            ey = std::max(ey, std::fabs(B.y[b]));
+        }
     x = sx / ws + 0.0;                  // + 0.0: no negative zeros
     y = sy / ws + 0.0;
-    if (g.size() > 1) {
+    if (s > 0) {
         if (std::fabs(x) <= 1e-12 * ex) x = 0.0;
         if (std::fabs(y) <= 1e-12 * ey) y = 0.0;
     }
@@ -348,73 +354,75 @@ void merged_point(const Base& B, const std::vector<int>& g, double& ws, double& 
 std::unique_ptr<Level> build_level(const Base& B, const std::vector<uint8_t>& kappa) {
     auto L = std::make_unique<Level>();
     L->kappa = kappa;
-    std::vector<std::vector<int>> groups;
-    std::vector<char> covered(B.N, 0);
+    // a level point is an aligned 2^s block (s = 1, 2, 3) or a single base
+    // point (s = 0), named by its first base index
+    struct Grp { int b0, s; };
+    // scale of the point starting at each base index (-1: inside another point)
+    std::vector<signed char> start(B.N, 0);
     auto block = [&](int s, int bx, int by) {
-        const int size = 1 << s;
-        std::vector<int> g;
-        for (int iy = by * size; iy < by * size + size; ++iy)
-            for (int ix = bx * size; ix < bx * size + size; ++ix) g.push_back(ix + B.nx * iy);
-        return g;
+        const int size = 1 << s, b0 = bx * size + B.nx * by * size;
+        for (int iy = 0; iy < size; ++iy)
+            for (int ix = 0; ix < size; ++ix) start[b0 + ix + B.nx * iy] = -1;
+        start[b0] = (signed char)s;
     };
     auto kap = [&](int bx, int by) { return (int)kappa[bx + B.nbx * by]; };
     if (B.Nb > 0) {
         for (int oy = 0; oy < B.nby / 4; ++oy)
             for (int ox = 0; ox < B.nbx / 4; ++ox)
-                if (kap(4 * ox, 4 * oy) == 3) groups.push_back(block(3, ox, oy));
+                if (kap(4 * ox, 4 * oy) == 3) block(3, ox, oy);
         for (int qy = 0; qy < B.nby / 2; ++qy)
             for (int qx = 0; qx < B.nbx / 2; ++qx)
-                if (kap(2 * qx, 2 * qy) == 2) groups.push_back(block(2, qx, qy));
+                if (kap(2 * qx, 2 * qy) == 2) block(2, qx, qy);
         for (int by = 0; by < B.nby; ++by)
             for (int bx = 0; bx < B.nbx; ++bx)
-                if (kap(bx, by) == 1) groups.push_back(block(1, bx, by));
+                if (kap(bx, by) == 1) block(1, bx, by);
     }
-    for (auto& g : groups)
-        for (int b : g) covered[b] = 1;
-    for (int b = 0; b < B.N; ++b)
-        if (!covered[b]) groups.push_back({b});
-    for (auto& g : groups) std::sort(g.begin(), g.end());
     // canonical order (the interface order of every per-point array): ascending
     // smallest base index of each point
-    std::sort(groups.begin(), groups.end(), [](const std::vector<int>& a, const std::vector<int>& b) { return a[0] < b[0]; });
+    std::vector<Grp> groups;
+    groups.reserve(B.N);
+    for (int b = 0; b < B.N; ++b)
+        if (start[b] >= 0) groups.push_back({b, start[b]});
+    const int n = (int)groups.size();
+    std::vector<double> pw(n), px(n), py(n);
+    for (int p = 0; p < n; ++p) merged_point(B, groups[p].b0, groups[p].s, pw[p], px[p], py[p]);
     // device order: by polar angle of the point's velocity, then speed, then
     // canonical index.  For any face normal n the points with xi . n > 0 then
     // form one arc of consecutive indices (two pieces if it wraps), so almost
     // every 64-point chunk of a face has a single upwind side.
+    std::vector<int> ord(n);
     {
-        const int n = (int)groups.size();
-        std::vector<double> ang(n), r2(n);
-        for (int p = 0; p < n; ++p) {
-            double ws, x, y;
-            merged_point(B, groups[p], ws, x, y);
-            ang[p] = std::atan2(y, x);
-            r2[p] = x * x + y * y;
-        }
-        std::vector<int> ord(n);
-        for (int p = 0; p < n; ++p) ord[p] = p;
-        std::sort(ord.begin(), ord.end(), [&](int a, int b) {
-            if (ang[a] != ang[b]) return ang[a] < ang[b];
-            if (r2[a] != r2[b]) return r2[a] < r2[b];
-            return a < b;
+        struct Key { double ang, r2; int p; };
+        std::vector<Key> key(n);
+        for (int p = 0; p < n; ++p) key[p] = {std::atan2(py[p], px[p]), px[p] * px[p] + py[p] * py[p], p};
+        std::sort(key.begin(), key.end(), [](const Key& a, const Key& b) {
+            if (a.ang != b.ang) return a.ang < b.ang;
+            if (a.r2 != b.r2) return a.r2 < b.r2;
+            return a.p < b.p;
         });
-        std::vector<std::vector<int>> dev(n);
-        L->canon_of.resize(n);
-        for (int d = 0; d < n; ++d) { dev[d] = std::move(groups[ord[d]]); L->canon_of[d] = ord[d]; }
-        groups = std::move(dev);
+        for (int d = 0; d < n; ++d) ord[d] = key[d].p;
     }
-    L->N = (int)groups.size();
+    L->N = n;
+    L->canon_of = ord;
     L->pt_of_base.assign(B.N, -1);
-    L->mem_off.assign(L->N + 1, 0);
-    L->xi_x.resize(L->N);
-    L->xi_y.resize(L->N);
-    L->w.resize(L->N);
-    for (int p = 0; p < L->N; ++p) {
-        for (int b : groups[p]) {
-            L->pt_of_base[b] = p;
-            L->mem_idx.push_back(b);
-        }
-        merged_point(B, groups[p], L->w[p], L->xi_x[p], L->xi_y[p]);
-        L->mem_off[p + 1] = (int)L->mem_idx.size();
+    L->mem_off.assign(n + 1, 0);
+    L->mem_idx.reserve(B.N);
+    L->xi_x.resize(n);
+    L->xi_y.resize(n);
+    L->w.resize(n);
+    for (int d = 0; d < n; ++d) {
+        const Grp& G = groups[ord[d]];
+        const int size = 1 << G.s;
+        for (int iy = 0; iy < size; ++iy)
+            for (int ix = 0; ix < size; ++ix) {
+                const int b = G.b0 + ix + B.nx * iy;
+                L->pt_of_base[b] = d;
+                L->mem_idx.push_back(b);
+            }
+        L->w[d] = pw[ord[d]];
+        L->xi_x[d] = px[ord[d]];
+        L->xi_y[d] = py[ord[d]];
+        L->mem_off[d + 1] = (int)L->mem_idx.size();
     }
     // criterion tables of the points (normalisations S_r of Eq. merge-transport-error)
     L->crit_tab.assign(6 * (size_t)L->N, 0.0);
