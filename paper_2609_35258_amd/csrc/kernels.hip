@@ -2626,13 +2626,15 @@ __device__ __forceinline__ bool crit_test(const CritCtx& cc, gptr<S> g, gptr<S> 
     return cand;
 }
 
-// Sum of a value over the four lanes of an aligned group of four, in lane
-// order (the same on all four lanes).
+// Sum of a value over the four lanes of an aligned group of four, as
+// (v0 + v1) + (v2 + v3) on all four lanes, by two quad exchanges: lanes 4j,
+// 4j+1 form v0 + v1 and lanes 4j+2, 4j+3 form v2 + v3 (each pair the same
+// value, addition being commutative), then every lane adds the other pair's
+// sum.  The four lanes of a group always run together, so every source lane
+// is active.
 __device__ __forceinline__ double group4_sum(double v) {
-    const int base = lane_id() & ~3;
-    const double v0 = __shfl(v, base, WL), v1 = __shfl(v, base + 1, WL);
-    const double v2 = __shfl(v, base + 2, WL), v3 = __shfl(v, base + 3, WL);
-    return (v0 + v1) + (v2 + v3);
+    const double x = v + dpp_mov<0xB1>(v);       // quad_perm [1,0,3,2]
+    return x + dpp_mov<0x4E>(x);                 // quad_perm [2,3,0,1]
 }
 
 template <typename S>
