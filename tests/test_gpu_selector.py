@@ -32,9 +32,12 @@ def _net(K=4, B=257, seed=3):
     return th, X, y
 
 
-def test_network_forward_backward_matches_oracle():
-    K = 4
-    th, X, y = _net(K)
+@pytest.mark.parametrize("K,B", [(4, 257), (16, 1), (2, 33), (16, 4100)])
+def test_network_forward_backward_matches_oracle(K, B):
+    # ragged batches (not a multiple of the 16-sample workgroup pass), one
+    # sample, 2 and 16 classes, and more passes than partial gradients (4100
+    # samples: 257 passes on 256 workgroups, one of which takes two)
+    th, X, y = _net(K, B=B)
     th32 = th.astype(np.float32)
     probs, grad, loss = _m().mlp_eval(th32, K, X.astype(np.float32), y)
     lo, go, po = mlp.loss_and_grad(th32.astype(np.float64), X.astype(np.float32).astype(np.float64), y, K)

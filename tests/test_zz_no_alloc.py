@@ -46,8 +46,8 @@ def _noalloc(P, K, X, y, B):
 def test_noalloc_eval_matches_the_allocating_entry_point():
     m = _m()
     K = 5
-    P, X, y = _net(K, 3000, 11)
-    for B in (3000, 700):                       # two calls in a row, the second smaller
+    P, X, y = _net(K, 4096, 11)
+    for B in (4096, 700):                       # two calls in a row, the second smaller; 4096 the limit
         print("noalloc eval, batch", B, flush=True)
         p_ref, g_ref, l_ref = m.mlp_eval(P, K, X[:B], y[:B])
         p, g, lsum = _noalloc(P, K, X, y, B)
