@@ -271,21 +271,24 @@ def two_cavity_to_time(t_end=4.0, precision=32, interval=5, map_moments=4, tau_c
             "mlvs_vs_uvs_rel_l2": err, "meets_1e-3_gate_rho_T": _gate(err)}
 
 
-def long_run(kind="cylinder", steps=10000, warmup=100, precision=32, map_moments=4):
+def long_run(kind="cylinder", steps=10000, warmup=100, precision=32, map_moments=4, scale=1.0):
     """A whole run of the cylinder (10,000 steps, about one flow-through) or the
     jet (2,000 steps) from the freestream or background state, MLVS against
     UVS, each timed over the whole run: `warmup` base-grid steps, then the
     MLVS run adapts at the start of every block of 100 steps (adaptation
-    included).  Field differences at the end."""
+    included).  Field differences at the end.  `scale` multiplies C_split,
+    C_merge and eps_merge."""
     import torch
     import paper_2609_35258_amd as m
     from paper_2609_35258_amd import autotune
     p = (W.cylinder(256, 128, Kn=0.1, nv=101, vmax=10.0) if kind == "cylinder"
          else W.jet(512, 256, Kn_jet=1e-3, nv=161, vmax=7.0))
+    ap = dict(CYL_ADAPT, C_split=CYL_ADAPT["C_split"] * scale, C_merge=CYL_ADAPT["C_merge"] * scale,
+              eps_merge=CYL_ADAPT["eps_merge"] * scale)
     out = {}
     for mode in ("mlvs", "uvs"):
         s = m.Solver.from_problem(p, precision=precision, compat=4, map_moments=map_moments,
-                                  adapt=CYL_ADAPT if mode == "mlvs" else None, graph=True)
+                                  adapt=ap if mode == "mlvs" else None, graph=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.step(10)
@@ -315,7 +318,9 @@ def long_run(kind="cylinder", steps=10000, warmup=100, precision=32, map_moments
     err = {"rho": rl2(fm[:, 0], fu[:, 0]), "u": rl2(fm[:, 1:3], fu[:, 1:3]), "T": rl2(fm[:, 3], fu[:, 3]),
            "q": rl2(fm[:, 4:6], fu[:, 4:6])}
     return {"workload": "%s, %d steps (%d on the base grid first), fp%d, MLVS adaptation every %d steps, %d-moment "
-                        "mapping; whole runs timed" % (kind, steps, warmup, precision, CYL_INTERVAL, map_moments),
+                        "mapping, C_split %g C_merge %g eps_merge %g; whole runs timed"
+                        % (kind, steps, warmup, precision, CYL_INTERVAL, map_moments, ap["C_split"], ap["C_merge"],
+                           ap["eps_merge"]),
             "mlvs_seconds": out["mlvs"]["seconds"], "uvs_seconds": out["uvs"]["seconds"],
             "speedup": out["uvs"]["seconds"] / out["mlvs"]["seconds"],
             "memory_ratio": out["uvs"]["memory"] / out["mlvs"]["memory"], "levels": out["mlvs"]["levels"],
@@ -964,6 +969,8 @@ def main():
     ap.add_argument("--jet-mode", choices=("both", "mlvs", "uvs"), default="both")
     ap.add_argument("--tau-sweep", action="store_true", help="only the clustering-threshold sweep on the cylinder")
     ap.add_argument("--long-map", type=int, default=4, choices=[4, 9], help="mapping order of the --long runs")
+    ap.add_argument("--long-scale", type=float, default=1.0,
+                    help="factor on C_split, C_merge and eps_merge of the --long runs")
     ap.add_argument("--long", choices=("cylinder", "jet"), default=None,
                     help="only a whole run of that case, MLVS against UVS (10,000 cylinder or 2,000 jet steps)")
     ap.add_argument("--two-cavity-only", action="store_true", help="only the two-cavity comparison")
@@ -1004,7 +1011,7 @@ def main():
         return
     if args.long:
         print(json.dumps({"long_run": long_run(args.long, 10000 if args.long == "cylinder" else 2000,
-                                               map_moments=args.long_map)}), flush=True)
+                                               map_moments=args.long_map, scale=args.long_scale)}), flush=True)
         return
     if args.two_cavity_only:
         if args.tc_t_end > 0:
