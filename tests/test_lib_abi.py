@@ -129,6 +129,7 @@ def test_context_calls_reject_a_null_context():
     assert L.mlvs_selector_snapshot(None, 0, None) == -1
     assert L.mlvs_selector_train(None, ctypes.byref(cfg), None) == -1
     assert L.mlvs_selector_params(None, None, None) == -1
+    assert L.mlvs_selector_check(None, None, None) == -1
     assert L.mlvs_set_persistent(None, 1) == -1
     assert L.mlvs_graph_info(None, None, None, None, None, None) == -1
     assert L.mlvs_set_tiling(None, 16, 8) == -1
